@@ -1,0 +1,428 @@
+/*
+ * oracle.c -- plain, slow FP64 CPU oracle for the QMC-CPW Greeks estimator
+ * (Bilokon, Kucherenko, Williams, "Quasi-Monte Carlo methods for calculating
+ * derivatives sensitivities on the GPU", arXiv 2209.11337).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this file's library.  It shares no
+ * code, header, table or constant generator with the HIP library: it builds
+ * its own direction numbers from the raw Joe-Kuo (poly, m) data handed in by
+ * its Python wrapper, its own digital shifts, its own inverse normal and its
+ * own path factor, and it takes every step in the paper's order, one path
+ * at a time, with no blocking or fusion.
+ *
+ * Conventions (readings of points the paper leaves open; each is listed in
+ * the design notes):
+ *   - d equally spaced monitoring dates t_j = j*T/d, j = 1..d; t_1 = T/d.
+ *   - omega = r - sigma^2/2 (the drift in Sec. 3.4.1, eqn:Stilde1).
+ *   - x_1 (the conditioned normal that drives W(t_1)) is integrated out in
+ *     closed form and never drawn; Sobol dimension 0 is reserved for it.
+ *     z_j (j = 1..n, n = d-1) comes from Sobol dimension j.
+ *   - Brownian bridge: generic breadth-first bridge over the n grid points
+ *     tau'_m = m*dt, m = 1..n, terminal point first (Sec. 4.4 generalised
+ *     from 2^m steps to any n).
+ *   - Lookback vega: the derivative of max_j S~(t_j) is the single term at
+ *     the argmax; no 1/d factor (Sec. 4.5.3 printed formula carries a
+ *     spurious 1/d, checked by finite differences).
+ *   - Point k of the Sobol sequence is G * bits(gray(k)) (Gray-code order),
+ *     points k = 0..N-1 including k = 0.
+ *   - Uniform from a 32-bit integer y: u = (y + 1/2) * 2^-32.
+ *   - Digital shift of replication l, dimension j: high 32 bits of output
+ *     number (l * 2^16 + j) of SplitMix64 seeded with the option's seed.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_BITS 32
+
+enum { ORC_ARITH = 0, ORC_BINARY = 1, ORC_LOOKBACK = 2 };
+enum { ORC_BB = 0, ORC_PCA = 1, ORC_STANDARD = 2 };
+
+/* ------------------------------------------------------------------------
+ * Sobol direction numbers (Sec. 2.2.2, eqn:SobolPrimitivePolynomial and
+ * eqn:SobolRecurrenceRelation).
+ *
+ * poly[j]  : primitive polynomial x^q + c_1 x^{q-1} + ... + c_{q-1} x + 1 as
+ *            a bit pattern (bit q leading term, bit 0 constant term);
+ *            q = bit length - 1.  poly = 1 (q = 0) is dimension 0, whose
+ *            generator matrix is the identity (van der Corput, Sec. 2.2.1).
+ * minit    : [n_dims][minit_stride] initial m_1..m_q (odd, m_i < 2^i).
+ * V        : [n_dims][32] output, V[j][b] = m_{b+1} * 2^(31-b), i.e. the
+ *            direction number g_{b+1} = m_{b+1}/2^{b+1} as a 32-bit fraction.
+ * ---------------------------------------------------------------------- */
+int oracle_direction_numbers(int n_dims, const int64_t *poly,
+                             const int64_t *minit, int minit_stride,
+                             uint32_t *V)
+{
+    for (int j = 0; j < n_dims; ++j) {
+        uint64_t p = (uint64_t)poly[j];
+        int q = 0;
+        while ((p >> (q + 1)) != 0) ++q;          /* degree */
+        uint64_t m[ORC_MAX_BITS + 1];             /* m[1..32] */
+        if (q == 0) {
+            for (int i = 1; i <= ORC_MAX_BITS; ++i) m[i] = 1;
+        } else {
+            for (int i = 1; i <= q && i <= ORC_MAX_BITS; ++i) {
+                m[i] = (uint64_t)minit[(size_t)j * minit_stride + (i - 1)];
+                if ((m[i] & 1) == 0 || m[i] >= ((uint64_t)1 << i))
+                    return -1;                    /* not a valid initial value */
+            }
+            /* m_i = 2 c_1 m_{i-1} ^ 4 c_2 m_{i-2} ^ ... ^ 2^{q-1} c_{q-1} m_{i-q+1}
+             *       ^ 2^q m_{i-q} ^ m_{i-q}                                     */
+            for (int i = q + 1; i <= ORC_MAX_BITS; ++i) {
+                uint64_t v = ((uint64_t)1 << q) * m[i - q] ^ m[i - q];
+                for (int k = 1; k <= q - 1; ++k) {
+                    uint64_t c_k = (p >> (q - k)) & 1;
+                    if (c_k) v ^= ((uint64_t)1 << k) * m[i - k];
+                }
+                m[i] = v;
+            }
+        }
+        for (int b = 0; b < ORC_MAX_BITS; ++b)
+            V[(size_t)j * 32 + b] = (uint32_t)(m[b + 1] << (31 - b));
+    }
+    return 0;
+}
+
+/* Point k, dimension j, of the unshifted sequence: the XOR of the direction
+ * numbers selected by the binary digits of gray(k) = k ^ (k >> 1)
+ * (eqn:GeneratorMatrixExpression and its XOR form). */
+static uint32_t sobol_int(const uint32_t *Vj, uint64_t k)
+{
+    uint64_t g = k ^ (k >> 1);
+    uint32_t y = 0;
+    for (int b = 0; b < ORC_MAX_BITS; ++b)
+        if ((g >> b) & 1) y ^= Vj[b];
+    return y;
+}
+
+void oracle_sobol_points(const uint32_t *V, int n_dims, int64_t k0,
+                         int64_t count, uint32_t *out /* [count][n_dims] */)
+{
+    for (int64_t i = 0; i < count; ++i)
+        for (int j = 0; j < n_dims; ++j)
+            out[i * n_dims + j] = sobol_int(V + (size_t)j * 32, (uint64_t)(k0 + i));
+}
+
+/* ------------------------------------------------------------------------
+ * SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): state advances by the golden-ratio gamma, each
+ * output is the state passed through the variant-13 mixer.  Output number i
+ * (0-based) of a generator seeded with s is mix(s + (i+1)*gamma).
+ * ---------------------------------------------------------------------- */
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Random digital shift of replication l in dimension j (Sec. 2.2.3: a
+ * randomisation of the point set so that independent replications give an
+ * error estimate). */
+uint32_t oracle_shift(uint64_t seed, int l, int j)
+{
+    return (uint32_t)(oracle_splitmix64(seed, ((uint64_t)l << 16) + (uint64_t)j) >> 32);
+}
+
+/* ------------------------------------------------------------------------
+ * Inverse standard normal: Wichura, "Algorithm AS 241: The percentage
+ * points of the normal distribution", Applied Statistics 37 (1988),
+ * PPND16 (about 1e-16 relative accuracy).
+ * ---------------------------------------------------------------------- */
+double oracle_norm_inv(double p)
+{
+    double q = p - 0.5, r, x;
+    if (fabs(q) <= 0.425) {
+        r = 0.180625 - q * q;
+        x = q * (((((((2.5090809287301226727e+3 * r + 3.3430575583588128105e+4) * r
+                    + 6.7265770927008700853e+4) * r + 4.5921953931549871457e+4) * r
+                    + 1.3731693765509461125e+4) * r + 1.9715909503065514427e+3) * r
+                    + 1.3314166789178437745e+2) * r + 3.3871328727963666080e+0)
+              / (((((((5.2264952788528545610e+3 * r + 2.8729085735721942674e+4) * r
+                    + 3.9307895800092710610e+4) * r + 2.1213794301586595867e+4) * r
+                    + 5.3941960214247511077e+3) * r + 6.8718700749205790830e+2) * r
+                    + 4.2313330701600911252e+1) * r + 1.0);
+        return x;
+    }
+    r = (q < 0.0) ? p : 1.0 - p;
+    r = sqrt(-log(r));
+    if (r <= 5.0) {
+        r -= 1.6;
+        x = (((((((7.74545014278341407640e-4 * r + 2.27238449892691845833e-2) * r
+                 + 2.41780725177450611770e-1) * r + 1.27045825245236838258e+0) * r
+                 + 3.64784832476320460504e+0) * r + 5.76949722146069140550e+0) * r
+                 + 4.63033784615654529590e+0) * r + 1.42343711074968357734e+0)
+            / (((((((1.05075007164441684324e-9 * r + 5.47593808499534494600e-4) * r
+                 + 1.51986665636164571966e-2) * r + 1.48103976427480074590e-1) * r
+                 + 6.89767334985100004550e-1) * r + 1.67638483018380384940e+0) * r
+                 + 2.05319162663775882187e+0) * r + 1.0);
+    } else {
+        r -= 5.0;
+        x = (((((((2.01033439929228813265e-7 * r + 2.71155556874348757815e-5) * r
+                 + 1.24266094738807843860e-3) * r + 2.65321895265761230930e-2) * r
+                 + 2.96560571828504891230e-1) * r + 1.78482653991729133580e+0) * r
+                 + 5.46378491116411436990e+0) * r + 6.65790464350110377720e+0)
+            / (((((((2.04426310338993978564e-15 * r + 1.42151175831644588870e-7) * r
+                 + 1.84631831751005468180e-5) * r + 7.86869131145613259100e-4) * r
+                 + 1.48753612908506148525e-2) * r + 1.36929880922735805310e-1) * r
+                 + 5.99832206555887937690e-1) * r + 1.0);
+    }
+    return (q < 0.0) ? -x : x;
+}
+
+/* Standard normal cdf and density (library erfc/exp as primitives). */
+double oracle_norm_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+double oracle_norm_pdf(double x) { return exp(-0.5 * x * x) / sqrt(2.0 * M_PI); }
+
+/* ------------------------------------------------------------------------
+ * Path construction: W~ = A z  (Sec. 3.4.1, eqn:WboldTilde), the Brownian
+ * motion W~(tau) = W(t_1 + tau) - W(t_1) at tau'_m = m*dt, m = 1..n.
+ * W[0] = 0 is W~ at tau = 0 (date t_1).  W must hold n+1 values.
+ * ---------------------------------------------------------------------- */
+
+/* Standard construction (Alg. 3): left-to-right increments sqrt(dt)*z. */
+static void build_standard(int n, double dt, const double *z, double *W)
+{
+    W[0] = 0.0;
+    for (int m = 1; m <= n; ++m) W[m] = W[m - 1] + sqrt(dt) * z[m - 1];
+}
+
+/* Brownian bridge (Sec. 4.4): terminal value first from the first normal,
+ * then the midpoint of every interval taken breadth first, each drawn from
+ * its conditional law given the two ends.  z[0] -> W[n]; later normals go to
+ * midpoints in queue order. */
+static void build_bridge(int n, double dt, const double *z, double *W)
+{
+    W[0] = 0.0;
+    if (n == 0) return;
+    W[n] = sqrt(n * dt) * z[0];
+    /* every split pushes two intervals: at most 2n - 1 entries ever queued */
+    int *ql = (int *)malloc(sizeof(int) * (size_t)(2 * n + 1));
+    int *qr = (int *)malloc(sizeof(int) * (size_t)(2 * n + 1));
+    int head = 0, tail = 0, next = 1;
+    ql[tail] = 0; qr[tail] = n; ++tail;
+    while (head < tail) {
+        int l = ql[head], r = qr[head]; ++head;
+        if (r - l < 2) continue;
+        int m = (l + r) / 2;
+        double mean = ((double)(r - m) * W[l] + (double)(m - l) * W[r]) / (double)(r - l);
+        double var = dt * (double)(m - l) * (double)(r - m) / (double)(r - l);
+        W[m] = mean + sqrt(var) * z[next++];
+        ql[tail] = l; qr[tail] = m; ++tail;
+        ql[tail] = m; qr[tail] = r; ++tail;
+    }
+    free(ql); free(qr);
+}
+
+/* Principal-component factor of Sigma_{kl} = dt * min(k, l), k, l = 1..n
+ * (Sec. 3.4.1 asks for any A with A A^T = Sigma; the principal components
+ * are the choice that concentrates variance in the leading coordinates).
+ * The eigenpairs of this matrix are known in closed form:
+ *   lambda_i = dt / (4 sin^2((2i-1) pi / (2(2n+1)))),
+ *   v_i(k)   = 2/sqrt(2n+1) * sin((2i-1) k pi / (2n+1)),
+ * i = 1..n in decreasing lambda; every v_i(1) > 0 fixes the signs.
+ * A_{k,i} = sqrt(lambda_i) v_i(k), row-major n x n.  The integer product
+ * (2i-1)k is reduced modulo 2(2n+1) before scaling by pi so the sine's
+ * argument stays below 2 pi and carries no large rounding error. */
+void oracle_pca_factor(int n, double dt, double *A)
+{
+    long M = 2L * (2 * n + 1);
+    for (int i = 1; i <= n; ++i) {
+        double s = sin((2 * i - 1) * M_PI / (double)M);
+        double sq_lam = sqrt(dt / (4.0 * s * s));
+        for (int k = 1; k <= n; ++k) {
+            long a = ((long)(2 * i - 1) * k) % M;
+            double v = 2.0 / sqrt(2.0 * n + 1.0) * sin((double)a * M_PI / (double)(2 * n + 1));
+            A[(size_t)(k - 1) * n + (i - 1)] = sq_lam * v;
+        }
+    }
+}
+
+/* Dense factor (principal components): W[1..n] = A z, A row-major n x n. */
+static void build_dense(int n, const double *A, const double *z, double *W)
+{
+    W[0] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += A[(size_t)k * n + i] * z[i];
+        W[k + 1] = s;
+    }
+}
+
+int oracle_build_path(int path, int n, double dt, const double *z,
+                      const double *A, double *W)
+{
+    switch (path) {
+    case ORC_BB: build_bridge(n, dt, z, W); return 0;
+    case ORC_STANDARD: build_standard(n, dt, z, W); return 0;
+    case ORC_PCA: if (!A) return -1; build_dense(n, A, z, W); return 0;
+    default: return -1;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Conditional payoff G and its pathwise derivatives for one path
+ * (Sec. 3.4.2 and Sec. 4.5).  Given W~ at the d dates, returns
+ * out = {price, delta, vega, gamma} of the smoothed payoff G(theta, z).
+ * ---------------------------------------------------------------------- */
+void oracle_path_greeks(int type, int d, double S0, double K, double r,
+                        double sigma, double T, const double *W, double *out)
+{
+    double dt = T / d;
+    double t1 = dt;
+    double omega = r - 0.5 * sigma * sigma;
+    double s1 = sigma * sqrt(t1);
+    double D = exp(-r * T);
+    double D1 = exp(r * (t1 - T));
+
+    /* S~(t_j) = S0 exp(omega (t_j - t_1) + sigma W~(t_j - t_1))  (eqn:Stilde1) */
+    double X = 0.0, VX = 0.0;
+    if (type == ORC_LOOKBACK) {
+        int jstar = 0;
+        double best = -1.0;
+        for (int m = 0; m < d; ++m) {
+            double tau = m * dt;
+            double St = S0 * exp(omega * tau + sigma * W[m]);
+            if (St > best) { best = St; jstar = m; }   /* lowest index wins ties */
+        }
+        X = best;
+        /* d S~max / d sigma = S~(t_j*) (W~ - sigma tau) at the argmax */
+        VX = best * (W[jstar] - sigma * jstar * dt);
+    } else {
+        for (int m = 0; m < d; ++m) {
+            double tau = m * dt;
+            double St = S0 * exp(omega * tau + sigma * W[m]);
+            X += St;
+            VX += St * (W[m] - sigma * tau);
+        }
+        X /= d;
+        VX /= d;
+    }
+
+    /* Breakpoint of the conditioned normal x_1: S(x_1) = X exp(omega t1 + s1 x1)
+     * crosses K at psi (Sec. 3.4.2, psi_d). */
+    double psi = (log(K) - log(X) - omega * t1) / s1;
+    double Q0 = oracle_norm_cdf(-psi);          /* 1 - Phi(psi) */
+    double Q1 = oracle_norm_cdf(s1 - psi);      /* 1 - Phi(psi - s1) */
+    double phi0 = oracle_norm_pdf(psi);
+
+    if (type == ORC_BINARY) {
+        /* G = e^{-rT}[1 - Phi(psi)]  (eqn:GAnalyticalSolution, Sec. 4.5.1) */
+        out[0] = D * Q0;
+        out[1] = D * phi0 / (S0 * s1);
+        out[2] = D * phi0 * (VX / (s1 * X) + psi / sigma - sqrt(t1));
+        out[3] = D * phi0 / (S0 * S0 * s1) * (psi / s1 - 1.0);
+    } else {
+        /* G = e^{r(t1-T)} X [1 - Phi(psi - s1)] - e^{-rT} K [1 - Phi(psi)]
+         * (Sec. 4.5.2 arithmetic Asian, Sec. 4.5.3 lookback on the max) */
+        out[0] = D1 * X * Q1 - D * K * Q0;
+        out[1] = D1 * (X / S0) * Q1;
+        out[2] = D1 * Q1 * VX + D * K * phi0 * sqrt(t1);
+        out[3] = D * K * phi0 / (S0 * S0 * s1);
+    }
+}
+
+/* Neumaier's compensated summation. */
+typedef struct { double s, c; } orc_sum;
+static void sum_add(orc_sum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double sum_val(const orc_sum *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------
+ * One option, all replications (Sec. 5): for replication l the estimate
+ * C_l = (1/N) sum_k F(theta, z_{l,k}) over the N shifted Sobol points;
+ * C = (1/L) sum_l C_l; stderr = sqrt(sum_l (C_l - C)^2 / (L (L-1))).
+ *
+ * V        : [>= d][32] direction numbers
+ * A        : n x n dense factor for ORC_PCA (row-major), else ignored
+ * C_l      : [L][4] per-replication estimates (may be NULL)
+ * mean     : [4], stderr: [4], abs_mean: [4] = (1/(N L)) sum |F| (the scale
+ *            of the summands, used for scale-aware comparisons)
+ * ---------------------------------------------------------------------- */
+int oracle_option(int type, int d, double S0, double K, double r, double sigma,
+                  double T, uint64_t seed, int64_t N, int L, int path,
+                  const uint32_t *V, const double *A,
+                  double *C_l, double *mean, double *stderr_, double *abs_mean)
+{
+    if (d < 1 || N < 1 || L < 1) return -1;
+    int n = d - 1;
+    double dt = T / d;
+    double *z = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *W = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *Cl = (double *)malloc(sizeof(double) * (size_t)L * 4);
+    orc_sum absum[4];
+    memset(absum, 0, sizeof absum);
+
+    for (int l = 0; l < L; ++l) {
+        orc_sum acc[4];
+        memset(acc, 0, sizeof acc);
+        for (int64_t k = 0; k < N; ++k) {
+            for (int j = 1; j <= n; ++j) {
+                uint32_t y = sobol_int(V + (size_t)j * 32, (uint64_t)k) ^ oracle_shift(seed, l, j);
+                double u = ((double)y + 0.5) / 4294967296.0;
+                z[j - 1] = oracle_norm_inv(u);
+            }
+            oracle_build_path(path, n, dt, z, A, W);
+            double F[4];
+            oracle_path_greeks(type, d, S0, K, r, sigma, T, W, F);
+            for (int o = 0; o < 4; ++o) {
+                sum_add(&acc[o], F[o]);
+                sum_add(&absum[o], fabs(F[o]));
+            }
+        }
+        for (int o = 0; o < 4; ++o) Cl[l * 4 + o] = sum_val(&acc[o]) / (double)N;
+    }
+    for (int o = 0; o < 4; ++o) {
+        orc_sum s = {0, 0};
+        for (int l = 0; l < L; ++l) sum_add(&s, Cl[l * 4 + o]);
+        double C = sum_val(&s) / L;
+        double ss = 0.0;
+        for (int l = 0; l < L; ++l) ss += (Cl[l * 4 + o] - C) * (Cl[l * 4 + o] - C);
+        mean[o] = C;
+        stderr_[o] = (L >= 2) ? sqrt(ss / ((double)L * (L - 1))) : NAN;
+        if (abs_mean) abs_mean[o] = sum_val(&absum[o]) / ((double)N * L);
+    }
+    if (C_l) memcpy(C_l, Cl, sizeof(double) * (size_t)L * 4);
+    free(z); free(W); free(Cl);
+    return 0;
+}
+
+/* Many options, OpenMP over options (independent work).  Arrays are
+ * structure-of-arrays of length n_opts; A_list[i] may be NULL unless
+ * path == ORC_PCA.  Returns the number of threads used. */
+int oracle_options(int n_opts, const int *type, const int *d, const double *S0,
+                   const double *K, const double *r, const double *sigma,
+                   const double *T, const uint64_t *seed, const int64_t *N,
+                   int L, int path, const uint32_t *V, const double *const *A_list,
+                   double *mean, double *stderr_, double *abs_mean, int n_threads)
+{
+    int used = 1;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int i = 0; i < n_opts; ++i) {
+        oracle_option(type[i], d[i], S0[i], K[i], r[i], sigma[i], T[i], seed[i],
+                      N[i], L, path, V, A_list ? A_list[i] : NULL, NULL,
+                      mean + 4 * i, stderr_ + 4 * i, abs_mean + 4 * i);
+    }
+    (void)n_threads;
+    return used;
+}

@@ -1,0 +1,389 @@
+"""Pins of the FP64 oracle against facts fixed outside it (no GPU needed).
+
+Each test checks one part of the oracle against something other than the
+oracle itself: values derived by hand from the paper, a textbook worked
+example, a published generator test vector, a library routine (scipy), a
+closed form, an invariant, finite differences, or numerical quadrature of the
+unconditioned payoff.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.optimize
+import scipy.special
+import scipy.stats
+from scipy.stats import qmc
+
+import oracle
+
+# --------------------------------------------------------------------------
+# Sobol' points (Sec. 2.2)
+# --------------------------------------------------------------------------
+
+
+def _read_rows(path):
+    rows = []
+    with open(path) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def test_sobol_leading_points_from_paper(golden_dir):
+    rows = _read_rows(os.path.join(golden_dir, "sobol_leading_points.txt"))
+    P = oracle.sobol_points(2, 0, len(rows))
+    for k, (kk, a, b) in enumerate(rows):
+        assert int(kk) == k
+        assert P[k, 0] == int(round(float(a) * 2**32))
+        assert P[k, 1] == int(round(float(b) * 2**32))
+
+
+def test_direction_recurrence_textbook_example(golden_dir):
+    (row,) = _read_rows(os.path.join(golden_dir, "sobol_recurrence_example.txt"))
+    poly, m = int(row[0]), [int(x) for x in row[1:]]
+    V = np.zeros((1, 32), dtype=np.uint32)
+    minit = np.zeros((1, 18), dtype=np.int64)
+    minit[0, :3] = m[:3]
+    rc = oracle._load().oracle_direction_numbers(1, np.array([poly], dtype=np.int64), minit, 18, V)
+    assert rc == 0
+    got = [int(V[0, b]) >> (31 - b) for b in range(6)]
+    assert got == m
+
+
+def test_direction_numbers_reject_even_initial_value():
+    V = np.zeros((1, 32), dtype=np.uint32)
+    minit = np.zeros((1, 18), dtype=np.int64)
+    minit[0, :2] = [1, 2]
+    rc = oracle._load().oracle_direction_numbers(1, np.array([7], dtype=np.int64), minit, 18, V)
+    assert rc != 0
+
+
+@pytest.mark.parametrize("n_dims,m", [(16, 12), (365, 10)])
+def test_sobol_matches_scipy_bit_exact(n_dims, m):
+    P = oracle.sobol_points(n_dims, 0, 1 << m)
+    S = qmc.Sobol(n_dims, scramble=False, bits=32).random_base2(m)
+    ints = np.round(S * 2.0**32).astype(np.uint64)
+    assert np.array_equal(P.astype(np.uint64), ints)
+
+
+def test_sobol_random_access_offset():
+    S = qmc.Sobol(40, scramble=False, bits=32).random_base2(11)
+    ints = np.round(S * 2.0**32).astype(np.uint64)
+    for k0, cnt in [(1, 5), (1000, 48), (2040, 8)]:
+        P = oracle.sobol_points(40, k0, cnt)
+        assert np.array_equal(P.astype(np.uint64), ints[k0:k0 + cnt])
+
+
+# --------------------------------------------------------------------------
+# Digital shift (Sec. 2.2.3) and its generator
+# --------------------------------------------------------------------------
+
+
+def test_splitmix64_published_vector(golden_dir):
+    for seed, i, out in _read_rows(os.path.join(golden_dir, "splitmix64_vectors.txt")):
+        assert oracle.splitmix64(int(seed), int(i)) == int(out)
+
+
+def test_shift_is_high_word_of_counter_output():
+    seed = 0xDEADBEEF12345
+    for l, j in [(0, 1), (3, 17), (31, 364)]:
+        assert oracle.shift(seed, l, j) == oracle.splitmix64(seed, (l << 16) + j) >> 32
+
+
+@pytest.mark.parametrize("m", [4, 8, 11])
+def test_shifted_points_remain_a_net(m):
+    """A digital shift maps each dyadic interval of length 2^-m onto another one,
+    so the first 2^m shifted points still hit every such interval once per
+    coordinate (the (0,m,1)-net property in each 1-D projection)."""
+    n_dims = 24
+    P = oracle.sobol_points(n_dims, 0, 1 << m).astype(np.uint64)
+    s = oracle.shifts(0x1234, 3, n_dims)
+    for l in range(3):
+        Y = P ^ s[l][None, :].astype(np.uint64)
+        for j in range(n_dims):
+            cells = np.sort(Y[:, j] >> (32 - m))
+            assert np.array_equal(cells, np.arange(1 << m, dtype=np.uint64))
+
+
+def test_shifts_differ_between_replications_and_dims():
+    s = oracle.shifts(77, 8, 64)
+    assert len(np.unique(s)) == s.size
+
+
+# --------------------------------------------------------------------------
+# Inverse normal
+# --------------------------------------------------------------------------
+
+
+def test_norm_inv_matches_scipy():
+    u = np.concatenate([np.linspace(0, 1, 4001)[1:-1], 10.0 ** -np.arange(1, 300, 0.5),
+                        [0.075, 0.925, 0.425, 0.5 + 2**-33, 2**-33, 1 - 2**-33]])
+    ref = scipy.special.ndtri(u)
+    got = np.array([oracle.norm_inv(x) for x in u])
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+    assert err.max() < 4e-15
+
+
+def test_norm_inv_symmetry_and_centre():
+    assert oracle.norm_inv(0.5) == 0.0
+    for y in [0, 1, 12345, 2**31 - 1, 2**30 + 7]:
+        u = (y + 0.5) / 2**32
+        v = ((2**32 - 1 - y) + 0.5) / 2**32
+        assert abs(oracle.norm_inv(u) + oracle.norm_inv(v)) <= 4e-16 * abs(oracle.norm_inv(u))
+
+
+def test_norm_cdf_matches_scipy():
+    # Phi(x) = erfc(-x/sqrt 2)/2: the rounding of x/sqrt 2 alone moves the tail
+    # value by about x^2 ulp, so two correct implementations differ by that much
+    for x in [-30.0, -8.0, -1.0, 0.0, 0.3, 5.0, 8.5]:
+        ref = scipy.special.ndtr(x)
+        assert abs(oracle.norm_cdf(x) - ref) <= 4e-16 * (1 + x * x) * ref
+
+
+# --------------------------------------------------------------------------
+# Path factor (Sec. 3.4.1: A A^T = Sigma)
+# --------------------------------------------------------------------------
+
+
+def _factor_matrix(path, n, dt):
+    cols = []
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        cols.append(oracle.build_path(path, n, dt, e)[1:])
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("path", [oracle.PATH_BB, oracle.PATH_STANDARD, oracle.PATH_PCA])
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 15, 16, 63, 100, 255])
+def test_factor_reproduces_covariance(path, n):
+    dt = 1.0 / (n + 1)
+    A = _factor_matrix(path, n, dt)
+    Sig = dt * np.minimum.outer(np.arange(1, n + 1), np.arange(1, n + 1)).astype(float)
+    assert np.abs(A @ A.T - Sig).max() <= 1e-14 * Sig.max() * max(1, n / 16)
+
+
+def test_bridge_terminal_and_first_midpoint():
+    """The bridge puts the first normal on the terminal value and the second on
+    the midpoint, each with its conditional variance (Sec. 4.4)."""
+    n, dt = 63, 1 / 64
+    z = np.zeros(n)
+    z[0] = 1.3
+    W = oracle.build_path(oracle.PATH_BB, n, dt, z)
+    assert W[n] == pytest.approx(math.sqrt(n * dt) * 1.3, rel=1e-15)
+    assert W[31] == pytest.approx(31 / 63 * W[n], rel=1e-14)
+    z = np.zeros(n)
+    z[1] = 1.0
+    W = oracle.build_path(oracle.PATH_BB, n, dt, z)
+    assert W[n] == 0.0
+    assert W[31] == pytest.approx(math.sqrt(dt * 31 * 32 / 63), rel=1e-14)
+
+
+@pytest.mark.parametrize("n", [5, 63, 255, 364])
+def test_pca_factor_matches_library_eigensolver(n):
+    """The oracle's closed-form principal components must be the eigenpairs a
+    library eigensolver finds for Sigma (decreasing eigenvalue, first entry of
+    each eigenvector positive), within the solver's own error
+    (eps * ||Sigma|| / eigenvalue gap for the eigenvectors)."""
+    dt = 1.0 / (n + 1)
+    A = oracle.pca_factor(n, dt)
+    lam, vec = np.linalg.eigh(oracle.covariance(n, dt))
+    order = np.argsort(lam)[::-1]
+    lam, vec = lam[order], vec[:, order]
+    vec = vec * np.where(vec[0, :] < 0, -1.0, 1.0)[None, :]
+    lam_A = (A**2).sum(axis=0)
+    assert np.abs(lam_A - lam).max() < 1e-13 * lam.max()
+    assert np.all(np.diff(lam_A) < 0)
+    assert np.all(A[0, :] > 0)
+    assert np.abs(A - vec * np.sqrt(lam)[None, :]).max() < 1e-13 * n
+
+
+# --------------------------------------------------------------------------
+# Conditional payoff and Greeks (Sec. 3.4.2, Sec. 4.5)
+# --------------------------------------------------------------------------
+
+
+def _bs(S0, K, r, sig, T):
+    d1 = (math.log(S0 / K) + (r + 0.5 * sig**2) * T) / (sig * math.sqrt(T))
+    d2 = d1 - sig * math.sqrt(T)
+    N, n = scipy.stats.norm.cdf, scipy.stats.norm.pdf
+    call = [S0 * N(d1) - K * math.exp(-r * T) * N(d2), N(d1), S0 * n(d1) * math.sqrt(T),
+            n(d1) / (S0 * sig * math.sqrt(T))]
+    D = math.exp(-r * T)
+    digital = [D * N(d2), D * n(d2) / (S0 * sig * math.sqrt(T)), -D * n(d2) * d1 / sig,
+               -D * n(d2) * d1 / (S0**2 * sig**2 * T)]
+    return np.array(call), np.array(digital)
+
+
+@pytest.mark.parametrize("S0,K,r,sig,T", [(100, 100, 0.05, 0.2, 1.0), (100, 90, 0.1, 0.2, 1.0),
+                                          (100, 120, 0.0, 0.5, 0.25), (80, 95, 0.08, 0.1, 2.0)])
+def test_one_date_reduces_to_black_scholes(S0, K, r, sig, T):
+    """With d = 1 the Asian average and the lookback maximum are S(T): the
+    arithmetic Asian and lookback calls are the European call and the binary
+    Asian is the cash-or-nothing digital, with exact Greeks and no noise."""
+    call, digital = _bs(S0, K, r, sig, T)
+    for typ, ref in [(oracle.ARITH_ASIAN, call), (oracle.LOOKBACK, call), (oracle.BINARY_ASIAN, digital)]:
+        res = oracle.option(typ, 1, S0, K, r, sig, T, 99, 8, 4)
+        assert np.allclose(res["mean"], ref, rtol=2e-13, atol=0)
+        assert np.all(res["stderr"] == 0)
+
+
+def _fd_check(typ, d, path, z, S0=100.0, K=100.0, r=0.05, sig=0.2, T=1.0):
+    n = d - 1
+    dt = T / d
+    W = oracle.build_path(path, n, dt, z)
+    g = oracle.path_greeks(typ, d, S0, K, r, sig, T, W)
+    s1 = sig * math.sqrt(dt)
+
+    def price(s0, sg):
+        # the path W~ is fixed (same z); S0 and sigma are bumped
+        return oracle.path_greeks(typ, d, s0, K, r, sg, T, W)[0]
+
+    def richardson(f, x, h):
+        a = (f(x + h) - f(x - h)) / (2 * h)
+        b = (f(x + h / 2) - f(x - h / 2)) / h
+        return (4 * b - a) / 3
+
+    hS = 1e-3 * S0 * s1
+    delta = richardson(lambda s: price(s, sig), S0, hS)
+    # gamma as the S0-derivative of the pathwise delta (itself pinned to the
+    # price just above); a second difference of a deep in-the-money price
+    # would lose the small gamma to rounding
+    gamma = richardson(lambda s: oracle.path_greeks(typ, d, s, K, r, sig, T, W)[1], S0, hS)
+    hs = 1e-3 * s1 * sig
+    vega = richardson(lambda s: price(S0, s), sig, hs)
+    # rounding floor of each difference quotient: ~eps * |f| / h
+    eps = np.finfo(float).eps
+    floor = np.array([0.0, 50 * eps * (abs(g[0]) + K) / hS, 50 * eps * (abs(g[0]) + K) / hs,
+                      50 * eps * abs(g[1]) / hS])
+    return g, np.array([g[0], delta, vega, gamma]), floor
+
+
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK])
+@pytest.mark.parametrize("d,path", [(2, oracle.PATH_BB), (12, oracle.PATH_BB), (64, oracle.PATH_BB),
+                                    (17, oracle.PATH_STANDARD), (33, oracle.PATH_PCA)])
+def test_greeks_equal_finite_differences_of_conditional_price(typ, d, path):
+    rng = np.random.default_rng(1000 * d + typ)
+    for trial in range(4):
+        z = rng.standard_normal(d - 1)
+        g, fd, floor = _fd_check(typ, d, path, z, K=[90.0, 100.0, 110.0, 100.0][trial])
+        for i in (1, 2, 3):
+            assert abs(g[i] - fd[i]) <= 1e-6 * abs(fd[i]) + floor[i], (i, g, fd)
+
+
+def test_lookback_vega_has_no_one_over_d():
+    """The printed lookback vega divides by d; finite differences reject that."""
+    d = 24
+    z = np.random.default_rng(5).standard_normal(d - 1)
+    g, fd, _ = _fd_check(oracle.LOOKBACK, d, oracle.PATH_BB, z, K=95.0)
+    assert abs(g[2] - fd[2]) < 1e-6 * abs(fd[2])
+    assert abs(fd[2]) > 2.0 * abs(fd[2] - 0.0) / d
+
+
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK])
+@pytest.mark.parametrize("K", [90.0, 100.0, 115.0])
+def test_conditional_price_is_quadrature_of_unconditioned_payoff(typ, K):
+    """G(theta, z) = E[discounted payoff | z]: integrate the original payoff
+    over the conditioned normal x_1 numerically, with the breakpoint found by
+    root-finding on the path, and compare with the oracle's closed form."""
+    S0, r, sig, T, d = 100.0, 0.05, 0.3, 1.0, 10
+    dt = T / d
+    rng = np.random.default_rng(int(K) + 7 * typ)
+    for _ in range(3):
+        z = rng.standard_normal(d - 1)
+        Wt = oracle.build_path(oracle.PATH_BB, d - 1, dt, z)
+        t = dt * np.arange(1, d + 1)
+
+        def stat(x1):
+            # Black-Scholes path: W(t_j) = sqrt(t_1) x_1 + W~(t_j - t_1)
+            W = math.sqrt(dt) * x1 + Wt
+            S = S0 * np.exp((r - 0.5 * sig**2) * t + sig * W)
+            return S.max() if typ == oracle.LOOKBACK else S.mean()
+
+        def payoff(x1):
+            A = stat(x1)
+            if typ == oracle.BINARY_ASIAN:
+                return math.exp(-r * T) * (1.0 if A > K else 0.0)
+            return math.exp(-r * T) * max(A - K, 0.0)
+
+        root = scipy.optimize.brentq(lambda x: stat(x) - K, -60, 60, xtol=1e-15, rtol=1e-15)
+        f = lambda x: payoff(x) * scipy.stats.norm.pdf(x)
+        val = scipy.integrate.quad(f, root, 40, epsabs=0, epsrel=1e-13, limit=200)[0]
+        g = oracle.path_greeks(typ, d, S0, K, r, sig, T, Wt)
+        assert abs(g[0] - val) <= 1e-10 * max(abs(val), 1e-12), (g[0], val)
+        # the breakpoint itself: binary price is e^{-rT} (1 - Phi(psi))
+        if typ == oracle.BINARY_ASIAN:
+            psi = -scipy.special.ndtri(g[0] / math.exp(-r * T))
+            assert abs(psi - root) < 1e-8 * max(1, abs(root))
+
+
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK])
+def test_rqmc_estimate_agrees_with_quadrature_at_two_dates(typ):
+    """d = 2 leaves one conditioned and one sampled normal: E_z[G] and E_z[dG]
+    by adaptive quadrature must lie within 4 standard errors of the
+    randomised QMC estimate (Sobol + shift + inverse normal + bridge)."""
+    S0, K, r, sig, T, d = 100.0, 105.0, 0.05, 0.25, 1.0, 2
+    dt = T / d
+
+    def G(zz, i):
+        W = oracle.build_path(oracle.PATH_BB, 1, dt, np.array([zz]))
+        return oracle.path_greeks(typ, d, S0, K, r, sig, T, W)[i] * scipy.stats.norm.pdf(zz)
+
+    # the lookback maximum switches date where S~(t_2) = S0, i.e. at
+    # z = -omega*dt / (sigma*sqrt(dt)); split the integral there
+    kink = -(r - 0.5 * sig**2) * dt / (sig * math.sqrt(dt))
+    ref = np.array([scipy.integrate.quad(G, -40, kink, args=(i,), epsabs=0, epsrel=1e-13, limit=200)[0] +
+                    scipy.integrate.quad(G, kink, 40, args=(i,), epsabs=0, epsrel=1e-13, limit=200)[0]
+                    for i in range(4)])
+    res = oracle.option(typ, d, S0, K, r, sig, T, 4242, 1 << 12, 16)
+    for i in range(4):
+        assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-13 * abs(ref[i]), i
+        assert res["stderr"][i] < 1e-3 * max(abs(ref[i]), 1e-6)
+
+
+def test_rqmc_estimate_agrees_with_quadrature_at_three_dates():
+    S0, K, r, sig, T, d = 100.0, 95.0, 0.03, 0.3, 0.5, 3
+    x, w = np.polynomial.hermite_e.hermegauss(64)
+    w = w / w.sum()
+    ref = np.zeros(4)
+    for a, wa in zip(x, w):
+        for b, wb in zip(x, w):
+            W = oracle.build_path(oracle.PATH_BB, 2, T / d, np.array([a, b]))
+            ref += wa * wb * oracle.path_greeks(oracle.ARITH_ASIAN, d, S0, K, r, sig, T, W)
+    res = oracle.option(oracle.ARITH_ASIAN, d, S0, K, r, sig, T, 11, 1 << 12, 16)
+    for i in range(4):
+        assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-13 * abs(ref[i])
+
+
+# --------------------------------------------------------------------------
+# Reduction across replications (Sec. 5)
+# --------------------------------------------------------------------------
+
+
+def test_replication_statistics():
+    res = oracle.option(oracle.ARITH_ASIAN, 8, 100, 100, 0.05, 0.2, 1.0, 5, 256, 6)
+    Cl = res["C_l"]
+    assert np.allclose(res["mean"], Cl.mean(axis=0), rtol=1e-15)
+    se = np.sqrt(((Cl - Cl.mean(axis=0)) ** 2).sum(axis=0) / (6 * 5))
+    assert np.allclose(res["stderr"], se, rtol=1e-12)
+    one = oracle.option(oracle.ARITH_ASIAN, 8, 100, 100, 0.05, 0.2, 1.0, 5, 256, 1)
+    assert np.all(np.isnan(one["stderr"]))
+    assert np.allclose(one["mean"], Cl[0], rtol=1e-15)
+
+
+def test_ragged_point_count_and_many_options():
+    import workloads
+    opts = workloads.three_products_grid(d=9, n_points=777)
+    mean, se, am, used = oracle.options(opts, L=4, n_threads=2)
+    for i in (0, 7, 17):
+        o = opts[i]
+        one = oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"],
+                            o["seed"], o["n_points"], 4)
+        assert np.array_equal(one["mean"], mean[i])
+    assert used >= 1
+    assert np.all(am >= np.abs(mean) * (1 - 1e-12))
