@@ -1,0 +1,152 @@
+"""Benchmark: Greek-path throughput of the QMC-CPW hot path on one MI355X.
+
+One step = one call of the whole hot path (Sobol points + shifts, inverse
+normal, Brownian-bridge path, exponentials and sums, breakpoint, Phi tails,
+price/delta/vega/gamma, reduction over points and replications) over the
+workload "three products at d = 64": arithmetic Asian, binary Asian and
+lookback calls x K {90, 100, 110} x sigma {0.1, 0.3}, S0 = 100, r = 0.05,
+T = 1, 2^20 Sobol points x 32 random shifts each (18 options, 6.04e8
+Greek-paths, 3.8e10 path-dates), FP32-mixed arithmetic.  Inputs are
+synthetic option parameters (no dataset) and stay on the device.
+
+Prints one JSON line.  Extra legs (each its own timed loop, outside the
+headline value): the same workload in plain FP64, and the oracle on the
+host cores (cpu_baseline, a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work (op-count model of the method, independent of the kernel):
+# per path-date (one conditioned coordinate of one path) the inverse normal
+# (log + degree-9 polynomial + argument and sign: 24), the bridge step (5), the
+# exponential (1) and the running sums (5) make about 35 FP32 flops (36 with
+# the uint->float conversion); per path the breakpoint (log), two Phi tails,
+# the density, the four Greeks and the compensated sums make about 200 FP64
+# flops.
+F32_PER_PATH_DATE = 36.0
+F64_PER_PATH = 200.0
+PEAK_F32 = 157.3e12       # MI355X vector FP32 (packed), 256 CU x 2.4 GHz x 256 flop/clk
+PEAK_F64 = 78.6e12        # MI355X vector FP64
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    p.add_argument("--no-extras", action="store_true", help="skip the FP64 and CPU legs")
+    p.add_argument("--cpu-points", type=int, default=1 << 19)
+    return p.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2209_11337_amd as q
+    import workloads
+
+    q.lib()  # raises if the HIP library is not built
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    L = 32
+    opts = workloads.three_products_grid(d=64, n_points=1 << 20)
+    n_paths = workloads.total_paths(opts, L)
+    n_pd = workloads.total_path_dates(opts, L)
+    prec = q.FP32_MIXED if a.precision == "fp32" else q.FP64
+    out = (torch.empty((len(opts), 4), dtype=torch.float64, device=dev),
+           torch.empty((len(opts), 4), dtype=torch.float64, device=dev))
+    stream = torch.cuda.Stream()
+
+    def step(p):
+        q.greeks(opts, L, q.PATH_BB, p, device_outputs=True, out=out, stream=stream)
+
+    def timed(p, steps, warmup):
+        for _ in range(warmup):
+            step(p)
+        torch.cuda.synchronize()
+        stream.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for s, e in evs:
+            s.record(stream)
+            step(p)
+            e.record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = float(np.mean([s.elapsed_time(e) for s, e in evs]))
+        return wall, ev_ms
+
+    wall, ev_ms = timed(prec, a.steps, a.warmup)
+    print("timed %d steps: %.3f s wall, %.3f ms/launch (events)" % (a.steps, wall, ev_ms),
+          file=sys.stderr, flush=True)
+    value = n_paths * a.steps / wall
+    g = out[0].cpu().numpy()
+    e = out[1].cpu().numpy()
+
+    f32 = F32_PER_PATH_DATE * n_pd if prec == q.FP32_MIXED else 0.0
+    f64 = F64_PER_PATH * n_paths + (0.0 if prec == q.FP32_MIXED else F32_PER_PATH_DATE * n_pd)
+    t_ideal = f32 / PEAK_F32 + f64 / PEAK_F64
+    t_kernel = ev_ms * 1e-3
+    achieved = (f32 + f64 * PEAK_F32 / PEAK_F64) / t_kernel
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_F32 / 1e12, "unit": "TFLOP/s",
+                "frac": t_ideal / t_kernel, "traffic": None,
+                "model": "FP32-equivalent flops: %.0f FP32/path-date + %.0f FP64/path (FP64 weighted x2)"
+                         % (F32_PER_PATH_DATE, F64_PER_PATH),
+                "kernel_ms": ev_ms}
+
+    res = {"metric": "Greek-paths/sec (delta+vega+gamma) at fixed RMSE vs FP64; p99 request latency",
+           "value": value, "unit": "Greek-paths/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": wall / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64" if prec == q.FP32_MIXED else "f64",
+           "data": "synthetic (Black-Scholes option parameters, seeded)",
+           "config": {"workload": "three products (arith Asian, binary Asian, lookback) x K{90,100,110} x "
+                                  "sigma{0.1,0.3}, d=64, Brownian bridge, 2^20 Sobol points x 32 shifts",
+                      "options": len(opts), "greek_paths_per_step": n_paths, "path_dates_per_step": n_pd,
+                      "precision": a.precision},
+           "roofline": roofline}
+
+    if not a.no_extras:
+        # plain FP64 on the same workload, same launch path
+        w64, ev64 = timed(q.FP64, 2, 1)
+        g64 = out[0].cpu().numpy()
+        res["fp64"] = {"value": n_paths * 2 / w64, "ms_per_step": w64 / 2 * 1e3, "kernel_ms": ev64}
+        if prec == q.FP32_MIXED:
+            rel = np.abs(g - g64) / np.maximum(np.abs(g64), 1e-300)
+            res["fp32_vs_fp64_max_rel_diff"] = {k: float(rel[:, i].max()) for i, k in enumerate(q.OUTPUTS)}
+            res["stderr_max_rel"] = {k: float((e[:, i] / np.maximum(np.abs(g64[:, i]), 1e-300)).max())
+                                     for i, k in enumerate(q.OUTPUTS)}
+        # the oracle on the host cores, a bounded sample of the same workload
+        import oracle
+        n_cpu = a.cpu_points
+        Ls = 4
+        sample = workloads.three_products_grid(d=64, n_points=n_cpu)
+        threads = os.cpu_count() or 1
+        t0 = time.perf_counter()
+        _, _, _, used = oracle.options(sample, Ls, oracle.PATH_BB, n_threads=threads)
+        tc = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": workloads.total_paths(sample, Ls) / tc, "unit": "Greek-paths/s",
+                               "cores": used, "kind": "oracle",
+                               "sample": "the 18 options at d=64, 2^%d points x %d shifts (%.1f s)"
+                                         % (int(np.log2(n_cpu)), Ls, tc)}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

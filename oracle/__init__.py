@@ -79,6 +79,10 @@ def _load():
                                           [C.c_uint64, C.c_int64, C.c_int, C.c_int, u32p, C.c_void_p,
                                            C.c_void_p, f64p, f64p, f64p])
             lib.oracle_option.restype = C.c_int
+            lib.oracle_replication.argtypes = ([C.c_int, C.c_int] + [C.c_double] * 5 +
+                                               [C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int, u32p,
+                                                C.c_void_p, f64p, C.c_void_p])
+            lib.oracle_replication.restype = C.c_int
             lib.oracle_options.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_int, C.c_int, u32p, C.c_void_p, f64p, f64p, f64p, C.c_int]
@@ -206,6 +210,21 @@ def option(type_: int, d: int, S0, K, r, sigma, T, seed: int, N: int, L: int, pa
     if rc != 0:
         raise ValueError("oracle_option rejected its arguments")
     return {"mean": mean, "stderr": se, "abs_mean": am, "C_l": C_l}
+
+
+def replication(o: dict, l: int, path: int = PATH_BB, k0: int = 0, N: int | None = None) -> np.ndarray:
+    """C_l[4] of replication l of option dict o over points k0 .. k0 + N - 1."""
+    d = int(o["d"])
+    N = int(o["n_points"]) if N is None else int(N)
+    V = direction_numbers(max(d, 2))
+    A = pca_factor(d - 1, o["T"] / d) if (path == PATH_PCA and d > 1) else None
+    out = np.zeros(4)
+    rc = _load().oracle_replication(int(o["type"]), d, float(o["S0"]), float(o["K"]), float(o["r"]),
+                                    float(o["sigma"]), float(o["T"]), int(o["seed"]) & (2**64 - 1), k0, N,
+                                    l, path, V, A.ctypes.data if A is not None else None, out, None)
+    if rc != 0:
+        raise ValueError("oracle_replication rejected its arguments")
+    return out
 
 
 def options(specs, L: int, path: int = PATH_BB, n_threads: int = 0):

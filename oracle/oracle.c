@@ -351,39 +351,52 @@ static double sum_val(const orc_sum *a) { return a->s + a->c; }
  * mean     : [4], stderr: [4], abs_mean: [4] = (1/(N L)) sum |F| (the scale
  *            of the summands, used for scale-aware comparisons)
  * ---------------------------------------------------------------------- */
+/* Replication l of one option: C_l[4] = (1/N) sum_k F(theta, z_{l,k}) over
+ * points k = k0 .. k0 + N - 1, and abs_sum[4] += sum_k |F| (may be NULL). */
+int oracle_replication(int type, int d, double S0, double K, double r, double sigma,
+                       double T, uint64_t seed, int64_t k0, int64_t N, int l, int path,
+                       const uint32_t *V, const double *A, double *C_l, double *abs_sum)
+{
+    if (d < 1 || N < 1 || k0 < 0) return -1;
+    int n = d - 1;
+    double dt = T / d;
+    double *z = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *W = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    orc_sum acc[4], ab[4];
+    memset(acc, 0, sizeof acc);
+    memset(ab, 0, sizeof ab);
+    for (int64_t k = k0; k < k0 + N; ++k) {
+        for (int j = 1; j <= n; ++j) {
+            uint32_t y = sobol_int(V + (size_t)j * 32, (uint64_t)k) ^ oracle_shift(seed, l, j);
+            double u = ((double)y + 0.5) / 4294967296.0;
+            z[j - 1] = oracle_norm_inv(u);
+        }
+        oracle_build_path(path, n, dt, z, A, W);
+        double F[4];
+        oracle_path_greeks(type, d, S0, K, r, sigma, T, W, F);
+        for (int o = 0; o < 4; ++o) {
+            sum_add(&acc[o], F[o]);
+            sum_add(&ab[o], fabs(F[o]));
+        }
+    }
+    for (int o = 0; o < 4; ++o) {
+        C_l[o] = sum_val(&acc[o]) / (double)N;
+        if (abs_sum) abs_sum[o] += sum_val(&ab[o]);
+    }
+    free(z); free(W);
+    return 0;
+}
+
 int oracle_option(int type, int d, double S0, double K, double r, double sigma,
                   double T, uint64_t seed, int64_t N, int L, int path,
                   const uint32_t *V, const double *A,
                   double *C_l, double *mean, double *stderr_, double *abs_mean)
 {
     if (d < 1 || N < 1 || L < 1) return -1;
-    int n = d - 1;
-    double dt = T / d;
-    double *z = (double *)malloc(sizeof(double) * (size_t)(n + 1));
-    double *W = (double *)malloc(sizeof(double) * (size_t)(n + 1));
     double *Cl = (double *)malloc(sizeof(double) * (size_t)L * 4);
-    orc_sum absum[4];
-    memset(absum, 0, sizeof absum);
-
-    for (int l = 0; l < L; ++l) {
-        orc_sum acc[4];
-        memset(acc, 0, sizeof acc);
-        for (int64_t k = 0; k < N; ++k) {
-            for (int j = 1; j <= n; ++j) {
-                uint32_t y = sobol_int(V + (size_t)j * 32, (uint64_t)k) ^ oracle_shift(seed, l, j);
-                double u = ((double)y + 0.5) / 4294967296.0;
-                z[j - 1] = oracle_norm_inv(u);
-            }
-            oracle_build_path(path, n, dt, z, A, W);
-            double F[4];
-            oracle_path_greeks(type, d, S0, K, r, sigma, T, W, F);
-            for (int o = 0; o < 4; ++o) {
-                sum_add(&acc[o], F[o]);
-                sum_add(&absum[o], fabs(F[o]));
-            }
-        }
-        for (int o = 0; o < 4; ++o) Cl[l * 4 + o] = sum_val(&acc[o]) / (double)N;
-    }
+    double absum[4] = {0, 0, 0, 0};
+    for (int l = 0; l < L; ++l)
+        oracle_replication(type, d, S0, K, r, sigma, T, seed, 0, N, l, path, V, A, Cl + 4 * l, absum);
     for (int o = 0; o < 4; ++o) {
         orc_sum s = {0, 0};
         for (int l = 0; l < L; ++l) sum_add(&s, Cl[l * 4 + o]);
@@ -392,10 +405,10 @@ int oracle_option(int type, int d, double S0, double K, double r, double sigma,
         for (int l = 0; l < L; ++l) ss += (Cl[l * 4 + o] - C) * (Cl[l * 4 + o] - C);
         mean[o] = C;
         stderr_[o] = (L >= 2) ? sqrt(ss / ((double)L * (L - 1))) : NAN;
-        if (abs_mean) abs_mean[o] = sum_val(&absum[o]) / ((double)N * L);
+        if (abs_mean) abs_mean[o] = absum[o] / ((double)N * L);
     }
     if (C_l) memcpy(C_l, Cl, sizeof(double) * (size_t)L * 4);
-    free(z); free(W); free(Cl);
+    free(Cl);
     return 0;
 }
 

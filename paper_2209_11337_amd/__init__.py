@@ -1,0 +1,243 @@
+"""MI355X QMC-CPW Greeks: Python binding of the C ABI in include/qmc_cpw.h.
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library ``libqmccpw.so`` built from ``csrc/`` (``python -m
+paper_2209_11337_amd.build`` or ``__graft_entry__.build()``).  Importing this
+package without the built library raises; there is no CPU fallback.
+
+Torch, when used, only provides device buffers and the current stream
+(``greeks(..., device_outputs=True)``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from typing import Iterable, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqmccpw.so")
+
+ARITH_ASIAN, BINARY_ASIAN, LOOKBACK = 0, 1, 2
+PATH_BB, PATH_PCA, PATH_STANDARD = 0, 1, 2
+FP64, FP32_MIXED = 0, 1
+GEMM_FP32, GEMM_BF16X3 = 0, 1
+OUTPUTS = ("price", "delta", "vega", "gamma")
+MAX_D, MAX_D_PCA = 385, 257
+
+STATUS = {0: "QCPW_OK", -1: "QCPW_EINVAL", -2: "QCPW_ENOMEM", -3: "QCPW_EDEVICE", -4: "QCPW_EDIMS",
+          -5: "QCPW_EBUSY", -6: "QCPW_ECANCELLED", -7: "QCPW_ENOTFOUND"}
+
+# names of every entry point declared in include/qmc_cpw.h
+EXPORTS = ("qmc_cpw_greeks", "qmc_cpw_greeks_ex", "qcpw_sobol_points", "qcpw_path_factor",
+           "qcpw_last_error", "qcpw_version", "qcpw_server_create", "qcpw_submit", "qcpw_poll",
+           "qcpw_wait", "qcpw_cancel", "qcpw_server_stats", "qcpw_server_destroy")
+
+
+class QcpwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class OptionSpec(C.Structure):
+    _fields_ = [("type", C.c_int32), ("d", C.c_int32), ("S0", C.c_double), ("K", C.c_double),
+                ("r", C.c_double), ("sigma", C.c_double), ("T", C.c_double), ("seed", C.c_uint64),
+                ("n_points", C.c_int64)]
+
+
+class RunConfig(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("pca_gemm", C.c_int32), ("device", C.c_int32),
+                ("outputs_on_device", C.c_int32), ("stream", C.c_void_p),
+                ("out_per_shift", C.c_void_p), ("block_threads", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib() -> C.CDLL:
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError("libqmccpw.so is not built (run paper_2209_11337_amd/build.py); "
+                                  "there is no fallback path")
+            # One HIP runtime per process: torch ships its own libamdhip64.so.7;
+            # loading it first lets the library bind to that copy (same soname),
+            # so device pointers and streams from torch are valid here.
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
+            L = C.CDLL(LIB_PATH)
+            vp, i32, i64, u64, f64p = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
+            L.qmc_cpw_greeks.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p]
+            L.qmc_cpw_greeks_ex.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p, vp]
+            L.qcpw_sobol_points.argtypes = [u64, i32, i32, i64, i64, vp]
+            L.qcpw_path_factor.argtypes = [i32, i32, C.c_double, vp]
+            L.qcpw_last_error.restype = C.c_char_p
+            L.qcpw_version.restype = C.c_char_p
+            L.qcpw_server_create.argtypes = [vp, i64, C.POINTER(vp)]
+            L.qcpw_submit.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.POINTER(u64)]
+            L.qcpw_poll.argtypes = [vp, u64, vp, vp, vp]
+            L.qcpw_wait.argtypes = [vp, u64, vp, vp, vp]
+            L.qcpw_cancel.argtypes = [vp, u64]
+            L.qcpw_server_stats.argtypes = [vp, vp]
+            L.qcpw_server_destroy.argtypes = [vp]
+            for name in EXPORTS:
+                f = getattr(L, name)
+                if f.restype is C.c_int or f.restype is None:
+                    if name not in ("qcpw_last_error", "qcpw_version"):
+                        f.restype = C.c_int32
+            _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise QcpwError(st, lib().qcpw_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().qcpw_last_error().decode()
+
+
+def version() -> str:
+    return lib().qcpw_version().decode()
+
+
+def make_specs(options: Sequence[dict]) -> C.Array:
+    arr = (OptionSpec * len(options))()
+    for i, o in enumerate(options):
+        arr[i] = OptionSpec(int(o["type"]), int(o.get("d", 0)), float(o["S0"]), float(o["K"]),
+                            float(o["r"]), float(o["sigma"]), float(o["T"]),
+                            int(o.get("seed", 0)) & (2**64 - 1), int(o.get("n_points", 0)))
+    return arr
+
+
+def greeks(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precision: int = FP64,
+           d: int = 0, n_points: int = 0, pca_gemm: int = GEMM_FP32, per_shift: bool = False,
+           block_threads: int = 0, stream=None, device_outputs: bool = False, device: int = -1,
+           out=None):
+    """Greeks of many options in one launch.
+
+    Host mode (default): returns (greeks[n][4], stderr[n][4]) numpy arrays
+    (and per_shift[n][L][4] if asked).  Device mode: ``out`` is a tuple of
+    torch CUDA tensors (greeks, stderr[, per_shift]) the results are written
+    to on ``stream`` (default: torch's current stream); returns ``out``.
+    """
+    specs = make_specs(options)
+    n = len(options)
+    cfg = RunConfig(precision, pca_gemm, device, 1 if device_outputs else 0, None, None,
+                    block_threads, 0)
+    if device_outputs:
+        import torch
+        if out is None:
+            dev = torch.device("cuda", torch.cuda.current_device() if device < 0 else device)
+            out = (torch.empty((n, 4), dtype=torch.float64, device=dev),
+                   torch.empty((n, 4), dtype=torch.float64, device=dev))
+            if per_shift:
+                out = out + (torch.empty((n, n_shifts, 4), dtype=torch.float64, device=dev),)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        cfg.stream = C.c_void_p(s.cuda_stream)
+        if per_shift:
+            cfg.out_per_shift = C.c_void_p(out[2].data_ptr())
+        _check(lib().qmc_cpw_greeks_ex(specs, n, d, n_points, n_shifts, path, out[0].data_ptr(),
+                                       out[1].data_ptr(), C.byref(cfg)))
+        return out
+    g = np.zeros((n, 4))
+    e = np.zeros((n, 4))
+    ps = np.zeros((n, n_shifts, 4)) if per_shift else None
+    if per_shift:
+        cfg.out_per_shift = C.c_void_p(ps.ctypes.data)
+    if stream is not None:
+        cfg.stream = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    _check(lib().qmc_cpw_greeks_ex(specs, n, d, n_points, n_shifts, path, g.ctypes.data, e.ctypes.data,
+                                   C.byref(cfg)))
+    return (g, e, ps) if per_shift else (g, e)
+
+
+def greeks_plain(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, d: int = 0,
+                 n_points: int = 0):
+    """The plain entry point qmc_cpw_greeks (FP64, host buffers)."""
+    specs = make_specs(options)
+    n = len(options)
+    g = np.zeros((n, 4))
+    e = np.zeros((n, 4))
+    _check(lib().qmc_cpw_greeks(specs, n, d, n_points, n_shifts, path, g.ctypes.data, e.ctypes.data))
+    return g, e
+
+
+def sobol_points(seed: int, shift_index: int, n_dims: int, k0: int, count: int) -> np.ndarray:
+    out = np.zeros((count, n_dims), dtype=np.uint32)
+    _check(lib().qcpw_sobol_points(seed & (2**64 - 1), shift_index, n_dims, k0, count, out.ctypes.data))
+    return out
+
+
+def path_factor(path: int, d: int, T: float) -> np.ndarray:
+    n = d - 1
+    out = np.zeros((max(n, 0), max(n, 0)))
+    _check(lib().qcpw_path_factor(path, d, T, out.ctypes.data if n > 0 else None))
+    return out
+
+
+class Server:
+    """Continuous-batching request server (qcpw_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, precision: int = FP32_MIXED, device: int = -1,
+                 block_threads: int = 0):
+        cfg = RunConfig(precision, GEMM_FP32, device, 0, None, None, block_threads, 0)
+        h = C.c_void_p()
+        _check(lib().qcpw_server_create(C.byref(cfg), hbm_budget_bytes, C.byref(h)))
+        self._h = h
+
+    def submit(self, options: Sequence[dict], n_shifts: int, target_stderr: float,
+               path: int = PATH_BB) -> int:
+        specs = make_specs(options)
+        rid = C.c_uint64()
+        _check(lib().qcpw_submit(self._h, specs, len(options), n_shifts, path, target_stderr, C.byref(rid)))
+        return rid.value
+
+    def _result(self, fn, rid: int, n: int):
+        g = np.zeros((n, 4))
+        e = np.zeros((n, 4))
+        pts = C.c_int64()
+        st = fn(self._h, rid, g.ctypes.data, e.ctypes.data, C.byref(pts))
+        return st, g, e, pts.value
+
+    def poll(self, rid: int, n: int):
+        """None while running; else (greeks, stderr, points_used)."""
+        st, g, e, p = self._result(lib().qcpw_poll, rid, n)
+        if st == -5:
+            return None
+        _check(st)
+        return g, e, p
+
+    def wait(self, rid: int, n: int):
+        st, g, e, p = self._result(lib().qcpw_wait, rid, n)
+        _check(st)
+        return g, e, p
+
+    def cancel(self, rid: int):
+        _check(lib().qcpw_cancel(self._h, rid))
+
+    def stats(self) -> dict:
+        out = (C.c_int64 * 7)()
+        _check(lib().qcpw_server_stats(self._h, out))
+        keys = ("admitted", "completed", "cancelled", "launches", "bytes_in_use", "peak_bytes", "queued")
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if self._h:
+            _check(lib().qcpw_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

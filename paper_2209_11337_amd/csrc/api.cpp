@@ -1,0 +1,276 @@
+// api.cpp -- the C ABI: argument checks, per-device contexts with their
+// resident tables, workspace management and the synchronous entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qcpw_host.h"
+
+namespace qcpw {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+qcpw_status fail(qcpw_status code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+qcpw_status Workspace::ensure(size_t need)
+{
+    if (need <= bytes) return QCPW_OK;
+    if (ptr) {
+        QCPW_HIP(hipFree(ptr));
+        ptr = nullptr;
+        bytes = 0;
+    }
+    size_t want = need + need / 4;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return fail(QCPW_ENOMEM, "hipMalloc of " + std::to_string(want) + " workspace bytes failed");
+    }
+    bytes = want;
+    return QCPW_OK;
+}
+
+static std::mutex g_ctx_mu;
+static std::vector<std::unique_ptr<Context>> g_ctx;
+
+static qcpw_status init_tables(Context *ctx, int device)
+{
+    DeviceTables &t = ctx->tab;
+    t.device = device;
+    hipDeviceProp_t prop;
+    QCPW_HIP(hipGetDeviceProperties(&prop, device));
+    t.n_cu = prop.multiProcessorCount;
+
+    std::vector<uint32_t> dir, lane;
+    build_direction_numbers(dir);
+    build_lane_table(dir, lane);
+    std::vector<PlanStep> all;
+    std::vector<PlanStep64> all64;
+    t.plan_off.assign(QCPW_MAX_N + 1, 0);
+    t.depth.assign(QCPW_MAX_N + 1, 0);
+    for (int n = 1; n <= QCPW_MAX_N; ++n) {
+        std::vector<PlanStep> s;
+        std::vector<PlanStep64> s64;
+        int depth = build_bridge_plan(n, s, s64);
+        if (depth > QCPW_STACK_MAX) return fail(QCPW_EDEVICE, "bridge plan deeper than the kernel's stack");
+        t.max_stack = std::max(t.max_stack, depth);
+        t.depth[n] = depth;
+        t.plan_off[n] = (int32_t)all.size();
+        all.insert(all.end(), s.begin(), s.end());
+        all64.insert(all64.end(), s64.begin(), s64.end());
+    }
+    QCPW_HIP(hipMalloc(&t.dir, dir.size() * 4));
+    QCPW_HIP(hipMalloc(&t.lane, lane.size() * 4));
+    QCPW_HIP(hipMalloc(&t.plan, all.size() * sizeof(PlanStep)));
+    QCPW_HIP(hipMalloc(&t.plan64, all64.size() * sizeof(PlanStep64)));
+    QCPW_HIP(hipMemcpy(t.dir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice));
+    QCPW_HIP(hipMemcpy(t.lane, lane.data(), lane.size() * 4, hipMemcpyHostToDevice));
+    QCPW_HIP(hipMemcpy(t.plan, all.data(), all.size() * sizeof(PlanStep), hipMemcpyHostToDevice));
+    QCPW_HIP(hipMemcpy(t.plan64, all64.data(), all64.size() * sizeof(PlanStep64), hipMemcpyHostToDevice));
+    QCPW_HIP(hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
+    QCPW_HIP(hipEventCreateWithFlags(&ctx->ws_done, hipEventDisableTiming));
+    return QCPW_OK;
+}
+
+qcpw_status get_context(int device, Context **out)
+{
+    int cur = 0;
+    if (device < 0) {
+        QCPW_HIP(hipGetDevice(&cur));
+        device = cur;
+    }
+    int count = 0;
+    QCPW_HIP(hipGetDeviceCount(&count));
+    if (device >= count) return fail(QCPW_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    if ((int)g_ctx.size() < count) g_ctx.resize(count);
+    if (!g_ctx[device]) {
+        std::unique_ptr<Context> c(new Context());
+        QCPW_HIP(hipSetDevice(device));
+        qcpw_status st = init_tables(c.get(), device);
+        if (st != QCPW_OK) return st;
+        g_ctx[device] = std::move(c);
+    }
+    QCPW_HIP(hipSetDevice(device));
+    *out = g_ctx[device].get();
+    return QCPW_OK;
+}
+
+// Unit-dt principal-component factor for n coordinates (the kernels scale
+// the normals by sqrt(dt) instead), resident per n.  Row-major NPAD x NPAD
+// FP32 (zero padded), the same split into BF16 hi/lo, and n x n FP64.
+qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out)
+{
+    for (auto &p : ctx->pca)
+        if (p.n == n && p.dt == dt) {
+            *out = &p;
+            return QCPW_OK;
+        }
+    std::vector<double> A;
+    build_pca_factor(n, dt, A);
+    const int NP = QCPW_PCA_NPAD;
+    std::vector<float> A32((size_t)NP * NP, 0.0f);
+    std::vector<uint16_t> hi((size_t)NP * NP, 0), lo((size_t)NP * NP, 0);
+    auto to_bf16 = [](float x) -> uint16_t {   // round to nearest even
+        uint32_t u;
+        memcpy(&u, &x, 4);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    };
+    auto from_bf16 = [](uint16_t h) -> float {
+        uint32_t u = (uint32_t)h << 16;
+        float x;
+        memcpy(&x, &u, 4);
+        return x;
+    };
+    for (int k = 0; k < n; ++k)
+        for (int i = 0; i < n; ++i) {
+            const float a = (float)A[(size_t)k * n + i];
+            A32[(size_t)k * NP + i] = a;
+            const uint16_t h = to_bf16(a);
+            hi[(size_t)k * NP + i] = h;
+            lo[(size_t)k * NP + i] = to_bf16(a - from_bf16(h));
+        }
+    Context::Pca p;
+    p.n = n;
+    p.dt = dt;
+    QCPW_HIP(hipMalloc(&p.A32, A32.size() * 4));
+    QCPW_HIP(hipMalloc(&p.A64, A.size() * 8));
+    QCPW_HIP(hipMalloc(&p.Ahi, hi.size() * 2));
+    QCPW_HIP(hipMalloc(&p.Alo, lo.size() * 2));
+    QCPW_HIP(hipMemcpy(p.A32, A32.data(), A32.size() * 4, hipMemcpyHostToDevice));
+    QCPW_HIP(hipMemcpy(p.A64, A.data(), A.size() * 8, hipMemcpyHostToDevice));
+    QCPW_HIP(hipMemcpy(p.Ahi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
+    QCPW_HIP(hipMemcpy(p.Alo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+    ctx->pca.push_back(p);
+    *out = &ctx->pca.back();
+    return QCPW_OK;
+}
+
+}  // namespace qcpw
+
+using namespace qcpw;
+
+extern "C" {
+
+const char *qcpw_last_error(void) { return g_last_error.c_str(); }
+
+const char *qcpw_version(void) { return "qmc-cpw-mi355x 0.1 (gfx950)"; }
+
+qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_opts, int32_t d,
+                              int64_t n_points, int32_t n_shifts, int32_t path_construction,
+                              double *out_greeks, double *out_stderr, const qcpw_run_config *cfg)
+{
+    g_last_error.clear();
+    qcpw_run_config c;
+    memset(&c, 0, sizeof c);
+    c.device = -1;
+    if (cfg) c = *cfg;
+    if (!out_greeks || !out_stderr) return fail(QCPW_EINVAL, "output pointer is NULL");
+    qcpw_status st = validate_call(option_specs, n_opts, d, n_points, n_shifts, path_construction,
+                                   c.precision, c.pca_gemm, c.block_threads);
+    if (st != QCPW_OK) return st;
+    Context *ctx = nullptr;
+    st = get_context(c.device, &ctx);
+    if (st != QCPW_OK) return st;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    LaunchPlan lp;
+    st = plan_launch(ctx, option_specs, n_opts, d, n_points, n_shifts, path_construction, c.precision,
+                     c.pca_gemm, c.block_threads, lp);
+    if (st != QCPW_OK) return st;
+    const size_t n = (size_t)n_opts;
+    const size_t out_bytes = n * 4 * sizeof(double);
+    const size_t ps_bytes = n * (size_t)n_shifts * 4 * sizeof(double);
+    const size_t need = launch_workspace_bytes(lp);
+    const bool dev_out = c.outputs_on_device != 0;
+    const size_t extra = dev_out ? 0 : 2 * out_bytes + (c.out_per_shift ? ps_bytes : 0) + 768;
+    hipStream_t stream = (hipStream_t)c.stream;   // NULL is the default stream
+    if (ctx->ws_pending) {
+        // the workspace may still be in use by a launch on another stream
+        if (need + extra > ctx->ws.bytes) QCPW_HIP(hipEventSynchronize(ctx->ws_done));
+        else QCPW_HIP(hipStreamWaitEvent(stream, ctx->ws_done, 0));
+    }
+    st = ctx->ws.ensure(need + extra);
+    if (st != QCPW_OK) return st;
+    char *ws = (char *)ctx->ws.ptr;
+    double *g = out_greeks, *e = out_stderr, *ps = c.out_per_shift;
+    if (!dev_out) {
+        char *p = ws + need;
+        g = (double *)p;
+        e = (double *)(p + ((out_bytes + 255) / 256) * 256);
+        ps = c.out_per_shift ? (double *)(p + 2 * ((out_bytes + 255) / 256) * 256) : nullptr;
+    }
+    st = enqueue_launch(ctx, lp, stream, g, e, ps, ws, need);
+    if (st != QCPW_OK) return st;
+    QCPW_HIP(hipEventRecord(ctx->ws_done, stream));
+    ctx->ws_pending = true;
+    if (!dev_out) {
+        QCPW_HIP(hipMemcpyAsync(out_greeks, g, out_bytes, hipMemcpyDeviceToHost, stream));
+        QCPW_HIP(hipMemcpyAsync(out_stderr, e, out_bytes, hipMemcpyDeviceToHost, stream));
+        if (c.out_per_shift)
+            QCPW_HIP(hipMemcpyAsync(c.out_per_shift, ps, ps_bytes, hipMemcpyDeviceToHost, stream));
+        QCPW_HIP(hipStreamSynchronize(stream));
+    }
+    return QCPW_OK;
+}
+
+qcpw_status qmc_cpw_greeks(const qcpw_option_spec *option_specs, int32_t n_opts, int32_t d, int64_t n_points,
+                           int32_t n_shifts, int32_t path_construction, double *out_greeks, double *out_stderr)
+{
+    return qmc_cpw_greeks_ex(option_specs, n_opts, d, n_points, n_shifts, path_construction, out_greeks,
+                             out_stderr, nullptr);
+}
+
+qcpw_status qcpw_sobol_points(uint64_t seed, int32_t shift_index, int32_t n_dims, int64_t k0, int64_t count,
+                              uint32_t *out)
+{
+    g_last_error.clear();
+    if (!out) return fail(QCPW_EINVAL, "out is NULL");
+    if (n_dims < 1 || n_dims > QCPW_TAB_DIMS) return fail(QCPW_EINVAL, "n_dims out of range");
+    if (count < 1 || count > (int64_t(1) << 24)) return fail(QCPW_EINVAL, "count out of range");
+    if (k0 < 0 || k0 + count > (int64_t(1) << 32)) return fail(QCPW_EINVAL, "points beyond 2^32");
+    if (shift_index < 0 || shift_index > QCPW_MAX_SHIFTS) return fail(QCPW_EINVAL, "shift_index out of range");
+    Context *ctx = nullptr;
+    qcpw_status st = get_context(-1, &ctx);
+    if (st != QCPW_OK) return st;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const size_t bytes = (size_t)count * n_dims * 4;
+    if (ctx->ws_pending) QCPW_HIP(hipEventSynchronize(ctx->ws_done));
+    st = ctx->ws.ensure(bytes);
+    if (st != QCPW_OK) return st;
+    st = launch_sobol_points(ctx, seed, shift_index, n_dims, k0, count, (uint32_t *)ctx->ws.ptr, ctx->own_stream);
+    if (st != QCPW_OK) return st;
+    QCPW_HIP(hipMemcpyAsync(out, ctx->ws.ptr, bytes, hipMemcpyDeviceToHost, ctx->own_stream));
+    QCPW_HIP(hipStreamSynchronize(ctx->own_stream));
+    return QCPW_OK;
+}
+
+qcpw_status qcpw_path_factor(int32_t path_construction, int32_t d, double T, double *out)
+{
+    g_last_error.clear();
+    if (!out) return fail(QCPW_EINVAL, "out is NULL");
+    if (path_construction != QCPW_PATH_BB && path_construction != QCPW_PATH_PCA &&
+        path_construction != QCPW_PATH_STANDARD)
+        return fail(QCPW_EINVAL, "unknown path_construction");
+    const int dmax = path_construction == QCPW_PATH_PCA ? QCPW_MAX_D_PCA : QCPW_MAX_D;
+    if (d < 1 || d > dmax) return fail(QCPW_EDIMS, "d out of range");
+    if (!(T > 0) || !std::isfinite(T)) return fail(QCPW_EINVAL, "T must be finite and > 0");
+    std::vector<double> A;
+    build_factor(path_construction, d - 1, T / d, A);
+    if (!A.empty()) memcpy(out, A.data(), A.size() * sizeof(double));
+    return QCPW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,857 @@
+// kernels.hip -- the fused per-path QMC-CPW kernel for gfx950 (MI355X), the
+// per-replication finalize kernel, and their launch planning.
+//
+// One persistent launch covers every option of a call.  Work units are
+// (option, replication l, chunk of QCPW_CHUNK consecutive Sobol points);
+// workgroups pull units from a device counter.  Inside a unit each wave owns
+// a contiguous range of points and each lane one point per iteration, so for
+// point k = base + lane (base a multiple of 64):
+//
+//   Sobol integer of dimension j (Sec. 2.2.2, XOR form of
+//   eqn:GeneratorMatrixExpression, Gray-code order):
+//       y_j = lane_table[j][lane]  XOR  U_j(base),
+//   where U_j(base) = dir_j . gray(base) XOR s_{l,j} is the same for the
+//   whole wave (the digital shift of Sec. 2.2.3 is folded in).  Stepping to
+//   the next base changes U_j by two direction numbers only.  U is held in
+//   registers, distributed over the lanes in the order the path consumes the
+//   dimensions, and broadcast with v_readlane.
+//
+//   Inverse normal, path construction (Sec. 3.4.1 W~ = A z, Sec. 4.4 bridge
+//   or Alg. 3 increments), exponentials and running sums (Sec. 4.1: nothing
+//   about the path is stored) all stay in registers / LDS.  The path is
+//   built directly in log2 space, Y_m = log2(S~(t_{m+1}) / S0), so each date
+//   costs one exp2.
+//
+//   Per path, in FP64: breakpoint psi of the conditioned normal x_1
+//   (Sec. 3.4.2), Phi tails, and price/delta/vega/gamma (Sec. 4.5), added
+//   into compensated per-lane sums; wave shuffles, then LDS, reduce them to
+//   one partial per unit.  The finalize kernel adds a replication's partials
+//   in chunk order and forms mean and standard error over replications
+//   (Sec. 5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "qcpw_host.h"
+
+namespace qcpw {
+
+#include "ninv_f32_coeffs.inc"
+
+// ------------------------------------------------------------------------
+// device helpers
+// ------------------------------------------------------------------------
+
+// SplitMix64 (Steele, Lea, Flood 2014): output i of the generator seeded
+// with `seed` is the variant-13 mixer applied to seed + (i + 1) * gamma.
+__device__ __host__ inline uint64_t splitmix64_out(uint64_t seed, uint64_t i)
+{
+    uint64_t x = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__device__ inline uint32_t digital_shift(uint64_t seed, int l, int j)
+{
+    return (uint32_t)(splitmix64_out(seed, ((uint64_t)l << 16) | (uint64_t)j) >> 32);
+}
+
+template <int N>
+__device__ inline float horner(const float (&c)[N], float v)
+{
+    float p = c[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) p = fmaf(p, v, c[i]);
+    return p;
+}
+
+// Phi^{-1}((y + 1/2) 2^-32) * scale in FP32.
+// With m = min(y, ~y) (so the uniform is folded onto (0, 1/2]) the two
+// quantities that lose no precision are q = (m + 1/2) 2^-32 and
+// |x| = 1 - 2q = (2 (2^31 - 1 - m) + 1) 2^-32, both formed from integers.
+// Phi^{-1}(u) = sqrt(2) erfinv(2u - 1), and erfinv(x)/x is a polynomial in
+// w = -ln(1 - x^2) = -ln(4 q (1 - q)) (two branches, coefficients in
+// ninv_f32_coeffs.inc).  The sign is + iff y >= 2^31.
+__device__ inline float ninv_scaled_f32(uint32_t y, float scale)
+{
+    const uint32_t neg = (uint32_t)((int32_t)y >> 31);   // all ones iff y >= 2^31
+    const uint32_t m = y ^ neg;
+    const float q = fmaf((float)m, 0x1p-32f, 0x1p-33f);
+    const float ax = fmaf((float)(m ^ 0x7FFFFFFFu), 0x1p-31f, 0x1p-32f);
+    const float t = fmaf(-q, q, q);                       // q (1 - q) = (1 - x^2) / 4
+    const float lg = __builtin_amdgcn_logf(t);            // log2 t
+    constexpr float LN2 = 0.693147180559945309f;
+    constexpr float LG_SPLIT = -(QCPW_NINV_WSPLIT / 0.693147180559945309f) - 2.0f;
+    float p;
+    if (lg > LG_SPLIT) {
+        p = horner(QCPW_NINV_P, fmaf(lg, -LN2, -2.0f * LN2 - QCPW_NINV_C1));
+    } else {
+        const float w = fmaf(lg, -LN2, -2.0f * LN2);
+        p = horner(QCPW_NINV_Q, __builtin_amdgcn_sqrtf(w) - QCPW_NINV_C2);
+    }
+    const float k = neg ? scale : -scale;                 // scale already holds sqrt(2)
+    return (p * ax) * k;
+}
+
+// Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library), evaluated on the
+// lower half so that 1 - u never has to be formed.
+__device__ inline double ninv_f64(uint32_t y)
+{
+    const uint32_t neg = (uint32_t)((int32_t)y >> 31);
+    const uint32_t m = y ^ neg;
+    const double x = normcdfinv(((double)m + 0.5) * 0x1p-32);   // <= 0
+    return neg ? -x : x;
+}
+
+__device__ inline float exp2_r(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ inline double exp2_r(double x) { return exp2(x); }
+
+// Knuth two-sum: s + c accumulates x with the rounding error kept in c.
+__device__ inline void acc_add(double &s, double &c, double x)
+{
+    const double t = s + x;
+    const double bp = t - s;
+    c += (s - (t - bp)) + (x - bp);
+    s = t;
+}
+
+// Combine compensated pairs across the wave (xor butterfly, fixed order).
+__device__ inline void wave_reduce(double &s, double &c)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double s2 = __shfl_xor(s, off, 64);
+        const double c2 = __shfl_xor(c, off, 64);
+        const double t = s + s2;
+        const double bp = t - s;
+        const double e = (s - (t - bp)) + (s2 - bp);
+        s = t;
+        c = (c + c2) + e;
+    }
+}
+
+__device__ inline uint32_t rdlane(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+template <typename R>
+struct PathSums {
+    R A1, A2y, A2m;   // sum E_m, sum E_m Y_m, sum E_m m   (averages)
+    R bE, bY, bm;     // running max of E_m, its Y_m and m (lookback)
+};
+
+template <typename R, bool MAX>
+__device__ inline void consume(PathSums<R> &ps, R Y, R mf)
+{
+    const R E = exp2_r(Y);
+    if (MAX) {
+        const bool take = (E > ps.bE) || (E == ps.bE && mf < ps.bm);   // lowest index wins ties
+        ps.bE = take ? E : ps.bE;
+        ps.bY = take ? Y : ps.bY;
+        ps.bm = take ? mf : ps.bm;
+    } else {
+        ps.A1 += E;
+        ps.A2y = fma(E, Y, ps.A2y);
+        ps.A2m = fma(E, mf, ps.A2m);
+    }
+}
+
+// price, delta, vega, gamma of the smoothed payoff for one path (Sec. 4.5),
+// from the path statistic X = S0 * a (a = A1/d or max E) and its sigma
+// derivative.  All FP64.
+__device__ inline void path_greeks(const OptDev &op, double lnA, double Xs, double VXs, double F[4])
+{
+    // X = S0 * Xs, V_X = S0 * VXs
+    const double psi = (op.c0 - lnA) * op.inv_s1;
+    const double Q0 = 0.5 * erfc(psi * M_SQRT1_2);
+    const double Q1 = 0.5 * erfc((psi - op.s1) * M_SQRT1_2);
+    const double phi0 = exp(-0.5 * psi * psi) * 0.398942280401432677939946;
+    if (op.type == QCPW_BINARY_ASIAN_CALL) {
+        const double Dphi = op.D * phi0;
+        F[0] = op.D * Q0;
+        F[1] = Dphi * op.inv_s1 * op.inv_S0;
+        F[2] = Dphi * (VXs / Xs * op.inv_s1 + psi * op.inv_sigma - op.sqrt_t1);
+        F[3] = Dphi * op.inv_s1 * op.inv_S0sq * (psi * op.inv_s1 - 1.0);
+    } else {
+        const double X = op.S0 * Xs;
+        const double DKphi = op.D * op.K * phi0;
+        F[0] = op.D1 * X * Q1 - op.D * op.K * Q0;
+        F[1] = op.D1 * Xs * Q1;
+        F[2] = op.D1 * Q1 * (op.S0 * VXs) + DKphi * op.sqrt_t1;
+        F[3] = DKphi * op.inv_s1 * op.inv_S0sq;
+    }
+}
+
+template <typename R>
+__device__ inline void path_tail(const OptDev &op, const PathSums<R> &ps, bool is_max, double F[4])
+{
+    double lnA, Xs, VXs;
+    if (is_max) {
+        const double bE = (double)ps.bE;
+        lnA = log(bE);
+        Xs = bE;
+        VXs = bE * ((double)ps.bY - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
+    } else {
+        const double A1 = (double)ps.A1;
+        lnA = log(A1);                          // ln d is folded into c0
+        Xs = A1 * op.invd;
+        VXs = ((double)ps.A2y - op.kappa * (double)ps.A2m) * op.invd * op.inv_sig_log2e;
+    }
+    path_greeks(op, lnA, Xs, VXs, F);
+}
+
+template <typename R>
+__device__ inline void init_sums(PathSums<R> &ps)
+{
+    ps.A1 = R(1); ps.A2y = R(0); ps.A2m = R(0);   // date 1: S~ = S0, Y = 0
+    ps.bE = R(1); ps.bY = R(0); ps.bm = R(0);
+}
+
+template <bool F32>
+struct Real;
+template <>
+struct Real<true> { using T = float; };
+template <>
+struct Real<false> { using T = double; };
+
+// Sobol + shift + inverse normal for one coordinate, result in Y units.
+template <bool F32>
+__device__ inline typename Real<F32>::T coord(uint32_t y, const OptDev &op)
+{
+    if constexpr (F32) {
+        return ninv_scaled_f32(y, op.zscale_f);
+    } else {
+        return ninv_f64(y) * op.zscale;
+    }
+}
+
+// ------------------------------------------------------------------------
+// the fused per-path kernel
+// ------------------------------------------------------------------------
+struct UnitCtx {
+    int64_t unit;
+    int o;
+    int shift;
+    int64_t chunk;
+};
+
+template <bool F32, bool MAX>
+__device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
+                                       typename Real<F32>::T *lds_stack, int tid, int lane,
+                                       const uint32_t (&U)[QCPW_UQ], PathSums<typename Real<F32>::T> &ps)
+{
+    using R = typename Real<F32>::T;
+    const int n = op.n;
+    const int bd = blockDim.x;
+    const PlanStep *plan = ld.plan + op.plan_off;
+    const PlanStep64 *plan64 = ld.plan64 + op.plan_off;
+    R L = R(0), Rr;
+    {   // terminal point
+        const PlanStep st = plan[0];
+        const uint32_t y = lds_lane[st.lds_off + lane] ^ rdlane(U[0], 0);
+        const R z = coord<F32>(y, op);
+        const R sd = F32 ? (R)st.sd : (R)plan64[0].sd;
+        const R drift = F32 ? (R)op.ydrift_n_f : (R)op.ydrift_n;
+        Rr = fma(sd, z, drift);
+        consume<R, MAX>(ps, Rr, F32 ? (R)st.mf : (R)plan64[0].mf);
+    }
+    int sp = 0;
+#pragma unroll
+    for (int q = 0; q < QCPW_UQ; ++q) {
+        const int s_lo = q == 0 ? 1 : 64 * q;
+        const int s_hi = min(64 * (q + 1), n);
+        for (int s = s_lo; s < s_hi; ++s) {
+            const PlanStep st = plan[s];
+            for (int p = 0; p < st.pops; ++p) {
+                L = Rr;
+                --sp;
+                Rr = lds_stack[sp * bd + tid];
+            }
+            const uint32_t y = lds_lane[st.lds_off + lane] ^ rdlane(U[q], s - 64 * q);
+            const R z = coord<F32>(y, op);
+            R Ym;
+            R mf;
+            if constexpr (F32) {
+                Ym = fmaf(st.sd, z, fmaf(st.wr, Rr, st.wl * L));
+                mf = st.mf;
+            } else {
+                const PlanStep64 s64 = plan64[s];
+                Ym = fma(s64.sd, z, fma(s64.wr, Rr, s64.wl * L));
+                mf = s64.mf;
+            }
+            lds_stack[sp * bd + tid] = Rr;
+            ++sp;
+            Rr = Ym;
+            consume<R, MAX>(ps, Ym, mf);
+        }
+        if (s_hi >= n) break;
+    }
+}
+
+template <bool F32, bool MAX>
+__device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, int lane,
+                                         const uint32_t (&U)[QCPW_UQ], PathSums<typename Real<F32>::T> &ps)
+{
+    using R = typename Real<F32>::T;
+    const int n = op.n;
+    const R drift = F32 ? (R)op.ydrift_1_f : (R)op.ydrift_1;
+    R Y = R(0);
+#pragma unroll
+    for (int q = 0; q < QCPW_UQ; ++q) {
+        const int s_hi = min(64 * (q + 1), n);
+        for (int s = 64 * q; s < s_hi; ++s) {
+            const uint32_t y = lds_lane[s * 64 + lane] ^ rdlane(U[q], s - 64 * q);
+            const R z = coord<F32>(y, op);
+            Y = Y + (drift + z);
+            consume<R, MAX>(ps, Y, (R)(s + 1));
+        }
+        if (s_hi >= n) break;
+    }
+}
+
+// U_j(base) for the dimensions this lane holds: steps s = lane + 64 q.
+template <int PATHK>
+__device__ inline int step_dim(const LaunchDesc &ld, const OptDev &op, int s)
+{
+    return (PATHK == QCPW_PATH_BB) ? ld.plan[op.plan_off + s].dim : s + 1;
+}
+
+template <int PATHK>
+__device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op, int shift, int lane,
+                                         uint64_t base, uint32_t (&U)[QCPW_UQ])
+{
+    const uint64_t g = (base ^ (base >> 1)) >> 5;   // gray(base) has no bits below 5
+#pragma unroll
+    for (int q = 0; q < QCPW_UQ; ++q) {
+        const int s = lane + 64 * q;
+        int dim;
+        uint32_t u = 0;
+        if (s < op.n) {
+            dim = step_dim<PATHK>(ld, op, s);
+            u = digital_shift(op.seed, shift, dim);
+            const uint32_t *v = ld.dir + (size_t)dim * 32;
+            uint64_t gg = g;
+            for (int b = 5; gg != 0; ++b, gg >>= 1)
+                if (gg & 1) u ^= v[b];
+        }
+        U[q] = u;
+    }
+}
+
+// base -> base + 64: gray changes in bits 5 and 6 + ctz(base/64 + 1).
+template <int PATHK>
+__device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op, int lane, uint64_t base,
+                                         uint32_t (&U)[QCPW_UQ])
+{
+    const int c = __builtin_ctzll((base >> 6) + 1);
+#pragma unroll
+    for (int q = 0; q < QCPW_UQ; ++q) {
+        const int s = lane + 64 * q;
+        if (s < op.n) {
+            const uint32_t *v = ld.dir + (size_t)step_dim<PATHK>(ld, op, s) * 32;
+            U[q] ^= v[5] ^ v[6 + c];
+        }
+    }
+}
+
+template <bool F32, int PATHK>
+__global__ __launch_bounds__(1024) void paths_kernel(const OptDev *__restrict__ opts,
+                                                     const int64_t *__restrict__ unit_prefix,
+                                                     const PlanStep *__restrict__ plan_all,
+                                                     const PlanStep64 *__restrict__ plan64_all,
+                                                     const uint32_t *__restrict__ dir,
+                                                     const uint32_t *__restrict__ lane_tab,
+                                                     double *__restrict__ partials,
+                                                     unsigned long long *__restrict__ counter,
+                                                     int n_opts, int max_n, int stack_depth,
+                                                     long long total_units)
+{
+    LaunchDesc ld;
+    ld.opts = opts;
+    ld.unit_prefix = unit_prefix;
+    ld.n_opts = n_opts;
+    ld.max_n = max_n;
+    ld.total_units = total_units;
+    ld.plan = plan_all;
+    ld.plan64 = plan64_all;
+    ld.dir = dir;
+    ld.lane = lane_tab;
+    ld.partials = partials;
+    ld.counter = counter;
+    using R = typename Real<F32>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long s_unit;
+    const int bd = blockDim.x;
+    const int nwaves = bd >> 6;
+    uint32_t *lds_lane = (uint32_t *)smem;                                    // [max_n][64]
+    const size_t lane_bytes = (size_t)ld.max_n * 64 * 4;
+    R *lds_stack = (R *)(smem + lane_bytes);                                  // [stack][bd]
+    const size_t stack_bytes = PATHK == QCPW_PATH_BB ? (size_t)stack_depth * bd * sizeof(R) : 0;
+    double *lds_red = (double *)(smem + lane_bytes + stack_bytes);            // [nwaves][8]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int loaded_n = 0;
+    int o = 0;
+
+    for (;;) {
+        if (tid == 0) s_unit = (long long)atomicAdd(ld.counter, 1ull);
+        __syncthreads();
+        const long long unit_v = s_unit;
+        const long long unit = ((long long)__builtin_amdgcn_readfirstlane((int)(unit_v >> 32)) << 32) |
+                               (unsigned)__builtin_amdgcn_readfirstlane((int)unit_v);
+        __syncthreads();
+        if (unit >= ld.total_units) break;
+
+        // option of this unit (units are consumed in increasing order, so the
+        // previous option is the usual answer)
+        if (!(ld.unit_prefix[o] <= unit && unit < ld.unit_prefix[o + 1])) {
+            int lo = 0, hi = ld.n_opts - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (ld.unit_prefix[mid] <= unit) lo = mid; else hi = mid - 1;
+            }
+            o = lo;
+        }
+        const OptDev &op = opts[o];
+        const int64_t rem = unit - op.unit0;
+        const int shift = (int)(rem / op.chunks);
+        const int64_t chunk = rem - (int64_t)shift * op.chunks;
+
+        if (op.n > loaded_n) {
+            for (int i = loaded_n * 64 + tid; i < op.n * 64; i += bd) lds_lane[i] = ld.lane[64 + i];
+            loaded_n = op.n;
+            __syncthreads();
+        }
+
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        double c[4] = {0.0, 0.0, 0.0, 0.0};
+        const int64_t per_wave = QCPW_CHUNK / nwaves;
+        const int64_t k_end = op.k_begin + op.n_points;
+        const int64_t start = op.k_begin + chunk * QCPW_CHUNK + (int64_t)wave * per_wave;
+        const int64_t end = min(start + per_wave, k_end);
+        if (start < k_end) {
+            uint32_t U[QCPW_UQ];
+            init_uniform_part<PATHK>(ld, op, shift, lane, (uint64_t)start, U);
+            for (int64_t base = start; base < end; base += 64) {
+                const bool valid = base + lane < k_end;
+                double F[4] = {0.0, 0.0, 0.0, 0.0};
+                PathSums<R> ps;
+                init_sums(ps);
+                const bool is_max = op.type == QCPW_LOOKBACK_FIXED_CALL;
+                if (op.n > 0) {
+                    if (PATHK == QCPW_PATH_BB) {
+                        if (is_max) run_bridge_wave<F32, true>(ld, op, lds_lane, lds_stack, tid, lane, U, ps);
+                        else run_bridge_wave<F32, false>(ld, op, lds_lane, lds_stack, tid, lane, U, ps);
+                    } else {
+                        if (is_max) run_standard_wave<F32, true>(op, lds_lane, lane, U, ps);
+                        else run_standard_wave<F32, false>(op, lds_lane, lane, U, ps);
+                    }
+                }
+                if (valid) path_tail<R>(op, ps, is_max, F);
+                if (valid) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc_add(s[i], c[i], F[i]);
+                }
+                if (base + 64 < end) step_uniform_part<PATHK>(ld, op, lane, (uint64_t)base, U);
+            }
+        }
+        // unit reduction: wave butterflies, then wave 0 over the waves
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wave_reduce(s[i], c[i]);
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                lds_red[wave * 8 + i] = s[i];
+                lds_red[wave * 8 + 4 + i] = c[i];
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double ss = lane < nwaves ? lds_red[lane * 8 + i] : 0.0;
+                double cc = lane < nwaves ? lds_red[lane * 8 + 4 + i] : 0.0;
+                wave_reduce(ss, cc);
+                if (lane == 0) {
+                    ld.partials[unit * 8 + i] = ss;
+                    ld.partials[unit * 8 + 4 + i] = cc;
+                }
+            }
+        }
+    }
+}
+
+__global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
+
+// One block per option: replication estimates C_l (chunk partials added in
+// chunk order), then the mean over replications and its standard error.
+// per_shift: [n_opts(caller order)][L][4].
+__global__ __launch_bounds__(256) void finalize_kernel(const OptDev *opts, const double *partials,
+                                                       double *per_shift, double *out_mean,
+                                                       double *out_stderr)
+{
+    __shared__ double red_s[256], red_c[256];
+    const OptDev &op = opts[blockIdx.x];
+    const int L = op.n_shifts;
+    const int t = threadIdx.x;
+    double *Cl = per_shift + (size_t)op.out_index * L * 4;
+    const double invN = 1.0 / (double)op.n_points;
+    for (int l = t; l < L; l += blockDim.x) {
+        for (int i = 0; i < 4; ++i) {
+            double S = 0.0, C = 0.0;
+            for (int64_t k = 0; k < op.chunks; ++k) {
+                const double *p = partials + (op.unit0 + (int64_t)l * op.chunks + k) * 8;
+                const double t2 = S + p[i];
+                const double bp = t2 - S;
+                C += (S - (t2 - bp)) + (p[i] - bp) + p[4 + i];
+                S = t2;
+            }
+            Cl[l * 4 + i] = (S + C) * invN;
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < 4; ++i) {
+        // mean: strided compensated sums, then a fixed pairwise tree
+        double S = 0.0, C = 0.0;
+        for (int l = t; l < L; l += blockDim.x) acc_add(S, C, Cl[l * 4 + i]);
+        red_s[t] = S;
+        red_c[t] = C;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+            if (t < w) {
+                const double a = red_s[t], b = red_s[t + w];
+                const double s2 = a + b, bp = s2 - a;
+                red_c[t] = red_c[t] + red_c[t + w] + ((a - (s2 - bp)) + (b - bp));
+                red_s[t] = s2;
+            }
+            __syncthreads();
+        }
+        const double mean = (red_s[0] + red_c[0]) / (double)L;
+        __syncthreads();
+        double V = 0.0;
+        for (int l = t; l < L; l += blockDim.x) {
+            const double dv = Cl[l * 4 + i] - mean;
+            V += dv * dv;
+        }
+        red_s[t] = V;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+            if (t < w) red_s[t] += red_s[t + w];
+            __syncthreads();
+        }
+        if (t == 0) {
+            out_mean[op.out_index * 4 + i] = mean;
+            out_stderr[op.out_index * 4 + i] =
+                L >= 2 ? sqrt(red_s[0] / ((double)L * (double)(L - 1))) : NAN;
+        }
+        __syncthreads();
+    }
+}
+
+// Shifted Sobol integers through the same lane-table / uniform-part split
+// the per-path kernel uses.  One wave per 64 consecutive points; out is
+// [count][n_dims].  k0 need not be a multiple of 64: the wave's base is
+// rounded down and lanes outside [k0, k0 + count) store nothing.
+__global__ __launch_bounds__(64) void sobol_points_kernel(const uint32_t *dir, const uint32_t *lane_tab,
+                                                          uint64_t seed, int shift, int n_dims, int64_t k0,
+                                                          int64_t count, uint32_t *out)
+{
+    const int lane = threadIdx.x;
+    const uint64_t base = ((uint64_t)k0 & ~63ull) + (uint64_t)blockIdx.x * 64;
+    const uint64_t k = base + lane;
+    const bool in = k >= (uint64_t)k0 && k < (uint64_t)(k0 + count);
+    const uint64_t g = (base ^ (base >> 1)) >> 5;
+    for (int j0 = 0; j0 < n_dims; j0 += 64) {
+        // lane holds U for dimension j0 + lane
+        const int jl = j0 + lane;
+        uint32_t u = 0;
+        if (jl < n_dims) {
+            u = jl == 0 ? 0u : digital_shift(seed, shift, jl);
+            uint64_t gg = g;
+            for (int b = 5; gg != 0; ++b, gg >>= 1)
+                if (gg & 1) u ^= dir[(size_t)jl * 32 + b];
+        }
+        const int jmax = min(64, n_dims - j0);
+        for (int jj = 0; jj < jmax; ++jj) {
+            const int j = j0 + jj;
+            const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(u, jj);
+            if (in) out[(size_t)(k - (uint64_t)k0) * n_dims + j] = y;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// launch planning (host)
+// ------------------------------------------------------------------------
+static inline bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t d, int64_t n_points,
+                          int32_t n_shifts, int32_t path, int32_t precision, int32_t pca_gemm,
+                          int32_t block_threads)
+{
+    if (!specs) return fail(QCPW_EINVAL, "option_specs is NULL");
+    if (n_opts < 1) return fail(QCPW_EINVAL, "n_opts must be >= 1");
+    if (n_shifts < 1 || n_shifts > QCPW_MAX_SHIFTS) return fail(QCPW_EINVAL, "n_shifts out of range");
+    if (path != QCPW_PATH_BB && path != QCPW_PATH_PCA && path != QCPW_PATH_STANDARD)
+        return fail(QCPW_EINVAL, "unknown path_construction");
+    if (precision != QCPW_FP64 && precision != QCPW_FP32_MIXED) return fail(QCPW_EINVAL, "unknown precision");
+    if (pca_gemm != QCPW_GEMM_FP32 && pca_gemm != QCPW_GEMM_BF16X3) return fail(QCPW_EINVAL, "unknown pca_gemm");
+    if (block_threads != 0 && block_threads != 256 && block_threads != 512 && block_threads != 1024)
+        return fail(QCPW_EINVAL, "block_threads must be 0, 256, 512 or 1024");
+    if (d < 0 || n_points < 0) return fail(QCPW_EINVAL, "negative d or n_points");
+    const int dmax = path == QCPW_PATH_PCA ? QCPW_MAX_D_PCA : QCPW_MAX_D;
+    for (int i = 0; i < n_opts; ++i) {
+        const qcpw_option_spec &sp = specs[i];
+        const int di = d ? d : sp.d;
+        const int64_t Ni = n_points ? n_points : sp.n_points;
+        if (sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL &&
+            sp.type != QCPW_LOOKBACK_FIXED_CALL)
+            return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": unknown type");
+        if (di < 1) return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": d must be >= 1");
+        if (di > dmax)
+            return fail(QCPW_EDIMS, "option " + std::to_string(i) + ": d = " + std::to_string(di) +
+                                        " exceeds " + std::to_string(dmax) + " for this path construction");
+        if (Ni < 1 || Ni > (int64_t(1) << 32))
+            return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": n_points must be in [1, 2^32]");
+        if (!finite_pos(sp.S0) || !finite_pos(sp.K) || !finite_pos(sp.sigma) || !finite_pos(sp.T) ||
+            !std::isfinite(sp.r))
+            return fail(QCPW_EINVAL, "option " + std::to_string(i) +
+                                         ": S0, K, sigma, T must be finite and > 0, r finite");
+    }
+    return QCPW_OK;
+}
+
+qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
+                        int64_t n_points, int32_t n_shifts, int32_t path, int32_t precision,
+                        int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp, const int64_t *k_begin)
+{
+    {
+        qcpw_status st = validate_call(specs, n_opts, d, n_points, n_shifts, path, precision, pca_gemm,
+                                       block_threads);
+        if (st != QCPW_OK) return st;
+    }
+
+    lp = LaunchPlan();
+    lp.path = path;
+    lp.precision = precision;
+    lp.pca_gemm = pca_gemm;
+    lp.n_shifts = n_shifts;
+    std::vector<OptDev> opts(n_opts);
+    std::vector<double> cost(n_opts);
+    for (int i = 0; i < n_opts; ++i) {
+        const qcpw_option_spec &sp = specs[i];
+        const int di = d ? d : sp.d;
+        const int64_t Ni = n_points ? n_points : sp.n_points;
+        const int64_t kb = k_begin ? k_begin[i] : 0;
+        if (kb < 0 || kb % QCPW_CHUNK != 0 || kb + Ni > (int64_t(1) << 32))
+            return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": bad point range");
+        OptDev &op = opts[i];
+        memset(&op, 0, sizeof op);
+        op.type = sp.type;
+        op.d = di;
+        op.n = di - 1;
+        op.path = path;
+        op.n_points = Ni;
+        op.k_begin = kb;
+        op.seed = sp.seed;
+        op.n_shifts = n_shifts;
+        op.out_index = i;
+        op.chunks = (int32_t)((Ni + QCPW_CHUNK - 1) / QCPW_CHUNK);
+        op.plan_off = (path == QCPW_PATH_BB && op.n >= 1) ? ctx->tab.plan_off[op.n] : 0;
+        const double LOG2E = 1.4426950408889634074;
+        const double dt = sp.T / di, t1 = dt;
+        const double omega = sp.r - 0.5 * sp.sigma * sp.sigma;
+        op.zscale = sp.sigma * std::sqrt(dt) * LOG2E;
+        op.ydrift_n = omega * op.n * dt * LOG2E;
+        op.ydrift_1 = omega * dt * LOG2E;
+        op.kappa = (sp.r + 0.5 * sp.sigma * sp.sigma) * dt * LOG2E;
+        op.inv_sig_log2e = 1.0 / (sp.sigma * LOG2E);
+        op.s1 = sp.sigma * std::sqrt(t1);
+        op.inv_s1 = 1.0 / op.s1;
+        op.sqrt_t1 = std::sqrt(t1);
+        op.inv_sigma = 1.0 / sp.sigma;
+        op.c0 = std::log(sp.K) - std::log(sp.S0) - omega * t1 +
+                (sp.type == QCPW_LOOKBACK_FIXED_CALL ? 0.0 : std::log((double)di));
+        op.S0 = sp.S0;
+        op.K = sp.K;
+        op.D = std::exp(-sp.r * sp.T);
+        op.D1 = std::exp(sp.r * (t1 - sp.T));
+        op.invd = 1.0 / di;
+        op.inv_S0 = 1.0 / sp.S0;
+        op.inv_S0sq = 1.0 / (sp.S0 * sp.S0);
+        // FP32 kernels fold sqrt(2) of Phi^{-1}(u) = sqrt(2) erfinv(2u-1) into the scale
+        op.zscale_f = (float)(op.zscale * M_SQRT2);
+        op.ydrift_n_f = (float)op.ydrift_n;
+        op.ydrift_1_f = (float)op.ydrift_1;
+        op.kappa_f = (float)op.kappa;
+        cost[i] = (double)std::max(op.n, 1) * (double)op.chunks;
+        lp.max_n = std::max(lp.max_n, op.n);
+        if (path == QCPW_PATH_BB && op.n >= 1) lp.stack_depth = std::max(lp.stack_depth, ctx->tab.depth[op.n]);
+    }
+    // most expensive units first (longest-processing-time order)
+    std::vector<int32_t> order(n_opts);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return opts[a].n > opts[b].n; });
+    lp.opts.resize(n_opts);
+    lp.unit_prefix.assign(n_opts + 1, 0);
+    for (int i = 0; i < n_opts; ++i) {
+        lp.opts[i] = opts[order[i]];
+        lp.opts[i].unit0 = lp.unit_prefix[i];
+        lp.unit_prefix[i + 1] = lp.unit_prefix[i] + (int64_t)lp.opts[i].chunks * n_shifts;
+    }
+    lp.order = order;
+    lp.total_units = lp.unit_prefix[n_opts];
+    lp.block_threads = block_threads ? block_threads : autotune_block_threads(ctx, lp);
+    if (path == QCPW_PATH_PCA) {
+        lp.pca.resize(n_opts, nullptr);
+        for (int i = 0; i < n_opts; ++i) {
+            if (lp.opts[i].n == 0) continue;
+            const Context::Pca *pc = nullptr;
+            qcpw_status st = get_pca(ctx, lp.opts[i].n, 1.0, &pc);
+            if (st != QCPW_OK) return st;
+            lp.pca[i] = pc;
+        }
+    }
+    return QCPW_OK;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct WsLayout {
+    size_t opts, prefix, partials, per_shift, counter, total;
+};
+
+static WsLayout ws_layout(const LaunchPlan &lp)
+{
+    WsLayout w;
+    const size_t n = lp.opts.size();
+    w.opts = 0;
+    w.prefix = align_up(w.opts + n * sizeof(OptDev), 256);
+    w.partials = align_up(w.prefix + (n + 1) * sizeof(int64_t), 256);
+    w.per_shift = align_up(w.partials + (size_t)lp.total_units * 8 * sizeof(double), 256);
+    w.counter = align_up(w.per_shift + n * (size_t)lp.n_shifts * 4 * sizeof(double), 256);
+    w.total = align_up(w.counter + 256, 256);
+    return w;
+}
+
+size_t launch_workspace_bytes(const LaunchPlan &lp) { return ws_layout(lp).total; }
+
+static size_t paths_lds_bytes(const LaunchPlan &lp, int bd)
+{
+    const size_t lane_bytes = (size_t)lp.max_n * 64 * 4;
+    const size_t elem = lp.precision == QCPW_FP32_MIXED ? 4 : 8;
+    const size_t stack = lp.path == QCPW_PATH_BB ? (size_t)lp.stack_depth * bd * elem : 0;
+    return lane_bytes + stack + (size_t)(bd / 64) * 8 * sizeof(double);
+}
+
+template <bool F32, int PATHK>
+static const void *paths_fn()
+{
+    return reinterpret_cast<const void *>(&paths_kernel<F32, PATHK>);
+}
+
+static const void *select_paths_kernel(const LaunchPlan &lp)
+{
+    const bool f32 = lp.precision == QCPW_FP32_MIXED;
+    if (lp.path == QCPW_PATH_STANDARD) return f32 ? paths_fn<true, QCPW_PATH_STANDARD>() : paths_fn<false, QCPW_PATH_STANDARD>();
+    return f32 ? paths_fn<true, QCPW_PATH_BB>() : paths_fn<false, QCPW_PATH_BB>();
+}
+
+// Workgroup size: large lane tables want one big workgroup per CU sharing
+// them; small ones leave room for several workgroups of 512.  The choice is
+// capped by what fits in LDS.
+int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
+{
+    (void)ctx;
+    if (lp.path == QCPW_PATH_PCA) return 256;
+    int bd = lp.max_n > 160 ? 1024 : 512;
+    while (bd > 256 && paths_lds_bytes(lp, bd) > 160 * 1024) bd /= 2;
+    return bd;
+}
+
+qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, const LaunchDesc &ld,
+                        const OptDev *d_opts);
+
+qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream, double *dev_out_greeks,
+                           double *dev_out_stderr, double *dev_out_per_shift, void *ws, size_t ws_bytes)
+{
+    const WsLayout w = ws_layout(lp);
+    if (ws_bytes < w.total) return fail(QCPW_ENOMEM, "workspace too small");
+    char *base = (char *)ws;
+    OptDev *d_opts = (OptDev *)(base + w.opts);
+    int64_t *d_prefix = (int64_t *)(base + w.prefix);
+    double *d_partials = (double *)(base + w.partials);
+    double *d_per_shift = dev_out_per_shift ? dev_out_per_shift : (double *)(base + w.per_shift);
+    unsigned long long *d_counter = (unsigned long long *)(base + w.counter);
+    const size_t n = lp.opts.size();
+    QCPW_HIP(hipMemcpyAsync(d_opts, lp.opts.data(), n * sizeof(OptDev), hipMemcpyHostToDevice, stream));
+    QCPW_HIP(hipMemcpyAsync(d_prefix, lp.unit_prefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    reset_counter_kernel<<<1, 1, 0, stream>>>(d_counter);
+    QCPW_HIP(hipGetLastError());
+
+    LaunchDesc ld;
+    ld.opts = d_opts;
+    ld.unit_prefix = d_prefix;
+    ld.n_opts = (int32_t)n;
+    ld.max_n = lp.max_n;
+    ld.total_units = lp.total_units;
+    ld.plan = ctx->tab.plan;
+    ld.plan64 = ctx->tab.plan64;
+    ld.dir = ctx->tab.dir;
+    ld.lane = ctx->tab.lane;
+    ld.partials = d_partials;
+    ld.counter = d_counter;
+
+    if (lp.path == QCPW_PATH_PCA) {
+        qcpw_status st = enqueue_pca(ctx, lp, stream, ld, d_opts);
+        if (st != QCPW_OK) return st;
+    } else {
+        const int bd = lp.block_threads;
+        const size_t lds = paths_lds_bytes(lp, bd);
+        if (lds > 160 * 1024) return fail(QCPW_EDIMS, "LDS footprint exceeds 160 KiB");
+        const void *fn = select_paths_kernel(lp);
+        QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        int per_cu = 0;
+        QCPW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds));
+        if (per_cu < 1) return fail(QCPW_EDEVICE, "per-path kernel cannot be resident with this block size");
+        int64_t grid = (int64_t)per_cu * ctx->tab.n_cu;
+        grid = std::min<int64_t>(grid, lp.total_units);
+        const OptDev *a_opts = ld.opts;
+        const int64_t *a_prefix = ld.unit_prefix;
+        const PlanStep *a_plan = ld.plan;
+        const PlanStep64 *a_plan64 = ld.plan64;
+        const uint32_t *a_dir = ld.dir, *a_lane = ld.lane;
+        double *a_part = ld.partials;
+        unsigned long long *a_ctr = ld.counter;
+        int a_nopts = ld.n_opts, a_maxn = ld.max_n, a_depth = lp.stack_depth;
+        long long a_total = ld.total_units;
+        void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_dir, &a_lane, &a_part, &a_ctr,
+                        &a_nopts, &a_maxn, &a_depth, &a_total};
+        QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
+    }
+    finalize_kernel<<<(unsigned)n, 256, 0, stream>>>(d_opts, d_partials, d_per_shift, dev_out_greeks, dev_out_stderr);
+    QCPW_HIP(hipGetLastError());
+    return QCPW_OK;
+}
+
+qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index, int32_t n_dims, int64_t k0,
+                                int64_t count, uint32_t *dev_out, hipStream_t stream)
+{
+    const int64_t first = k0 & ~int64_t(63);
+    const int64_t blocks = (k0 + count - first + 63) / 64;
+    sobol_points_kernel<<<(unsigned)blocks, 64, 0, stream>>>(ctx->tab.dir, ctx->tab.lane, seed, shift_index,
+                                                             n_dims, k0, count, dev_out);
+    QCPW_HIP(hipGetLastError());
+    return QCPW_OK;
+}
+
+}  // namespace qcpw

@@ -1,0 +1,114 @@
+// qcpw_host.h -- host-side declarations of the QMC-CPW library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/qmc_cpw.h"
+#include "qcpw_internal.h"
+
+namespace qcpw {
+
+// ---- tables.cpp -----------------------------------------------------------
+void build_direction_numbers(std::vector<uint32_t> &dir);
+void build_lane_table(const std::vector<uint32_t> &dir, std::vector<uint32_t> &lane);
+int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep64> &steps64);
+void build_pca_factor(int n, double dt, std::vector<double> &A);
+void build_factor(int path, int n, double dt, std::vector<double> &A);
+
+// ---- errors ---------------------------------------------------------------
+void set_error(const std::string &msg);
+qcpw_status fail(qcpw_status code, const std::string &msg);
+#define QCPW_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::qcpw::fail(QCPW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---- device context (one per device, lives until process exit) -----------
+struct DeviceTables {
+    int device = -1;
+    int n_cu = 0;
+    uint32_t *dir = nullptr;     // [QCPW_TAB_DIMS][32]
+    uint32_t *lane = nullptr;    // [QCPW_TAB_DIMS][64]
+    PlanStep *plan = nullptr;    // all bridge plans, n = 1..QCPW_MAX_N
+    PlanStep64 *plan64 = nullptr;
+    std::vector<int32_t> plan_off;   // [QCPW_MAX_N + 1]
+    std::vector<int32_t> depth;      // [QCPW_MAX_N + 1] bridge stack depth per n
+    int max_stack = 0;
+};
+
+// Grow-only device workspace.
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    qcpw_status ensure(size_t need);
+};
+
+struct Context {
+    std::mutex mu;               // serialises launches on this device
+    DeviceTables tab;
+    hipStream_t own_stream = nullptr;
+    Workspace ws;                // per-launch device buffers
+    hipEvent_t ws_done = nullptr;   // recorded after the last launch that used ws
+    bool ws_pending = false;
+    // PCA factors, keyed by (n, dt bits)
+    struct Pca { int n; double dt; float *A32 = nullptr; double *A64 = nullptr;
+                 uint16_t *Ahi = nullptr, *Alo = nullptr; };
+    std::deque<Pca> pca;     // deque: pointers stay valid as factors are added
+};
+
+qcpw_status get_context(int device, Context **out);
+qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out);
+
+// ---- launches (kernels.hip) -------------------------------------------------
+struct LaunchPlan {
+    // host copies of what the kernels read
+    std::vector<OptDev> opts;          // sorted by cost (descending)
+    std::vector<int64_t> unit_prefix;  // [n_opts + 1]
+    std::vector<int32_t> order;        // opts[i] is caller's option order[i]
+    int max_n = 0;
+    int stack_depth = 0;               // deepest bridge stack among the options
+    int path = 0;
+    int precision = 0;
+    int pca_gemm = 0;
+    int n_shifts = 0;
+    int block_threads = 0;
+    int64_t total_units = 0;
+    std::vector<const Context::Pca *> pca;   // per sorted option (PCA only)
+};
+
+// Argument checks of a Greeks call (host only, no device needed).
+qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t d, int64_t n_points,
+                          int32_t n_shifts, int32_t path, int32_t precision, int32_t pca_gemm,
+                          int32_t block_threads);
+
+// Builds the per-option constants and work units.  k_begin (optional, per
+// caller option) starts an option's points at a multiple of QCPW_CHUNK
+// instead of 0; n_points then counts the points from there.
+qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
+                        int64_t n_points, int32_t n_shifts, int32_t path, int32_t precision,
+                        int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp,
+                        const int64_t *k_begin = nullptr);
+
+// Device bytes one launch needs in the workspace.
+size_t launch_workspace_bytes(const LaunchPlan &lp);
+
+// Enqueues the whole hot path on `stream`: uploads, the per-path kernel, the
+// finalize kernel; results go to dev_out_greeks / dev_out_stderr ([n][4],
+// caller order) and optionally dev_out_per_shift ([n][L][4]).
+qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream,
+                           double *dev_out_greeks, double *dev_out_stderr,
+                           double *dev_out_per_shift, void *ws, size_t ws_bytes);
+
+qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index, int32_t n_dims,
+                                int64_t k0, int64_t count, uint32_t *dev_out, hipStream_t stream);
+
+int autotune_block_threads(Context *ctx, const LaunchPlan &lp);
+
+}  // namespace qcpw

@@ -1,0 +1,84 @@
+// qcpw_internal.h -- structures shared by the host library and the kernels.
+//
+// Device-resident tables (built once per device, kept for the process):
+//   * dir[QCPW_TAB_DIMS][32]   Sobol direction numbers, dir[j][b] = g_{b+1} of
+//                              dimension j as a 32-bit binary fraction.
+//   * lane[QCPW_TAB_DIMS][64]  the low part of every point inside a wave:
+//                              lane[j][t] = XOR of dir[j][b] over the set bits
+//                              b of gray(t), t = 0..63.  Because point
+//                              k = base + t with base a multiple of 64 has
+//                              gray(k) = gray(base) XOR gray(t), the Sobol
+//                              integer is lane[j][t] XOR (dir_j . gray(base)),
+//                              and the second term is the same for the whole
+//                              wave.
+//   * bridge plans             one per n = d - 1 (see PlanStep).
+// Per launch:
+//   * OptDev[n_opts]           derived FP64 / FP32 constants of each option.
+//   * unit prefix              work units (option, replication, chunk) of each
+//                              option, options sorted by cost.
+//   * partials[units][8]       per-chunk compensated sums (4 values + errors).
+#pragma once
+#include <stdint.h>
+
+#define QCPW_TAB_DIMS 1024       // Sobol dimensions held on the device
+#define QCPW_MAX_N 384           // conditioned coordinates in the fused kernel
+#define QCPW_UQ 6                // QCPW_MAX_N / 64 registers of wave-uniform state
+#define QCPW_CHUNK 8192          // points per work unit (canonical; not tuned)
+#define QCPW_STACK_MAX 12        // bridge stack depth bound (ceil log2 QCPW_MAX_N + 2)
+#define QCPW_PCA_NPAD 256        // padded factor size of the matrix-core PCA kernel
+
+// One step of a bridge plan, in the order the kernel walks the bridge: the
+// intervals of the breadth-first bridge are visited depth first, so that only
+// a short stack of right end points is live at any time.  Step 0 is the
+// terminal point W~(n dt) (no push); step s >= 1 is the midpoint m of an
+// interval (l, r): before it, `pops` times "L = R; R = stack.pop()"; then
+// W_m = wl * L + wr * R + sd * z_{dim}; stack.push(R); R = W_m.
+struct PlanStep {
+    int32_t lds_off;   // (dim - 1) * 64: row of the lane table for this step's dimension
+    int32_t m;         // grid index of the new point (1..n)
+    int32_t pops;      // stack pops before the step
+    int32_t dim;       // Sobol dimension of the step (1..n)
+    float wl, wr, sd;  // (r-m)/(r-l), (m-l)/(r-l), sqrt((m-l)(r-m)/(r-l)) in units of sqrt(dt)
+    float mf;          // float(m)
+};
+struct PlanStep64 {
+    double wl, wr, sd, mf;
+};
+
+// Per-option constants (host-computed in FP64).
+struct OptDev {
+    int32_t type, d, n, path;     // n = d - 1
+    int32_t plan_off;             // first PlanStep of this option's bridge plan
+    int32_t chunks;               // work units per replication
+    int64_t n_points;             // points in this launch: k_begin .. k_begin + n_points - 1
+    int64_t k_begin;              // first Sobol point (a multiple of QCPW_CHUNK)
+    uint64_t seed;
+    int64_t unit0;                // first work unit of this option
+    int32_t n_shifts;
+    int32_t out_index;            // row of this option in the caller's arrays
+    // FP64 path constants (log2-space path Y_m = log2(S~(t_{m+1}) / S0))
+    double zscale;                // sigma * sqrt(dt) * log2(e): z -> Y units
+    double ydrift_n;              // omega * n * dt * log2(e): drift of Y_n
+    double ydrift_1;              // omega * dt * log2(e): drift per step (standard)
+    double kappa;                 // (r + sigma^2/2) dt log2(e): W - sigma tau = (Y - kappa m)/(sigma log2 e)
+    double inv_sig_log2e;         // 1 / (sigma log2(e))
+    double c0;                    // ln K - ln S0 - omega t1 (+ ln d for averages)
+    double inv_s1, s1, sqrt_t1, inv_sigma;
+    double S0, K, D, D1, invd, inv_S0, inv_S0sq;
+    float zscale_f, ydrift_n_f, ydrift_1_f, kappa_f;
+};
+
+// Packed work description for one launch.
+struct LaunchDesc {
+    const OptDev *opts;           // [n_opts], sorted by cost
+    const int64_t *unit_prefix;   // [n_opts + 1] exclusive prefix of units
+    int32_t n_opts;
+    int32_t max_n;                // largest n in the launch (LDS sizing)
+    int64_t total_units;
+    const PlanStep *plan;         // all plans
+    const PlanStep64 *plan64;
+    const uint32_t *dir;          // [QCPW_TAB_DIMS][32]
+    const uint32_t *lane;         // [QCPW_TAB_DIMS][64]
+    double *partials;             // [total_units][8]
+    unsigned long long *counter;  // work-queue head
+};

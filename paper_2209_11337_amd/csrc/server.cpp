@@ -1,0 +1,484 @@
+// server.cpp -- continuous batching of Greek requests on one device.
+//
+// A worker thread owns two launch slots (stream + workspace each).  While one
+// launch runs, the worker packs everything runnable into the other slot and
+// enqueues it, so work of requests that arrived meanwhile overlaps on the
+// device with work already running.  Requests are admitted in arrival order
+// as long as their device footprint fits the HBM budget; a request's options
+// start at 2^14 points per replication and double (only the new points are
+// computed: Sobol points extend, and the sums of earlier rounds are kept)
+// until the standard errors of delta, vega and gamma meet the target or
+// 2^22 points are reached.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "qcpw_host.h"
+
+namespace qcpw {
+
+static constexpr int64_t kFirstPoints = int64_t(1) << 14;
+static constexpr int64_t kMaxPoints = int64_t(1) << 22;
+static constexpr int kMaxBatchOptions = 8192;
+static constexpr int kSlots = 2;
+
+enum ReqState { RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_CANCELLED };
+
+struct Request {
+    uint64_t id = 0;
+    std::vector<qcpw_option_spec> specs;
+    int n_shifts = 0, path = 0;
+    double target = 0.0;
+    ReqState state = RQ_QUEUED;
+    bool in_flight = false;
+    int64_t n_done = 0;            // points per replication already summed
+    int64_t n_next = 0;            // points after the round in flight
+    std::vector<double> S, Cc;     // [n_opts][L][4] compensated sums of F over points
+    std::vector<double> greeks, stderr_;
+    int64_t footprint = 0;
+    bool charged = false;
+    bool collected = false;        // cancelled and reported while a launch still held it
+};
+
+// Device bytes one option occupies in a launch at most (the largest round
+// covers 2^21 new points).
+static int64_t option_footprint(int n_shifts)
+{
+    const int64_t chunks = (kMaxPoints / 2) / QCPW_CHUNK;
+    return chunks * n_shifts * 8 * (int64_t)sizeof(double) + (int64_t)n_shifts * 4 * sizeof(double) +
+           (int64_t)sizeof(OptDev) + 16 * (int64_t)sizeof(double) + 64;
+}
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    Workspace ws;
+    bool busy = false;
+    std::vector<Request *> reqs;
+    std::vector<int> first_opt;        // first option of each request in the launch
+    std::vector<double> per_shift;     // host copy [n][L][4]
+    std::vector<double> g, e;
+    double *d_g = nullptr, *d_e = nullptr, *d_ps = nullptr;
+    int L = 0;
+    int n = 0;
+};
+
+}  // namespace qcpw
+
+struct qcpw_server {
+    qcpw::Context *ctx = nullptr;
+    qcpw_run_config cfg;
+    int64_t budget = 0;
+    int64_t in_use = 0, peak = 0;
+    int64_t n_admitted = 0, n_completed = 0, n_cancelled = 0, n_launches = 0;
+    uint64_t next_id = 1;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::map<uint64_t, std::unique_ptr<qcpw::Request>> reqs;
+    std::deque<uint64_t> queue;       // admitted order of queued requests
+    bool stop = false;
+    std::thread worker;
+    qcpw::Slot slots[qcpw::kSlots];
+};
+
+namespace qcpw {
+
+static void finish_locked(qcpw_server *s, Request *r, ReqState st)
+{
+    r->state = st;
+    r->in_flight = false;
+    if (r->charged) {
+        s->in_use -= r->footprint;
+        r->charged = false;
+    }
+    if (st == RQ_DONE) ++s->n_completed;
+    if (st == RQ_CANCELLED) ++s->n_cancelled;
+    s->cv_done.notify_all();
+}
+
+// Pick runnable requests for one launch (caller holds the lock).  All
+// requests of a launch share path construction and replication count; the
+// oldest runnable request decides which.
+static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out)
+{
+    out.clear();
+    int group_path = -1, group_L = -1;
+    int n_opts = 0;
+    auto fits_group = [&](Request *r) {
+        if (group_path < 0) {
+            group_path = r->path;
+            group_L = r->n_shifts;
+        }
+        return r->path == group_path && r->n_shifts == group_L;
+    };
+    // running requests that need another round already hold their budget
+    for (auto &kv : s->reqs) {
+        Request *r = kv.second.get();
+        if (r->state != RQ_RUNNING || r->in_flight) continue;
+        if (!fits_group(r)) continue;
+        if (n_opts + (int)r->specs.size() > kMaxBatchOptions && !out.empty()) break;
+        out.push_back(r);
+        n_opts += (int)r->specs.size();
+    }
+    // admit queued requests in arrival order while budget and slots allow
+    while (!s->queue.empty()) {
+        auto it = s->reqs.find(s->queue.front());
+        if (it == s->reqs.end() || it->second->state != RQ_QUEUED) {
+            s->queue.pop_front();
+            continue;
+        }
+        Request *r = it->second.get();
+        if (s->in_use + r->footprint > s->budget) break;             // wait for memory
+        if (n_opts + (int)r->specs.size() > kMaxBatchOptions && !out.empty()) break;
+        if (!fits_group(r)) break;
+        s->queue.pop_front();
+        r->state = RQ_RUNNING;
+        r->charged = true;
+        s->in_use += r->footprint;
+        s->peak = std::max(s->peak, s->in_use);
+        ++s->n_admitted;
+        out.push_back(r);
+        n_opts += (int)r->specs.size();
+    }
+    for (Request *r : out) {
+        r->in_flight = true;
+        r->n_next = r->n_done == 0 ? kFirstPoints : 2 * r->n_done;
+    }
+}
+
+static qcpw_status enqueue_slot(qcpw_server *s, Slot &sl, std::vector<Request *> &batch)
+{
+    std::vector<qcpw_option_spec> specs;
+    std::vector<int64_t> kb;
+    sl.reqs = batch;
+    sl.first_opt.clear();
+    for (Request *r : batch) {
+        sl.first_opt.push_back((int)specs.size());
+        for (const auto &sp : r->specs) {
+            qcpw_option_spec x = sp;
+            x.n_points = r->n_next - r->n_done;
+            specs.push_back(x);
+            kb.push_back(r->n_done);
+        }
+    }
+    const int n = (int)specs.size();
+    const int L = batch[0]->n_shifts;
+    LaunchPlan lp;
+    qcpw_status st;
+    {
+        std::lock_guard<std::mutex> lk(s->ctx->mu);   // plan_launch may add PCA factors
+        st = plan_launch(s->ctx, specs.data(), n, 0, 0, L, batch[0]->path, s->cfg.precision, s->cfg.pca_gemm,
+                         s->cfg.block_threads, lp, kb.data());
+    }
+    if (st != QCPW_OK) return st;
+    const size_t need = launch_workspace_bytes(lp);
+    const size_t out_bytes = ((size_t)n * 4 * sizeof(double) + 255) / 256 * 256;
+    const size_t ps_bytes = ((size_t)n * L * 4 * sizeof(double) + 255) / 256 * 256;
+    st = sl.ws.ensure(need + 2 * out_bytes + ps_bytes);
+    if (st != QCPW_OK) return st;
+    char *base = (char *)sl.ws.ptr;
+    sl.d_g = (double *)(base + need);
+    sl.d_e = (double *)(base + need + out_bytes);
+    sl.d_ps = (double *)(base + need + 2 * out_bytes);
+    sl.n = n;
+    sl.L = L;
+    st = enqueue_launch(s->ctx, lp, sl.stream, sl.d_g, sl.d_e, sl.d_ps, base, need);
+    if (st != QCPW_OK) return st;
+    sl.per_shift.resize((size_t)n * L * 4);
+    QCPW_HIP(hipMemcpyAsync(sl.per_shift.data(), sl.d_ps, (size_t)n * L * 4 * sizeof(double),
+                            hipMemcpyDeviceToHost, sl.stream));
+    sl.busy = true;
+    return QCPW_OK;
+}
+
+// Fold a finished launch into its requests (caller holds the lock).
+static void absorb_slot_locked(qcpw_server *s, Slot &sl)
+{
+    for (size_t bi = 0; bi < sl.reqs.size(); ++bi) {
+        Request *r = sl.reqs[bi];
+        r->in_flight = false;
+        if (r->state == RQ_CANCELLED) {
+            if (r->collected) s->reqs.erase(r->id);
+            continue;
+        }
+        const int n = (int)r->specs.size(), L = r->n_shifts;
+        const double len = (double)(r->n_next - r->n_done);
+        if (r->S.empty()) {
+            r->S.assign((size_t)n * L * 4, 0.0);
+            r->Cc.assign((size_t)n * L * 4, 0.0);
+        }
+        for (int i = 0; i < n; ++i)
+            for (int l = 0; l < L; ++l)
+                for (int k = 0; k < 4; ++k) {
+                    const size_t src = ((size_t)(sl.first_opt[bi] + i) * L + l) * 4 + k;
+                    const size_t dst = ((size_t)i * L + l) * 4 + k;
+                    const double x = sl.per_shift[src] * len;
+                    const double t = r->S[dst] + x, bp = t - r->S[dst];
+                    r->Cc[dst] += (r->S[dst] - (t - bp)) + (x - bp);
+                    r->S[dst] = t;
+                }
+        r->n_done = r->n_next;
+        // mean and standard error over replications
+        r->greeks.assign((size_t)n * 4, 0.0);
+        r->stderr_.assign((size_t)n * 4, 0.0);
+        bool met = true;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < 4; ++k) {
+                double m = 0.0;
+                for (int l = 0; l < L; ++l) {
+                    const size_t id = ((size_t)i * L + l) * 4 + k;
+                    m += (r->S[id] + r->Cc[id]) / (double)r->n_done;
+                }
+                m /= L;
+                double v = 0.0;
+                for (int l = 0; l < L; ++l) {
+                    const size_t id = ((size_t)i * L + l) * 4 + k;
+                    const double dv = (r->S[id] + r->Cc[id]) / (double)r->n_done - m;
+                    v += dv * dv;
+                }
+                const double se = L >= 2 ? std::sqrt(v / ((double)L * (L - 1))) : NAN;
+                r->greeks[(size_t)i * 4 + k] = m;
+                r->stderr_[(size_t)i * 4 + k] = se;
+                if (k >= 1 && !(se <= r->target * std::max(1.0, std::fabs(m)))) met = false;
+            }
+        if (met || r->n_done >= kMaxPoints) finish_locked(s, r, RQ_DONE);
+    }
+    sl.reqs.clear();
+    sl.busy = false;
+    ++s->n_launches;
+}
+
+static void fail_slot_locked(qcpw_server *s, Slot &sl)
+{
+    for (Request *r : sl.reqs) finish_locked(s, r, RQ_CANCELLED);
+    sl.reqs.clear();
+    sl.busy = false;
+}
+
+static bool work_available_locked(qcpw_server *s)
+{
+    if (!s->queue.empty()) return true;
+    for (auto &kv : s->reqs)
+        if (kv.second->state == RQ_RUNNING && !kv.second->in_flight) return true;
+    return false;
+}
+
+static void retire_slot(qcpw_server *s, Slot &sl)
+{
+    const hipError_t q = hipStreamSynchronize(sl.stream);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (q == hipSuccess) absorb_slot_locked(s, sl);
+    else fail_slot_locked(s, sl);
+}
+
+static void worker_main(qcpw_server *s)
+{
+    hipSetDevice(s->ctx->tab.device);
+    uint64_t seq = 0, slot_seq[kSlots] = {};
+    for (;;) {
+        std::vector<Request *> batch;
+        int free_slot = -1, busy = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (auto &sl : s->slots) busy += sl.busy;
+            if (busy == 0) {
+                s->cv_work.wait(lk, [&] { return s->stop || work_available_locked(s); });
+                if (s->stop) break;
+            }
+            for (int i = 0; i < kSlots; ++i)
+                if (!s->slots[i].busy) {
+                    free_slot = i;
+                    break;
+                }
+            if (free_slot >= 0) pick_batch_locked(s, batch);
+        }
+        if (!batch.empty()) {
+            Slot &sl = s->slots[free_slot];
+            if (enqueue_slot(s, sl, batch) == QCPW_OK) {
+                slot_seq[free_slot] = ++seq;
+                ++busy;
+            } else {
+                std::lock_guard<std::mutex> lk(s->mu);
+                sl.reqs = batch;
+                fail_slot_locked(s, sl);
+            }
+        }
+        // Wait for the oldest launch when every slot is busy, or when there is
+        // nothing new to enqueue; otherwise go round and fill the free slot.
+        if (busy == kSlots || (batch.empty() && busy > 0)) {
+            int oldest = -1;
+            for (int i = 0; i < kSlots; ++i)
+                if (s->slots[i].busy && (oldest < 0 || slot_seq[i] < slot_seq[oldest])) oldest = i;
+            if (oldest >= 0) retire_slot(s, s->slots[oldest]);
+        }
+    }
+    for (int i = 0; i < kSlots; ++i)
+        if (s->slots[i].busy) retire_slot(s, s->slots[i]);
+}
+
+}  // namespace qcpw
+
+using namespace qcpw;
+
+extern "C" {
+
+qcpw_status qcpw_server_create(const qcpw_run_config *cfg, int64_t hbm_budget_bytes, qcpw_server **out)
+{
+    set_error("");
+    if (!out) return fail(QCPW_EINVAL, "out is NULL");
+    if (hbm_budget_bytes <= 0) return fail(QCPW_EINVAL, "hbm_budget_bytes must be > 0");
+    qcpw_run_config c;
+    memset(&c, 0, sizeof c);
+    c.device = -1;
+    if (cfg) c = *cfg;
+    if (c.precision != QCPW_FP64 && c.precision != QCPW_FP32_MIXED) return fail(QCPW_EINVAL, "unknown precision");
+    if (c.block_threads != 0 && c.block_threads != 256 && c.block_threads != 512 && c.block_threads != 1024)
+        return fail(QCPW_EINVAL, "block_threads must be 0, 256, 512 or 1024");
+    Context *ctx = nullptr;
+    qcpw_status st = get_context(c.device, &ctx);
+    if (st != QCPW_OK) return st;
+    std::unique_ptr<qcpw_server> s(new qcpw_server());
+    s->ctx = ctx;
+    s->cfg = c;
+    s->budget = hbm_budget_bytes;
+    for (auto &sl : s->slots) QCPW_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+    qcpw_server *raw = s.get();
+    s->worker = std::thread(worker_main, raw);
+    *out = s.release();
+    return QCPW_OK;
+}
+
+qcpw_status qcpw_submit(qcpw_server *srv, const qcpw_option_spec *specs, int32_t n_opts, int32_t n_shifts,
+                        int32_t path_construction, double target_stderr, uint64_t *request_id)
+{
+    set_error("");
+    if (!srv || !request_id) return fail(QCPW_EINVAL, "NULL server or request_id");
+    if (n_opts < 1 || n_opts > 4096) return fail(QCPW_EINVAL, "n_opts must be in [1, 4096]");
+    if (!(target_stderr > 0) || !std::isfinite(target_stderr)) return fail(QCPW_EINVAL, "target_stderr must be > 0");
+    qcpw_status st = validate_call(specs, n_opts, 0, kFirstPoints, n_shifts, path_construction, srv->cfg.precision,
+                                   srv->cfg.pca_gemm, srv->cfg.block_threads);
+    if (st != QCPW_OK) return st;
+    std::unique_ptr<Request> r(new Request());
+    r->specs.assign(specs, specs + n_opts);
+    r->n_shifts = n_shifts;
+    r->path = path_construction;
+    r->target = target_stderr;
+    r->footprint = option_footprint(n_shifts) * n_opts;
+    if (r->footprint > srv->budget) return fail(QCPW_ENOMEM, "request footprint exceeds the HBM budget");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return fail(QCPW_EINVAL, "server is shutting down");
+    r->id = srv->next_id++;
+    *request_id = r->id;
+    srv->queue.push_back(r->id);
+    srv->reqs[r->id] = std::move(r);
+    srv->cv_work.notify_one();
+    return QCPW_OK;
+}
+
+static qcpw_status take_result_locked(qcpw_server *srv, std::map<uint64_t, std::unique_ptr<Request>>::iterator it,
+                                      double *g, double *e, int64_t *pts)
+{
+    Request *r = it->second.get();
+    if (r->state == RQ_CANCELLED) {
+        if (r->in_flight) r->collected = true;   // the launch that holds it erases it
+        else srv->reqs.erase(it);
+        return fail(QCPW_ECANCELLED, "request was cancelled");
+    }
+    if (g) memcpy(g, r->greeks.data(), r->greeks.size() * sizeof(double));
+    if (e) memcpy(e, r->stderr_.data(), r->stderr_.size() * sizeof(double));
+    if (pts) *pts = r->n_done;
+    srv->reqs.erase(it);
+    return QCPW_OK;
+}
+
+qcpw_status qcpw_poll(qcpw_server *srv, uint64_t request_id, double *out_greeks, double *out_stderr,
+                      int64_t *out_points_used)
+{
+    set_error("");
+    if (!srv) return fail(QCPW_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(request_id);
+    if (it == srv->reqs.end() || it->second->collected) return fail(QCPW_ENOTFOUND, "unknown request id");
+    if (it->second->state == RQ_QUEUED || it->second->state == RQ_RUNNING) return QCPW_EBUSY;
+    return take_result_locked(srv, it, out_greeks, out_stderr, out_points_used);
+}
+
+qcpw_status qcpw_wait(qcpw_server *srv, uint64_t request_id, double *out_greeks, double *out_stderr,
+                      int64_t *out_points_used)
+{
+    set_error("");
+    if (!srv) return fail(QCPW_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(request_id);
+    if (it == srv->reqs.end() || it->second->collected) return fail(QCPW_ENOTFOUND, "unknown request id");
+    srv->cv_done.wait(lk, [&] {
+        auto jt = srv->reqs.find(request_id);
+        return jt == srv->reqs.end() || jt->second->state == RQ_DONE || jt->second->state == RQ_CANCELLED;
+    });
+    it = srv->reqs.find(request_id);
+    if (it == srv->reqs.end() || it->second->collected)
+        return fail(QCPW_ENOTFOUND, "request was collected by another caller");
+    return take_result_locked(srv, it, out_greeks, out_stderr, out_points_used);
+}
+
+qcpw_status qcpw_cancel(qcpw_server *srv, uint64_t request_id)
+{
+    set_error("");
+    if (!srv) return fail(QCPW_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(request_id);
+    if (it == srv->reqs.end() || it->second->collected) return fail(QCPW_ENOTFOUND, "unknown request id");
+    Request *r = it->second.get();
+    if (r->state == RQ_QUEUED || r->state == RQ_RUNNING) finish_locked(srv, r, RQ_CANCELLED);
+    return QCPW_OK;
+}
+
+qcpw_status qcpw_server_stats(qcpw_server *srv, int64_t out[7])
+{
+    if (!srv || !out) return fail(QCPW_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    int64_t queued = 0;
+    for (auto &kv : srv->reqs) queued += kv.second->state == RQ_QUEUED;
+    out[0] = srv->n_admitted;
+    out[1] = srv->n_completed;
+    out[2] = srv->n_cancelled;
+    out[3] = srv->n_launches;
+    out[4] = srv->in_use;
+    out[5] = srv->peak;
+    out[6] = queued;
+    return QCPW_OK;
+}
+
+qcpw_status qcpw_server_destroy(qcpw_server *srv)
+{
+    if (!srv) return fail(QCPW_EINVAL, "NULL server");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->cv_work.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (auto &kv : srv->reqs)
+            if (kv.second->state == RQ_QUEUED || kv.second->state == RQ_RUNNING)
+                finish_locked(srv, kv.second.get(), RQ_CANCELLED);
+    }
+    for (auto &sl : srv->slots) {
+        if (sl.ws.ptr) hipFree(sl.ws.ptr);
+        if (sl.stream) hipStreamDestroy(sl.stream);
+    }
+    delete srv;
+    return QCPW_OK;
+}
+
+}  // extern "C"
