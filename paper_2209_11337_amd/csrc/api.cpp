@@ -109,8 +109,10 @@ qcpw_status get_context(int device, Context **out)
 }
 
 // Unit-dt principal-component factor for n coordinates (the kernels scale
-// the normals by sqrt(dt) instead), resident per n.  Row-major NPAD x NPAD
-// FP32 (zero padded), the same split into BF16 hi/lo, and n x n FP64.
+// the normals by sqrt(dt) instead), resident per n, in the layouts the PCA
+// kernels read: FP32 k-major At[k][row] (NP x NP, zero padded, NP = n rounded
+// up to 32), the same split as BF16 hi + lo in 16-wide k slabs
+// [k/16][row][16], and n x n FP64 row-major.
 qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out)
 {
     for (auto &p : ctx->pca)
@@ -120,8 +122,8 @@ qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out)
         }
     std::vector<double> A;
     build_pca_factor(n, dt, A);
-    const int NP = QCPW_PCA_NPAD;
-    std::vector<float> A32((size_t)NP * NP, 0.0f);
+    const int NP = (n + 31) / 32 * 32;
+    std::vector<float> At((size_t)NP * NP, 0.0f);
     std::vector<uint16_t> hi((size_t)NP * NP, 0), lo((size_t)NP * NP, 0);
     auto to_bf16 = [](float x) -> uint16_t {   // round to nearest even
         uint32_t u;
@@ -135,22 +137,24 @@ qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out)
         memcpy(&x, &u, 4);
         return x;
     };
-    for (int k = 0; k < n; ++k)
-        for (int i = 0; i < n; ++i) {
-            const float a = (float)A[(size_t)k * n + i];
-            A32[(size_t)k * NP + i] = a;
+    for (int row = 0; row < n; ++row)
+        for (int k = 0; k < n; ++k) {
+            const float a = (float)A[(size_t)row * n + k];
+            At[(size_t)k * NP + row] = a;
             const uint16_t h = to_bf16(a);
-            hi[(size_t)k * NP + i] = h;
-            lo[(size_t)k * NP + i] = to_bf16(a - from_bf16(h));
+            const size_t blk = ((size_t)(k / 16) * NP + row) * 16 + (k % 16);
+            hi[blk] = h;
+            lo[blk] = to_bf16(a - from_bf16(h));
         }
     Context::Pca p;
     p.n = n;
     p.dt = dt;
-    QCPW_HIP(hipMalloc(&p.A32, A32.size() * 4));
+    p.np = NP;
+    QCPW_HIP(hipMalloc(&p.At, At.size() * 4));
     QCPW_HIP(hipMalloc(&p.A64, A.size() * 8));
     QCPW_HIP(hipMalloc(&p.Ahi, hi.size() * 2));
     QCPW_HIP(hipMalloc(&p.Alo, lo.size() * 2));
-    QCPW_HIP(hipMemcpy(p.A32, A32.data(), A32.size() * 4, hipMemcpyHostToDevice));
+    QCPW_HIP(hipMemcpy(p.At, At.data(), At.size() * 4, hipMemcpyHostToDevice));
     QCPW_HIP(hipMemcpy(p.A64, A.data(), A.size() * 8, hipMemcpyHostToDevice));
     QCPW_HIP(hipMemcpy(p.Ahi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
     QCPW_HIP(hipMemcpy(p.Alo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));

@@ -1,0 +1,205 @@
+// device_math.h -- device helpers shared by the per-path and PCA kernels:
+// digital shifts, the FP32 / FP64 inverse normal, path sums, the per-path
+// FP64 tail (breakpoint, Phi tails, Greeks) and compensated reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "qcpw_internal.h"
+#include "../../include/qmc_cpw.h"
+
+namespace qcpw {
+
+#include "ninv_f32_coeffs.inc"
+
+// ------------------------------------------------------------------------
+// device helpers
+// ------------------------------------------------------------------------
+
+// SplitMix64 (Steele, Lea, Flood 2014): output i of the generator seeded
+// with `seed` is the variant-13 mixer applied to seed + (i + 1) * gamma.
+__device__ __host__ inline uint64_t splitmix64_out(uint64_t seed, uint64_t i)
+{
+    uint64_t x = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__device__ inline uint32_t digital_shift(uint64_t seed, int l, int j)
+{
+    return (uint32_t)(splitmix64_out(seed, ((uint64_t)l << 16) | (uint64_t)j) >> 32);
+}
+
+template <int N>
+__device__ inline float horner(const float (&c)[N], float v)
+{
+    float p = c[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) p = fmaf(p, v, c[i]);
+    return p;
+}
+
+// Phi^{-1}((y + 1/2) 2^-32) * scale in FP32.
+// With m = min(y, ~y) (so the uniform is folded onto (0, 1/2]) the two
+// quantities that lose no precision are q = (m + 1/2) 2^-32 and
+// |x| = 1 - 2q = (2 (2^31 - 1 - m) + 1) 2^-32, both formed from integers.
+// Phi^{-1}(u) = sqrt(2) erfinv(2u - 1), and erfinv(x)/x is a polynomial in
+// w = -ln(1 - x^2) = -ln(4 q (1 - q)) (two branches, coefficients in
+// ninv_f32_coeffs.inc).  The sign is + iff y >= 2^31.
+__device__ inline float ninv_scaled_f32(uint32_t y, float scale)
+{
+    const uint32_t neg = (uint32_t)((int32_t)y >> 31);   // all ones iff y >= 2^31
+    const uint32_t m = y ^ neg;
+    const float q = fmaf((float)m, 0x1p-32f, 0x1p-33f);
+    const float ax = fmaf((float)(m ^ 0x7FFFFFFFu), 0x1p-31f, 0x1p-32f);
+    const float t = fmaf(-q, q, q);                       // q (1 - q) = (1 - x^2) / 4
+    const float lg = __builtin_amdgcn_logf(t);            // log2 t
+    constexpr float LN2 = 0.693147180559945309f;
+    constexpr float LG_SPLIT = -(QCPW_NINV_WSPLIT / 0.693147180559945309f) - 2.0f;
+    float p;
+    if (lg > LG_SPLIT) {
+        p = horner(QCPW_NINV_P, fmaf(lg, -LN2, -2.0f * LN2 - QCPW_NINV_C1));
+    } else {
+        const float w = fmaf(lg, -LN2, -2.0f * LN2);
+        p = horner(QCPW_NINV_Q, __builtin_amdgcn_sqrtf(w) - QCPW_NINV_C2);
+    }
+    const float k = neg ? scale : -scale;                 // scale already holds sqrt(2)
+    return (p * ax) * k;
+}
+
+// Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library), evaluated on the
+// lower half so that 1 - u never has to be formed.
+__device__ inline double ninv_f64(uint32_t y)
+{
+    const uint32_t neg = (uint32_t)((int32_t)y >> 31);
+    const uint32_t m = y ^ neg;
+    const double x = normcdfinv(((double)m + 0.5) * 0x1p-32);   // <= 0
+    return neg ? -x : x;
+}
+
+__device__ inline float exp2_r(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ inline double exp2_r(double x) { return exp2(x); }
+
+// Knuth two-sum: s + c accumulates x with the rounding error kept in c.
+__device__ inline void acc_add(double &s, double &c, double x)
+{
+    const double t = s + x;
+    const double bp = t - s;
+    c += (s - (t - bp)) + (x - bp);
+    s = t;
+}
+
+// Combine compensated pairs across the wave (xor butterfly, fixed order).
+__device__ inline void wave_reduce(double &s, double &c)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double s2 = __shfl_xor(s, off, 64);
+        const double c2 = __shfl_xor(c, off, 64);
+        const double t = s + s2;
+        const double bp = t - s;
+        const double e = (s - (t - bp)) + (s2 - bp);
+        s = t;
+        c = (c + c2) + e;
+    }
+}
+
+__device__ inline uint32_t rdlane(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+template <typename R>
+struct PathSums {
+    R A1, A2y, A2m;   // sum E_m, sum E_m Y_m, sum E_m m   (averages)
+    R bE, bY, bm;     // running max of E_m, its Y_m and m (lookback)
+};
+
+template <typename R, bool MAX>
+__device__ inline void consume(PathSums<R> &ps, R Y, R mf)
+{
+    const R E = exp2_r(Y);
+    if (MAX) {
+        const bool take = (E > ps.bE) || (E == ps.bE && mf < ps.bm);   // lowest index wins ties
+        ps.bE = take ? E : ps.bE;
+        ps.bY = take ? Y : ps.bY;
+        ps.bm = take ? mf : ps.bm;
+    } else {
+        ps.A1 += E;
+        ps.A2y = fma(E, Y, ps.A2y);
+        ps.A2m = fma(E, mf, ps.A2m);
+    }
+}
+
+// price, delta, vega, gamma of the smoothed payoff for one path (Sec. 4.5),
+// from the path statistic X = S0 * a (a = A1/d or max E) and its sigma
+// derivative.  All FP64.
+__device__ inline void path_greeks(const OptDev &op, double lnA, double Xs, double VXs, double F[4])
+{
+    // X = S0 * Xs, V_X = S0 * VXs
+    const double psi = (op.c0 - lnA) * op.inv_s1;
+    const double Q0 = 0.5 * erfc(psi * M_SQRT1_2);
+    const double Q1 = 0.5 * erfc((psi - op.s1) * M_SQRT1_2);
+    const double phi0 = exp(-0.5 * psi * psi) * 0.398942280401432677939946;
+    if (op.type == QCPW_BINARY_ASIAN_CALL) {
+        const double Dphi = op.D * phi0;
+        F[0] = op.D * Q0;
+        F[1] = Dphi * op.inv_s1 * op.inv_S0;
+        F[2] = Dphi * (VXs / Xs * op.inv_s1 + psi * op.inv_sigma - op.sqrt_t1);
+        F[3] = Dphi * op.inv_s1 * op.inv_S0sq * (psi * op.inv_s1 - 1.0);
+    } else {
+        const double X = op.S0 * Xs;
+        const double DKphi = op.D * op.K * phi0;
+        F[0] = op.D1 * X * Q1 - op.D * op.K * Q0;
+        F[1] = op.D1 * Xs * Q1;
+        F[2] = op.D1 * Q1 * (op.S0 * VXs) + DKphi * op.sqrt_t1;
+        F[3] = DKphi * op.inv_s1 * op.inv_S0sq;
+    }
+}
+
+template <typename R>
+__device__ inline void path_tail(const OptDev &op, const PathSums<R> &ps, bool is_max, double F[4])
+{
+    double lnA, Xs, VXs;
+    if (is_max) {
+        const double bE = (double)ps.bE;
+        lnA = log(bE);
+        Xs = bE;
+        VXs = bE * ((double)ps.bY - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
+    } else {
+        const double A1 = (double)ps.A1;
+        lnA = log(A1);                          // ln d is folded into c0
+        Xs = A1 * op.invd;
+        VXs = ((double)ps.A2y - op.kappa * (double)ps.A2m) * op.invd * op.inv_sig_log2e;
+    }
+    path_greeks(op, lnA, Xs, VXs, F);
+}
+
+template <typename R>
+__device__ inline void init_sums(PathSums<R> &ps)
+{
+    ps.A1 = R(1); ps.A2y = R(0); ps.A2m = R(0);   // date 1: S~ = S0, Y = 0
+    ps.bE = R(1); ps.bY = R(0); ps.bm = R(0);
+}
+
+template <bool F32>
+struct Real;
+template <>
+struct Real<true> { using T = float; };
+template <>
+struct Real<false> { using T = double; };
+
+// Sobol + shift + inverse normal for one coordinate, result in Y units.
+template <bool F32>
+__device__ inline typename Real<F32>::T coord(uint32_t y, const OptDev &op)
+{
+    if constexpr (F32) {
+        return ninv_scaled_f32(y, op.zscale_f);
+    } else {
+        return ninv_f64(y) * op.zscale;
+    }
+}
+
+}  // namespace qcpw

@@ -1,16 +1,447 @@
-// pca.hip -- principal-component path construction (placeholder until the
-// matrix-core kernel lands).
+// pca.hip -- principal-component path construction (Sec. 3.4.1: W~ = A z
+// with A A^T = Sigma; here A holds the eigenvectors of Sigma scaled by the
+// square roots of their eigenvalues, largest first).
+//
+// For a tile of 64 consecutive Sobol points the product W~ = A Z is a dense
+// (n x n) by (n x 64) contraction, so it runs on the matrix cores:
+//
+//   prologue   each of the 4 waves generates 64 dimensions of the tile
+//              (lane = point; Sobol via the lane table and a wave-uniform
+//              part, digital shift, FP32 inverse normal, scaled to log2
+//              units) and stores Z^T in LDS, as FP32 or split into BF16
+//              hi + lo;
+//   GEMM       wave w owns the 32 x 32 output blocks t = w, w+4, ... (row
+//              block t/2, point block t%2): FP32 v_mfma_f32_32x32x2f32, or
+//              three v_mfma_f32_32x32x16_bf16 per 16-wide k slab
+//              (hi*hi + hi*lo + lo*hi), accumulating in FP32;
+//   epilogue   Y_m = W'_m + drift m; E = exp2(Y) and the path sums (or the
+//              running maximum) over the lane's rows; the two lane halves
+//              and the waves of a point block are combined through LDS; the
+//              FP64 tail (breakpoint, Phi tails, Greeks) runs on wave 0 and
+//              feeds its compensated sums.
+//
+// The FP64 variant keeps Z^T in FP64 in LDS and forms A z with FP64 FMAs
+// (A read as wave-uniform scalars), for exact parity with the oracle.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "device_math.h"
 #include "qcpw_host.h"
 
 namespace qcpw {
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short v8us __attribute__((ext_vector_type(8)));
+
+static constexpr int TP = 64;        // points per tile (one wave width)
+static constexpr int PCA_WAVES = 4;  // waves per workgroup
+
+__device__ inline unsigned short bf16_bits(float x)   // round to nearest even
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_value(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+
+// unit of work -> (option index, replication, chunk)
+__device__ inline void locate_unit(const int64_t *__restrict__ prefix, int n_opts, long long unit, int &o)
+{
+    if (!(prefix[o] <= unit && unit < prefix[o + 1])) {
+        int lo = 0, hi = n_opts - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= unit) lo = mid; else hi = mid - 1;
+        }
+        o = lo;
+    }
+}
+
+__device__ inline long long next_unit(unsigned long long *counter, long long *s_unit)
+{
+    if (threadIdx.x == 0) *s_unit = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const long long v = *s_unit;
+    const long long unit = ((long long)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+                           (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+    __syncthreads();
+    return unit;
+}
+
+// U_j(base) for dimension j (held by one lane), shift folded in.
+__device__ inline uint32_t uniform_part(const uint32_t *__restrict__ dir, uint64_t seed, int shift, int j,
+                                        uint64_t base)
+{
+    uint32_t u = digital_shift(seed, shift, j);
+    uint64_t g = (base ^ (base >> 1)) >> 5;
+    const uint32_t *v = dir + (size_t)j * 32;
+    for (int b = 5; g != 0; ++b, g >>= 1)
+        if (g & 1) u ^= v[b];
+    return u;
+}
+
+template <typename R>
+__device__ inline void sums_neutral(PathSums<R> &ps)
+{
+    ps.A1 = R(0); ps.A2y = R(0); ps.A2m = R(0);
+    ps.bE = R(0); ps.bY = R(0); ps.bm = R(1e30);
+}
+
+template <typename R>
+__device__ inline void sums_merge(PathSums<R> &a, const PathSums<R> &b)
+{
+    a.A1 += b.A1;
+    a.A2y += b.A2y;
+    a.A2m += b.A2m;
+    const bool take = (b.bE > a.bE) || (b.bE == a.bE && b.bm < a.bm);
+    a.bE = take ? b.bE : a.bE;
+    a.bY = take ? b.bY : a.bY;
+    a.bm = take ? b.bm : a.bm;
+}
+
+template <typename R>
+__device__ inline void sums_add_date(PathSums<R> &ps, R Y, R mf)
+{
+    const R E = exp2_r(Y);
+    ps.A1 += E;
+    ps.A2y = fma(E, Y, ps.A2y);
+    ps.A2m = fma(E, mf, ps.A2m);
+    const bool take = (E > ps.bE) || (E == ps.bE && mf < ps.bm);
+    ps.bE = take ? E : ps.bE;
+    ps.bY = take ? Y : ps.bY;
+    ps.bm = take ? mf : ps.bm;
+}
+
+template <typename R>
+__device__ inline PathSums<R> shfl_xor_sums(const PathSums<R> &p, int off)
+{
+    PathSums<R> q;
+    q.A1 = __shfl_xor(p.A1, off, 64);
+    q.A2y = __shfl_xor(p.A2y, off, 64);
+    q.A2m = __shfl_xor(p.A2m, off, 64);
+    q.bE = __shfl_xor(p.bE, off, 64);
+    q.bY = __shfl_xor(p.bY, off, 64);
+    q.bm = __shfl_xor(p.bm, off, 64);
+    return q;
+}
+
+// Per-point combination of the wave partials in LDS, the date at tau = 0
+// (E = 1, Y = 0) and the FP64 tail; wave 0, lane = point of the tile.
+template <typename R>
+__device__ inline void tile_tail(const OptDev &op, const PathSums<R> *red, int lane, bool valid, int nwaves_pt,
+                                 const int *waves_pt, double (&s)[4], double (&c)[4])
+{
+    PathSums<R> ps;
+    init_sums(ps);   // date 1: E = 1, Y = 0, m = 0
+    for (int i = 0; i < nwaves_pt; ++i) sums_merge(ps, red[waves_pt[i] * TP + lane]);
+    if (valid) {
+        double F[4];
+        path_tail<R>(op, ps, op.type == QCPW_LOOKBACK_FIXED_CALL, F);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc_add(s[k], c[k], F[k]);
+    }
+}
+
+// ------------------------------------------------------------------------
+// FP32-mixed: matrix-core GEMM
+// ------------------------------------------------------------------------
+template <bool BF16X3>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void pca_f32_kernel(const OptDev *__restrict__ opts,
+                                                      const int64_t *__restrict__ unit_prefix,
+                                                      const uint32_t *__restrict__ dir,
+                                                      const uint32_t *__restrict__ lane_tab,
+                                                      double *__restrict__ partials,
+                                                      unsigned long long *__restrict__ counter, int n_opts,
+                                                      int np_max, long long total_units)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long s_unit;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // Z^T tile: FP32 [TP][np+1], or BF16 hi and lo [TP][np+8] each
+    const int zstride = BF16X3 ? np_max + 8 : np_max + 1;
+    const size_t zbytes = BF16X3 ? (size_t)2 * TP * zstride * 2 : (size_t)TP * zstride * 4;
+    float *Zf = (float *)smem;
+    unsigned short *Zh = (unsigned short *)smem;
+    unsigned short *Zl = Zh + (size_t)TP * zstride;
+    PathSums<float> *red = (PathSums<float> *)(smem + ((zbytes + 15) / 16) * 16);   // [4][TP]
+
+    int o = 0;
+    for (;;) {
+        const long long unit = next_unit(counter, &s_unit);
+        if (unit >= total_units) break;
+        locate_unit(unit_prefix, n_opts, unit, o);
+        const OptDev &op = opts[o];
+        const int n = op.n, NP = op.pca_np;
+        const int64_t rem = unit - op.unit0;
+        const int shift = (int)(rem / op.chunks);
+        const int64_t chunk = rem - (int64_t)shift * op.chunks;
+        const int64_t k_end = op.k_begin + op.n_points;
+        const int64_t t0 = op.k_begin + chunk * QCPW_CHUNK;
+        const int64_t t1 = min(t0 + (int64_t)QCPW_CHUNK, k_end);
+
+        // padding columns of Z (k = n .. NP-1) must hold zeros
+        for (int i = tid; i < TP * (NP - n); i += blockDim.x) {
+            const int p = i / (NP - n), k = n + i % (NP - n);
+            if (BF16X3) {
+                Zh[p * zstride + k] = 0;
+                Zl[p * zstride + k] = 0;
+            } else {
+                Zf[p * zstride + k] = 0.0f;
+            }
+        }
+        const int myj = 1 + 64 * wave + lane;   // dimension whose uniform part this lane holds
+        uint32_t U = 0;
+        if (myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
+        const int jcount = max(0, min(64, n - 64 * wave));   // dimensions generated by this wave
+
+        // output blocks of this wave: t = wave + 4 s; row block t / 2, point block t % 2 = wave & 1
+        const int nblocks = (NP / 32) * 2;
+        const int cb = wave & 1;
+        double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
+
+        for (int64_t base = t0; base < t1; base += TP) {
+            // ---- prologue: z' = Phi^{-1}(u) * sigma sqrt(dt) log2(e) for 64 points x this wave's dims
+            for (int jj = 0; jj < jcount; ++jj) {
+                const int j = 1 + 64 * wave + jj;
+                const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
+                const float z = ninv_scaled_f32(y, op.zscale_f);
+                const int k = j - 1;
+                if (BF16X3) {
+                    const unsigned short h = bf16_bits(z);
+                    Zh[lane * zstride + k] = h;
+                    Zl[lane * zstride + k] = bf16_bits(z - bf16_value(h));
+                } else {
+                    Zf[lane * zstride + k] = z;
+                }
+            }
+            if (base + TP < t1 && myj <= n) {   // Gray-code step to the next tile
+                const uint32_t *v = dir + (size_t)myj * 32;
+                U ^= v[5] ^ v[6 + __builtin_ctzll(((uint64_t)base >> 6) + 1)];
+            }
+            __syncthreads();
+
+            // ---- GEMM on the matrix cores
+            v16f acc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = (v16f){};
+            const int col = cb * 32 + (lane & 31);
+            const int khalf = lane >> 5;
+            if (BF16X3) {
+                for (int k0 = 0; k0 < NP; k0 += 16) {
+                    const v8us bh = *(const v8us *)&Zh[col * zstride + k0 + khalf * 8];
+                    const v8us bl = *(const v8us *)&Zl[col * zstride + k0 + khalf * 8];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int t = wave + 4 * q;
+                        if (t < nblocks) {
+                            const int row = (t >> 1) * 32 + (lane & 31);
+                            const size_t off = ((size_t)(k0 >> 4) * NP + row) * 16 + khalf * 8;
+                            const v8us ah = *(const v8us *)&op.pca_hi[off];
+                            const v8us al = *(const v8us *)&op.pca_lo[off];
+                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(v8bf, al), __builtin_bit_cast(v8bf, bh), acc[q], 0, 0, 0);
+                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(v8bf, ah), __builtin_bit_cast(v8bf, bl), acc[q], 0, 0, 0);
+                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(v8bf, ah), __builtin_bit_cast(v8bf, bh), acc[q], 0, 0, 0);
+                        }
+                    }
+                }
+            } else {
+                for (int k0 = 0; k0 < NP; k0 += 2) {
+                    const float b = Zf[col * zstride + k0 + khalf];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int t = wave + 4 * q;
+                        if (t < nblocks) {
+                            const int row = (t >> 1) * 32 + (lane & 31);
+                            const float a = op.pca_At[(size_t)(k0 + khalf) * NP + row];
+                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[q], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+
+            // ---- epilogue: exp2 and path sums over this lane's rows of its point
+            PathSums<float> ps;
+            sums_neutral(ps);
+            const float drift = op.ydrift_1_f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = wave + 4 * q;
+                if (t < nblocks) {
+                    const int rb = t >> 1;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = rb * 32 + (r >> 2) * 8 + khalf * 4 + (r & 3);
+                        if (row < n) {
+                            const float mf = (float)(row + 1);
+                            sums_add_date<float>(ps, fmaf(drift, mf, acc[q][r]), mf);
+                        }
+                    }
+                }
+            }
+            sums_merge(ps, shfl_xor_sums(ps, 32));
+            if (lane < 32) red[wave * TP + col] = ps;
+            __syncthreads();
+            if (wave == 0) {
+                // point p = lane lives in point block p / 32, i.e. waves cb and cb + 2
+                const int pb = lane >> 5;
+                const int waves_pt[2] = {pb, pb + 2};
+                tile_tail<float>(op, red, lane, base + lane < t1, 2, waves_pt, s, c);
+            }
+            __syncthreads();
+        }
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                wave_reduce(s[i], c[i]);
+                if (lane == 0) {
+                    partials[unit * 8 + i] = s[i];
+                    partials[unit * 8 + 4 + i] = c[i];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// FP64: the same tiles with Z^T in FP64 and FP64 FMAs
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void pca_f64_kernel(const OptDev *__restrict__ opts,
+                                                      const int64_t *__restrict__ unit_prefix,
+                                                      const uint32_t *__restrict__ dir,
+                                                      const uint32_t *__restrict__ lane_tab,
+                                                      double *__restrict__ partials,
+                                                      unsigned long long *__restrict__ counter, int n_opts,
+                                                      int n_max, long long total_units)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long s_unit;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int zstride = n_max + 1;
+    double *Z = (double *)smem;                                              // [TP][n_max + 1]
+    PathSums<double> *red = (PathSums<double> *)(smem + (size_t)TP * zstride * 8);   // [4][TP]
+
+    int o = 0;
+    for (;;) {
+        const long long unit = next_unit(counter, &s_unit);
+        if (unit >= total_units) break;
+        locate_unit(unit_prefix, n_opts, unit, o);
+        const OptDev &op = opts[o];
+        const int n = op.n;
+        const int64_t rem = unit - op.unit0;
+        const int shift = (int)(rem / op.chunks);
+        const int64_t chunk = rem - (int64_t)shift * op.chunks;
+        const int64_t k_end = op.k_begin + op.n_points;
+        const int64_t t0 = op.k_begin + chunk * QCPW_CHUNK;
+        const int64_t t1 = min(t0 + (int64_t)QCPW_CHUNK, k_end);
+        const int myj = 1 + 64 * wave + lane;
+        uint32_t U = 0;
+        if (myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
+        const int jcount = max(0, min(64, n - 64 * wave));
+        double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
+
+        for (int64_t base = t0; base < t1; base += TP) {
+            for (int jj = 0; jj < jcount; ++jj) {
+                const int j = 1 + 64 * wave + jj;
+                const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
+                Z[lane * zstride + (j - 1)] = ninv_f64(y) * op.zscale;
+            }
+            if (base + TP < t1 && myj <= n) {
+                const uint32_t *v = dir + (size_t)myj * 32;
+                U ^= v[5] ^ v[6 + __builtin_ctzll(((uint64_t)base >> 6) + 1)];
+            }
+            __syncthreads();
+            // rows m = wave, wave + 4, ...: W'_m = sum_i A[m][i] z'_i, four rows at a time
+            PathSums<double> ps;
+            sums_neutral(ps);
+            const double drift = op.ydrift_1;
+            for (int m0 = wave; m0 < n; m0 += 16) {
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                const double *A0 = op.pca_A64 + (size_t)m0 * n;
+                for (int i = 0; i < n; ++i) {
+                    const double z = Z[lane * zstride + i];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (m0 + 4 * q < n) acc[q] = fma(A0[(size_t)4 * q * n + i], z, acc[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = m0 + 4 * q;
+                    if (m < n) {
+                        const double mf = (double)(m + 1);
+                        sums_add_date<double>(ps, fma(drift, mf, acc[q]), mf);
+                    }
+                }
+            }
+            red[wave * TP + lane] = ps;
+            __syncthreads();
+            if (wave == 0) {
+                const int waves_pt[4] = {0, 1, 2, 3};
+                tile_tail<double>(op, red, lane, base + lane < t1, 4, waves_pt, s, c);
+            }
+            __syncthreads();
+        }
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                wave_reduce(s[i], c[i]);
+                if (lane == 0) {
+                    partials[unit * 8 + i] = s[i];
+                    partials[unit * 8 + 4 + i] = c[i];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// launch
+// ------------------------------------------------------------------------
 qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, const LaunchDesc &ld,
                         const OptDev *d_opts)
 {
-    (void)ctx; (void)lp; (void)stream; (void)ld; (void)d_opts;
-    return fail(QCPW_EINVAL, "PCA path construction is not available in this build");
+    (void)d_opts;
+    int np_max = 32, n_max = 1;
+    for (const auto &op : lp.opts) {
+        np_max = std::max(np_max, op.pca_np);
+        n_max = std::max(n_max, op.n);
+    }
+    const void *fn;
+    size_t lds;
+    int extra;
+    if (lp.precision == QCPW_FP64) {
+        fn = reinterpret_cast<const void *>(&pca_f64_kernel);
+        lds = (size_t)TP * (n_max + 1) * 8 + (size_t)PCA_WAVES * TP * sizeof(PathSums<double>);
+        extra = n_max;
+    } else {
+        const bool bf = lp.pca_gemm == QCPW_GEMM_BF16X3;
+        fn = bf ? reinterpret_cast<const void *>(&pca_f32_kernel<true>)
+                : reinterpret_cast<const void *>(&pca_f32_kernel<false>);
+        const size_t z = bf ? (size_t)2 * TP * (np_max + 8) * 2 : (size_t)TP * (np_max + 1) * 4;
+        lds = (z + 15) / 16 * 16 + (size_t)PCA_WAVES * TP * sizeof(PathSums<float>);
+        extra = np_max;
+    }
+    if (lds > 160 * 1024) return fail(QCPW_EDIMS, "PCA tile exceeds 160 KiB of LDS");
+    QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    const int bd = 64 * PCA_WAVES;
+    QCPW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds));
+    if (per_cu < 1) return fail(QCPW_EDEVICE, "PCA kernel cannot be resident");
+    int64_t grid = std::min<int64_t>((int64_t)per_cu * ctx->tab.n_cu, lp.total_units);
+    const OptDev *a_opts = ld.opts;
+    const int64_t *a_prefix = ld.unit_prefix;
+    const uint32_t *a_dir = ld.dir, *a_lane = ld.lane;
+    double *a_part = ld.partials;
+    unsigned long long *a_ctr = ld.counter;
+    int a_nopts = ld.n_opts;
+    long long a_total = ld.total_units;
+    void *args[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_part, &a_ctr, &a_nopts, &extra, &a_total};
+    QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
+    return QCPW_OK;
 }
 
 }  // namespace qcpw

@@ -58,7 +58,7 @@ struct Context {
     hipEvent_t ws_done = nullptr;   // recorded after the last launch that used ws
     bool ws_pending = false;
     // PCA factors, keyed by (n, dt bits)
-    struct Pca { int n; double dt; float *A32 = nullptr; double *A64 = nullptr;
+    struct Pca { int n; double dt; int np; float *At = nullptr; double *A64 = nullptr;
                  uint16_t *Ahi = nullptr, *Alo = nullptr; };
     std::deque<Pca> pca;     // deque: pointers stay valid as factors are added
 };

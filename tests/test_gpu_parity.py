@@ -202,3 +202,102 @@ def test_full_size_three_products_sampled(prec):
     # replications are exchangeable: the spread of C_l is the reported stderr
     se = ps.std(axis=1, ddof=1) / np.sqrt(32)
     assert np.allclose(se, e, rtol=1e-9, atol=1e-300)
+
+
+# ------------------------------------------------------------------------
+# principal components on the matrix cores
+# ------------------------------------------------------------------------
+# FP32 MFMA keeps the FP32 bound; the BF16x3 split carries ~2^-17 relative
+# error per product into W~, which psi amplifies like any other path error.
+BF16X3_TOL = np.array([2e-4, 2e-4, 1e-3, 2e-3])
+
+
+@pytest.mark.parametrize("d", [2, 17, 64, 100, 257])
+def test_fp64_pca_parity(d):
+    opts = workloads.three_products_grid(d=d, n_points=8192 + 150)[::4]
+    say("pca fp64", d)
+    g, e, ps = q.greeks(opts, 2, q.PATH_PCA, q.FP64, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_PCA)
+    assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
+
+
+@pytest.mark.parametrize("gemm,tol", [(q.GEMM_FP32, FP32_TOL), (q.GEMM_BF16X3, BF16X3_TOL)])
+@pytest.mark.parametrize("d", [17, 64, 257])
+def test_pca_matrix_cores_within_bound(gemm, tol, d):
+    opts = workloads.three_products_grid(d=d, n_points=4096 + 100)[::3]
+    say("pca mfma", gemm, d)
+    g, e, ps = q.greeks(opts, 2, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_PCA)
+    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    say("pca scaled error", gemm, d, err.max(axis=(0, 1)))
+    for k in range(4):
+        assert err[..., k].max() <= tol[k], (k, err[..., k].max())
+
+
+def test_pca_full_size_properties():
+    """The d = 256 PCA workload at full size (2 options x 2^22 points x 16
+    shifts): the matrix-core results agree with the FP64 path at the same
+    points within their bounds, and the standard errors match the spread of
+    the replications."""
+    opts = workloads.pca_pair(d=256, n_points=1 << 22)
+    say("pca full fp64")
+    g64, e64, p64 = q.greeks(opts, 16, q.PATH_PCA, q.FP64, per_shift=True)
+    for gemm, tol in [(q.GEMM_FP32, FP32_TOL), (q.GEMM_BF16X3, BF16X3_TOL)]:
+        say("pca full", gemm)
+        g, e, ps = q.greeks(opts, 16, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+        o1 = [oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["seed"], 512, 1,
+                            oracle.PATH_PCA)["abs_mean"] for o in opts]
+        scale = np.array(o1)[:, None, :]
+        err = np.abs(ps - p64) / np.maximum(np.abs(p64), scale)
+        say("full pca scaled diff", gemm, err.max(axis=(0, 1)))
+        for k in range(4):
+            assert err[..., k].max() <= tol[k]
+        se = ps.std(axis=1, ddof=1) / 4.0
+        assert np.allclose(se, e, rtol=1e-9, atol=1e-300)
+
+
+# ------------------------------------------------------------------------
+# serving: continuous batching
+# ------------------------------------------------------------------------
+def test_server_results_match_direct_calls_and_overlap():
+    """Requests submitted while others run are admitted into later launches;
+    each result equals a direct call on the same options at the number of
+    points the request reached (same points, same shifts)."""
+    import time
+    reqs = [workloads.portfolio(n, seed=100 + i, d_range=(8, 96)) for i, n in enumerate([3, 40, 1, 17, 64, 5])]
+    with q.Server(hbm_budget_bytes=1 << 30, precision=q.FP32_MIXED) as srv:
+        ids = []
+        for i, opts in enumerate(reqs):
+            ids.append(srv.submit(opts, 8, target_stderr=1e-4))
+            if i == 2:
+                time.sleep(0.01)   # later requests arrive while earlier ones run
+        results = [srv.wait(rid, len(opts)) for rid, opts in zip(ids, reqs)]
+        st = srv.stats()
+    say("server stats", st)
+    assert st["completed"] == len(reqs) and st["bytes_in_use"] == 0
+    for opts, (g, e, pts) in zip(reqs, results):
+        assert pts >= 1 << 14 and pts <= 1 << 22
+        gd, ed = q.greeks([dict(o, n_points=pts) for o in opts], 8, q.PATH_BB, q.FP32_MIXED)
+        scale = np.maximum(np.abs(gd), 1e-12)
+        assert np.all(np.abs(g - gd) <= 1e-12 * scale + 1e-15), np.abs(g - gd).max()
+        met = (e[:, 1:] <= 1e-4 * np.maximum(1.0, np.abs(g[:, 1:]))).all()
+        assert met or pts == 1 << 22
+
+
+def test_server_admission_budget_and_cancel():
+    # each request holds 20 options x 16 shifts (~5.3 MB at its largest
+    # round), so at most two of them fit the 12 MB budget at a time
+    small = workloads.portfolio(20, seed=1, d_range=(8, 32))
+    with q.Server(hbm_budget_bytes=12 << 20, precision=q.FP32_MIXED) as srv:
+        with pytest.raises(q.QcpwError):
+            srv.submit(workloads.portfolio(200, seed=2), 16, 1e-6)      # alone exceeds the budget
+        ids = [srv.submit(small, 16, 1e-9) for _ in range(6)]           # unmet target: run to the cap
+        srv.cancel(ids[-1])
+        out = [srv.wait(i, len(small)) if i != ids[-1] else None for i in ids]
+        with pytest.raises(q.QcpwError):
+            srv.wait(ids[-1], len(small))
+        st = srv.stats()
+    say("admission stats", st)
+    assert st["peak_bytes"] <= 12 << 20
+    assert st["cancelled"] >= 1
+    assert all(o[2] == 1 << 22 for o in out if o is not None)
