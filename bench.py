@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     p.add_argument("--no-extras", action="store_true", help="skip the FP64 and CPU legs")
     p.add_argument("--cpu-points", type=int, default=1 << 19)
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="after the timed loop, run one plain device copy of this many MiB "
+                        "(reference kernel for HBM byte counters)")
     return p.parse_args()
 
 
@@ -94,6 +97,12 @@ def main():
         return wall, ev_ms
 
     wall, ev_ms = timed(prec, a.steps, a.warmup)
+    if a.copy_mib > 0:
+        src = torch.ones(a.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print("timed %d steps: %.3f s wall, %.3f ms/launch (events)" % (a.steps, wall, ev_ms),
           file=sys.stderr, flush=True)
     value = n_paths * a.steps / wall

@@ -41,21 +41,21 @@ __device__ inline float horner(const float (&c)[N], float v)
     return p;
 }
 
-// Phi^{-1}((y + 1/2) 2^-32) * scale in FP32.
-// With m = min(y, ~y) (so the uniform is folded onto (0, 1/2]) the two
-// quantities that lose no precision are q = (m + 1/2) 2^-32 and
-// |x| = 1 - 2q = (2 (2^31 - 1 - m) + 1) 2^-32, both formed from integers.
-// Phi^{-1}(u) = sqrt(2) erfinv(2u - 1), and erfinv(x)/x is a polynomial in
-// w = -ln(1 - x^2) = -ln(4 q (1 - q)) (two branches, coefficients in
-// ninv_f32_coeffs.inc).  The sign is + iff y >= 2^31.
-__device__ inline float ninv_scaled_f32(uint32_t y, float scale)
+// Phi^{-1}((y + 1/2) 2^-32) * scale in FP32, with sa = scale * 2^-31 and
+// sb = scale * 2^-32 (scale includes the sqrt(2) of
+// Phi^{-1}(u) = sqrt(2) erfinv(2u - 1)).
+// Folding y onto the lower half, m = min(y, ~y), gives q = (m + 1/2) 2^-32
+// exactly from an integer; x = 2u - 1 = (2 (y - 2^31) + 1) 2^-32 likewise
+// (signed, so it carries the sign of the result).  erfinv(x)/x is a
+// polynomial in w = -ln(1 - x^2) = -ln(4 q (1 - q)) (two branches,
+// coefficients in ninv_f32_coeffs.inc).
+__device__ inline float ninv_scaled_f32(uint32_t y, float sa, float sb)
 {
-    const uint32_t neg = (uint32_t)((int32_t)y >> 31);   // all ones iff y >= 2^31
-    const uint32_t m = y ^ neg;
+    const uint32_t m = y ^ (uint32_t)((int32_t)y >> 31);   // min(y, ~y)
     const float q = fmaf((float)m, 0x1p-32f, 0x1p-33f);
-    const float ax = fmaf((float)(m ^ 0x7FFFFFFFu), 0x1p-31f, 0x1p-32f);
-    const float t = fmaf(-q, q, q);                       // q (1 - q) = (1 - x^2) / 4
-    const float lg = __builtin_amdgcn_logf(t);            // log2 t
+    const float xs = fmaf((float)(int32_t)(y ^ 0x80000000u), sa, sb);   // scale * (2u - 1)
+    const float t = fmaf(-q, q, q);                         // q (1 - q) = (1 - x^2) / 4
+    const float lg = __builtin_amdgcn_logf(t);              // log2 t
     constexpr float LN2 = 0.693147180559945309f;
     constexpr float LG_SPLIT = -(QCPW_NINV_WSPLIT / 0.693147180559945309f) - 2.0f;
     float p;
@@ -65,8 +65,7 @@ __device__ inline float ninv_scaled_f32(uint32_t y, float scale)
         const float w = fmaf(lg, -LN2, -2.0f * LN2);
         p = horner(QCPW_NINV_Q, __builtin_amdgcn_sqrtf(w) - QCPW_NINV_C2);
     }
-    const float k = neg ? scale : -scale;                 // scale already holds sqrt(2)
-    return (p * ax) * k;
+    return p * xs;
 }
 
 // Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library), evaluated on the
@@ -196,7 +195,7 @@ template <bool F32>
 __device__ inline typename Real<F32>::T coord(uint32_t y, const OptDev &op)
 {
     if constexpr (F32) {
-        return ninv_scaled_f32(y, op.zscale_f);
+        return ninv_scaled_f32(y, op.zs_a, op.zs_b);
     } else {
         return ninv_f64(y) * op.zscale;
     }

@@ -498,6 +498,8 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.inv_S0sq = 1.0 / (sp.S0 * sp.S0);
         // FP32 kernels fold sqrt(2) of Phi^{-1}(u) = sqrt(2) erfinv(2u-1) into the scale
         op.zscale_f = (float)(op.zscale * M_SQRT2);
+        op.zs_a = (float)(op.zscale * M_SQRT2 * 0x1p-31);
+        op.zs_b = (float)(op.zscale * M_SQRT2 * 0x1p-32);
         op.ydrift_n_f = (float)op.ydrift_n;
         op.ydrift_1_f = (float)op.ydrift_1;
         op.kappa_f = (float)op.kappa;

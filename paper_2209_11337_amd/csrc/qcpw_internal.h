@@ -66,6 +66,7 @@ struct OptDev {
     double inv_s1, s1, sqrt_t1, inv_sigma;
     double S0, K, D, D1, invd, inv_S0, inv_S0sq;
     float zscale_f, ydrift_n_f, ydrift_1_f, kappa_f;
+    float zs_a, zs_b;             // sqrt(2) zscale 2^-31 and 2^-32 (FP32 inverse normal)
     // principal-component factor of this option's n (unit dt), device layouts:
     const float *pca_At;          // [NP][NP] FP32, k-major: At[k][row]
     const uint16_t *pca_hi;       // [NP/16][NP][16] BF16 hi part, 16-wide k slabs
