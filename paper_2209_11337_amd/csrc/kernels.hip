@@ -75,6 +75,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
     for (int q = 0; q < QCPW_UQ; ++q) {
         const int s_lo = q == 0 ? 1 : 64 * q;
         const int s_hi = min(64 * (q + 1), n);
+#pragma unroll 2
         for (int s = s_lo; s < s_hi; ++s) {
             const PlanStep st = plan[s];
             for (int p = 0; p < st.pops; ++p) {

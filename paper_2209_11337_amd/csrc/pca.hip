@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             for (int jj = 0; jj < jcount; ++jj) {
                 const int j = 1 + 64 * wave + jj;
                 const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
-                const float z = ninv_scaled_f32(y, op.zs_a, op.zs_b);
+                const float z = ninv_scaled_f32(y, op.zs_a);
                 const int k = j - 1;
                 if (BF16X3) {
                     const unsigned short h = bf16_bits(z);
