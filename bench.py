@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     p.add_argument("--no-extras", action="store_true", help="skip the FP64 and CPU legs")
     p.add_argument("--cpu-points", type=int, default=1 << 19)
+    p.add_argument("--no-portfolio", action="store_true", help="skip the uneven-portfolio leg")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed loop, run one plain device copy of this many MiB "
                         "(reference kernel for HBM byte counters)")
@@ -154,7 +156,109 @@ def main():
                                "cores": used, "kind": "oracle",
                                "sample": "the 18 options at d=64, 2^%d points x %d shifts (%.1f s)"
                                          % (int(np.log2(n_cpu)), Ls, tc)}
+    if not a.no_extras and not a.no_portfolio:
+        res["portfolio"] = portfolio_leg(q, workloads, torch)
+    if not a.no_extras and not a.no_serve:
+        res["serving"] = serving_leg(q, workloads)
     print(json.dumps(res), flush=True)
+
+
+def portfolio_leg(q, workloads, torch):
+    """4096 options of uneven type, d, K, sigma, T, r and 2^14..2^20 points,
+    16 shifts, FP32-mixed, in one persistent launch; beside it the plain
+    path (FP64, one option per launch) on a fixed sample of the options."""
+    opts = workloads.portfolio(4096)
+    L = 16
+    q.greeks(opts[:64], L, q.PATH_BB, q.FP32_MIXED)   # warm the tables / workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, e = q.greeks(opts, L, q.PATH_BB, q.FP32_MIXED)
+    t = time.perf_counter() - t0
+    paths = workloads.total_paths(opts, L)
+    sample = opts[::128]
+    t1 = time.perf_counter()
+    for o in sample:
+        q.greeks([o], L, q.PATH_BB, q.FP64)
+    t64 = time.perf_counter() - t1
+    p64 = workloads.total_paths(sample, L)
+    return {"options": len(opts), "shifts": L, "greek_paths": paths,
+            "path_dates": workloads.total_path_dates(opts, L), "seconds": t, "value": paths / t,
+            "unit": "Greek-paths/s", "precision": "fp32-mixed, one persistent launch",
+            "fp64_one_option_per_launch": {"value": p64 / t64, "sample": "every 128th option (%d)" % len(sample),
+                                           "seconds": t64}}
+
+
+def serving_leg(q, workloads, n_requests=300, rate=150.0):
+    """Poisson request stream into the continuous-batching server (FP32-mixed):
+    requests of 1..32 options (d in [4, 64]) with a target standard error of
+    1e-3 or 1e-4 (relative to max(1, |Greek|)); latency = submit to result.
+    Beside it the plain path: each option of the first 40 requests alone in
+    FP64 at the point count the server reached."""
+    import threading
+    stream = workloads.request_stream(n_requests, rate, max_opts=32, d_range=(4, 64), targets=(1e-3, 1e-4))
+    L = 16
+    lat, pts, paths = [], [], 0
+    done = {}
+    pending = []
+    lock = threading.Lock()
+    finished = threading.Event()
+    with q.Server(hbm_budget_bytes=8 << 30, precision=q.FP32_MIXED) as srv:
+
+        def poller():
+            # completion times are taken as soon as a result is ready
+            while True:
+                with lock:
+                    todo = list(pending)
+                for item in todo:
+                    rid, ts, r = item
+                    out = srv.poll(rid, len(r["options"]))
+                    if out is not None:
+                        done[rid] = (time.perf_counter() - ts, out[2])
+                        with lock:
+                            pending.remove(item)
+                if finished.is_set() and not todo:
+                    return
+                time.sleep(0.0002)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t0 = time.perf_counter()
+        ids = []
+        for r in stream:
+            now = time.perf_counter() - t0
+            if r["t_arrival"] > now:
+                time.sleep(r["t_arrival"] - now)
+            item = (srv.submit(r["options"], L, r["target_stderr"]), time.perf_counter(), r)
+            ids.append(item)
+            with lock:
+                pending.append(item)
+        finished.set()
+        th.join()
+        wall = time.perf_counter() - t0
+        stats = srv.stats()
+    for rid, ts, r in ids:
+        l, p = done[rid]
+        lat.append(l)
+        pts.append(p)
+        paths += len(r["options"]) * p * L
+    lat = np.array(lat) * 1e3
+    # plain FP64, one option per launch, same points
+    base_lat, base_paths, t64 = [], 0, 0.0
+    for (rid, ts, r), p in list(zip(ids, pts))[:40]:
+        t1 = time.perf_counter()
+        for o in r["options"]:
+            q.greeks([dict(o, n_points=p)], L, q.PATH_BB, q.FP64)
+        dt = time.perf_counter() - t1
+        base_lat.append(dt * 1e3)
+        t64 += dt
+        base_paths += len(r["options"]) * p * L
+    return {"requests": n_requests, "rate_per_s": rate, "shifts": L, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_points": float(np.mean(pts)),
+            "value": paths / wall, "unit": "Greek-paths/s", "launches": stats["launches"],
+            "fp64_one_option_per_launch": {"value": base_paths / t64,
+                                           "p50_ms_no_queueing": float(np.percentile(base_lat, 50)),
+                                           "p99_ms_no_queueing": float(np.percentile(base_lat, 99)),
+                                           "sample": "first 40 requests"}}
 
 
 if __name__ == "__main__":

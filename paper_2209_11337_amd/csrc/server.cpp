@@ -1,14 +1,21 @@
 // server.cpp -- continuous batching of Greek requests on one device.
 //
 // A worker thread owns two launch slots (stream + workspace each).  While one
-// launch runs, the worker packs everything runnable into the other slot and
-// enqueues it, so work of requests that arrived meanwhile overlaps on the
+// launch runs, the worker packs the next runnable work into the other slot
+// and enqueues it, so work of requests that arrived meanwhile overlaps on the
 // device with work already running.  Requests are admitted in arrival order
-// as long as their device footprint fits the HBM budget; a request's options
-// start at 2^14 points per replication and double (only the new points are
-// computed: Sobol points extend, and the sums of earlier rounds are kept)
-// until the standard errors of delta, vega and gamma meet the target or
-// 2^22 points are reached.
+// as long as their device footprint fits the HBM budget.
+//
+// Point schedule: a request starts with 2^14 points per replication; once a
+// round is complete its standard errors predict how many points the target
+// needs (error ~ n^-3/4, between the Monte Carlo and QMC rates), and the next
+// round extends the point set to that power of two (Sobol points extend, so
+// all earlier sums are kept), at least doubling, up to 2^22.
+//
+// Launch size: a launch carries at most ~kLaunchPathDates path-dates.  A
+// large round is cut into point ranges (slices) that ride in successive
+// launches, so a request that arrives behind it waits for one bounded launch
+// rather than for the whole round.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +38,7 @@ static constexpr int64_t kFirstPoints = int64_t(1) << 14;
 static constexpr int64_t kMaxPoints = int64_t(1) << 22;
 static constexpr int kMaxBatchOptions = 8192;
 static constexpr int kSlots = 2;
+static constexpr double kLaunchPathDates = 2.0e10;   // ~25 ms of FP32-mixed work
 
 enum ReqState { RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_CANCELLED };
 
@@ -42,7 +50,10 @@ struct Request {
     ReqState state = RQ_QUEUED;
     bool in_flight = false;
     int64_t n_done = 0;            // points per replication already summed
-    int64_t n_next = 0;            // points after the round in flight
+    int64_t n_target = 0;          // end of the current round
+    int64_t n_issued = 0;          // points handed to launches (n_done <= n_issued <= n_target)
+    int slices_in_flight = 0;
+    double cost_per_point = 0.0;   // path-dates per point (all options, all replications)
     std::vector<double> S, Cc;     // [n_opts][L][4] compensated sums of F over points
     std::vector<double> greeks, stderr_;
     int64_t footprint = 0;
@@ -64,6 +75,7 @@ struct Slot {
     Workspace ws;
     bool busy = false;
     std::vector<Request *> reqs;
+    std::vector<int64_t> k0, len;      // point slice of each request in the launch
     std::vector<int> first_opt;        // first option of each request in the launch
     std::vector<double> per_shift;     // host copy [n][L][4]
     std::vector<double> g, e;
@@ -94,8 +106,7 @@ namespace qcpw {
 
 static void finish_locked(qcpw_server *s, Request *r, ReqState st)
 {
-    r->state = st;
-    r->in_flight = false;
+    r->state = st;   // slices still in launches keep r->in_flight until absorbed
     if (r->charged) {
         s->in_use -= r->footprint;
         r->charged = false;
@@ -105,14 +116,20 @@ static void finish_locked(qcpw_server *s, Request *r, ReqState st)
     s->cv_done.notify_all();
 }
 
-// Pick runnable requests for one launch (caller holds the lock).  All
-// requests of a launch share path construction and replication count; the
-// oldest runnable request decides which.
-static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out)
+// Pick the work of one launch (caller holds the lock): running requests
+// with points left in their round, then newly admitted ones, each with one
+// slice, until the launch's path-date budget is used.  All requests of a
+// launch share path construction and replication count; the oldest runnable
+// request decides which.
+static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out, std::vector<int64_t> &k0,
+                              std::vector<int64_t> &len)
 {
     out.clear();
+    k0.clear();
+    len.clear();
     int group_path = -1, group_L = -1;
     int n_opts = 0;
+    double budget = kLaunchPathDates;
     auto fits_group = [&](Request *r) {
         if (group_path < 0) {
             group_path = r->path;
@@ -120,17 +137,29 @@ static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out)
         }
         return r->path == group_path && r->n_shifts == group_L;
     };
-    // running requests that need another round already hold their budget
-    for (auto &kv : s->reqs) {
+    auto take = [&](Request *r) {
+        const int64_t remaining = r->n_target - r->n_issued;
+        int64_t cap = (int64_t)(budget / r->cost_per_point) / QCPW_CHUNK * QCPW_CHUNK;
+        if (cap < QCPW_CHUNK) cap = QCPW_CHUNK;
+        const int64_t l = std::min(remaining, cap);
+        out.push_back(r);
+        k0.push_back(r->n_issued);
+        len.push_back(l);
+        r->n_issued += l;
+        r->slices_in_flight += 1;
+        r->in_flight = true;
+        budget -= (double)l * r->cost_per_point;
+        n_opts += (int)r->specs.size();
+    };
+    for (auto &kv : s->reqs) {   // ids increase with arrival: FIFO
         Request *r = kv.second.get();
-        if (r->state != RQ_RUNNING || r->in_flight) continue;
+        if (budget <= 0.0) break;
+        if (r->state != RQ_RUNNING || r->n_issued >= r->n_target) continue;
         if (!fits_group(r)) continue;
         if (n_opts + (int)r->specs.size() > kMaxBatchOptions && !out.empty()) break;
-        out.push_back(r);
-        n_opts += (int)r->specs.size();
+        take(r);
     }
-    // admit queued requests in arrival order while budget and slots allow
-    while (!s->queue.empty()) {
+    while (!s->queue.empty() && budget > 0.0) {
         auto it = s->reqs.find(s->queue.front());
         if (it == s->reqs.end() || it->second->state != RQ_QUEUED) {
             s->queue.pop_front();
@@ -146,28 +175,28 @@ static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out)
         s->in_use += r->footprint;
         s->peak = std::max(s->peak, s->in_use);
         ++s->n_admitted;
-        out.push_back(r);
-        n_opts += (int)r->specs.size();
-    }
-    for (Request *r : out) {
-        r->in_flight = true;
-        r->n_next = r->n_done == 0 ? kFirstPoints : 2 * r->n_done;
+        r->n_target = kFirstPoints;
+        take(r);
     }
 }
 
-static qcpw_status enqueue_slot(qcpw_server *s, Slot &sl, std::vector<Request *> &batch)
+static qcpw_status enqueue_slot(qcpw_server *s, Slot &sl, std::vector<Request *> &batch,
+                                const std::vector<int64_t> &k0, const std::vector<int64_t> &len)
 {
     std::vector<qcpw_option_spec> specs;
     std::vector<int64_t> kb;
     sl.reqs = batch;
+    sl.k0 = k0;
+    sl.len = len;
     sl.first_opt.clear();
-    for (Request *r : batch) {
+    for (size_t bi = 0; bi < batch.size(); ++bi) {
+        Request *r = batch[bi];
         sl.first_opt.push_back((int)specs.size());
         for (const auto &sp : r->specs) {
             qcpw_option_spec x = sp;
-            x.n_points = r->n_next - r->n_done;
+            x.n_points = len[bi];
             specs.push_back(x);
-            kb.push_back(r->n_done);
+            kb.push_back(k0[bi]);
         }
     }
     const int n = (int)specs.size();
@@ -200,18 +229,29 @@ static qcpw_status enqueue_slot(qcpw_server *s, Slot &sl, std::vector<Request *>
     return QCPW_OK;
 }
 
+// Next round end after a complete round: the largest ratio of standard
+// error to target predicts the points needed with error ~ n^-3/4.
+static int64_t next_round_end(const Request *r, double worst_ratio)
+{
+    const double factor = std::pow(std::max(worst_ratio, 1.0), 4.0 / 3.0) * 1.2;
+    int64_t n = 2 * r->n_done;
+    while ((double)n < (double)r->n_done * factor && n < kMaxPoints) n *= 2;
+    return std::min(n, kMaxPoints);
+}
+
 // Fold a finished launch into its requests (caller holds the lock).
 static void absorb_slot_locked(qcpw_server *s, Slot &sl)
 {
     for (size_t bi = 0; bi < sl.reqs.size(); ++bi) {
         Request *r = sl.reqs[bi];
-        r->in_flight = false;
+        r->slices_in_flight -= 1;
+        r->in_flight = r->slices_in_flight > 0;
         if (r->state == RQ_CANCELLED) {
-            if (r->collected) s->reqs.erase(r->id);
+            if (r->collected && !r->in_flight) s->reqs.erase(r->id);
             continue;
         }
         const int n = (int)r->specs.size(), L = r->n_shifts;
-        const double len = (double)(r->n_next - r->n_done);
+        const double len = (double)sl.len[bi];
         if (r->S.empty()) {
             r->S.assign((size_t)n * L * 4, 0.0);
             r->Cc.assign((size_t)n * L * 4, 0.0);
@@ -226,11 +266,12 @@ static void absorb_slot_locked(qcpw_server *s, Slot &sl)
                     r->Cc[dst] += (r->S[dst] - (t - bp)) + (x - bp);
                     r->S[dst] = t;
                 }
-        r->n_done = r->n_next;
+        r->n_done += sl.len[bi];
+        if (r->n_done < r->n_target) continue;   // round not complete yet
         // mean and standard error over replications
         r->greeks.assign((size_t)n * 4, 0.0);
         r->stderr_.assign((size_t)n * 4, 0.0);
-        bool met = true;
+        double worst = 0.0;
         for (int i = 0; i < n; ++i)
             for (int k = 0; k < 4; ++k) {
                 double m = 0.0;
@@ -248,9 +289,13 @@ static void absorb_slot_locked(qcpw_server *s, Slot &sl)
                 const double se = L >= 2 ? std::sqrt(v / ((double)L * (L - 1))) : NAN;
                 r->greeks[(size_t)i * 4 + k] = m;
                 r->stderr_[(size_t)i * 4 + k] = se;
-                if (k >= 1 && !(se <= r->target * std::max(1.0, std::fabs(m)))) met = false;
+                if (k >= 1) {
+                    const double ratio = se / (r->target * std::max(1.0, std::fabs(m)));
+                    worst = std::isnan(ratio) ? INFINITY : std::max(worst, ratio);
+                }
             }
-        if (met || r->n_done >= kMaxPoints) finish_locked(s, r, RQ_DONE);
+        if (worst <= 1.0 || r->n_done >= kMaxPoints) finish_locked(s, r, RQ_DONE);
+        else r->n_target = next_round_end(r, std::min(worst, 1e6));
     }
     sl.reqs.clear();
     sl.busy = false;
@@ -259,7 +304,12 @@ static void absorb_slot_locked(qcpw_server *s, Slot &sl)
 
 static void fail_slot_locked(qcpw_server *s, Slot &sl)
 {
-    for (Request *r : sl.reqs) finish_locked(s, r, RQ_CANCELLED);
+    for (Request *r : sl.reqs) {
+        r->slices_in_flight -= 1;
+        r->in_flight = r->slices_in_flight > 0;
+        if (r->state == RQ_QUEUED || r->state == RQ_RUNNING) finish_locked(s, r, RQ_CANCELLED);
+        if (r->collected && !r->in_flight) s->reqs.erase(r->id);
+    }
     sl.reqs.clear();
     sl.busy = false;
 }
@@ -268,7 +318,7 @@ static bool work_available_locked(qcpw_server *s)
 {
     if (!s->queue.empty()) return true;
     for (auto &kv : s->reqs)
-        if (kv.second->state == RQ_RUNNING && !kv.second->in_flight) return true;
+        if (kv.second->state == RQ_RUNNING && kv.second->n_issued < kv.second->n_target) return true;
     return false;
 }
 
@@ -286,6 +336,7 @@ static void worker_main(qcpw_server *s)
     uint64_t seq = 0, slot_seq[kSlots] = {};
     for (;;) {
         std::vector<Request *> batch;
+        std::vector<int64_t> bk0, blen;
         int free_slot = -1, busy = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
@@ -299,11 +350,11 @@ static void worker_main(qcpw_server *s)
                     free_slot = i;
                     break;
                 }
-            if (free_slot >= 0) pick_batch_locked(s, batch);
+            if (free_slot >= 0) pick_batch_locked(s, batch, bk0, blen);
         }
         if (!batch.empty()) {
             Slot &sl = s->slots[free_slot];
-            if (enqueue_slot(s, sl, batch) == QCPW_OK) {
+            if (enqueue_slot(s, sl, batch, bk0, blen) == QCPW_OK) {
                 slot_seq[free_slot] = ++seq;
                 ++busy;
             } else {
@@ -373,6 +424,7 @@ qcpw_status qcpw_submit(qcpw_server *srv, const qcpw_option_spec *specs, int32_t
     r->path = path_construction;
     r->target = target_stderr;
     r->footprint = option_footprint(n_shifts) * n_opts;
+    for (int i = 0; i < n_opts; ++i) r->cost_per_point += (double)std::max(specs[i].d - 1, 1) * n_shifts;
     if (r->footprint > srv->budget) return fail(QCPW_ENOMEM, "request footprint exceeds the HBM budget");
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return fail(QCPW_EINVAL, "server is shutting down");

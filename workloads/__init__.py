@@ -98,10 +98,10 @@ def portfolio(n_opts: int = 4096, seed: int = 220911337, d_range=(4, 365),
 
 
 def request_stream(n_requests: int, rate_per_s: float, seed: int = 22091,
-                   max_opts: int = 512, d_range=(4, 365)) -> list[dict]:
+                   max_opts: int = 512, d_range=(4, 365), targets=(1e-4, 1e-6)) -> list[dict]:
     """Poisson arrivals: exponential gaps at rate_per_s; each request holds
     U{1..max_opts} options drawn as in ``portfolio`` and a target standard
-    error of 1e-4 or 1e-6 (equal odds)."""
+    error drawn from ``targets`` (equal odds; 1e-4 or 1e-6 by default)."""
     g = _rng(seed)
     gaps = g.exponential(1.0 / rate_per_s, size=n_requests)
     t = np.cumsum(gaps) - gaps[0]
@@ -110,7 +110,7 @@ def request_stream(n_requests: int, rate_per_s: float, seed: int = 22091,
         n = int(g.integers(1, max_opts + 1))
         opts = portfolio(n, seed=int(g.integers(0, 2**31)), d_range=d_range)
         out.append(dict(t_arrival=float(t[i]), options=opts,
-                        target_stderr=float(g.choice([1e-4, 1e-6]))))
+                        target_stderr=float(g.choice(list(targets)))))
     return out
 
 
