@@ -156,11 +156,34 @@ def main():
                                "cores": used, "kind": "oracle",
                                "sample": "the 18 options at d=64, 2^%d points x %d shifts (%.1f s)"
                                          % (int(np.log2(n_cpu)), Ls, tc)}
+    if not a.no_extras:
+        res["small_call"] = small_call_leg(q, workloads, torch)
     if not a.no_extras and not a.no_portfolio:
         res["portfolio"] = portfolio_leg(q, workloads, torch)
     if not a.no_extras and not a.no_serve:
         res["serving"] = serving_leg(q, workloads)
     print(json.dumps(res), flush=True)
+
+
+def small_call_leg(q, workloads, torch, calls=200):
+    """Latency-bound call: one arithmetic Asian, d = 16, 2^12 points x 16
+    shifts, FP64 bridge, device outputs; per-call time eager vs replayed
+    from a captured HIP graph."""
+    opts = workloads.single_asian()
+    s = torch.cuda.Stream()
+    out = (torch.empty((1, 4), dtype=torch.float64, device="cuda"),
+           torch.empty((1, 4), dtype=torch.float64, device="cuda"))
+    res = {"workload": "1 arithmetic Asian, d=16, 2^12 points x 16 shifts, FP64, bridge"}
+    for name, graph in (("eager_us", False), ("graph_us", True)):
+        for _ in range(3):
+            q.greeks(opts, 16, q.PATH_BB, q.FP64, device_outputs=True, out=out, stream=s, graph=graph)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            q.greeks(opts, 16, q.PATH_BB, q.FP64, device_outputs=True, out=out, stream=s, graph=graph)
+        s.synchronize()
+        res[name] = (time.perf_counter() - t0) / calls * 1e6
+    return res
 
 
 def portfolio_leg(q, workloads, torch):
@@ -188,7 +211,7 @@ def portfolio_leg(q, workloads, torch):
                                            "seconds": t64}}
 
 
-def serving_leg(q, workloads, n_requests=300, rate=150.0):
+def serving_leg(q, workloads, n_requests=300, rate=100.0):
     """Poisson request stream into the continuous-batching server (FP32-mixed):
     requests of 1..32 options (d in [4, 64]) with a target standard error of
     1e-3 or 1e-4 (relative to max(1, |Greek|)); latency = submit to result.

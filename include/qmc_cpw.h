@@ -125,8 +125,15 @@ typedef struct {
     void *stream;               /* hipStream_t to run on (NULL = the default stream) */
     double *out_per_shift;      /* optional [n_opts][L][4] per-replication C_l       */
     int32_t block_threads;      /* 0 = autotuned; else 256, 512 or 1024             */
-    int32_t reserved;
+    int32_t flags;              /* QCPW_FLAG_* bits                                  */
 } qcpw_run_config;
+
+/* Capture the device work of a call into a HIP graph the first time a given
+ * argument set is seen and replay the graph for later calls with identical
+ * arguments (same specs, sizes, enums, stream and output pointers).  Requires
+ * outputs_on_device; the graph keeps its own device workspace (up to 16
+ * graphs are cached per device, least recently used evicted). */
+#define QCPW_FLAG_GRAPH 1
 
 /*
  * qmc_cpw_greeks_ex -- as qmc_cpw_greeks with explicit precision, device,

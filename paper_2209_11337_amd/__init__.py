@@ -24,6 +24,7 @@ ARITH_ASIAN, BINARY_ASIAN, LOOKBACK = 0, 1, 2
 PATH_BB, PATH_PCA, PATH_STANDARD = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 GEMM_FP32, GEMM_BF16X3 = 0, 1
+FLAG_GRAPH = 1
 OUTPUTS = ("price", "delta", "vega", "gamma")
 MAX_D, MAX_D_PCA = 385, 257
 
@@ -51,7 +52,7 @@ class OptionSpec(C.Structure):
 class RunConfig(C.Structure):
     _fields_ = [("precision", C.c_int32), ("pca_gemm", C.c_int32), ("device", C.c_int32),
                 ("outputs_on_device", C.c_int32), ("stream", C.c_void_p),
-                ("out_per_shift", C.c_void_p), ("block_threads", C.c_int32), ("reserved", C.c_int32)]
+                ("out_per_shift", C.c_void_p), ("block_threads", C.c_int32), ("flags", C.c_int32)]
 
 
 _lib = None
@@ -122,7 +123,7 @@ def make_specs(options: Sequence[dict]) -> C.Array:
 def greeks(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precision: int = FP64,
            d: int = 0, n_points: int = 0, pca_gemm: int = GEMM_FP32, per_shift: bool = False,
            block_threads: int = 0, stream=None, device_outputs: bool = False, device: int = -1,
-           out=None):
+           out=None, graph: bool = False):
     """Greeks of many options in one launch.
 
     Host mode (default): returns (greeks[n][4], stderr[n][4]) numpy arrays
@@ -133,7 +134,7 @@ def greeks(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precisio
     specs = make_specs(options)
     n = len(options)
     cfg = RunConfig(precision, pca_gemm, device, 1 if device_outputs else 0, None, None,
-                    block_threads, 0)
+                    block_threads, FLAG_GRAPH if graph else 0)
     if device_outputs:
         import torch
         if out is None:

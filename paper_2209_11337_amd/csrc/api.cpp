@@ -14,6 +14,8 @@
 
 namespace qcpw {
 
+#include "ninv_table.inc"
+
 static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
@@ -79,6 +81,8 @@ static qcpw_status init_tables(Context *ctx, int device)
     QCPW_HIP(hipMemcpy(t.lane, lane.data(), lane.size() * 4, hipMemcpyHostToDevice));
     QCPW_HIP(hipMemcpy(t.plan, all.data(), all.size() * sizeof(PlanStep), hipMemcpyHostToDevice));
     QCPW_HIP(hipMemcpy(t.plan64, all64.data(), all64.size() * sizeof(PlanStep64), hipMemcpyHostToDevice));
+    QCPW_HIP(hipMalloc(&t.ninv_tab, sizeof(QCPW_NINV_TAB)));
+    QCPW_HIP(hipMemcpy(t.ninv_tab, QCPW_NINV_TAB, sizeof(QCPW_NINV_TAB), hipMemcpyHostToDevice));
     QCPW_HIP(hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
     QCPW_HIP(hipEventCreateWithFlags(&ctx->ws_done, hipEventDisableTiming));
     return QCPW_OK;
@@ -173,6 +177,98 @@ const char *qcpw_last_error(void) { return g_last_error.c_str(); }
 
 const char *qcpw_version(void) { return "qmc-cpw-mi355x 0.1 (gfx950)"; }
 
+}  // extern "C"
+
+namespace qcpw {
+
+static constexpr size_t kMaxGraphs = 16;
+
+static void append(std::vector<unsigned char> &k, const void *p, size_t n)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    k.insert(k.end(), b, b + n);
+}
+
+static void free_graph(Context::Graph &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.ws) (void)hipFree(g.ws);
+    if (g.host) (void)hipHostFree(g.host);
+    g = Context::Graph();
+}
+
+// QCPW_FLAG_GRAPH: replay the captured graph of an identical earlier call, or
+// capture this call's device work (uploads from pinned copies, counter reset,
+// per-path kernel, finalize) into a new graph with its own workspace.
+static qcpw_status run_graph(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
+                             int64_t n_points, int32_t n_shifts, int32_t path, const qcpw_run_config &c,
+                             double *g_out, double *e_out)
+{
+    std::vector<unsigned char> key;
+    append(key, specs, sizeof(qcpw_option_spec) * (size_t)n_opts);
+    const int64_t scal[] = {n_opts, d, n_points, n_shifts, path, c.precision, c.pca_gemm, c.block_threads};
+    append(key, scal, sizeof scal);
+    const void *ptrs[] = {c.stream, g_out, e_out, c.out_per_shift};
+    append(key, ptrs, sizeof ptrs);
+    hipStream_t stream = (hipStream_t)c.stream;
+    for (auto &g : ctx->graphs)
+        if (g.key == key) {
+            g.last_use = ++ctx->graph_clock;
+            QCPW_HIP(hipGraphLaunch(g.exec, stream));
+            return QCPW_OK;
+        }
+    LaunchPlan lp;
+    qcpw_status st = plan_launch(ctx, specs, n_opts, d, n_points, n_shifts, path, c.precision, c.pca_gemm,
+                                 c.block_threads, lp);
+    if (st != QCPW_OK) return st;
+    if (ctx->graphs.size() >= kMaxGraphs) {   // evict the least recently used
+        size_t lru = 0;
+        for (size_t i = 1; i < ctx->graphs.size(); ++i)
+            if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
+        QCPW_HIP(hipDeviceSynchronize());
+        free_graph(ctx->graphs[lru]);
+        ctx->graphs.erase(ctx->graphs.begin() + (long)lru);
+    }
+    Context::Graph g;
+    g.key = key;
+    const size_t need = launch_workspace_bytes(lp);
+    const size_t n = lp.opts.size();
+    const size_t hbytes = n * sizeof(OptDev) + (n + 1) * sizeof(int64_t);
+    if (hipMalloc(&g.ws, need) != hipSuccess || hipHostMalloc(&g.host, hbytes, hipHostMallocDefault) != hipSuccess) {
+        free_graph(g);
+        return fail(QCPW_ENOMEM, "graph workspace allocation failed");
+    }
+    OptDev *h_opts = (OptDev *)g.host;
+    int64_t *h_prefix = (int64_t *)((char *)g.host + n * sizeof(OptDev));
+    memcpy(h_opts, lp.opts.data(), n * sizeof(OptDev));
+    memcpy(h_prefix, lp.unit_prefix.data(), (n + 1) * sizeof(int64_t));
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return fail(QCPW_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    st = enqueue_launch(ctx, lp, stream, g_out, e_out, c.out_per_shift, g.ws, need, h_opts, h_prefix);
+    e = hipStreamEndCapture(stream, &g.graph);
+    if (st != QCPW_OK || e != hipSuccess) {
+        free_graph(g);
+        return st != QCPW_OK ? st : fail(QCPW_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return fail(QCPW_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    g.last_use = ++ctx->graph_clock;
+    ctx->graphs.push_back(g);
+    QCPW_HIP(hipGraphLaunch(ctx->graphs.back().exec, stream));
+    return QCPW_OK;
+}
+
+}  // namespace qcpw
+
+extern "C" {
+
 qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_opts, int32_t d,
                               int64_t n_points, int32_t n_shifts, int32_t path_construction,
                               double *out_greeks, double *out_stderr, const qcpw_run_config *cfg)
@@ -190,6 +286,12 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
     st = get_context(c.device, &ctx);
     if (st != QCPW_OK) return st;
     std::lock_guard<std::mutex> lk(ctx->mu);
+    if (c.flags & ~QCPW_FLAG_GRAPH) return fail(QCPW_EINVAL, "unknown flags");
+    if (c.flags & QCPW_FLAG_GRAPH) {
+        if (!c.outputs_on_device) return fail(QCPW_EINVAL, "QCPW_FLAG_GRAPH needs outputs_on_device");
+        return run_graph(ctx, option_specs, n_opts, d, n_points, n_shifts, path_construction, c, out_greeks,
+                         out_stderr);
+    }
     LaunchPlan lp;
     st = plan_launch(ctx, option_specs, n_opts, d, n_points, n_shifts, path_construction, c.precision,
                      c.pca_gemm, c.block_threads, lp);

@@ -10,6 +10,7 @@
 namespace qcpw {
 
 #include "ninv_f32_coeffs.inc"
+#include "ninv_table.inc"
 
 // ------------------------------------------------------------------------
 // device helpers
@@ -67,6 +68,24 @@ __device__ inline float ninv_scaled_f32(uint32_t y, float sa)
         p = horner(QCPW_NINV_Q, __builtin_amdgcn_sqrtf(w) - QCPW_NINV_C2);
     }
     return p * xs;
+}
+
+// Phi^{-1}((y + 1/2) 2^-32) * scale in FP32 from the cubic table of
+// ninv_table.inc held in LDS: q = (min(y, ~y) + 1/2) 2^-32 in FP32 (kept
+// below 1/2), its exponent and top 5 mantissa bits select the cell, its low
+// 18 mantissa bits are the cubic's variable; Phi^{-1}(q) <= 0, and the sign
+// of the result is + iff y >= 2^31.  scale > 0 (no sqrt(2) here).
+__device__ inline float ninv_table_f32(uint32_t y, float scale, const float4 *__restrict__ tab)
+{
+    const uint32_t m = y ^ (uint32_t)((int32_t)y >> 31);
+    const float q = fminf(fmaf((float)m, 0x1p-32f, 0x1p-33f), 0x1.fffffep-2f);
+    const uint32_t b = __float_as_uint(q);
+    const float4 c = (tab - (QCPW_NINV_TAB_EXP_LO << 5))[b >> 18];
+    const float j = (float)(b & 0x3FFFFu);
+    const float p = fmaf(fmaf(fmaf(c.x, j, c.y), j, c.z), j, c.w);
+    // -scale when y >= 2^31 (p <= 0 there and the result must be positive)
+    const float k = __uint_as_float((__float_as_uint(scale) & 0x7FFFFFFFu) | (y & 0x80000000u));
+    return p * k;
 }
 
 // Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library), evaluated on the
@@ -190,6 +209,18 @@ template <>
 struct Real<true> { using T = float; };
 template <>
 struct Real<false> { using T = double; };
+
+// Sobol + shift + inverse normal for one coordinate, result in Y units;
+// FP32 from the LDS cubic table.
+template <bool F32>
+__device__ inline typename Real<F32>::T coord_tab(uint32_t y, const OptDev &op, const float4 *tab)
+{
+    if constexpr (F32) {
+        return ninv_table_f32(y, op.zs_t, tab);
+    } else {
+        return ninv_f64(y) * op.zscale;
+    }
+}
 
 // Sobol + shift + inverse normal for one coordinate, result in Y units.
 template <bool F32>

@@ -2,10 +2,10 @@
 // per-replication finalize kernel, and their launch planning.
 //
 // One persistent launch covers every option of a call.  Work units are
-// (option, replication l, chunk of QCPW_CHUNK consecutive Sobol points);
-// workgroups pull units from a device counter.  Inside a unit each wave owns
-// a contiguous range of points and each lane one point per iteration, so for
-// point k = base + lane (base a multiple of 64):
+// (option, replication l, range of unit_pts consecutive Sobol points, a
+// function of the option's point count alone); each wave pulls units from a
+// device counter and gives each lane one point per iteration, so for point
+// k = base + lane (base a multiple of 64):
 //
 //   Sobol integer of dimension j (Sec. 2.2.2, XOR form of
 //   eqn:GeneratorMatrixExpression, Gray-code order):
@@ -24,13 +24,14 @@
 //
 //   Per path, in FP64: breakpoint psi of the conditioned normal x_1
 //   (Sec. 3.4.2), Phi tails, and price/delta/vega/gamma (Sec. 4.5), added
-//   into compensated per-lane sums; wave shuffles, then LDS, reduce them to
+//   into compensated per-lane sums; a fixed wave butterfly reduces them to
 //   one partial per unit.  The finalize kernel adds a replication's partials
 //   in chunk order and forms mean and standard error over replications
 //   (Sec. 5).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -52,7 +53,7 @@ struct UnitCtx {
 
 template <bool F32, bool MAX>
 __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
-                                       typename Real<F32>::T *lds_stack, int tid, int lane,
+                                       const float4 *lds_tab, typename Real<F32>::T *lds_stack, int tid, int lane,
                                        const uint32_t (&U)[QCPW_UQ], PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
@@ -64,7 +65,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
     {   // terminal point
         const PlanStep st = plan[0];
         const uint32_t y = lds_lane[st.lds_off + lane] ^ rdlane(U[0], 0);
-        const R z = coord<F32>(y, op);
+        const R z = coord_tab<F32>(y, op, lds_tab);
         const R sd = F32 ? (R)st.sd : (R)plan64[0].sd;
         const R drift = F32 ? (R)op.ydrift_n_f : (R)op.ydrift_n;
         Rr = fma(sd, z, drift);
@@ -84,7 +85,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
                 Rr = lds_stack[sp * bd + tid];
             }
             const uint32_t y = lds_lane[st.lds_off + lane] ^ rdlane(U[q], s - 64 * q);
-            const R z = coord<F32>(y, op);
+            const R z = coord_tab<F32>(y, op, lds_tab);
             R Ym;
             R mf;
             if constexpr (F32) {
@@ -105,7 +106,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
 }
 
 template <bool F32, bool MAX>
-__device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, int lane,
+__device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, const float4 *lds_tab, int lane,
                                          const uint32_t (&U)[QCPW_UQ], PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
@@ -117,7 +118,7 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
         const int s_hi = min(64 * (q + 1), n);
         for (int s = 64 * q; s < s_hi; ++s) {
             const uint32_t y = lds_lane[s * 64 + lane] ^ rdlane(U[q], s - 64 * q);
-            const R z = coord<F32>(y, op);
+            const R z = coord_tab<F32>(y, op, lds_tab);
             Y = Y + (drift + z);
             consume<R, MAX>(ps, Y, (R)(s + 1));
         }
@@ -170,6 +171,11 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
     }
 }
 
+// Every wave pulls its own work units (option, replication, range of
+// unit_pts consecutive points): no workgroup barrier after start-up, and the
+// order of every sum depends on the unit alone.  The workgroup only shares
+// the LDS tables (inverse-normal cells, lane rows of all dimensions the
+// launch needs), loaded once.
 template <bool F32, int PATHK>
 __global__ __launch_bounds__(1024) void paths_kernel(const OptDev *__restrict__ opts,
                                                      const int64_t *__restrict__ unit_prefix,
@@ -177,6 +183,7 @@ __global__ __launch_bounds__(1024) void paths_kernel(const OptDev *__restrict__ 
                                                      const PlanStep64 *__restrict__ plan64_all,
                                                      const uint32_t *__restrict__ dir,
                                                      const uint32_t *__restrict__ lane_tab,
+                                                     const float4 *__restrict__ ninv_tab,
                                                      double *__restrict__ partials,
                                                      unsigned long long *__restrict__ counter,
                                                      int n_opts, int max_n, int stack_depth,
@@ -196,37 +203,34 @@ __global__ __launch_bounds__(1024) void paths_kernel(const OptDev *__restrict__ 
     ld.counter = counter;
     using R = typename Real<F32>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ long long s_unit;
     const int bd = blockDim.x;
-    const int nwaves = bd >> 6;
-    uint32_t *lds_lane = (uint32_t *)smem;                                    // [max_n][64]
-    const size_t lane_bytes = (size_t)ld.max_n * 64 * 4;
-    R *lds_stack = (R *)(smem + lane_bytes);                                  // [stack][bd]
-    const size_t stack_bytes = PATHK == QCPW_PATH_BB ? (size_t)stack_depth * bd * sizeof(R) : 0;
-    double *lds_red = (double *)(smem + lane_bytes + stack_bytes);            // [nwaves][8]
-
+    const size_t tab_bytes = F32 ? QCPW_NINV_TAB_CELLS * sizeof(float4) : 0;
+    float4 *lds_tab = (float4 *)smem;                                         // [1024] cubic cells
+    uint32_t *lds_lane = (uint32_t *)(smem + tab_bytes);                      // [max_n][64]
+    const size_t lane_bytes = (size_t)max_n * 64 * 4;
+    R *lds_stack = (R *)(smem + tab_bytes + lane_bytes);                      // [stack][bd]
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
-    int loaded_n = 0;
-    int o = 0;
+    if (F32)
+        for (int i = tid; i < QCPW_NINV_TAB_CELLS; i += bd) lds_tab[i] = ninv_tab[i];
+    for (int i = tid; i < max_n * 64; i += bd) lds_lane[i] = lane_tab[64 + i];
+    __syncthreads();
 
+    int o = 0;
     for (;;) {
-        if (tid == 0) s_unit = (long long)atomicAdd(ld.counter, 1ull);
-        __syncthreads();
-        const long long unit_v = s_unit;
-        const long long unit = ((long long)__builtin_amdgcn_readfirstlane((int)(unit_v >> 32)) << 32) |
-                               (unsigned)__builtin_amdgcn_readfirstlane((int)unit_v);
-        __syncthreads();
-        if (unit >= ld.total_units) break;
+        unsigned long long u = 0;
+        if (lane == 0) u = atomicAdd(counter, 1ull);
+        const long long unit = ((long long)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                               (unsigned)__builtin_amdgcn_readfirstlane((int)u);
+        if (unit >= total_units) break;
 
         // option of this unit (units are consumed in increasing order, so the
         // previous option is the usual answer)
-        if (!(ld.unit_prefix[o] <= unit && unit < ld.unit_prefix[o + 1])) {
-            int lo = 0, hi = ld.n_opts - 1;
+        if (!(unit_prefix[o] <= unit && unit < unit_prefix[o + 1])) {
+            int lo = 0, hi = n_opts - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (ld.unit_prefix[mid] <= unit) lo = mid; else hi = mid - 1;
+                if (unit_prefix[mid] <= unit) lo = mid; else hi = mid - 1;
             }
             o = lo;
         }
@@ -235,65 +239,41 @@ __global__ __launch_bounds__(1024) void paths_kernel(const OptDev *__restrict__ 
         const int shift = (int)(rem / op.chunks);
         const int64_t chunk = rem - (int64_t)shift * op.chunks;
 
-        if (op.n > loaded_n) {
-            for (int i = loaded_n * 64 + tid; i < op.n * 64; i += bd) lds_lane[i] = ld.lane[64 + i];
-            loaded_n = op.n;
-            __syncthreads();
-        }
-
         double s[4] = {0.0, 0.0, 0.0, 0.0};
         double c[4] = {0.0, 0.0, 0.0, 0.0};
-        const int64_t per_wave = QCPW_CHUNK / nwaves;
         const int64_t k_end = op.k_begin + op.n_points;
-        const int64_t start = op.k_begin + chunk * QCPW_CHUNK + (int64_t)wave * per_wave;
-        const int64_t end = min(start + per_wave, k_end);
-        if (start < k_end) {
-            uint32_t U[QCPW_UQ];
-            init_uniform_part<PATHK>(ld, op, shift, lane, (uint64_t)start, U);
-            for (int64_t base = start; base < end; base += 64) {
-                const bool valid = base + lane < k_end;
-                double F[4] = {0.0, 0.0, 0.0, 0.0};
-                PathSums<R> ps;
-                init_sums(ps);
-                const bool is_max = op.type == QCPW_LOOKBACK_FIXED_CALL;
-                if (op.n > 0) {
-                    if (PATHK == QCPW_PATH_BB) {
-                        if (is_max) run_bridge_wave<F32, true>(ld, op, lds_lane, lds_stack, tid, lane, U, ps);
-                        else run_bridge_wave<F32, false>(ld, op, lds_lane, lds_stack, tid, lane, U, ps);
-                    } else {
-                        if (is_max) run_standard_wave<F32, true>(op, lds_lane, lane, U, ps);
-                        else run_standard_wave<F32, false>(op, lds_lane, lane, U, ps);
-                    }
+        const int64_t start = op.k_begin + chunk * op.unit_pts;
+        const int64_t end = min(start + (int64_t)op.unit_pts, k_end);
+        const bool is_max = op.type == QCPW_LOOKBACK_FIXED_CALL;
+        uint32_t U[QCPW_UQ];
+        init_uniform_part<PATHK>(ld, op, shift, lane, (uint64_t)start, U);
+        for (int64_t base = start; base < end; base += 64) {
+            const bool valid = base + lane < k_end;
+            double F[4] = {0.0, 0.0, 0.0, 0.0};
+            PathSums<R> ps;
+            init_sums(ps);
+            if (op.n > 0) {
+                if (PATHK == QCPW_PATH_BB) {
+                    if (is_max) run_bridge_wave<F32, true>(ld, op, lds_lane, lds_tab, lds_stack, tid, lane, U, ps);
+                    else run_bridge_wave<F32, false>(ld, op, lds_lane, lds_tab, lds_stack, tid, lane, U, ps);
+                } else {
+                    if (is_max) run_standard_wave<F32, true>(op, lds_lane, lds_tab, lane, U, ps);
+                    else run_standard_wave<F32, false>(op, lds_lane, lds_tab, lane, U, ps);
                 }
-                if (valid) path_tail<R>(op, ps, is_max, F);
-                if (valid) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) acc_add(s[i], c[i], F[i]);
-                }
-                if (base + 64 < end) step_uniform_part<PATHK>(ld, op, lane, (uint64_t)base, U);
             }
-        }
-        // unit reduction: wave butterflies, then wave 0 over the waves
+            if (valid) {
+                path_tail<R>(op, ps, is_max, F);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) wave_reduce(s[i], c[i]);
-        if (lane == 0) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                lds_red[wave * 8 + i] = s[i];
-                lds_red[wave * 8 + 4 + i] = c[i];
+                for (int i = 0; i < 4; ++i) acc_add(s[i], c[i], F[i]);
             }
+            if (base + 64 < end) step_uniform_part<PATHK>(ld, op, lane, (uint64_t)base, U);
         }
-        __syncthreads();
-        if (wave == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                double ss = lane < nwaves ? lds_red[lane * 8 + i] : 0.0;
-                double cc = lane < nwaves ? lds_red[lane * 8 + 4 + i] : 0.0;
-                wave_reduce(ss, cc);
-                if (lane == 0) {
-                    ld.partials[unit * 8 + i] = ss;
-                    ld.partials[unit * 8 + 4 + i] = cc;
-                }
+        for (int i = 0; i < 4; ++i) {
+            wave_reduce(s[i], c[i]);
+            if (lane == 0) {
+                partials[unit * 8 + i] = s[i];
+                partials[unit * 8 + 4 + i] = c[i];
             }
         }
     }
@@ -402,6 +382,7 @@ __global__ __launch_bounds__(64) void sobol_points_kernel(const uint32_t *dir, c
 // launch planning (host)
 // ------------------------------------------------------------------------
 static inline bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+static size_t paths_lds_bytes(const LaunchPlan &lp, int bd);
 
 qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t d, int64_t n_points,
                           int32_t n_shifts, int32_t path, int32_t precision, int32_t pca_gemm,
@@ -474,7 +455,8 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.seed = sp.seed;
         op.n_shifts = n_shifts;
         op.out_index = i;
-        op.chunks = (int32_t)((Ni + QCPW_CHUNK - 1) / QCPW_CHUNK);
+        op.unit_pts = (int32_t)(path == QCPW_PATH_PCA ? QCPW_CHUNK : qcpw_unit_points(Ni));
+        op.chunks = (int32_t)((Ni + op.unit_pts - 1) / op.unit_pts);
         op.plan_off = (path == QCPW_PATH_BB && op.n >= 1) ? ctx->tab.plan_off[op.n] : 0;
         const double LOG2E = 1.4426950408889634074;
         const double dt = sp.T / di, t1 = dt;
@@ -501,6 +483,7 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.zscale_f = (float)(op.zscale * M_SQRT2);
         op.zs_a = (float)(op.zscale * M_SQRT2 * 0x1p-31);
         op.zs_b = (float)(op.zscale * M_SQRT2 * 0x1p-32);
+        op.zs_t = (float)op.zscale;
         op.ydrift_n_f = (float)op.ydrift_n;
         op.ydrift_1_f = (float)op.ydrift_1;
         op.kappa_f = (float)op.kappa;
@@ -563,10 +546,11 @@ size_t launch_workspace_bytes(const LaunchPlan &lp) { return ws_layout(lp).total
 
 static size_t paths_lds_bytes(const LaunchPlan &lp, int bd)
 {
-    const size_t lane_bytes = (size_t)lp.max_n * 64 * 4;
+    const size_t tab_bytes = lp.precision == QCPW_FP32_MIXED ? QCPW_NINV_TAB_CELLS * 16 : 0;
+    const size_t lane_bytes = tab_bytes + (size_t)lp.max_n * 64 * 4;
     const size_t elem = lp.precision == QCPW_FP32_MIXED ? 4 : 8;
     const size_t stack = lp.path == QCPW_PATH_BB ? (size_t)lp.stack_depth * bd * elem : 0;
-    return lane_bytes + stack + (size_t)(bd / 64) * 8 * sizeof(double);
+    return lane_bytes + stack;
 }
 
 template <bool F32, int PATHK>
@@ -582,24 +566,81 @@ static const void *select_paths_kernel(const LaunchPlan &lp)
     return f32 ? paths_fn<true, QCPW_PATH_BB>() : paths_fn<false, QCPW_PATH_BB>();
 }
 
-// Workgroup size: large lane tables want one big workgroup per CU sharing
-// them; small ones leave room for several workgroups of 512.  The choice is
-// capped by what fits in LDS.
+// Workgroup size of the fused kernel, chosen by measurement.  For each
+// (construction, precision, lane-table size bucket) the first launch times a
+// probe -- one arithmetic Asian option with the launch's largest d, 2^16
+// points x 64 replications (512 work units) -- at every workgroup size that
+// fits in LDS, and keeps the fastest.  QCPW_BLOCK_THREADS in the environment
+// overrides the choice.  Only the order of floating-point sums depends on it.
 int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
 {
-    (void)ctx;
     if (lp.path == QCPW_PATH_PCA) return 256;
-    int bd = lp.max_n > 160 ? 1024 : 512;
-    while (bd > 256 && paths_lds_bytes(lp, bd) > 160 * 1024) bd /= 2;
-    return bd;
+    if (const char *env = getenv("QCPW_BLOCK_THREADS")) {
+        const int v = atoi(env);
+        if ((v == 256 || v == 512 || v == 1024) && paths_lds_bytes(lp, v) <= 160 * 1024) return v;
+    }
+    const int key = (lp.path * 2 + lp.precision) * 64 + (lp.max_n + 31) / 32;
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second;
+    int best = 256;
+    float best_ms = 1e30f;
+    qcpw_option_spec probe;
+    memset(&probe, 0, sizeof probe);
+    probe.type = QCPW_ARITH_ASIAN_CALL;
+    probe.d = std::max(lp.max_n, 1) + 1;
+    probe.S0 = 100.0; probe.K = 100.0; probe.r = 0.05; probe.sigma = 0.2; probe.T = 1.0;
+    probe.seed = 0x51ab;
+    probe.n_points = int64_t(1) << 16;
+    void *ws = nullptr;
+    double *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+              hipMalloc(&out, 2 * 4 * sizeof(double) + 64 * 4 * sizeof(double)) == hipSuccess;
+    for (int bd : {256, 512, 1024}) {
+        if (!ok) break;
+        LaunchPlan p;
+        if (plan_launch(ctx, &probe, 1, 0, 0, 64, lp.path, lp.precision, lp.pca_gemm, bd, p) != QCPW_OK) continue;
+        p.max_n = std::max(p.max_n, lp.max_n);
+        p.stack_depth = std::max(p.stack_depth, lp.stack_depth);
+        if (paths_lds_bytes(p, bd) > 160 * 1024) continue;
+        const size_t need = launch_workspace_bytes(p);
+        if (ws) (void)hipFree(ws);
+        ws = nullptr;
+        if (hipMalloc(&ws, need) != hipSuccess) { ok = false; break; }
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(e0, ctx->own_stream);
+            if (enqueue_launch(ctx, p, ctx->own_stream, out, out + 4, out + 8, ws, need) != QCPW_OK) { ms = 1e30f; break; }
+            (void)hipEventRecord(e1, ctx->own_stream);
+            (void)hipEventSynchronize(e1);
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (rep > 0) ms = std::min(ms, t);   // first repetition warms up
+        }
+        if (ms < best_ms) { best_ms = ms; best = bd; }
+    }
+    if (ws) (void)hipFree(ws);
+    if (out) (void)hipFree(out);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipGetLastError();
+    if (best_ms >= 1e29f) {   // nothing could be timed: the static rule
+        best = lp.max_n > 160 ? 1024 : 512;
+        while (best > 256 && paths_lds_bytes(lp, best) > 160 * 1024) best /= 2;
+    }
+    ctx->tuned[key] = best;
+    return best;
 }
 
 qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, const LaunchDesc &ld,
                         const OptDev *d_opts);
 
 qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream, double *dev_out_greeks,
-                           double *dev_out_stderr, double *dev_out_per_shift, void *ws, size_t ws_bytes)
+                           double *dev_out_stderr, double *dev_out_per_shift, void *ws, size_t ws_bytes,
+                           const OptDev *h_opts, const int64_t *h_prefix)
 {
+    if (!h_opts) h_opts = lp.opts.data();
+    if (!h_prefix) h_prefix = lp.unit_prefix.data();
     const WsLayout w = ws_layout(lp);
     if (ws_bytes < w.total) return fail(QCPW_ENOMEM, "workspace too small");
     char *base = (char *)ws;
@@ -609,8 +650,8 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
     double *d_per_shift = dev_out_per_shift ? dev_out_per_shift : (double *)(base + w.per_shift);
     unsigned long long *d_counter = (unsigned long long *)(base + w.counter);
     const size_t n = lp.opts.size();
-    QCPW_HIP(hipMemcpyAsync(d_opts, lp.opts.data(), n * sizeof(OptDev), hipMemcpyHostToDevice, stream));
-    QCPW_HIP(hipMemcpyAsync(d_prefix, lp.unit_prefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    QCPW_HIP(hipMemcpyAsync(d_opts, h_opts, n * sizeof(OptDev), hipMemcpyHostToDevice, stream));
+    QCPW_HIP(hipMemcpyAsync(d_prefix, h_prefix, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
     reset_counter_kernel<<<1, 1, 0, stream>>>(d_counter);
     QCPW_HIP(hipGetLastError());
 
@@ -646,11 +687,12 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         const PlanStep *a_plan = ld.plan;
         const PlanStep64 *a_plan64 = ld.plan64;
         const uint32_t *a_dir = ld.dir, *a_lane = ld.lane;
+        const float4 *a_tab = ctx->tab.ninv_tab;
         double *a_part = ld.partials;
         unsigned long long *a_ctr = ld.counter;
         int a_nopts = ld.n_opts, a_maxn = ld.max_n, a_depth = lp.stack_depth;
         long long a_total = ld.total_units;
-        void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_dir, &a_lane, &a_part, &a_ctr,
+        void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_dir, &a_lane, &a_tab, &a_part, &a_ctr,
                         &a_nopts, &a_maxn, &a_depth, &a_total};
         QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
     }

@@ -178,8 +178,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const int shift = (int)(rem / op.chunks);
         const int64_t chunk = rem - (int64_t)shift * op.chunks;
         const int64_t k_end = op.k_begin + op.n_points;
-        const int64_t t0 = op.k_begin + chunk * QCPW_CHUNK;
-        const int64_t t1 = min(t0 + (int64_t)QCPW_CHUNK, k_end);
+        const int64_t t0 = op.k_begin + chunk * op.unit_pts;
+        const int64_t t1 = min(t0 + (int64_t)op.unit_pts, k_end);
 
         // padding columns of Z (k = n .. NP-1) must hold zeros
         for (int i = tid; i < TP * (NP - n); i += blockDim.x) {
@@ -336,8 +336,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const int shift = (int)(rem / op.chunks);
         const int64_t chunk = rem - (int64_t)shift * op.chunks;
         const int64_t k_end = op.k_begin + op.n_points;
-        const int64_t t0 = op.k_begin + chunk * QCPW_CHUNK;
-        const int64_t t1 = min(t0 + (int64_t)QCPW_CHUNK, k_end);
+        const int64_t t0 = op.k_begin + chunk * op.unit_pts;
+        const int64_t t1 = min(t0 + (int64_t)op.unit_pts, k_end);
         const int myj = 1 + 64 * wave + lane;
         uint32_t U = 0;
         if (myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -38,6 +39,7 @@ struct DeviceTables {
     uint32_t *lane = nullptr;    // [QCPW_TAB_DIMS][64]
     PlanStep *plan = nullptr;    // all bridge plans, n = 1..QCPW_MAX_N
     PlanStep64 *plan64 = nullptr;
+    float4 *ninv_tab = nullptr;  // FP32 inverse-normal cubic table (1024 cells)
     std::vector<int32_t> plan_off;   // [QCPW_MAX_N + 1]
     std::vector<int32_t> depth;      // [QCPW_MAX_N + 1] bridge stack depth per n
     int max_stack = 0;
@@ -61,6 +63,18 @@ struct Context {
     struct Pca { int n; double dt; int np; float *At = nullptr; double *A64 = nullptr;
                  uint16_t *Ahi = nullptr, *Alo = nullptr; };
     std::deque<Pca> pca;     // deque: pointers stay valid as factors are added
+    std::map<int, int> tuned;   // autotuned workgroup size per (path, precision, n bucket)
+    // captured launch graphs (QCPW_FLAG_GRAPH), keyed by the call's argument bytes
+    struct Graph {
+        std::vector<unsigned char> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        void *ws = nullptr;
+        void *host = nullptr;    // pinned copies of the uploaded OptDev[] and unit prefix
+        uint64_t last_use = 0;
+    };
+    std::vector<Graph> graphs;
+    uint64_t graph_clock = 0;
 };
 
 qcpw_status get_context(int device, Context **out);
@@ -102,9 +116,12 @@ size_t launch_workspace_bytes(const LaunchPlan &lp);
 // Enqueues the whole hot path on `stream`: uploads, the per-path kernel, the
 // finalize kernel; results go to dev_out_greeks / dev_out_stderr ([n][4],
 // caller order) and optionally dev_out_per_shift ([n][L][4]).
+// h_opts / h_prefix: host copies to upload from (default: lp's own vectors;
+// graph capture passes pinned copies that outlive the call).
 qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream,
                            double *dev_out_greeks, double *dev_out_stderr,
-                           double *dev_out_per_shift, void *ws, size_t ws_bytes);
+                           double *dev_out_per_shift, void *ws, size_t ws_bytes,
+                           const OptDev *h_opts = nullptr, const int64_t *h_prefix = nullptr);
 
 qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index, int32_t n_dims,
                                 int64_t k0, int64_t count, uint32_t *dev_out, hipStream_t stream);

@@ -23,7 +23,18 @@
 #define QCPW_TAB_DIMS 1024       // Sobol dimensions held on the device
 #define QCPW_MAX_N 384           // conditioned coordinates in the fused kernel
 #define QCPW_UQ 6                // QCPW_MAX_N / 64 registers of wave-uniform state
-#define QCPW_CHUNK 8192          // points per work unit (canonical; not tuned)
+#define QCPW_CHUNK 8192          // alignment of point ranges; points per PCA work unit
+
+// Points per work unit of the fused kernel (one wave per unit): a function of
+// the option's point count only, so an option's result does not depend on
+// what else shares the launch or on the workgroup size.  256..4096 points,
+// about N/256, a power of two (so it divides QCPW_CHUNK).
+static inline int64_t qcpw_unit_points(int64_t n_points)
+{
+    int64_t c = 256;
+    while (c < 4096 && c * 256 < n_points) c *= 2;
+    return c;
+}
 #define QCPW_STACK_MAX 12        // bridge stack depth bound (ceil log2 QCPW_MAX_N + 2)
 #define QCPW_PCA_NPAD 256        // padded factor size of the matrix-core PCA kernel
 
@@ -50,6 +61,7 @@ struct OptDev {
     int32_t type, d, n, path;     // n = d - 1
     int32_t plan_off;             // first PlanStep of this option's bridge plan
     int32_t chunks;               // work units per replication
+    int32_t unit_pts;             // points per work unit
     int64_t n_points;             // points in this launch: k_begin .. k_begin + n_points - 1
     int64_t k_begin;              // first Sobol point (a multiple of QCPW_CHUNK)
     uint64_t seed;
@@ -66,7 +78,8 @@ struct OptDev {
     double inv_s1, s1, sqrt_t1, inv_sigma;
     double S0, K, D, D1, invd, inv_S0, inv_S0sq;
     float zscale_f, ydrift_n_f, ydrift_1_f, kappa_f;
-    float zs_a, zs_b;             // sqrt(2) zscale 2^-31 and 2^-32 (FP32 inverse normal)
+    float zs_a, zs_b;             // sqrt(2) zscale 2^-31 and 2^-32 (FP32 polynomial inverse normal)
+    float zs_t;                   // zscale (FP32 table inverse normal)
     // principal-component factor of this option's n (unit dt), device layouts:
     const float *pca_At;          // [NP][NP] FP32, k-major: At[k][row]
     const uint16_t *pca_hi;       // [NP/16][NP][16] BF16 hi part, 16-wide k slabs

@@ -65,7 +65,7 @@ struct Request {
 // covers 2^21 new points).
 static int64_t option_footprint(int n_shifts)
 {
-    const int64_t chunks = (kMaxPoints / 2) / QCPW_CHUNK;
+    const int64_t chunks = (kMaxPoints / 2) / qcpw_unit_points(kMaxPoints / 2);
     return chunks * n_shifts * 8 * (int64_t)sizeof(double) + (int64_t)n_shifts * 4 * sizeof(double) +
            (int64_t)sizeof(OptDev) + 16 * (int64_t)sizeof(double) + 64;
 }
