@@ -11,6 +11,7 @@ namespace qcpw {
 
 #include "ninv_f32_coeffs.inc"
 #include "ninv_table.inc"
+#include "phi_f64_coeffs.inc"
 
 // ------------------------------------------------------------------------
 // device helpers
@@ -152,21 +153,111 @@ __device__ inline void consume(PathSums<R> &ps, R Y, R mf)
     }
 }
 
-// price, delta, vega, gamma of the smoothed payoff for one path (Sec. 4.5),
-// from the path statistic X = S0 * a (a = A1/d or max E) and its sigma
-// derivative.  All FP64.
-__device__ inline void path_greeks(const OptDev &op, double lnA, double Xs, double VXs, double F[4])
+// ---- compact FP64 elementary functions for the per-path tail -------------
+// (few live registers, no special-case branches beyond what the path's
+// values can reach: finite positive arguments for ln, non-positive for exp).
+// Polynomial coefficients go through coef_after(): an empty asm that ties
+// each coefficient to the previous Horner value, so the compiler materialises
+// it (two scalar moves) just before its use instead of hoisting all of them
+// into ~80 registers held across the point loop, which would halve the
+// kernel's occupancy.
+__device__ inline double coef_after(double c, double dep)
 {
-    // X = S0 * Xs, V_X = S0 * VXs
-    const double psi = (op.c0 - lnA) * op.inv_s1;
-    const double Q0 = 0.5 * erfc(psi * M_SQRT1_2);
-    const double Q1 = 0.5 * erfc((psi - op.s1) * M_SQRT1_2);
-    const double phi0 = exp(-0.5 * psi * psi) * 0.398942280401432677939946;
+    uint64_t b = __builtin_bit_cast(uint64_t, c);
+    asm volatile("" : "+s"(b) : "v"(dep));
+    return __builtin_bit_cast(double, b);
+}
+
+// A pointer passed through an empty asm: loads through it cannot be hoisted
+// out of the loop that calls the tail, so per-option fields are re-read
+// (scalar loads, cache hits) instead of held in registers across the loop.
+template <typename T>
+__device__ inline const T *reread(const T *p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// 1/d to ~1 ulp: hardware reciprocal refined by two Newton steps.
+__device__ inline double recip_f64(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+// ln x for finite x > 0: x = 2^e m, m in [sqrt(1/2), sqrt(2)),
+// ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^23/23), s = (m - 1)/(m + 1),
+// |s| <= 0.1716; ln 2 split so that e ln2_hi is exact.
+__device__ inline double ln_f64(double x)
+{
+    int e;
+    double m = frexp(x, &e);   // m in [1/2, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) * recip_f64(m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+#pragma unroll
+    for (int k = 21; k >= 1; k -= 2) p = fma(p, z, coef_after(1.0 / k, p));
+    const double de = (double)e;
+    return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * p));
+}
+
+// exp x for x <= 0 (underflows to 0 below about -745): x = k ln 2 + r,
+// |r| <= ln2/2, e^r by its Taylor series to r^13, scaled by 2^k.
+__device__ inline double exp_neg_f64(double x)
+{
+    const double k = rint(x * 1.44269504088896340736);
+    double r = fma(-k, 6.93147180369123816490e-01, x);
+    r = fma(-k, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 6227020800.0;   // 1/13!
+    double f = 6227020800.0;
+#pragma unroll
+    for (int j = 12; j >= 0; --j) {
+        f /= (j + 1);                 // j! (compile-time constant after unrolling)
+        p = fma(p, r, coef_after(1.0 / f, p));
+    }
+    return ldexp(p, (int)k);
+}
+
+// erfc(a) from ea2 = exp(-a^2): erfcx(|a|) = t P(t), t = 3/(3 + |a|)
+// (phi_f64_coeffs.inc); erfc(a) = 2 - erfc(-a) for a < 0.
+__device__ inline double erfc_scaled(double a, double ea2)
+{
+    const double x = fabs(a);
+    const double t = QCPW_ERFCX_C * recip_f64(QCPW_ERFCX_C + x);
+    double p = coef_after(QCPW_ERFCX_P[0], t);
+#pragma unroll
+    for (int i = 1; i < (int)(sizeof(QCPW_ERFCX_P) / sizeof(double)); ++i)
+        p = fma(p, t, coef_after(QCPW_ERFCX_P[i], p));
+    const double v = ea2 * (t * p);
+    return a >= 0.0 ? v : 2.0 - v;
+}
+
+// price, delta, vega, gamma of the smoothed payoff for one path (Sec. 4.5),
+// from the path statistic X = S0 * Xs (Xs = A/d or max E, with A the sum or
+// maximum of E = S~/S0) and its sigma derivative V_X = S0 * VXs.  All FP64.
+// The three Gaussian factors come from one exponential: with
+// psi = (c0 - ln A)/s1 (Sec. 3.4.2), exp(-(psi - s1)^2/2) =
+// exp(-psi^2/2) exp(c0 - s1^2/2) / A.
+__device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, double VXs, double F[4])
+{
+    const OptDev &op = *reread(&op_in);
+    const double psi = (op.c0 - ln_f64(A)) * op.inv_s1;
+    const double g0 = exp_neg_f64(-0.5 * psi * psi);
+    const double invA = recip_f64(A);
+    const double Q0 = 0.5 * erfc_scaled(psi * M_SQRT1_2, g0);                      // 1 - Phi(psi)
+    const double Q1 = 0.5 * erfc_scaled((psi - op.s1) * M_SQRT1_2, g0 * op.h * invA);   // 1 - Phi(psi - s1)
+    const double phi0 = g0 * 0.398942280401432677939946;
     if (op.type == QCPW_BINARY_ASIAN_CALL) {
         const double Dphi = op.D * phi0;
         F[0] = op.D * Q0;
         F[1] = Dphi * op.inv_s1 * op.inv_S0;
-        F[2] = Dphi * (VXs / Xs * op.inv_s1 + psi * op.inv_sigma - op.sqrt_t1);
+        F[2] = Dphi * (VXs * recip_f64(Xs) * op.inv_s1 + psi * op.inv_sigma - op.sqrt_t1);
         F[3] = Dphi * op.inv_s1 * op.inv_S0sq * (psi * op.inv_s1 - 1.0);
     } else {
         const double X = op.S0 * Xs;
@@ -179,21 +270,20 @@ __device__ inline void path_greeks(const OptDev &op, double lnA, double Xs, doub
 }
 
 template <typename R>
-__device__ inline void path_tail(const OptDev &op, const PathSums<R> &ps, bool is_max, double F[4])
+__device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, bool is_max, double F[4])
 {
-    double lnA, Xs, VXs;
+    const OptDev &op = *reread(&op_in);
+    double A, Xs, VXs;
     if (is_max) {
-        const double bE = (double)ps.bE;
-        lnA = log(bE);
-        Xs = bE;
-        VXs = bE * ((double)ps.bY - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
+        A = (double)ps.bE;
+        Xs = A;
+        VXs = A * ((double)ps.bY - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
     } else {
-        const double A1 = (double)ps.A1;
-        lnA = log(A1);                          // ln d is folded into c0
-        Xs = A1 * op.invd;
+        A = (double)ps.A1;                      // ln d is folded into c0
+        Xs = A * op.invd;
         VXs = ((double)ps.A2y - op.kappa * (double)ps.A2m) * op.invd * op.inv_sig_log2e;
     }
-    path_greeks(op, lnA, Xs, VXs, F);
+    path_greeks(op, A, Xs, VXs, F);
 }
 
 template <typename R>

@@ -472,6 +472,7 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.inv_sigma = 1.0 / sp.sigma;
         op.c0 = std::log(sp.K) - std::log(sp.S0) - omega * t1 +
                 (sp.type == QCPW_LOOKBACK_FIXED_CALL ? 0.0 : std::log((double)di));
+        op.h = std::exp(op.c0 - 0.5 * op.s1 * op.s1);
         op.S0 = sp.S0;
         op.K = sp.K;
         op.D = std::exp(-sp.r * sp.T);
