@@ -124,7 +124,9 @@ typedef struct {
                                    returns without waiting for them                */
     void *stream;               /* hipStream_t to run on (NULL = the default stream) */
     double *out_per_shift;      /* optional [n_opts][L][4] per-replication C_l       */
-    int32_t block_threads;      /* 0 = autotuned; else 256, 512 or 1024             */
+    int32_t block_threads;      /* 0 = autotuned; else a multiple of 64 in [64, 1024]
+                                   (workgroup size of the per-path kernel; the PCA
+                                   kernel always uses 256)                          */
     int32_t flags;              /* QCPW_FLAG_* bits                                  */
 } qcpw_run_config;
 

@@ -71,32 +71,39 @@ __device__ inline float ninv_scaled_f32(uint32_t y, float sa)
     return p * xs;
 }
 
-// Phi^{-1}((y + 1/2) 2^-32) * scale in FP32 from the cubic table of
-// ninv_table.inc held in LDS: q = (min(y, ~y) + 1/2) 2^-32 in FP32 (kept
-// below 1/2), its exponent and top 5 mantissa bits select the cell, its low
-// 18 mantissa bits are the cubic's variable; Phi^{-1}(q) <= 0, and the sign
-// of the result is + iff y >= 2^31.  scale > 0 (no sqrt(2) here).
-__device__ inline float ninv_table_f32(uint32_t y, float scale, const float4 *__restrict__ tab)
+// Sign folding of a 32-bit Sobol integer y: fold(y) keeps bit 31 and, when
+// it is set, complements bits 0..30, so the low 31 bits are min(y, ~y) and
+// bit 31 says whether u = (y + 1/2) 2^-32 lies above 1/2.  fold is linear
+// over XOR (fold(a ^ b) = fold(a) ^ fold(b)), so it is applied to the lane
+// table and to the wave-uniform part separately, and the kernels combine
+// the folded halves with one XOR per coordinate.
+__host__ __device__ inline uint32_t fold_sign(uint32_t y)
 {
-    const uint32_t m = y ^ (uint32_t)((int32_t)y >> 31);
-    const float q = fminf(fmaf((float)m, 0x1p-32f, 0x1p-33f), 0x1.fffffep-2f);
+    return y ^ ((uint32_t)((int32_t)y >> 31) >> 1);
+}
+
+// Phi^{-1}((y + 1/2) 2^-32) * scale in FP32 for folded x = fold(y), from the
+// cubic table of ninv_table.inc held in LDS at `tab`:
+// q = (m + 1/2) 2^-32 in FP32 with m the low 31 bits of x (so q <= 1/2),
+// bits 18..27 of q select the cell, the cubic is evaluated in q itself;
+// Phi^{-1}(q) <= 0, and the result has the sign of scale times + iff bit 31
+// of x is set.
+__device__ inline float ninv_table_f32(uint32_t x, float scale, const float4 *__restrict__ tab)
+{
+    const float q = fmaf((float)(x & 0x7FFFFFFFu), 0x1p-32f, 0x1p-33f);
     const uint32_t b = __float_as_uint(q);
-    const float4 c = (tab - (QCPW_NINV_TAB_EXP_LO << 5))[b >> 18];
-    const float j = (float)(b & 0x3FFFFu);
-    const float p = fmaf(fmaf(fmaf(c.x, j, c.y), j, c.z), j, c.w);
-    // -scale when y >= 2^31 (p <= 0 there and the result must be positive)
-    const float k = __uint_as_float((__float_as_uint(scale) & 0x7FFFFFFFu) | (y & 0x80000000u));
+    const float4 c = *(const float4 *)((const char *)tab + ((b >> 14) & 0x3FF0u));
+    const float p = fmaf(fmaf(fmaf(c.x, q, c.y), q, c.z), q, c.w);
+    const float k = __uint_as_float((x & 0x80000000u) ^ __float_as_uint(scale));
     return p * k;
 }
 
-// Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library), evaluated on the
-// lower half so that 1 - u never has to be formed.
-__device__ inline double ninv_f64(uint32_t y)
+// Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library) for folded x = fold(y),
+// evaluated on the lower half so that 1 - u never has to be formed.
+__device__ inline double ninv_f64(uint32_t x)
 {
-    const uint32_t neg = (uint32_t)((int32_t)y >> 31);
-    const uint32_t m = y ^ neg;
-    const double x = normcdfinv(((double)m + 0.5) * 0x1p-32);   // <= 0
-    return neg ? -x : x;
+    const double v = normcdfinv(((double)(x & 0x7FFFFFFFu) + 0.5) * 0x1p-32);   // <= 0
+    return (x >> 31) ? -v : v;
 }
 
 __device__ inline float exp2_r(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -134,19 +141,18 @@ __device__ inline uint32_t rdlane(uint32_t v, int l)
 template <typename R>
 struct PathSums {
     R A1, A2y, A2m;   // sum E_m, sum E_m Y_m, sum E_m m   (averages)
-    R bE, bY, bm;     // running max of E_m, its Y_m and m (lookback)
+    R bY, bm;         // running max of Y_m and its m (lookback; E = 2^Y once, at the end)
 };
 
 template <typename R, bool MAX>
 __device__ inline void consume(PathSums<R> &ps, R Y, R mf)
 {
-    const R E = exp2_r(Y);
     if (MAX) {
-        const bool take = (E > ps.bE) || (E == ps.bE && mf < ps.bm);   // lowest index wins ties
-        ps.bE = take ? E : ps.bE;
+        const bool take = (Y > ps.bY) || (Y == ps.bY && mf < ps.bm);   // lowest index wins ties
         ps.bY = take ? Y : ps.bY;
         ps.bm = take ? mf : ps.bm;
     } else {
+        const R E = exp2_r(Y);
         ps.A1 += E;
         ps.A2y = fma(E, Y, ps.A2y);
         ps.A2m = fma(E, mf, ps.A2m);
@@ -275,7 +281,7 @@ __device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, boo
     const OptDev &op = *reread(&op_in);
     double A, Xs, VXs;
     if (is_max) {
-        A = (double)ps.bE;
+        A = (double)exp2_r(ps.bY);
         Xs = A;
         VXs = A * ((double)ps.bY - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
     } else {
@@ -290,7 +296,7 @@ template <typename R>
 __device__ inline void init_sums(PathSums<R> &ps)
 {
     ps.A1 = R(1); ps.A2y = R(0); ps.A2m = R(0);   // date 1: S~ = S0, Y = 0
-    ps.bE = R(1); ps.bY = R(0); ps.bm = R(0);
+    ps.bY = R(0); ps.bm = R(0);
 }
 
 template <bool F32>
@@ -300,15 +306,15 @@ struct Real<true> { using T = float; };
 template <>
 struct Real<false> { using T = double; };
 
-// Sobol + shift + inverse normal for one coordinate, result in Y units;
+// Inverse normal of one folded coordinate x = fold(y), result in Y units;
 // FP32 from the LDS cubic table.
 template <bool F32>
-__device__ inline typename Real<F32>::T coord_tab(uint32_t y, const OptDev &op, const float4 *tab)
+__device__ inline typename Real<F32>::T coord_tab(uint32_t x, const OptDev &op, const float4 *tab)
 {
     if constexpr (F32) {
-        return ninv_table_f32(y, op.zs_t, tab);
+        return ninv_table_f32(x, op.zs_t, tab);
     } else {
-        return ninv_f64(y) * op.zscale;
+        return ninv_f64(x) * op.zscale;
     }
 }
 
@@ -319,7 +325,7 @@ __device__ inline typename Real<F32>::T coord(uint32_t y, const OptDev &op)
     if constexpr (F32) {
         return ninv_scaled_f32(y, op.zs_a);
     } else {
-        return ninv_f64(y) * op.zscale;
+        return ninv_f64(fold_sign(y)) * op.zscale;
     }
 }
 

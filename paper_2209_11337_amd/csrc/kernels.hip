@@ -53,25 +53,23 @@ struct UnitCtx {
 
 template <bool F32, bool MAX>
 __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
-                                       const float4 *lds_tab, typename Real<F32>::T *lds_stack, int tid, int lane,
+                                       const float4 *lds_tab, typename Real<F32>::T *stk, int lane,
                                        const uint32_t (&U)[QCPW_UQ], PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
     const int n = op.n;
-    const int bd = blockDim.x;
     const PlanStep *plan = ld.plan + op.plan_off;
     const PlanStep64 *plan64 = ld.plan64 + op.plan_off;
     R L = R(0), Rr;
     {   // terminal point
         const PlanStep st = plan[0];
-        const uint32_t y = lds_lane[st.lds_off + lane] ^ rdlane(U[0], 0);
-        const R z = coord_tab<F32>(y, op, lds_tab);
+        const uint32_t x = lds_lane[st.lds_off + lane] ^ rdlane(U[0], 0);
+        const R z = coord_tab<F32>(x, op, lds_tab);
         const R sd = F32 ? (R)st.sd : (R)plan64[0].sd;
         const R drift = F32 ? (R)op.ydrift_n_f : (R)op.ydrift_n;
         Rr = fma(sd, z, drift);
         consume<R, MAX>(ps, Rr, F32 ? (R)st.mf : (R)plan64[0].mf);
     }
-    int sp = 0;
 #pragma unroll
     for (int q = 0; q < QCPW_UQ; ++q) {
         const int s_lo = q == 0 ? 1 : 64 * q;
@@ -79,13 +77,17 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
 #pragma unroll 2
         for (int s = s_lo; s < s_hi; ++s) {
             const PlanStep st = plan[s];
-            for (int p = 0; p < st.pops; ++p) {
-                L = Rr;
-                --sp;
-                Rr = lds_stack[sp * bd + tid];
+            // stack: this lane's column, slot k at stk[64 k]
+            R *slot = stk + st.slot * 64;
+            if (st.pops == 0) {
+                *slot = Rr;
+            } else {
+                const R r = slot[0];
+                L = st.pops == 1 ? Rr : slot[64];
+                Rr = r;
             }
-            const uint32_t y = lds_lane[st.lds_off + lane] ^ rdlane(U[q], s - 64 * q);
-            const R z = coord_tab<F32>(y, op, lds_tab);
+            const uint32_t x = lds_lane[st.lds_off + lane] ^ rdlane(U[q], s - 64 * q);
+            const R z = coord_tab<F32>(x, op, lds_tab);
             R Ym;
             R mf;
             if constexpr (F32) {
@@ -96,8 +98,6 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
                 Ym = fma(s64.sd, z, fma(s64.wr, Rr, s64.wl * L));
                 mf = s64.mf;
             }
-            lds_stack[sp * bd + tid] = Rr;
-            ++sp;
             Rr = Ym;
             consume<R, MAX>(ps, Ym, mf);
         }
@@ -126,7 +126,7 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
     }
 }
 
-// U_j(base) for the dimensions this lane holds: steps s = lane + 64 q.
+// fold(U_j(base)) for the dimensions this lane holds: steps s = lane + 64 q.
 template <int PATHK>
 __device__ inline int step_dim(const LaunchDesc &ld, const OptDev &op, int s)
 {
@@ -151,7 +151,7 @@ __device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op,
             for (int b = 5; gg != 0; ++b, gg >>= 1)
                 if (gg & 1) u ^= v[b];
         }
-        U[q] = u;
+        U[q] = fold_sign(u);
     }
 }
 
@@ -166,7 +166,7 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
         const int s = lane + 64 * q;
         if (s < op.n) {
             const uint32_t *v = ld.dir + (size_t)step_dim<PATHK>(ld, op, s) * 32;
-            U[q] ^= v[5] ^ v[6 + c];
+            U[q] ^= fold_sign(v[5] ^ v[6 + c]);
         }
     }
 }
@@ -202,18 +202,20 @@ __global__ __launch_bounds__(1024) void paths_kernel(const OptDev *__restrict__ 
     ld.partials = partials;
     ld.counter = counter;
     using R = typename Real<F32>::T;
+    // static LDS first (so the cubic cells sit at a fixed address and a
+    // cell's address is just its byte offset), then the dynamic part
+    __shared__ float4 lds_tab[F32 ? QCPW_NINV_TAB_CELLS : 1];                  // cubic cells
     extern __shared__ __align__(16) unsigned char smem[];
     const int bd = blockDim.x;
-    const size_t tab_bytes = F32 ? QCPW_NINV_TAB_CELLS * sizeof(float4) : 0;
-    float4 *lds_tab = (float4 *)smem;                                         // [1024] cubic cells
-    uint32_t *lds_lane = (uint32_t *)(smem + tab_bytes);                      // [max_n][64]
+    uint32_t *lds_lane = (uint32_t *)smem;                                    // [max_n][64], folded
     const size_t lane_bytes = (size_t)max_n * 64 * 4;
-    R *lds_stack = (R *)(smem + tab_bytes + lane_bytes);                      // [stack][bd]
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    // bridge stack: [wave][stack_depth][64]; this lane's column
+    R *stk = (R *)(smem + lane_bytes) + (size_t)(tid >> 6) * stack_depth * 64 + lane;
     if (F32)
         for (int i = tid; i < QCPW_NINV_TAB_CELLS; i += bd) lds_tab[i] = ninv_tab[i];
-    for (int i = tid; i < max_n * 64; i += bd) lds_lane[i] = lane_tab[64 + i];
+    for (int i = tid; i < max_n * 64; i += bd) lds_lane[i] = fold_sign(lane_tab[64 + i]);
     __syncthreads();
 
     int o = 0;
@@ -254,8 +256,8 @@ __global__ __launch_bounds__(1024) void paths_kernel(const OptDev *__restrict__ 
             init_sums(ps);
             if (op.n > 0) {
                 if (PATHK == QCPW_PATH_BB) {
-                    if (is_max) run_bridge_wave<F32, true>(ld, op, lds_lane, lds_tab, lds_stack, tid, lane, U, ps);
-                    else run_bridge_wave<F32, false>(ld, op, lds_lane, lds_tab, lds_stack, tid, lane, U, ps);
+                    if (is_max) run_bridge_wave<F32, true>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
+                    else run_bridge_wave<F32, false>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
                 } else {
                     if (is_max) run_standard_wave<F32, true>(op, lds_lane, lds_tab, lane, U, ps);
                     else run_standard_wave<F32, false>(op, lds_lane, lds_tab, lane, U, ps);
@@ -395,8 +397,8 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
         return fail(QCPW_EINVAL, "unknown path_construction");
     if (precision != QCPW_FP64 && precision != QCPW_FP32_MIXED) return fail(QCPW_EINVAL, "unknown precision");
     if (pca_gemm != QCPW_GEMM_FP32 && pca_gemm != QCPW_GEMM_BF16X3) return fail(QCPW_EINVAL, "unknown pca_gemm");
-    if (block_threads != 0 && block_threads != 256 && block_threads != 512 && block_threads != 1024)
-        return fail(QCPW_EINVAL, "block_threads must be 0, 256, 512 or 1024");
+    if (!qcpw_block_threads_ok(block_threads))
+        return fail(QCPW_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
     if (d < 0 || n_points < 0) return fail(QCPW_EINVAL, "negative d or n_points");
     const int dmax = path == QCPW_PATH_PCA ? QCPW_MAX_D_PCA : QCPW_MAX_D;
     for (int i = 0; i < n_opts; ++i) {
@@ -545,13 +547,20 @@ static WsLayout ws_layout(const LaunchPlan &lp)
 
 size_t launch_workspace_bytes(const LaunchPlan &lp) { return ws_layout(lp).total; }
 
+// Dynamic LDS of the fused kernel (lane rows and bridge stacks) ...
 static size_t paths_lds_bytes(const LaunchPlan &lp, int bd)
 {
-    const size_t tab_bytes = lp.precision == QCPW_FP32_MIXED ? QCPW_NINV_TAB_CELLS * 16 : 0;
-    const size_t lane_bytes = tab_bytes + (size_t)lp.max_n * 64 * 4;
+    const size_t lane_bytes = (size_t)lp.max_n * 64 * 4;
     const size_t elem = lp.precision == QCPW_FP32_MIXED ? 4 : 8;
     const size_t stack = lp.path == QCPW_PATH_BB ? (size_t)lp.stack_depth * bd * elem : 0;
     return lane_bytes + stack;
+}
+
+// ... and its total with the static inverse-normal cells, against the CU's 160 KiB.
+static bool paths_lds_fits(const LaunchPlan &lp, int bd)
+{
+    const size_t tab = lp.precision == QCPW_FP32_MIXED ? QCPW_NINV_TAB_CELLS * 16 : 16;
+    return paths_lds_bytes(lp, bd) + tab <= 160 * 1024;
 }
 
 template <bool F32, int PATHK>
@@ -567,68 +576,101 @@ static const void *select_paths_kernel(const LaunchPlan &lp)
     return f32 ? paths_fn<true, QCPW_PATH_BB>() : paths_fn<false, QCPW_PATH_BB>();
 }
 
-// Workgroup size of the fused kernel, chosen by measurement.  For each
-// (construction, precision, lane-table size bucket) the first launch times a
-// probe -- one arithmetic Asian option with the launch's largest d, 2^16
-// points x 64 replications (512 work units) -- at every workgroup size that
-// fits in LDS, and keeps the fastest.  QCPW_BLOCK_THREADS in the environment
+// Resident waves per CU of the fused kernel at workgroup size bd (0 if it
+// cannot be resident): registers, LDS and the workgroup granularity decide.
+static int resident_waves(const LaunchPlan &lp, int bd)
+{
+    if (!paths_lds_fits(lp, bd)) return 0;
+    const size_t lds = paths_lds_bytes(lp, bd);
+    const void *fn = select_paths_kernel(lp);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds) != hipSuccess) return 0;
+    return per_cu * bd / 64;
+}
+
+// Workgroup size of the fused kernel, chosen by measurement among 256, 512
+// and 1024 threads (whole multiples of the CU's four SIMDs, so that every
+// SIMD holds the same number of waves; sizes in between measured slower).
+// The lane rows and inverse-normal cells are shared per workgroup and the
+// bridge stack is per thread, so the best size depends on d.  Each size that
+// can be resident is timed on a probe -- one arithmetic Asian option with the
+// launch's largest d, 2^18 points x 64 replications (16384 work units, a few
+// per resident wave) -- and the fastest is kept per (construction,
+// precision, lane-table size bucket).  QCPW_BLOCK_THREADS in the environment
 // overrides the choice.  Only the order of floating-point sums depends on it.
 int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
 {
     if (lp.path == QCPW_PATH_PCA) return 256;
     if (const char *env = getenv("QCPW_BLOCK_THREADS")) {
         const int v = atoi(env);
-        if ((v == 256 || v == 512 || v == 1024) && paths_lds_bytes(lp, v) <= 160 * 1024) return v;
+        if (v != 0 && qcpw_block_threads_ok(v) && resident_waves(lp, v) > 0) return v;
     }
     const int key = (lp.path * 2 + lp.precision) * 64 + (lp.max_n + 31) / 32;
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return it->second;
-    int best = 256;
-    float best_ms = 1e30f;
     qcpw_option_spec probe;
     memset(&probe, 0, sizeof probe);
     probe.type = QCPW_ARITH_ASIAN_CALL;
     probe.d = std::max(lp.max_n, 1) + 1;
     probe.S0 = 100.0; probe.K = 100.0; probe.r = 0.05; probe.sigma = 0.2; probe.T = 1.0;
     probe.seed = 0x51ab;
-    probe.n_points = int64_t(1) << 16;
+    probe.n_points = int64_t(1) << 18;
+    const int n_probe_shifts = 64;
+
+    std::vector<LaunchPlan> plans;
+    std::vector<int> cands;
+    for (int bd : {256, 512, 1024}) {
+        LaunchPlan p;
+        if (plan_launch(ctx, &probe, 1, 0, 0, n_probe_shifts, lp.path, lp.precision, lp.pca_gemm, bd, p) != QCPW_OK)
+            continue;
+        p.max_n = std::max(p.max_n, lp.max_n);
+        p.stack_depth = std::max(p.stack_depth, lp.stack_depth);
+        if (resident_waves(p, bd) == 0) continue;
+        cands.push_back(bd);
+        plans.push_back(std::move(p));
+    }
+    (void)hipGetLastError();
+    std::vector<size_t> pick;
+    for (size_t i = 0; i < cands.size(); ++i) pick.push_back(i);
+
+    int best = cands.empty() ? 256 : cands.back();
+    float best_ms = 1e30f;
     void *ws = nullptr;
     double *out = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
-              hipMalloc(&out, 2 * 4 * sizeof(double) + 64 * 4 * sizeof(double)) == hipSuccess;
-    for (int bd : {256, 512, 1024}) {
-        if (!ok) break;
-        LaunchPlan p;
-        if (plan_launch(ctx, &probe, 1, 0, 0, 64, lp.path, lp.precision, lp.pca_gemm, bd, p) != QCPW_OK) continue;
-        p.max_n = std::max(p.max_n, lp.max_n);
-        p.stack_depth = std::max(p.stack_depth, lp.stack_depth);
-        if (paths_lds_bytes(p, bd) > 160 * 1024) continue;
+    bool ok = !pick.empty() && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+              hipMalloc(&out, 2 * 4 * sizeof(double) + n_probe_shifts * 4 * sizeof(double)) == hipSuccess;
+    size_t ws_have = 0;
+    for (size_t j = 0; ok && j < pick.size(); ++j) {
+        const LaunchPlan &p = plans[pick[j]];
         const size_t need = launch_workspace_bytes(p);
-        if (ws) (void)hipFree(ws);
-        ws = nullptr;
-        if (hipMalloc(&ws, need) != hipSuccess) { ok = false; break; }
+        if (need > ws_have) {
+            if (ws) (void)hipFree(ws);
+            ws = nullptr;
+            if (hipMalloc(&ws, need) != hipSuccess) { ok = false; break; }
+            ws_have = need;
+        }
         float ms = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             (void)hipEventRecord(e0, ctx->own_stream);
-            if (enqueue_launch(ctx, p, ctx->own_stream, out, out + 4, out + 8, ws, need) != QCPW_OK) { ms = 1e30f; break; }
+            if (enqueue_launch(ctx, p, ctx->own_stream, out, out + 4, out + 8, ws, ws_have) != QCPW_OK) {
+                ms = 1e30f;
+                break;
+            }
             (void)hipEventRecord(e1, ctx->own_stream);
             (void)hipEventSynchronize(e1);
             float t = 0.0f;
             (void)hipEventElapsedTime(&t, e0, e1);
             if (rep > 0) ms = std::min(ms, t);   // first repetition warms up
         }
-        if (ms < best_ms) { best_ms = ms; best = bd; }
+        if (ms < best_ms) { best_ms = ms; best = cands[pick[j]]; }
     }
     if (ws) (void)hipFree(ws);
     if (out) (void)hipFree(out);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipGetLastError();
-    if (best_ms >= 1e29f) {   // nothing could be timed: the static rule
-        best = lp.max_n > 160 ? 1024 : 512;
-        while (best > 256 && paths_lds_bytes(lp, best) > 160 * 1024) best /= 2;
-    }
     ctx->tuned[key] = best;
     return best;
 }
@@ -674,8 +716,8 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         if (st != QCPW_OK) return st;
     } else {
         const int bd = lp.block_threads;
+        if (!paths_lds_fits(lp, bd)) return fail(QCPW_EDIMS, "LDS footprint exceeds 160 KiB");
         const size_t lds = paths_lds_bytes(lp, bd);
-        if (lds > 160 * 1024) return fail(QCPW_EDIMS, "LDS footprint exceeds 160 KiB");
         const void *fn = select_paths_kernel(lp);
         QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int per_cu = 0;

@@ -82,15 +82,23 @@ __device__ inline uint32_t uniform_part(const uint32_t *__restrict__ dir, uint64
     return u;
 }
 
+// Per-point sums of a path piece: the averages' sums and the running maximum
+// of E with its Y and m (compared on E, lowest m wins ties).
 template <typename R>
-__device__ inline void sums_neutral(PathSums<R> &ps)
+struct PcaSums {
+    R A1, A2y, A2m;
+    R bE, bY, bm;
+};
+
+template <typename R>
+__device__ inline void sums_neutral(PcaSums<R> &ps)
 {
     ps.A1 = R(0); ps.A2y = R(0); ps.A2m = R(0);
     ps.bE = R(0); ps.bY = R(0); ps.bm = R(1e30);
 }
 
 template <typename R>
-__device__ inline void sums_merge(PathSums<R> &a, const PathSums<R> &b)
+__device__ inline void sums_merge(PcaSums<R> &a, const PcaSums<R> &b)
 {
     a.A1 += b.A1;
     a.A2y += b.A2y;
@@ -102,7 +110,7 @@ __device__ inline void sums_merge(PathSums<R> &a, const PathSums<R> &b)
 }
 
 template <typename R>
-__device__ inline void sums_add_date(PathSums<R> &ps, R Y, R mf)
+__device__ inline void sums_add_date(PcaSums<R> &ps, R Y, R mf)
 {
     const R E = exp2_r(Y);
     ps.A1 += E;
@@ -115,9 +123,9 @@ __device__ inline void sums_add_date(PathSums<R> &ps, R Y, R mf)
 }
 
 template <typename R>
-__device__ inline PathSums<R> shfl_xor_sums(const PathSums<R> &p, int off)
+__device__ inline PcaSums<R> shfl_xor_sums(const PcaSums<R> &p, int off)
 {
-    PathSums<R> q;
+    PcaSums<R> q;
     q.A1 = __shfl_xor(p.A1, off, 64);
     q.A2y = __shfl_xor(p.A2y, off, 64);
     q.A2m = __shfl_xor(p.A2m, off, 64);
@@ -130,15 +138,19 @@ __device__ inline PathSums<R> shfl_xor_sums(const PathSums<R> &p, int off)
 // Per-point combination of the wave partials in LDS, the date at tau = 0
 // (E = 1, Y = 0) and the FP64 tail; wave 0, lane = point of the tile.
 template <typename R>
-__device__ inline void tile_tail(const OptDev &op, const PathSums<R> *red, int lane, bool valid, int nwaves_pt,
+__device__ inline void tile_tail(const OptDev &op, const PcaSums<R> *red, int lane, bool valid, int nwaves_pt,
                                  const int *waves_pt, double (&s)[4], double (&c)[4])
 {
-    PathSums<R> ps;
-    init_sums(ps);   // date 1: E = 1, Y = 0, m = 0
+    PcaSums<R> ps;
+    ps.A1 = R(1); ps.A2y = R(0); ps.A2m = R(0);   // date 1: E = 1, Y = 0, m = 0
+    ps.bE = R(1); ps.bY = R(0); ps.bm = R(0);
     for (int i = 0; i < nwaves_pt; ++i) sums_merge(ps, red[waves_pt[i] * TP + lane]);
     if (valid) {
+        PathSums<R> t;
+        t.A1 = ps.A1; t.A2y = ps.A2y; t.A2m = ps.A2m;
+        t.bY = ps.bY; t.bm = ps.bm;   // the tail forms E = 2^bY, the same value as bE
         double F[4];
-        path_tail<R>(op, ps, op.type == QCPW_LOOKBACK_FIXED_CALL, F);
+        path_tail<R>(op, t, op.type == QCPW_LOOKBACK_FIXED_CALL, F);
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc_add(s[k], c[k], F[k]);
     }
@@ -165,7 +177,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     float *Zf = (float *)smem;
     unsigned short *Zh = (unsigned short *)smem;
     unsigned short *Zl = Zh + (size_t)TP * zstride;
-    PathSums<float> *red = (PathSums<float> *)(smem + ((zbytes + 15) / 16) * 16);   // [4][TP]
+    PcaSums<float> *red = (PcaSums<float> *)(smem + ((zbytes + 15) / 16) * 16);   // [4][TP]
 
     int o = 0;
     for (;;) {
@@ -265,7 +277,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             }
 
             // ---- epilogue: exp2 and path sums over this lane's rows of its point
-            PathSums<float> ps;
+            PcaSums<float> ps;
             sums_neutral(ps);
             const float drift = op.ydrift_1_f;
 #pragma unroll
@@ -323,7 +335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int zstride = n_max + 1;
     double *Z = (double *)smem;                                              // [TP][n_max + 1]
-    PathSums<double> *red = (PathSums<double> *)(smem + (size_t)TP * zstride * 8);   // [4][TP]
+    PcaSums<double> *red = (PcaSums<double> *)(smem + (size_t)TP * zstride * 8);   // [4][TP]
 
     int o = 0;
     for (;;) {
@@ -348,7 +360,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             for (int jj = 0; jj < jcount; ++jj) {
                 const int j = 1 + 64 * wave + jj;
                 const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
-                Z[lane * zstride + (j - 1)] = ninv_f64(y) * op.zscale;
+                Z[lane * zstride + (j - 1)] = ninv_f64(fold_sign(y)) * op.zscale;
             }
             if (base + TP < t1 && myj <= n) {
                 const uint32_t *v = dir + (size_t)myj * 32;
@@ -356,7 +368,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             }
             __syncthreads();
             // rows m = wave, wave + 4, ...: W'_m = sum_i A[m][i] z'_i, four rows at a time
-            PathSums<double> ps;
+            PcaSums<double> ps;
             sums_neutral(ps);
             const double drift = op.ydrift_1;
             for (int m0 = wave; m0 < n; m0 += 16) {
@@ -415,14 +427,14 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
     int extra;
     if (lp.precision == QCPW_FP64) {
         fn = reinterpret_cast<const void *>(&pca_f64_kernel);
-        lds = (size_t)TP * (n_max + 1) * 8 + (size_t)PCA_WAVES * TP * sizeof(PathSums<double>);
+        lds = (size_t)TP * (n_max + 1) * 8 + (size_t)PCA_WAVES * TP * sizeof(PcaSums<double>);
         extra = n_max;
     } else {
         const bool bf = lp.pca_gemm == QCPW_GEMM_BF16X3;
         fn = bf ? reinterpret_cast<const void *>(&pca_f32_kernel<true>)
                 : reinterpret_cast<const void *>(&pca_f32_kernel<false>);
         const size_t z = bf ? (size_t)2 * TP * (np_max + 8) * 2 : (size_t)TP * (np_max + 1) * 4;
-        lds = (z + 15) / 16 * 16 + (size_t)PCA_WAVES * TP * sizeof(PathSums<float>);
+        lds = (z + 15) / 16 * 16 + (size_t)PCA_WAVES * TP * sizeof(PcaSums<float>);
         extra = np_max;
     }
     if (lds > 160 * 1024) return fail(QCPW_EDIMS, "PCA tile exceeds 160 KiB of LDS");

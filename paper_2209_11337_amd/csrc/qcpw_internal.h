@@ -35,6 +35,9 @@ static inline int64_t qcpw_unit_points(int64_t n_points)
     while (c < 4096 && c * 256 < n_points) c *= 2;
     return c;
 }
+// Workgroup sizes the fused kernel accepts: 0 (autotuned) or whole waves up
+// to the kernel's launch bound.
+static inline bool qcpw_block_threads_ok(int v) { return v == 0 || (v >= 64 && v <= 1024 && v % 64 == 0); }
 #define QCPW_STACK_MAX 12        // bridge stack depth bound (ceil log2 QCPW_MAX_N + 2)
 #define QCPW_PCA_NPAD 256        // padded factor size of the matrix-core PCA kernel
 
@@ -44,13 +47,18 @@ static inline int64_t qcpw_unit_points(int64_t n_points)
 // terminal point W~(n dt) (no push); step s >= 1 is the midpoint m of an
 // interval (l, r): before it, `pops` times "L = R; R = stack.pop()"; then
 // W_m = wl * L + wr * R + sd * z_{dim}; stack.push(R); R = W_m.
+// A pop followed by the push of the value it returned leaves the stack as
+// it was, so the kernel only writes when pops = 0 (slot = the stack depth
+// before the step) and otherwise only reads: R = stack[slot] and, for
+// pops >= 2, L = stack[slot + 1] (slot = depth - pops; depth after the
+// step = slot + 1).
 struct PlanStep {
     int32_t lds_off;   // (dim - 1) * 64: row of the lane table for this step's dimension
-    int32_t m;         // grid index of the new point (1..n)
+    int32_t slot;      // stack slot written (pops = 0) or read (pops >= 1)
     int32_t pops;      // stack pops before the step
     int32_t dim;       // Sobol dimension of the step (1..n)
     float wl, wr, sd;  // (r-m)/(r-l), (m-l)/(r-l), sqrt((m-l)(r-m)/(r-l)) in units of sqrt(dt)
-    float mf;          // float(m)
+    float mf;          // float(m), m = grid index of the new point (1..n)
 };
 struct PlanStep64 {
     double wl, wr, sd, mf;

@@ -392,8 +392,8 @@ qcpw_status qcpw_server_create(const qcpw_run_config *cfg, int64_t hbm_budget_by
     c.device = -1;
     if (cfg) c = *cfg;
     if (c.precision != QCPW_FP64 && c.precision != QCPW_FP32_MIXED) return fail(QCPW_EINVAL, "unknown precision");
-    if (c.block_threads != 0 && c.block_threads != 256 && c.block_threads != 512 && c.block_threads != 1024)
-        return fail(QCPW_EINVAL, "block_threads must be 0, 256, 512 or 1024");
+    if (!qcpw_block_threads_ok(c.block_threads))
+        return fail(QCPW_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
     Context *ctx = nullptr;
     qcpw_status st = get_context(c.device, &ctx);
     if (st != QCPW_OK) return st;

@@ -2,6 +2,7 @@
 // Sobol direction numbers, the per-wave lane table, bridge plans and
 // principal-component factors.  Everything here is computed once per process
 // (direction numbers, plans) or once per distinct (n, dt) (PCA factors).
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -84,10 +85,19 @@ int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep6
             fifo.emplace_back(m, iv.second);
         }
     }
+    int sp = 0, max_sp = 0;   // stack depth as the kernel sees it
     auto add = [&](int dim, int m, int pops, double wl, double wr, double sd) {
         PlanStep s;
         s.lds_off = (dim - 1) * 64;
-        s.m = m;
+        if (steps.empty()) {
+            s.slot = 0;                 // terminal point: no stack access
+        } else if (pops == 0) {
+            s.slot = sp++;              // push R
+        } else {
+            s.slot = sp - pops;         // R = stack[slot], L = stack[slot + 1] if pops >= 2
+            sp = s.slot + 1;
+        }
+        max_sp = std::max(max_sp, sp);
         s.pops = pops;
         s.dim = dim;
         s.wl = (float)wl;
@@ -129,7 +139,7 @@ int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep6
             st.pop_back();
         }
     }
-    return max_depth;
+    return std::max(max_depth, max_sp);
 }
 
 // Principal components of Sigma_{kl} = dt min(k, l), k, l = 1..n, in closed
@@ -165,13 +175,14 @@ void build_factor(int path, int n, double dt, std::vector<double> &A)
             for (int i = 0; i <= k; ++i) A[(size_t)k * n + i] = std::sqrt(dt);
         return;
     }
-    // bridge: apply the plan to every unit vector (column by column)
+    // bridge: apply the plan to every unit vector (column by column), with
+    // the stack slots exactly as the kernels use them
     std::vector<PlanStep> steps;
     std::vector<PlanStep64> s64;
-    build_bridge_plan(n, steps, s64);
+    const int depth = build_bridge_plan(n, steps, s64);
     std::vector<double> W(n + 1);
     for (int col = 0; col < n; ++col) {
-        std::vector<double> stack;
+        std::vector<double> stack(depth + 1, std::nan(""));
         double L = 0.0, R = 0.0;
         for (size_t s = 0; s < steps.size(); ++s) {
             double z = (steps[s].dim - 1 == col) ? std::sqrt(dt) : 0.0;
@@ -180,15 +191,21 @@ void build_factor(int path, int n, double dt, std::vector<double> &A)
                 W[n] = R;
                 continue;
             }
-            for (int p = 0; p < steps[s].pops; ++p) {
-                L = R;
-                R = stack.back();
-                stack.pop_back();
+            const int slot = steps[s].slot, pops = steps[s].pops;
+            if (slot < 0 || slot >= depth || (pops >= 2 && slot + 1 >= depth)) {
+                std::fill(A.begin(), A.end(), std::nan(""));   // a broken plan fails every check
+                return;
+            }
+            if (pops == 0) {
+                stack[slot] = R;
+            } else {
+                const double r = stack[slot];
+                L = pops == 1 ? R : stack[slot + 1];
+                R = r;
             }
             double Wm = s64[s].wl * L + s64[s].wr * R + s64[s].sd * z;
-            stack.push_back(R);
             R = Wm;
-            W[steps[s].m] = Wm;
+            W[(int)steps[s].mf] = Wm;
         }
         for (int k = 0; k < n; ++k) A[(size_t)k * n + col] = W[k + 1];
     }

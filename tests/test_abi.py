@@ -65,7 +65,7 @@ def test_invalid_specs_rejected_before_any_device_work(patch, msg):
 def test_invalid_call_arguments():
     o = dict(type=0, d=16, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, seed=1, n_points=64)
     for kw in (dict(n_shifts=0), dict(n_shifts=70000), dict(path=9), dict(precision=5),
-               dict(block_threads=100), dict(pca_gemm=3)):
+               dict(block_threads=100), dict(block_threads=1088), dict(pca_gemm=3)):
         args = dict(n_shifts=4)
         args.update(kw)
         with pytest.raises(q.QcpwError):
@@ -91,6 +91,19 @@ def test_library_factor_matches_oracle(path, d):
         assert np.abs(A @ Z[:, c] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
     Sig = oracle.covariance(n, dt)
     assert np.abs(A @ A.T - Sig).max() <= 1e-14 * Sig.max() * max(1, n / 16)
+
+
+def test_bridge_plan_every_size():
+    """Every bridge plan the kernels can be given (d = 2..385), replayed on
+    the host with the kernels' stack slots, builds the oracle's bridge."""
+    rng = np.random.default_rng(385)
+    for d in range(2, 386):
+        n, dt = d - 1, 1.0 / d
+        A = q.path_factor(q.PATH_BB, d, 1.0)
+        z = rng.standard_normal(n)
+        ref = oracle.build_path(q.PATH_BB, n, dt, z)[1:]
+        assert np.isfinite(A).all(), d
+        assert np.abs(A @ z - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), d
 
 
 def test_library_factor_argument_checks():

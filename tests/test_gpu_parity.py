@@ -165,7 +165,7 @@ def test_each_option_same_alone_and_in_a_mix(prec):
         assert np.array_equal(g1[0], g_mix[i]) and np.array_equal(e1[0], e_mix[i])
     # work units belong to waves and depend on the option alone, so the
     # workgroup shape does not change a single bit
-    for bd in (256, 1024):
+    for bd in (256, 640, 1024):
         g_other, e_other = q.greeks(mix, 4, q.PATH_BB, prec, block_threads=bd)
         assert np.array_equal(g_other, g_mix) and np.array_equal(e_other, e_mix)
 
