@@ -169,6 +169,24 @@ qcpw_status qcpw_sobol_points(uint64_t seed, int32_t shift_index, int32_t n_dims
  */
 qcpw_status qcpw_path_factor(int32_t path_construction, int32_t d, double T, double *out);
 
+/*
+ * qcpw_kernel_timer -- measurement of the main kernel (the fused per-path
+ * kernel, or the PCA kernel) of each qmc_cpw_greeks / qmc_cpw_greeks_ex call
+ * on `device` (-1 = current) that runs eagerly (not from a captured graph,
+ * not from a server).  The library records a pair of HIP events on the
+ * call's stream around that kernel alone.
+ *   op = QCPW_TIMER_START: forget earlier pairs and start recording;
+ *   op = QCPW_TIMER_READ:  wait for the recorded events, write the summed
+ *        kernel time in milliseconds to *total_ms and the number of timed
+ *        launches to *launches (either pointer may be NULL); keep recording;
+ *   op = QCPW_TIMER_STOP:  as READ, then stop recording.
+ * Errors: QCPW_EINVAL for another op, QCPW_EDEVICE without a usable device.
+ */
+#define QCPW_TIMER_START 1
+#define QCPW_TIMER_READ 2
+#define QCPW_TIMER_STOP 3
+qcpw_status qcpw_kernel_timer(int32_t device, int32_t op, double *total_ms, int64_t *launches);
+
 /* Message describing the calling thread's last error ("" if none). */
 const char *qcpw_last_error(void);
 

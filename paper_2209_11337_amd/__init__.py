@@ -33,7 +33,7 @@ STATUS = {0: "QCPW_OK", -1: "QCPW_EINVAL", -2: "QCPW_ENOMEM", -3: "QCPW_EDEVICE"
 
 # names of every entry point declared in include/qmc_cpw.h
 EXPORTS = ("qmc_cpw_greeks", "qmc_cpw_greeks_ex", "qcpw_sobol_points", "qcpw_path_factor",
-           "qcpw_last_error", "qcpw_version", "qcpw_server_create", "qcpw_submit", "qcpw_poll",
+           "qcpw_kernel_timer", "qcpw_last_error", "qcpw_version", "qcpw_server_create", "qcpw_submit", "qcpw_poll",
            "qcpw_wait", "qcpw_cancel", "qcpw_server_stats", "qcpw_server_destroy")
 
 
@@ -80,6 +80,7 @@ def lib() -> C.CDLL:
             L.qmc_cpw_greeks_ex.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p, vp]
             L.qcpw_sobol_points.argtypes = [u64, i32, i32, i64, i64, vp]
             L.qcpw_path_factor.argtypes = [i32, i32, C.c_double, vp]
+            L.qcpw_kernel_timer.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(i64)]
             L.qcpw_last_error.restype = C.c_char_p
             L.qcpw_version.restype = C.c_char_p
             L.qcpw_server_create.argtypes = [vp, i64, C.POINTER(vp)]
@@ -184,6 +185,17 @@ def path_factor(path: int, d: int, T: float) -> np.ndarray:
     out = np.zeros((max(n, 0), max(n, 0)))
     _check(lib().qcpw_path_factor(path, d, T, out.ctypes.data if n > 0 else None))
     return out
+
+
+TIMER_START, TIMER_READ, TIMER_STOP = 1, 2, 3
+
+
+def kernel_timer(op: int, device: int = -1) -> tuple[float, int]:
+    """qcpw_kernel_timer: (summed main-kernel milliseconds, timed launches)."""
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    _check(lib().qcpw_kernel_timer(device, op, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 class Server:

@@ -318,7 +318,7 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
         e = (double *)(p + ((out_bytes + 255) / 256) * 256);
         ps = c.out_per_shift ? (double *)(p + 2 * ((out_bytes + 255) / 256) * 256) : nullptr;
     }
-    st = enqueue_launch(ctx, lp, stream, g, e, ps, ws, need);
+    st = enqueue_launch(ctx, lp, stream, g, e, ps, ws, need, nullptr, nullptr, true);
     if (st != QCPW_OK) return st;
     QCPW_HIP(hipEventRecord(ctx->ws_done, stream));
     ctx->ws_pending = true;
@@ -329,6 +329,34 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
             QCPW_HIP(hipMemcpyAsync(c.out_per_shift, ps, ps_bytes, hipMemcpyDeviceToHost, stream));
         QCPW_HIP(hipStreamSynchronize(stream));
     }
+    return QCPW_OK;
+}
+
+qcpw_status qcpw_kernel_timer(int32_t device, int32_t op, double *total_ms, int64_t *launches)
+{
+    g_last_error.clear();
+    if (op != QCPW_TIMER_START && op != QCPW_TIMER_READ && op != QCPW_TIMER_STOP)
+        return fail(QCPW_EINVAL, "op must be QCPW_TIMER_START, _READ or _STOP");
+    Context *ctx = nullptr;
+    qcpw_status st = get_context(device, &ctx);
+    if (st != QCPW_OK) return st;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Context::Timer &tm = ctx->timer;
+    if (op == QCPW_TIMER_START) {
+        tm.on = true;
+        tm.used = 0;
+        return QCPW_OK;
+    }
+    double total = 0.0;
+    for (size_t i = 0; i + 1 < tm.used; i += 2) {
+        QCPW_HIP(hipEventSynchronize(tm.ev[i + 1]));
+        float ms = 0.0f;
+        QCPW_HIP(hipEventElapsedTime(&ms, tm.ev[i], tm.ev[i + 1]));
+        total += ms;
+    }
+    if (total_ms) *total_ms = total;
+    if (launches) *launches = (int64_t)(tm.used / 2);
+    if (op == QCPW_TIMER_STOP) tm.on = false;
     return QCPW_OK;
 }
 

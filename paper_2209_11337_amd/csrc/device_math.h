@@ -82,20 +82,17 @@ __host__ __device__ inline uint32_t fold_sign(uint32_t y)
     return y ^ ((uint32_t)((int32_t)y >> 31) >> 1);
 }
 
-// Phi^{-1}((y + 1/2) 2^-32) * scale in FP32 for folded x = fold(y), from the
-// cubic table of ninv_table.inc held in LDS at `tab`:
-// q = (m + 1/2) 2^-32 in FP32 with m the low 31 bits of x (so q <= 1/2),
-// bits 18..27 of q select the cell, the cubic is evaluated in q itself;
-// Phi^{-1}(q) <= 0, and the result has the sign of scale times + iff bit 31
-// of x is set.
-__device__ inline float ninv_table_f32(uint32_t x, float scale, const float4 *__restrict__ tab)
+// Phi^{-1}((y + 1/2) 2^-32) in FP32 for folded x = fold(y), from the cubic
+// table of ninv_table.inc held in LDS at `tab`: q = float(m), m the low 31
+// bits of x; bits 18..27 of q select the cell and the cubic is evaluated in
+// q itself, giving Phi^{-1}((m + 1/2) 2^-32) <= 0; bit 31 of x is the sign.
+__device__ inline float ninv_table_f32(uint32_t x, const float4 *__restrict__ tab)
 {
-    const float q = fmaf((float)(x & 0x7FFFFFFFu), 0x1p-32f, 0x1p-33f);
+    const float q = (float)(x & 0x7FFFFFFFu);
     const uint32_t b = __float_as_uint(q);
     const float4 c = *(const float4 *)((const char *)tab + ((b >> 14) & 0x3FF0u));
     const float p = fmaf(fmaf(fmaf(c.x, q, c.y), q, c.z), q, c.w);
-    const float k = __uint_as_float((x & 0x80000000u) ^ __float_as_uint(scale));
-    return p * k;
+    return __uint_as_float(__float_as_uint(p) ^ (x & 0x80000000u));
 }
 
 // Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library) for folded x = fold(y),
@@ -306,13 +303,14 @@ struct Real<true> { using T = float; };
 template <>
 struct Real<false> { using T = double; };
 
-// Inverse normal of one folded coordinate x = fold(y), result in Y units;
-// FP32 from the LDS cubic table.
+// Inverse normal of one folded coordinate x = fold(y): FP32 from the LDS
+// cubic table as a standard normal (the caller applies the option's scale
+// sigma sqrt(dt) log2(e)), FP64 already in Y units.
 template <bool F32>
 __device__ inline typename Real<F32>::T coord_tab(uint32_t x, const OptDev &op, const float4 *tab)
 {
     if constexpr (F32) {
-        return ninv_table_f32(x, op.zs_t, tab);
+        return ninv_table_f32(x, tab);
     } else {
         return ninv_f64(x) * op.zscale;
     }

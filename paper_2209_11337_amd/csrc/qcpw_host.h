@@ -75,6 +75,8 @@ struct Context {
     };
     std::vector<Graph> graphs;
     uint64_t graph_clock = 0;
+    // qcpw_kernel_timer: event pairs around the main kernel of eager calls
+    struct Timer { bool on = false; std::vector<hipEvent_t> ev; size_t used = 0; } timer;
 };
 
 qcpw_status get_context(int device, Context **out);
@@ -121,7 +123,8 @@ size_t launch_workspace_bytes(const LaunchPlan &lp);
 qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream,
                            double *dev_out_greeks, double *dev_out_stderr,
                            double *dev_out_per_shift, void *ws, size_t ws_bytes,
-                           const OptDev *h_opts = nullptr, const int64_t *h_prefix = nullptr);
+                           const OptDev *h_opts = nullptr, const int64_t *h_prefix = nullptr,
+                           bool timed = false);
 
 qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index, int32_t n_dims,
                                 int64_t k0, int64_t count, uint32_t *dev_out, hipStream_t stream);

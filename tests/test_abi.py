@@ -106,6 +106,13 @@ def test_bridge_plan_every_size():
         assert np.abs(A @ z - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), d
 
 
+def test_kernel_timer_argument_checks():
+    for op in (0, 4, -1):
+        with pytest.raises(q.QcpwError) as ei:
+            q.kernel_timer(op)
+        assert ei.value.status == -1
+
+
 def test_library_factor_argument_checks():
     with pytest.raises(q.QcpwError):
         q.path_factor(q.PATH_PCA, 300, 1.0)

@@ -182,6 +182,26 @@ def test_device_outputs_on_torch_stream():
     assert np.array_equal(out[1].cpu().numpy(), ref_e)
 
 
+def test_kernel_timer_counts_eager_launches():
+    import torch
+    opts = workloads.three_products_grid(d=16, n_points=1 << 14)
+    s = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    q.kernel_timer(q.TIMER_START)
+    e0.record(s)
+    for _ in range(3):
+        q.greeks(opts, 8, q.PATH_BB, q.FP32_MIXED, device_outputs=True, stream=s)
+    e1.record(s)
+    s.synchronize()
+    ms, n = q.kernel_timer(q.TIMER_READ)
+    assert n == 3 and 0.0 < ms <= e0.elapsed_time(e1) * 1.01 + 0.01
+    q.greeks(opts, 8, q.PATH_BB, q.FP32_MIXED, device_outputs=True, stream=s, graph=True)   # not timed
+    ms2, n2 = q.kernel_timer(q.TIMER_STOP)
+    assert n2 == 3 and ms2 == ms
+    q.greeks(opts, 8, q.PATH_BB, q.FP32_MIXED)
+    assert q.kernel_timer(q.TIMER_READ)[1] == 3   # stopped
+
+
 # ------------------------------------------------------------------------
 # full size: the benchmark's workload, sampled
 # ------------------------------------------------------------------------
