@@ -66,6 +66,7 @@ static qcpw_status init_tables(Context *ctx, int device)
         std::vector<PlanStep> s;
         std::vector<PlanStep64> s64;
         int depth = build_bridge_plan(n, s, s64);
+        if (depth < 0) return fail(QCPW_EDEVICE, "bridge plan disagrees with the compile-time bridges");
         if (depth > QCPW_STACK_MAX) return fail(QCPW_EDEVICE, "bridge plan deeper than the kernel's stack");
         t.max_stack = std::max(t.max_stack, depth);
         t.depth[n] = depth;

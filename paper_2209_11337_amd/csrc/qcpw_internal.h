@@ -40,6 +40,72 @@ static inline int64_t qcpw_unit_points(int64_t n_points)
 static inline bool qcpw_block_threads_ok(int v) { return v == 0 || (v >= 64 && v <= 1024 && v % 64 == 0); }
 #define QCPW_STACK_MAX 12        // bridge stack depth bound (ceil log2 QCPW_MAX_N + 2)
 #define QCPW_PCA_NPAD 256        // padded factor size of the matrix-core PCA kernel
+#define QCPW_FIXED_MAX_N 127     // largest n with a compile-time bridge
+
+// Square root by Newton's method from above, usable in constant expressions
+// (within one ulp).  The bridge weights of the run-time plans and of the
+// compile-time bridges both come from this function, so they hold the same
+// bits.
+constexpr double qcpw_csqrt(double x)
+{
+    if (!(x > 0.0)) return 0.0;
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 400; ++i) {
+        const double nr = 0.5 * (r + x / r);
+        if (!(nr < r)) break;
+        r = nr;
+    }
+    return r;
+}
+
+// Sobol dimension of the midpoint of interval (lo, hi) in the bridge over
+// grid points 0..n: intervals with hi - lo >= 2 taken breadth first from
+// (0, n), left half before right half, get dimensions 2, 3, ... (dimension 1
+// is the terminal point).  -1 if (lo, hi) is not such an interval.
+constexpr int qcpw_bridge_dim(int n, int lo, int hi)
+{
+    int ql[2 * QCPW_FIXED_MAX_N + 4] = {}, qh[2 * QCPW_FIXED_MAX_N + 4] = {};
+    if (n > QCPW_FIXED_MAX_N) return -1;
+    int head = 0, tail = 0, next = 2;
+    ql[tail] = 0;
+    qh[tail] = n;
+    ++tail;
+    while (head < tail) {
+        const int l = ql[head], r = qh[head];
+        ++head;
+        if (r - l < 2) continue;
+        if (l == lo && r == hi) return next;
+        ++next;
+        const int m = (l + r) / 2;
+        ql[tail] = l; qh[tail] = m; ++tail;
+        ql[tail] = m; qh[tail] = r; ++tail;
+    }
+    return -1;
+}
+
+// Position of the midpoint of interval (lo, hi) in the order the kernels
+// walk the bridge: depth first, a midpoint before its left half before its
+// right half; the terminal point is step 0.  -1 if not such an interval.
+constexpr int qcpw_bridge_step(int n, int lo, int hi)
+{
+    int sl[64] = {}, sh[64] = {};
+    if (n > QCPW_FIXED_MAX_N) return -1;
+    int top = 0, step = 1;
+    sl[top] = 0;
+    sh[top] = n;
+    ++top;
+    while (top > 0) {
+        --top;
+        const int l = sl[top], r = sh[top];
+        if (r - l < 2) continue;
+        if (l == lo && r == hi) return step;
+        ++step;
+        const int m = (l + r) / 2;
+        sl[top] = m; sh[top] = r; ++top;   // right half, taken after the left half
+        sl[top] = l; sh[top] = m; ++top;
+    }
+    return -1;
+}
 
 // One step of a bridge plan, in the order the kernel walks the bridge: the
 // intervals of the breadth-first bridge are visited depth first, so that only

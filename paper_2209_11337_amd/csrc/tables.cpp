@@ -107,7 +107,8 @@ int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep6
         steps.push_back(s);
         steps64.push_back(PlanStep64{wl, wr, sd, (double)m});
     };
-    add(1, n, 0, 0.0, 0.0, std::sqrt((double)n));   // terminal point
+    add(1, n, 0, 0.0, 0.0, qcpw_csqrt((double)n));   // terminal point
+    bool consistent = true;   // the compile-time bridges walk the same intervals
 
     int pending = 0, depth = 0, max_depth = 0;
     // iterative depth-first walk: frame = (l, r, state)
@@ -123,8 +124,12 @@ int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep6
         int m = (f.l + f.r) / 2;
         if (f.state == 0) {
             double len = f.r - f.l;
+            if (n <= QCPW_FIXED_MAX_N &&
+                (qcpw_bridge_dim(n, f.l, f.r) != dim_of[{f.l, f.r}] ||
+                 qcpw_bridge_step(n, f.l, f.r) != (int)steps.size()))
+                consistent = false;
             add(dim_of[{f.l, f.r}], m, pending, (f.r - m) / len, (m - f.l) / len,
-                std::sqrt((double)(m - f.l) * (double)(f.r - m) / len));
+                qcpw_csqrt((double)(m - f.l) * (double)(f.r - m) / len));
             pending = 0;
             ++depth;
             if (depth > max_depth) max_depth = depth;
@@ -139,6 +144,7 @@ int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep6
             st.pop_back();
         }
     }
+    if (!consistent) return -1;
     return std::max(max_depth, max_sp);
 }
 
@@ -180,6 +186,10 @@ void build_factor(int path, int n, double dt, std::vector<double> &A)
     std::vector<PlanStep> steps;
     std::vector<PlanStep64> s64;
     const int depth = build_bridge_plan(n, steps, s64);
+    if (depth < 0) {
+        std::fill(A.begin(), A.end(), std::nan(""));   // plan self-check failed
+        return;
+    }
     std::vector<double> W(n + 1);
     for (int col = 0; col < n; ++col) {
         std::vector<double> stack(depth + 1, std::nan(""));
