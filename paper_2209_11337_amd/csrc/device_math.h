@@ -84,13 +84,15 @@ __host__ __device__ inline uint32_t fold_sign(uint32_t y)
 
 // Phi^{-1}((y + 1/2) 2^-32) in FP32 for folded x = fold(y), from the cubic
 // table of ninv_table.inc held in LDS at `tab`: q = float(m), m the low 31
-// bits of x; bits 18..27 of q select the cell and the cubic is evaluated in
+// bits of x; bits 23-c..27 of q (c = QCPW_NINV_CELL_BITS) select the cell and the cubic is evaluated in
 // q itself, giving Phi^{-1}((m + 1/2) 2^-32) <= 0; bit 31 of x is the sign.
 __device__ inline float ninv_table_f32(uint32_t x, const float4 *__restrict__ tab)
 {
     const float q = (float)(x & 0x7FFFFFFFu);
     const uint32_t b = __float_as_uint(q);
-    const float4 c = *(const float4 *)((const char *)tab + ((b >> 14) & 0x3FF0u));
+    constexpr uint32_t sh = 19 - QCPW_NINV_CELL_BITS;   // byte offset = 16 x bits (23 - CELL_BITS)..27
+    constexpr uint32_t mask = ((1u << (QCPW_NINV_CELL_BITS + 5)) - 1u) << 4;
+    const float4 c = *(const float4 *)((const char *)tab + ((b >> sh) & mask));
     const float p = fmaf(fmaf(fmaf(c.x, q, c.y), q, c.z), q, c.w);
     return __uint_as_float(__float_as_uint(p) ^ (x & 0x80000000u));
 }

@@ -155,6 +155,7 @@ template <bool MAX>
 __device__ inline bool bridge_fixed_any(const OptDev &op, const uint32_t *lds_lane, const float4 *tab, int lane,
                                         const uint32_t (&U)[QCPW_UQ], PathSums<float> &ps)
 {
+    if (!qcpw_has_fixed_bridge(op.n)) return false;
     switch (op.n) {
     case 15: run_bridge_fixed<MAX, 15>(op, lds_lane, tab, lane, U, ps); return true;
     case 31: run_bridge_fixed<MAX, 31>(op, lds_lane, tab, lane, U, ps); return true;
@@ -494,6 +495,16 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
     return QCPW_OK;
 }
 
+// Compile-time bridges (FP32 kernel): on unless QCPW_FIXED_BRIDGES=0.
+static bool fixed_bridges_on()
+{
+    static const bool on = [] {
+        const char *e = getenv("QCPW_FIXED_BRIDGES");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
                         int64_t n_points, int32_t n_shifts, int32_t path, int32_t precision,
                         int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp, const int64_t *k_begin)
@@ -561,7 +572,10 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.ydrift_1_f = (float)op.ydrift_1;
         cost[i] = (double)std::max(op.n, 1) * (double)op.chunks;
         lp.max_n = std::max(lp.max_n, op.n);
-        if (path == QCPW_PATH_BB && op.n >= 1) lp.stack_depth = std::max(lp.stack_depth, ctx->tab.depth[op.n]);
+        // options walked by a compile-time bridge need no LDS stack
+        const bool fixed = precision == QCPW_FP32_MIXED && fixed_bridges_on() && qcpw_has_fixed_bridge(op.n);
+        if (path == QCPW_PATH_BB && op.n >= 1 && !fixed)
+            lp.stack_depth = std::max(lp.stack_depth, ctx->tab.depth[op.n]);
     }
     // most expensive units first (longest-processing-time order)
     std::vector<int32_t> order(n_opts);
@@ -819,12 +833,7 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         unsigned long long *a_ctr = ld.counter;
         int a_nopts = ld.n_opts, a_maxn = ld.max_n, a_depth = lp.stack_depth;
         long long a_total = ld.total_units;
-        // QCPW_FIXED_BRIDGES=0 in the environment walks every bridge from its plan
-        static const int a_fixed = [] {
-            const char *e = getenv("QCPW_FIXED_BRIDGES");
-            return (e && e[0] == '0') ? 0 : 1;
-        }();
-        int a_fixed_arg = a_fixed;
+        int a_fixed_arg = fixed_bridges_on() ? 1 : 0;
         void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_dir, &a_lane, &a_tab, &a_part, &a_ctr,
                         &a_nopts, &a_maxn, &a_depth, &a_total, &a_fixed_arg};
         if (t0) QCPW_HIP(hipEventRecord(t0, stream));

@@ -42,6 +42,13 @@ static inline bool qcpw_block_threads_ok(int v) { return v == 0 || (v >= 64 && v
 #define QCPW_PCA_NPAD 256        // padded factor size of the matrix-core PCA kernel
 #define QCPW_FIXED_MAX_N 127     // largest n with a compile-time bridge
 
+// n (= d - 1) that the FP32 kernel walks with a compile-time bridge; the
+// host leaves such options out of the LDS stack size, so this is the one list.
+__host__ __device__ constexpr bool qcpw_has_fixed_bridge(int n)
+{
+    return n == 15 || n == 31 || n == 63 || n == 127;
+}
+
 // Square root by Newton's method from above, usable in constant expressions
 // (within one ulp).  The bridge weights of the run-time plans and of the
 // compile-time bridges both come from this function, so they hold the same
