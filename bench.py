@@ -38,6 +38,23 @@ F64_PER_PATH = 200.0
 PEAK_F32 = 157.3e12       # MI355X vector FP32 (packed), 256 CU x 2.4 GHz x 256 flop/clk
 PEAK_F64 = 78.6e12        # MI355X vector FP64
 
+# HBM bytes per launch of the fused kernel on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (profiles/
+# paths_kernel_fp32_bridge_three_products_d64.md), valid only for the kernel
+# sources they were taken on (sha256 prefix of their concatenation).
+TRAFFIC_SOURCES = ("kernels.hip", "device_math.h", "qcpw_internal.h", "ninv_table.inc")
+TRAFFIC_SHA = "7068e07457b490f6"
+TRAFFIC_BYTES = {"fetch": 0.863e6, "write": 14.357e6}
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2209_11337_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -121,8 +138,10 @@ def main():
     t_ideal = f32 / PEAK_F32 + f64 / PEAK_F64
     t_kernel = kern_ms * 1e-3
     achieved = (f32 + f64 * PEAK_F32 / PEAK_F64) / t_kernel
+    same_kernel = prec == q.FP32_MIXED and kernel_sources_sha() == TRAFFIC_SHA
+    traffic = TRAFFIC_BYTES["fetch"] + TRAFFIC_BYTES["write"] if same_kernel else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_F32 / 1e12, "unit": "TFLOP/s",
-                "frac": t_ideal / t_kernel, "traffic": None,
+                "frac": t_ideal / t_kernel, "traffic": traffic,
                 "model": "FP32-equivalent flops: %.0f FP32/path-date + %.0f FP64/path (FP64 weighted x2)"
                          % (F32_PER_PATH_DATE, F64_PER_PATH),
                 "kernel": "qcpw::paths_kernel", "kernel_ms": kern_ms, "call_ms": ev_ms}
@@ -151,7 +170,7 @@ def main():
         # the oracle on the host cores, a bounded sample of the same workload
         import oracle
         n_cpu = a.cpu_points
-        Ls = 4
+        Ls = 8
         sample = workloads.three_products_grid(d=64, n_points=n_cpu)
         threads = os.cpu_count() or 1
         t0 = time.perf_counter()
@@ -163,6 +182,7 @@ def main():
                                          % (int(np.log2(n_cpu)), Ls, tc)}
     if not a.no_extras:
         res["small_call"] = small_call_leg(q, workloads, torch)
+        res["pca"] = pca_leg(q, workloads, torch)
     if not a.no_extras and not a.no_portfolio:
         res["portfolio"] = portfolio_leg(q, workloads, torch)
     if not a.no_extras and not a.no_serve:
@@ -188,6 +208,42 @@ def small_call_leg(q, workloads, torch, calls=200):
             q.greeks(opts, 16, q.PATH_BB, q.FP64, device_outputs=True, out=out, stream=s, graph=graph)
         s.synchronize()
         res[name] = (time.perf_counter() - t0) / calls * 1e6
+    return res
+
+
+def pca_leg(q, workloads, torch, steps=3):
+    """Principal-component paths at d = 256 (255 x 255 factor padded to 256,
+    a dense (256 x 256) x (256 x 64-point) product per tile on the matrix
+    cores): arithmetic and binary Asian, 2^22 points x 16 shifts, FP32-mixed,
+    GEMM in FP32 MFMA and in split BF16x3; kernel time from the library's
+    HIP events.  gemm_frac is the product's algorithmic flops 2 n^2 per path
+    over the time of the whole fused kernel, against the FP32 MFMA peak
+    (157.3 TFLOP/s) or, for BF16x3 (three BF16 products per FP32 product),
+    a third of the BF16 peak (2.5 PFLOP/s / 3)."""
+    opts = workloads.pca_pair(d=256, n_points=1 << 22)
+    L = 16
+    n = 255
+    paths = workloads.total_paths(opts, L)
+    s = torch.cuda.Stream()
+    out = (torch.empty((2, 4), dtype=torch.float64, device="cuda"),
+           torch.empty((2, 4), dtype=torch.float64, device="cuda"))
+    res = {"workload": "arith + binary Asian, d=256, PCA, 2^22 points x 16 shifts, FP32-mixed",
+           "greek_paths": paths}
+    for name, gemm, peak in (("fp32_mfma", q.GEMM_FP32, 157.3e12), ("bf16x3_mfma", q.GEMM_BF16X3, 2.5e15 / 3)):
+        q.greeks(opts, L, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, device_outputs=True, out=out, stream=s)
+        s.synchronize()
+        q.kernel_timer(q.TIMER_START)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            q.greeks(opts, L, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, device_outputs=True, out=out, stream=s)
+        s.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
+        k_ms /= max(k_n, 1)
+        gflop = 2.0 * n * n * paths
+        res[name] = {"value": paths / wall, "unit": "Greek-paths/s", "kernel_ms": k_ms,
+                     "gemm_tflops": gflop / (k_ms * 1e-3) / 1e12,
+                     "gemm_frac": gflop / (k_ms * 1e-3) / peak}
     return res
 
 
