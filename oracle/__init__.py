@@ -34,7 +34,7 @@ _lock = threading.Lock()
 _lib = None
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK = 0, 1, 2
-PATH_BB, PATH_PCA, PATH_STANDARD = 0, 1, 2
+PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
 OUTPUTS = ("price", "delta", "vega", "gamma")
 
 
@@ -75,6 +75,10 @@ def _load():
             lib.oracle_build_path.restype = C.c_int
             lib.oracle_path_greeks.argtypes = [C.c_int, C.c_int] + [C.c_double] * 5 + [f64p, f64p]
             lib.oracle_path_greeks.restype = None
+            lib.oracle_full_root.argtypes = [C.c_int, f64p, f64p, C.c_double]
+            lib.oracle_full_root.restype = C.c_double
+            lib.oracle_path_greeks_full.argtypes = [C.c_int, C.c_int] + [C.c_double] * 5 + [f64p, f64p, f64p]
+            lib.oracle_path_greeks_full.restype = C.c_int
             lib.oracle_option.argtypes = ([C.c_int, C.c_int] + [C.c_double] * 5 +
                                           [C.c_uint64, C.c_int64, C.c_int, C.c_int, u32p, C.c_void_p,
                                            C.c_void_p, f64p, f64p, f64p])
@@ -194,15 +198,39 @@ def path_greeks(type_: int, d: int, S0, K, r, sigma, T, W) -> np.ndarray:
     return out
 
 
+def full_root(alpha, beta, K) -> float:
+    """Root psi of (1/d) sum_j exp(alpha_j + beta_j x) = K (full-PCA conditioning)."""
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    return float(_load().oracle_full_root(len(al), al, be, float(K)))
+
+
+def path_greeks_full(type_: int, d: int, S0, K, r, sigma, T, a, c) -> np.ndarray:
+    """{price, delta, vega, gamma} of one path conditioned on the first
+    principal component: a = first column of the d x d factor, c = the other
+    components' part of W(t_1..t_d)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    out = np.zeros(4)
+    if _load().oracle_path_greeks_full(type_, d, S0, K, r, sigma, T, a, c, out) != 0:
+        raise ValueError("full-PCA conditioning covers arithmetic and binary Asian options only")
+    return out
+
+
+def _factor(path: int, d: int, T: float):
+    """The dense factor the oracle needs for a path construction (None if none)."""
+    if path == PATH_PCA and d > 1:
+        return np.ascontiguousarray(pca_factor(d - 1, T / d))
+    if path == PATH_PCA_FULL:
+        return np.ascontiguousarray(pca_factor(d, T / d))
+    return None
+
+
 def option(type_: int, d: int, S0, K, r, sigma, T, seed: int, N: int, L: int, path: int = PATH_BB):
     """One option: dict(mean[4], stderr[4], abs_mean[4], C_l[L][4])."""
     V = direction_numbers(max(d, 2))
-    n = d - 1
-    A = None
-    Ap = None
-    if path == PATH_PCA and n > 0:
-        A = pca_factor(n, T / d)
-        Ap = A.ctypes.data
+    A = _factor(path, d, T)
+    Ap = A.ctypes.data if A is not None else None
     C_l = np.zeros((L, 4))
     mean, se, am = np.zeros(4), np.zeros(4), np.zeros(4)
     rc = _load().oracle_option(type_, d, S0, K, r, sigma, T, seed & (2**64 - 1), N, L, path,
@@ -217,7 +245,7 @@ def replication(o: dict, l: int, path: int = PATH_BB, k0: int = 0, N: int | None
     d = int(o["d"])
     N = int(o["n_points"]) if N is None else int(N)
     V = direction_numbers(max(d, 2))
-    A = pca_factor(d - 1, o["T"] / d) if (path == PATH_PCA and d > 1) else None
+    A = _factor(path, d, o["T"])
     out = np.zeros(4)
     rc = _load().oracle_replication(int(o["type"]), d, float(o["S0"]), float(o["K"]), float(o["r"]),
                                     float(o["sigma"]), float(o["T"]), int(o["seed"]) & (2**64 - 1), k0, N,
@@ -241,11 +269,11 @@ def options(specs, L: int, path: int = PATH_BB, n_threads: int = 0):
     V = direction_numbers(max(2, int(dd.max())))
     keep = []
     Aptr = None
-    if path == PATH_PCA:
+    if path in (PATH_PCA, PATH_PCA_FULL):
         Aptr = (C.c_void_p * n)()
         for i, s in enumerate(specs):
-            A = pca_factor(s["d"] - 1, s["T"] / s["d"]) if s["d"] > 1 else np.zeros((1, 1))
-            A = np.ascontiguousarray(A)
+            A = _factor(path, s["d"], s["T"])
+            A = A if A is not None else np.zeros((1, 1))
             keep.append(A)
             Aptr[i] = A.ctypes.data
     mean, se, am = np.zeros((n, 4)), np.zeros((n, 4)), np.zeros((n, 4))

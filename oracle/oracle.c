@@ -29,6 +29,13 @@
  *   - Uniform from a 32-bit integer y: u = (y + 1/2) * 2^-32.
  *   - Digital shift of replication l, dimension j: high 32 bits of output
  *     number (l * 2^16 + j) of SplitMix64 seeded with the option's seed.
+ *   - ORC_PCA_FULL (the principal-component conditioning the paper names as
+ *     the route to larger variance reduction, Sec. 6): W(t_1..t_d) = A z with
+ *     A the d x d principal-component factor of the full covariance
+ *     dt min(j, k); the first component z_1 (largest eigenvalue) is the
+ *     conditioned variable, integrated out in closed form; z_2..z_d come from
+ *     Sobol dimensions 1..d-1 (dimension 0 stays reserved).  Arithmetic and
+ *     binary Asian only.
  */
 #include <math.h>
 #include <stdint.h>
@@ -41,7 +48,7 @@
 #define ORC_MAX_BITS 32
 
 enum { ORC_ARITH = 0, ORC_BINARY = 1, ORC_LOOKBACK = 2 };
-enum { ORC_BB = 0, ORC_PCA = 1, ORC_STANDARD = 2 };
+enum { ORC_BB = 0, ORC_PCA = 1, ORC_STANDARD = 2, ORC_PCA_FULL = 3 };
 
 /* ------------------------------------------------------------------------
  * Sobol direction numbers (Sec. 2.2.2, eqn:SobolPrimitivePolynomial and
@@ -329,6 +336,112 @@ void oracle_path_greeks(int type, int d, double S0, double K, double r,
     }
 }
 
+/* ------------------------------------------------------------------------
+ * Principal-component conditioning on the first component of the full
+ * covariance (ORC_PCA_FULL).  With W(t_j) = a_j x + c_j, a_j = A_{j,1} > 0,
+ * c_j = sum_{i>=2} A_{j,i} z_i, every log-price is affine in the
+ * conditioned normal x:
+ *     ln S(t_j) = alpha_j + beta_j x,  alpha_j = ln S0 + omega t_j + sigma c_j,
+ *                                      beta_j = sigma a_j.
+ * The average A(x) = (1/d) sum_j exp(alpha_j + beta_j x) is increasing and
+ * convex in x, so A(x) = K has exactly one root psi; it is found by Newton's
+ * method safeguarded by a bracket [lo, hi] (bisection whenever a Newton
+ * step leaves it).  Then, with D = e^{-rT} and x ~ N(0, 1):
+ *   arithmetic:  G = D [ (1/d) sum_j E_j Phi(beta_j - psi) - K Phi(-psi) ],
+ *                E_j = exp(alpha_j + beta_j^2 / 2);
+ *   binary:      G = D Phi(-psi).
+ * The derivatives follow by the chain rule through alpha_j, beta_j and psi
+ * (d alpha_j/d S0 = 1/S0, d alpha_j/d sigma = c_j - sigma t_j,
+ * d beta_j/d sigma = a_j, d psi = -dF/F' with F(x) = A(x) - K); for the
+ * arithmetic payoff the terms in d psi cancel at the root.
+ * ---------------------------------------------------------------------- */
+static double full_F(int d, const double *al, const double *be, double x, double K,
+                     double *Fp)
+{
+    double s = 0.0, s1 = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double g = exp(al[j] + be[j] * x);
+        s += g;
+        s1 += be[j] * g;
+    }
+    *Fp = s1 / d;
+    return s / d - K;
+}
+
+double oracle_full_root(int d, const double *al, const double *be, double K)
+{
+    /* hi: by Jensen, A(x) >= exp(mean(alpha) + mean(beta) x), which equals K at
+     * x = (ln K - mean alpha) / mean beta, so F(hi) >= 0 there */
+    double ma = 0.0, mb = 0.0, Fp;
+    for (int j = 0; j < d; ++j) { ma += al[j]; mb += be[j]; }
+    ma /= d; mb /= d;
+    double hi = (log(K) - ma) / mb;
+    double lo = hi - 1.0;
+    for (int i = 0; i < 200 && full_F(d, al, be, lo, K, &Fp) >= 0.0; ++i) lo -= (hi - lo);
+    double x = hi;
+    for (int it = 0; it < 200; ++it) {
+        double F = full_F(d, al, be, x, K, &Fp);
+        if (F == 0.0) return x;
+        if (F > 0.0) hi = x; else lo = x;
+        double xn = x - F / Fp;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);     /* safeguard */
+        if (fabs(xn - x) <= 1e-15 * (1.0 + fabs(x)) || hi - lo <= 1e-15 * (1.0 + fabs(x))) return xn;
+        x = xn;
+    }
+    return x;
+}
+
+int oracle_path_greeks_full(int type, int d, double S0, double K, double r,
+                            double sigma, double T, const double *a, const double *c,
+                            double *out)
+{
+    if (type != ORC_ARITH && type != ORC_BINARY) return -1;
+    double dt = T / d;
+    double omega = r - 0.5 * sigma * sigma;
+    double D = exp(-r * T);
+    double *al = (double *)malloc(sizeof(double) * (size_t)d);
+    double *be = (double *)malloc(sizeof(double) * (size_t)d);
+    for (int j = 0; j < d; ++j) {
+        double t = (j + 1) * dt;
+        al[j] = log(S0) + omega * t + sigma * c[j];
+        be[j] = sigma * a[j];
+    }
+    double psi = oracle_full_root(d, al, be, K);
+    double phi0 = oracle_norm_pdf(psi);
+    /* F'(psi), F''(psi), dF/dsigma at psi */
+    double F1 = 0.0, F2 = 0.0, Fs = 0.0;
+    double sEP = 0.0, sV = 0.0, sAg = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double t = (j + 1) * dt;
+        double g = exp(al[j] + be[j] * psi);
+        double das = c[j] - sigma * t;                 /* d alpha_j / d sigma */
+        F1 += be[j] * g;
+        F2 += be[j] * be[j] * g;
+        Fs += g * (das + psi * a[j]);
+        double E = exp(al[j] + 0.5 * be[j] * be[j]);
+        double P = oracle_norm_cdf(be[j] - psi);
+        sEP += E * P;
+        sV += E * P * (das + be[j] * a[j]);
+        sAg += a[j] * g;
+    }
+    F1 /= d; F2 /= d; Fs /= d; sEP /= d; sV /= d; sAg /= d;
+    if (type == ORC_ARITH) {
+        out[0] = D * (sEP - K * oracle_norm_cdf(-psi));
+        out[1] = D * sEP / S0;
+        /* sum_j E_j phi(beta_j - psi) a_j = phi(psi) sum_j a_j exp(alpha_j + beta_j psi) */
+        out[2] = D * (sV + phi0 * sAg);
+        out[3] = D * phi0 * K * K / (S0 * S0 * F1);
+    } else {
+        double psiS = -(K / S0) / F1;                  /* d psi / d S0 */
+        out[0] = D * oracle_norm_cdf(-psi);
+        out[1] = -D * phi0 * psiS;
+        out[2] = D * phi0 * Fs / F1;
+        out[3] = D * K * phi0 / (S0 * F1) * (-psi * psiS - 2.0 / S0 - F2 * psiS / F1);
+    }
+    free(al); free(be);
+    return 0;
+}
+
 /* Neumaier's compensated summation. */
 typedef struct { double s, c; } orc_sum;
 static void sum_add(orc_sum *a, double x)
@@ -358,10 +471,14 @@ int oracle_replication(int type, int d, double S0, double K, double r, double si
                        const uint32_t *V, const double *A, double *C_l, double *abs_sum)
 {
     if (d < 1 || N < 1 || k0 < 0) return -1;
+    if (path == ORC_PCA_FULL && (!A || (type != ORC_ARITH && type != ORC_BINARY))) return -1;
     int n = d - 1;
     double dt = T / d;
     double *z = (double *)malloc(sizeof(double) * (size_t)(n + 1));
-    double *W = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *W = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *a1 = (double *)malloc(sizeof(double) * (size_t)d);
+    if (path == ORC_PCA_FULL)   /* first column of the d x d factor */
+        for (int j = 0; j < d; ++j) a1[j] = A[(size_t)j * d];
     orc_sum acc[4], ab[4];
     memset(acc, 0, sizeof acc);
     memset(ab, 0, sizeof ab);
@@ -371,9 +488,19 @@ int oracle_replication(int type, int d, double S0, double K, double r, double si
             double u = ((double)y + 0.5) / 4294967296.0;
             z[j - 1] = oracle_norm_inv(u);
         }
-        oracle_build_path(path, n, dt, z, A, W);
         double F[4];
-        oracle_path_greeks(type, d, S0, K, r, sigma, T, W, F);
+        if (path == ORC_PCA_FULL) {
+            /* c_j = sum over components 2..d of A_{j,i} z_i */
+            for (int j = 0; j < d; ++j) {
+                double cj = 0.0;
+                for (int i = 1; i < d; ++i) cj += A[(size_t)j * d + i] * z[i - 1];
+                W[j] = cj;
+            }
+            oracle_path_greeks_full(type, d, S0, K, r, sigma, T, a1, W, F);
+        } else {
+            oracle_build_path(path, n, dt, z, A, W);
+            oracle_path_greeks(type, d, S0, K, r, sigma, T, W, F);
+        }
         for (int o = 0; o < 4; ++o) {
             sum_add(&acc[o], F[o]);
             sum_add(&ab[o], fabs(F[o]));
@@ -383,7 +510,7 @@ int oracle_replication(int type, int d, double S0, double K, double r, double si
         C_l[o] = sum_val(&acc[o]) / (double)N;
         if (abs_sum) abs_sum[o] += sum_val(&ab[o]);
     }
-    free(z); free(W);
+    free(z); free(W); free(a1);
     return 0;
 }
 
@@ -396,7 +523,10 @@ int oracle_option(int type, int d, double S0, double K, double r, double sigma,
     double *Cl = (double *)malloc(sizeof(double) * (size_t)L * 4);
     double absum[4] = {0, 0, 0, 0};
     for (int l = 0; l < L; ++l)
-        oracle_replication(type, d, S0, K, r, sigma, T, seed, 0, N, l, path, V, A, Cl + 4 * l, absum);
+        if (oracle_replication(type, d, S0, K, r, sigma, T, seed, 0, N, l, path, V, A, Cl + 4 * l, absum) != 0) {
+            free(Cl);
+            return -1;
+        }
     for (int o = 0; o < 4; ++o) {
         orc_sum s = {0, 0};
         for (int l = 0; l < L; ++l) sum_add(&s, Cl[l * 4 + o]);

@@ -361,6 +361,130 @@ def test_rqmc_estimate_agrees_with_quadrature_at_three_dates():
 
 
 # --------------------------------------------------------------------------
+# Conditioning on the first principal component of the full covariance
+# --------------------------------------------------------------------------
+
+def _full_path(d, T, rng):
+    A = oracle.pca_factor(d, T / d)
+    z = rng.standard_normal(d - 1)
+    return A[:, 0].copy(), A[:, 1:] @ z
+
+
+@pytest.mark.parametrize("S0,K,r,sig,T", [(100, 100, 0.05, 0.2, 1.0), (100, 90, 0.1, 0.2, 1.0),
+                                          (100, 120, 0.02, 0.4, 0.5)])
+def test_full_pca_one_date_is_black_scholes(S0, K, r, sig, T):
+    """d = 1 leaves only the conditioned component: the estimate is the
+    Black-Scholes call / cash-or-nothing digital and their Greeks."""
+    d1 = (math.log(S0 / K) + (r + sig**2 / 2) * T) / (sig * math.sqrt(T))
+    d2 = d1 - sig * math.sqrt(T)
+    D = math.exp(-r * T)
+    N, n = scipy.stats.norm.cdf, scipy.stats.norm.pdf
+    call = [S0 * N(d1) - K * D * N(d2), N(d1), S0 * math.sqrt(T) * n(d1), n(d1) / (S0 * sig * math.sqrt(T))]
+    dig = [D * N(d2), D * n(d2) / (S0 * sig * math.sqrt(T)), -D * n(d2) * d1 / sig,
+           -D * n(d2) * d1 / (S0 * S0 * sig * sig * T)]
+    for typ, ref in ((oracle.ARITH_ASIAN, call), (oracle.BINARY_ASIAN, dig)):
+        res = oracle.option(typ, 1, S0, K, r, sig, T, 99, 64, 2, oracle.PATH_PCA_FULL)
+        np.testing.assert_allclose(res["mean"], ref, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("d", [2, 5, 16, 64])
+def test_full_pca_root_matches_bracketing_solver(d):
+    rng = np.random.default_rng(d)
+    S0, r, sig, T = 100.0, 0.05, 0.3, 1.0
+    for K in (60.0, 100.0, 160.0):
+        a, c = _full_path(d, T, rng)
+        t = T / d * np.arange(1, d + 1)
+        al = math.log(S0) + (r - sig**2 / 2) * t + sig * c
+        be = sig * a
+        f = lambda x: np.mean(np.exp(al + be * x)) - K
+        ref = scipy.optimize.brentq(f, -80, 80, xtol=1e-15, rtol=1e-15)
+        assert abs(oracle.full_root(al, be, K) - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN])
+@pytest.mark.parametrize("d", [2, 7, 32])
+def test_full_pca_greeks_equal_finite_differences(typ, d):
+    """Per path, the pathwise delta, vega and gamma equal Richardson finite
+    differences of the conditional price with the other components fixed."""
+    rng = np.random.default_rng(31 * d + typ)
+    T, r = 1.0, 0.05
+    for trial in range(3):
+        a, c = _full_path(d, T, rng)
+        S0, K, sig = 100.0, [90.0, 100.0, 112.0][trial], [0.15, 0.25, 0.4][trial]
+        g = oracle.path_greeks_full(typ, d, S0, K, r, sig, T, a, c)
+
+        def rich(f, x, h):
+            A1 = (f(x + h) - f(x - h)) / (2 * h)
+            B1 = (f(x + h / 2) - f(x - h / 2)) / h
+            return (4 * B1 - A1) / 3
+
+        pr = lambda s0, sg: oracle.path_greeks_full(typ, d, s0, K, r, sg, T, a, c)
+        hS, hs = 1e-3 * S0 * sig, 1e-4
+        delta = rich(lambda s0: pr(s0, sig)[0], S0, hS)
+        vega = rich(lambda sg: pr(S0, sg)[0], sig, hs)
+        gamma = rich(lambda s0: pr(s0, sig)[1], S0, hS)
+        eps = np.finfo(float).eps
+        for got, fd, h, scale in ((g[1], delta, hS, abs(g[0]) + K), (g[2], vega, hs, abs(g[0]) + K),
+                                  (g[3], gamma, hS, abs(g[1]))):
+            assert abs(got - fd) <= 1e-6 * abs(fd) + 50 * eps * scale / h, (typ, d, got, fd)
+
+
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN])
+def test_full_pca_conditional_price_is_quadrature_of_payoff(typ):
+    """G = E[discounted payoff | other components]: integrate the original
+    payoff over the first component numerically and compare."""
+    S0, r, sig, T, d = 100.0, 0.05, 0.3, 1.0, 12
+    rng = np.random.default_rng(12 + typ)
+    t = T / d * np.arange(1, d + 1)
+    for K in (85.0, 100.0, 120.0):
+        a, c = _full_path(d, T, rng)
+        avg = lambda x: np.mean(S0 * np.exp((r - sig**2 / 2) * t + sig * (a * x + c)))
+        root = scipy.optimize.brentq(lambda x: avg(x) - K, -60, 60, xtol=1e-15, rtol=1e-15)
+        if typ == oracle.BINARY_ASIAN:
+            f = lambda x: math.exp(-r * T) * scipy.stats.norm.pdf(x)
+        else:
+            f = lambda x: math.exp(-r * T) * (avg(x) - K) * scipy.stats.norm.pdf(x)
+        val = scipy.integrate.quad(f, root, 40, epsabs=0, epsrel=1e-13, limit=200)[0]
+        g = oracle.path_greeks_full(typ, d, S0, K, r, sig, T, a, c)
+        assert abs(g[0] - val) <= 1e-10 * max(abs(val), 1e-12), (g[0], val)
+
+
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN])
+def test_full_pca_estimate_agrees_with_first_date_conditioning(typ):
+    """Two different conditional estimators of the same Greeks -- the first
+    principal component integrated out, or the first date's normal with a
+    bridge for the rest -- must agree within their standard errors."""
+    S0, K, r, sig, T, d = 100.0, 102.0, 0.05, 0.3, 1.0, 8
+    a = oracle.option(typ, d, S0, K, r, sig, T, 71, 1 << 13, 16, oracle.PATH_PCA_FULL)
+    b = oracle.option(typ, d, S0, K, r, sig, T, 72, 1 << 13, 16, oracle.PATH_BB)
+    for i in range(4):
+        tol = 4 * math.hypot(a["stderr"][i], b["stderr"][i]) + 1e-12 * abs(b["mean"][i])
+        assert abs(a["mean"][i] - b["mean"][i]) <= tol, (i, a["mean"], b["mean"])
+
+
+def test_full_pca_estimate_agrees_with_quadrature_at_two_dates():
+    """d = 2: one conditioned and one sampled component; E over the sampled
+    one by quadrature lies within 4 standard errors of the estimate."""
+    S0, K, r, sig, T, d = 100.0, 97.0, 0.04, 0.25, 1.0, 2
+    A = oracle.pca_factor(d, T / d)
+
+    def G(zz, i):
+        return oracle.path_greeks_full(oracle.ARITH_ASIAN, d, S0, K, r, sig, T, A[:, 0].copy(),
+                                       A[:, 1] * zz)[i] * scipy.stats.norm.pdf(zz)
+
+    ref = np.array([scipy.integrate.quad(G, -40, 40, args=(i,), epsabs=0, epsrel=1e-13, limit=200)[0]
+                    for i in range(4)])
+    res = oracle.option(oracle.ARITH_ASIAN, d, S0, K, r, sig, T, 5151, 1 << 12, 16, oracle.PATH_PCA_FULL)
+    for i in range(4):
+        assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-13 * abs(ref[i]), i
+
+
+def test_full_pca_rejects_lookback():
+    with pytest.raises(ValueError):
+        oracle.option(oracle.LOOKBACK, 8, 100.0, 100.0, 0.05, 0.2, 1.0, 1, 64, 2, oracle.PATH_PCA_FULL)
+
+
+# --------------------------------------------------------------------------
 # Reduction across replications (Sec. 5)
 # --------------------------------------------------------------------------
 
