@@ -47,12 +47,21 @@ enum {
 /* Product (Sec. 4.5.1 binary Asian, 4.5.2 arithmetic Asian, 4.5.3 lookback). */
 enum { QCPW_ARITH_ASIAN_CALL = 0, QCPW_BINARY_ASIAN_CALL = 1, QCPW_LOOKBACK_FIXED_CALL = 2 };
 
-/* Factor A of the d-1 Brownian coordinates (Sec. 3.4.1 and Sec. 4.4):
+/* Path construction.  The first three condition on the normal x_1 that
+ * drives W(t_1) (Sec. 3.4.2) and build the d-1 remaining coordinates with a
+ * factor A (Sec. 3.4.1 and Sec. 4.4):
  *  QCPW_PATH_BB       Brownian bridge: terminal value from the first normal,
  *                     then breadth-first midpoints, for any d (Sec. 4.4);
  *  QCPW_PATH_PCA      principal components of Sigma (largest first);
- *  QCPW_PATH_STANDARD left-to-right increments (Alg. 3).                    */
-enum { QCPW_PATH_BB = 0, QCPW_PATH_PCA = 1, QCPW_PATH_STANDARD = 2 };
+ *  QCPW_PATH_STANDARD left-to-right increments (Alg. 3).
+ *  QCPW_PATH_PCA_FULL principal components of the covariance of all d dates
+ *                     (W(t_j), j = 1..d); the first component (largest
+ *                     eigenvalue) is the conditioned variable instead of x_1
+ *                     -- the principal-component conditioning Sec. 6 names
+ *                     for larger variance reduction.  Its breakpoint needs a
+ *                     root-find (Newton, FP64).  Arithmetic and binary Asian
+ *                     calls only; d <= QCPW_MAX_D_PCA_FULL.                */
+enum { QCPW_PATH_BB = 0, QCPW_PATH_PCA = 1, QCPW_PATH_STANDARD = 2, QCPW_PATH_PCA_FULL = 3 };
 
 /* Arithmetic of the per-path work.  QCPW_FP64: everything in FP64.
  * QCPW_FP32_MIXED: inverse normal, path construction, exponentials and the
@@ -83,6 +92,7 @@ typedef struct {
 /* Limits. */
 #define QCPW_MAX_D 385          /* d - 1 <= 384 conditioned coordinates (BB, STANDARD) */
 #define QCPW_MAX_D_PCA 257      /* PCA factor padded to at most 256 x 256            */
+#define QCPW_MAX_D_PCA_FULL 256 /* full-covariance factor, d x d <= 256 x 256         */
 #define QCPW_MAX_SHIFTS 65535   /* replications per option                           */
 
 /*
@@ -91,7 +101,8 @@ typedef struct {
  * option_specs      host array [n_opts], read only, caller-owned.
  * n_opts            >= 1.
  * d                 monitoring dates for every option (1..QCPW_MAX_D, or up
- *                   to QCPW_MAX_D_PCA with PCA); 0 = use each spec's d.
+ *                   to QCPW_MAX_D_PCA with PCA, QCPW_MAX_D_PCA_FULL with
+ *                   PCA_FULL); 0 = use each spec's d.
  * n_points          Sobol points k = 0..n_points-1 per replication, in Gray
  *                   code order (1..2^32; powers of two recommended); 0 = use
  *                   each spec's n_points.
@@ -165,7 +176,9 @@ qcpw_status qcpw_sobol_points(uint64_t seed, int32_t shift_index, int32_t n_dims
 /*
  * qcpw_path_factor -- the factor A (row-major (d-1) x (d-1), FP64) that the
  * library uses for path_construction with d dates and maturity T, for
- * inspection (A A^T = Sigma).  out must hold (d-1)^2 doubles.
+ * inspection (A A^T = Sigma).  out must hold (d-1)^2 doubles; for
+ * QCPW_PATH_PCA_FULL it is the d x d factor of the covariance of all d dates
+ * (column 0 = the conditioned component) and out must hold d^2 doubles.
  */
 qcpw_status qcpw_path_factor(int32_t path_construction, int32_t d, double T, double *out);
 

@@ -21,12 +21,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqmccpw.so")
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK = 0, 1, 2
-PATH_BB, PATH_PCA, PATH_STANDARD = 0, 1, 2
+PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
 FP64, FP32_MIXED = 0, 1
 GEMM_FP32, GEMM_BF16X3 = 0, 1
 FLAG_GRAPH = 1
 OUTPUTS = ("price", "delta", "vega", "gamma")
-MAX_D, MAX_D_PCA = 385, 257
+MAX_D, MAX_D_PCA, MAX_D_PCA_FULL = 385, 257, 256
 
 STATUS = {0: "QCPW_OK", -1: "QCPW_EINVAL", -2: "QCPW_ENOMEM", -3: "QCPW_EDEVICE", -4: "QCPW_EDIMS",
           -5: "QCPW_EBUSY", -6: "QCPW_ECANCELLED", -7: "QCPW_ENOTFOUND"}
@@ -181,9 +181,11 @@ def sobol_points(seed: int, shift_index: int, n_dims: int, k0: int, count: int) 
 
 
 def path_factor(path: int, d: int, T: float) -> np.ndarray:
-    n = d - 1
-    out = np.zeros((max(n, 0), max(n, 0)))
-    _check(lib().qcpw_path_factor(path, d, T, out.ctypes.data if n > 0 else None))
+    """The factor A: (d-1) x (d-1), or d x d for PATH_PCA_FULL."""
+    m = d if path == PATH_PCA_FULL else d - 1
+    out = np.zeros((max(m, 0), max(m, 0)))
+    buf = out if m > 0 else np.zeros(1)
+    _check(lib().qcpw_path_factor(path, d, T, buf.ctypes.data))
     return out
 
 

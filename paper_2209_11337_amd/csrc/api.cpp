@@ -118,16 +118,30 @@ qcpw_status get_context(int device, Context **out)
 // kernels read: FP32 k-major At[k][row] (NP x NP, zero padded, NP = n rounded
 // up to 32), the same split as BF16 hi + lo in 16-wide k slabs
 // [k/16][row][16], and n x n FP64 row-major.
-qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out)
+qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out, bool full)
 {
     for (auto &p : ctx->pca)
-        if (p.n == n && p.dt == dt) {
+        if (p.n == n && p.dt == dt && p.full == full) {
             *out = &p;
             return QCPW_OK;
         }
-    std::vector<double> A;
-    build_pca_factor(n, dt, A);
-    const int NP = (n + 31) / 32 * 32;
+    // rows x n matrix the kernels multiply by the n sampled normals
+    std::vector<double> A, a1;
+    int rows = n;
+    if (full) {
+        std::vector<double> F;
+        rows = n + 1;
+        build_pca_factor(rows, dt, F);   // d x d, column 0 = conditioned component
+        A.assign((size_t)rows * n, 0.0);
+        a1.assign(rows, 0.0);
+        for (int j = 0; j < rows; ++j) {
+            a1[j] = F[(size_t)j * rows];
+            for (int k = 0; k < n; ++k) A[(size_t)j * n + k] = F[(size_t)j * rows + k + 1];
+        }
+    } else {
+        build_pca_factor(n, dt, A);
+    }
+    const int NP = (std::max(rows, 1) + 31) / 32 * 32;
     std::vector<float> At((size_t)NP * NP, 0.0f);
     std::vector<uint16_t> hi((size_t)NP * NP, 0), lo((size_t)NP * NP, 0);
     auto to_bf16 = [](float x) -> uint16_t {   // round to nearest even
@@ -142,7 +156,7 @@ qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out)
         memcpy(&x, &u, 4);
         return x;
     };
-    for (int row = 0; row < n; ++row)
+    for (int row = 0; row < rows; ++row)
         for (int k = 0; k < n; ++k) {
             const float a = (float)A[(size_t)row * n + k];
             At[(size_t)k * NP + row] = a;
@@ -155,8 +169,14 @@ qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out)
     p.n = n;
     p.dt = dt;
     p.np = NP;
+    p.full = full;
+    if (A.empty()) A.assign(1, 0.0);
     QCPW_HIP(hipMalloc(&p.At, At.size() * 4));
     QCPW_HIP(hipMalloc(&p.A64, A.size() * 8));
+    if (full) {
+        QCPW_HIP(hipMalloc(&p.a1, a1.size() * 8));
+        QCPW_HIP(hipMemcpy(p.a1, a1.data(), a1.size() * 8, hipMemcpyHostToDevice));
+    }
     QCPW_HIP(hipMalloc(&p.Ahi, hi.size() * 2));
     QCPW_HIP(hipMalloc(&p.Alo, lo.size() * 2));
     QCPW_HIP(hipMemcpy(p.At, At.data(), At.size() * 4, hipMemcpyHostToDevice));
@@ -397,13 +417,16 @@ qcpw_status qcpw_path_factor(int32_t path_construction, int32_t d, double T, dou
     g_last_error.clear();
     if (!out) return fail(QCPW_EINVAL, "out is NULL");
     if (path_construction != QCPW_PATH_BB && path_construction != QCPW_PATH_PCA &&
-        path_construction != QCPW_PATH_STANDARD)
+        path_construction != QCPW_PATH_STANDARD && path_construction != QCPW_PATH_PCA_FULL)
         return fail(QCPW_EINVAL, "unknown path_construction");
-    const int dmax = path_construction == QCPW_PATH_PCA ? QCPW_MAX_D_PCA : QCPW_MAX_D;
+    const int dmax = path_construction == QCPW_PATH_PCA        ? QCPW_MAX_D_PCA
+                     : path_construction == QCPW_PATH_PCA_FULL ? QCPW_MAX_D_PCA_FULL
+                                                               : QCPW_MAX_D;
     if (d < 1 || d > dmax) return fail(QCPW_EDIMS, "d out of range");
     if (!(T > 0) || !std::isfinite(T)) return fail(QCPW_EINVAL, "T must be finite and > 0");
     std::vector<double> A;
-    build_factor(path_construction, d - 1, T / d, A);
+    if (path_construction == QCPW_PATH_PCA_FULL) build_pca_factor(d, T / d, A);
+    else build_factor(path_construction, d - 1, T / d, A);
     if (!A.empty()) memcpy(out, A.data(), A.size() * sizeof(double));
     return QCPW_OK;
 }

@@ -466,14 +466,17 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
     if (!specs) return fail(QCPW_EINVAL, "option_specs is NULL");
     if (n_opts < 1) return fail(QCPW_EINVAL, "n_opts must be >= 1");
     if (n_shifts < 1 || n_shifts > QCPW_MAX_SHIFTS) return fail(QCPW_EINVAL, "n_shifts out of range");
-    if (path != QCPW_PATH_BB && path != QCPW_PATH_PCA && path != QCPW_PATH_STANDARD)
+    if (path != QCPW_PATH_BB && path != QCPW_PATH_PCA && path != QCPW_PATH_STANDARD &&
+        path != QCPW_PATH_PCA_FULL)
         return fail(QCPW_EINVAL, "unknown path_construction");
     if (precision != QCPW_FP64 && precision != QCPW_FP32_MIXED) return fail(QCPW_EINVAL, "unknown precision");
     if (pca_gemm != QCPW_GEMM_FP32 && pca_gemm != QCPW_GEMM_BF16X3) return fail(QCPW_EINVAL, "unknown pca_gemm");
     if (!qcpw_block_threads_ok(block_threads))
         return fail(QCPW_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
     if (d < 0 || n_points < 0) return fail(QCPW_EINVAL, "negative d or n_points");
-    const int dmax = path == QCPW_PATH_PCA ? QCPW_MAX_D_PCA : QCPW_MAX_D;
+    const int dmax = path == QCPW_PATH_PCA        ? QCPW_MAX_D_PCA
+                     : path == QCPW_PATH_PCA_FULL ? QCPW_MAX_D_PCA_FULL
+                                                  : QCPW_MAX_D;
     for (int i = 0; i < n_opts; ++i) {
         const qcpw_option_spec &sp = specs[i];
         const int di = d ? d : sp.d;
@@ -481,6 +484,10 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
         if (sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL &&
             sp.type != QCPW_LOOKBACK_FIXED_CALL)
             return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": unknown type");
+        if (path == QCPW_PATH_PCA_FULL && sp.type == QCPW_LOOKBACK_FIXED_CALL)
+            return fail(QCPW_EINVAL, "option " + std::to_string(i) +
+                                         ": conditioning on the first principal component covers "
+                                         "arithmetic and binary Asian calls only");
         if (di < 1) return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": d must be >= 1");
         if (di > dmax)
             return fail(QCPW_EDIMS, "option " + std::to_string(i) + ": d = " + std::to_string(di) +
@@ -540,7 +547,8 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.seed = sp.seed;
         op.n_shifts = n_shifts;
         op.out_index = i;
-        op.unit_pts = (int32_t)(path == QCPW_PATH_PCA ? QCPW_CHUNK : qcpw_unit_points(Ni));
+        const bool pca_like = path == QCPW_PATH_PCA || path == QCPW_PATH_PCA_FULL;
+        op.unit_pts = (int32_t)(pca_like ? QCPW_CHUNK : qcpw_unit_points(Ni));
         op.chunks = (int32_t)((Ni + op.unit_pts - 1) / op.unit_pts);
         op.plan_off = (path == QCPW_PATH_BB && op.n >= 1) ? ctx->tab.plan_off[op.n] : 0;
         const double LOG2E = 1.4426950408889634074;
@@ -591,20 +599,26 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
     lp.order = order;
     lp.total_units = lp.unit_prefix[n_opts];
     lp.block_threads = block_threads ? block_threads : autotune_block_threads(ctx, lp);
-    if (path == QCPW_PATH_PCA) {
+    if (path == QCPW_PATH_PCA || path == QCPW_PATH_PCA_FULL) {
+        const bool full = path == QCPW_PATH_PCA_FULL;
         lp.pca.resize(n_opts, nullptr);
         for (int i = 0; i < n_opts; ++i) {
-            if (lp.opts[i].n == 0) continue;
+            if (lp.opts[i].n == 0 && !full) continue;
             const Context::Pca *pc = nullptr;
-            qcpw_status st = get_pca(ctx, lp.opts[i].n, 1.0, &pc);
+            qcpw_status st = get_pca(ctx, lp.opts[i].n, 1.0, &pc, full);
             if (st != QCPW_OK) return st;
             lp.pca[i] = pc;
             lp.opts[i].pca_At = pc->At;
             lp.opts[i].pca_hi = pc->Ahi;
             lp.opts[i].pca_lo = pc->Alo;
             lp.opts[i].pca_A64 = pc->A64;
+            lp.opts[i].pca_a1 = pc->a1;
             lp.opts[i].pca_np = pc->np;
         }
+        // FP64 PCA_FULL keeps each tile's d x 64 products in a global scratch
+        // tile per workgroup (they do not fit in LDS beside the FP64 normals)
+        if (full && precision == QCPW_FP64)
+            lp.full_blocks = std::min<int64_t>((int64_t)2 * std::max(ctx->tab.n_cu, 1), lp.total_units);
     }
     return QCPW_OK;
 }
@@ -612,7 +626,7 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct WsLayout {
-    size_t opts, prefix, partials, per_shift, counter, total;
+    size_t opts, prefix, partials, per_shift, counter, scratch, total;
 };
 
 static WsLayout ws_layout(const LaunchPlan &lp)
@@ -624,7 +638,8 @@ static WsLayout ws_layout(const LaunchPlan &lp)
     w.partials = align_up(w.prefix + (n + 1) * sizeof(int64_t), 256);
     w.per_shift = align_up(w.partials + (size_t)lp.total_units * 8 * sizeof(double), 256);
     w.counter = align_up(w.per_shift + n * (size_t)lp.n_shifts * 4 * sizeof(double), 256);
-    w.total = align_up(w.counter + 256, 256);
+    w.scratch = align_up(w.counter + 256, 256);
+    w.total = align_up(w.scratch + (size_t)lp.full_blocks * 64 * QCPW_MAX_D_PCA_FULL * sizeof(double), 256);
     return w;
 }
 
@@ -684,7 +699,7 @@ static int resident_waves(const LaunchPlan &lp, int bd)
 // overrides the choice.  Only the order of floating-point sums depends on it.
 int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
 {
-    if (lp.path == QCPW_PATH_PCA) return 256;
+    if (lp.path == QCPW_PATH_PCA || lp.path == QCPW_PATH_PCA_FULL) return 256;
     if (const char *env = getenv("QCPW_BLOCK_THREADS")) {
         const int v = atoi(env);
         if (v != 0 && qcpw_block_threads_ok(v) && resident_waves(lp, v) > 0) return v;
@@ -806,8 +821,9 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
     ld.lane = ctx->tab.lane;
     ld.partials = d_partials;
     ld.counter = d_counter;
+    ld.scratch = (double *)(base + w.scratch);
 
-    if (lp.path == QCPW_PATH_PCA) {
+    if (lp.path == QCPW_PATH_PCA || lp.path == QCPW_PATH_PCA_FULL) {
         if (t0) QCPW_HIP(hipEventRecord(t0, stream));
         qcpw_status st = enqueue_pca(ctx, lp, stream, ld, d_opts);
         if (st != QCPW_OK) return st;

@@ -157,9 +157,124 @@ __device__ inline void tile_tail(const OptDev &op, const PcaSums<R> *red, int la
 }
 
 // ------------------------------------------------------------------------
+// Conditioning on the first principal component of all d dates (PCA_FULL)
+// ------------------------------------------------------------------------
+// One point's FP64 tail, shared by the four threads part = 0..3 of a quad of
+// consecutive lanes; thread `part` takes the dates j = part (mod 4).  y(j)
+// is date j's row of the factor (first column dropped) times the scaled
+// normals, i.e. log2(e) sigma c_j, so that
+//     ln S(t_j) = alpha_j + beta_j x,  alpha_j = ln S0 + omega t_j + sigma c_j,
+//     beta_j = sigma sqrt(dt) a1_j
+// in the conditioned component x.  The breakpoint psi solves
+// (1/d) sum_j exp(alpha_j + beta_j psi) = K: Newton's method on the log of
+// the sum, which is increasing and convex in x, started at the Jensen bound
+// (to the right of the root), so the iterates decrease to the root.  Price,
+// delta, vega and gamma then follow in closed form (arithmetic: the terms in
+// d psi cancel at the root; binary: through d psi = -dF / F').
+template <typename YF>
+__device__ inline void full_point_tail(const OptDev &op, YF y, int part, double F[4])
+{
+    constexpr double LN2 = 0.69314718055994530942;
+    const int d = op.n + 1;
+    const double sig = 1.0 / op.inv_sigma;
+    const double sdt = op.zscale * LN2;     // sigma sqrt(dt)
+    const double wdt = op.ydrift_1 * LN2;   // omega dt
+    const double dt = op.sqrt_t1 * op.sqrt_t1;
+    const double lnS0 = log(op.S0), K = op.K;
+    const double *a1 = op.pca_a1;
+    auto quad_sum = [](double v) {          // the same bits in all four threads
+        v += __shfl_xor(v, 1, 64);
+        return v + __shfl_xor(v, 2, 64);
+    };
+    double sa = 0.0, sb = 0.0;
+    for (int j = part; j < d; j += 4) {
+        sa += lnS0 + wdt * (j + 1) + LN2 * y(j);
+        sb += sdt * a1[j];
+    }
+    sa = quad_sum(sa);
+    sb = quad_sum(sb);
+    double x = (log(K) - sa / d) / (sb / d);
+    const double lndk = log(K * d);
+    for (int it = 0; it < 64; ++it) {
+        double S = 0.0, S1 = 0.0;
+        for (int j = part; j < d; j += 4) {
+            const double be = sdt * a1[j];
+            const double g = exp(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x);
+            S += g;
+            S1 += be * g;
+        }
+        S = quad_sum(S);
+        S1 = quad_sum(S1);
+        const double dx = (log(S) - lndk) * S / S1;
+        x -= dx;
+        if (!(fabs(dx) > 1e-12 * (1.0 + fabs(x)))) break;   // also ends on NaN
+    }
+    const double psi = x;
+    const bool arith = op.type == QCPW_ARITH_ASIAN_CALL;
+    double F1 = 0.0, F2 = 0.0, Fs = 0.0, sEP = 0.0, sV = 0.0, sAg = 0.0;
+    for (int j = part; j < d; j += 4) {
+        const double yj = y(j);
+        const double al = lnS0 + wdt * (j + 1) + LN2 * yj, be = sdt * a1[j];
+        const double a = be / sig;                                // first-column entry, W units
+        const double das = LN2 * yj / sig - sig * dt * (j + 1);   // c_j - sigma t_j
+        const double g = exp(al + be * psi);
+        F1 += be * g;
+        if (arith) {
+            const double EP = exp(al + 0.5 * be * be) * 0.5 * erfc((psi - be) * M_SQRT1_2);
+            sEP += EP;
+            sV += EP * (das + be * a);
+            sAg += a * g;
+        } else {
+            F2 += be * be * g;
+            Fs += g * (das + psi * a);
+        }
+    }
+    F1 = quad_sum(F1) / d;
+    const double D = op.D, S0 = op.S0;
+    const double phi0 = exp(-0.5 * psi * psi) * 0.39894228040143267794;
+    if (arith) {
+        sEP = quad_sum(sEP) / d;
+        sV = quad_sum(sV) / d;
+        sAg = quad_sum(sAg) / d;
+        F[0] = D * (sEP - K * 0.5 * erfc(psi * M_SQRT1_2));
+        F[1] = D * sEP / S0;
+        F[2] = D * (sV + phi0 * sAg);
+        F[3] = D * phi0 * K * K / (S0 * S0 * F1);
+    } else {
+        F2 = quad_sum(F2) / d;
+        Fs = quad_sum(Fs) / d;
+        const double psiS = -(K / S0) / F1;   // d psi / d S0
+        F[0] = D * 0.5 * erfc(psi * M_SQRT1_2);
+        F[1] = -D * phi0 * psiS;
+        F[2] = D * phi0 * Fs / F1;
+        F[3] = D * K * phi0 / (S0 * F1) * (-psi * psiS - 2.0 / S0 - F2 * psiS / F1);
+    }
+}
+
+// The four threads of point p = tid / 4 run full_point_tail; quad leader
+// writes F to Fb[p][4]; wave 0, lane p, adds valid points into its sums.
+template <typename YF>
+__device__ inline void full_tile_tail(const OptDev &op, YF y_of, double *Fb, int tid, int lane, int wave,
+                                      bool lane_valid_for_wave0, double (&s)[4], double (&c)[4])
+{
+    const int p = tid >> 2, part = tid & 3;
+    double F[4];
+    full_point_tail(op, [&](int j) { return y_of(p, j); }, part, F);
+    if (part == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Fb[p * 4 + k] = F[k];
+    }
+    __syncthreads();
+    if (wave == 0 && lane_valid_for_wave0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc_add(s[k], c[k], Fb[lane * 4 + k]);
+    }
+}
+
+// ------------------------------------------------------------------------
 // FP32-mixed: matrix-core GEMM
 // ------------------------------------------------------------------------
-template <bool BF16X3>
+template <bool BF16X3, bool FULL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void pca_f32_kernel(const OptDev *__restrict__ opts,
                                                       const int64_t *__restrict__ unit_prefix,
                                                       const uint32_t *__restrict__ dir,
@@ -193,16 +308,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const int64_t t0 = op.k_begin + chunk * op.unit_pts;
         const int64_t t1 = min(t0 + (int64_t)op.unit_pts, k_end);
 
-        // padding columns of Z (k = n .. NP-1) must hold zeros
-        for (int i = tid; i < TP * (NP - n); i += blockDim.x) {
-            const int p = i / (NP - n), k = n + i % (NP - n);
-            if (BF16X3) {
-                Zh[p * zstride + k] = 0;
-                Zl[p * zstride + k] = 0;
-            } else {
-                Zf[p * zstride + k] = 0.0f;
+        // padding columns of Z (k = n .. NP-1) must hold zeros (also after a
+        // PCA_FULL epilogue has used the Z area for the products)
+        auto zero_padding = [&] {
+            for (int i = tid; i < TP * (NP - n); i += blockDim.x) {
+                const int p = i / (NP - n), k = n + i % (NP - n);
+                if (BF16X3) {
+                    Zh[p * zstride + k] = 0;
+                    Zl[p * zstride + k] = 0;
+                } else {
+                    Zf[p * zstride + k] = 0.0f;
+                }
             }
-        }
+        };
+        zero_padding();
         const int myj = 1 + 64 * wave + lane;   // dimension whose uniform part this lane holds
         uint32_t U = 0;
         if (myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
@@ -276,6 +395,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 }
             }
 
+            if constexpr (FULL) {
+                // ---- epilogue: the d products of each point into LDS (over Z),
+                // then the FP64 root-find and Greeks, four threads per point
+                const int cstride = NP + 1;
+                float *Cb = (float *)smem;
+                __syncthreads();   // every wave is done reading Z
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int t = wave + 4 * q;
+                    if (t < nblocks) {
+                        const int rb = t >> 1;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int row = rb * 32 + (r >> 2) * 8 + khalf * 4 + (r & 3);
+                            if (row <= n) Cb[col * cstride + row] = acc[q][r];
+                        }
+                    }
+                }
+                __syncthreads();
+                full_tile_tail(op, [&](int p, int j) { return (double)Cb[p * cstride + j]; }, (double *)red, tid,
+                               lane, wave, base + lane < t1, s, c);
+                __syncthreads();
+                zero_padding();   // the next tile's prologue writes columns 0..n-1 only
+                continue;
+            }
             // ---- epilogue: exp2 and path sums over this lane's rows of its point
             PcaSums<float> ps;
             sums_neutral(ps);
@@ -322,18 +466,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 // ------------------------------------------------------------------------
 // FP64: the same tiles with Z^T in FP64 and FP64 FMAs
 // ------------------------------------------------------------------------
+template <bool FULL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void pca_f64_kernel(const OptDev *__restrict__ opts,
                                                       const int64_t *__restrict__ unit_prefix,
                                                       const uint32_t *__restrict__ dir,
                                                       const uint32_t *__restrict__ lane_tab,
                                                       double *__restrict__ partials,
                                                       unsigned long long *__restrict__ counter, int n_opts,
-                                                      int n_max, long long total_units)
+                                                      int n_max, long long total_units,
+                                                      double *__restrict__ scratch)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_unit;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int zstride = n_max + 1;
+    // PCA_FULL: this workgroup's [date][64] products (global, L2-resident)
+    double *Cg = scratch + (size_t)blockIdx.x * QCPW_MAX_D_PCA_FULL * TP;
     double *Z = (double *)smem;                                              // [TP][n_max + 1]
     PcaSums<double> *red = (PcaSums<double> *)(smem + (size_t)TP * zstride * 8);   // [4][TP]
 
@@ -371,23 +519,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             PcaSums<double> ps;
             sums_neutral(ps);
             const double drift = op.ydrift_1;
-            for (int m0 = wave; m0 < n; m0 += 16) {
+            const int rows = FULL ? n + 1 : n;
+            for (int m0 = wave; m0 < rows; m0 += 16) {
                 double acc[4] = {0.0, 0.0, 0.0, 0.0};
                 const double *A0 = op.pca_A64 + (size_t)m0 * n;
                 for (int i = 0; i < n; ++i) {
                     const double z = Z[lane * zstride + i];
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (m0 + 4 * q < n) acc[q] = fma(A0[(size_t)4 * q * n + i], z, acc[q]);
+                        if (m0 + 4 * q < rows) acc[q] = fma(A0[(size_t)4 * q * n + i], z, acc[q]);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int m = m0 + 4 * q;
-                    if (m < n) {
-                        const double mf = (double)(m + 1);
-                        sums_add_date<double>(ps, fma(drift, mf, acc[q]), mf);
+                    if (m < rows) {
+                        if (FULL) {
+                            Cg[(size_t)m * TP + lane] = acc[q];
+                        } else {
+                            const double mf = (double)(m + 1);
+                            sums_add_date<double>(ps, fma(drift, mf, acc[q]), mf);
+                        }
                     }
                 }
+            }
+            if constexpr (FULL) {
+                __syncthreads();
+                full_tile_tail(op, [&](int p, int j) { return Cg[(size_t)j * TP + p]; }, (double *)red, tid, lane,
+                               wave, base + lane < t1, s, c);
+                __syncthreads();
+                continue;
             }
             red[wave * TP + lane] = ps;
             __syncthreads();
@@ -425,14 +585,18 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
     const void *fn;
     size_t lds;
     int extra;
+    const bool full = lp.path == QCPW_PATH_PCA_FULL;
     if (lp.precision == QCPW_FP64) {
-        fn = reinterpret_cast<const void *>(&pca_f64_kernel);
+        fn = full ? reinterpret_cast<const void *>(&pca_f64_kernel<true>)
+                  : reinterpret_cast<const void *>(&pca_f64_kernel<false>);
         lds = (size_t)TP * (n_max + 1) * 8 + (size_t)PCA_WAVES * TP * sizeof(PcaSums<double>);
         extra = n_max;
     } else {
         const bool bf = lp.pca_gemm == QCPW_GEMM_BF16X3;
-        fn = bf ? reinterpret_cast<const void *>(&pca_f32_kernel<true>)
-                : reinterpret_cast<const void *>(&pca_f32_kernel<false>);
+        fn = bf ? (full ? reinterpret_cast<const void *>(&pca_f32_kernel<true, true>)
+                        : reinterpret_cast<const void *>(&pca_f32_kernel<true, false>))
+                : (full ? reinterpret_cast<const void *>(&pca_f32_kernel<false, true>)
+                        : reinterpret_cast<const void *>(&pca_f32_kernel<false, false>));
         const size_t z = bf ? (size_t)2 * TP * (np_max + 8) * 2 : (size_t)TP * (np_max + 1) * 4;
         lds = (z + 15) / 16 * 16 + (size_t)PCA_WAVES * TP * sizeof(PcaSums<float>);
         extra = np_max;
@@ -444,6 +608,10 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
     QCPW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds));
     if (per_cu < 1) return fail(QCPW_EDEVICE, "PCA kernel cannot be resident");
     int64_t grid = std::min<int64_t>((int64_t)per_cu * ctx->tab.n_cu, lp.total_units);
+    if (full && lp.precision == QCPW_FP64) {
+        if (lp.full_blocks < 1) return fail(QCPW_EDEVICE, "PCA_FULL scratch was not planned");
+        grid = std::min<int64_t>(grid, lp.full_blocks);   // one scratch tile per workgroup
+    }
     const OptDev *a_opts = ld.opts;
     const int64_t *a_prefix = ld.unit_prefix;
     const uint32_t *a_dir = ld.dir, *a_lane = ld.lane;
@@ -451,8 +619,11 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
     unsigned long long *a_ctr = ld.counter;
     int a_nopts = ld.n_opts;
     long long a_total = ld.total_units;
-    void *args[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_part, &a_ctr, &a_nopts, &extra, &a_total};
-    QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
+    double *a_scratch = ld.scratch;
+    void *args32[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_part, &a_ctr, &a_nopts, &extra, &a_total};
+    void *args64[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_part, &a_ctr, &a_nopts, &extra, &a_total, &a_scratch};
+    QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), lp.precision == QCPW_FP64 ? args64 : args32, lds,
+                             stream));
     return QCPW_OK;
 }
 

@@ -60,8 +60,11 @@ struct Context {
     hipEvent_t ws_done = nullptr;   // recorded after the last launch that used ws
     bool ws_pending = false;
     // PCA factors, keyed by (n, dt bits)
-    struct Pca { int n; double dt; int np; float *At = nullptr; double *A64 = nullptr;
-                 uint16_t *Ahi = nullptr, *Alo = nullptr; };
+    // full = false: the n x n factor of the d - 1 coordinates after x_1;
+    // full = true: the d x d factor of all d dates without its first column
+    // (rows = dates, n = d - 1 columns), plus that first column a1 (FP64).
+    struct Pca { int n; double dt; int np; bool full = false; float *At = nullptr; double *A64 = nullptr;
+                 uint16_t *Ahi = nullptr, *Alo = nullptr; double *a1 = nullptr; };
     std::deque<Pca> pca;     // deque: pointers stay valid as factors are added
     std::map<int, int> tuned;   // autotuned workgroup size per (path, precision, n bucket)
     // captured launch graphs (QCPW_FLAG_GRAPH), keyed by the call's argument bytes
@@ -80,7 +83,7 @@ struct Context {
 };
 
 qcpw_status get_context(int device, Context **out);
-qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out);
+qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out, bool full = false);
 
 // ---- launches (kernels.hip) -------------------------------------------------
 struct LaunchPlan {
@@ -96,7 +99,8 @@ struct LaunchPlan {
     int n_shifts = 0;
     int block_threads = 0;
     int64_t total_units = 0;
-    std::vector<const Context::Pca *> pca;   // per sorted option (PCA only)
+    int64_t full_blocks = 0;           // PCA_FULL in FP64: workgroups with a global scratch tile
+    std::vector<const Context::Pca *> pca;   // per sorted option (PCA and PCA_FULL)
 };
 
 // Argument checks of a Greeks call (host only, no device needed).

@@ -166,8 +166,9 @@ struct OptDev {
     const float *pca_At;          // [NP][NP] FP32, k-major: At[k][row]
     const uint16_t *pca_hi;       // [NP/16][NP][16] BF16 hi part, 16-wide k slabs
     const uint16_t *pca_lo;       // same, lo part
-    const double *pca_A64;        // [n][n] FP64 row-major
-    int32_t pca_np;               // n rounded up to a multiple of 32 (<= QCPW_PCA_NPAD)
+    const double *pca_A64;        // [n][n] FP64 row-major ([d][n] for PCA_FULL)
+    const double *pca_a1;         // PCA_FULL: first column of the d x d unit-dt factor
+    int32_t pca_np;               // rows / columns padded to a multiple of 32 (<= QCPW_PCA_NPAD)
     int32_t pad_;
 };
 
@@ -183,5 +184,6 @@ struct LaunchDesc {
     const uint32_t *dir;          // [QCPW_TAB_DIMS][32]
     const uint32_t *lane;         // [QCPW_TAB_DIMS][64]
     double *partials;             // [total_units][8]
+    double *scratch;              // FP64 PCA_FULL: [workgroup][date][64] products
     unsigned long long *counter;  // work-queue head
 };

@@ -106,6 +106,29 @@ def test_bridge_plan_every_size():
         assert np.abs(A @ z - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), d
 
 
+@pytest.mark.parametrize("d", [1, 2, 17, 64, 256])
+def test_library_full_pca_factor_matches_oracle(d):
+    """The d x d factor of all dates (first column = conditioned component)."""
+    T = 0.8
+    A = q.path_factor(q.PATH_PCA_FULL, d, T)
+    ref = oracle.pca_factor(d, T / d)
+    assert A.shape == (d, d)
+    assert np.abs(A - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    assert (A[:, 0] > 0).all()
+
+
+def test_full_pca_argument_checks():
+    o = dict(type=0, d=16, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, seed=1, n_points=64)
+    with pytest.raises(q.QcpwError) as ei:
+        q.greeks([dict(o, type=2)], 4, q.PATH_PCA_FULL)
+    assert ei.value.status == -1 and "Asian" in str(ei.value)
+    with pytest.raises(q.QcpwError) as ei:
+        q.greeks([dict(o, d=257)], 4, q.PATH_PCA_FULL)
+    assert ei.value.status == -4
+    with pytest.raises(q.QcpwError):
+        q.path_factor(q.PATH_PCA_FULL, 257, 1.0)
+
+
 def test_kernel_timer_argument_checks():
     for op in (0, 4, -1):
         with pytest.raises(q.QcpwError) as ei:

@@ -279,6 +279,63 @@ def test_pca_full_size_properties():
 
 
 # ------------------------------------------------------------------------
+# conditioning on the first principal component of all d dates
+# ------------------------------------------------------------------------
+def _asians(opts):
+    return [o for o in opts if o["type"] != workloads.LOOKBACK]
+
+
+@pytest.mark.parametrize("d,pts,step", [(1, 8192 + 150, 3), (2, 8192 + 150, 3), (16, 8192 + 150, 3),
+                                        (63, 8192 + 150, 3), (256, 4096 + 100, 6)])
+def test_fp64_pca_full_parity(d, pts, step):
+    opts = _asians(workloads.three_products_grid(d=d, n_points=pts))[::step]
+    say("pca_full fp64", d, len(opts))
+    g, e, ps = q.greeks(opts, 2, q.PATH_PCA_FULL, q.FP64, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_PCA_FULL)
+    assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
+    assert_scaled(g, m, am, TOL64, "mean")
+
+
+@pytest.mark.parametrize("gemm,tol", [(q.GEMM_FP32, FP32_TOL), (q.GEMM_BF16X3, BF16X3_TOL)])
+@pytest.mark.parametrize("d", [17, 64, 256])
+def test_pca_full_matrix_cores_within_bound(gemm, tol, d):
+    opts = _asians(workloads.three_products_grid(d=d, n_points=4096 + 100))[::3 if d < 256 else 6]
+    say("pca_full mfma", gemm, d)
+    g, e, ps = q.greeks(opts, 2, q.PATH_PCA_FULL, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_PCA_FULL)
+    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    say("pca_full scaled error", gemm, d, err.max(axis=(0, 1)))
+    for k in range(4):
+        assert err[..., k].max() <= tol[k], (k, err[..., k].max())
+
+
+def test_pca_full_large_properties():
+    """d = 256, 2^20 points x 8 shifts: the matrix-core results agree with
+    the FP64 path at the same points within their bounds and the standard
+    errors match the spread of the replications; one replication of 2^16
+    points (eight work units) is recomputed by the oracle."""
+    opts = workloads.pca_pair(d=256, n_points=1 << 20)
+    say("pca_full large fp64")
+    g64, e64, p64 = q.greeks(opts, 8, q.PATH_PCA_FULL, q.FP64, per_shift=True)
+    o1 = [oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["seed"], 512, 1,
+                        oracle.PATH_PCA_FULL)["abs_mean"] for o in opts]
+    scale = np.array(o1)
+    mid = dict(opts[1], n_points=1 << 16)
+    _, _, pm = q.greeks([mid], 8, q.PATH_PCA_FULL, q.FP64, per_shift=True)
+    ref = oracle.replication(mid, 5, oracle.PATH_PCA_FULL)
+    assert_scaled(pm[0, 5], ref, scale[1], TOL64, "replication 5 of the binary Asian, 2^16 points")
+    for gemm, tol in [(q.GEMM_FP32, FP32_TOL), (q.GEMM_BF16X3, BF16X3_TOL)]:
+        say("pca_full large", gemm)
+        g, e, ps = q.greeks(opts, 8, q.PATH_PCA_FULL, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+        err = np.abs(ps - p64) / np.maximum(np.abs(p64), scale[:, None, :])
+        say("pca_full large scaled diff", gemm, err.max(axis=(0, 1)))
+        for k in range(4):
+            assert err[..., k].max() <= tol[k]
+        se = ps.std(axis=1, ddof=1) / np.sqrt(8)
+        assert np.allclose(se, e, rtol=1e-9, atol=1e-300)
+
+
+# ------------------------------------------------------------------------
 # serving: continuous batching
 # ------------------------------------------------------------------------
 def test_server_results_match_direct_calls_and_overlap():
