@@ -244,6 +244,25 @@ def pca_leg(q, workloads, torch, steps=3):
         res[name] = {"value": paths / wall, "unit": "Greek-paths/s", "kernel_ms": k_ms,
                      "gemm_tflops": gflop / (k_ms * 1e-3) / 1e12,
                      "gemm_frac": gflop / (k_ms * 1e-3) / peak}
+        if gemm == q.GEMM_FP32:
+            se_x1 = out[1].cpu().numpy().copy()
+    # the same points conditioned on the first principal component of all d
+    # dates (FP64 Newton root-find per path): time, and the variance ratio of
+    # each Greek against conditioning on the first date's normal
+    q.greeks(opts, L, q.PATH_PCA_FULL, q.FP32_MIXED, device_outputs=True, out=out, stream=s)
+    s.synchronize()
+    q.kernel_timer(q.TIMER_START)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        q.greeks(opts, L, q.PATH_PCA_FULL, q.FP32_MIXED, device_outputs=True, out=out, stream=s)
+    s.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
+    se_full = out[1].cpu().numpy()
+    res["pca_full_fp32_mfma"] = {
+        "value": paths / wall, "unit": "Greek-paths/s", "kernel_ms": k_ms / max(k_n, 1),
+        "variance_ratio_vs_first_date": {k: [float((se_x1[i, j] / se_full[i, j]) ** 2) for i in range(2)]
+                                         for j, k in enumerate(q.OUTPUTS)}}
     return res
 
 
