@@ -35,6 +35,7 @@ _lib = None
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK = 0, 1, 2
 PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
+RAND_SHIFT, RAND_OWEN = 0, 1
 OUTPUTS = ("price", "delta", "vega", "gamma")
 
 
@@ -79,17 +80,20 @@ def _load():
             lib.oracle_full_root.restype = C.c_double
             lib.oracle_path_greeks_full.argtypes = [C.c_int, C.c_int] + [C.c_double] * 5 + [f64p, f64p, f64p]
             lib.oracle_path_greeks_full.restype = C.c_int
+            lib.oracle_owen.argtypes = [C.c_uint32, C.c_uint32]
+            lib.oracle_owen.restype = C.c_uint32
             lib.oracle_option.argtypes = ([C.c_int, C.c_int] + [C.c_double] * 5 +
-                                          [C.c_uint64, C.c_int64, C.c_int, C.c_int, u32p, C.c_void_p,
+                                          [C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, u32p, C.c_void_p,
                                            C.c_void_p, f64p, f64p, f64p])
             lib.oracle_option.restype = C.c_int
             lib.oracle_replication.argtypes = ([C.c_int, C.c_int] + [C.c_double] * 5 +
-                                               [C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int, u32p,
-                                                C.c_void_p, f64p, C.c_void_p])
+                                               [C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                                u32p, C.c_void_p, f64p, C.c_void_p])
             lib.oracle_replication.restype = C.c_int
             lib.oracle_options.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                           C.c_int, C.c_int, u32p, C.c_void_p, f64p, f64p, f64p, C.c_int]
+                                           C.c_int, C.c_int, C.c_int, u32p, C.c_void_p, f64p, f64p, f64p,
+                                           C.c_int]
             lib.oracle_options.restype = C.c_int
             _lib = lib
     return _lib
@@ -226,21 +230,28 @@ def _factor(path: int, d: int, T: float):
     return None
 
 
-def option(type_: int, d: int, S0, K, r, sigma, T, seed: int, N: int, L: int, path: int = PATH_BB):
+def owen(y: int, seed32: int) -> int:
+    """Nested (Owen) scrambling of one 32-bit coordinate with a 32-bit seed."""
+    return int(_load().oracle_owen(int(y) & 0xFFFFFFFF, int(seed32) & 0xFFFFFFFF))
+
+
+def option(type_: int, d: int, S0, K, r, sigma, T, seed: int, N: int, L: int, path: int = PATH_BB,
+           rand: int = RAND_SHIFT):
     """One option: dict(mean[4], stderr[4], abs_mean[4], C_l[L][4])."""
     V = direction_numbers(max(d, 2))
     A = _factor(path, d, T)
     Ap = A.ctypes.data if A is not None else None
     C_l = np.zeros((L, 4))
     mean, se, am = np.zeros(4), np.zeros(4), np.zeros(4)
-    rc = _load().oracle_option(type_, d, S0, K, r, sigma, T, seed & (2**64 - 1), N, L, path,
+    rc = _load().oracle_option(type_, d, S0, K, r, sigma, T, seed & (2**64 - 1), N, L, path, rand,
                                V, Ap, C_l.ctypes.data, mean, se, am)
     if rc != 0:
         raise ValueError("oracle_option rejected its arguments")
     return {"mean": mean, "stderr": se, "abs_mean": am, "C_l": C_l}
 
 
-def replication(o: dict, l: int, path: int = PATH_BB, k0: int = 0, N: int | None = None) -> np.ndarray:
+def replication(o: dict, l: int, path: int = PATH_BB, k0: int = 0, N: int | None = None,
+                rand: int = RAND_SHIFT) -> np.ndarray:
     """C_l[4] of replication l of option dict o over points k0 .. k0 + N - 1."""
     d = int(o["d"])
     N = int(o["n_points"]) if N is None else int(N)
@@ -249,13 +260,13 @@ def replication(o: dict, l: int, path: int = PATH_BB, k0: int = 0, N: int | None
     out = np.zeros(4)
     rc = _load().oracle_replication(int(o["type"]), d, float(o["S0"]), float(o["K"]), float(o["r"]),
                                     float(o["sigma"]), float(o["T"]), int(o["seed"]) & (2**64 - 1), k0, N,
-                                    l, path, V, A.ctypes.data if A is not None else None, out, None)
+                                    l, path, rand, V, A.ctypes.data if A is not None else None, out, None)
     if rc != 0:
         raise ValueError("oracle_replication rejected its arguments")
     return out
 
 
-def options(specs, L: int, path: int = PATH_BB, n_threads: int = 0):
+def options(specs, L: int, path: int = PATH_BB, n_threads: int = 0, rand: int = RAND_SHIFT):
     """Many options (list of dicts with type,d,S0,K,r,sigma,T,seed,n_points).
 
     Returns (mean[n][4], stderr[n][4], abs_mean[n][4], threads_used)."""
@@ -279,7 +290,7 @@ def options(specs, L: int, path: int = PATH_BB, n_threads: int = 0):
     mean, se, am = np.zeros((n, 4)), np.zeros((n, 4)), np.zeros((n, 4))
     used = _load().oracle_options(n, typ.ctypes.data, dd.ctypes.data, f["S0"].ctypes.data,
                                   f["K"].ctypes.data, f["r"].ctypes.data, f["sigma"].ctypes.data,
-                                  f["T"].ctypes.data, seed.ctypes.data, NN.ctypes.data, L, path, V,
+                                  f["T"].ctypes.data, seed.ctypes.data, NN.ctypes.data, L, path, rand, V,
                                   C.cast(Aptr, C.c_void_p) if Aptr is not None else None,
                                   mean.reshape(-1), se.reshape(-1), am.reshape(-1), n_threads)
     return mean, se, am, used

@@ -49,6 +49,7 @@
 
 enum { ORC_ARITH = 0, ORC_BINARY = 1, ORC_LOOKBACK = 2 };
 enum { ORC_BB = 0, ORC_PCA = 1, ORC_STANDARD = 2, ORC_PCA_FULL = 3 };
+enum { ORC_RAND_SHIFT = 0, ORC_RAND_OWEN = 1 };
 
 /* ------------------------------------------------------------------------
  * Sobol direction numbers (Sec. 2.2.2, eqn:SobolPrimitivePolynomial and
@@ -136,6 +137,34 @@ uint64_t oracle_splitmix64(uint64_t seed, uint64_t i)
 uint32_t oracle_shift(uint64_t seed, int l, int j)
 {
     return (uint32_t)(oracle_splitmix64(seed, ((uint64_t)l << 16) + (uint64_t)j) >> 32);
+}
+
+/* ------------------------------------------------------------------------
+ * Nested (Owen) scrambling of one coordinate in base 2 (Sec. 2.2.3): digit
+ * k of the binary expansion (k = 1 the most significant) is flipped or not
+ * by a random function of digits 1..k-1 only, so every subinterval of every
+ * level is swapped independently.  On the bit-reversed value v (digit k ->
+ * bit k-1) "flip bit i by a function of the bits below i" is what adding a
+ * seed does (the carry) and what v ^= ((v mod 2^24) * C) does for an even
+ * constant C (the product's bit i sees only bits below i); four such rounds
+ * with fixed constants follow the seeded addition (the Laine-Karras style of
+ * hash-based nested scrambling).  Each step is a bijection that maps a
+ * uniform v to a uniform v, so each scrambled point is uniform for a random
+ * seed, and scrambled nets stay nets.
+ * ---------------------------------------------------------------------- */
+static uint32_t reverse32(uint32_t x)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 32; ++b) r |= ((x >> b) & 1u) << (31 - b);
+    return r;
+}
+
+uint32_t oracle_owen(uint32_t y, uint32_t seed32)
+{
+    static const uint32_t C[4] = {0xcca0d0u, 0x6292a6u, 0xb21bbau, 0x70b6f2u};
+    uint32_t v = reverse32(y) + seed32;
+    for (int i = 0; i < 4; ++i) v ^= (v & 0xFFFFFFu) * C[i];
+    return reverse32(v);
 }
 
 /* ------------------------------------------------------------------------
@@ -468,7 +497,7 @@ static double sum_val(const orc_sum *a) { return a->s + a->c; }
  * points k = k0 .. k0 + N - 1, and abs_sum[4] += sum_k |F| (may be NULL). */
 int oracle_replication(int type, int d, double S0, double K, double r, double sigma,
                        double T, uint64_t seed, int64_t k0, int64_t N, int l, int path,
-                       const uint32_t *V, const double *A, double *C_l, double *abs_sum)
+                       int rand, const uint32_t *V, const double *A, double *C_l, double *abs_sum)
 {
     if (d < 1 || N < 1 || k0 < 0) return -1;
     if (path == ORC_PCA_FULL && (!A || (type != ORC_ARITH && type != ORC_BINARY))) return -1;
@@ -484,7 +513,10 @@ int oracle_replication(int type, int d, double S0, double K, double r, double si
     memset(ab, 0, sizeof ab);
     for (int64_t k = k0; k < k0 + N; ++k) {
         for (int j = 1; j <= n; ++j) {
-            uint32_t y = sobol_int(V + (size_t)j * 32, (uint64_t)k) ^ oracle_shift(seed, l, j);
+            uint32_t y = sobol_int(V + (size_t)j * 32, (uint64_t)k);
+            /* randomisation: digital shift (XOR) or nested scrambling, both
+             * keyed by the same per-(replication, dimension) 32-bit value */
+            y = rand == ORC_RAND_OWEN ? oracle_owen(y, oracle_shift(seed, l, j)) : (y ^ oracle_shift(seed, l, j));
             double u = ((double)y + 0.5) / 4294967296.0;
             z[j - 1] = oracle_norm_inv(u);
         }
@@ -515,7 +547,7 @@ int oracle_replication(int type, int d, double S0, double K, double r, double si
 }
 
 int oracle_option(int type, int d, double S0, double K, double r, double sigma,
-                  double T, uint64_t seed, int64_t N, int L, int path,
+                  double T, uint64_t seed, int64_t N, int L, int path, int rand,
                   const uint32_t *V, const double *A,
                   double *C_l, double *mean, double *stderr_, double *abs_mean)
 {
@@ -523,7 +555,7 @@ int oracle_option(int type, int d, double S0, double K, double r, double sigma,
     double *Cl = (double *)malloc(sizeof(double) * (size_t)L * 4);
     double absum[4] = {0, 0, 0, 0};
     for (int l = 0; l < L; ++l)
-        if (oracle_replication(type, d, S0, K, r, sigma, T, seed, 0, N, l, path, V, A, Cl + 4 * l, absum) != 0) {
+        if (oracle_replication(type, d, S0, K, r, sigma, T, seed, 0, N, l, path, rand, V, A, Cl + 4 * l, absum) != 0) {
             free(Cl);
             return -1;
         }
@@ -548,7 +580,7 @@ int oracle_option(int type, int d, double S0, double K, double r, double sigma,
 int oracle_options(int n_opts, const int *type, const int *d, const double *S0,
                    const double *K, const double *r, const double *sigma,
                    const double *T, const uint64_t *seed, const int64_t *N,
-                   int L, int path, const uint32_t *V, const double *const *A_list,
+                   int L, int path, int rand, const uint32_t *V, const double *const *A_list,
                    double *mean, double *stderr_, double *abs_mean, int n_threads)
 {
     int used = 1;
@@ -563,7 +595,7 @@ int oracle_options(int n_opts, const int *type, const int *d, const double *S0,
 #endif
     for (int i = 0; i < n_opts; ++i) {
         oracle_option(type[i], d[i], S0[i], K[i], r[i], sigma[i], T[i], seed[i],
-                      N[i], L, path, V, A_list ? A_list[i] : NULL, NULL,
+                      N[i], L, path, rand, V, A_list ? A_list[i] : NULL, NULL,
                       mean + 4 * i, stderr_ + 4 * i, abs_mean + 4 * i);
     }
     (void)n_threads;

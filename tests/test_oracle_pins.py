@@ -110,6 +110,87 @@ def test_shifted_points_remain_a_net(m):
             assert np.array_equal(cells, np.arange(1 << m, dtype=np.uint64))
 
 
+# --------------------------------------------------------------------------
+# Nested (Owen) scrambling (Sec. 2.2.3)
+# --------------------------------------------------------------------------
+
+def test_owen_scrambling_is_nested():
+    """Digit k of the scrambled value depends on digits 1..k of the input
+    only: two inputs that share their first k digits share the first k
+    scrambled digits, and the k-th scrambled digits differ iff the k-th
+    input digits do."""
+    rng = np.random.default_rng(17)
+    for _ in range(300):
+        seed = int(rng.integers(0, 2**32))
+        y = int(rng.integers(0, 2**32))
+        k = int(rng.integers(1, 32))                    # change digits k+1 .. 32 (bits below 32-k)
+        y2 = y ^ int(rng.integers(1, 2**(32 - k)))
+        a, b = oracle.owen(y, seed), oracle.owen(y2, seed)
+        assert (a >> (32 - k)) == (b >> (32 - k))
+        # flipping digit k alone flips scrambled digit k
+        y3 = y ^ (1 << (32 - k))
+        c = oracle.owen(y3, seed)
+        assert (a >> (32 - k)) ^ (c >> (32 - k)) == 1
+
+
+def test_owen_scrambling_is_a_bijection_per_seed():
+    seed = 0x9E3779B9
+    ys = np.arange(1 << 16, dtype=np.uint64) << np.uint64(16)   # all 16-digit prefixes
+    out = {oracle.owen(int(y), seed) >> 16 for y in ys}
+    assert len(out) == 1 << 16
+
+
+def test_owen_scrambling_depends_on_the_prefix():
+    """Unlike a digital shift (one XOR pattern for every point), the flips
+    of a digit change with the digits above it."""
+    seed = 12345
+    pats = {oracle.owen(y << 24, seed) ^ (y << 24) for y in range(256)}
+    assert len(pats) > 64
+
+
+@pytest.mark.parametrize("m", [4, 8, 11])
+def test_owen_scrambled_points_remain_a_net(m):
+    """Every scrambled 2^m prefix of a coordinate keeps one point per dyadic
+    cell of width 2^-m, in every dimension, for several seeds."""
+    n_dims = 12
+    pts = oracle.sobol_points(n_dims, 0, 1 << m)
+    for seed in (1, 77, 2**31 + 5):
+        for j in range(n_dims):
+            s = oracle.shift(seed, 3, j)
+            cells = sorted(oracle.owen(int(y), s) >> (32 - m) for y in pts[:, j])
+            assert cells == list(range(1 << m))
+
+
+def test_owen_scrambled_digit_is_balanced_over_seeds():
+    """For a fixed input, each scrambled digit is 0 or 1 with equal odds over
+    random seeds (the scrambled point is uniform)."""
+    rng = np.random.default_rng(3)
+    seeds = rng.integers(0, 2**32, size=4000)
+    for y in (0, 0x80000000, 0x12345678):
+        outs = np.array([oracle.owen(y, int(sd)) for sd in seeds], dtype=np.uint64)
+        for bit in (31, 27, 20, 12):
+            frac = float(((outs >> np.uint64(bit)) & np.uint64(1)).mean())
+            assert abs(frac - 0.5) < 0.04, (y, bit, frac)
+
+
+def test_owen_rqmc_estimate_agrees_with_quadrature():
+    """The scrambled estimator is unbiased: at d = 2 the mean over
+    replications lies within 4 standard errors of quadrature."""
+    S0, K, r, sig, T, d = 100.0, 103.0, 0.05, 0.25, 1.0, 2
+    dt = T / d
+
+    def G(zz, i):
+        W = oracle.build_path(oracle.PATH_BB, 1, dt, np.array([zz]))
+        return oracle.path_greeks(oracle.ARITH_ASIAN, d, S0, K, r, sig, T, W)[i] * scipy.stats.norm.pdf(zz)
+
+    ref = np.array([scipy.integrate.quad(G, -40, 40, args=(i,), epsabs=0, epsrel=1e-13, limit=200)[0]
+                    for i in range(4)])
+    res = oracle.option(oracle.ARITH_ASIAN, d, S0, K, r, sig, T, 9191, 1 << 10, 32, oracle.PATH_BB,
+                        oracle.RAND_OWEN)
+    for i in range(4):
+        assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-13 * abs(ref[i]), i
+
+
 def test_shifts_differ_between_replications_and_dims():
     s = oracle.shifts(77, 8, 64)
     assert len(np.unique(s)) == s.size
