@@ -148,6 +148,16 @@ typedef struct {
  * graphs are cached per device, least recently used evicted). */
 #define QCPW_FLAG_GRAPH 1
 
+/* Randomise the Sobol points by nested (Owen) scrambling (Sec. 2.2.3)
+ * instead of the random digital shift: digit k of each coordinate is
+ * flipped by a random function of the digits above it, seeded per
+ * (replication l, dimension j) by the same 32-bit value s_{l,j} that is the
+ * digital shift otherwise (hash-based nested scrambling: a seeded addition
+ * and four rounds v ^= (v mod 2^24) * C, C even, on the bit-reversed
+ * value).  QCPW_PATH_BB and QCPW_PATH_STANDARD only (QCPW_EINVAL
+ * otherwise); also accepted by qcpw_server_create. */
+#define QCPW_FLAG_OWEN 2
+
 /*
  * qmc_cpw_greeks_ex -- as qmc_cpw_greeks with explicit precision, device,
  * stream and output placement.  cfg may be NULL (defaults of
@@ -172,6 +182,14 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
  */
 qcpw_status qcpw_sobol_points(uint64_t seed, int32_t shift_index, int32_t n_dims,
                               int64_t k0, int64_t count, uint32_t *out);
+
+/*
+ * qcpw_scrambled_points -- as qcpw_sobol_points with nested scrambling
+ * (QCPW_FLAG_OWEN) in place of the digital shift: out[k][j] =
+ * owen(G_j gray(k0 + k), s_{l,j}) for j >= 1, dimension 0 unscrambled.
+ */
+qcpw_status qcpw_scrambled_points(uint64_t seed, int32_t shift_index, int32_t n_dims,
+                                  int64_t k0, int64_t count, uint32_t *out);
 
 /*
  * qcpw_path_factor -- the factor A (row-major (d-1) x (d-1), FP64) that the

@@ -24,7 +24,7 @@ ARITH_ASIAN, BINARY_ASIAN, LOOKBACK = 0, 1, 2
 PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
 FP64, FP32_MIXED = 0, 1
 GEMM_FP32, GEMM_BF16X3 = 0, 1
-FLAG_GRAPH = 1
+FLAG_GRAPH, FLAG_OWEN = 1, 2
 OUTPUTS = ("price", "delta", "vega", "gamma")
 MAX_D, MAX_D_PCA, MAX_D_PCA_FULL = 385, 257, 256
 
@@ -32,7 +32,7 @@ STATUS = {0: "QCPW_OK", -1: "QCPW_EINVAL", -2: "QCPW_ENOMEM", -3: "QCPW_EDEVICE"
           -5: "QCPW_EBUSY", -6: "QCPW_ECANCELLED", -7: "QCPW_ENOTFOUND"}
 
 # names of every entry point declared in include/qmc_cpw.h
-EXPORTS = ("qmc_cpw_greeks", "qmc_cpw_greeks_ex", "qcpw_sobol_points", "qcpw_path_factor",
+EXPORTS = ("qmc_cpw_greeks", "qmc_cpw_greeks_ex", "qcpw_sobol_points", "qcpw_scrambled_points", "qcpw_path_factor",
            "qcpw_kernel_timer", "qcpw_last_error", "qcpw_version", "qcpw_server_create", "qcpw_submit", "qcpw_poll",
            "qcpw_wait", "qcpw_cancel", "qcpw_server_stats", "qcpw_server_destroy")
 
@@ -79,6 +79,7 @@ def lib() -> C.CDLL:
             L.qmc_cpw_greeks.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p]
             L.qmc_cpw_greeks_ex.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p, vp]
             L.qcpw_sobol_points.argtypes = [u64, i32, i32, i64, i64, vp]
+            L.qcpw_scrambled_points.argtypes = [u64, i32, i32, i64, i64, vp]
             L.qcpw_path_factor.argtypes = [i32, i32, C.c_double, vp]
             L.qcpw_kernel_timer.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(i64)]
             L.qcpw_last_error.restype = C.c_char_p
@@ -124,7 +125,7 @@ def make_specs(options: Sequence[dict]) -> C.Array:
 def greeks(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precision: int = FP64,
            d: int = 0, n_points: int = 0, pca_gemm: int = GEMM_FP32, per_shift: bool = False,
            block_threads: int = 0, stream=None, device_outputs: bool = False, device: int = -1,
-           out=None, graph: bool = False):
+           out=None, graph: bool = False, owen: bool = False):
     """Greeks of many options in one launch.
 
     Host mode (default): returns (greeks[n][4], stderr[n][4]) numpy arrays
@@ -135,7 +136,7 @@ def greeks(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precisio
     specs = make_specs(options)
     n = len(options)
     cfg = RunConfig(precision, pca_gemm, device, 1 if device_outputs else 0, None, None,
-                    block_threads, FLAG_GRAPH if graph else 0)
+                    block_threads, (FLAG_GRAPH if graph else 0) | (FLAG_OWEN if owen else 0))
     if device_outputs:
         import torch
         if out is None:
@@ -174,9 +175,13 @@ def greeks_plain(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, d:
     return g, e
 
 
-def sobol_points(seed: int, shift_index: int, n_dims: int, k0: int, count: int) -> np.ndarray:
+def sobol_points(seed: int, shift_index: int, n_dims: int, k0: int, count: int,
+                 owen: bool = False) -> np.ndarray:
+    """The randomised Sobol integers the kernels use: digital shift, or nested
+    scrambling with owen=True."""
     out = np.zeros((count, n_dims), dtype=np.uint32)
-    _check(lib().qcpw_sobol_points(seed & (2**64 - 1), shift_index, n_dims, k0, count, out.ctypes.data))
+    f = lib().qcpw_scrambled_points if owen else lib().qcpw_sobol_points
+    _check(f(seed & (2**64 - 1), shift_index, n_dims, k0, count, out.ctypes.data))
     return out
 
 
@@ -204,8 +209,8 @@ class Server:
     """Continuous-batching request server (qcpw_server_*)."""
 
     def __init__(self, hbm_budget_bytes: int, precision: int = FP32_MIXED, device: int = -1,
-                 block_threads: int = 0):
-        cfg = RunConfig(precision, GEMM_FP32, device, 0, None, None, block_threads, 0)
+                 block_threads: int = 0, owen: bool = False):
+        cfg = RunConfig(precision, GEMM_FP32, device, 0, None, None, block_threads, FLAG_OWEN if owen else 0)
         h = C.c_void_p()
         _check(lib().qcpw_server_create(C.byref(cfg), hbm_budget_bytes, C.byref(h)))
         self._h = h

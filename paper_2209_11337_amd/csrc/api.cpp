@@ -228,7 +228,7 @@ static qcpw_status run_graph(Context *ctx, const qcpw_option_spec *specs, int32_
 {
     std::vector<unsigned char> key;
     append(key, specs, sizeof(qcpw_option_spec) * (size_t)n_opts);
-    const int64_t scal[] = {n_opts, d, n_points, n_shifts, path, c.precision, c.pca_gemm, c.block_threads};
+    const int64_t scal[] = {n_opts, d, n_points, n_shifts, path, c.precision, c.pca_gemm, c.block_threads, c.flags};
     append(key, scal, sizeof scal);
     const void *ptrs[] = {c.stream, g_out, e_out, c.out_per_shift};
     append(key, ptrs, sizeof ptrs);
@@ -241,7 +241,7 @@ static qcpw_status run_graph(Context *ctx, const qcpw_option_spec *specs, int32_
         }
     LaunchPlan lp;
     qcpw_status st = plan_launch(ctx, specs, n_opts, d, n_points, n_shifts, path, c.precision, c.pca_gemm,
-                                 c.block_threads, lp);
+                                 c.block_threads, lp, nullptr, (c.flags & QCPW_FLAG_OWEN) != 0);
     if (st != QCPW_OK) return st;
     if (ctx->graphs.size() >= kMaxGraphs) {   // evict the least recently used
         size_t lru = 0;
@@ -303,19 +303,23 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
     qcpw_status st = validate_call(option_specs, n_opts, d, n_points, n_shifts, path_construction,
                                    c.precision, c.pca_gemm, c.block_threads);
     if (st != QCPW_OK) return st;
+    if (c.flags & ~(QCPW_FLAG_GRAPH | QCPW_FLAG_OWEN)) return fail(QCPW_EINVAL, "unknown flags");
+    const bool owen = (c.flags & QCPW_FLAG_OWEN) != 0;
+    if (owen && path_construction != QCPW_PATH_BB && path_construction != QCPW_PATH_STANDARD)
+        return fail(QCPW_EINVAL, "nested scrambling is available with the BB and STANDARD constructions");
+    if ((c.flags & QCPW_FLAG_GRAPH) && !c.outputs_on_device)
+        return fail(QCPW_EINVAL, "QCPW_FLAG_GRAPH needs outputs_on_device");
     Context *ctx = nullptr;
     st = get_context(c.device, &ctx);
     if (st != QCPW_OK) return st;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    if (c.flags & ~QCPW_FLAG_GRAPH) return fail(QCPW_EINVAL, "unknown flags");
     if (c.flags & QCPW_FLAG_GRAPH) {
-        if (!c.outputs_on_device) return fail(QCPW_EINVAL, "QCPW_FLAG_GRAPH needs outputs_on_device");
         return run_graph(ctx, option_specs, n_opts, d, n_points, n_shifts, path_construction, c, out_greeks,
                          out_stderr);
     }
     LaunchPlan lp;
     st = plan_launch(ctx, option_specs, n_opts, d, n_points, n_shifts, path_construction, c.precision,
-                     c.pca_gemm, c.block_threads, lp);
+                     c.pca_gemm, c.block_threads, lp, nullptr, owen);
     if (st != QCPW_OK) return st;
     const size_t n = (size_t)n_opts;
     const size_t out_bytes = n * 4 * sizeof(double);
@@ -388,8 +392,23 @@ qcpw_status qmc_cpw_greeks(const qcpw_option_spec *option_specs, int32_t n_opts,
                              out_stderr, nullptr);
 }
 
+static qcpw_status points(uint64_t seed, int32_t shift_index, int32_t n_dims, int64_t k0, int64_t count,
+                          uint32_t *out, bool owen);
+
 qcpw_status qcpw_sobol_points(uint64_t seed, int32_t shift_index, int32_t n_dims, int64_t k0, int64_t count,
                               uint32_t *out)
+{
+    return points(seed, shift_index, n_dims, k0, count, out, false);
+}
+
+qcpw_status qcpw_scrambled_points(uint64_t seed, int32_t shift_index, int32_t n_dims, int64_t k0, int64_t count,
+                                  uint32_t *out)
+{
+    return points(seed, shift_index, n_dims, k0, count, out, true);
+}
+
+static qcpw_status points(uint64_t seed, int32_t shift_index, int32_t n_dims, int64_t k0, int64_t count,
+                          uint32_t *out, bool owen)
 {
     g_last_error.clear();
     if (!out) return fail(QCPW_EINVAL, "out is NULL");
@@ -405,7 +424,8 @@ qcpw_status qcpw_sobol_points(uint64_t seed, int32_t shift_index, int32_t n_dims
     if (ctx->ws_pending) QCPW_HIP(hipEventSynchronize(ctx->ws_done));
     st = ctx->ws.ensure(bytes);
     if (st != QCPW_OK) return st;
-    st = launch_sobol_points(ctx, seed, shift_index, n_dims, k0, count, (uint32_t *)ctx->ws.ptr, ctx->own_stream);
+    st = launch_sobol_points(ctx, seed, shift_index, n_dims, k0, count, (uint32_t *)ctx->ws.ptr, ctx->own_stream,
+                             owen);
     if (st != QCPW_OK) return st;
     QCPW_HIP(hipMemcpyAsync(out, ctx->ws.ptr, bytes, hipMemcpyDeviceToHost, ctx->own_stream));
     QCPW_HIP(hipStreamSynchronize(ctx->own_stream));

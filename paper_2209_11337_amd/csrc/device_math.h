@@ -82,6 +82,22 @@ __host__ __device__ inline uint32_t fold_sign(uint32_t y)
     return y ^ ((uint32_t)((int32_t)y >> 31) >> 1);
 }
 
+// Nested (Owen) scrambling of one 32-bit coordinate in base 2 (Sec. 2.2.3):
+// digit k (k = 1 most significant) is flipped by a function of digits
+// 1..k-1 only.  On the bit-reversed value that is what a seeded addition
+// (carries move up) and v ^= (v mod 2^24) * C with an even constant C (the
+// product's bit i sees only bits below i) do; four such rounds follow the
+// addition.  24-bit products (v_mul_u32_u24) run at the full VALU rate.
+__device__ inline uint32_t owen_scramble(uint32_t y, uint32_t seed)
+{
+    uint32_t v = __builtin_bitreverse32(y) + seed;
+    v ^= __umul24(v, 0xcca0d0u);
+    v ^= __umul24(v, 0x6292a6u);
+    v ^= __umul24(v, 0xb21bbau);
+    v ^= __umul24(v, 0x70b6f2u);
+    return __builtin_bitreverse32(v);
+}
+
 // Phi^{-1}((y + 1/2) 2^-32) in FP32 for folded x = fold(y), from the cubic
 // table of ninv_table.inc held in LDS at `tab`: q = float(m), m the low 31
 // bits of x; bits 23-c..27 of q (c = QCPW_NINV_CELL_BITS) select the cell and the cubic is evaluated in

@@ -51,10 +51,26 @@ struct UnitCtx {
     int64_t chunk;
 };
 
-template <bool F32, bool MAX>
+// The wave-uniform part of the Sobol coordinates the lanes consume: for step
+// s = lane + 64 q, U[q] = G_dim gray(base), folded with the digital shift
+// (the lane table is folded too), or -- with nested scrambling -- raw, with
+// the dimension's scrambling seed in Sd[q] (the lane table then raw too).
+template <bool OWEN>
+struct UParts {
+    uint32_t U[QCPW_UQ];
+    uint32_t Sd[OWEN ? QCPW_UQ : 1];
+    // folded randomised coordinate of step 64 q + k from the lane's table word
+    __device__ __forceinline__ uint32_t bits(uint32_t lane_word, int q, int k) const
+    {
+        if constexpr (OWEN) return fold_sign(owen_scramble(lane_word ^ rdlane(U[q], k), rdlane(Sd[q], k)));
+        else return lane_word ^ rdlane(U[q], k);
+    }
+};
+
+template <bool F32, bool MAX, bool OWEN>
 __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
                                        const float4 *lds_tab, typename Real<F32>::T *stk, int lane,
-                                       const uint32_t (&U)[QCPW_UQ], PathSums<typename Real<F32>::T> &ps)
+                                       const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
     const int n = op.n;
@@ -63,7 +79,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
     R L = R(0), Rr;
     {   // terminal point
         const PlanStep st = plan[0];
-        const uint32_t x = lds_lane[st.lds_off + lane] ^ rdlane(U[0], 0);
+        const uint32_t x = U.bits(lds_lane[st.lds_off + lane], 0, 0);
         const R z = coord_tab<F32>(x, op, lds_tab);
         const R sd = F32 ? (R)st.sd * op.zs_t : (R)plan64[0].sd;
         const R drift = F32 ? (R)op.ydrift_n_f : (R)op.ydrift_n;
@@ -86,7 +102,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
                 L = st.pops == 1 ? Rr : slot[64];
                 Rr = r;
             }
-            const uint32_t x = lds_lane[st.lds_off + lane] ^ rdlane(U[q], s - 64 * q);
+            const uint32_t x = U.bits(lds_lane[st.lds_off + lane], q, s - 64 * q);
             const R z = coord_tab<F32>(x, op, lds_tab);
             R Ym;
             R mf;
@@ -115,9 +131,9 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
 // the same constexpr functions); price, delta and gamma come out bit-identical
 // to the plan walker's, vega (from the FP32 sums of E Y and E m) within FP32
 // rounding.  Removes about a quarter of the VALU work per date.
-template <bool MAX, int N, int LO, int HI>
+template <bool MAX, bool OWEN, int N, int LO, int HI>
 __device__ __forceinline__ void fixed_interval(const uint32_t *row0, const float4 *tab, float zs,
-                                               const uint32_t (&U)[QCPW_UQ], float WL, float WR,
+                                               const UParts<OWEN> &U, float WL, float WR,
                                                PathSums<float> &ps)
 {
     if constexpr (HI - LO >= 2) {
@@ -128,46 +144,46 @@ __device__ __forceinline__ void fixed_interval(const uint32_t *row0, const float
         constexpr float wl = (float)((double)(HI - M) / (double)(HI - LO));
         constexpr float wr = (float)((double)(M - LO) / (double)(HI - LO));
         constexpr float sd = (float)qcpw_csqrt((double)(M - LO) * (double)(HI - M) / (double)(HI - LO));
-        const uint32_t x = row0[(DIM - 1) * 64] ^ rdlane(U[S / 64], S % 64);
+        const uint32_t x = U.bits(row0[(DIM - 1) * 64], S / 64, S % 64);
         const float z = ninv_table_f32(x, tab);
         const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
         consume<float, MAX>(ps, Ym, (float)M);
-        fixed_interval<MAX, N, LO, M>(row0, tab, zs, U, WL, Ym, ps);
-        fixed_interval<MAX, N, M, HI>(row0, tab, zs, U, Ym, WR, ps);
+        fixed_interval<MAX, OWEN, N, LO, M>(row0, tab, zs, U, WL, Ym, ps);
+        fixed_interval<MAX, OWEN, N, M, HI>(row0, tab, zs, U, Ym, WR, ps);
     }
 }
 
-template <bool MAX, int N>
+template <bool MAX, bool OWEN, int N>
 __device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_t *lds_lane, const float4 *tab,
-                                                 int lane, const uint32_t (&U)[QCPW_UQ], PathSums<float> &ps)
+                                                 int lane, const UParts<OWEN> &U, PathSums<float> &ps)
 {
     const uint32_t *row0 = lds_lane + lane;
     const float zs = op.zs_t;
     constexpr float sd0 = (float)qcpw_csqrt((double)N);
-    const float z = ninv_table_f32(row0[0] ^ rdlane(U[0], 0), tab);   // terminal point, dimension 1
+    const float z = ninv_table_f32(U.bits(row0[0], 0, 0), tab);   // terminal point, dimension 1
     const float WR = fmaf(sd0 * zs, z, op.ydrift_n_f);
     consume<float, MAX>(ps, WR, (float)N);
-    fixed_interval<MAX, N, 0, N>(row0, tab, zs, U, 0.0f, WR, ps);
+    fixed_interval<MAX, OWEN, N, 0, N>(row0, tab, zs, U, 0.0f, WR, ps);
 }
 
 // true if op.n has a compile-time bridge (then the path is done)
-template <bool MAX>
+template <bool MAX, bool OWEN>
 __device__ inline bool bridge_fixed_any(const OptDev &op, const uint32_t *lds_lane, const float4 *tab, int lane,
-                                        const uint32_t (&U)[QCPW_UQ], PathSums<float> &ps)
+                                        const UParts<OWEN> &U, PathSums<float> &ps)
 {
     if (!qcpw_has_fixed_bridge(op.n)) return false;
     switch (op.n) {
-    case 15: run_bridge_fixed<MAX, 15>(op, lds_lane, tab, lane, U, ps); return true;
-    case 31: run_bridge_fixed<MAX, 31>(op, lds_lane, tab, lane, U, ps); return true;
-    case 63: run_bridge_fixed<MAX, 63>(op, lds_lane, tab, lane, U, ps); return true;
-    case 127: run_bridge_fixed<MAX, 127>(op, lds_lane, tab, lane, U, ps); return true;
+    case 15: run_bridge_fixed<MAX, OWEN, 15>(op, lds_lane, tab, lane, U, ps); return true;
+    case 31: run_bridge_fixed<MAX, OWEN, 31>(op, lds_lane, tab, lane, U, ps); return true;
+    case 63: run_bridge_fixed<MAX, OWEN, 63>(op, lds_lane, tab, lane, U, ps); return true;
+    case 127: run_bridge_fixed<MAX, OWEN, 127>(op, lds_lane, tab, lane, U, ps); return true;
     default: return false;
     }
 }
 
-template <bool F32, bool MAX>
+template <bool F32, bool MAX, bool OWEN>
 __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, const float4 *lds_tab, int lane,
-                                         const uint32_t (&U)[QCPW_UQ], PathSums<typename Real<F32>::T> &ps)
+                                         const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
     const int n = op.n;
@@ -178,7 +194,7 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
     for (int q = 0; q < QCPW_UQ; ++q) {
         const int s_hi = min(64 * (q + 1), n);
         for (int s = 64 * q; s < s_hi; ++s) {
-            const uint32_t y = lds_lane[s * 64 + lane] ^ rdlane(U[q], s - 64 * q);
+            const uint32_t y = U.bits(lds_lane[s * 64 + lane], q, s - 64 * q);
             const R z = coord_tab<F32>(y, op, lds_tab);
             Y = Y + fma(zs, z, drift);
             consume<R, MAX>(ps, Y, (R)(s + 1));
@@ -187,39 +203,44 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
     }
 }
 
-// fold(U_j(base)) for the dimensions this lane holds: steps s = lane + 64 q.
+// U_j(base) (and its seed) for the dimensions this lane holds: steps s = lane + 64 q.
 template <int PATHK>
 __device__ inline int step_dim(const LaunchDesc &ld, const OptDev &op, int s)
 {
     return (PATHK == QCPW_PATH_BB) ? ld.plan[op.plan_off + s].dim : s + 1;
 }
 
-template <int PATHK>
+template <int PATHK, bool OWEN>
 __device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op, int shift, int lane,
-                                         uint64_t base, uint32_t (&U)[QCPW_UQ])
+                                         uint64_t base, UParts<OWEN> &U)
 {
     const uint64_t g = (base ^ (base >> 1)) >> 5;   // gray(base) has no bits below 5
 #pragma unroll
     for (int q = 0; q < QCPW_UQ; ++q) {
         const int s = lane + 64 * q;
         int dim;
-        uint32_t u = 0;
+        uint32_t u = 0, key = 0;
         if (s < op.n) {
             dim = step_dim<PATHK>(ld, op, s);
-            u = digital_shift(op.seed, shift, dim);
+            key = digital_shift(op.seed, shift, dim);
             const uint32_t *v = ld.dir + (size_t)dim * 32;
             uint64_t gg = g;
             for (int b = 5; gg != 0; ++b, gg >>= 1)
                 if (gg & 1) u ^= v[b];
         }
-        U[q] = fold_sign(u);
+        if constexpr (OWEN) {
+            U.U[q] = u;
+            U.Sd[q] = key;
+        } else {
+            U.U[q] = fold_sign(u ^ key);
+        }
     }
 }
 
 // base -> base + 64: gray changes in bits 5 and 6 + ctz(base/64 + 1).
-template <int PATHK>
+template <int PATHK, bool OWEN>
 __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op, int lane, uint64_t base,
-                                         uint32_t (&U)[QCPW_UQ])
+                                         UParts<OWEN> &U)
 {
     const int c = __builtin_ctzll((base >> 6) + 1);
 #pragma unroll
@@ -227,7 +248,7 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
         const int s = lane + 64 * q;
         if (s < op.n) {
             const uint32_t *v = ld.dir + (size_t)step_dim<PATHK>(ld, op, s) * 32;
-            U[q] ^= fold_sign(v[5] ^ v[6 + c]);
+            U.U[q] ^= OWEN ? (v[5] ^ v[6 + c]) : fold_sign(v[5] ^ v[6 + c]);
         }
     }
 }
@@ -241,7 +262,7 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
 // on scalar plan loads and two dependent LDS reads), so it is held to 80
 // VGPRs: six waves per SIMD instead of four (measured 1.3x faster); with
 // 512-thread workgroups the LDS of three workgroups fits a CU at d = 64.
-template <bool F32, int PATHK>
+template <bool F32, int PATHK, bool OWEN>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 1))) void paths_kernel(const OptDev *__restrict__ opts,
                                                      const int64_t *__restrict__ unit_prefix,
                                                      const PlanStep *__restrict__ plan_all,
@@ -280,7 +301,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
     R *stk = (R *)(smem + lane_bytes) + (size_t)(tid >> 6) * stack_depth * 64 + lane;
     if (F32)
         for (int i = tid; i < QCPW_NINV_TAB_CELLS; i += bd) lds_tab[i] = ninv_tab[i];
-    for (int i = tid; i < max_n * 64; i += bd) lds_lane[i] = fold_sign(lane_tab[64 + i]);
+    for (int i = tid; i < max_n * 64; i += bd) lds_lane[i] = OWEN ? lane_tab[64 + i] : fold_sign(lane_tab[64 + i]);
     __syncthreads();
 
     int o = 0;
@@ -312,8 +333,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
         const int64_t start = op.k_begin + chunk * op.unit_pts;
         const int64_t end = min(start + (int64_t)op.unit_pts, k_end);
         const bool is_max = op.type == QCPW_LOOKBACK_FIXED_CALL;
-        uint32_t U[QCPW_UQ];
-        init_uniform_part<PATHK>(ld, op, shift, lane, (uint64_t)start, U);
+        UParts<OWEN> U;
+        init_uniform_part<PATHK, OWEN>(ld, op, shift, lane, (uint64_t)start, U);
         for (int64_t base = start; base < end; base += 64) {
             const bool valid = base + lane < k_end;
             double F[4] = {0.0, 0.0, 0.0, 0.0};
@@ -324,16 +345,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
                     bool done = false;
                     if constexpr (F32) {
                         if (fixed_bridges)
-                            done = is_max ? bridge_fixed_any<true>(op, lds_lane, lds_tab, lane, U, ps)
-                                          : bridge_fixed_any<false>(op, lds_lane, lds_tab, lane, U, ps);
+                            done = is_max ? bridge_fixed_any<true, OWEN>(op, lds_lane, lds_tab, lane, U, ps)
+                                          : bridge_fixed_any<false, OWEN>(op, lds_lane, lds_tab, lane, U, ps);
                     }
                     if (!done) {
-                        if (is_max) run_bridge_wave<F32, true>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
-                        else run_bridge_wave<F32, false>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
+                        if (is_max) run_bridge_wave<F32, true, OWEN>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
+                        else run_bridge_wave<F32, false, OWEN>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
                     }
                 } else {
-                    if (is_max) run_standard_wave<F32, true>(op, lds_lane, lds_tab, lane, U, ps);
-                    else run_standard_wave<F32, false>(op, lds_lane, lds_tab, lane, U, ps);
+                    if (is_max) run_standard_wave<F32, true, OWEN>(op, lds_lane, lds_tab, lane, U, ps);
+                    else run_standard_wave<F32, false, OWEN>(op, lds_lane, lds_tab, lane, U, ps);
                 }
             }
             if (valid) {
@@ -341,7 +362,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc_add(s[i], c[i], F[i]);
             }
-            if (base + 64 < end) step_uniform_part<PATHK>(ld, op, lane, (uint64_t)base, U);
+            if (base + 64 < end) step_uniform_part<PATHK, OWEN>(ld, op, lane, (uint64_t)base, U);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -425,6 +446,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const OptDev *opts, const
 // the per-path kernel uses.  One wave per 64 consecutive points; out is
 // [count][n_dims].  k0 need not be a multiple of 64: the wave's base is
 // rounded down and lanes outside [k0, k0 + count) store nothing.
+template <bool OWEN>
 __global__ __launch_bounds__(64) void sobol_points_kernel(const uint32_t *dir, const uint32_t *lane_tab,
                                                           uint64_t seed, int shift, int n_dims, int64_t k0,
                                                           int64_t count, uint32_t *out)
@@ -437,17 +459,19 @@ __global__ __launch_bounds__(64) void sobol_points_kernel(const uint32_t *dir, c
     for (int j0 = 0; j0 < n_dims; j0 += 64) {
         // lane holds U for dimension j0 + lane
         const int jl = j0 + lane;
-        uint32_t u = 0;
+        uint32_t u = 0, key = 0;
         if (jl < n_dims) {
-            u = jl == 0 ? 0u : digital_shift(seed, shift, jl);
+            key = jl == 0 ? 0u : digital_shift(seed, shift, jl);
             uint64_t gg = g;
             for (int b = 5; gg != 0; ++b, gg >>= 1)
                 if (gg & 1) u ^= dir[(size_t)jl * 32 + b];
+            if (!OWEN) u ^= key;
         }
         const int jmax = min(64, n_dims - j0);
         for (int jj = 0; jj < jmax; ++jj) {
             const int j = j0 + jj;
-            const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(u, jj);
+            uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(u, jj);
+            if (OWEN && j > 0) y = owen_scramble(y, rdlane(key, jj));   // dimension 0 stays as it is
             if (in) out[(size_t)(k - (uint64_t)k0) * n_dims + j] = y;
         }
     }
@@ -514,15 +538,19 @@ static bool fixed_bridges_on()
 
 qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
                         int64_t n_points, int32_t n_shifts, int32_t path, int32_t precision,
-                        int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp, const int64_t *k_begin)
+                        int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp, const int64_t *k_begin,
+                        bool owen)
 {
     {
         qcpw_status st = validate_call(specs, n_opts, d, n_points, n_shifts, path, precision, pca_gemm,
                                        block_threads);
         if (st != QCPW_OK) return st;
     }
+    if (owen && path != QCPW_PATH_BB && path != QCPW_PATH_STANDARD)
+        return fail(QCPW_EINVAL, "nested scrambling is available with the BB and STANDARD constructions");
 
     lp = LaunchPlan();
+    lp.owen = owen;
     lp.path = path;
     lp.precision = precision;
     lp.pca_gemm = pca_gemm;
@@ -661,17 +689,24 @@ static bool paths_lds_fits(const LaunchPlan &lp, int bd)
     return paths_lds_bytes(lp, bd) + tab <= 160 * 1024;
 }
 
-template <bool F32, int PATHK>
+template <bool F32, int PATHK, bool OWEN>
 static const void *paths_fn()
 {
-    return reinterpret_cast<const void *>(&paths_kernel<F32, PATHK>);
+    return reinterpret_cast<const void *>(&paths_kernel<F32, PATHK, OWEN>);
+}
+
+template <bool OWEN>
+static const void *select_paths_kernel_r(const LaunchPlan &lp)
+{
+    const bool f32 = lp.precision == QCPW_FP32_MIXED;
+    if (lp.path == QCPW_PATH_STANDARD)
+        return f32 ? paths_fn<true, QCPW_PATH_STANDARD, OWEN>() : paths_fn<false, QCPW_PATH_STANDARD, OWEN>();
+    return f32 ? paths_fn<true, QCPW_PATH_BB, OWEN>() : paths_fn<false, QCPW_PATH_BB, OWEN>();
 }
 
 static const void *select_paths_kernel(const LaunchPlan &lp)
 {
-    const bool f32 = lp.precision == QCPW_FP32_MIXED;
-    if (lp.path == QCPW_PATH_STANDARD) return f32 ? paths_fn<true, QCPW_PATH_STANDARD>() : paths_fn<false, QCPW_PATH_STANDARD>();
-    return f32 ? paths_fn<true, QCPW_PATH_BB>() : paths_fn<false, QCPW_PATH_BB>();
+    return lp.owen ? select_paths_kernel_r<true>(lp) : select_paths_kernel_r<false>(lp);
 }
 
 // Resident waves per CU of the fused kernel at workgroup size bd (0 if it
@@ -704,7 +739,7 @@ int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
         const int v = atoi(env);
         if (v != 0 && qcpw_block_threads_ok(v) && resident_waves(lp, v) > 0) return v;
     }
-    const int key = (lp.path * 2 + lp.precision) * 64 + (lp.max_n + 31) / 32;
+    const int key = ((lp.path * 2 + lp.precision) * 2 + (lp.owen ? 1 : 0)) * 64 + (lp.max_n + 31) / 32;
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return it->second;
     qcpw_option_spec probe;
@@ -720,7 +755,8 @@ int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
     std::vector<int> cands;
     for (int bd : {256, 512, 1024}) {
         LaunchPlan p;
-        if (plan_launch(ctx, &probe, 1, 0, 0, n_probe_shifts, lp.path, lp.precision, lp.pca_gemm, bd, p) != QCPW_OK)
+        if (plan_launch(ctx, &probe, 1, 0, 0, n_probe_shifts, lp.path, lp.precision, lp.pca_gemm, bd, p, nullptr,
+                        lp.owen) != QCPW_OK)
             continue;
         p.max_n = std::max(p.max_n, lp.max_n);
         p.stack_depth = std::max(p.stack_depth, lp.stack_depth);
@@ -862,12 +898,16 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
 }
 
 qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index, int32_t n_dims, int64_t k0,
-                                int64_t count, uint32_t *dev_out, hipStream_t stream)
+                                int64_t count, uint32_t *dev_out, hipStream_t stream, bool owen)
 {
     const int64_t first = k0 & ~int64_t(63);
     const int64_t blocks = (k0 + count - first + 63) / 64;
-    sobol_points_kernel<<<(unsigned)blocks, 64, 0, stream>>>(ctx->tab.dir, ctx->tab.lane, seed, shift_index,
-                                                             n_dims, k0, count, dev_out);
+    if (owen)
+        sobol_points_kernel<true><<<(unsigned)blocks, 64, 0, stream>>>(ctx->tab.dir, ctx->tab.lane, seed,
+                                                                       shift_index, n_dims, k0, count, dev_out);
+    else
+        sobol_points_kernel<false><<<(unsigned)blocks, 64, 0, stream>>>(ctx->tab.dir, ctx->tab.lane, seed,
+                                                                        shift_index, n_dims, k0, count, dev_out);
     QCPW_HIP(hipGetLastError());
     return QCPW_OK;
 }

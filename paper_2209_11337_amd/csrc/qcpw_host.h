@@ -100,6 +100,7 @@ struct LaunchPlan {
     int block_threads = 0;
     int64_t total_units = 0;
     int64_t full_blocks = 0;           // PCA_FULL in FP64: workgroups with a global scratch tile
+    bool owen = false;                 // nested scrambling instead of the digital shift
     std::vector<const Context::Pca *> pca;   // per sorted option (PCA and PCA_FULL)
 };
 
@@ -114,7 +115,7 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
 qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
                         int64_t n_points, int32_t n_shifts, int32_t path, int32_t precision,
                         int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp,
-                        const int64_t *k_begin = nullptr);
+                        const int64_t *k_begin = nullptr, bool owen = false);
 
 // Device bytes one launch needs in the workspace.
 size_t launch_workspace_bytes(const LaunchPlan &lp);
@@ -131,7 +132,8 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
                            bool timed = false);
 
 qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index, int32_t n_dims,
-                                int64_t k0, int64_t count, uint32_t *dev_out, hipStream_t stream);
+                                int64_t k0, int64_t count, uint32_t *dev_out, hipStream_t stream,
+                                bool owen = false);
 
 int autotune_block_threads(Context *ctx, const LaunchPlan &lp);
 

@@ -206,7 +206,7 @@ static qcpw_status enqueue_slot(qcpw_server *s, Slot &sl, std::vector<Request *>
     {
         std::lock_guard<std::mutex> lk(s->ctx->mu);   // plan_launch may add PCA factors
         st = plan_launch(s->ctx, specs.data(), n, 0, 0, L, batch[0]->path, s->cfg.precision, s->cfg.pca_gemm,
-                         s->cfg.block_threads, lp, kb.data());
+                         s->cfg.block_threads, lp, kb.data(), (s->cfg.flags & QCPW_FLAG_OWEN) != 0);
     }
     if (st != QCPW_OK) return st;
     const size_t need = launch_workspace_bytes(lp);
@@ -392,6 +392,7 @@ qcpw_status qcpw_server_create(const qcpw_run_config *cfg, int64_t hbm_budget_by
     c.device = -1;
     if (cfg) c = *cfg;
     if (c.precision != QCPW_FP64 && c.precision != QCPW_FP32_MIXED) return fail(QCPW_EINVAL, "unknown precision");
+    if (c.flags & ~QCPW_FLAG_OWEN) return fail(QCPW_EINVAL, "unknown flags for a server");
     if (!qcpw_block_threads_ok(c.block_threads))
         return fail(QCPW_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
     Context *ctx = nullptr;
@@ -418,6 +419,9 @@ qcpw_status qcpw_submit(qcpw_server *srv, const qcpw_option_spec *specs, int32_t
     qcpw_status st = validate_call(specs, n_opts, 0, kFirstPoints, n_shifts, path_construction, srv->cfg.precision,
                                    srv->cfg.pca_gemm, srv->cfg.block_threads);
     if (st != QCPW_OK) return st;
+    if ((srv->cfg.flags & QCPW_FLAG_OWEN) && path_construction != QCPW_PATH_BB &&
+        path_construction != QCPW_PATH_STANDARD)
+        return fail(QCPW_EINVAL, "nested scrambling is available with the BB and STANDARD constructions");
     std::unique_ptr<Request> r(new Request());
     r->specs.assign(specs, specs + n_opts);
     r->n_shifts = n_shifts;

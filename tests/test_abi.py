@@ -129,6 +129,14 @@ def test_full_pca_argument_checks():
         q.path_factor(q.PATH_PCA_FULL, 257, 1.0)
 
 
+def test_owen_flag_checks():
+    o = dict(type=0, d=16, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, seed=1, n_points=64)
+    for path in (q.PATH_PCA, q.PATH_PCA_FULL):
+        with pytest.raises(q.QcpwError) as ei:
+            q.greeks([o], 4, path, owen=True)
+        assert ei.value.status == -1 and "scrambling" in str(ei.value)
+
+
 def test_kernel_timer_argument_checks():
     for op in (0, 4, -1):
         with pytest.raises(q.QcpwError) as ei:

@@ -336,6 +336,50 @@ def test_pca_full_large_properties():
 
 
 # ------------------------------------------------------------------------
+# nested (Owen) scrambling instead of the digital shift
+# ------------------------------------------------------------------------
+@pytest.mark.parametrize("n_dims,k0,count,shift", [(16, 0, 4096, 0), (65, 0, 3000, 3), (365, 1000, 700, 7),
+                                                   (130, (1 << 20) - 50, 300, 31)])
+def test_scrambled_points_bit_exact(n_dims, k0, count, shift):
+    say("owen points", n_dims, k0, count, shift)
+    seed = 0x5C4A + n_dims
+    got = q.sobol_points(seed, shift, n_dims, k0, count, owen=True)
+    raw = oracle.sobol_points(n_dims, k0, count)
+    keys = oracle.shifts(seed, shift + 1, n_dims)[shift]
+    ref = raw.copy()
+    for j in range(1, n_dims):
+        ref[:, j] = [oracle.owen(int(y), int(keys[j])) for y in raw[:, j]]
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("path,d", [(q.PATH_BB, 16), (q.PATH_BB, 65), (q.PATH_STANDARD, 33)])
+def test_fp64_owen_parity(path, d):
+    opts = workloads.three_products_grid(d=d, n_points=4096 + 77)[::4]
+    say("owen fp64", path, d)
+    g, e, ps = q.greeks(opts, 3, path, q.FP64, per_shift=True, owen=True)
+    m, se, am, Cl = oracle_many_rand(opts, 3, path, oracle.RAND_OWEN)
+    assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
+
+
+@pytest.mark.parametrize("path,d", [(q.PATH_BB, 64), (q.PATH_BB, 65), (q.PATH_STANDARD, 17)])
+def test_fp32_owen_within_bound(path, d):
+    opts = workloads.three_products_grid(d=d, n_points=4096 + 77)[::3]
+    say("owen fp32", path, d)
+    g, e, ps = q.greeks(opts, 3, path, q.FP32_MIXED, per_shift=True, owen=True)
+    m, se, am, Cl = oracle_many_rand(opts, 3, path, oracle.RAND_OWEN)
+    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    for k in range(4):
+        assert err[..., k].max() <= FP32_TOL[k], (k, err[..., k].max())
+
+
+def oracle_many_rand(opts, L, path, rand):
+    out = [oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["seed"],
+                         o["n_points"], L, path, rand) for o in opts]
+    return (np.array([r["mean"] for r in out]), np.array([r["stderr"] for r in out]),
+            np.array([r["abs_mean"] for r in out]), np.array([r["C_l"] for r in out]))
+
+
+# ------------------------------------------------------------------------
 # serving: continuous batching
 # ------------------------------------------------------------------------
 def test_server_results_match_direct_calls_and_overlap():
