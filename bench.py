@@ -181,6 +181,20 @@ def main():
                                "sample": "the 18 options at d=64, 2^%d points x %d shifts (%.1f s)"
                                          % (int(np.log2(n_cpu)), Ls, tc)}
     if not a.no_extras:
+        # the same workload randomised by nested scrambling instead of the shift
+        q.greeks(opts, L, q.PATH_BB, prec, device_outputs=True, out=out, stream=stream, owen=True)
+        stream.synchronize()
+        q.kernel_timer(q.TIMER_START)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            q.greeks(opts, L, q.PATH_BB, prec, device_outputs=True, out=out, stream=stream, owen=True)
+        stream.synchronize()
+        w_owen = (time.perf_counter() - t0) / 3
+        k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
+        e_owen = out[1].cpu().numpy()
+        res["owen"] = {"value": n_paths / w_owen, "unit": "Greek-paths/s", "kernel_ms": k_ms / max(k_n, 1),
+                       "stderr_ratio_owen_over_shift": {k: float(np.median(e_owen[:, i] / e[:, i]))
+                                                        for i, k in enumerate(q.OUTPUTS)}}
         res["small_call"] = small_call_leg(q, workloads, torch)
         res["pca"] = pca_leg(q, workloads, torch)
     if not a.no_extras and not a.no_portfolio:
