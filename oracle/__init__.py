@@ -33,7 +33,7 @@ _JK_NPZ = None
 _lock = threading.Lock()
 _lib = None
 
-ARITH_ASIAN, BINARY_ASIAN, LOOKBACK = 0, 1, 2
+ARITH_ASIAN, BINARY_ASIAN, LOOKBACK, GEOMETRIC_ASIAN = 0, 1, 2, 3
 PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
 RAND_SHIFT, RAND_OWEN = 0, 1
 OUTPUTS = ("price", "delta", "vega", "gamma")

@@ -47,7 +47,7 @@
 
 #define ORC_MAX_BITS 32
 
-enum { ORC_ARITH = 0, ORC_BINARY = 1, ORC_LOOKBACK = 2 };
+enum { ORC_ARITH = 0, ORC_BINARY = 1, ORC_LOOKBACK = 2, ORC_GEOMETRIC = 3 };
 enum { ORC_BB = 0, ORC_PCA = 1, ORC_STANDARD = 2, ORC_PCA_FULL = 3 };
 enum { ORC_RAND_SHIFT = 0, ORC_RAND_OWEN = 1 };
 
@@ -331,6 +331,18 @@ void oracle_path_greeks(int type, int d, double S0, double K, double r,
         X = best;
         /* d S~max / d sigma = S~(t_j*) (W~ - sigma tau) at the argmax */
         VX = best * (W[jstar] - sigma * jstar * dt);
+    } else if (type == ORC_GEOMETRIC) {
+        /* geometric average: X = (prod_j S~(t_j))^{1/d} = S0 exp(mean_j (omega tau_j + sigma W~_j));
+         * like the arithmetic average it carries the common factor of x_1, so
+         * the same conditional payoff applies (Sec. 4.5 with another average) */
+        double lsum = 0.0, vsum = 0.0;
+        for (int m = 0; m < d; ++m) {
+            double tau = m * dt;
+            lsum += omega * tau + sigma * W[m];
+            vsum += W[m] - sigma * tau;
+        }
+        X = S0 * exp(lsum / d);
+        VX = X * vsum / d;
     } else {
         for (int m = 0; m < d; ++m) {
             double tau = m * dt;
@@ -357,7 +369,8 @@ void oracle_path_greeks(int type, int d, double S0, double K, double r,
         out[3] = D * phi0 / (S0 * S0 * s1) * (psi / s1 - 1.0);
     } else {
         /* G = e^{r(t1-T)} X [1 - Phi(psi - s1)] - e^{-rT} K [1 - Phi(psi)]
-         * (Sec. 4.5.2 arithmetic Asian, Sec. 4.5.3 lookback on the max) */
+         * (Sec. 4.5.2 arithmetic Asian, Sec. 4.5.3 lookback on the max; the
+         * geometric average enters the same way) */
         out[0] = D1 * X * Q1 - D * K * Q0;
         out[1] = D1 * (X / S0) * Q1;
         out[2] = D1 * Q1 * VX + D * K * phi0 * sqrt(t1);

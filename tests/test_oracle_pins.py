@@ -345,7 +345,7 @@ def _fd_check(typ, d, path, z, S0=100.0, K=100.0, r=0.05, sig=0.2, T=1.0):
     return g, np.array([g[0], delta, vega, gamma]), floor
 
 
-@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK])
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK, oracle.GEOMETRIC_ASIAN])
 @pytest.mark.parametrize("d,path", [(2, oracle.PATH_BB), (12, oracle.PATH_BB), (64, oracle.PATH_BB),
                                     (17, oracle.PATH_STANDARD), (33, oracle.PATH_PCA)])
 def test_greeks_equal_finite_differences_of_conditional_price(typ, d, path):
@@ -366,7 +366,7 @@ def test_lookback_vega_has_no_one_over_d():
     assert abs(fd[2]) > 2.0 * abs(fd[2] - 0.0) / d
 
 
-@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK])
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK, oracle.GEOMETRIC_ASIAN])
 @pytest.mark.parametrize("K", [90.0, 100.0, 115.0])
 def test_conditional_price_is_quadrature_of_unconditioned_payoff(typ, K):
     """G(theta, z) = E[discounted payoff | z]: integrate the original payoff
@@ -384,6 +384,8 @@ def test_conditional_price_is_quadrature_of_unconditioned_payoff(typ, K):
             # Black-Scholes path: W(t_j) = sqrt(t_1) x_1 + W~(t_j - t_1)
             W = math.sqrt(dt) * x1 + Wt
             S = S0 * np.exp((r - 0.5 * sig**2) * t + sig * W)
+            if typ == oracle.GEOMETRIC_ASIAN:
+                return math.exp(np.log(S).mean())
             return S.max() if typ == oracle.LOOKBACK else S.mean()
 
         def payoff(x1):
@@ -439,6 +441,64 @@ def test_rqmc_estimate_agrees_with_quadrature_at_three_dates():
     res = oracle.option(oracle.ARITH_ASIAN, d, S0, K, r, sig, T, 11, 1 << 12, 16)
     for i in range(4):
         assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-13 * abs(ref[i])
+
+
+# --------------------------------------------------------------------------
+# Geometric Asian call: exact lognormal closed form at any d
+# --------------------------------------------------------------------------
+
+def geometric_asian_closed_form(S0, K, r, sig, T, d):
+    """Price, delta, vega, gamma of the discretely monitored geometric Asian
+    call (dates jT/d, j = 1..d): ln G is normal with mean
+    ln S0 + (r - sig^2/2) mean(t_j) and variance sig^2 (1/d^2) sum min(t_j, t_k)."""
+    dt = T / d
+    tbar = dt * (d + 1) / 2
+    v = sig * math.sqrt(dt * (d + 1) * (2 * d + 1) / (6 * d))
+    mu = math.log(S0) + (r - sig**2 / 2) * tbar
+    D = math.exp(-r * T)
+    F = math.exp(mu + v * v / 2)
+    d2 = (mu - math.log(K)) / v
+    d1 = d2 + v
+    N, n = scipy.stats.norm.cdf, scipy.stats.norm.pdf
+    price = D * (F * N(d1) - K * N(d2))
+    delta = D * F * N(d1) / S0
+    gamma = D * F * n(d1) / (S0 * S0 * v)
+    mu_s, v_s = -sig * tbar, v / sig
+    vega = D * (F * (mu_s + v * v_s) * N(d1) + K * n(d2) * v_s)
+    return np.array([price, delta, vega, gamma])
+
+
+def test_geometric_closed_form_by_quadrature():
+    """The closed form above against direct quadrature of the lognormal
+    payoff, and its Greeks against finite differences of its price."""
+    S0, K, r, sig, T, d = 100.0, 104.0, 0.04, 0.3, 1.5, 9
+    ref = geometric_asian_closed_form(S0, K, r, sig, T, d)
+    dt = T / d
+    mu = math.log(S0) + (r - sig**2 / 2) * dt * (d + 1) / 2
+    v = sig * math.sqrt(dt * (d + 1) * (2 * d + 1) / (6 * d))
+    f = lambda x: max(math.exp(mu + v * x) - K, 0.0) * scipy.stats.norm.pdf(x)
+    price = math.exp(-r * T) * scipy.integrate.quad(f, (math.log(K) - mu) / v, 40, epsrel=1e-13)[0]
+    assert abs(price - ref[0]) < 1e-11 * ref[0]
+    h = 1e-4
+    fd = [(geometric_asian_closed_form(S0 + h, K, r, sig, T, d)[0] -
+           geometric_asian_closed_form(S0 - h, K, r, sig, T, d)[0]) / (2 * h),
+          (geometric_asian_closed_form(S0, K, r, sig + h, T, d)[0] -
+           geometric_asian_closed_form(S0, K, r, sig - h, T, d)[0]) / (2 * h),
+          (geometric_asian_closed_form(S0 + h, K, r, sig, T, d)[1] -
+           geometric_asian_closed_form(S0 - h, K, r, sig, T, d)[1]) / (2 * h)]
+    np.testing.assert_allclose(ref[1:], fd, rtol=1e-7)
+
+
+@pytest.mark.parametrize("d,path", [(1, oracle.PATH_BB), (12, oracle.PATH_BB), (64, oracle.PATH_BB),
+                                    (20, oracle.PATH_STANDARD), (16, oracle.PATH_PCA)])
+def test_geometric_estimate_matches_closed_form(d, path):
+    """The QMC-CPW estimate of the geometric Asian call is unbiased for the
+    exact price and Greeks: within 4 standard errors (plus 1e-12) at any d."""
+    S0, K, r, sig, T = 100.0, 98.0, 0.05, 0.25, 1.0
+    ref = geometric_asian_closed_form(S0, K, r, sig, T, d)
+    res = oracle.option(oracle.GEOMETRIC_ASIAN, d, S0, K, r, sig, T, 4711, 1 << 12, 16, path)
+    for i in range(4):
+        assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-12 * abs(ref[i]), (i, res["mean"], ref)
 
 
 # --------------------------------------------------------------------------
