@@ -44,8 +44,14 @@ enum {
     QCPW_ENOTFOUND = -7   /* unknown request id                               */
 };
 
-/* Product (Sec. 4.5.1 binary Asian, 4.5.2 arithmetic Asian, 4.5.3 lookback). */
-enum { QCPW_ARITH_ASIAN_CALL = 0, QCPW_BINARY_ASIAN_CALL = 1, QCPW_LOOKBACK_FIXED_CALL = 2 };
+/* Product (Sec. 4.5.1 binary Asian, 4.5.2 arithmetic Asian, 4.5.3 lookback).
+ * QCPW_GEOMETRIC_ASIAN_CALL: a call on the geometric average of S(t_j),
+ * j = 1..d -- one more payoff under the same conditional template (the
+ * extension Sec. 5 describes): its conditional price and Greeks take the
+ * arithmetic call's formulas with X the geometric mean, and log X is normal,
+ * so its expectation has a closed form to test against.                   */
+enum { QCPW_ARITH_ASIAN_CALL = 0, QCPW_BINARY_ASIAN_CALL = 1, QCPW_LOOKBACK_FIXED_CALL = 2,
+       QCPW_GEOMETRIC_ASIAN_CALL = 3 };
 
 /* Path construction.  The first three condition on the normal x_1 that
  * drives W(t_1) (Sec. 3.4.2) and build the d-1 remaining coordinates with a
@@ -57,7 +63,7 @@ enum { QCPW_ARITH_ASIAN_CALL = 0, QCPW_BINARY_ASIAN_CALL = 1, QCPW_LOOKBACK_FIXE
  *  QCPW_PATH_PCA_FULL principal components of the covariance of all d dates
  *                     (W(t_j), j = 1..d); the first component (largest
  *                     eigenvalue) is the conditioned variable instead of x_1
- *                     -- the principal-component conditioning Sec. 6 names
+ *                     -- the principal-component conditioning Sec. 7 names
  *                     for larger variance reduction.  Its breakpoint needs a
  *                     root-find (Newton, FP64).  Arithmetic and binary Asian
  *                     calls only; d <= QCPW_MAX_D_PCA_FULL.                */

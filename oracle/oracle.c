@@ -30,7 +30,7 @@
  *   - Digital shift of replication l, dimension j: high 32 bits of output
  *     number (l * 2^16 + j) of SplitMix64 seeded with the option's seed.
  *   - ORC_PCA_FULL (the principal-component conditioning the paper names as
- *     the route to larger variance reduction, Sec. 6): W(t_1..t_d) = A z with
+ *     the route to larger variance reduction, Sec. 7): W(t_1..t_d) = A z with
  *     A the d x d principal-component factor of the full covariance
  *     dt min(j, k); the first component z_1 (largest eigenvalue) is the
  *     conditioned variable, integrated out in closed form; z_2..z_d come from

@@ -159,13 +159,26 @@ struct PathSums {
     R bY, bm;         // running max of Y_m and its m (lookback; E = 2^Y once, at the end)
 };
 
-template <typename R, bool MAX>
+// What a date adds to the path statistic: the arithmetic average's sums,
+// the running maximum, or (geometric average) the sum of Y = log2 S~/S0.
+enum { QCPW_STAT_AVG = 0, QCPW_STAT_MAX = 1, QCPW_STAT_GEO = 2 };
+
+__host__ __device__ inline int qcpw_stat_of(int type)
+{
+    return type == QCPW_LOOKBACK_FIXED_CALL ? QCPW_STAT_MAX
+           : type == QCPW_GEOMETRIC_ASIAN_CALL ? QCPW_STAT_GEO
+                                               : QCPW_STAT_AVG;
+}
+
+template <typename R, int MODE>
 __device__ inline void consume(PathSums<R> &ps, R Y, R mf)
 {
-    if (MAX) {
+    if (MODE == QCPW_STAT_MAX) {
         const bool take = (Y > ps.bY) || (Y == ps.bY && mf < ps.bm);   // lowest index wins ties
         ps.bY = take ? Y : ps.bY;
         ps.bm = take ? mf : ps.bm;
+    } else if (MODE == QCPW_STAT_GEO) {
+        ps.A2y += Y;
     } else {
         const R E = exp2_r(Y);
         ps.A1 += E;
@@ -230,7 +243,7 @@ __device__ inline double ln_f64(double x)
 
 // exp x for x <= 0 (underflows to 0 below about -745): x = k ln 2 + r,
 // |r| <= ln2/2, e^r by its Taylor series to r^13, scaled by 2^k.
-__device__ inline double exp_neg_f64(double x)
+__device__ inline double exp_neg_f64(double x)   // any |x| < 700 (named for its use on -psi^2/2)
 {
     const double k = rint(x * 1.44269504088896340736);
     double r = fma(-k, 6.93147180369123816490e-01, x);
@@ -291,14 +304,20 @@ __device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, dou
 }
 
 template <typename R>
-__device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, bool is_max, double F[4])
+__device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, int mode, double F[4])
 {
     const OptDev &op = *reread(&op_in);
     double A, Xs, VXs;
-    if (is_max) {
+    if (mode == QCPW_STAT_MAX) {
         A = (double)exp2_r(ps.bY);
         Xs = A;
         VXs = A * ((double)ps.bY - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
+    } else if (mode == QCPW_STAT_GEO) {
+        // X/S0 = 2^{mean Y}; sum over dates of (W~ - sigma tau) = (sum Y - kappa sum m)/(sigma log2 e)
+        const double sy = (double)ps.A2y;
+        A = exp_neg_f64(sy * op.invd * 0.69314718055994530942);
+        Xs = A;
+        VXs = A * (sy - op.kappa * 0.5 * (double)op.n * (double)(op.n + 1)) * op.invd * op.inv_sig_log2e;
     } else {
         A = (double)ps.A1;                      // ln d is folded into c0
         Xs = A * op.invd;

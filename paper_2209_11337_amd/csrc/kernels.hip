@@ -67,7 +67,7 @@ struct UParts {
     }
 };
 
-template <bool F32, bool MAX, bool OWEN>
+template <bool F32, int MODE, bool OWEN>
 __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
                                        const float4 *lds_tab, typename Real<F32>::T *stk, int lane,
                                        const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps)
@@ -84,7 +84,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
         const R sd = F32 ? (R)st.sd * op.zs_t : (R)plan64[0].sd;
         const R drift = F32 ? (R)op.ydrift_n_f : (R)op.ydrift_n;
         Rr = fma(sd, z, drift);
-        consume<R, MAX>(ps, Rr, F32 ? (R)st.mf : (R)plan64[0].mf);
+        consume<R, MODE>(ps, Rr, F32 ? (R)st.mf : (R)plan64[0].mf);
     }
 #pragma unroll
     for (int q = 0; q < QCPW_UQ; ++q) {
@@ -115,7 +115,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
                 mf = s64.mf;
             }
             Rr = Ym;
-            consume<R, MAX>(ps, Ym, mf);
+            consume<R, MODE>(ps, Ym, mf);
         }
         if (s_hi >= n) break;
     }
@@ -131,7 +131,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
 // the same constexpr functions); price, delta and gamma come out bit-identical
 // to the plan walker's, vega (from the FP32 sums of E Y and E m) within FP32
 // rounding.  Removes about a quarter of the VALU work per date.
-template <bool MAX, bool OWEN, int N, int LO, int HI>
+template <int MODE, bool OWEN, int N, int LO, int HI>
 __device__ __forceinline__ void fixed_interval(const uint32_t *row0, const float4 *tab, float zs,
                                                const UParts<OWEN> &U, float WL, float WR,
                                                PathSums<float> &ps)
@@ -147,13 +147,13 @@ __device__ __forceinline__ void fixed_interval(const uint32_t *row0, const float
         const uint32_t x = U.bits(row0[(DIM - 1) * 64], S / 64, S % 64);
         const float z = ninv_table_f32(x, tab);
         const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
-        consume<float, MAX>(ps, Ym, (float)M);
-        fixed_interval<MAX, OWEN, N, LO, M>(row0, tab, zs, U, WL, Ym, ps);
-        fixed_interval<MAX, OWEN, N, M, HI>(row0, tab, zs, U, Ym, WR, ps);
+        consume<float, MODE>(ps, Ym, (float)M);
+        fixed_interval<MODE, OWEN, N, LO, M>(row0, tab, zs, U, WL, Ym, ps);
+        fixed_interval<MODE, OWEN, N, M, HI>(row0, tab, zs, U, Ym, WR, ps);
     }
 }
 
-template <bool MAX, bool OWEN, int N>
+template <int MODE, bool OWEN, int N>
 __device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_t *lds_lane, const float4 *tab,
                                                  int lane, const UParts<OWEN> &U, PathSums<float> &ps)
 {
@@ -162,26 +162,26 @@ __device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_
     constexpr float sd0 = (float)qcpw_csqrt((double)N);
     const float z = ninv_table_f32(U.bits(row0[0], 0, 0), tab);   // terminal point, dimension 1
     const float WR = fmaf(sd0 * zs, z, op.ydrift_n_f);
-    consume<float, MAX>(ps, WR, (float)N);
-    fixed_interval<MAX, OWEN, N, 0, N>(row0, tab, zs, U, 0.0f, WR, ps);
+    consume<float, MODE>(ps, WR, (float)N);
+    fixed_interval<MODE, OWEN, N, 0, N>(row0, tab, zs, U, 0.0f, WR, ps);
 }
 
 // true if op.n has a compile-time bridge (then the path is done)
-template <bool MAX, bool OWEN>
+template <int MODE, bool OWEN>
 __device__ inline bool bridge_fixed_any(const OptDev &op, const uint32_t *lds_lane, const float4 *tab, int lane,
                                         const UParts<OWEN> &U, PathSums<float> &ps)
 {
     if (!qcpw_has_fixed_bridge(op.n)) return false;
     switch (op.n) {
-    case 15: run_bridge_fixed<MAX, OWEN, 15>(op, lds_lane, tab, lane, U, ps); return true;
-    case 31: run_bridge_fixed<MAX, OWEN, 31>(op, lds_lane, tab, lane, U, ps); return true;
-    case 63: run_bridge_fixed<MAX, OWEN, 63>(op, lds_lane, tab, lane, U, ps); return true;
-    case 127: run_bridge_fixed<MAX, OWEN, 127>(op, lds_lane, tab, lane, U, ps); return true;
+    case 15: run_bridge_fixed<MODE, OWEN, 15>(op, lds_lane, tab, lane, U, ps); return true;
+    case 31: run_bridge_fixed<MODE, OWEN, 31>(op, lds_lane, tab, lane, U, ps); return true;
+    case 63: run_bridge_fixed<MODE, OWEN, 63>(op, lds_lane, tab, lane, U, ps); return true;
+    case 127: run_bridge_fixed<MODE, OWEN, 127>(op, lds_lane, tab, lane, U, ps); return true;
     default: return false;
     }
 }
 
-template <bool F32, bool MAX, bool OWEN>
+template <bool F32, int MODE, bool OWEN>
 __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, const float4 *lds_tab, int lane,
                                          const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps)
 {
@@ -197,9 +197,26 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
             const uint32_t y = U.bits(lds_lane[s * 64 + lane], q, s - 64 * q);
             const R z = coord_tab<F32>(y, op, lds_tab);
             Y = Y + fma(zs, z, drift);
-            consume<R, MAX>(ps, Y, (R)(s + 1));
+            consume<R, MODE>(ps, Y, (R)(s + 1));
         }
         if (s_hi >= n) break;
+    }
+}
+
+// One wave's 64 paths from the terminal point (bridge) or the first step
+// (standard) to the last date, accumulated into ps.
+template <bool F32, int PATHK, bool OWEN, int MODE>
+__device__ inline void walk_path(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
+                                 const float4 *lds_tab, typename Real<F32>::T *stk, int lane,
+                                 const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps, int fixed_bridges)
+{
+    if constexpr (PATHK == QCPW_PATH_BB) {
+        if constexpr (F32) {
+            if (fixed_bridges && bridge_fixed_any<MODE, OWEN>(op, lds_lane, lds_tab, lane, U, ps)) return;
+        }
+        run_bridge_wave<F32, MODE, OWEN>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
+    } else {
+        run_standard_wave<F32, MODE, OWEN>(op, lds_lane, lds_tab, lane, U, ps);
     }
 }
 
@@ -332,7 +349,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
         const int64_t k_end = op.k_begin + op.n_points;
         const int64_t start = op.k_begin + chunk * op.unit_pts;
         const int64_t end = min(start + (int64_t)op.unit_pts, k_end);
-        const bool is_max = op.type == QCPW_LOOKBACK_FIXED_CALL;
+        const int mode = qcpw_stat_of(op.type);
         UParts<OWEN> U;
         init_uniform_part<PATHK, OWEN>(ld, op, shift, lane, (uint64_t)start, U);
         for (int64_t base = start; base < end; base += 64) {
@@ -341,24 +358,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
             PathSums<R> ps;
             init_sums(ps);
             if (op.n > 0) {
-                if (PATHK == QCPW_PATH_BB) {
-                    bool done = false;
-                    if constexpr (F32) {
-                        if (fixed_bridges)
-                            done = is_max ? bridge_fixed_any<true, OWEN>(op, lds_lane, lds_tab, lane, U, ps)
-                                          : bridge_fixed_any<false, OWEN>(op, lds_lane, lds_tab, lane, U, ps);
-                    }
-                    if (!done) {
-                        if (is_max) run_bridge_wave<F32, true, OWEN>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
-                        else run_bridge_wave<F32, false, OWEN>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
-                    }
-                } else {
-                    if (is_max) run_standard_wave<F32, true, OWEN>(op, lds_lane, lds_tab, lane, U, ps);
-                    else run_standard_wave<F32, false, OWEN>(op, lds_lane, lds_tab, lane, U, ps);
+                switch (mode) {
+                case QCPW_STAT_MAX:
+                    walk_path<F32, PATHK, OWEN, QCPW_STAT_MAX>(ld, op, lds_lane, lds_tab, stk, lane, U, ps, fixed_bridges);
+                    break;
+                case QCPW_STAT_GEO:
+                    walk_path<F32, PATHK, OWEN, QCPW_STAT_GEO>(ld, op, lds_lane, lds_tab, stk, lane, U, ps, fixed_bridges);
+                    break;
+                default:
+                    walk_path<F32, PATHK, OWEN, QCPW_STAT_AVG>(ld, op, lds_lane, lds_tab, stk, lane, U, ps, fixed_bridges);
                 }
             }
             if (valid) {
-                path_tail<R>(op, ps, is_max, F);
+                path_tail<R>(op, ps, mode, F);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc_add(s[i], c[i], F[i]);
             }
@@ -506,9 +518,9 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
         const int di = d ? d : sp.d;
         const int64_t Ni = n_points ? n_points : sp.n_points;
         if (sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL &&
-            sp.type != QCPW_LOOKBACK_FIXED_CALL)
+            sp.type != QCPW_LOOKBACK_FIXED_CALL && sp.type != QCPW_GEOMETRIC_ASIAN_CALL)
             return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": unknown type");
-        if (path == QCPW_PATH_PCA_FULL && sp.type == QCPW_LOOKBACK_FIXED_CALL)
+        if (path == QCPW_PATH_PCA_FULL && sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL)
             return fail(QCPW_EINVAL, "option " + std::to_string(i) +
                                          ": conditioning on the first principal component covers "
                                          "arithmetic and binary Asian calls only");
@@ -592,7 +604,7 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.sqrt_t1 = std::sqrt(t1);
         op.inv_sigma = 1.0 / sp.sigma;
         op.c0 = std::log(sp.K) - std::log(sp.S0) - omega * t1 +
-                (sp.type == QCPW_LOOKBACK_FIXED_CALL ? 0.0 : std::log((double)di));
+                (sp.type == QCPW_ARITH_ASIAN_CALL || sp.type == QCPW_BINARY_ASIAN_CALL ? std::log((double)di) : 0.0);
         op.h = std::exp(op.c0 - 0.5 * op.s1 * op.s1);
         op.S0 = sp.S0;
         op.K = sp.K;

@@ -82,12 +82,14 @@ __device__ inline uint32_t uniform_part(const uint32_t *__restrict__ dir, uint64
     return u;
 }
 
-// Per-point sums of a path piece: the averages' sums and the running maximum
-// of E with its Y and m (compared on E, lowest m wins ties).
+// Per-point sums of a path piece: the arithmetic average's sums, the running
+// maximum of E with its Y and m (compared on E, lowest m wins ties) and the
+// sum of Y (geometric average).
 template <typename R>
 struct PcaSums {
     R A1, A2y, A2m;
     R bE, bY, bm;
+    R sY;
 };
 
 template <typename R>
@@ -95,6 +97,7 @@ __device__ inline void sums_neutral(PcaSums<R> &ps)
 {
     ps.A1 = R(0); ps.A2y = R(0); ps.A2m = R(0);
     ps.bE = R(0); ps.bY = R(0); ps.bm = R(1e30);
+    ps.sY = R(0);
 }
 
 template <typename R>
@@ -103,6 +106,7 @@ __device__ inline void sums_merge(PcaSums<R> &a, const PcaSums<R> &b)
     a.A1 += b.A1;
     a.A2y += b.A2y;
     a.A2m += b.A2m;
+    a.sY += b.sY;
     const bool take = (b.bE > a.bE) || (b.bE == a.bE && b.bm < a.bm);
     a.bE = take ? b.bE : a.bE;
     a.bY = take ? b.bY : a.bY;
@@ -116,6 +120,7 @@ __device__ inline void sums_add_date(PcaSums<R> &ps, R Y, R mf)
     ps.A1 += E;
     ps.A2y = fma(E, Y, ps.A2y);
     ps.A2m = fma(E, mf, ps.A2m);
+    ps.sY += Y;
     const bool take = (E > ps.bE) || (E == ps.bE && mf < ps.bm);
     ps.bE = take ? E : ps.bE;
     ps.bY = take ? Y : ps.bY;
@@ -132,6 +137,7 @@ __device__ inline PcaSums<R> shfl_xor_sums(const PcaSums<R> &p, int off)
     q.bE = __shfl_xor(p.bE, off, 64);
     q.bY = __shfl_xor(p.bY, off, 64);
     q.bm = __shfl_xor(p.bm, off, 64);
+    q.sY = __shfl_xor(p.sY, off, 64);
     return q;
 }
 
@@ -144,13 +150,15 @@ __device__ inline void tile_tail(const OptDev &op, const PcaSums<R> *red, int la
     PcaSums<R> ps;
     ps.A1 = R(1); ps.A2y = R(0); ps.A2m = R(0);   // date 1: E = 1, Y = 0, m = 0
     ps.bE = R(1); ps.bY = R(0); ps.bm = R(0);
+    ps.sY = R(0);
     for (int i = 0; i < nwaves_pt; ++i) sums_merge(ps, red[waves_pt[i] * TP + lane]);
     if (valid) {
+        const int mode = qcpw_stat_of(op.type);
         PathSums<R> t;
-        t.A1 = ps.A1; t.A2y = ps.A2y; t.A2m = ps.A2m;
+        t.A1 = ps.A1; t.A2y = mode == QCPW_STAT_GEO ? ps.sY : ps.A2y; t.A2m = ps.A2m;
         t.bY = ps.bY; t.bm = ps.bm;   // the tail forms E = 2^bY, the same value as bE
         double F[4];
-        path_tail<R>(op, t, op.type == QCPW_LOOKBACK_FIXED_CALL, F);
+        path_tail<R>(op, t, mode, F);
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc_add(s[k], c[k], F[k]);
     }

@@ -155,7 +155,7 @@ struct OptDev {
     double ydrift_1;              // omega * dt * log2(e): drift per step (standard)
     double kappa;                 // (r + sigma^2/2) dt log2(e): W - sigma tau = (Y - kappa m)/(sigma log2 e)
     double inv_sig_log2e;         // 1 / (sigma log2(e))
-    double c0;                    // ln K - ln S0 - omega t1 (+ ln d for averages)
+    double c0;                    // ln K - ln S0 - omega t1 (+ ln d for the arithmetic average)
     double h;                     // exp(c0 - s1^2/2)
     double inv_s1, s1, sqrt_t1, inv_sigma;
     double S0, K, D, D1, invd, inv_S0, inv_S0sq;

@@ -332,7 +332,8 @@ static void retire_slot(qcpw_server *s, Slot &sl)
 
 static void worker_main(qcpw_server *s)
 {
-    hipSetDevice(s->ctx->tab.device);
+    // without its device the worker enqueues nothing and cancels every batch
+    const bool dev_ok = hipSetDevice(s->ctx->tab.device) == hipSuccess;
     uint64_t seq = 0, slot_seq[kSlots] = {};
     for (;;) {
         std::vector<Request *> batch;
@@ -354,7 +355,7 @@ static void worker_main(qcpw_server *s)
         }
         if (!batch.empty()) {
             Slot &sl = s->slots[free_slot];
-            if (enqueue_slot(s, sl, batch, bk0, blen) == QCPW_OK) {
+            if (dev_ok && enqueue_slot(s, sl, batch, bk0, blen) == QCPW_OK) {
                 slot_seq[free_slot] = ++seq;
                 ++busy;
             } else {
@@ -530,8 +531,8 @@ qcpw_status qcpw_server_destroy(qcpw_server *srv)
                 finish_locked(srv, kv.second.get(), RQ_CANCELLED);
     }
     for (auto &sl : srv->slots) {
-        if (sl.ws.ptr) hipFree(sl.ws.ptr);
-        if (sl.stream) hipStreamDestroy(sl.stream);
+        if (sl.ws.ptr) (void)hipFree(sl.ws.ptr);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     delete srv;
     return QCPW_OK;

@@ -380,6 +380,55 @@ def oracle_many_rand(opts, L, path, rand):
 
 
 # ------------------------------------------------------------------------
+# geometric Asian call: the same template with another average
+# ------------------------------------------------------------------------
+@pytest.mark.parametrize("path", [q.PATH_BB, q.PATH_STANDARD, q.PATH_PCA])
+@pytest.mark.parametrize("d", [2, 64, 100])
+def test_fp64_geometric_parity(path, d):
+    opts = workloads.geometric_grid(d=d, n_points=2 * 8192 + 77)
+    say("geometric fp64", path, d)
+    g, e, ps = q.greeks(opts, 3, path, q.FP64, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 3, path)
+    assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
+    assert_scaled(g, m, am, TOL64, "mean")
+
+
+@pytest.mark.parametrize("path,d,gemm", [(q.PATH_BB, 64, 0), (q.PATH_BB, 65, 0), (q.PATH_STANDARD, 64, 0),
+                                         (q.PATH_PCA, 64, q.GEMM_FP32), (q.PATH_PCA, 64, q.GEMM_BF16X3)])
+def test_fp32_geometric_within_bound(path, d, gemm):
+    opts = workloads.geometric_grid(d=d, n_points=8192 + 300)
+    say("geometric fp32", path, d, gemm)
+    g, e, ps = q.greeks(opts, 2, path, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 2, path)
+    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    say("geometric fp32 scaled error", err.max(axis=(0, 1)))
+    tol = BF16X3_TOL if (path == q.PATH_PCA and gemm == q.GEMM_BF16X3) else FP32_TOL
+    for k in range(4):
+        assert err[..., k].max() <= tol[k], (k, err[..., k].max())
+
+
+@pytest.mark.parametrize("path,prec", [(q.PATH_BB, q.FP32_MIXED), (q.PATH_BB, q.FP64),
+                                       (q.PATH_STANDARD, q.FP32_MIXED), (q.PATH_PCA, q.FP32_MIXED)])
+def test_geometric_full_size_matches_closed_form(path, prec):
+    """6 geometric calls, d = 64, 2^20 points x 32 shifts: every Greek lies
+    within 5 reported standard errors of the exact discrete-monitoring value
+    (plus the FP32 bound where the path runs in FP32), and the standard
+    errors are the spread of the replications."""
+    from closed_forms import geometric_asian_closed_form
+    opts = workloads.geometric_grid(d=64, n_points=1 << 20)
+    say("geometric full size", path, prec)
+    g, e, ps = q.greeks(opts, 32, path, prec, per_shift=True)
+    exact = np.array([geometric_asian_closed_form(o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["d"])
+                      for o in opts])
+    slack = 0.0 if prec == q.FP64 else 1.0
+    z = np.abs(g - exact) / (5 * e + slack * FP32_TOL[None, :] * np.abs(exact))
+    say("geometric |g - exact| / allowed:", z.max(axis=0), "stderr / |exact|:", (e / np.abs(exact)).max(axis=0))
+    assert (z <= 1).all(), z
+    se = ps.std(axis=1, ddof=1) / np.sqrt(32)
+    assert np.allclose(se, e, rtol=1e-9, atol=1e-300)
+
+
+# ------------------------------------------------------------------------
 # serving: continuous batching
 # ------------------------------------------------------------------------
 def test_server_results_match_direct_calls_and_overlap():

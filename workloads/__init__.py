@@ -19,9 +19,10 @@ from __future__ import annotations
 
 import numpy as np
 
-ARITH_ASIAN, BINARY_ASIAN, LOOKBACK = 0, 1, 2
+ARITH_ASIAN, BINARY_ASIAN, LOOKBACK, GEOMETRIC_ASIAN = 0, 1, 2, 3
 PATH_BB, PATH_PCA, PATH_STANDARD = 0, 1, 2
-TYPE_NAMES = {ARITH_ASIAN: "arith_asian", BINARY_ASIAN: "binary_asian", LOOKBACK: "lookback"}
+TYPE_NAMES = {ARITH_ASIAN: "arith_asian", BINARY_ASIAN: "binary_asian", LOOKBACK: "lookback",
+              GEOMETRIC_ASIAN: "geometric_asian"}
 
 BASE_SEED = 0x220911337
 
@@ -64,6 +65,17 @@ def paper_grid(d: int = 64, n_points: int = 1 << 15) -> list[dict]:
             out.append(dict(type=typ, d=d, S0=100.0, K=K, r=0.1, sigma=0.2, T=1.0,
                             n_points=n_points))
     for o, s in zip(out, _seeds(len(out), BASE_SEED + 1)):
+        o["seed"] = s
+    return out
+
+
+def geometric_grid(d: int = 64, n_points: int = 1 << 20) -> list[dict]:
+    """6 geometric Asian calls: K {90,100,110} x sigma {0.1, 0.3}; S0 = 100,
+    r = 0.05, T = 1, d dates (default 64) -- the three-product grid's setting
+    for the one product whose expectation has a closed form."""
+    out = [dict(type=GEOMETRIC_ASIAN, d=d, S0=100.0, K=K, r=0.05, sigma=sig, T=1.0, n_points=n_points)
+           for K in (90.0, 100.0, 110.0) for sig in (0.1, 0.3)]
+    for o, s in zip(out, _seeds(len(out), BASE_SEED + 3)):
         o["seed"] = s
     return out
 
