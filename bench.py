@@ -195,6 +195,7 @@ def main():
         res["owen"] = {"value": n_paths / w_owen, "unit": "Greek-paths/s", "kernel_ms": k_ms / max(k_n, 1),
                        "stderr_ratio_owen_over_shift": {k: float(np.median(e_owen[:, i] / e[:, i]))
                                                         for i, k in enumerate(q.OUTPUTS)}}
+        res["geometric"] = geometric_leg(q, workloads, torch, prec)
         res["small_call"] = small_call_leg(q, workloads, torch)
         res["pca"] = pca_leg(q, workloads, torch)
     if not a.no_extras and not a.no_portfolio:
@@ -202,6 +203,36 @@ def main():
     if not a.no_extras and not a.no_serve:
         res["serving"] = serving_leg(q, workloads)
     print(json.dumps(res), flush=True)
+
+
+def geometric_leg(q, workloads, torch, prec, L=32, steps=3):
+    """Six geometric Asian calls on the main workload's setting (d = 64, bridge,
+    2^20 points x 32 shifts): rate, kernel time, and the distance of every
+    estimate from the closed form of the discretely monitored geometric call
+    in reported standard errors."""
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    from closed_forms import geometric_asian_closed_form
+    dev = torch.device("cuda", 0)
+    opts = workloads.geometric_grid(d=64, n_points=1 << 20)
+    out = (torch.empty((len(opts), 4), dtype=torch.float64, device=dev),
+           torch.empty((len(opts), 4), dtype=torch.float64, device=dev))
+    stream = torch.cuda.Stream()
+    q.greeks(opts, L, q.PATH_BB, prec, device_outputs=True, out=out, stream=stream)
+    stream.synchronize()
+    q.kernel_timer(q.TIMER_START)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        q.greeks(opts, L, q.PATH_BB, prec, device_outputs=True, out=out, stream=stream)
+    stream.synchronize()
+    w = (time.perf_counter() - t0) / steps
+    k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
+    g, e = out[0].cpu().numpy(), out[1].cpu().numpy()
+    exact = np.array([geometric_asian_closed_form(o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["d"])
+                      for o in opts])
+    z = np.abs(g - exact) / e
+    return {"value": workloads.total_paths(opts, L) / w, "unit": "Greek-paths/s", "kernel_ms": k_ms / max(k_n, 1),
+            "max_abs_err_in_stderr": {k: float(z[:, i].max()) for i, k in enumerate(q.OUTPUTS)},
+            "stderr_max_rel": {k: float((e[:, i] / np.abs(exact[:, i])).max()) for i, k in enumerate(q.OUTPUTS)}}
 
 
 def small_call_leg(q, workloads, torch, calls=200):
