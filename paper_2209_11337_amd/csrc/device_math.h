@@ -71,17 +71,6 @@ __device__ inline float ninv_scaled_f32(uint32_t y, float sa)
     return p * xs;
 }
 
-// Sign folding of a 32-bit Sobol integer y: fold(y) keeps bit 31 and, when
-// it is set, complements bits 0..30, so the low 31 bits are min(y, ~y) and
-// bit 31 says whether u = (y + 1/2) 2^-32 lies above 1/2.  fold is linear
-// over XOR (fold(a ^ b) = fold(a) ^ fold(b)), so it is applied to the lane
-// table and to the wave-uniform part separately, and the kernels combine
-// the folded halves with one XOR per coordinate.
-__host__ __device__ inline uint32_t fold_sign(uint32_t y)
-{
-    return y ^ ((uint32_t)((int32_t)y >> 31) >> 1);
-}
-
 // Nested (Owen) scrambling of one 32-bit coordinate in base 2 (Sec. 2.2.3):
 // digit k (k = 1 most significant) is flipped by a function of digits
 // 1..k-1 only.  On the bit-reversed value that is what a seeded addition
@@ -98,27 +87,31 @@ __device__ inline uint32_t owen_scramble(uint32_t y, uint32_t seed)
     return __builtin_bitreverse32(v);
 }
 
-// Phi^{-1}((y + 1/2) 2^-32) in FP32 for folded x = fold(y), from the cubic
-// table of ninv_table.inc held in LDS at `tab`: q = float(m), m the low 31
-// bits of x; bits 23-c..27 of q (c = QCPW_NINV_CELL_BITS) select the cell and the cubic is evaluated in
-// q itself, giving Phi^{-1}((m + 1/2) 2^-32) <= 0; bit 31 of x is the sign.
-__device__ inline float ninv_table_f32(uint32_t x, const float4 *__restrict__ tab)
+// Phi^{-1}((y + 1/2) 2^-32) in FP32 for the raw 32-bit Sobol coordinate y,
+// from the cubic tables of ninv_table.inc held in LDS at address 0 (lower
+// half) and QCPW_LDS_TAB_HI (upper half).  q = float(int32(y)) is y itself
+// below 2^31 and -(2^32 - y) above; bits 16..31 of q masked with 0x8FF0 are
+// the LDS address of the cell (sign: which half; low exponent and top
+// mantissa bits: which cell), and the cubic is evaluated in |q| (a free
+// source modifier).  Each half's table carries its own sign.
+__device__ inline float ninv_table_f32(uint32_t y)
 {
-    const float q = (float)(x & 0x7FFFFFFFu);
-    const uint32_t b = __float_as_uint(q);
-    constexpr uint32_t sh = 19 - QCPW_NINV_CELL_BITS;   // byte offset = 16 x bits (23 - CELL_BITS)..27
-    constexpr uint32_t mask = ((1u << (QCPW_NINV_CELL_BITS + 5)) - 1u) << 4;
-    const float4 c = *(const float4 *)((const char *)tab + ((b >> sh) & mask));
-    const float p = fmaf(fmaf(fmaf(c.x, q, c.y), q, c.z), q, c.w);
-    return __uint_as_float(__float_as_uint(p) ^ (x & 0x80000000u));
+    static_assert(QCPW_NINV_CELL_BITS == 3 && QCPW_LDS_TAB_HI == 0x8000, "cell address = (bits >> 16) & 0x8FF0");
+    const float q = (float)(int32_t)y;
+    const uint32_t addr = (__float_as_uint(q) >> 16) & 0x8FF0u;
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    const f32x4 c = *(const __attribute__((address_space(3))) f32x4 *)addr;
+    const float a = fabsf(q);
+    return fmaf(fmaf(fmaf(c.x, a, c.y), a, c.z), a, c.w);
 }
 
-// Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library) for folded x = fold(y),
-// evaluated on the lower half so that 1 - u never has to be formed.
-__device__ inline double ninv_f64(uint32_t x)
+// Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library), evaluated on the
+// lower half (m = min(y, ~y)) so that 1 - u never has to be formed.
+__device__ inline double ninv_f64(uint32_t y)
 {
-    const double v = normcdfinv(((double)(x & 0x7FFFFFFFu) + 0.5) * 0x1p-32);   // <= 0
-    return (x >> 31) ? -v : v;
+    const uint32_t m = (y >> 31) ? ~y : y;
+    const double v = normcdfinv(((double)m + 0.5) * 0x1p-32);   // <= 0
+    return (y >> 31) ? -v : v;
 }
 
 __device__ inline float exp2_r(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -340,16 +333,16 @@ struct Real<true> { using T = float; };
 template <>
 struct Real<false> { using T = double; };
 
-// Inverse normal of one folded coordinate x = fold(y): FP32 from the LDS
-// cubic table as a standard normal (the caller applies the option's scale
+// Inverse normal of one Sobol coordinate y (raw 32 bits): FP32 from the LDS
+// cubic tables as a standard normal (the caller applies the option's scale
 // sigma sqrt(dt) log2(e)), FP64 already in Y units.
 template <bool F32>
-__device__ inline typename Real<F32>::T coord_tab(uint32_t x, const OptDev &op, const float4 *tab)
+__device__ inline typename Real<F32>::T coord_tab(uint32_t y, const OptDev &op)
 {
     if constexpr (F32) {
-        return ninv_table_f32(x, tab);
+        return ninv_table_f32(y);
     } else {
-        return ninv_f64(x) * op.zscale;
+        return ninv_f64(y) * op.zscale;
     }
 }
 
@@ -360,7 +353,7 @@ __device__ inline typename Real<F32>::T coord(uint32_t y, const OptDev &op)
     if constexpr (F32) {
         return ninv_scaled_f32(y, op.zs_a);
     } else {
-        return ninv_f64(fold_sign(y)) * op.zscale;
+        return ninv_f64(y) * op.zscale;
     }
 }
 

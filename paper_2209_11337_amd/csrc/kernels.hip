@@ -59,17 +59,25 @@ template <bool OWEN>
 struct UParts {
     uint32_t U[QCPW_UQ];
     uint32_t Sd[OWEN ? QCPW_UQ : 1];
-    // folded randomised coordinate of step 64 q + k from the lane's table word
+    // randomised coordinate of step 64 q + k from the lane's table word
     __device__ __forceinline__ uint32_t bits(uint32_t lane_word, int q, int k) const
     {
-        if constexpr (OWEN) return fold_sign(owen_scramble(lane_word ^ rdlane(U[q], k), rdlane(Sd[q], k)));
+        if constexpr (OWEN) return owen_scramble(lane_word ^ rdlane(U[q], k), rdlane(Sd[q], k));
         else return lane_word ^ rdlane(U[q], k);
     }
 };
 
+// LDS word of lane-table row r: around the inverse-normal cells in the FP32
+// kernels (qcpw_row_word), contiguous from 0 in the FP64 kernels.
+template <bool F32>
+__device__ __forceinline__ int lane_row(int r)
+{
+    return F32 ? qcpw_row_word(r) : 64 * r;
+}
+
 template <bool F32, int MODE, bool OWEN>
 __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
-                                       const float4 *lds_tab, typename Real<F32>::T *stk, int lane,
+                                       typename Real<F32>::T *stk, int lane,
                                        const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
@@ -79,8 +87,8 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
     R L = R(0), Rr;
     {   // terminal point
         const PlanStep st = plan[0];
-        const uint32_t x = U.bits(lds_lane[st.lds_off + lane], 0, 0);
-        const R z = coord_tab<F32>(x, op, lds_tab);
+        const uint32_t x = U.bits(lds_lane[(F32 ? st.lds_off : (st.dim - 1) * 64) + lane], 0, 0);
+        const R z = coord_tab<F32>(x, op);
         const R sd = F32 ? (R)st.sd * op.zs_t : (R)plan64[0].sd;
         const R drift = F32 ? (R)op.ydrift_n_f : (R)op.ydrift_n;
         Rr = fma(sd, z, drift);
@@ -102,8 +110,8 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
                 L = st.pops == 1 ? Rr : slot[64];
                 Rr = r;
             }
-            const uint32_t x = U.bits(lds_lane[st.lds_off + lane], q, s - 64 * q);
-            const R z = coord_tab<F32>(x, op, lds_tab);
+            const uint32_t x = U.bits(lds_lane[(F32 ? st.lds_off : (st.dim - 1) * 64) + lane], q, s - 64 * q);
+            const R z = coord_tab<F32>(x, op);
             R Ym;
             R mf;
             if constexpr (F32) {
@@ -132,7 +140,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
 // to the plan walker's, vega (from the FP32 sums of E Y and E m) within FP32
 // rounding.  Removes about a quarter of the VALU work per date.
 template <int MODE, bool OWEN, int N, int LO, int HI>
-__device__ __forceinline__ void fixed_interval(const uint32_t *row0, const float4 *tab, float zs,
+__device__ __forceinline__ void fixed_interval(const uint32_t *row0, float zs,
                                                const UParts<OWEN> &U, float WL, float WR,
                                                PathSums<float> &ps)
 {
@@ -144,45 +152,45 @@ __device__ __forceinline__ void fixed_interval(const uint32_t *row0, const float
         constexpr float wl = (float)((double)(HI - M) / (double)(HI - LO));
         constexpr float wr = (float)((double)(M - LO) / (double)(HI - LO));
         constexpr float sd = (float)qcpw_csqrt((double)(M - LO) * (double)(HI - M) / (double)(HI - LO));
-        const uint32_t x = U.bits(row0[(DIM - 1) * 64], S / 64, S % 64);
-        const float z = ninv_table_f32(x, tab);
+        const uint32_t x = U.bits(row0[qcpw_row_word(DIM - 1)], S / 64, S % 64);
+        const float z = ninv_table_f32(x);
         const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
         consume<float, MODE>(ps, Ym, (float)M);
-        fixed_interval<MODE, OWEN, N, LO, M>(row0, tab, zs, U, WL, Ym, ps);
-        fixed_interval<MODE, OWEN, N, M, HI>(row0, tab, zs, U, Ym, WR, ps);
+        fixed_interval<MODE, OWEN, N, LO, M>(row0, zs, U, WL, Ym, ps);
+        fixed_interval<MODE, OWEN, N, M, HI>(row0, zs, U, Ym, WR, ps);
     }
 }
 
 template <int MODE, bool OWEN, int N>
-__device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_t *lds_lane, const float4 *tab,
+__device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_t *lds_lane,
                                                  int lane, const UParts<OWEN> &U, PathSums<float> &ps)
 {
     const uint32_t *row0 = lds_lane + lane;
     const float zs = op.zs_t;
     constexpr float sd0 = (float)qcpw_csqrt((double)N);
-    const float z = ninv_table_f32(U.bits(row0[0], 0, 0), tab);   // terminal point, dimension 1
+    const float z = ninv_table_f32(U.bits(row0[qcpw_row_word(0)], 0, 0));   // terminal point, dimension 1
     const float WR = fmaf(sd0 * zs, z, op.ydrift_n_f);
     consume<float, MODE>(ps, WR, (float)N);
-    fixed_interval<MODE, OWEN, N, 0, N>(row0, tab, zs, U, 0.0f, WR, ps);
+    fixed_interval<MODE, OWEN, N, 0, N>(row0, zs, U, 0.0f, WR, ps);
 }
 
 // true if op.n has a compile-time bridge (then the path is done)
 template <int MODE, bool OWEN>
-__device__ inline bool bridge_fixed_any(const OptDev &op, const uint32_t *lds_lane, const float4 *tab, int lane,
+__device__ inline bool bridge_fixed_any(const OptDev &op, const uint32_t *lds_lane, int lane,
                                         const UParts<OWEN> &U, PathSums<float> &ps)
 {
     if (!qcpw_has_fixed_bridge(op.n)) return false;
     switch (op.n) {
-    case 15: run_bridge_fixed<MODE, OWEN, 15>(op, lds_lane, tab, lane, U, ps); return true;
-    case 31: run_bridge_fixed<MODE, OWEN, 31>(op, lds_lane, tab, lane, U, ps); return true;
-    case 63: run_bridge_fixed<MODE, OWEN, 63>(op, lds_lane, tab, lane, U, ps); return true;
-    case 127: run_bridge_fixed<MODE, OWEN, 127>(op, lds_lane, tab, lane, U, ps); return true;
+    case 15: run_bridge_fixed<MODE, OWEN, 15>(op, lds_lane, lane, U, ps); return true;
+    case 31: run_bridge_fixed<MODE, OWEN, 31>(op, lds_lane, lane, U, ps); return true;
+    case 63: run_bridge_fixed<MODE, OWEN, 63>(op, lds_lane, lane, U, ps); return true;
+    case 127: run_bridge_fixed<MODE, OWEN, 127>(op, lds_lane, lane, U, ps); return true;
     default: return false;
     }
 }
 
 template <bool F32, int MODE, bool OWEN>
-__device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, const float4 *lds_tab, int lane,
+__device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, int lane,
                                          const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
@@ -194,8 +202,8 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
     for (int q = 0; q < QCPW_UQ; ++q) {
         const int s_hi = min(64 * (q + 1), n);
         for (int s = 64 * q; s < s_hi; ++s) {
-            const uint32_t y = U.bits(lds_lane[s * 64 + lane], q, s - 64 * q);
-            const R z = coord_tab<F32>(y, op, lds_tab);
+            const uint32_t y = U.bits(lds_lane[lane_row<F32>(s) + lane], q, s - 64 * q);
+            const R z = coord_tab<F32>(y, op);
             Y = Y + fma(zs, z, drift);
             consume<R, MODE>(ps, Y, (R)(s + 1));
         }
@@ -207,16 +215,16 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
 // (standard) to the last date, accumulated into ps.
 template <bool F32, int PATHK, bool OWEN, int MODE>
 __device__ inline void walk_path(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
-                                 const float4 *lds_tab, typename Real<F32>::T *stk, int lane,
+                                 typename Real<F32>::T *stk, int lane,
                                  const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps, int fixed_bridges)
 {
     if constexpr (PATHK == QCPW_PATH_BB) {
         if constexpr (F32) {
-            if (fixed_bridges && bridge_fixed_any<MODE, OWEN>(op, lds_lane, lds_tab, lane, U, ps)) return;
+            if (fixed_bridges && bridge_fixed_any<MODE, OWEN>(op, lds_lane, lane, U, ps)) return;
         }
-        run_bridge_wave<F32, MODE, OWEN>(ld, op, lds_lane, lds_tab, stk, lane, U, ps);
+        run_bridge_wave<F32, MODE, OWEN>(ld, op, lds_lane, stk, lane, U, ps);
     } else {
-        run_standard_wave<F32, MODE, OWEN>(op, lds_lane, lds_tab, lane, U, ps);
+        run_standard_wave<F32, MODE, OWEN>(op, lds_lane, lane, U, ps);
     }
 }
 
@@ -249,7 +257,7 @@ __device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op,
             U.U[q] = u;
             U.Sd[q] = key;
         } else {
-            U.U[q] = fold_sign(u ^ key);
+            U.U[q] = u ^ key;
         }
     }
 }
@@ -265,7 +273,7 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
         const int s = lane + 64 * q;
         if (s < op.n) {
             const uint32_t *v = ld.dir + (size_t)step_dim<PATHK>(ld, op, s) * 32;
-            U.U[q] ^= OWEN ? (v[5] ^ v[6 + c]) : fold_sign(v[5] ^ v[6 + c]);
+            U.U[q] ^= v[5] ^ v[6 + c];
         }
     }
 }
@@ -286,10 +294,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
                                                      const PlanStep64 *__restrict__ plan64_all,
                                                      const uint32_t *__restrict__ dir,
                                                      const uint32_t *__restrict__ lane_tab,
-                                                     const float4 *__restrict__ ninv_tab,
+                                                     const float4 *__restrict__ ninv_tab,   // [2][256] cells
                                                      double *__restrict__ partials,
                                                      unsigned long long *__restrict__ counter,
-                                                     int n_opts, int max_n, int stack_depth,
+                                                     int n_opts, int max_n, int stack_depth, int stk_off,
                                                      long long total_units, int fixed_bridges)
 {
     LaunchDesc ld;
@@ -305,20 +313,22 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
     ld.partials = partials;
     ld.counter = counter;
     using R = typename Real<F32>::T;
-    // static LDS first (so the cubic cells sit at a fixed address and a
-    // cell's address is just its byte offset), then the dynamic part
-    __shared__ float4 lds_tab[F32 ? QCPW_NINV_TAB_CELLS : 1];                  // cubic cells
+    // all LDS is dynamic and starts at address 0, so a cell's address is its
+    // byte offset: FP32 keeps the cells of both halves, lane rows
+    // (qcpw_row_word) and stacks; FP64 the rows from 0 and the stacks
     extern __shared__ __align__(16) unsigned char smem[];
     const int bd = blockDim.x;
-    uint32_t *lds_lane = (uint32_t *)smem;                                    // [max_n][64], folded
-    const size_t lane_bytes = (size_t)max_n * 64 * 4;
+    uint32_t *lds_lane = (uint32_t *)smem;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     // bridge stack: [wave][stack_depth][64]; this lane's column
-    R *stk = (R *)(smem + lane_bytes) + (size_t)(tid >> 6) * stack_depth * 64 + lane;
-    if (F32)
-        for (int i = tid; i < QCPW_NINV_TAB_CELLS; i += bd) lds_tab[i] = ninv_tab[i];
-    for (int i = tid; i < max_n * 64; i += bd) lds_lane[i] = OWEN ? lane_tab[64 + i] : fold_sign(lane_tab[64 + i]);
+    R *stk = (R *)(smem + stk_off) + (size_t)(tid >> 6) * stack_depth * 64 + lane;
+    if (F32) {
+        float4 *cells = (float4 *)smem;
+        for (int i = tid; i < 2 * QCPW_NINV_TAB_CELLS; i += bd)
+            cells[(i < QCPW_NINV_TAB_CELLS ? 0 : QCPW_LDS_TAB_HI / 16 - QCPW_NINV_TAB_CELLS) + i] = ninv_tab[i];
+    }
+    for (int i = tid; i < max_n * 64; i += bd) lds_lane[lane_row<F32>(i >> 6) + (i & 63)] = lane_tab[64 + i];
     __syncthreads();
 
     int o = 0;
@@ -360,13 +370,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
             if (op.n > 0) {
                 switch (mode) {
                 case QCPW_STAT_MAX:
-                    walk_path<F32, PATHK, OWEN, QCPW_STAT_MAX>(ld, op, lds_lane, lds_tab, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, OWEN, QCPW_STAT_MAX>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
                 case QCPW_STAT_GEO:
-                    walk_path<F32, PATHK, OWEN, QCPW_STAT_GEO>(ld, op, lds_lane, lds_tab, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, OWEN, QCPW_STAT_GEO>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
                 default:
-                    walk_path<F32, PATHK, OWEN, QCPW_STAT_AVG>(ld, op, lds_lane, lds_tab, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, OWEN, QCPW_STAT_AVG>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                 }
             }
             if (valid) {
@@ -493,7 +503,7 @@ __global__ __launch_bounds__(64) void sobol_points_kernel(const uint32_t *dir, c
 // launch planning (host)
 // ------------------------------------------------------------------------
 static inline bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
-static size_t paths_lds_bytes(const LaunchPlan &lp, int bd);
+static size_t paths_lds_bytes(const LaunchPlan &lp, int bd, int *stk_off = nullptr);
 
 qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t d, int64_t n_points,
                           int32_t n_shifts, int32_t path, int32_t precision, int32_t pca_gemm,
@@ -685,21 +695,29 @@ static WsLayout ws_layout(const LaunchPlan &lp)
 
 size_t launch_workspace_bytes(const LaunchPlan &lp) { return ws_layout(lp).total; }
 
-// Dynamic LDS of the fused kernel (lane rows and bridge stacks) ...
-static size_t paths_lds_bytes(const LaunchPlan &lp, int bd)
+// LDS of the fused kernel at workgroup size bd.  FP32: the inverse-normal
+// cells and the lane rows at fixed places (qcpw_row_word), the bridge stacks
+// after the last row, or in the gap below the upper cells when they fit
+// there.  FP64: the rows from 0, then the stacks.  *stk_off (optional)
+// receives the stacks' byte offset.
+static size_t paths_lds_bytes(const LaunchPlan &lp, int bd, int *stk_off)
 {
-    const size_t lane_bytes = (size_t)lp.max_n * 64 * 4;
-    const size_t elem = lp.precision == QCPW_FP32_MIXED ? 4 : 8;
-    const size_t stack = lp.path == QCPW_PATH_BB ? (size_t)lp.stack_depth * bd * elem : 0;
-    return lane_bytes + stack;
+    const bool f32 = lp.precision == QCPW_FP32_MIXED;
+    const size_t stack = lp.path == QCPW_PATH_BB ? (size_t)lp.stack_depth * bd * (f32 ? 4 : 8) : 0;
+    if (!f32) {
+        if (stk_off) *stk_off = lp.max_n * 256;
+        return (size_t)lp.max_n * 256 + stack;
+    }
+    const bool in_gap = lp.max_n <= QCPW_LDS_GAP_ROWS;
+    const size_t rows_end = in_gap ? QCPW_LDS_GAP_BEGIN + (size_t)lp.max_n * 256
+                                   : QCPW_LDS_FIXED + (size_t)(lp.max_n - QCPW_LDS_GAP_ROWS) * 256;
+    const size_t s = (in_gap && rows_end + stack > QCPW_LDS_TAB_HI) ? QCPW_LDS_FIXED : rows_end;
+    if (stk_off) *stk_off = (int)s;
+    return std::max<size_t>(s + stack, QCPW_LDS_FIXED);
 }
 
-// ... and its total with the static inverse-normal cells, against the CU's 160 KiB.
-static bool paths_lds_fits(const LaunchPlan &lp, int bd)
-{
-    const size_t tab = lp.precision == QCPW_FP32_MIXED ? QCPW_NINV_TAB_CELLS * 16 : 16;
-    return paths_lds_bytes(lp, bd) + tab <= 160 * 1024;
-}
+// ... against the CU's 160 KiB.
+static bool paths_lds_fits(const LaunchPlan &lp, int bd) { return paths_lds_bytes(lp, bd) <= 160 * 1024; }
 
 template <bool F32, int PATHK, bool OWEN>
 static const void *paths_fn()
@@ -879,7 +897,8 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
     } else {
         const int bd = lp.block_threads;
         if (!paths_lds_fits(lp, bd)) return fail(QCPW_EDIMS, "LDS footprint exceeds 160 KiB");
-        const size_t lds = paths_lds_bytes(lp, bd);
+        int a_stk_off = 0;
+        const size_t lds = paths_lds_bytes(lp, bd, &a_stk_off);
         const void *fn = select_paths_kernel(lp);
         QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int per_cu = 0;
@@ -899,7 +918,7 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         long long a_total = ld.total_units;
         int a_fixed_arg = fixed_bridges_on() ? 1 : 0;
         void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_dir, &a_lane, &a_tab, &a_part, &a_ctr,
-                        &a_nopts, &a_maxn, &a_depth, &a_total, &a_fixed_arg};
+                        &a_nopts, &a_maxn, &a_depth, &a_stk_off, &a_total, &a_fixed_arg};
         if (t0) QCPW_HIP(hipEventRecord(t0, stream));
         QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
         if (t1) QCPW_HIP(hipEventRecord(t1, stream));

@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             for (int jj = 0; jj < jcount; ++jj) {
                 const int j = 1 + 64 * wave + jj;
                 const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
-                Z[lane * zstride + (j - 1)] = ninv_f64(fold_sign(y)) * op.zscale;
+                Z[lane * zstride + (j - 1)] = ninv_f64(y) * op.zscale;
             }
             if (base + TP < t1 && myj <= n) {
                 const uint32_t *v = dir + (size_t)myj * 32;

@@ -23,6 +23,23 @@
 #define QCPW_TAB_DIMS 1024       // Sobol dimensions held on the device
 #define QCPW_MAX_N 384           // conditioned coordinates in the fused kernel
 #define QCPW_UQ 6                // QCPW_MAX_N / 64 registers of wave-uniform state
+// LDS of the per-path kernel (all dynamic, so it starts at address 0):
+// the lower-half inverse-normal cells at 0, the upper-half cells at
+// QCPW_LDS_TAB_HI (the sign bit of the cell offset), the lane-table rows of
+// dimensions 1..QCPW_LDS_GAP_ROWS between them and the rest after the upper
+// cells; the bridge stacks follow the rows.
+#define QCPW_LDS_TAB_HI 0x8000
+#define QCPW_LDS_GAP_BEGIN 0x1000
+#define QCPW_LDS_FIXED (QCPW_LDS_TAB_HI + 0x1000)
+#define QCPW_LDS_GAP_ROWS ((QCPW_LDS_TAB_HI - QCPW_LDS_GAP_BEGIN) / 256)
+
+// 32-bit word offset in that LDS of lane-table row r (dimension r + 1)
+__host__ __device__ constexpr int qcpw_row_word(int r)
+{
+    return r < QCPW_LDS_GAP_ROWS ? QCPW_LDS_GAP_BEGIN / 4 + 64 * r
+                                 : QCPW_LDS_FIXED / 4 + 64 * (r - QCPW_LDS_GAP_ROWS);
+}
+
 #define QCPW_CHUNK 8192          // alignment of point ranges; points per PCA work unit
 
 // Points per work unit of the fused kernel (one wave per unit): a function of
@@ -126,7 +143,7 @@ constexpr int qcpw_bridge_step(int n, int lo, int hi)
 // pops >= 2, L = stack[slot + 1] (slot = depth - pops; depth after the
 // step = slot + 1).
 struct PlanStep {
-    int32_t lds_off;   // (dim - 1) * 64: row of the lane table for this step's dimension
+    int32_t lds_off;   // qcpw_row_word(dim - 1): LDS word of the lane-table row of this step's dimension
     int32_t slot;      // stack slot written (pops = 0) or read (pops >= 1)
     int32_t pops;      // stack pops before the step
     int32_t dim;       // Sobol dimension of the step (1..n)

@@ -88,7 +88,7 @@ int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep6
     int sp = 0, max_sp = 0;   // stack depth as the kernel sees it
     auto add = [&](int dim, int m, int pops, double wl, double wr, double sd) {
         PlanStep s;
-        s.lds_off = (dim - 1) * 64;
+        s.lds_off = qcpw_row_word(dim - 1);
         if (steps.empty()) {
             s.slot = 0;                 // terminal point: no stack access
         } else if (pops == 0) {
