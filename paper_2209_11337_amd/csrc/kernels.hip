@@ -139,9 +139,45 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
 // the same constexpr functions); price, delta and gamma come out bit-identical
 // to the plan walker's, vega (from the FP32 sums of E Y and E m) within FP32
 // rounding.  Removes about a quarter of the VALU work per date.
+// The wave-uniform parts as the compile-time bridges read them.  Without
+// scrambling they are copied once per 64 points into every row of 16 lanes
+// (lane l of R[i] holds step 16 i + l mod 16), so that a DPP row broadcast
+// (row_newbcast) hands step S's value to all lanes inside the very XOR that
+// combines it with the lane word: no v_readlane per date.  With nested
+// scrambling the distributed parts are read as in the plan walker.
+template <bool OWEN, int NSTEP>
+struct FixedU;
+
+template <int NSTEP>
+struct FixedU<false, NSTEP> {
+    static constexpr int NR = (NSTEP + 15) / 16;
+    uint32_t R[NR];
+    __device__ __forceinline__ FixedU(const UParts<false> &U, int lane)
+    {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) R[i] = (uint32_t)__shfl((int)U.U[i / 4], 16 * (i % 4) + (lane & 15), 64);
+    }
+    template <int S>
+    __device__ __forceinline__ uint32_t bits(uint32_t lane_word) const
+    {
+        return lane_word ^ (uint32_t)__builtin_amdgcn_update_dpp(0, (int)R[S / 16], 0x150 + S % 16, 0xF, 0xF, false);
+    }
+};
+
+template <int NSTEP>
+struct FixedU<true, NSTEP> {
+    const UParts<true> &U;
+    __device__ __forceinline__ FixedU(const UParts<true> &u, int) : U(u) {}
+    template <int S>
+    __device__ __forceinline__ uint32_t bits(uint32_t lane_word) const
+    {
+        return U.bits(lane_word, S / 64, S % 64);
+    }
+};
+
 template <int MODE, bool OWEN, int N, int LO, int HI>
 __device__ __forceinline__ void fixed_interval(const uint32_t *row0, float zs,
-                                               const UParts<OWEN> &U, float WL, float WR,
+                                               const FixedU<OWEN, N> &U, float WL, float WR,
                                                PathSums<float> &ps)
 {
     if constexpr (HI - LO >= 2) {
@@ -152,7 +188,7 @@ __device__ __forceinline__ void fixed_interval(const uint32_t *row0, float zs,
         constexpr float wl = (float)((double)(HI - M) / (double)(HI - LO));
         constexpr float wr = (float)((double)(M - LO) / (double)(HI - LO));
         constexpr float sd = (float)qcpw_csqrt((double)(M - LO) * (double)(HI - M) / (double)(HI - LO));
-        const uint32_t x = U.bits(row0[qcpw_row_word(DIM - 1)], S / 64, S % 64);
+        const uint32_t x = U.template bits<S>(row0[qcpw_row_word(DIM - 1)]);
         const float z = ninv_table_f32(x);
         const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
         consume<float, MODE>(ps, Ym, (float)M);
@@ -163,12 +199,13 @@ __device__ __forceinline__ void fixed_interval(const uint32_t *row0, float zs,
 
 template <int MODE, bool OWEN, int N>
 __device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_t *lds_lane,
-                                                 int lane, const UParts<OWEN> &U, PathSums<float> &ps)
+                                                 int lane, const UParts<OWEN> &Ud, PathSums<float> &ps)
 {
     const uint32_t *row0 = lds_lane + lane;
     const float zs = op.zs_t;
     constexpr float sd0 = (float)qcpw_csqrt((double)N);
-    const float z = ninv_table_f32(U.bits(row0[qcpw_row_word(0)], 0, 0));   // terminal point, dimension 1
+    const FixedU<OWEN, N> U(Ud, lane);
+    const float z = ninv_table_f32(U.template bits<0>(row0[qcpw_row_word(0)]));   // terminal point, dimension 1
     const float WR = fmaf(sd0 * zs, z, op.ydrift_n_f);
     consume<float, MODE>(ps, WR, (float)N);
     fixed_interval<MODE, OWEN, N, 0, N>(row0, zs, U, 0.0f, WR, ps);
