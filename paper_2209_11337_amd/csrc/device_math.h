@@ -105,15 +105,6 @@ __device__ inline float ninv_table_f32(uint32_t y)
     return fmaf(fmaf(fmaf(c.x, a, c.y), a, c.z), a, c.w);
 }
 
-// Phi^{-1}((y + 1/2) 2^-32) in FP64 (device library), evaluated on the
-// lower half (m = min(y, ~y)) so that 1 - u never has to be formed.
-__device__ inline double ninv_f64(uint32_t y)
-{
-    const uint32_t m = (y >> 31) ? ~y : y;
-    const double v = normcdfinv(((double)m + 0.5) * 0x1p-32);   // <= 0
-    return (y >> 31) ? -v : v;
-}
-
 __device__ inline float exp2_r(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline double exp2_r(double x) { return exp2(x); }
 
@@ -251,18 +242,45 @@ __device__ inline double exp_neg_f64(double x)   // any |x| < 700 (named for its
     return ldexp(p, (int)k);
 }
 
-// erfc(a) from ea2 = exp(-a^2): erfcx(|a|) = t P(t), t = 3/(3 + |a|)
-// (phi_f64_coeffs.inc); erfc(a) = 2 - erfc(-a) for a < 0.
-__device__ inline double erfc_scaled(double a, double ea2)
+// erfcx(x) = exp(x^2) erfc(x) for x >= 0: t P(t), t = 3/(3 + x)
+// (phi_f64_coeffs.inc).
+__device__ inline double erfcx_f64(double x)
 {
-    const double x = fabs(a);
     const double t = QCPW_ERFCX_C * recip_f64(QCPW_ERFCX_C + x);
     double p = coef_after(QCPW_ERFCX_P[0], t);
 #pragma unroll
     for (int i = 1; i < (int)(sizeof(QCPW_ERFCX_P) / sizeof(double)); ++i)
         p = fma(p, t, coef_after(QCPW_ERFCX_P[i], p));
-    const double v = ea2 * (t * p);
+    return t * p;
+}
+
+// erfc(a) from ea2 = exp(-a^2): erfcx(|a|) ea2, and erfc(a) = 2 - erfc(-a)
+// for a < 0.
+__device__ inline double erfc_scaled(double a, double ea2)
+{
+    const double v = ea2 * erfcx_f64(fabs(a));
     return a >= 0.0 ? v : 2.0 - v;
+}
+
+// Phi^{-1}((y + 1/2) 2^-32) in FP64 for the raw 32-bit Sobol coordinate y.
+// On the lower half (m = min(y, ~y), u = (m + 1/2) 2^-32 <= 1/2, z <= 0,
+// so 1 - u is never formed) the FP32 estimate z0 (about 1e-6 relative) is
+// refined by one Halley step on Phi(z) = u: with Phi(z) = e^{-z^2/2}
+// erfcx(-z/sqrt 2)/2 and phi(z) = e^{-z^2/2}/sqrt(2 pi), the Newton
+// correction is rho = (Phi(z0) - u)/phi(z0) = sqrt(2 pi) (erfcx(-z0/sqrt 2)/2
+// - u e^{z0^2/2}) and, since Phi'' = -z phi, Halley's step is
+// z0 - rho/(1 + z0 rho/2) = z0 - rho + z0 rho^2/2 + O(rho^3).  The error
+// goes from about 1e-6 to below FP64 rounding (cubic convergence).
+__device__ inline double ninv_f64(uint32_t y)
+{
+    const uint32_t m = (y >> 31) ? ~y : y;
+    const double u = ((double)m + 0.5) * 0x1p-32;
+    const double z0 = (double)ninv_scaled_f32(m, (float)(M_SQRT2 * 0x1p-31));   // <= 0
+    const double ez = exp_neg_f64(0.5 * z0 * z0);                                 // e^{+z0^2/2}
+    const double ex = erfcx_f64(-z0 * M_SQRT1_2);
+    const double rho = 2.50662827463100050242 * fma(0.5, ex, -u * ez);
+    const double z = z0 - rho + 0.5 * z0 * rho * rho;
+    return (y >> 31) ? -z : z;
 }
 
 // price, delta, vega, gamma of the smoothed payoff for one path (Sec. 4.5),
