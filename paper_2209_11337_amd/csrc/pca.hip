@@ -335,9 +335,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         if (myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
         const int jcount = max(0, min(64, n - 64 * wave));   // dimensions generated by this wave
 
-        // output blocks of this wave: t = wave + 4 s; row block t / 2, point block t % 2 = wave & 1
-        const int nblocks = (NP / 32) * 2;
-        const int cb = wave & 1;
+        // output blocks of this wave: row blocks rb = wave + 4 q (q = 0, 1) times
+        // both point blocks, so each A fragment feeds two MFMAs and every
+        // element of A is read once per tile by the workgroup
+        const int nrb = NP / 32;
         double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
 
         for (int64_t base = t0; base < t1; base += TP) {
@@ -362,42 +363,90 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             __syncthreads();
 
             // ---- GEMM on the matrix cores
-            v16f acc[4];
+            v16f acc[2][2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = (v16f){};
-            const int col = cb * 32 + (lane & 31);
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb) acc[q][pb] = (v16f){};
+            const int lr = lane & 31;
             const int khalf = lane >> 5;
-            if (BF16X3) {
-                for (int k0 = 0; k0 < NP; k0 += 16) {
-                    const v8us bh = *(const v8us *)&Zh[col * zstride + k0 + khalf * 8];
-                    const v8us bl = *(const v8us *)&Zl[col * zstride + k0 + khalf * 8];
+            const bool has_q1 = wave + 4 < nrb;
+            if (wave < nrb) {
+                // A streams from L2 (256 KiB FP32, too large for LDS next to Z):
+                // its fragments are loaded one k-block ahead of the MFMAs that use them
+                const int row0 = wave * 32 + lr, row1 = (wave + 4) * 32 + lr;
+                if (BF16X3) {
+                    auto load_a = [&](int k0, v8us (&ah)[2], v8us (&al)[2]) {
+                        const size_t off0 = ((size_t)(k0 >> 4) * NP + row0) * 16 + khalf * 8;
+                        ah[0] = *(const v8us *)&op.pca_hi[off0];
+                        al[0] = *(const v8us *)&op.pca_lo[off0];
+                        if (has_q1) {
+                            const size_t off1 = ((size_t)(k0 >> 4) * NP + row1) * 16 + khalf * 8;
+                            ah[1] = *(const v8us *)&op.pca_hi[off1];
+                            al[1] = *(const v8us *)&op.pca_lo[off1];
+                        }
+                    };
+                    v8us ah[2] = {}, al[2] = {}, nh[2] = {}, nl[2] = {};
+                    load_a(0, ah, al);
+                    for (int k0 = 0; k0 < NP; k0 += 16) {
+                        if (k0 + 16 < NP) load_a(k0 + 16, nh, nl);
+                        v8us bh[2], bl[2];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int t = wave + 4 * q;
-                        if (t < nblocks) {
-                            const int row = (t >> 1) * 32 + (lane & 31);
-                            const size_t off = ((size_t)(k0 >> 4) * NP + row) * 16 + khalf * 8;
-                            const v8us ah = *(const v8us *)&op.pca_hi[off];
-                            const v8us al = *(const v8us *)&op.pca_lo[off];
-                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                __builtin_bit_cast(v8bf, al), __builtin_bit_cast(v8bf, bh), acc[q], 0, 0, 0);
-                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                __builtin_bit_cast(v8bf, ah), __builtin_bit_cast(v8bf, bl), acc[q], 0, 0, 0);
-                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                __builtin_bit_cast(v8bf, ah), __builtin_bit_cast(v8bf, bh), acc[q], 0, 0, 0);
+                        for (int pb = 0; pb < 2; ++pb) {
+                            bh[pb] = *(const v8us *)&Zh[(pb * 32 + lr) * zstride + k0 + khalf * 8];
+                            bl[pb] = *(const v8us *)&Zl[(pb * 32 + lr) * zstride + k0 + khalf * 8];
+                        }
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            if (q == 1 && !has_q1) continue;
+                            const v8bf h = __builtin_bit_cast(v8bf, ah[q]), l = __builtin_bit_cast(v8bf, al[q]);
+#pragma unroll
+                            for (int pb = 0; pb < 2; ++pb) {
+                                acc[q][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    l, __builtin_bit_cast(v8bf, bh[pb]), acc[q][pb], 0, 0, 0);
+                                acc[q][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    h, __builtin_bit_cast(v8bf, bl[pb]), acc[q][pb], 0, 0, 0);
+                                acc[q][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    h, __builtin_bit_cast(v8bf, bh[pb]), acc[q][pb], 0, 0, 0);
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            ah[q] = nh[q];
+                            al[q] = nl[q];
                         }
                     }
-                }
-            } else {
-                for (int k0 = 0; k0 < NP; k0 += 2) {
-                    const float b = Zf[col * zstride + k0 + khalf];
+                } else {
+                    constexpr int KB = 8;   // k per block: four MFMA k-steps
+                    auto load_a = [&](int k0, float (&a)[KB / 2][2]) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int t = wave + 4 * q;
-                        if (t < nblocks) {
-                            const int row = (t >> 1) * 32 + (lane & 31);
-                            const float a = op.pca_At[(size_t)(k0 + khalf) * NP + row];
-                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[q], 0, 0, 0);
+                        for (int u = 0; u < KB / 2; ++u) {
+                            const float *At = op.pca_At + (size_t)(k0 + 2 * u + khalf) * NP;
+                            a[u][0] = At[row0];
+                            if (has_q1) a[u][1] = At[row1];
+                        }
+                    };
+                    float a[KB / 2][2] = {}, an[KB / 2][2] = {};
+                    load_a(0, a);
+                    for (int k0 = 0; k0 < NP; k0 += KB) {
+                        if (k0 + KB < NP) load_a(k0 + KB, an);
+#pragma unroll
+                        for (int u = 0; u < KB / 2; ++u) {
+                            float b[2];
+#pragma unroll
+                            for (int pb = 0; pb < 2; ++pb) b[pb] = Zf[(pb * 32 + lr) * zstride + k0 + 2 * u + khalf];
+#pragma unroll
+                            for (int q = 0; q < 2; ++q) {
+                                if (q == 1 && !has_q1) continue;
+#pragma unroll
+                                for (int pb = 0; pb < 2; ++pb)
+                                    acc[q][pb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u][q], b[pb], acc[q][pb], 0, 0, 0);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < KB / 2; ++u) {
+                            a[u][0] = an[u][0];
+                            a[u][1] = an[u][1];
                         }
                     }
                 }
@@ -410,15 +459,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 float *Cb = (float *)smem;
                 __syncthreads();   // every wave is done reading Z
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int t = wave + 4 * q;
-                    if (t < nblocks) {
-                        const int rb = t >> 1;
+                for (int q = 0; q < 2; ++q) {
+                    const int rb = wave + 4 * q;
+                    if (rb < nrb) {
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int row = rb * 32 + (r >> 2) * 8 + khalf * 4 + (r & 3);
-                            if (row <= n) Cb[col * cstride + row] = acc[q][r];
-                        }
+                        for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                const int row = rb * 32 + (r >> 2) * 8 + khalf * 4 + (r & 3);
+                                if (row <= n) Cb[(pb * 32 + lr) * cstride + row] = acc[q][pb][r];
+                            }
                     }
                 }
                 __syncthreads();
@@ -428,33 +478,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 zero_padding();   // the next tile's prologue writes columns 0..n-1 only
                 continue;
             }
-            // ---- epilogue: exp2 and path sums over this lane's rows of its point
-            PcaSums<float> ps;
-            sums_neutral(ps);
+            // ---- epilogue: exp2 and path sums over this lane's rows of its two points
+            PcaSums<float> ps[2];
+            sums_neutral(ps[0]);
+            sums_neutral(ps[1]);
             const float drift = op.ydrift_1_f;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int t = wave + 4 * q;
-                if (t < nblocks) {
-                    const int rb = t >> 1;
+            for (int q = 0; q < 2; ++q) {
+                const int rb = wave + 4 * q;
+                if (rb < nrb) {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int row = rb * 32 + (r >> 2) * 8 + khalf * 4 + (r & 3);
-                        if (row < n) {
-                            const float mf = (float)(row + 1);
-                            sums_add_date<float>(ps, fmaf(drift, mf, acc[q][r]), mf);
+                    for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int row = rb * 32 + (r >> 2) * 8 + khalf * 4 + (r & 3);
+                            if (row < n) {
+                                const float mf = (float)(row + 1);
+                                sums_add_date<float>(ps[pb], fmaf(drift, mf, acc[q][pb][r]), mf);
+                            }
                         }
-                    }
                 }
             }
-            sums_merge(ps, shfl_xor_sums(ps, 32));
-            if (lane < 32) red[wave * TP + col] = ps;
+            // lane halves hold other rows of the same points; lane l keeps point l
+            // (l < 32: block 0, l >= 32: block 1)
+            sums_merge(ps[0], shfl_xor_sums(ps[0], 32));
+            sums_merge(ps[1], shfl_xor_sums(ps[1], 32));
+            if (khalf) red[wave * TP + lane] = ps[1];
+            else red[wave * TP + lane] = ps[0];
             __syncthreads();
             if (wave == 0) {
-                // point p = lane lives in point block p / 32, i.e. waves cb and cb + 2
-                const int pb = lane >> 5;
-                const int waves_pt[2] = {pb, pb + 2};
-                tile_tail<float>(op, red, lane, base + lane < t1, 2, waves_pt, s, c);
+                const int waves_pt[4] = {0, 1, 2, 3};
+                tile_tail<float>(op, red, lane, base + lane < t1, 4, waves_pt, s, c);
             }
             __syncthreads();
         }
