@@ -36,7 +36,8 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned short v8us __attribute__((ext_vector_type(8)));
 
 static constexpr int TP = 64;        // points per tile (one wave width)
-static constexpr int PCA_WAVES = 4;  // waves per workgroup
+static constexpr int PCA_WAVES = 4;     // waves per workgroup (FP64)
+static constexpr int PCA_AS_WAVES = 8;  // waves per workgroup (matrix cores, one row block of A each)
 
 __device__ inline unsigned short bf16_bits(float x)   // round to nearest even
 {
@@ -267,8 +268,8 @@ __device__ inline void full_tile_tail(const OptDev &op, YF y_of, double *Fb, int
 {
     const int p = tid >> 2, part = tid & 3;
     double F[4];
-    full_point_tail(op, [&](int j) { return y_of(p, j); }, part, F);
-    if (part == 0) {
+    if (p < TP) full_point_tail(op, [&](int j) { return y_of(p, j); }, part, F);   // quads of threads 0 .. 4 TP - 1
+    if (part == 0 && p < TP) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) Fb[p * 4 + k] = F[k];
     }
@@ -282,29 +283,44 @@ __device__ inline void full_tile_tail(const OptDev &op, YF y_of, double *Fb, int
 // ------------------------------------------------------------------------
 // FP32-mixed: matrix-core GEMM
 // ------------------------------------------------------------------------
+// Eight waves, one 32-row block of A each (rows 32 w .. 32 w + 31 of the
+// padded NP x NP factor), both 32-point blocks of the tile.  A is
+// stationary: a wave loads its row block into registers once per work unit
+// (128 VGPRs: FP32, or BF16 hi and lo) and every tile of the unit streams
+// only Z^T through LDS, so A costs no bandwidth in the tile loop.
 template <bool BF16X3, bool FULL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void pca_f32_kernel(const OptDev *__restrict__ opts,
-                                                      const int64_t *__restrict__ unit_prefix,
-                                                      const uint32_t *__restrict__ dir,
-                                                      const uint32_t *__restrict__ lane_tab,
-                                                      double *__restrict__ partials,
-                                                      unsigned long long *__restrict__ counter, int n_opts,
-                                                      int np_max, long long total_units)
+__global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_eu(2, 2))) void pca_f32_kernel(
+    const OptDev *__restrict__ opts, const int64_t *__restrict__ unit_prefix, const uint32_t *__restrict__ dir,
+    const uint32_t *__restrict__ lane_tab, const float4 *__restrict__ ninv_tab, double *__restrict__ partials,
+    unsigned long long *__restrict__ counter, int n_opts, int np_max, long long total_units)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ long long s_unit;
+    // LDS (all dynamic, from address 0): the inverse-normal cells of both halves
+    // at 0 and QCPW_LDS_TAB_HI, the wave partials between them, the Z^T tile
+    // after: FP32 [TP][np+1], or BF16 hi and lo [TP][np+8] each
+    extern __shared__ __align__(16) unsigned char smem[];   // no static LDS: smem is address 0
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // Z^T tile: FP32 [TP][np+1], or BF16 hi and lo [TP][np+8] each
+    const int lr = lane & 31, khalf = lane >> 5;
     const int zstride = BF16X3 ? np_max + 8 : np_max + 1;
-    const size_t zbytes = BF16X3 ? (size_t)2 * TP * zstride * 2 : (size_t)TP * zstride * 4;
-    float *Zf = (float *)smem;
-    unsigned short *Zh = (unsigned short *)smem;
+    float *Zf = (float *)(smem + QCPW_LDS_FIXED);
+    unsigned short *Zh = (unsigned short *)(smem + QCPW_LDS_FIXED);
     unsigned short *Zl = Zh + (size_t)TP * zstride;
-    PcaSums<float> *red = (PcaSums<float> *)(smem + ((zbytes + 15) / 16) * 16);   // [4][TP]
-
+    PcaSums<float> *red = (PcaSums<float> *)(smem + QCPW_LDS_GAP_BEGIN);   // [PCA_AS_WAVES][TP]
+    long long *s_unit = (long long *)(smem + QCPW_LDS_GAP_BEGIN + PCA_AS_WAVES * TP * sizeof(PcaSums<float>));
+    static_assert(QCPW_LDS_GAP_BEGIN + PCA_AS_WAVES * TP * sizeof(PcaSums<float>) + 8 <= QCPW_LDS_TAB_HI, "gap");
+    {
+        float4 *cells = (float4 *)smem;
+        for (int i = tid; i < 2 * QCPW_NINV_TAB_CELLS; i += blockDim.x)
+            cells[(i < QCPW_NINV_TAB_CELLS ? 0 : QCPW_LDS_TAB_HI / 16 - QCPW_NINV_TAB_CELLS) + i] = ninv_tab[i];
+        __syncthreads();
+    }
+    constexpr int KS = BF16X3 ? QCPW_PCA_NPAD / 16 : QCPW_PCA_NPAD / 2;           // k steps of the MFMA
+    // this wave's row block: FP32 Ar[u] = A[row][2 u + khalf]; BF16: Ah/Al[u] = A[row][16 u + 8 khalf ..]
+    float Ar[BF16X3 ? 1 : KS];
+    v8us Ah[BF16X3 ? KS : 1], Al[BF16X3 ? KS : 1];
+    const int row = 32 * wave + lr;
     int o = 0;
     for (;;) {
-        const long long unit = next_unit(counter, &s_unit);
+        const long long unit = next_unit(counter, s_unit);
         if (unit >= total_units) break;
         locate_unit(unit_prefix, n_opts, unit, o);
         const OptDev &op = opts[o];
@@ -315,6 +331,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const int64_t k_end = op.k_begin + op.n_points;
         const int64_t t0 = op.k_begin + chunk * op.unit_pts;
         const int64_t t1 = min(t0 + (int64_t)op.unit_pts, k_end);
+        const bool gemm_wave = wave < NP / 32;
+        if (gemm_wave) {
+#pragma unroll
+            for (int u = 0; u < KS; ++u) {
+                if (BF16X3) {
+                    if (16 * u < NP) {
+                        const size_t off = ((size_t)u * NP + row) * 16 + khalf * 8;
+                        Ah[u] = *(const v8us *)&op.pca_hi[off];
+                        Al[u] = *(const v8us *)&op.pca_lo[off];
+                    }
+                } else {
+                    if (2 * u < NP) Ar[u] = op.pca_At[(size_t)(2 * u + khalf) * NP + row];
+                }
+            }
+        }
 
         // padding columns of Z (k = n .. NP-1) must hold zeros (also after a
         // PCA_FULL epilogue has used the Z area for the products)
@@ -330,23 +361,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             }
         };
         zero_padding();
-        const int myj = 1 + 64 * wave + lane;   // dimension whose uniform part this lane holds
+        // Waves 1..7 generate the normals (wave 0 meanwhile runs the previous
+        // tile's FP64 tail): prologue wave pw = wave - 1 takes dimensions
+        // 1 + PD pw .. PD (pw + 1), and its lane l holds the uniform part of 1 + PD pw + l.
+        constexpr int PD = (QCPW_PCA_NPAD + PCA_AS_WAVES - 2) / (PCA_AS_WAVES - 1);
+        static_assert(PD <= 64, "one uniform part per lane");
+        const int pw = wave - 1;
+        const int myj = 1 + PD * pw + lane;
         uint32_t U = 0;
-        if (myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
-        const int jcount = max(0, min(64, n - 64 * wave));   // dimensions generated by this wave
-
-        // output blocks of this wave: row blocks rb = wave + 4 q (q = 0, 1) times
-        // both point blocks, so each A fragment feeds two MFMAs and every
-        // element of A is read once per tile by the workgroup
-        const int nrb = NP / 32;
+        if (wave > 0 && lane < PD && myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
+        const int jcount = wave > 0 ? max(0, min(PD, n - PD * pw)) : 0;
         double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
-
-        for (int64_t base = t0; base < t1; base += TP) {
-            // ---- prologue: z' = Phi^{-1}(u) * sigma sqrt(dt) log2(e) for 64 points x this wave's dims
+        // ---- prologue: z' = Phi^{-1}(u) * sigma sqrt(dt) log2(e) for the 64 points of the
+        // tile at `base` x this wave's dimensions, then the Gray-code step to the next tile
+        auto prologue = [&](int64_t base) {
             for (int jj = 0; jj < jcount; ++jj) {
-                const int j = 1 + 64 * wave + jj;
+                const int j = 1 + PD * pw + jj;
                 const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
-                const float z = ninv_scaled_f32(y, op.zs_a);
+                const float z = ninv_table_f32(y) * op.zs_t;
                 const int k = j - 1;
                 if (BF16X3) {
                     const unsigned short h = bf16_bits(z);
@@ -356,98 +388,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                     Zf[lane * zstride + k] = z;
                 }
             }
-            if (base + TP < t1 && myj <= n) {   // Gray-code step to the next tile
+            if (base + TP < t1 && wave > 0 && lane < PD && myj <= n) {
                 const uint32_t *v = dir + (size_t)myj * 32;
                 U ^= v[5] ^ v[6 + __builtin_ctzll(((uint64_t)base >> 6) + 1)];
             }
-            __syncthreads();
+        };
+        prologue(t0);
+        __syncthreads();
 
-            // ---- GEMM on the matrix cores
-            v16f acc[2][2];
+        for (int64_t base = t0; base < t1; base += TP) {
+            // ---- GEMM on the matrix cores: rows of this wave x points 0..31 (acc0), 32..63 (acc1)
+            v16f acc0 = (v16f){}, acc1 = (v16f){};
+            if (gemm_wave) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int pb = 0; pb < 2; ++pb) acc[q][pb] = (v16f){};
-            const int lr = lane & 31;
-            const int khalf = lane >> 5;
-            const bool has_q1 = wave + 4 < nrb;
-            if (wave < nrb) {
-                // A streams from L2 (256 KiB FP32, too large for LDS next to Z):
-                // its fragments are loaded one k-block ahead of the MFMAs that use them
-                const int row0 = wave * 32 + lr, row1 = (wave + 4) * 32 + lr;
-                if (BF16X3) {
-                    auto load_a = [&](int k0, v8us (&ah)[2], v8us (&al)[2]) {
-                        const size_t off0 = ((size_t)(k0 >> 4) * NP + row0) * 16 + khalf * 8;
-                        ah[0] = *(const v8us *)&op.pca_hi[off0];
-                        al[0] = *(const v8us *)&op.pca_lo[off0];
-                        if (has_q1) {
-                            const size_t off1 = ((size_t)(k0 >> 4) * NP + row1) * 16 + khalf * 8;
-                            ah[1] = *(const v8us *)&op.pca_hi[off1];
-                            al[1] = *(const v8us *)&op.pca_lo[off1];
-                        }
-                    };
-                    v8us ah[2] = {}, al[2] = {}, nh[2] = {}, nl[2] = {};
-                    load_a(0, ah, al);
-                    for (int k0 = 0; k0 < NP; k0 += 16) {
-                        if (k0 + 16 < NP) load_a(k0 + 16, nh, nl);
-                        v8us bh[2], bl[2];
-#pragma unroll
-                        for (int pb = 0; pb < 2; ++pb) {
-                            bh[pb] = *(const v8us *)&Zh[(pb * 32 + lr) * zstride + k0 + khalf * 8];
-                            bl[pb] = *(const v8us *)&Zl[(pb * 32 + lr) * zstride + k0 + khalf * 8];
-                        }
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            if (q == 1 && !has_q1) continue;
-                            const v8bf h = __builtin_bit_cast(v8bf, ah[q]), l = __builtin_bit_cast(v8bf, al[q]);
-#pragma unroll
-                            for (int pb = 0; pb < 2; ++pb) {
-                                acc[q][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                    l, __builtin_bit_cast(v8bf, bh[pb]), acc[q][pb], 0, 0, 0);
-                                acc[q][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                    h, __builtin_bit_cast(v8bf, bl[pb]), acc[q][pb], 0, 0, 0);
-                                acc[q][pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                    h, __builtin_bit_cast(v8bf, bh[pb]), acc[q][pb], 0, 0, 0);
-                            }
-                        }
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            ah[q] = nh[q];
-                            al[q] = nl[q];
-                        }
-                    }
-                } else {
-                    constexpr int KB = 8;   // k per block: four MFMA k-steps
-                    auto load_a = [&](int k0, float (&a)[KB / 2][2]) {
-#pragma unroll
-                        for (int u = 0; u < KB / 2; ++u) {
-                            const float *At = op.pca_At + (size_t)(k0 + 2 * u + khalf) * NP;
-                            a[u][0] = At[row0];
-                            if (has_q1) a[u][1] = At[row1];
-                        }
-                    };
-                    float a[KB / 2][2] = {}, an[KB / 2][2] = {};
-                    load_a(0, a);
-                    for (int k0 = 0; k0 < NP; k0 += KB) {
-                        if (k0 + KB < NP) load_a(k0 + KB, an);
-#pragma unroll
-                        for (int u = 0; u < KB / 2; ++u) {
-                            float b[2];
-#pragma unroll
-                            for (int pb = 0; pb < 2; ++pb) b[pb] = Zf[(pb * 32 + lr) * zstride + k0 + 2 * u + khalf];
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) {
-                                if (q == 1 && !has_q1) continue;
-#pragma unroll
-                                for (int pb = 0; pb < 2; ++pb)
-                                    acc[q][pb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u][q], b[pb], acc[q][pb], 0, 0, 0);
-                            }
-                        }
-#pragma unroll
-                        for (int u = 0; u < KB / 2; ++u) {
-                            a[u][0] = an[u][0];
-                            a[u][1] = an[u][1];
-                        }
+                for (int u = 0; u < KS; ++u) {
+                    if (BF16X3) {
+                        if (16 * u >= NP) continue;
+                        const int k = 16 * u + khalf * 8;
+                        const v8bf bh0 = __builtin_bit_cast(v8bf, *(const v8us *)&Zh[lr * zstride + k]);
+                        const v8bf bl0 = __builtin_bit_cast(v8bf, *(const v8us *)&Zl[lr * zstride + k]);
+                        const v8bf bh1 = __builtin_bit_cast(v8bf, *(const v8us *)&Zh[(32 + lr) * zstride + k]);
+                        const v8bf bl1 = __builtin_bit_cast(v8bf, *(const v8us *)&Zl[(32 + lr) * zstride + k]);
+                        const v8bf h = __builtin_bit_cast(v8bf, Ah[u]), l = __builtin_bit_cast(v8bf, Al[u]);
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bh0, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bh1, acc1, 0, 0, 0);
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bl0, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bl1, acc1, 0, 0, 0);
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bh0, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bh1, acc1, 0, 0, 0);
+                    } else {
+                        if (2 * u >= NP) continue;
+                        const int k = 2 * u + khalf;
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(Ar[u], Zf[lr * zstride + k], acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(Ar[u], Zf[(32 + lr) * zstride + k], acc1, 0, 0, 0);
                     }
                 }
             }
@@ -456,59 +429,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 // ---- epilogue: the d products of each point into LDS (over Z),
                 // then the FP64 root-find and Greeks, four threads per point
                 const int cstride = NP + 1;
-                float *Cb = (float *)smem;
+                float *Cb = Zf;
                 __syncthreads();   // every wave is done reading Z
+                if (gemm_wave) {
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int rb = wave + 4 * q;
-                    if (rb < nrb) {
-#pragma unroll
-                        for (int pb = 0; pb < 2; ++pb)
-#pragma unroll
-                            for (int r = 0; r < 16; ++r) {
-                                const int row = rb * 32 + (r >> 2) * 8 + khalf * 4 + (r & 3);
-                                if (row <= n) Cb[(pb * 32 + lr) * cstride + row] = acc[q][pb][r];
-                            }
+                    for (int r = 0; r < 16; ++r) {
+                        const int m = 32 * wave + (r >> 2) * 8 + khalf * 4 + (r & 3);
+                        if (m <= n) {
+                            Cb[lr * cstride + m] = acc0[r];
+                            Cb[(32 + lr) * cstride + m] = acc1[r];
+                        }
                     }
                 }
                 __syncthreads();
                 full_tile_tail(op, [&](int p, int j) { return (double)Cb[p * cstride + j]; }, (double *)red, tid,
                                lane, wave, base + lane < t1, s, c);
                 __syncthreads();
-                zero_padding();   // the next tile's prologue writes columns 0..n-1 only
+                zero_padding();   // the prologue writes columns 0..n-1 only
+                if (base + TP < t1) prologue(base + TP);
+                __syncthreads();
                 continue;
             }
             // ---- epilogue: exp2 and path sums over this lane's rows of its two points
-            PcaSums<float> ps[2];
-            sums_neutral(ps[0]);
-            sums_neutral(ps[1]);
+            PcaSums<float> ps0, ps1;
+            sums_neutral(ps0);
+            sums_neutral(ps1);
             const float drift = op.ydrift_1_f;
+            if (gemm_wave) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int rb = wave + 4 * q;
-                if (rb < nrb) {
-#pragma unroll
-                    for (int pb = 0; pb < 2; ++pb)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int row = rb * 32 + (r >> 2) * 8 + khalf * 4 + (r & 3);
-                            if (row < n) {
-                                const float mf = (float)(row + 1);
-                                sums_add_date<float>(ps[pb], fmaf(drift, mf, acc[q][pb][r]), mf);
-                            }
-                        }
+                for (int r = 0; r < 16; ++r) {
+                    const int m = 32 * wave + (r >> 2) * 8 + khalf * 4 + (r & 3);
+                    if (m < n) {
+                        const float mf = (float)(m + 1);
+                        sums_add_date<float>(ps0, fmaf(drift, mf, acc0[r]), mf);
+                        sums_add_date<float>(ps1, fmaf(drift, mf, acc1[r]), mf);
+                    }
                 }
             }
             // lane halves hold other rows of the same points; lane l keeps point l
-            // (l < 32: block 0, l >= 32: block 1)
-            sums_merge(ps[0], shfl_xor_sums(ps[0], 32));
-            sums_merge(ps[1], shfl_xor_sums(ps[1], 32));
-            if (khalf) red[wave * TP + lane] = ps[1];
-            else red[wave * TP + lane] = ps[0];
+            sums_merge(ps0, shfl_xor_sums(ps0, 32));
+            sums_merge(ps1, shfl_xor_sums(ps1, 32));
+            if (khalf) red[wave * TP + lane] = ps1;
+            else red[wave * TP + lane] = ps0;
             __syncthreads();
-            if (wave == 0) {
-                const int waves_pt[4] = {0, 1, 2, 3};
-                tile_tail<float>(op, red, lane, base + lane < t1, 4, waves_pt, s, c);
+            if (wave == 0) {   // this tile's tail, while the other waves fill Z with the next tile
+                const int waves_pt[PCA_AS_WAVES] = {0, 1, 2, 3, 4, 5, 6, 7};
+                tile_tail<float>(op, red, lane, base + lane < t1, PCA_AS_WAVES, waves_pt, s, c);
+            } else if (base + TP < t1) {
+                prologue(base + TP);
             }
             __syncthreads();
         }
@@ -660,13 +628,13 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
                 : (full ? reinterpret_cast<const void *>(&pca_f32_kernel<false, true>)
                         : reinterpret_cast<const void *>(&pca_f32_kernel<false, false>));
         const size_t z = bf ? (size_t)2 * TP * (np_max + 8) * 2 : (size_t)TP * (np_max + 1) * 4;
-        lds = (z + 15) / 16 * 16 + (size_t)PCA_WAVES * TP * sizeof(PcaSums<float>);
+        lds = QCPW_LDS_FIXED + z;   // cells, wave partials between them, then Z^T
         extra = np_max;
     }
     if (lds > 160 * 1024) return fail(QCPW_EDIMS, "PCA tile exceeds 160 KiB of LDS");
     QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    const int bd = 64 * PCA_WAVES;
+    const int bd = 64 * (lp.precision == QCPW_FP64 ? PCA_WAVES : PCA_AS_WAVES);
     QCPW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds));
     if (per_cu < 1) return fail(QCPW_EDEVICE, "PCA kernel cannot be resident");
     int64_t grid = std::min<int64_t>((int64_t)per_cu * ctx->tab.n_cu, lp.total_units);
@@ -682,7 +650,8 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
     int a_nopts = ld.n_opts;
     long long a_total = ld.total_units;
     double *a_scratch = ld.scratch;
-    void *args32[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_part, &a_ctr, &a_nopts, &extra, &a_total};
+    const float4 *a_tab = ctx->tab.ninv_tab;
+    void *args32[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_tab, &a_part, &a_ctr, &a_nopts, &extra, &a_total};
     void *args64[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_part, &a_ctr, &a_nopts, &extra, &a_total, &a_scratch};
     QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), lp.precision == QCPW_FP64 ? args64 : args32, lds,
                              stream));
