@@ -400,10 +400,15 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
             // ---- GEMM on the matrix cores: rows of this wave x points 0..31 (acc0), 32..63 (acc1)
             v16f acc0 = (v16f){}, acc1 = (v16f){};
             if (gemm_wave) {
+                // NP is a multiple of 32: one guard per 32 k, so that each group's LDS
+                // reads can be scheduled ahead of its MFMAs
+                constexpr int KG = BF16X3 ? 2 : 16;   // k steps per 32 k
 #pragma unroll
-                for (int u = 0; u < KS; ++u) {
+                for (int g = 0; g < KS / KG; ++g) {
+                    if (32 * g >= NP) continue;
+#pragma unroll
+                for (int u = g * KG; u < (g + 1) * KG; ++u) {
                     if (BF16X3) {
-                        if (16 * u >= NP) continue;
                         const int k = 16 * u + khalf * 8;
                         const v8bf bh0 = __builtin_bit_cast(v8bf, *(const v8us *)&Zh[lr * zstride + k]);
                         const v8bf bl0 = __builtin_bit_cast(v8bf, *(const v8us *)&Zl[lr * zstride + k]);
@@ -417,11 +422,11 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
                         acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bh0, acc0, 0, 0, 0);
                         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bh1, acc1, 0, 0, 0);
                     } else {
-                        if (2 * u >= NP) continue;
                         const int k = 2 * u + khalf;
                         acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(Ar[u], Zf[lr * zstride + k], acc0, 0, 0, 0);
                         acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(Ar[u], Zf[(32 + lr) * zstride + k], acc1, 0, 0, 0);
                     }
+                }
                 }
             }
 
