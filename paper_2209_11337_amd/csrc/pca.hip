@@ -374,18 +374,27 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
         double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
         // ---- prologue: z' = Phi^{-1}(u) * sigma sqrt(dt) log2(e) for the 64 points of the
         // tile at `base` x this wave's dimensions, then the Gray-code step to the next tile
+        const int jc = __builtin_amdgcn_readfirstlane(jcount);
         auto prologue = [&](int64_t base) {
-            for (int jj = 0; jj < jcount; ++jj) {
-                const int j = 1 + PD * pw + jj;
-                const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
-                const float z = ninv_table_f32(y) * op.zs_t;
-                const int k = j - 1;
-                if (BF16X3) {
-                    const unsigned short h = bf16_bits(z);
-                    Zh[lane * zstride + k] = h;
-                    Zl[lane * zstride + k] = bf16_bits(z - bf16_value(h));
-                } else {
-                    Zf[lane * zstride + k] = z;
+            // lane-table words eight at a time, all loads in flight before the first use
+            for (int j0 = 0; j0 < jc; j0 += 8) {
+                uint32_t w[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    w[i] = j0 + i < jc ? lane_tab[(size_t)(1 + PD * pw + j0 + i) * 64 + lane] : 0u;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int jj = j0 + i;
+                    if (jj >= jc) break;
+                    const float z = ninv_table_f32(w[i] ^ rdlane(U, jj)) * op.zs_t;
+                    const int k = PD * pw + jj;   // column of dimension j = k + 1
+                    if (BF16X3) {
+                        const unsigned short h = bf16_bits(z);
+                        Zh[lane * zstride + k] = h;
+                        Zl[lane * zstride + k] = bf16_bits(z - bf16_value(h));
+                    } else {
+                        Zf[lane * zstride + k] = z;
+                    }
                 }
             }
             if (base + TP < t1 && wave > 0 && lane < PD && myj <= n) {
