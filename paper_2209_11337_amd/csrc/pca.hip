@@ -168,8 +168,8 @@ __device__ inline void tile_tail(const OptDev &op, const PcaSums<R> *red, int la
 // ------------------------------------------------------------------------
 // Conditioning on the first principal component of all d dates (PCA_FULL)
 // ------------------------------------------------------------------------
-// One point's FP64 tail, shared by the four threads part = 0..3 of a quad of
-// consecutive lanes; thread `part` takes the dates j = part (mod 4).  y(j)
+// One point's FP64 tail, shared by PARTS (4 or 8) consecutive lanes; thread
+// `part` takes the dates j = part (mod PARTS).  y(j)
 // is date j's row of the factor (first column dropped) times the scaled
 // normals, i.e. log2(e) sigma c_j, so that
 //     ln S(t_j) = alpha_j + beta_j x,  alpha_j = ln S0 + omega t_j + sigma c_j,
@@ -180,7 +180,7 @@ __device__ inline void tile_tail(const OptDev &op, const PcaSums<R> *red, int la
 // (to the right of the root), so the iterates decrease to the root.  Price,
 // delta, vega and gamma then follow in closed form (arithmetic: the terms in
 // d psi cancel at the root; binary: through d psi = -dF / F').
-template <typename YF>
+template <int PARTS, typename YF>
 __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double F[4])
 {
     constexpr double LN2 = 0.69314718055994530942;
@@ -191,12 +191,13 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
     const double dt = op.sqrt_t1 * op.sqrt_t1;
     const double lnS0 = log(op.S0), K = op.K;
     const double *a1 = op.pca_a1;
-    auto quad_sum = [](double v) {          // the same bits in all four threads
-        v += __shfl_xor(v, 1, 64);
-        return v + __shfl_xor(v, 2, 64);
+    auto quad_sum = [](double v) {          // the same bits in all PARTS threads of the point
+#pragma unroll
+        for (int m = 1; m < PARTS; m <<= 1) v += __shfl_xor(v, m, 64);
+        return v;
     };
     double sa = 0.0, sb = 0.0;
-    for (int j = part; j < d; j += 4) {
+    for (int j = part; j < d; j += PARTS) {
         sa += lnS0 + wdt * (j + 1) + LN2 * y(j);
         sb += sdt * a1[j];
     }
@@ -206,7 +207,7 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
     const double lndk = log(K * d);
     for (int it = 0; it < 64; ++it) {
         double S = 0.0, S1 = 0.0;
-        for (int j = part; j < d; j += 4) {
+        for (int j = part; j < d; j += PARTS) {
             const double be = sdt * a1[j];
             const double g = exp(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x);
             S += g;
@@ -221,7 +222,7 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
     const double psi = x;
     const bool arith = op.type == QCPW_ARITH_ASIAN_CALL;
     double F1 = 0.0, F2 = 0.0, Fs = 0.0, sEP = 0.0, sV = 0.0, sAg = 0.0;
-    for (int j = part; j < d; j += 4) {
+    for (int j = part; j < d; j += PARTS) {
         const double yj = y(j);
         const double al = lnS0 + wdt * (j + 1) + LN2 * yj, be = sdt * a1[j];
         const double a = be / sig;                                // first-column entry, W units
@@ -260,15 +261,16 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
     }
 }
 
-// The four threads of point p = tid / 4 run full_point_tail; quad leader
+// The PARTS threads of point p = tid / PARTS run full_point_tail; the first
 // writes F to Fb[p][4]; wave 0, lane p, adds valid points into its sums.
-template <typename YF>
+template <int PARTS, typename YF>
 __device__ inline void full_tile_tail(const OptDev &op, YF y_of, double *Fb, int tid, int lane, int wave,
                                       bool lane_valid_for_wave0, double (&s)[4], double (&c)[4])
 {
-    const int p = tid >> 2, part = tid & 3;
+    static_assert(PARTS == 4 || PARTS == 8, "threads per point");
+    const int p = tid / PARTS, part = tid % PARTS;
     double F[4];
-    if (p < TP) full_point_tail(op, [&](int j) { return y_of(p, j); }, part, F);   // quads of threads 0 .. 4 TP - 1
+    if (p < TP) full_point_tail<PARTS>(op, [&](int j) { return y_of(p, j); }, part, F);
     if (part == 0 && p < TP) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) Fb[p * 4 + k] = F[k];
@@ -441,7 +443,7 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
 
             if constexpr (FULL) {
                 // ---- epilogue: the d products of each point into LDS (over Z),
-                // then the FP64 root-find and Greeks, four threads per point
+                // then the FP64 root-find and Greeks, eight threads per point
                 const int cstride = NP + 1;
                 float *Cb = Zf;
                 __syncthreads();   // every wave is done reading Z
@@ -456,7 +458,7 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
                     }
                 }
                 __syncthreads();
-                full_tile_tail(op, [&](int p, int j) { return (double)Cb[p * cstride + j]; }, (double *)red, tid,
+                full_tile_tail<PCA_AS_WAVES>(op, [&](int p, int j) { return (double)Cb[p * cstride + j]; }, (double *)red, tid,
                                lane, wave, base + lane < t1, s, c);
                 __syncthreads();
                 zero_padding();   // the prologue writes columns 0..n-1 only
@@ -588,7 +590,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             }
             if constexpr (FULL) {
                 __syncthreads();
-                full_tile_tail(op, [&](int p, int j) { return Cg[(size_t)j * TP + p]; }, (double *)red, tid, lane,
+                full_tile_tail<PCA_WAVES>(op, [&](int p, int j) { return Cg[(size_t)j * TP + p]; }, (double *)red, tid, lane,
                                wave, base + lane < t1, s, c);
                 __syncthreads();
                 continue;
