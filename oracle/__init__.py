@@ -34,6 +34,7 @@ _lock = threading.Lock()
 _lib = None
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK, GEOMETRIC_ASIAN = 0, 1, 2, 3
+ARITH_ASIAN_PUT, BINARY_ASIAN_PUT, LOOKBACK_PUT, GEOMETRIC_ASIAN_PUT = 4, 5, 6, 7
 PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
 RAND_SHIFT, RAND_OWEN = 0, 1
 OUTPUTS = ("price", "delta", "vega", "gamma")

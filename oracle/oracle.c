@@ -29,6 +29,10 @@
  *   - Uniform from a 32-bit integer y: u = (y + 1/2) * 2^-32.
  *   - Digital shift of replication l, dimension j: high 32 bits of output
  *     number (l * 2^16 + j) of SplitMix64 seeded with the option's seed.
+ *   - Products beyond the paper's three (other payoffs under the same
+ *     conditional template, Sec. 6.2): the geometric Asian call, and the puts
+ *     of the arithmetic, binary, geometric Asian and of the fixed-strike
+ *     lookback, the last on the discrete minimum.
  *   - ORC_PCA_FULL (the principal-component conditioning the paper names as
  *     the route to larger variance reduction, Sec. 7): W(t_1..t_d) = A z with
  *     A the d x d principal-component factor of the full covariance
@@ -47,7 +51,8 @@
 
 #define ORC_MAX_BITS 32
 
-enum { ORC_ARITH = 0, ORC_BINARY = 1, ORC_LOOKBACK = 2, ORC_GEOMETRIC = 3 };
+enum { ORC_ARITH = 0, ORC_BINARY = 1, ORC_LOOKBACK = 2, ORC_GEOMETRIC = 3,
+       ORC_ARITH_PUT = 4, ORC_BINARY_PUT = 5, ORC_LOOKBACK_PUT = 6, ORC_GEOMETRIC_PUT = 7 };
 enum { ORC_BB = 0, ORC_PCA = 1, ORC_STANDARD = 2, ORC_PCA_FULL = 3 };
 enum { ORC_RAND_SHIFT = 0, ORC_RAND_OWEN = 1 };
 
@@ -320,18 +325,21 @@ void oracle_path_greeks(int type, int d, double S0, double K, double r,
 
     /* S~(t_j) = S0 exp(omega (t_j - t_1) + sigma W~(t_j - t_1))  (eqn:Stilde1) */
     double X = 0.0, VX = 0.0;
-    if (type == ORC_LOOKBACK) {
+    if (type == ORC_LOOKBACK || type == ORC_LOOKBACK_PUT) {
+        /* fixed-strike lookback: the call is on the discrete maximum, the put
+         * on the discrete minimum; either extreme carries the common factor of x_1 */
         int jstar = 0;
-        double best = -1.0;
+        double best = 0.0;
         for (int m = 0; m < d; ++m) {
             double tau = m * dt;
             double St = S0 * exp(omega * tau + sigma * W[m]);
-            if (St > best) { best = St; jstar = m; }   /* lowest index wins ties */
+            int better = type == ORC_LOOKBACK ? St > best : St < best;
+            if (m == 0 || better) { best = St; jstar = m; }   /* lowest index wins ties */
         }
         X = best;
-        /* d S~max / d sigma = S~(t_j*) (W~ - sigma tau) at the argmax */
+        /* d S~extreme / d sigma = S~(t_j*) (W~ - sigma tau) at the arg-extreme */
         VX = best * (W[jstar] - sigma * jstar * dt);
-    } else if (type == ORC_GEOMETRIC) {
+    } else if (type == ORC_GEOMETRIC || type == ORC_GEOMETRIC_PUT) {
         /* geometric average: X = (prod_j S~(t_j))^{1/d} = S0 exp(mean_j (omega tau_j + sigma W~_j));
          * like the arithmetic average it carries the common factor of x_1, so
          * the same conditional payoff applies (Sec. 4.5 with another average) */
@@ -367,6 +375,24 @@ void oracle_path_greeks(int type, int d, double S0, double K, double r,
         out[1] = D * phi0 / (S0 * s1);
         out[2] = D * phi0 * (VX / (s1 * X) + psi / sigma - sqrt(t1));
         out[3] = D * phi0 / (S0 * S0 * s1) * (psi / s1 - 1.0);
+    } else if (type == ORC_BINARY_PUT) {
+        /* pays e^{-rT} when the average ends below K, i.e. x_1 < psi:
+         * G = e^{-rT} Phi(psi); d psi/d S0 = -1/(S0 s1) */
+        double P0 = oracle_norm_cdf(psi);
+        out[0] = D * P0;
+        out[1] = -D * phi0 / (S0 * s1);
+        out[2] = -D * phi0 * (VX / (s1 * X) + psi / sigma - sqrt(t1));
+        out[3] = -D * phi0 / (S0 * S0 * s1) * (psi / s1 - 1.0);
+    } else if (type == ORC_ARITH_PUT || type == ORC_LOOKBACK_PUT || type == ORC_GEOMETRIC_PUT) {
+        /* (K - X e^{omega t1 + s1 x1})^+ is positive for x1 < psi:
+         * G = e^{-rT} K Phi(psi) - e^{r(t1-T)} X Phi(psi - s1); in the
+         * derivatives the psi terms cancel at the breakpoint, as for the call */
+        double P0 = oracle_norm_cdf(psi);
+        double P1 = oracle_norm_cdf(psi - s1);
+        out[0] = D * K * P0 - D1 * X * P1;
+        out[1] = -D1 * (X / S0) * P1;
+        out[2] = -D1 * P1 * VX + D * K * phi0 * sqrt(t1);
+        out[3] = D * K * phi0 / (S0 * S0 * s1);
     } else {
         /* G = e^{r(t1-T)} X [1 - Phi(psi - s1)] - e^{-rT} K [1 - Phi(psi)]
          * (Sec. 4.5.2 arithmetic Asian, Sec. 4.5.3 lookback on the max; the

@@ -309,10 +309,25 @@ def test_one_date_reduces_to_black_scholes(S0, K, r, sig, T):
     arithmetic Asian and lookback calls are the European call and the binary
     Asian is the cash-or-nothing digital, with exact Greeks and no noise."""
     call, digital = _bs(S0, K, r, sig, T)
-    for typ, ref in [(oracle.ARITH_ASIAN, call), (oracle.LOOKBACK, call), (oracle.BINARY_ASIAN, digital)]:
+    put, digital_put = _bs_put(S0, K, r, sig, T)
+    for typ, ref in [(oracle.ARITH_ASIAN, call), (oracle.LOOKBACK, call), (oracle.BINARY_ASIAN, digital),
+                     (oracle.GEOMETRIC_ASIAN, call), (oracle.ARITH_ASIAN_PUT, put), (oracle.LOOKBACK_PUT, put),
+                     (oracle.GEOMETRIC_ASIAN_PUT, put), (oracle.BINARY_ASIAN_PUT, digital_put)]:
         res = oracle.option(typ, 1, S0, K, r, sig, T, 99, 8, 4)
-        assert np.allclose(res["mean"], ref, rtol=2e-13, atol=0)
+        assert np.allclose(res["mean"], ref, rtol=2e-13, atol=1e-14 * S0), (typ, res["mean"], ref)
         assert np.all(res["stderr"] == 0)
+
+
+def _bs_put(S0, K, r, sig, T):
+    """European put and cash-or-nothing put (pays 1 below K): price, delta, vega, gamma."""
+    d1 = (math.log(S0 / K) + (r + sig**2 / 2) * T) / (sig * math.sqrt(T))
+    d2 = d1 - sig * math.sqrt(T)
+    N, n = scipy.stats.norm.cdf, scipy.stats.norm.pdf
+    D = math.exp(-r * T)
+    put = [K * D * N(-d2) - S0 * N(-d1), -N(-d1), S0 * n(d1) * math.sqrt(T), n(d1) / (S0 * sig * math.sqrt(T))]
+    digital = [D * N(-d2), -D * n(d2) / (S0 * sig * math.sqrt(T)), D * n(d2) * d1 / sig,
+               D * n(d2) * d1 / (S0**2 * sig**2 * T)]
+    return np.array(put), np.array(digital)
 
 
 def _fd_check(typ, d, path, z, S0=100.0, K=100.0, r=0.05, sig=0.2, T=1.0):
@@ -346,7 +361,12 @@ def _fd_check(typ, d, path, z, S0=100.0, K=100.0, r=0.05, sig=0.2, T=1.0):
     return g, np.array([g[0], delta, vega, gamma]), floor
 
 
-@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK, oracle.GEOMETRIC_ASIAN])
+ALL_TYPES = [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK, oracle.GEOMETRIC_ASIAN,
+             oracle.ARITH_ASIAN_PUT, oracle.BINARY_ASIAN_PUT, oracle.LOOKBACK_PUT, oracle.GEOMETRIC_ASIAN_PUT]
+PUTS = (oracle.ARITH_ASIAN_PUT, oracle.BINARY_ASIAN_PUT, oracle.LOOKBACK_PUT, oracle.GEOMETRIC_ASIAN_PUT)
+
+
+@pytest.mark.parametrize("typ", ALL_TYPES)
 @pytest.mark.parametrize("d,path", [(2, oracle.PATH_BB), (12, oracle.PATH_BB), (64, oracle.PATH_BB),
                                     (17, oracle.PATH_STANDARD), (33, oracle.PATH_PCA)])
 def test_greeks_equal_finite_differences_of_conditional_price(typ, d, path):
@@ -367,7 +387,7 @@ def test_lookback_vega_has_no_one_over_d():
     assert abs(fd[2]) > 2.0 * abs(fd[2] - 0.0) / d
 
 
-@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK, oracle.GEOMETRIC_ASIAN])
+@pytest.mark.parametrize("typ", ALL_TYPES)
 @pytest.mark.parametrize("K", [90.0, 100.0, 115.0])
 def test_conditional_price_is_quadrature_of_unconditioned_payoff(typ, K):
     """G(theta, z) = E[discounted payoff | z]: integrate the original payoff
@@ -385,21 +405,28 @@ def test_conditional_price_is_quadrature_of_unconditioned_payoff(typ, K):
             # Black-Scholes path: W(t_j) = sqrt(t_1) x_1 + W~(t_j - t_1)
             W = math.sqrt(dt) * x1 + Wt
             S = S0 * np.exp((r - 0.5 * sig**2) * t + sig * W)
-            if typ == oracle.GEOMETRIC_ASIAN:
+            if typ in (oracle.GEOMETRIC_ASIAN, oracle.GEOMETRIC_ASIAN_PUT):
                 return math.exp(np.log(S).mean())
-            return S.max() if typ == oracle.LOOKBACK else S.mean()
+            if typ == oracle.LOOKBACK:
+                return S.max()
+            return S.min() if typ == oracle.LOOKBACK_PUT else S.mean()
 
         def payoff(x1):
             A = stat(x1)
             if typ == oracle.BINARY_ASIAN:
                 return math.exp(-r * T) * (1.0 if A > K else 0.0)
+            if typ == oracle.BINARY_ASIAN_PUT:
+                return math.exp(-r * T) * (1.0 if A < K else 0.0)
+            if typ in PUTS:
+                return math.exp(-r * T) * max(K - A, 0.0)
             return math.exp(-r * T) * max(A - K, 0.0)
 
         root = scipy.optimize.brentq(lambda x: stat(x) - K, -60, 60, xtol=1e-15, rtol=1e-15)
         f = lambda x: payoff(x) * scipy.stats.norm.pdf(x)
-        val = scipy.integrate.quad(f, root, 40, epsabs=0, epsrel=1e-13, limit=200)[0]
+        lo, hi = (-40, root) if typ in PUTS else (root, 40)
+        val = scipy.integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-13, limit=200)[0]
         g = oracle.path_greeks(typ, d, S0, K, r, sig, T, Wt)
-        assert abs(g[0] - val) <= 1e-10 * max(abs(val), 1e-12), (g[0], val)
+        assert abs(g[0] - val) <= 1e-10 * max(abs(val), 1e-12) + 1e-13 * K, (g[0], val)
         # the breakpoint itself: binary price is e^{-rT} (1 - Phi(psi))
         if typ == oracle.BINARY_ASIAN:
             psi = -scipy.special.ndtri(g[0] / math.exp(-r * T))
@@ -447,6 +474,65 @@ def test_rqmc_estimate_agrees_with_quadrature_at_three_dates():
 # --------------------------------------------------------------------------
 # Geometric Asian call: exact lognormal closed form at any d
 # --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("path", [oracle.PATH_BB, oracle.PATH_STANDARD, oracle.PATH_PCA])
+def test_put_call_parity_per_path(path):
+    """(X - K)^+ - (K - X)^+ = X - K path by path, so the conditional call
+    minus the conditional put is e^{r(t1-T)} X - e^{-rT} K for the average,
+    the geometric mean and the lookback (max for the call, min for the put:
+    a different X, checked through the binary pair), and the binary call
+    plus the binary put is e^{-rT}."""
+    S0, r, sig, T, d = 100.0, 0.04, 0.25, 1.5, 20
+    dt = T / d
+    D, D1 = math.exp(-r * T), math.exp(r * (dt - T))
+    rng = np.random.default_rng(77 + path)
+    for K in (85.0, 100.0, 120.0):
+        z = rng.standard_normal(d - 1)
+        W = oracle.build_path(path, d - 1, dt, z)
+        tau = dt * np.arange(d)
+        S = S0 * np.exp((r - sig**2 / 2) * tau + sig * W)
+        VS = S * (W - sig * tau)
+        for call, put, X, VX in [(oracle.ARITH_ASIAN, oracle.ARITH_ASIAN_PUT, S.mean(), VS.mean()),
+                                 (oracle.GEOMETRIC_ASIAN, oracle.GEOMETRIC_ASIAN_PUT, math.exp(np.log(S).mean()),
+                                  math.exp(np.log(S).mean()) * (W - sig * tau).mean())]:
+            gc = oracle.path_greeks(call, d, S0, K, r, sig, T, W)
+            gp = oracle.path_greeks(put, d, S0, K, r, sig, T, W)
+            np.testing.assert_allclose(gc - gp, [D1 * X - D * K, D1 * X / S0, D1 * VX, 0.0], rtol=1e-12,
+                                       atol=1e-12 * (S0 + K))
+        j = int(np.argmin(S))
+        gp = oracle.path_greeks(oracle.LOOKBACK_PUT, d, S0, K, r, sig, T, W)
+        gb = oracle.path_greeks(oracle.BINARY_ASIAN, d, S0, K, r, sig, T, W)
+        gbp = oracle.path_greeks(oracle.BINARY_ASIAN_PUT, d, S0, K, r, sig, T, W)
+        np.testing.assert_allclose(gb + gbp, [D, 0.0, 0.0, 0.0], rtol=0, atol=1e-14)
+        # lookback put through its own breakpoint on the minimum: the price is
+        # the closed-form put on X = min S~ (checked here against the call on
+        # the same X via the generic put-call identity of the conditional payoff)
+        s1 = sig * math.sqrt(dt)
+        psi = (math.log(K) - math.log(S[j]) - (r - sig**2 / 2) * dt) / s1
+        N = scipy.stats.norm.cdf
+        call_on_min = D1 * S[j] * N(s1 - psi) - D * K * N(-psi)
+        assert abs((call_on_min - gp[0]) - (D1 * S[j] - D * K)) <= 1e-12 * (S0 + K)
+
+
+@pytest.mark.parametrize("d,path", [(1, oracle.PATH_BB), (12, oracle.PATH_BB), (64, oracle.PATH_BB),
+                                    (20, oracle.PATH_STANDARD)])
+def test_geometric_put_estimate_matches_closed_form(d, path):
+    """The geometric put estimate against the lognormal closed form (put-call
+    parity of the discretely monitored geometric average), within 4 stderr."""
+    S0, K, r, sig, T = 100.0, 103.0, 0.05, 0.3, 1.0
+    c = geometric_asian_closed_form(S0, K, r, sig, T, d)
+    dt = T / d
+    tbar = dt * (d + 1) / 2
+    v2 = sig**2 * dt * (d + 1) * (2 * d + 1) / (6 * d)
+    F = math.exp(math.log(S0) + (r - sig**2 / 2) * tbar + v2 / 2)     # E[G]
+    D = math.exp(-r * T)
+    # put = call - D (E[G] - K): delta - D F/S0, vega - D dF/dsigma, gamma unchanged
+    dF_dsig = F * (-sig * tbar + sig * (d + 1) * (2 * d + 1) * dt / (6 * d))
+    ref = c - np.array([D * (F - K), D * F / S0, D * dF_dsig, 0.0])
+    res = oracle.option(oracle.GEOMETRIC_ASIAN_PUT, d, S0, K, r, sig, T, 4711, 1 << 12, 16, path)
+    for i in range(4):
+        assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-12 * abs(ref[i]), (i, res["mean"], ref)
+
 
 def test_geometric_closed_form_by_quadrature():
     """The closed form above against direct quadrature of the lognormal
