@@ -45,13 +45,19 @@ enum {
 };
 
 /* Product (Sec. 4.5.1 binary Asian, 4.5.2 arithmetic Asian, 4.5.3 lookback).
- * QCPW_GEOMETRIC_ASIAN_CALL: a call on the geometric average of S(t_j),
- * j = 1..d -- one more payoff under the same conditional template (the
- * extension Sec. 5 describes): its conditional price and Greeks take the
- * arithmetic call's formulas with X the geometric mean, and log X is normal,
- * so its expectation has a closed form to test against.                   */
+ * Beyond the paper's three, more payoffs under the same conditional template
+ * (the extension Sec. 6.2 describes):
+ *  QCPW_GEOMETRIC_ASIAN_CALL  a call on the geometric average of S(t_j),
+ *                             j = 1..d: the arithmetic call's formulas with X
+ *                             the geometric mean; log X is normal, so its
+ *                             expectation has a closed form to test against;
+ *  *_PUT                      (K - X)^+ on the same average (binary: pays when
+ *                             the average ends below K); the fixed-strike
+ *                             lookback put is on the discrete minimum.  A put
+ *                             pays for x_1 below the breakpoint.          */
 enum { QCPW_ARITH_ASIAN_CALL = 0, QCPW_BINARY_ASIAN_CALL = 1, QCPW_LOOKBACK_FIXED_CALL = 2,
-       QCPW_GEOMETRIC_ASIAN_CALL = 3 };
+       QCPW_GEOMETRIC_ASIAN_CALL = 3, QCPW_ARITH_ASIAN_PUT = 4, QCPW_BINARY_ASIAN_PUT = 5,
+       QCPW_LOOKBACK_FIXED_PUT = 6, QCPW_GEOMETRIC_ASIAN_PUT = 7 };
 
 /* Path construction.  The first three condition on the normal x_1 that
  * drives W(t_1) (Sec. 3.4.2) and build the d-1 remaining coordinates with a

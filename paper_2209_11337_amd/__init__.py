@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqmccpw.so")
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK, GEOMETRIC_ASIAN = 0, 1, 2, 3
+ARITH_ASIAN_PUT, BINARY_ASIAN_PUT, LOOKBACK_PUT, GEOMETRIC_ASIAN_PUT = 4, 5, 6, 7
 PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
 FP64, FP32_MIXED = 0, 1
 GEMM_FP32, GEMM_BF16X3 = 0, 1

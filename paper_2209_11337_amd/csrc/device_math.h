@@ -140,25 +140,27 @@ __device__ inline uint32_t rdlane(uint32_t v, int l)
 template <typename R>
 struct PathSums {
     R A1, A2y, A2m;   // sum E_m, sum E_m Y_m, sum E_m m   (averages)
-    R bY, bm;         // running max of Y_m and its m (lookback; E = 2^Y once, at the end)
+    R bY, bm;         // running max (min) of Y_m and its m (lookback; E = 2^Y once, at the end)
 };
 
 // What a date adds to the path statistic: the arithmetic average's sums,
 // the running maximum, or (geometric average) the sum of Y = log2 S~/S0.
-enum { QCPW_STAT_AVG = 0, QCPW_STAT_MAX = 1, QCPW_STAT_GEO = 2 };
+enum { QCPW_STAT_AVG = 0, QCPW_STAT_MAX = 1, QCPW_STAT_GEO = 2, QCPW_STAT_MIN = 3 };
 
 __host__ __device__ inline int qcpw_stat_of(int type)
 {
     return type == QCPW_LOOKBACK_FIXED_CALL ? QCPW_STAT_MAX
-           : type == QCPW_GEOMETRIC_ASIAN_CALL ? QCPW_STAT_GEO
-                                               : QCPW_STAT_AVG;
+           : type == QCPW_LOOKBACK_FIXED_PUT ? QCPW_STAT_MIN
+           : (type == QCPW_GEOMETRIC_ASIAN_CALL || type == QCPW_GEOMETRIC_ASIAN_PUT) ? QCPW_STAT_GEO
+                                                                                   : QCPW_STAT_AVG;
 }
 
 template <typename R, int MODE>
 __device__ inline void consume(PathSums<R> &ps, R Y, R mf)
 {
-    if (MODE == QCPW_STAT_MAX) {
-        const bool take = (Y > ps.bY) || (Y == ps.bY && mf < ps.bm);   // lowest index wins ties
+    if (MODE == QCPW_STAT_MAX || MODE == QCPW_STAT_MIN) {
+        const bool better = MODE == QCPW_STAT_MAX ? Y > ps.bY : Y < ps.bY;
+        const bool take = better || (Y == ps.bY && mf < ps.bm);   // lowest index wins ties
         ps.bY = take ? Y : ps.bY;
         ps.bm = take ? mf : ps.bm;
     } else if (MODE == QCPW_STAT_GEO) {
@@ -254,14 +256,6 @@ __device__ inline double erfcx_f64(double x)
     return t * p;
 }
 
-// erfc(a) from ea2 = exp(-a^2): erfcx(|a|) ea2, and erfc(a) = 2 - erfc(-a)
-// for a < 0.
-__device__ inline double erfc_scaled(double a, double ea2)
-{
-    const double v = ea2 * erfcx_f64(fabs(a));
-    return a >= 0.0 ? v : 2.0 - v;
-}
-
 // Phi^{-1}((y + 1/2) 2^-32) in FP64 for the raw 32-bit Sobol coordinate y.
 // On the lower half (m = min(y, ~y), u = (m + 1/2) 2^-32 <= 1/2, z <= 0,
 // so 1 - u is never formed) the FP32 estimate z0 (about 1e-6 relative) is
@@ -284,32 +278,43 @@ __device__ inline double ninv_f64(uint32_t y)
 }
 
 // price, delta, vega, gamma of the smoothed payoff for one path (Sec. 4.5),
-// from the path statistic X = S0 * Xs (Xs = A/d or max E, with A the sum or
-// maximum of E = S~/S0) and its sigma derivative V_X = S0 * VXs.  All FP64.
-// The three Gaussian factors come from one exponential: with
-// psi = (c0 - ln A)/s1 (Sec. 3.4.2), exp(-(psi - s1)^2/2) =
-// exp(-psi^2/2) exp(c0 - s1^2/2) / A.
+// from the path statistic X = S0 * Xs (Xs = A/d, the extreme E or the
+// geometric mean, with A the sum of E = S~/S0) and its sigma derivative
+// V_X = S0 * VXs.  All FP64.  The three Gaussian factors come from one
+// exponential: with psi = (c0 - ln A)/s1 (Sec. 3.4.2), exp(-(psi - s1)^2/2)
+// = exp(-psi^2/2) exp(c0 - s1^2/2) / A.  Calls pay for x_1 above psi and
+// need 1 - Phi; puts pay below it and need Phi: both come from the smaller
+// tail e = erfc(|a|)/2 = exp(-a^2) erfcx(|a|)/2, a = psi/sqrt 2, as e or
+// 1 - e, so neither loses accuracy far from the money.  A put's price is
+// the call's minus the forward of the payoff, so its Greeks are the call's
+// with the X terms negated (binary: all negated).
 __device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, double VXs, double F[4])
 {
     const OptDev &op = *reread(&op_in);
     const double psi = (op.c0 - ln_f64(A)) * op.inv_s1;
+    const double psi1 = psi - op.s1;
     const double g0 = exp_neg_f64(-0.5 * psi * psi);
     const double invA = recip_f64(A);
-    const double Q0 = 0.5 * erfc_scaled(psi * M_SQRT1_2, g0);                      // 1 - Phi(psi)
-    const double Q1 = 0.5 * erfc_scaled((psi - op.s1) * M_SQRT1_2, g0 * op.h * invA);   // 1 - Phi(psi - s1)
+    const double e0 = 0.5 * g0 * erfcx_f64(fabs(psi) * M_SQRT1_2);
+    const double e1 = 0.5 * (g0 * op.h * invA) * erfcx_f64(fabs(psi1) * M_SQRT1_2);
+    const bool put = op.type >= QCPW_ARITH_ASIAN_PUT;
+    const double T0 = ((psi >= 0.0) != put) ? e0 : 1.0 - e0;    // call: 1 - Phi(psi); put: Phi(psi)
+    const double T1 = ((psi1 >= 0.0) != put) ? e1 : 1.0 - e1;   // the same at psi - s1
+    const double sgn = put ? -1.0 : 1.0;
     const double phi0 = g0 * 0.398942280401432677939946;
-    if (op.type == QCPW_BINARY_ASIAN_CALL) {
-        const double Dphi = op.D * phi0;
-        F[0] = op.D * Q0;
+    if (op.type == QCPW_BINARY_ASIAN_CALL || op.type == QCPW_BINARY_ASIAN_PUT) {
+        const double Dphi = sgn * op.D * phi0;
+        F[0] = op.D * T0;
         F[1] = Dphi * op.inv_s1 * op.inv_S0;
         F[2] = Dphi * (VXs * recip_f64(Xs) * op.inv_s1 + psi * op.inv_sigma - op.sqrt_t1);
         F[3] = Dphi * op.inv_s1 * op.inv_S0sq * (psi * op.inv_s1 - 1.0);
     } else {
         const double X = op.S0 * Xs;
         const double DKphi = op.D * op.K * phi0;
-        F[0] = op.D1 * X * Q1 - op.D * op.K * Q0;
-        F[1] = op.D1 * Xs * Q1;
-        F[2] = op.D1 * Q1 * (op.S0 * VXs) + DKphi * op.sqrt_t1;
+        const double D1T1 = sgn * op.D1 * T1;
+        F[0] = D1T1 * X - sgn * op.D * op.K * T0;
+        F[1] = D1T1 * Xs;
+        F[2] = D1T1 * (op.S0 * VXs) + DKphi * op.sqrt_t1;
         F[3] = DKphi * op.inv_s1 * op.inv_S0sq;
     }
 }
@@ -319,7 +324,7 @@ __device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, int
 {
     const OptDev &op = *reread(&op_in);
     double A, Xs, VXs;
-    if (mode == QCPW_STAT_MAX) {
+    if (mode == QCPW_STAT_MAX || mode == QCPW_STAT_MIN) {
         A = (double)exp2_r(ps.bY);
         Xs = A;
         VXs = A * ((double)ps.bY - op.kappa * (double)ps.bm) * op.inv_sig_log2e;

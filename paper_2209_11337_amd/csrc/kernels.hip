@@ -412,6 +412,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
                 case QCPW_STAT_GEO:
                     walk_path<F32, PATHK, OWEN, QCPW_STAT_GEO>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
+                case QCPW_STAT_MIN:
+                    walk_path<F32, PATHK, OWEN, QCPW_STAT_MIN>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    break;
                 default:
                     walk_path<F32, PATHK, OWEN, QCPW_STAT_AVG>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                 }
@@ -564,8 +567,7 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
         const qcpw_option_spec &sp = specs[i];
         const int di = d ? d : sp.d;
         const int64_t Ni = n_points ? n_points : sp.n_points;
-        if (sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL &&
-            sp.type != QCPW_LOOKBACK_FIXED_CALL && sp.type != QCPW_GEOMETRIC_ASIAN_CALL)
+        if (sp.type < QCPW_ARITH_ASIAN_CALL || sp.type > QCPW_GEOMETRIC_ASIAN_PUT)
             return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": unknown type");
         if (path == QCPW_PATH_PCA_FULL && sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL)
             return fail(QCPW_EINVAL, "option " + std::to_string(i) +
@@ -651,7 +653,7 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.sqrt_t1 = std::sqrt(t1);
         op.inv_sigma = 1.0 / sp.sigma;
         op.c0 = std::log(sp.K) - std::log(sp.S0) - omega * t1 +
-                (sp.type == QCPW_ARITH_ASIAN_CALL || sp.type == QCPW_BINARY_ASIAN_CALL ? std::log((double)di) : 0.0);
+                (qcpw_stat_of(sp.type) == QCPW_STAT_AVG ? std::log((double)di) : 0.0);
         op.h = std::exp(op.c0 - 0.5 * op.s1 * op.s1);
         op.S0 = sp.S0;
         op.K = sp.K;

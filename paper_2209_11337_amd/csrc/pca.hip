@@ -84,8 +84,9 @@ __device__ inline uint32_t uniform_part(const uint32_t *__restrict__ dir, uint64
 }
 
 // Per-point sums of a path piece: the arithmetic average's sums, the running
-// maximum of E with its Y and m (compared on E, lowest m wins ties) and the
-// sum of Y (geometric average).
+// extreme of E with its Y and m (the maximum, or the minimum when `lo`, for
+// the lookback put; compared on E, lowest m wins ties) and the sum of Y
+// (geometric average).
 template <typename R>
 struct PcaSums {
     R A1, A2y, A2m;
@@ -94,35 +95,41 @@ struct PcaSums {
 };
 
 template <typename R>
-__device__ inline void sums_neutral(PcaSums<R> &ps)
+__device__ inline void sums_neutral(PcaSums<R> &ps, bool lo)
 {
     ps.A1 = R(0); ps.A2y = R(0); ps.A2m = R(0);
-    ps.bE = R(0); ps.bY = R(0); ps.bm = R(1e30);
+    ps.bE = lo ? R(3.0e38) : R(0); ps.bY = R(0); ps.bm = R(1e30);
     ps.sY = R(0);
 }
 
 template <typename R>
-__device__ inline void sums_merge(PcaSums<R> &a, const PcaSums<R> &b)
+__device__ inline bool sums_take(R E, R m, R bE, R bm, bool lo)
+{
+    return (lo ? E < bE : E > bE) || (E == bE && m < bm);
+}
+
+template <typename R>
+__device__ inline void sums_merge(PcaSums<R> &a, const PcaSums<R> &b, bool lo)
 {
     a.A1 += b.A1;
     a.A2y += b.A2y;
     a.A2m += b.A2m;
     a.sY += b.sY;
-    const bool take = (b.bE > a.bE) || (b.bE == a.bE && b.bm < a.bm);
+    const bool take = sums_take(b.bE, b.bm, a.bE, a.bm, lo);
     a.bE = take ? b.bE : a.bE;
     a.bY = take ? b.bY : a.bY;
     a.bm = take ? b.bm : a.bm;
 }
 
 template <typename R>
-__device__ inline void sums_add_date(PcaSums<R> &ps, R Y, R mf)
+__device__ inline void sums_add_date(PcaSums<R> &ps, R Y, R mf, bool lo)
 {
     const R E = exp2_r(Y);
     ps.A1 += E;
     ps.A2y = fma(E, Y, ps.A2y);
     ps.A2m = fma(E, mf, ps.A2m);
     ps.sY += Y;
-    const bool take = (E > ps.bE) || (E == ps.bE && mf < ps.bm);
+    const bool take = sums_take(E, mf, ps.bE, ps.bm, lo);
     ps.bE = take ? E : ps.bE;
     ps.bY = take ? Y : ps.bY;
     ps.bm = take ? mf : ps.bm;
@@ -152,7 +159,8 @@ __device__ inline void tile_tail(const OptDev &op, const PcaSums<R> *red, int la
     ps.A1 = R(1); ps.A2y = R(0); ps.A2m = R(0);   // date 1: E = 1, Y = 0, m = 0
     ps.bE = R(1); ps.bY = R(0); ps.bm = R(0);
     ps.sY = R(0);
-    for (int i = 0; i < nwaves_pt; ++i) sums_merge(ps, red[waves_pt[i] * TP + lane]);
+    const bool lo = qcpw_stat_of(op.type) == QCPW_STAT_MIN;
+    for (int i = 0; i < nwaves_pt; ++i) sums_merge(ps, red[waves_pt[i] * TP + lane], lo);
     if (valid) {
         const int mode = qcpw_stat_of(op.type);
         PathSums<R> t;
@@ -468,8 +476,9 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
             }
             // ---- epilogue: exp2 and path sums over this lane's rows of its two points
             PcaSums<float> ps0, ps1;
-            sums_neutral(ps0);
-            sums_neutral(ps1);
+            const bool lo = qcpw_stat_of(op.type) == QCPW_STAT_MIN;
+            sums_neutral(ps0, lo);
+            sums_neutral(ps1, lo);
             const float drift = op.ydrift_1_f;
             if (gemm_wave) {
 #pragma unroll
@@ -477,14 +486,14 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
                     const int m = 32 * wave + (r >> 2) * 8 + khalf * 4 + (r & 3);
                     if (m < n) {
                         const float mf = (float)(m + 1);
-                        sums_add_date<float>(ps0, fmaf(drift, mf, acc0[r]), mf);
-                        sums_add_date<float>(ps1, fmaf(drift, mf, acc1[r]), mf);
+                        sums_add_date<float>(ps0, fmaf(drift, mf, acc0[r]), mf, lo);
+                        sums_add_date<float>(ps1, fmaf(drift, mf, acc1[r]), mf, lo);
                     }
                 }
             }
             // lane halves hold other rows of the same points; lane l keeps point l
-            sums_merge(ps0, shfl_xor_sums(ps0, 32));
-            sums_merge(ps1, shfl_xor_sums(ps1, 32));
+            sums_merge(ps0, shfl_xor_sums(ps0, 32), lo);
+            sums_merge(ps1, shfl_xor_sums(ps1, 32), lo);
             if (khalf) red[wave * TP + lane] = ps1;
             else red[wave * TP + lane] = ps0;
             __syncthreads();
@@ -563,7 +572,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             __syncthreads();
             // rows m = wave, wave + 4, ...: W'_m = sum_i A[m][i] z'_i, four rows at a time
             PcaSums<double> ps;
-            sums_neutral(ps);
+            const bool lo = qcpw_stat_of(op.type) == QCPW_STAT_MIN;
+            sums_neutral(ps, lo);
             const double drift = op.ydrift_1;
             const int rows = FULL ? n + 1 : n;
             for (int m0 = wave; m0 < rows; m0 += 16) {
@@ -583,7 +593,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                             Cg[(size_t)m * TP + lane] = acc[q];
                         } else {
                             const double mf = (double)(m + 1);
-                            sums_add_date<double>(ps, fma(drift, mf, acc[q]), mf);
+                            sums_add_date<double>(ps, fma(drift, mf, acc[q]), mf, lo);
                         }
                     }
                 }

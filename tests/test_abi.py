@@ -40,8 +40,8 @@ def test_version_string():
 
 
 BAD = [
-    (dict(type=7), "unknown type"),
-    (dict(type=4), "unknown type"),
+    (dict(type=9), "unknown type"),
+    (dict(type=8), "unknown type"),
     (dict(type=-1), "unknown type"),
     (dict(d=0), "d must be"),
     (dict(d=400), "exceeds"),
@@ -121,7 +121,7 @@ def test_library_full_pca_factor_matches_oracle(d):
 
 def test_full_pca_argument_checks():
     o = dict(type=0, d=16, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, seed=1, n_points=64)
-    for t in (2, 3):   # lookback, geometric
+    for t in (2, 3, 4, 5, 6, 7):   # lookback, geometric, puts
         with pytest.raises(q.QcpwError) as ei:
             q.greeks([dict(o, type=t)], 4, q.PATH_PCA_FULL)
         assert ei.value.status == -1 and "Asian" in str(ei.value)

@@ -429,6 +429,57 @@ def test_geometric_full_size_matches_closed_form(path, prec):
 
 
 # ------------------------------------------------------------------------
+# puts (average, binary, geometric, lookback on the minimum)
+# ------------------------------------------------------------------------
+@pytest.mark.parametrize("path", [q.PATH_BB, q.PATH_STANDARD, q.PATH_PCA])
+@pytest.mark.parametrize("d", [2, 64, 100])
+def test_fp64_puts_parity(path, d):
+    opts = workloads.put_grid(d=d, n_points=8192 + 77)[::2]
+    say("puts fp64", path, d)
+    g, e, ps = q.greeks(opts, 3, path, q.FP64, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 3, path)
+    assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
+    assert_scaled(g, m, am, TOL64, "mean")
+
+
+@pytest.mark.parametrize("path,d,gemm", [(q.PATH_BB, 64, 0), (q.PATH_BB, 65, 0), (q.PATH_STANDARD, 64, 0),
+                                         (q.PATH_PCA, 64, q.GEMM_FP32), (q.PATH_PCA, 64, q.GEMM_BF16X3)])
+def test_fp32_puts_within_bound(path, d, gemm):
+    opts = workloads.put_grid(d=d, n_points=8192 + 300)
+    say("puts fp32", path, d, gemm)
+    g, e, ps = q.greeks(opts, 2, path, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 2, path)
+    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    say("puts fp32 scaled error", err.max(axis=(0, 1)))
+    tol = BF16X3_TOL if (path == q.PATH_PCA and gemm == q.GEMM_BF16X3) else FP32_TOL
+    for k in range(4):
+        assert err[..., k].max() <= tol[k], (k, err[..., k].max())
+
+
+def test_geometric_put_full_size_matches_closed_form():
+    """6 geometric puts, d = 64, 2^20 points x 32 shifts, FP32-mixed bridge:
+    every Greek within 5 reported standard errors (plus the FP32 bound) of
+    the closed form obtained from the call's by put-call parity."""
+    from closed_forms import geometric_asian_closed_form
+    opts = [o for o in workloads.put_grid(d=64, n_points=1 << 20) if o["type"] == q.GEOMETRIC_ASIAN_PUT]
+    g, e = q.greeks(opts, 32, q.PATH_BB, q.FP32_MIXED)
+    ref = []
+    for o in opts:
+        S0, K, r, sig, T, d = o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["d"]
+        c = geometric_asian_closed_form(S0, K, r, sig, T, d)
+        dt = T / d
+        tbar = dt * (d + 1) / 2
+        cv = dt * (d + 1) * (2 * d + 1) / (6 * d)
+        F = np.exp(np.log(S0) + (r - sig**2 / 2) * tbar + sig**2 * cv / 2)
+        D = np.exp(-r * T)
+        ref.append(c - np.array([D * (F - K), D * F / S0, D * F * sig * (cv - tbar), 0.0]))
+    ref = np.array(ref)
+    z = np.abs(g - ref) / (5 * e + FP32_TOL[None, :] * np.abs(ref))
+    say("geometric put |g - exact| / allowed:", z.max(axis=0))
+    assert (z <= 1).all(), z
+
+
+# ------------------------------------------------------------------------
 # serving: continuous batching
 # ------------------------------------------------------------------------
 def test_server_results_match_direct_calls_and_overlap():

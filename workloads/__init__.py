@@ -20,9 +20,12 @@ from __future__ import annotations
 import numpy as np
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK, GEOMETRIC_ASIAN = 0, 1, 2, 3
+ARITH_ASIAN_PUT, BINARY_ASIAN_PUT, LOOKBACK_PUT, GEOMETRIC_ASIAN_PUT = 4, 5, 6, 7
 PATH_BB, PATH_PCA, PATH_STANDARD = 0, 1, 2
 TYPE_NAMES = {ARITH_ASIAN: "arith_asian", BINARY_ASIAN: "binary_asian", LOOKBACK: "lookback",
-              GEOMETRIC_ASIAN: "geometric_asian"}
+              GEOMETRIC_ASIAN: "geometric_asian", ARITH_ASIAN_PUT: "arith_asian_put",
+              BINARY_ASIAN_PUT: "binary_asian_put", LOOKBACK_PUT: "lookback_put",
+              GEOMETRIC_ASIAN_PUT: "geometric_asian_put"}
 
 BASE_SEED = 0x220911337
 
@@ -76,6 +79,17 @@ def geometric_grid(d: int = 64, n_points: int = 1 << 20) -> list[dict]:
     out = [dict(type=GEOMETRIC_ASIAN, d=d, S0=100.0, K=K, r=0.05, sigma=sig, T=1.0, n_points=n_points)
            for K in (90.0, 100.0, 110.0) for sig in (0.1, 0.3)]
     for o, s in zip(out, _seeds(len(out), BASE_SEED + 3)):
+        o["seed"] = s
+    return out
+
+
+def put_grid(d: int = 64, n_points: int = 1 << 20) -> list[dict]:
+    """24 puts: {arith, binary, geometric Asian, fixed-strike lookback on the
+    minimum} x K {90,100,110} x sigma {0.1, 0.3}; S0 = 100, r = 0.05, T = 1."""
+    out = [dict(type=t, d=d, S0=100.0, K=K, r=0.05, sigma=sig, T=1.0, n_points=n_points)
+           for t in (ARITH_ASIAN_PUT, BINARY_ASIAN_PUT, LOOKBACK_PUT, GEOMETRIC_ASIAN_PUT)
+           for K in (90.0, 100.0, 110.0) for sig in (0.1, 0.3)]
+    for o, s in zip(out, _seeds(len(out), BASE_SEED + 4)):
         o["seed"] = s
     return out
 
