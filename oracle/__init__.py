@@ -35,6 +35,7 @@ _lib = None
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK, GEOMETRIC_ASIAN = 0, 1, 2, 3
 ARITH_ASIAN_PUT, BINARY_ASIAN_PUT, LOOKBACK_PUT, GEOMETRIC_ASIAN_PUT = 4, 5, 6, 7
+BASKET_ASIAN, BASKET_ASIAN_PUT = 8, 9
 PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
 RAND_SHIFT, RAND_OWEN = 0, 1
 OUTPUTS = ("price", "delta", "vega", "gamma")
@@ -96,6 +97,17 @@ def _load():
                                            C.c_int, C.c_int, C.c_int, u32p, C.c_void_p, f64p, f64p, f64p,
                                            C.c_int]
             lib.oracle_options.restype = C.c_int
+            lib.oracle_basket_path_greeks.argtypes = ([C.c_int, C.c_int, C.c_int] + [C.c_double] * 6 +
+                                                      [f64p, f64p, f64p])
+            lib.oracle_basket_path_greeks.restype = None
+            lib.oracle_basket_option.argtypes = ([C.c_int, C.c_int, C.c_int] + [C.c_double] * 6 +
+                                                 [C.c_uint64, C.c_int64, C.c_int, C.c_int, u32p, C.c_void_p,
+                                                  f64p, f64p, f64p])
+            lib.oracle_basket_option.restype = C.c_int
+            lib.oracle_basket_replication.argtypes = ([C.c_int, C.c_int, C.c_int] + [C.c_double] * 6 +
+                                                      [C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int, u32p,
+                                                       f64p, C.c_void_p])
+            lib.oracle_basket_replication.restype = C.c_int
             _lib = lib
     return _lib
 
@@ -295,3 +307,49 @@ def options(specs, L: int, path: int = PATH_BB, n_threads: int = 0, rand: int = 
                                   C.cast(Aptr, C.c_void_p) if Aptr is not None else None,
                                   mean.reshape(-1), se.reshape(-1), am.reshape(-1), n_threads)
     return mean, se, am, used
+
+
+# --------------------------------------------------------------------------
+# basket of M assets (one-factor model, standard construction)
+# --------------------------------------------------------------------------
+def basket_dims(d: int, M: int) -> int:
+    """Sobol dimensions a basket path reads: 1 .. d - 1 + M d (0 is x_1)."""
+    return d - 1 + M * d
+
+
+def basket_path_greeks(type_: int, d: int, M: int, rho, S0, K, r, sigma, T, W0, Bi) -> np.ndarray:
+    """{price, delta, vega, gamma} of one basket path: W0[d] = B~_0(tau_m),
+    Bi[M][d] = B_i(t_{m+1})."""
+    W0 = np.ascontiguousarray(W0, dtype=np.float64)
+    Bi = np.ascontiguousarray(Bi, dtype=np.float64).reshape(-1)
+    out = np.zeros(4)
+    _load().oracle_basket_path_greeks(type_, d, M, rho, S0, K, r, sigma, T, W0, Bi, out)
+    return out
+
+
+def basket_option(type_: int, d: int, M: int, rho, S0, K, r, sigma, T, seed: int, N: int, L: int,
+                  rand: int = RAND_SHIFT):
+    """One basket option: dict(mean[4], stderr[4], abs_mean[4], C_l[L][4])."""
+    V = direction_numbers(basket_dims(d, M) + 1)
+    C_l = np.zeros((L, 4))
+    mean, se, am = np.zeros(4), np.zeros(4), np.zeros(4)
+    rc = _load().oracle_basket_option(type_, d, M, rho, S0, K, r, sigma, T, seed & (2**64 - 1), N, L, rand, V,
+                                      C_l.ctypes.data, mean, se, am)
+    if rc != 0:
+        raise ValueError("oracle_basket_option rejected its arguments")
+    return {"mean": mean, "stderr": se, "abs_mean": am, "C_l": C_l}
+
+
+def basket_replication(o: dict, l: int, k0: int = 0, N: int | None = None, rand: int = RAND_SHIFT) -> np.ndarray:
+    """C_l[4] of replication l of basket option dict o (keys as option() plus n_assets, rho)."""
+    d, M = int(o["d"]), int(o["n_assets"])
+    N = int(o["n_points"]) if N is None else int(N)
+    V = direction_numbers(basket_dims(d, M) + 1)
+    out = np.zeros(4)
+    rc = _load().oracle_basket_replication(int(o["type"]), d, M, float(o["rho"]), float(o["S0"]), float(o["K"]),
+                                           float(o["r"]), float(o["sigma"]), float(o["T"]),
+                                           int(o["seed"]) & (2**64 - 1), k0, N, l, rand, V, out, None)
+    if rc != 0:
+        raise ValueError("oracle_basket_replication rejected its arguments")
+    return out
+

@@ -33,6 +33,12 @@
  *     conditional template, Sec. 6.2): the geometric Asian call, and the puts
  *     of the arithmetic, binary, geometric Asian and of the fixed-strike
  *     lookback, the last on the discrete minimum.
+ *   - ORC_BASKET / ORC_BASKET_PUT (products on several underlyings, Sec.
+ *     6.2): M assets with the same S0 and sigma in a one-factor model,
+ *     W_i = sqrt(rho) B_0 + sqrt(1 - rho) B_i, paid on the average over
+ *     assets and dates; x_1 drives B_0(t_1); standard construction only, the
+ *     common factor's z from dimensions 1..d-1, asset i's d increments from
+ *     dimensions d + i d .. d + i d + d - 1.
  *   - ORC_PCA_FULL (the principal-component conditioning the paper names as
  *     the route to larger variance reduction, Sec. 7): W(t_1..t_d) = A z with
  *     A the d x d principal-component factor of the full covariance
@@ -52,7 +58,8 @@
 #define ORC_MAX_BITS 32
 
 enum { ORC_ARITH = 0, ORC_BINARY = 1, ORC_LOOKBACK = 2, ORC_GEOMETRIC = 3,
-       ORC_ARITH_PUT = 4, ORC_BINARY_PUT = 5, ORC_LOOKBACK_PUT = 6, ORC_GEOMETRIC_PUT = 7 };
+       ORC_ARITH_PUT = 4, ORC_BINARY_PUT = 5, ORC_LOOKBACK_PUT = 6, ORC_GEOMETRIC_PUT = 7,
+       ORC_BASKET = 8, ORC_BASKET_PUT = 9 };
 enum { ORC_BB = 0, ORC_PCA = 1, ORC_STANDARD = 2, ORC_PCA_FULL = 3 };
 enum { ORC_RAND_SHIFT = 0, ORC_RAND_OWEN = 1 };
 
@@ -510,6 +517,67 @@ int oracle_path_greeks_full(int type, int d, double S0, double K, double r,
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Basket of M assets in a one-factor model (products on several
+ * underlyings, Sec. 6.2): S_i(t) = S0 exp(omega t + sigma W_i(t)) with
+ * W_i = sqrt(rho) B_0 + sqrt(1 - rho) B_i (independent Brownian motions; every
+ * pair of assets has correlation rho), paid on X = (1/(M d)) sum_i sum_j
+ * S_i(t_j).  Conditioning on x_1 = B_0(t_1)/sqrt(t_1) (Sec. 3.4.2): every
+ * S_i(t_j) carries exp(sigma sqrt(rho) sqrt(t_1) x_1), so
+ * X = Xt exp(omega t_1 + s1 x_1) with s1 = sigma sqrt(rho t_1) and
+ *   Xt = (1/(M d)) sum S0 exp(omega tau_j + sigma (sqrt(rho) B~_0(tau_j)
+ *        + sqrt(1 - rho) B_i(t_j))),   tau_j = t_j - t_1,
+ * and the breakpoint psi = (ln K - ln Xt - omega t_1)/s1 is closed form.
+ * With a = omega t_1, E[e^{a + s1 x}; x > psi] = e^{a + s1^2/2} Phi(s1 - psi),
+ * so the call is e^{-rT} [Xt e^{a + s1^2/2} Phi(s1 - psi) - K Phi(-psi)];
+ * a + s1^2/2 = r t_1 - (1 - rho) sigma^2 t_1 / 2 depends on sigma unless
+ * rho = 1, which adds Xt d(a + s1^2/2)/d sigma to the pathwise sigma
+ * derivative of Xt in the vega, and ds1/dsigma = sqrt(rho t_1).
+ *
+ * W0[m], m = 0..d-1 : B~_0(tau_m) (W0[0] = 0)
+ * Bi[i*d + m]       : B_i(t_{m+1})
+ * ---------------------------------------------------------------------- */
+void oracle_basket_path_greeks(int type, int d, int M, double rho, double S0, double K, double r,
+                               double sigma, double T, const double *W0, const double *Bi, double *out)
+{
+    double dt = T / d;
+    double t1 = dt;
+    double omega = r - 0.5 * sigma * sigma;
+    double s1 = sigma * sqrt(rho * t1);
+    double a = omega * t1;
+    double D = exp(-r * T);
+    double sr = sqrt(rho), sq = sqrt(1.0 - rho);
+    double X = 0.0, VX = 0.0;
+    for (int i = 0; i < M; ++i)
+        for (int m = 0; m < d; ++m) {
+            double tau = m * dt;
+            double e = sr * W0[m] + sq * Bi[(size_t)i * d + m];
+            double St = S0 * exp(omega * tau + sigma * e);
+            X += St;
+            VX += St * (e - sigma * tau);   /* d/dsigma of omega tau + sigma e */
+        }
+    X /= (double)M * d;
+    VX /= (double)M * d;
+    double Df = D * exp(a + 0.5 * s1 * s1);
+    double dF = -sigma * (1.0 - rho) * t1;   /* d(a + s1^2/2)/d sigma */
+    double psi = (log(K) - log(X) - a) / s1;
+    double phi0 = oracle_norm_pdf(psi);
+    double vs = VX + X * dF;
+    if (type == ORC_BASKET) {
+        double Q0 = oracle_norm_cdf(-psi), Q1 = oracle_norm_cdf(s1 - psi);
+        out[0] = Df * X * Q1 - D * K * Q0;
+        out[1] = Df * (X / S0) * Q1;
+        out[2] = Df * Q1 * vs + D * K * phi0 * sqrt(rho * t1);
+    } else {
+        /* put: pays for x_1 < psi */
+        double P0 = oracle_norm_cdf(psi), P1 = oracle_norm_cdf(psi - s1);
+        out[0] = D * K * P0 - Df * X * P1;
+        out[1] = -Df * (X / S0) * P1;
+        out[2] = -Df * P1 * vs + D * K * phi0 * sqrt(rho * t1);
+    }
+    out[3] = D * K * phi0 / (S0 * S0 * s1);
+}
+
 /* Neumaier's compensated summation. */
 typedef struct { double s, c; } orc_sum;
 static void sum_add(orc_sum *a, double x)
@@ -582,6 +650,83 @@ int oracle_replication(int type, int d, double S0, double K, double r, double si
         if (abs_sum) abs_sum[o] += sum_val(&ab[o]);
     }
     free(z); free(W); free(a1);
+    return 0;
+}
+
+/* Replication l of a basket option (standard construction for every
+ * Brownian motion): C_l[4] over points k0 .. k0 + N - 1, abs_sum[4] += sum |F|. */
+int oracle_basket_replication(int type, int d, int M, double rho, double S0, double K, double r,
+                              double sigma, double T, uint64_t seed, int64_t k0, int64_t N, int l,
+                              int rand, const uint32_t *V, double *C_l, double *abs_sum)
+{
+    if (d < 1 || M < 1 || N < 1 || k0 < 0 || !(rho > 0.0 && rho <= 1.0)) return -1;
+    if (type != ORC_BASKET && type != ORC_BASKET_PUT) return -1;
+    int n = d - 1, dims = n + M * d;
+    double dt = T / d, sdt = sqrt(dt);
+    double *z = (double *)malloc(sizeof(double) * (size_t)(dims + 1));
+    double *W0 = (double *)malloc(sizeof(double) * (size_t)d);
+    double *Bi = (double *)malloc(sizeof(double) * (size_t)M * d);
+    orc_sum acc[4], ab[4];
+    memset(acc, 0, sizeof acc);
+    memset(ab, 0, sizeof ab);
+    for (int64_t k = k0; k < k0 + N; ++k) {
+        for (int j = 1; j <= dims; ++j) {
+            uint32_t y = sobol_int(V + (size_t)j * 32, (uint64_t)k);
+            y = rand == ORC_RAND_OWEN ? oracle_owen(y, oracle_shift(seed, l, j)) : (y ^ oracle_shift(seed, l, j));
+            z[j - 1] = oracle_norm_inv(((double)y + 0.5) / 4294967296.0);
+        }
+        /* common factor after x_1: B~_0(tau_m) = sqrt(dt) (z_1 + ... + z_m) */
+        W0[0] = 0.0;
+        for (int m = 1; m < d; ++m) W0[m] = W0[m - 1] + sdt * z[m - 1];
+        /* asset i: B_i(t_{m+1}) = sqrt(dt) (sum of its first m + 1 increments) */
+        for (int i = 0; i < M; ++i) {
+            double b = 0.0;
+            for (int m = 0; m < d; ++m) {
+                b += sdt * z[n + i * d + m];
+                Bi[(size_t)i * d + m] = b;
+            }
+        }
+        double F[4];
+        oracle_basket_path_greeks(type, d, M, rho, S0, K, r, sigma, T, W0, Bi, F);
+        for (int o = 0; o < 4; ++o) {
+            sum_add(&acc[o], F[o]);
+            sum_add(&ab[o], fabs(F[o]));
+        }
+    }
+    for (int o = 0; o < 4; ++o) {
+        C_l[o] = sum_val(&acc[o]) / (double)N;
+        if (abs_sum) abs_sum[o] += sum_val(&ab[o]);
+    }
+    free(z); free(W0); free(Bi);
+    return 0;
+}
+
+/* All replications of a basket option: mean, stderr, abs_mean as oracle_option. */
+int oracle_basket_option(int type, int d, int M, double rho, double S0, double K, double r,
+                         double sigma, double T, uint64_t seed, int64_t N, int L, int rand,
+                         const uint32_t *V, double *C_l, double *mean, double *stderr_, double *abs_mean)
+{
+    if (L < 1) return -1;
+    double *Cl = (double *)malloc(sizeof(double) * (size_t)L * 4);
+    double absum[4] = {0, 0, 0, 0};
+    for (int l = 0; l < L; ++l)
+        if (oracle_basket_replication(type, d, M, rho, S0, K, r, sigma, T, seed, 0, N, l, rand, V,
+                                      Cl + 4 * l, absum) != 0) {
+            free(Cl);
+            return -1;
+        }
+    for (int o = 0; o < 4; ++o) {
+        orc_sum s = {0, 0};
+        for (int l = 0; l < L; ++l) sum_add(&s, Cl[l * 4 + o]);
+        double C = sum_val(&s) / L;
+        double ss = 0.0;
+        for (int l = 0; l < L; ++l) ss += (Cl[l * 4 + o] - C) * (Cl[l * 4 + o] - C);
+        mean[o] = C;
+        stderr_[o] = (L >= 2) ? sqrt(ss / ((double)L * (L - 1))) : NAN;
+        if (abs_mean) abs_mean[o] = absum[o] / ((double)N * L);
+    }
+    if (C_l) memcpy(C_l, Cl, sizeof(double) * (size_t)L * 4);
+    free(Cl);
     return 0;
 }
 

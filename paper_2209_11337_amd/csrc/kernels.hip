@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <set>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
@@ -758,6 +760,24 @@ static size_t paths_lds_bytes(const LaunchPlan &lp, int bd, int *stk_off)
 // ... against the CU's 160 KiB.
 static bool paths_lds_fits(const LaunchPlan &lp, int bd) { return paths_lds_bytes(lp, bd) <= 160 * 1024; }
 
+// The FP32 kernels read the inverse-normal cells at absolute LDS addresses
+// (cell address = bits of q), which holds only while the kernel has no
+// static LDS, so that its dynamic LDS starts at address 0.  Checked once per
+// kernel before its first launch.
+qcpw_status check_lds_at_zero(const void *fn)
+{
+    static std::mutex mu;
+    static std::set<const void *> ok;
+    std::lock_guard<std::mutex> lk(mu);
+    if (ok.count(fn)) return QCPW_OK;
+    hipFuncAttributes at;
+    QCPW_HIP(hipFuncGetAttributes(&at, fn));
+    if (at.sharedSizeBytes != 0)
+        return fail(QCPW_EDEVICE, "an FP32 kernel has static LDS; its inverse-normal cells must sit at address 0");
+    ok.insert(fn);
+    return QCPW_OK;
+}
+
 template <bool F32, int PATHK, bool OWEN>
 static const void *paths_fn()
 {
@@ -939,6 +959,10 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         int a_stk_off = 0;
         const size_t lds = paths_lds_bytes(lp, bd, &a_stk_off);
         const void *fn = select_paths_kernel(lp);
+        if (lp.precision == QCPW_FP32_MIXED) {
+            qcpw_status st = check_lds_at_zero(fn);
+            if (st != QCPW_OK) return st;
+        }
         QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int per_cu = 0;
         QCPW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds));

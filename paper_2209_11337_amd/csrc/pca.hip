@@ -658,6 +658,10 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
         extra = np_max;
     }
     if (lds > 160 * 1024) return fail(QCPW_EDIMS, "PCA tile exceeds 160 KiB of LDS");
+    if (lp.precision == QCPW_FP32_MIXED) {
+        qcpw_status st = check_lds_at_zero(fn);
+        if (st != QCPW_OK) return st;
+    }
     QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     const int bd = 64 * (lp.precision == QCPW_FP64 ? PCA_WAVES : PCA_AS_WAVES);

@@ -137,4 +137,7 @@ qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index
 
 int autotune_block_threads(Context *ctx, const LaunchPlan &lp);
 
+// Fails unless kernel `fn` has no static LDS (its dynamic LDS starts at 0).
+qcpw_status check_lds_at_zero(const void *fn);
+
 }  // namespace qcpw

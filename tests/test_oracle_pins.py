@@ -718,3 +718,97 @@ def test_ragged_point_count_and_many_options():
         assert np.array_equal(one["mean"], mean[i])
     assert used >= 1
     assert np.all(am >= np.abs(mean) * (1 - 1e-12))
+
+
+# --------------------------------------------------------------------------
+# Basket of M assets, one-factor model (standard construction)
+# --------------------------------------------------------------------------
+def _basket_paths(d, M, T, rng):
+    dt = T / d
+    W0 = np.concatenate([[0.0], np.cumsum(math.sqrt(dt) * rng.standard_normal(d - 1))])
+    Bi = np.cumsum(math.sqrt(dt) * rng.standard_normal((M, d)), axis=1)
+    return W0, Bi
+
+
+@pytest.mark.parametrize("typ,single", [(oracle.BASKET_ASIAN, oracle.ARITH_ASIAN),
+                                        (oracle.BASKET_ASIAN_PUT, oracle.ARITH_ASIAN_PUT)])
+@pytest.mark.parametrize("d,M", [(1, 1), (12, 1), (12, 3), (40, 5)])
+def test_basket_with_full_correlation_is_the_single_asset(typ, single, d, M):
+    """rho = 1: every asset follows B_0, the basket average is the single
+    asset's average, and the estimator (same common dimensions 1..d-1,
+    standard construction) reproduces the single-asset estimate."""
+    S0, K, r, sig, T = 100.0, 104.0, 0.05, 0.25, 1.2
+    b = oracle.basket_option(typ, d, M, 1.0, S0, K, r, sig, T, 31, 2048, 4)
+    a = oracle.option(single, d, S0, K, r, sig, T, 31, 2048, 4, oracle.PATH_STANDARD)
+    np.testing.assert_allclose(b["mean"], a["mean"], rtol=1e-12, atol=1e-13 * S0)
+
+
+@pytest.mark.parametrize("typ", [oracle.BASKET_ASIAN, oracle.BASKET_ASIAN_PUT])
+@pytest.mark.parametrize("d,M,rho", [(1, 2, 0.5), (8, 3, 0.3), (24, 4, 0.8), (12, 2, 0.05)])
+def test_basket_greeks_equal_finite_differences(typ, d, M, rho):
+    """Per path, delta, vega and gamma are the S0 and sigma derivatives of the
+    conditional price with the Brownian paths fixed (catches the sigma
+    dependence of e^{a + s1^2/2} when rho < 1)."""
+    S0, r, sig, T = 100.0, 0.05, 0.2, 1.0
+    rng = np.random.default_rng(100 * d + M)
+    for K in (90.0, 100.0, 112.0):
+        W0, Bi = _basket_paths(d, M, T, rng)
+        g = oracle.basket_path_greeks(typ, d, M, rho, S0, K, r, sig, T, W0, Bi)
+        price = lambda s0, sg: oracle.basket_path_greeks(typ, d, M, rho, s0, K, r, sg, T, W0, Bi)[0]
+        hS, hs = 1e-3, 1e-5
+        delta = (price(S0 + hS, sig) - price(S0 - hS, sig)) / (2 * hS)
+        vega = (price(S0, sig + hs) - price(S0, sig - hs)) / (2 * hs)
+        gamma = (oracle.basket_path_greeks(typ, d, M, rho, S0 + hS, K, r, sig, T, W0, Bi)[1] -
+                 oracle.basket_path_greeks(typ, d, M, rho, S0 - hS, K, r, sig, T, W0, Bi)[1]) / (2 * hS)
+        np.testing.assert_allclose(g[1:], [delta, vega, gamma], rtol=2e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("typ", [oracle.BASKET_ASIAN, oracle.BASKET_ASIAN_PUT])
+@pytest.mark.parametrize("K", [92.0, 101.0, 115.0])
+def test_basket_conditional_price_is_quadrature_of_the_payoff(typ, K):
+    """G = E[discounted payoff | paths without x_1]: integrate the basket
+    payoff over x_1 (B_0(t_j) = sqrt(t_1) x_1 + B~_0(tau_j)) numerically, the
+    breakpoint by root-finding."""
+    S0, r, sig, T, d, M, rho = 100.0, 0.04, 0.3, 1.0, 6, 3, 0.6
+    dt = T / d
+    t = dt * np.arange(1, d + 1)
+    rng = np.random.default_rng(int(K))
+    for _ in range(3):
+        W0, Bi = _basket_paths(d, M, T, rng)
+
+        def avg(x):
+            B0 = math.sqrt(dt) * x + W0
+            S = S0 * np.exp((r - sig**2 / 2) * t[None, :] + sig * (math.sqrt(rho) * B0[None, :] +
+                                                                    math.sqrt(1 - rho) * Bi))
+            return S.mean()
+
+        root = scipy.optimize.brentq(lambda x: avg(x) - K, -80, 80, xtol=1e-15, rtol=1e-15)
+        D = math.exp(-r * T)
+        if typ == oracle.BASKET_ASIAN:
+            f = lambda x: D * max(avg(x) - K, 0.0) * scipy.stats.norm.pdf(x)
+            val = scipy.integrate.quad(f, root, 60, epsabs=0, epsrel=1e-13, limit=200)[0]
+        else:
+            f = lambda x: D * max(K - avg(x), 0.0) * scipy.stats.norm.pdf(x)
+            val = scipy.integrate.quad(f, -60, root, epsabs=0, epsrel=1e-13, limit=200)[0]
+        g = oracle.basket_path_greeks(typ, d, M, rho, S0, K, r, sig, T, W0, Bi)
+        assert abs(g[0] - val) <= 1e-10 * max(abs(val), 1e-12) + 1e-13 * K, (g[0], val)
+
+
+def test_basket_estimate_agrees_with_quadrature_one_date_two_assets():
+    """d = 1, M = 2: the conditioned common normal is integrated in closed
+    form and the two idiosyncratic normals are sampled; E over them of the
+    conditional price and Greeks by 64 x 64 Gauss-Hermite quadrature must lie
+    within 4 standard errors of the randomised QMC estimate."""
+    S0, K, r, sig, T, rho = 100.0, 98.0, 0.03, 0.35, 0.75, 0.4
+    x, w = np.polynomial.hermite_e.hermegauss(64)
+    w = w / w.sum()
+    for typ in (oracle.BASKET_ASIAN, oracle.BASKET_ASIAN_PUT):
+        ref = np.zeros(4)
+        for a, wa in zip(x, w):
+            for b, wb in zip(x, w):
+                Bi = math.sqrt(T) * np.array([[a], [b]])
+                ref += wa * wb * oracle.basket_path_greeks(typ, 1, 2, rho, S0, K, r, sig, T, np.zeros(1), Bi)
+        res = oracle.basket_option(typ, 1, 2, rho, S0, K, r, sig, T, 515, 1 << 12, 16)
+        for i in range(4):
+            assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-12 * abs(ref[i]), (typ, i)
+            assert res["stderr"][i] < 2e-3 * max(abs(ref[i]), 1e-6)
