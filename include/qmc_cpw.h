@@ -57,7 +57,17 @@ enum {
  *                             pays for x_1 below the breakpoint.          */
 enum { QCPW_ARITH_ASIAN_CALL = 0, QCPW_BINARY_ASIAN_CALL = 1, QCPW_LOOKBACK_FIXED_CALL = 2,
        QCPW_GEOMETRIC_ASIAN_CALL = 3, QCPW_ARITH_ASIAN_PUT = 4, QCPW_BINARY_ASIAN_PUT = 5,
-       QCPW_LOOKBACK_FIXED_PUT = 6, QCPW_GEOMETRIC_ASIAN_PUT = 7 };
+       QCPW_LOOKBACK_FIXED_PUT = 6, QCPW_GEOMETRIC_ASIAN_PUT = 7,
+       QCPW_BASKET_ASIAN_CALL = 8, QCPW_BASKET_ASIAN_PUT = 9 };
+/* Basket (products on several underlyings, Sec. 6.2): n_assets assets with
+ * the spec's S0 and sigma in a one-factor model, W_i = sqrt(rho) B_0 +
+ * sqrt(1 - rho) B_i (every pair correlated by rho), paying on the average
+ * of S_i(t_j) over assets and dates.  x_1 drives the common factor's first
+ * step, so the breakpoint stays closed form with s1 = sigma sqrt(rho t_1).
+ * delta and gamma are with respect to the common spot S0, vega to the
+ * common sigma.  QCPW_PATH_STANDARD only; Sobol dimensions 1..d-1 drive the
+ * common factor and d + i d .. d + i d + d - 1 asset i's increments, so
+ * (d - 1) + n_assets d <= QCPW_MAX_BASKET_DIMS.                           */
 
 /* Path construction.  The first three condition on the normal x_1 that
  * drives W(t_1) (Sec. 3.4.2) and build the d-1 remaining coordinates with a
@@ -88,7 +98,7 @@ enum { QCPW_GEMM_FP32 = 0, QCPW_GEMM_BF16X3 = 1 };
 
 /* One option.  Field order and sizes are part of the ABI (64 bytes). */
 typedef struct {
-    int32_t type;      /* QCPW_*_CALL                                          */
+    int32_t type;      /* QCPW_*_CALL, QCPW_*_PUT                              */
     int32_t d;         /* monitoring dates; used when the call's d == 0        */
     double S0;         /* spot S(0) > 0                                        */
     double K;          /* strike > 0                                           */
@@ -99,6 +109,10 @@ typedef struct {
                           not depend on which batch the option rides in)       */
     int64_t n_points;  /* Sobol points per replication; used when the call's
                           n_points == 0                                        */
+    int32_t n_assets;  /* basket types: assets in the basket, 1..QCPW_MAX_ASSETS;
+                          ignored by the other types                          */
+    int32_t reserved;  /* must be 0                                            */
+    double rho;        /* basket types: pairwise correlation, 0 < rho <= 1     */
 } qcpw_option_spec;
 
 /* Limits. */
@@ -106,6 +120,8 @@ typedef struct {
 #define QCPW_MAX_D_PCA 257      /* PCA factor padded to at most 256 x 256            */
 #define QCPW_MAX_D_PCA_FULL 256 /* full-covariance factor, d x d <= 256 x 256         */
 #define QCPW_MAX_SHIFTS 65535   /* replications per option                           */
+#define QCPW_MAX_ASSETS 8       /* assets in a basket                                */
+#define QCPW_MAX_BASKET_DIMS 384 /* Sobol dimensions of a basket path                */
 
 /*
  * qmc_cpw_greeks -- price, delta, vega, gamma of n_opts options.

@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libqmccpw.so")
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK, GEOMETRIC_ASIAN = 0, 1, 2, 3
 ARITH_ASIAN_PUT, BINARY_ASIAN_PUT, LOOKBACK_PUT, GEOMETRIC_ASIAN_PUT = 4, 5, 6, 7
+BASKET_ASIAN, BASKET_ASIAN_PUT = 8, 9
+MAX_ASSETS, MAX_BASKET_DIMS = 8, 384
 PATH_BB, PATH_PCA, PATH_STANDARD, PATH_PCA_FULL = 0, 1, 2, 3
 FP64, FP32_MIXED = 0, 1
 GEMM_FP32, GEMM_BF16X3 = 0, 1
@@ -47,7 +49,7 @@ class QcpwError(RuntimeError):
 class OptionSpec(C.Structure):
     _fields_ = [("type", C.c_int32), ("d", C.c_int32), ("S0", C.c_double), ("K", C.c_double),
                 ("r", C.c_double), ("sigma", C.c_double), ("T", C.c_double), ("seed", C.c_uint64),
-                ("n_points", C.c_int64)]
+                ("n_points", C.c_int64), ("n_assets", C.c_int32), ("reserved", C.c_int32), ("rho", C.c_double)]
 
 
 class RunConfig(C.Structure):
@@ -119,7 +121,8 @@ def make_specs(options: Sequence[dict]) -> C.Array:
     for i, o in enumerate(options):
         arr[i] = OptionSpec(int(o["type"]), int(o.get("d", 0)), float(o["S0"]), float(o["K"]),
                             float(o["r"]), float(o["sigma"]), float(o["T"]),
-                            int(o.get("seed", 0)) & (2**64 - 1), int(o.get("n_points", 0)))
+                            int(o.get("seed", 0)) & (2**64 - 1), int(o.get("n_points", 0)),
+                            int(o.get("n_assets", 0)), 0, float(o.get("rho", 1.0)))
     return arr
 
 

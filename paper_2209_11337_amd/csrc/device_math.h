@@ -147,6 +147,16 @@ struct PathSums {
 // the running maximum, or (geometric average) the sum of Y = log2 S~/S0.
 enum { QCPW_STAT_AVG = 0, QCPW_STAT_MAX = 1, QCPW_STAT_GEO = 2, QCPW_STAT_MIN = 3 };
 
+__host__ __device__ inline bool qcpw_is_put(int type)
+{
+    return (type >= QCPW_ARITH_ASIAN_PUT && type <= QCPW_GEOMETRIC_ASIAN_PUT) || type == QCPW_BASKET_ASIAN_PUT;
+}
+
+__host__ __device__ inline bool qcpw_is_basket(int type)
+{
+    return type == QCPW_BASKET_ASIAN_CALL || type == QCPW_BASKET_ASIAN_PUT;
+}
+
 __host__ __device__ inline int qcpw_stat_of(int type)
 {
     return type == QCPW_LOOKBACK_FIXED_CALL ? QCPW_STAT_MAX
@@ -287,7 +297,9 @@ __device__ inline double ninv_f64(uint32_t y)
 // tail e = erfc(|a|)/2 = exp(-a^2) erfcx(|a|)/2, a = psi/sqrt 2, as e or
 // 1 - e, so neither loses accuracy far from the money.  A put's price is
 // the call's minus the forward of the payoff, so its Greeks are the call's
-// with the X terms negated (binary: all negated).
+// with the X terms negated (binary: all negated).  For a basket (one-factor
+// model) D1 = e^{-rT} e^{omega t1 + s1^2/2}, s1 = sigma sqrt(rho t1), and
+// the vega gains vx_shift X from the sigma dependence of that factor.
 __device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, double VXs, double F[4])
 {
     const OptDev &op = *reread(&op_in);
@@ -297,7 +309,7 @@ __device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, dou
     const double invA = recip_f64(A);
     const double e0 = 0.5 * g0 * erfcx_f64(fabs(psi) * M_SQRT1_2);
     const double e1 = 0.5 * (g0 * op.h * invA) * erfcx_f64(fabs(psi1) * M_SQRT1_2);
-    const bool put = op.type >= QCPW_ARITH_ASIAN_PUT;
+    const bool put = qcpw_is_put(op.type);
     const double T0 = ((psi >= 0.0) != put) ? e0 : 1.0 - e0;    // call: 1 - Phi(psi); put: Phi(psi)
     const double T1 = ((psi1 >= 0.0) != put) ? e1 : 1.0 - e1;   // the same at psi - s1
     const double sgn = put ? -1.0 : 1.0;
@@ -314,7 +326,7 @@ __device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, dou
         const double D1T1 = sgn * op.D1 * T1;
         F[0] = D1T1 * X - sgn * op.D * op.K * T0;
         F[1] = D1T1 * Xs;
-        F[2] = D1T1 * (op.S0 * VXs) + DKphi * op.sqrt_t1;
+        F[2] = D1T1 * (op.S0 * fma(op.vx_shift, Xs, VXs)) + DKphi * op.sqrt_t1;
         F[3] = DKphi * op.inv_s1 * op.inv_S0sq;
     }
 }

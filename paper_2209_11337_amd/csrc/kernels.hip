@@ -250,6 +250,60 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
     }
 }
 
+// The uniform part of Sobol step s (dimension s + 1) for a step index known
+// only at run time (wave-uniform): the register holding it is picked by a
+// uniform branch.
+template <bool OWEN>
+__device__ __forceinline__ uint32_t ubits_at(const UParts<OWEN> &U, uint32_t lane_word, int s)
+{
+    const int k = s & 63;
+    switch (s >> 6) {
+    case 0: return U.bits(lane_word, 0, k);
+    case 1: return U.bits(lane_word, 1, k);
+    case 2: return U.bits(lane_word, 2, k);
+    case 3: return U.bits(lane_word, 3, k);
+    case 4: return U.bits(lane_word, 4, k);
+    default: return U.bits(lane_word, QCPW_UQ - 1, k);
+    }
+}
+
+// Basket of M assets (one-factor model), standard construction, in date
+// order: the common part C_m = log2(e) (omega tau_m + sigma sqrt(rho) B~_0)
+// (steps from dimensions 1..n) and asset i's idiosyncratic part
+// I_i = log2(e) sigma sqrt(1 - rho) B_i(t_{m+1}) (dimensions n + 1 + i d + m)
+// add to Y_{i,m} = C_m + I_i, and every (asset, date) pair feeds the
+// average's sums, date 1 included (its idiosyncratic part is random).
+template <bool F32, bool OWEN>
+__device__ inline void run_basket_wave(const OptDev &op, const uint32_t *lds_lane, int lane, const UParts<OWEN> &U,
+                                       PathSums<typename Real<F32>::T> &ps)
+{
+    using R = typename Real<F32>::T;
+    const int n = op.n, d = op.d, M = op.n_assets;
+    const R drift = F32 ? (R)op.ydrift_1_f : (R)op.ydrift_1;
+    const R bc = F32 ? (R)op.b_common_f : (R)op.b_common;
+    const R bi = F32 ? (R)op.b_idio_f : (R)op.b_idio;
+    auto normal = [&](int s) -> R {
+        const uint32_t y = ubits_at(U, lds_lane[lane_row<F32>(s) + lane], s);
+        if constexpr (F32) return ninv_table_f32(y);
+        else return (R)ninv_f64(y);
+    };
+    R I[QCPW_MAX_ASSETS];
+#pragma unroll
+    for (int i = 0; i < QCPW_MAX_ASSETS; ++i) I[i] = R(0);
+    ps.A1 = R(0);   // no date with a known value: every (asset, date) pair is summed below
+    R Cm = R(0);
+    for (int m = 0; m < d; ++m) {
+        if (m >= 1) Cm = Cm + fma(bc, normal(m - 1), drift);
+#pragma unroll
+        for (int i = 0; i < QCPW_MAX_ASSETS; ++i) {
+            if (i < M) {
+                I[i] = fma(bi, normal(n + i * d + m), I[i]);
+                consume<R, QCPW_STAT_AVG>(ps, Cm + I[i], (R)m);
+            }
+        }
+    }
+}
+
 // One wave's 64 paths from the terminal point (bridge) or the first step
 // (standard) to the last date, accumulated into ps.
 template <bool F32, int PATHK, bool OWEN, int MODE>
@@ -263,6 +317,12 @@ __device__ inline void walk_path(const LaunchDesc &ld, const OptDev &op, const u
         }
         run_bridge_wave<F32, MODE, OWEN>(ld, op, lds_lane, stk, lane, U, ps);
     } else {
+        if constexpr (MODE == QCPW_STAT_AVG) {
+            if (op.n_assets > 0) {
+                run_basket_wave<F32, OWEN>(op, lds_lane, lane, U, ps);
+                return;
+            }
+        }
         run_standard_wave<F32, MODE, OWEN>(op, lds_lane, lane, U, ps);
     }
 }
@@ -284,7 +344,7 @@ __device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op,
         const int s = lane + 64 * q;
         int dim;
         uint32_t u = 0, key = 0;
-        if (s < op.n) {
+        if (s < op.ndims) {
             dim = step_dim<PATHK>(ld, op, s);
             key = digital_shift(op.seed, shift, dim);
             const uint32_t *v = ld.dir + (size_t)dim * 32;
@@ -310,7 +370,7 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
 #pragma unroll
     for (int q = 0; q < QCPW_UQ; ++q) {
         const int s = lane + 64 * q;
-        if (s < op.n) {
+        if (s < op.ndims) {
             const uint32_t *v = ld.dir + (size_t)step_dim<PATHK>(ld, op, s) * 32;
             U.U[q] ^= v[5] ^ v[6 + c];
         }
@@ -406,7 +466,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
             double F[4] = {0.0, 0.0, 0.0, 0.0};
             PathSums<R> ps;
             init_sums(ps);
-            if (op.n > 0) {
+            if (op.ndims > 0) {
                 switch (mode) {
                 case QCPW_STAT_MAX:
                     walk_path<F32, PATHK, OWEN, QCPW_STAT_MAX>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
@@ -569,8 +629,22 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
         const qcpw_option_spec &sp = specs[i];
         const int di = d ? d : sp.d;
         const int64_t Ni = n_points ? n_points : sp.n_points;
-        if (sp.type < QCPW_ARITH_ASIAN_CALL || sp.type > QCPW_GEOMETRIC_ASIAN_PUT)
+        if (sp.type < QCPW_ARITH_ASIAN_CALL || sp.type > QCPW_BASKET_ASIAN_PUT)
             return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": unknown type");
+        if (sp.reserved != 0)
+            return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": reserved field must be 0");
+        if (qcpw_is_basket(sp.type)) {
+            if (path != QCPW_PATH_STANDARD)
+                return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": baskets use the standard construction");
+            if (sp.n_assets < 1 || sp.n_assets > QCPW_MAX_ASSETS)
+                return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": n_assets must be in [1, " +
+                                             std::to_string(QCPW_MAX_ASSETS) + "]");
+            if (!(std::isfinite(sp.rho) && sp.rho > 0.0 && sp.rho <= 1.0))
+                return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": rho must be in (0, 1]");
+            if (di >= 1 && (int64_t)(di - 1) + (int64_t)sp.n_assets * di > QCPW_MAX_BASKET_DIMS)
+                return fail(QCPW_EDIMS, "option " + std::to_string(i) + ": (d - 1) + n_assets d exceeds " +
+                                            std::to_string(QCPW_MAX_BASKET_DIMS));
+        }
         if (path == QCPW_PATH_PCA_FULL && sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL)
             return fail(QCPW_EINVAL, "option " + std::to_string(i) +
                                          ": conditioning on the first principal component covers "
@@ -669,8 +743,28 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.zs_t = (float)op.zscale;
         op.ydrift_n_f = (float)op.ydrift_n;
         op.ydrift_1_f = (float)op.ydrift_1;
-        cost[i] = (double)std::max(op.n, 1) * (double)op.chunks;
-        lp.max_n = std::max(lp.max_n, op.n);
+        op.ndims = op.n;
+        if (qcpw_is_basket(sp.type)) {
+            // one-factor basket: x_1 drives sqrt(rho) of every asset's first step
+            const int M = sp.n_assets;
+            const double rho = sp.rho;
+            op.n_assets = M;
+            op.ndims = op.n + M * di;
+            op.s1 = sp.sigma * std::sqrt(rho * t1);
+            op.inv_s1 = 1.0 / op.s1;
+            op.sqrt_t1 = std::sqrt(rho * t1);   // d s1 / d sigma
+            op.c0 = std::log(sp.K) - std::log(sp.S0) - omega * t1 + std::log((double)M * di);
+            op.h = std::exp(op.c0 - 0.5 * op.s1 * op.s1);
+            op.D1 = std::exp(-sp.r * sp.T + omega * t1 + 0.5 * op.s1 * op.s1);
+            op.vx_shift = -sp.sigma * (1.0 - rho) * t1;
+            op.invd = 1.0 / ((double)M * di);
+            op.b_common = std::sqrt(rho) * op.zscale;
+            op.b_idio = std::sqrt(1.0 - rho) * op.zscale;
+            op.b_common_f = (float)op.b_common;
+            op.b_idio_f = (float)op.b_idio;
+        }
+        cost[i] = (double)std::max(op.ndims, 1) * (double)op.chunks;
+        lp.max_n = std::max(lp.max_n, op.ndims);
         // options walked by a compile-time bridge need no LDS stack
         const bool fixed = precision == QCPW_FP32_MIXED && fixed_bridges_on() && qcpw_has_fixed_bridge(op.n);
         if (path == QCPW_PATH_BB && op.n >= 1 && !fixed)
@@ -679,7 +773,7 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
     // most expensive units first (longest-processing-time order)
     std::vector<int32_t> order(n_opts);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return opts[a].n > opts[b].n; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return opts[a].ndims > opts[b].ndims; });
     lp.opts.resize(n_opts);
     lp.unit_prefix.assign(n_opts + 1, 0);
     for (int i = 0; i < n_opts; ++i) {

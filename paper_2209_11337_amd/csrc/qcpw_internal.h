@@ -186,7 +186,14 @@ struct OptDev {
     const double *pca_A64;        // [n][n] FP64 row-major ([d][n] for PCA_FULL)
     const double *pca_a1;         // PCA_FULL: first column of the d x d unit-dt factor
     int32_t pca_np;               // rows / columns padded to a multiple of 32 (<= QCPW_PCA_NPAD)
+    int32_t n_assets;             // basket: assets M (0 for the single-asset products)
+    int32_t ndims;                // Sobol dimensions a path reads after x_1: n, or n + M d (basket)
     int32_t pad_;
+    // basket: scales of the common and idiosyncratic normals in Y units
+    // (sqrt(rho), sqrt(1 - rho) times sigma sqrt(dt) log2 e), and the sigma
+    // derivative of the drift factor exp(omega t1 + s1^2/2) per unit X
+    double b_common, b_idio, vx_shift;
+    float b_common_f, b_idio_f;
 };
 
 // Packed work description for one launch.

@@ -30,8 +30,9 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_layout():
-    assert C.sizeof(q.OptionSpec) == 64
+    assert C.sizeof(q.OptionSpec) == 80
     assert q.OptionSpec.seed.offset == 48 and q.OptionSpec.n_points.offset == 56
+    assert q.OptionSpec.n_assets.offset == 64 and q.OptionSpec.rho.offset == 72
     assert C.sizeof(q.RunConfig) == 40
 
 
@@ -40,8 +41,8 @@ def test_version_string():
 
 
 BAD = [
-    (dict(type=9), "unknown type"),
-    (dict(type=8), "unknown type"),
+    (dict(type=10), "unknown type"),
+    (dict(type=11), "unknown type"),
     (dict(type=-1), "unknown type"),
     (dict(d=0), "d must be"),
     (dict(d=400), "exceeds"),
@@ -130,6 +131,21 @@ def test_full_pca_argument_checks():
     assert ei.value.status == -4
     with pytest.raises(q.QcpwError):
         q.path_factor(q.PATH_PCA_FULL, 257, 1.0)
+
+
+def test_basket_argument_checks():
+    o = dict(type=8, d=16, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, seed=1, n_points=64, n_assets=4, rho=0.5)
+    for patch, path, msg in [(dict(), q.PATH_BB, "standard construction"),
+                             (dict(), q.PATH_PCA, "standard construction"),
+                             (dict(n_assets=0), q.PATH_STANDARD, "n_assets"),
+                             (dict(n_assets=9), q.PATH_STANDARD, "n_assets"),
+                             (dict(rho=0.0), q.PATH_STANDARD, "rho"),
+                             (dict(rho=1.5), q.PATH_STANDARD, "rho"),
+                             (dict(rho=float("nan")), q.PATH_STANDARD, "rho"),
+                             (dict(d=48, n_assets=8), q.PATH_STANDARD, "exceeds")]:
+        with pytest.raises(q.QcpwError) as ei:
+            q.greeks([dict(o, **patch)], 4, path)
+        assert msg in str(ei.value), (patch, str(ei.value))
 
 
 def test_owen_flag_checks():

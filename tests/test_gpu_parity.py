@@ -30,9 +30,16 @@ def say(*a):
     sys.stdout.flush()
 
 
+def _oracle_one(o, L, path, rand=oracle.RAND_SHIFT):
+    if o["type"] in (oracle.BASKET_ASIAN, oracle.BASKET_ASIAN_PUT):
+        return oracle.basket_option(o["type"], o["d"], o["n_assets"], o["rho"], o["S0"], o["K"], o["r"],
+                                    o["sigma"], o["T"], o["seed"], o["n_points"], L, rand)
+    return oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["seed"],
+                         o["n_points"], L, path, rand)
+
+
 def oracle_many(opts, L, path):
-    out = [oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["seed"],
-                         o["n_points"], L, path) for o in opts]
+    out = [_oracle_one(o, L, path) for o in opts]
     return (np.array([r["mean"] for r in out]), np.array([r["stderr"] for r in out]),
             np.array([r["abs_mean"] for r in out]), np.array([r["C_l"] for r in out]))
 
@@ -373,8 +380,7 @@ def test_fp32_owen_within_bound(path, d):
 
 
 def oracle_many_rand(opts, L, path, rand):
-    out = [oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["seed"],
-                         o["n_points"], L, path, rand) for o in opts]
+    out = [_oracle_one(o, L, path, rand) for o in opts]
     return (np.array([r["mean"] for r in out]), np.array([r["stderr"] for r in out]),
             np.array([r["abs_mean"] for r in out]), np.array([r["C_l"] for r in out]))
 
@@ -477,6 +483,38 @@ def test_geometric_put_full_size_matches_closed_form():
     z = np.abs(g - ref) / (5 * e + FP32_TOL[None, :] * np.abs(ref))
     say("geometric put |g - exact| / allowed:", z.max(axis=0))
     assert (z <= 1).all(), z
+
+
+# ------------------------------------------------------------------------
+# basket of M assets (one-factor model, standard construction)
+# ------------------------------------------------------------------------
+@pytest.mark.parametrize("d,M", [(1, 3), (16, 1), (16, 4), (40, 8)])
+def test_fp64_basket_parity(d, M):
+    opts = workloads.basket_grid(d=d, n_assets=M, n_points=8192 + 77)
+    say("basket fp64", d, M)
+    g, e, ps = q.greeks(opts, 3, q.PATH_STANDARD, q.FP64, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 3, q.PATH_STANDARD)
+    assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
+    assert_scaled(g, m, am, TOL64, "mean")
+
+
+@pytest.mark.parametrize("d,M", [(16, 4), (40, 8)])
+def test_fp32_basket_within_bound(d, M):
+    opts = workloads.basket_grid(d=d, n_assets=M, n_points=8192 + 300)
+    say("basket fp32", d, M)
+    g, e, ps = q.greeks(opts, 2, q.PATH_STANDARD, q.FP32_MIXED, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 2, q.PATH_STANDARD)
+    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    say("basket fp32 scaled error", err.max(axis=(0, 1)))
+    for k in range(4):
+        assert err[..., k].max() <= FP32_TOL[k], (k, err[..., k].max())
+
+
+def test_fp64_basket_owen_parity():
+    opts = workloads.basket_grid(d=12, n_assets=3, n_points=4096 + 77)[::2]
+    g, e, ps = q.greeks(opts, 3, q.PATH_STANDARD, q.FP64, per_shift=True, owen=True)
+    m, se, am, Cl = oracle_many_rand(opts, 3, q.PATH_STANDARD, oracle.RAND_OWEN)
+    assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
 
 
 # ------------------------------------------------------------------------

@@ -21,11 +21,13 @@ import numpy as np
 
 ARITH_ASIAN, BINARY_ASIAN, LOOKBACK, GEOMETRIC_ASIAN = 0, 1, 2, 3
 ARITH_ASIAN_PUT, BINARY_ASIAN_PUT, LOOKBACK_PUT, GEOMETRIC_ASIAN_PUT = 4, 5, 6, 7
+BASKET_ASIAN, BASKET_ASIAN_PUT = 8, 9
 PATH_BB, PATH_PCA, PATH_STANDARD = 0, 1, 2
 TYPE_NAMES = {ARITH_ASIAN: "arith_asian", BINARY_ASIAN: "binary_asian", LOOKBACK: "lookback",
               GEOMETRIC_ASIAN: "geometric_asian", ARITH_ASIAN_PUT: "arith_asian_put",
               BINARY_ASIAN_PUT: "binary_asian_put", LOOKBACK_PUT: "lookback_put",
-              GEOMETRIC_ASIAN_PUT: "geometric_asian_put"}
+              GEOMETRIC_ASIAN_PUT: "geometric_asian_put", BASKET_ASIAN: "basket_asian",
+              BASKET_ASIAN_PUT: "basket_asian_put"}
 
 BASE_SEED = 0x220911337
 
@@ -90,6 +92,17 @@ def put_grid(d: int = 64, n_points: int = 1 << 20) -> list[dict]:
            for t in (ARITH_ASIAN_PUT, BINARY_ASIAN_PUT, LOOKBACK_PUT, GEOMETRIC_ASIAN_PUT)
            for K in (90.0, 100.0, 110.0) for sig in (0.1, 0.3)]
     for o, s in zip(out, _seeds(len(out), BASE_SEED + 4)):
+        o["seed"] = s
+    return out
+
+
+def basket_grid(d: int = 16, n_assets: int = 4, n_points: int = 1 << 20) -> list[dict]:
+    """8 basket options on n_assets assets (one-factor model): {call, put} x
+    K {95, 105} x rho {0.3, 0.8}; S0 = 100, sigma = 0.25, r = 0.05, T = 1."""
+    out = [dict(type=t, d=d, S0=100.0, K=K, r=0.05, sigma=0.25, T=1.0, n_points=n_points,
+                n_assets=n_assets, rho=rho)
+           for t in (BASKET_ASIAN, BASKET_ASIAN_PUT) for K in (95.0, 105.0) for rho in (0.3, 0.8)]
+    for o, s in zip(out, _seeds(len(out), BASE_SEED + 5)):
         o["seed"] = s
     return out
 
