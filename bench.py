@@ -196,6 +196,7 @@ def main():
                        "stderr_ratio_owen_over_shift": {k: float(np.median(e_owen[:, i] / e[:, i]))
                                                         for i, k in enumerate(q.OUTPUTS)}}
         res["geometric"] = geometric_leg(q, workloads, torch, prec)
+        res["more_products"] = more_products_leg(q, workloads, torch, prec)
         res["small_call"] = small_call_leg(q, workloads, torch)
         res["pca"] = pca_leg(q, workloads, torch)
     if not a.no_extras and not a.no_portfolio:
@@ -233,6 +234,36 @@ def geometric_leg(q, workloads, torch, prec, L=32, steps=3):
     return {"value": workloads.total_paths(opts, L) / w, "unit": "Greek-paths/s", "kernel_ms": k_ms / max(k_n, 1),
             "max_abs_err_in_stderr": {k: float(z[:, i].max()) for i, k in enumerate(q.OUTPUTS)},
             "stderr_max_rel": {k: float((e[:, i] / np.abs(exact[:, i])).max()) for i, k in enumerate(q.OUTPUTS)}}
+
+
+def more_products_leg(q, workloads, torch, prec, L=32, steps=2):
+    """Puts (24 options: arithmetic, binary, geometric Asian and lookback on the
+    minimum, d = 64, bridge) and baskets (8 options on 4 assets, d = 64,
+    standard construction), 2^20 points x 32 shifts each: rate, kernel time
+    and the largest relative standard error per Greek."""
+    dev = torch.device("cuda", 0)
+    out = {}
+    for name, opts, path in [("puts_d64_bridge", workloads.put_grid(d=64, n_points=1 << 20), q.PATH_BB),
+                             ("basket_4_assets_d64_standard",
+                              workloads.basket_grid(d=64, n_assets=4, n_points=1 << 20), q.PATH_STANDARD)]:
+        res = (torch.empty((len(opts), 4), dtype=torch.float64, device=dev),
+               torch.empty((len(opts), 4), dtype=torch.float64, device=dev))
+        stream = torch.cuda.Stream()
+        q.greeks(opts, L, path, prec, device_outputs=True, out=res, stream=stream)
+        stream.synchronize()
+        q.kernel_timer(q.TIMER_START)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            q.greeks(opts, L, path, prec, device_outputs=True, out=res, stream=stream)
+        stream.synchronize()
+        w = (time.perf_counter() - t0) / steps
+        k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
+        g, e = res[0].cpu().numpy(), res[1].cpu().numpy()
+        out[name] = {"value": workloads.total_paths(opts, L) / w, "unit": "Greek-paths/s",
+                     "kernel_ms": k_ms / max(k_n, 1),
+                     "stderr_max_rel": {k: float((e[:, i] / np.maximum(np.abs(g[:, i]), 1e-300)).max())
+                                        for i, k in enumerate(q.OUTPUTS)}}
+    return out
 
 
 def small_call_leg(q, workloads, torch, calls=200):
