@@ -66,6 +66,8 @@ def parse():
     p.add_argument("--cpu-points", type=int, default=1 << 19)
     p.add_argument("--no-portfolio", action="store_true", help="skip the uneven-portfolio leg")
     p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    p.add_argument("--pca-only", action="store_true",
+                   help="run only the principal-component leg (one timed call per GEMM) and print it")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed loop, run one plain device copy of this many MiB "
                         "(reference kernel for HBM byte counters)")
@@ -86,6 +88,9 @@ def main():
     q.lib()  # raises if the HIP library is not built
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if a.pca_only:
+        print(json.dumps({"pca": pca_leg(q, workloads, torch, steps=1)}), flush=True)
+        return
     L = 32
     opts = workloads.three_products_grid(d=64, n_points=1 << 20)
     n_paths = workloads.total_paths(opts, L)
