@@ -211,23 +211,65 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
     }
     sa = quad_sum(sa);
     sb = quad_sum(sb);
-    double x = (log(K) - sa / d) / (sb / d);
+    const double x0 = (log(K) - sa / d) / (sb / d);   // Jensen bound, right of the root
     const double lndk = log(K * d);
-    for (int it = 0; it < 64; ++it) {
-        double S = 0.0, S1 = 0.0;
-        for (int j = part; j < d; j += PARTS) {
-            const double be = sdt * a1[j];
-            const double g = exp(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x);
-            S += g;
-            S1 += be * g;
+    // Moments M_k = sum_j g_j beta_j^k of g_j = exp(alpha_j + beta_j x0), k = 0..KM:
+    // S(x0 + delta) = sum_k M_k delta^k / k! is the Taylor series of the sum,
+    // so Newton's method runs on it without further exponentials.
+    constexpr int KM = 8;
+    double Mk[KM + 1];
+#pragma unroll
+    for (int k = 0; k <= KM; ++k) Mk[k] = 0.0;
+    double bmax = 0.0;
+    for (int j = part; j < d; j += PARTS) {
+        const double be = sdt * a1[j];
+        double p = exp(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x0);
+#pragma unroll
+        for (int k = 0; k <= KM; ++k) {
+            Mk[k] += p;
+            p *= be;
         }
-        S = quad_sum(S);
-        S1 = quad_sum(S1);
-        const double dx = (log(S) - lndk) * S / S1;
-        x -= dx;
-        if (!(fabs(dx) > 1e-12 * (1.0 + fabs(x)))) break;   // also ends on NaN
+        bmax = fmax(bmax, fabs(be));
+    }
+#pragma unroll
+    for (int k = 0; k <= KM; ++k) Mk[k] = quad_sum(Mk[k]);
+#pragma unroll
+    for (int m = 1; m < PARTS; m <<= 1) bmax = fmax(bmax, __shfl_xor(bmax, m, 64));
+    double delta = 0.0;
+    for (int it = 0; it < 64; ++it) {
+        double S = Mk[KM] / 40320.0, S1 = 0.0;   // 1/8!
+        double fk = 40320.0;
+#pragma unroll
+        for (int k = KM - 1; k >= 0; --k) {      // S = sum M_k d^k/k!, S1 = sum M_{k+1} d^k/k!
+            fk /= (k + 1);
+            S1 = fma(S1, delta, Mk[k + 1] / fk);
+            S = fma(S, delta, Mk[k] / fk);
+        }
+        const double dd = (log(S) - lndk) * S / S1;
+        delta -= dd;
+        if (!(fabs(dd) > 1e-13 * (1.0 + fabs(x0 + delta)))) break;   // also ends on NaN
+    }
+    double x = x0 + delta;
+    // The series' truncation error is below (bmax |delta|)^9 / 9! relative;
+    // when that may exceed FP64 rounding, finish with Newton on the exact sum.
+    if (!(bmax * fabs(delta) < 0.1)) {
+        for (int it = 0; it < 64; ++it) {
+            double S = 0.0, S1 = 0.0;
+            for (int j = part; j < d; j += PARTS) {
+                const double be = sdt * a1[j];
+                const double g = exp(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x);
+                S += g;
+                S1 += be * g;
+            }
+            S = quad_sum(S);
+            S1 = quad_sum(S1);
+            const double dx = (log(S) - lndk) * S / S1;
+            x -= dx;
+            if (!(fabs(dx) > 1e-12 * (1.0 + fabs(x)))) break;   // also ends on NaN
+        }
     }
     const double psi = x;
+    const double epsi = exp(-0.5 * psi * psi);
     const bool arith = op.type == QCPW_ARITH_ASIAN_CALL;
     double F1 = 0.0, F2 = 0.0, Fs = 0.0, sEP = 0.0, sV = 0.0, sAg = 0.0;
     for (int j = part; j < d; j += PARTS) {
@@ -238,7 +280,11 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
         const double g = exp(al + be * psi);
         F1 += be * g;
         if (arith) {
-            const double EP = exp(al + 0.5 * be * be) * 0.5 * erfc((psi - be) * M_SQRT1_2);
+            // EP = e^{alpha + beta^2/2} erfc(u)/2, u = (psi - beta)/sqrt 2; e^{alpha + beta^2/2 - u^2}
+            // = g e^{-psi^2/2}, so EP = erfcx(u) g e^{-psi^2/2} / 2 for u >= 0 (no exponential)
+            const double u = (psi - be) * M_SQRT1_2;
+            const double t = 0.5 * erfcx_f64(fabs(u)) * g * epsi;
+            const double EP = u >= 0.0 ? t : exp(al + 0.5 * be * be) - t;
             sEP += EP;
             sV += EP * (das + be * a);
             sAg += a * g;
@@ -249,7 +295,7 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
     }
     F1 = quad_sum(F1) / d;
     const double D = op.D, S0 = op.S0;
-    const double phi0 = exp(-0.5 * psi * psi) * 0.39894228040143267794;
+    const double phi0 = epsi * 0.39894228040143267794;
     if (arith) {
         sEP = quad_sum(sEP) / d;
         sV = quad_sum(sV) / d;
