@@ -56,6 +56,29 @@ def kernel_sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
+# The paper's own timings (Sec. 6.1; Tesla T4, CUDA 11.2, FP32 path arithmetic, CPU model not
+# stated): context only, other hardware and a single option per kernel run.
+PAPER_CONTEXT = {
+    "hardware": "NVIDIA Tesla T4 (paper), serial CPU of unstated model",
+    "qmc_bb_cpw_kernel_ms": {"2^15 paths": 0.8, "2^19 paths": 12.5},
+    "other_cpw_kernel_ms": {"2^15 paths": 0.2, "2^19 paths": 3.0},
+    "serial_cpu_ms_2^15_paths": 150.0,
+    "speedup_vs_serial_cpu": {"qmc_bb_cpw": "about 200x", "other methods": "over 500x (d=64), 900x (d=256)"},
+    "derived_greek_paths_per_s_qmc_bb_cpw": 4.2e7,
+}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -184,7 +207,17 @@ def main():
         res["cpu_baseline"] = {"value": workloads.total_paths(sample, Ls) / tc, "unit": "Greek-paths/s",
                                "cores": used, "kind": "oracle",
                                "sample": "the 18 options at d=64, 2^%d points x %d shifts (%.1f s)"
-                                         % (int(np.log2(n_cpu)), Ls, tc)}
+                                         % (int(np.log2(n_cpu)), Ls, tc),
+                               "cpu_model": cpu_model()}
+        # one host thread, a smaller sample of the same workload
+        sample1 = workloads.three_products_grid(d=64, n_points=1 << 14)
+        t0 = time.perf_counter()
+        oracle.options(sample1, 2, oracle.PATH_BB, n_threads=1)
+        t1c = time.perf_counter() - t0
+        res["cpu_baseline"]["single_thread"] = {"value": workloads.total_paths(sample1, 2) / t1c,
+                                                "sample": "the 18 options at d=64, 2^14 points x 2 shifts (%.1f s)"
+                                                          % t1c}
+        res["paper_context"] = PAPER_CONTEXT
     if not a.no_extras:
         # the same workload randomised by nested scrambling instead of the shift
         q.greeks(opts, L, q.PATH_BB, prec, device_outputs=True, out=out, stream=stream, owen=True)
@@ -207,7 +240,12 @@ def main():
     if not a.no_extras and not a.no_portfolio:
         res["portfolio"] = portfolio_leg(q, workloads, torch)
     if not a.no_extras and not a.no_serve:
-        res["serving"] = serving_leg(q, workloads)
+        # the configured stream (1..512 options, d in [4, 365], targets 1e-4 / 1e-6, which the
+        # point cap of 2^22 per option decides): a short stream at a rate the GPU sustains
+        res["serving"] = serving_leg(q, workloads, n_requests=12, rate=0.3, max_opts=512, d_range=(4, 365),
+                                     targets=(1e-4, 1e-6), fp64_requests=3, fp64_max_opts=8)
+        # a dense stream of small requests (1..32 options, d in [4, 64], targets 1e-3 / 1e-4)
+        res["serving_small_requests"] = serving_leg(q, workloads)
     print(json.dumps(res), flush=True)
 
 
@@ -372,14 +410,17 @@ def portfolio_leg(q, workloads, torch):
                                            "seconds": t64}}
 
 
-def serving_leg(q, workloads, n_requests=300, rate=100.0):
+def serving_leg(q, workloads, n_requests=300, rate=100.0, max_opts=32, d_range=(4, 64), targets=(1e-3, 1e-4),
+                fp64_requests=40, fp64_max_opts=None):
     """Poisson request stream into the continuous-batching server (FP32-mixed):
-    requests of 1..32 options (d in [4, 64]) with a target standard error of
-    1e-3 or 1e-4 (relative to max(1, |Greek|)); latency = submit to result.
-    Beside it the plain path: each option of the first 40 requests alone in
-    FP64 at the point count the server reached."""
+    requests of 1..max_opts options (d in d_range, otherwise drawn as the
+    uneven portfolio) with a target standard error from `targets` (relative
+    to max(1, |Greek|)); latency = submit to result.  Beside it the plain
+    path: each option of the first fp64_requests requests (at most
+    fp64_max_opts options of each) alone in FP64 at the point count the
+    server reached."""
     import threading
-    stream = workloads.request_stream(n_requests, rate, max_opts=32, d_range=(4, 64), targets=(1e-3, 1e-4))
+    stream = workloads.request_stream(n_requests, rate, max_opts=max_opts, d_range=d_range, targets=targets)
     L = 16
     lat, pts, paths = [], [], 0
     done = {}
@@ -428,21 +469,26 @@ def serving_leg(q, workloads, n_requests=300, rate=100.0):
     lat = np.array(lat) * 1e3
     # plain FP64, one option per launch, same points
     base_lat, base_paths, t64 = [], 0, 0.0
-    for (rid, ts, r), p in list(zip(ids, pts))[:40]:
+    for (rid, ts, r), p in list(zip(ids, pts))[:fp64_requests]:
+        sub = r["options"][:fp64_max_opts]
         t1 = time.perf_counter()
-        for o in r["options"]:
+        for o in sub:
             q.greeks([dict(o, n_points=p)], L, q.PATH_BB, q.FP64)
         dt = time.perf_counter() - t1
         base_lat.append(dt * 1e3)
         t64 += dt
-        base_paths += len(r["options"]) * p * L
-    return {"requests": n_requests, "rate_per_s": rate, "shifts": L, "p50_ms": float(np.percentile(lat, 50)),
+        base_paths += len(sub) * p * L
+    return {"requests": n_requests, "rate_per_s": rate, "options_per_request": [1, max_opts],
+            "d_range": list(d_range), "target_stderr": list(targets), "shifts": L,
+            "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "mean_points": float(np.mean(pts)),
             "value": paths / wall, "unit": "Greek-paths/s", "launches": stats["launches"],
             "fp64_one_option_per_launch": {"value": base_paths / t64,
                                            "p50_ms_no_queueing": float(np.percentile(base_lat, 50)),
                                            "p99_ms_no_queueing": float(np.percentile(base_lat, 99)),
-                                           "sample": "first 40 requests"}}
+                                           "sample": "first %d requests%s" % (
+                                               fp64_requests, "" if fp64_max_opts is None else
+                                               ", first %d options of each" % fp64_max_opts)}}
 
 
 if __name__ == "__main__":
