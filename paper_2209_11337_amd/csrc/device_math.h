@@ -381,15 +381,4 @@ __device__ inline typename Real<F32>::T coord_tab(uint32_t y, const OptDev &op)
     }
 }
 
-// Sobol + shift + inverse normal for one coordinate, result in Y units.
-template <bool F32>
-__device__ inline typename Real<F32>::T coord(uint32_t y, const OptDev &op)
-{
-    if constexpr (F32) {
-        return ninv_scaled_f32(y, op.zs_a);
-    } else {
-        return ninv_f64(y) * op.zscale;
-    }
-}
-
 }  // namespace qcpw

@@ -738,8 +738,6 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         op.invd = 1.0 / di;
         op.inv_S0 = 1.0 / sp.S0;
         op.inv_S0sq = 1.0 / (sp.S0 * sp.S0);
-        // the PCA kernel's polynomial inverse normal folds sqrt(2) and 2^-31 into its scale
-        op.zs_a = (float)(op.zscale * M_SQRT2 * 0x1p-31);
         op.zs_t = (float)op.zscale;
         op.ydrift_n_f = (float)op.ydrift_n;
         op.ydrift_1_f = (float)op.ydrift_1;

@@ -177,7 +177,6 @@ struct OptDev {
     double inv_s1, s1, sqrt_t1, inv_sigma;
     double S0, K, D, D1, invd, inv_S0, inv_S0sq;
     float ydrift_n_f, ydrift_1_f;
-    float zs_a;                   // sqrt(2) zscale 2^-31 (FP32 polynomial inverse normal, PCA)
     float zs_t;                   // zscale (FP32 table inverse normal)
     // principal-component factor of this option's n (unit dt), device layouts:
     const float *pca_At;          // [NP][NP] FP32, k-major: At[k][row]
