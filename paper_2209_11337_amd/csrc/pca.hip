@@ -526,15 +526,32 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
             sums_neutral(ps0, lo);
             sums_neutral(ps1, lo);
             const float drift = op.ydrift_1_f;
-            if (gemm_wave) {
+            // each product needs one statistic: the average's sums (one exp2 and three
+            // sums per date), the sum of Y, or the running extreme
+            auto rows = [&](auto add) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int m = 32 * wave + (r >> 2) * 8 + khalf * 4 + (r & 3);
                     if (m < n) {
                         const float mf = (float)(m + 1);
-                        sums_add_date<float>(ps0, fmaf(drift, mf, acc0[r]), mf, lo);
-                        sums_add_date<float>(ps1, fmaf(drift, mf, acc1[r]), mf, lo);
+                        add(ps0, fmaf(drift, mf, acc0[r]), mf);
+                        add(ps1, fmaf(drift, mf, acc1[r]), mf);
                     }
+                }
+            };
+            if (gemm_wave) {
+                const int mode = qcpw_stat_of(op.type);
+                if (mode == QCPW_STAT_AVG) {
+                    rows([](PcaSums<float> &p, float Y, float mf) {
+                        const float E = exp2_r(Y);
+                        p.A1 += E;
+                        p.A2y = fmaf(E, Y, p.A2y);
+                        p.A2m = fmaf(E, mf, p.A2m);
+                    });
+                } else if (mode == QCPW_STAT_GEO) {
+                    rows([](PcaSums<float> &p, float Y, float) { p.sY += Y; });
+                } else {
+                    rows([lo](PcaSums<float> &p, float Y, float mf) { sums_add_date<float>(p, Y, mf, lo); });
                 }
             }
             // lane halves hold other rows of the same points; lane l keeps point l
