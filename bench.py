@@ -100,8 +100,8 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (its work units "
+              "would shard across GPUs by option, replication and point range)", file=sys.stderr)
         sys.exit(2)
     import torch
 
