@@ -3,8 +3,8 @@
 //
 // One persistent launch covers every option of a call.  Work units are
 // (option, replication l, range of unit_pts consecutive Sobol points, a
-// function of the option's point count alone); each wave pulls units from a
-// device counter and gives each lane one point per iteration, so for point
+// function of the option's point count alone); each wave pulls units from
+// device counters and gives each lane one point per iteration, so for point
 // k = base + lane (base a multiple of 64):
 //
 //   Sobol integer of dimension j (Sec. 2.2.2, XOR form of
@@ -430,13 +430,27 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
     for (int i = tid; i < max_n * 64; i += bd) lds_lane[lane_row<F32>(i >> 6) + (i & 63)] = lane_tab[64 + i];
     __syncthreads();
 
+    // Units are dealt out by QCPW_QUEUES counters, queue q holding units
+    // q, q + QCPW_QUEUES, ...  All waves of the chip would otherwise take
+    // turns on one atomic (served one after another in memory, of the order
+    // of 10 ns each), which bounds launches of many cheap units.  Workgroups
+    // go to the XCDs in turn, so a wave starts on the queue of its
+    // workgroup's XCD and, once that queue is empty, helps the others in
+    // order; it leaves after finding all of them empty.
     int o = 0;
+    int q = blockIdx.x & (QCPW_QUEUES - 1);
+    int empty = 0;
     for (;;) {
         unsigned long long u = 0;
-        if (lane == 0) u = atomicAdd(counter, 1ull);
-        const long long unit = ((long long)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
-                               (unsigned)__builtin_amdgcn_readfirstlane((int)u);
-        if (unit >= total_units) break;
+        if (lane == 0) u = atomicAdd(counter + q * QCPW_QUEUE_STRIDE, 1ull);
+        const long long j = ((long long)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                            (unsigned)__builtin_amdgcn_readfirstlane((int)u);
+        const long long unit = j * QCPW_QUEUES + q;
+        if (unit >= total_units) {
+            if (++empty == QCPW_QUEUES) break;
+            q = (q + 1) & (QCPW_QUEUES - 1);
+            continue;
+        }
 
         // option of this unit (units are consumed in increasing order, so the
         // previous option is the usual answer)
@@ -499,7 +513,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
     }
 }
 
-__global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
+__global__ void reset_counter_kernel(unsigned long long *counter)
+{
+    if (threadIdx.x < QCPW_QUEUES) counter[threadIdx.x * QCPW_QUEUE_STRIDE] = 0ull;
+}
 
 // One block per option: replication estimates C_l (chunk partials added in
 // chunk order), then the mean over replications and its standard error.
@@ -821,7 +838,7 @@ static WsLayout ws_layout(const LaunchPlan &lp)
     w.partials = align_up(w.prefix + (n + 1) * sizeof(int64_t), 256);
     w.per_shift = align_up(w.partials + (size_t)lp.total_units * 8 * sizeof(double), 256);
     w.counter = align_up(w.per_shift + n * (size_t)lp.n_shifts * 4 * sizeof(double), 256);
-    w.scratch = align_up(w.counter + 256, 256);
+    w.scratch = align_up(w.counter + QCPW_QUEUES * QCPW_QUEUE_STRIDE * sizeof(unsigned long long), 256);
     w.total = align_up(w.scratch + (size_t)lp.full_blocks * 64 * QCPW_MAX_D_PCA_FULL * sizeof(double), 256);
     return w;
 }
@@ -1023,7 +1040,7 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
     const size_t n = lp.opts.size();
     QCPW_HIP(hipMemcpyAsync(d_opts, h_opts, n * sizeof(OptDev), hipMemcpyHostToDevice, stream));
     QCPW_HIP(hipMemcpyAsync(d_prefix, h_prefix, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-    reset_counter_kernel<<<1, 1, 0, stream>>>(d_counter);
+    reset_counter_kernel<<<1, 64, 0, stream>>>(d_counter);
     QCPW_HIP(hipGetLastError());
 
     LaunchDesc ld;

@@ -40,6 +40,10 @@ __host__ __device__ constexpr int qcpw_row_word(int r)
                                  : QCPW_LDS_FIXED / 4 + 64 * (r - QCPW_LDS_GAP_ROWS);
 }
 
+// Work queues of the fused kernel: one head per XCD, each on its own
+// 256-byte line.  Queue q hands out units q, q + QCPW_QUEUES, ...
+#define QCPW_QUEUES 8
+#define QCPW_QUEUE_STRIDE 32     // u64 words between heads
 #define QCPW_CHUNK 8192          // alignment of point ranges; points per PCA work unit
 
 // Points per work unit of the fused kernel (one wave per unit): a function of
@@ -208,5 +212,5 @@ struct LaunchDesc {
     const uint32_t *lane;         // [QCPW_TAB_DIMS][64]
     double *partials;             // [total_units][8]
     double *scratch;              // FP64 PCA_FULL: [workgroup][date][64] products
-    unsigned long long *counter;  // work-queue head
+    unsigned long long *counter;  // work-queue heads, QCPW_QUEUES of them, QCPW_QUEUE_STRIDE apart
 };
