@@ -127,6 +127,17 @@ def test_fp64_edge_counts_and_largest_d():
         assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
 
 
+@pytest.mark.parametrize("units", [1, 7, 9, 17])
+def test_fp64_every_unit_once(units):
+    # fewer, and not a multiple of, the work queues of the fused kernel: one
+    # option of 256-point units, so the launch holds exactly `units` units
+    o = dict(type=0, d=5, S0=100, K=100, r=0.03, sigma=0.3, T=1.0, seed=11 + units, n_points=256 * units)
+    say("units", units)
+    g, e, ps = q.greeks([o], 1, q.PATH_BB, q.FP64, per_shift=True)
+    m, se, am, Cl = oracle_many([o], 1, q.PATH_BB)
+    assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
+
+
 def test_single_shift_gives_nan_stderr():
     g, e = q.greeks(workloads.single_asian(n_points=256), 1, q.PATH_BB, q.FP64)
     assert np.all(np.isnan(e)) and np.all(np.isfinite(g))
