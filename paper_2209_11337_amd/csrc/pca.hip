@@ -34,6 +34,8 @@ namespace qcpw {
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned short v8us __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 static constexpr int TP = 64;        // points per tile (one wave width)
 static constexpr int PCA_WAVES = 4;     // waves per workgroup (FP64)
@@ -420,7 +422,9 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
         // Waves 1..7 generate the normals (wave 0 meanwhile runs the previous
         // tile's FP64 tail): prologue wave pw = wave - 1 takes dimensions
         // 1 + PD pw .. PD (pw + 1), and its lane l holds the uniform part of 1 + PD pw + l.
-        constexpr int PD = (QCPW_PCA_NPAD + PCA_AS_WAVES - 2) / (PCA_AS_WAVES - 1);
+        // (even with BF16 Z, so that pairs of columns share one 32-bit store)
+        constexpr int PD0 = (QCPW_PCA_NPAD + PCA_AS_WAVES - 2) / (PCA_AS_WAVES - 1);
+        constexpr int PD = BF16X3 ? (PD0 + 1) & ~1 : PD0;
         static_assert(PD <= 64, "one uniform part per lane");
         const int pw = wave - 1;
         const int myj = 1 + PD * pw + lane;
@@ -441,6 +445,17 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
                 Zf[lane * zstride + k] = z;
             }
         };
+        // BF16 Z: columns k, k + 1 (k even) rounded to BF16 together, hi and lo
+        // parts each stored as one 32-bit word
+        auto store_pair = [&](int jj, float z0, float z1) {
+            const int k = PD * pw + jj;
+            const f32x2 v = {z0, z1};
+            const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+            const f32x2 hv = {__uint_as_float(hb << 16), __uint_as_float(hb & 0xFFFF0000u)};
+            const uint32_t lb = __builtin_bit_cast(uint32_t, __builtin_convertvector(v - hv, bf16x2));
+            *(uint32_t *)&Zh[lane * zstride + k] = hb;
+            *(uint32_t *)&Zl[lane * zstride + k] = lb;
+        };
         auto prologue = [&](int64_t base) {
             // lane-table words eight at a time, all loads in flight before the first use
             for (int j0 = 0; j0 < jc; j0 += 8) {
@@ -448,11 +463,19 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
                     w[i] = j0 + i < jc ? lane_tab[(size_t)(1 + PD * pw + j0 + i) * 64 + lane] : 0u;
-                if (!BF16X3 && j0 + 8 <= jc) {
+                if (BF16X3) {
+                    // two columns at a time (both cell reads before the branch)
+#pragma unroll
+                    for (int i = 0; i < 8; i += 2) {
+                        if (j0 + i >= jc) break;
+                        const float z0 = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
+                        const float z1 = ninv_table_f32(w[i + 1] ^ rdlane(U, j0 + i + 1)) * op.zs_t;
+                        if (j0 + i + 1 < jc) store_pair(j0 + i, z0, z1);
+                        else store_z(j0 + i, z0);
+                    }
+                } else if (j0 + 8 <= jc) {
                     // a whole group: the eight cell reads go out before any store
                     // into Z, with no branch between them, so their latencies overlap
-                    // (FP32 Z only: with the BF16 split the extra live values spill,
-                    // measured 5 % slower)
                     float z[8];
 #pragma unroll
                     for (int i = 0; i < 8; ++i) z[i] = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
