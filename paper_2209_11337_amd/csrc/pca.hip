@@ -463,7 +463,13 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
                     w[i] = j0 + i < jc ? lane_tab[(size_t)(1 + PD * pw + j0 + i) * 64 + lane] : 0u;
-                if (BF16X3) {
+                if (BF16X3 && j0 + 8 <= jc) {
+                    float z[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) z[i] = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
+#pragma unroll
+                    for (int i = 0; i < 8; i += 2) store_pair(j0 + i, z[i], z[i + 1]);
+                } else if (BF16X3) {
                     // two columns at a time (both cell reads before the branch)
 #pragma unroll
                     for (int i = 0; i < 8; i += 2) {
