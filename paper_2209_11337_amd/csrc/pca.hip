@@ -463,35 +463,24 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
                     w[i] = j0 + i < jc ? lane_tab[(size_t)(1 + PD * pw + j0 + i) * 64 + lane] : 0u;
-                if (BF16X3 && j0 + 8 <= jc) {
-                    float z[8];
+                // the group's eight cell reads go out before any store into Z, with
+                // no branch between them, so their latencies overlap (past jc the
+                // value is computed from a zero word and never stored)
+                float z[8];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) z[i] = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
+                for (int i = 0; i < 8; ++i) z[i] = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
+                if (j0 + 8 <= jc) {
 #pragma unroll
-                    for (int i = 0; i < 8; i += 2) store_pair(j0 + i, z[i], z[i + 1]);
-                } else if (BF16X3) {
-                    // two columns at a time (both cell reads before the branch)
-#pragma unroll
-                    for (int i = 0; i < 8; i += 2) {
-                        if (j0 + i >= jc) break;
-                        const float z0 = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
-                        const float z1 = ninv_table_f32(w[i + 1] ^ rdlane(U, j0 + i + 1)) * op.zs_t;
-                        if (j0 + i + 1 < jc) store_pair(j0 + i, z0, z1);
-                        else store_z(j0 + i, z0);
+                    for (int i = 0; i < 8; i += BF16X3 ? 2 : 1) {
+                        if (BF16X3) store_pair(j0 + i, z[i], z[i + 1]);
+                        else store_z(j0 + i, z[i]);
                     }
-                } else if (j0 + 8 <= jc) {
-                    // a whole group: the eight cell reads go out before any store
-                    // into Z, with no branch between them, so their latencies overlap
-                    float z[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) z[i] = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) store_z(j0 + i, z[i]);
                 } else {
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) {
+                    for (int i = 0; i < 8; i += BF16X3 ? 2 : 1) {
                         if (j0 + i >= jc) break;
-                        store_z(j0 + i, ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t);
+                        if (BF16X3 && j0 + i + 1 < jc) store_pair(j0 + i, z[i], z[i + 1]);
+                        else store_z(j0 + i, z[i]);
                     }
                 }
             }
