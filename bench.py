@@ -43,8 +43,8 @@ PEAK_F64 = 78.6e12        # MI355X vector FP64
 # paths_kernel_fp32_bridge_three_products_d64.md), valid only for the kernel
 # sources they were taken on (sha256 prefix of their concatenation).
 TRAFFIC_SOURCES = ("kernels.hip", "device_math.h", "qcpw_internal.h", "ninv_table.inc")
-TRAFFIC_SHA = "a3017762fbe71056"
-TRAFFIC_BYTES = {"fetch": 0.891e6, "write": 15.729e6}
+TRAFFIC_SHA = "058e69e34590da59"
+TRAFFIC_BYTES = {"fetch": 0.925e6, "write": 15.729e6}
 
 
 def kernel_sources_sha() -> str:

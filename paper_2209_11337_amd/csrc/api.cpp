@@ -220,7 +220,7 @@ static void free_graph(Context::Graph &g)
 }
 
 // QCPW_FLAG_GRAPH: replay the captured graph of an identical earlier call, or
-// capture this call's device work (uploads from pinned copies, counter reset,
+// capture this call's device work (the set-up copy from a pinned buffer,
 // per-path kernel, finalize) into a new graph with its own workspace.
 static qcpw_status run_graph(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
                              int64_t n_points, int32_t n_shifts, int32_t path, const qcpw_run_config &c,
@@ -254,22 +254,18 @@ static qcpw_status run_graph(Context *ctx, const qcpw_option_spec *specs, int32_
     Context::Graph g;
     g.key = key;
     const size_t need = launch_workspace_bytes(lp);
-    const size_t n = lp.opts.size();
-    const size_t hbytes = n * sizeof(OptDev) + (n + 1) * sizeof(int64_t);
+    const size_t hbytes = launch_upload_bytes(lp);
     if (hipMalloc(&g.ws, need) != hipSuccess || hipHostMalloc(&g.host, hbytes, hipHostMallocDefault) != hipSuccess) {
         free_graph(g);
         return fail(QCPW_ENOMEM, "graph workspace allocation failed");
     }
-    OptDev *h_opts = (OptDev *)g.host;
-    int64_t *h_prefix = (int64_t *)((char *)g.host + n * sizeof(OptDev));
-    memcpy(h_opts, lp.opts.data(), n * sizeof(OptDev));
-    memcpy(h_prefix, lp.unit_prefix.data(), (n + 1) * sizeof(int64_t));
+    fill_launch_upload(lp, g.host);
     hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) {
         free_graph(g);
         return fail(QCPW_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
-    st = enqueue_launch(ctx, lp, stream, g_out, e_out, c.out_per_shift, g.ws, need, h_opts, h_prefix);
+    st = enqueue_launch(ctx, lp, stream, g_out, e_out, c.out_per_shift, g.ws, need, g.host);
     e = hipStreamEndCapture(stream, &g.graph);
     if (st != QCPW_OK || e != hipSuccess) {
         free_graph(g);
@@ -343,7 +339,7 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
         e = (double *)(p + ((out_bytes + 255) / 256) * 256);
         ps = c.out_per_shift ? (double *)(p + 2 * ((out_bytes + 255) / 256) * 256) : nullptr;
     }
-    st = enqueue_launch(ctx, lp, stream, g, e, ps, ws, need, nullptr, nullptr, true);
+    st = enqueue_launch(ctx, lp, stream, g, e, ps, ws, need, nullptr, true);
     if (st != QCPW_OK) return st;
     QCPW_HIP(hipEventRecord(ctx->ws_done, stream));
     ctx->ws_pending = true;

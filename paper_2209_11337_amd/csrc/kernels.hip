@@ -513,10 +513,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
     }
 }
 
-__global__ void reset_counter_kernel(unsigned long long *counter)
-{
-    if (threadIdx.x < QCPW_QUEUES) counter[threadIdx.x * QCPW_QUEUE_STRIDE] = 0ull;
-}
 
 // One block per option: replication estimates C_l (chunk partials added in
 // chunk order), then the mean over replications and its standard error.
@@ -825,8 +821,11 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Workspace of one launch.  The option table, the unit prefix and the queue
+// heads lead, so that one host-to-device copy of `upload` bytes (the heads
+// as zeros) sets up a launch.
 struct WsLayout {
-    size_t opts, prefix, partials, per_shift, counter, scratch, total;
+    size_t opts, prefix, counter, upload, partials, per_shift, scratch, total;
 };
 
 static WsLayout ws_layout(const LaunchPlan &lp)
@@ -835,12 +834,24 @@ static WsLayout ws_layout(const LaunchPlan &lp)
     const size_t n = lp.opts.size();
     w.opts = 0;
     w.prefix = align_up(w.opts + n * sizeof(OptDev), 256);
-    w.partials = align_up(w.prefix + (n + 1) * sizeof(int64_t), 256);
+    w.counter = align_up(w.prefix + (n + 1) * sizeof(int64_t), 256);
+    w.upload = w.counter + QCPW_QUEUES * QCPW_QUEUE_STRIDE * sizeof(unsigned long long);
+    w.partials = align_up(w.upload, 256);
     w.per_shift = align_up(w.partials + (size_t)lp.total_units * 8 * sizeof(double), 256);
-    w.counter = align_up(w.per_shift + n * (size_t)lp.n_shifts * 4 * sizeof(double), 256);
-    w.scratch = align_up(w.counter + QCPW_QUEUES * QCPW_QUEUE_STRIDE * sizeof(unsigned long long), 256);
+    w.scratch = align_up(w.per_shift + n * (size_t)lp.n_shifts * 4 * sizeof(double), 256);
     w.total = align_up(w.scratch + (size_t)lp.full_blocks * 64 * QCPW_MAX_D_PCA_FULL * sizeof(double), 256);
     return w;
+}
+
+size_t launch_upload_bytes(const LaunchPlan &lp) { return ws_layout(lp).upload; }
+
+void fill_launch_upload(const LaunchPlan &lp, void *dst)
+{
+    const WsLayout w = ws_layout(lp);
+    const size_t n = lp.opts.size();
+    memset(dst, 0, w.upload);
+    memcpy((char *)dst + w.opts, lp.opts.data(), n * sizeof(OptDev));
+    memcpy((char *)dst + w.prefix, lp.unit_prefix.data(), (n + 1) * sizeof(int64_t));
 }
 
 size_t launch_workspace_bytes(const LaunchPlan &lp) { return ws_layout(lp).total; }
@@ -1012,7 +1023,7 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
 
 qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream, double *dev_out_greeks,
                            double *dev_out_stderr, double *dev_out_per_shift, void *ws, size_t ws_bytes,
-                           const OptDev *h_opts, const int64_t *h_prefix, bool timed)
+                           const void *h_upload, bool timed)
 {
     // qcpw_kernel_timer: a pair of events around the main kernel
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -1027,8 +1038,6 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         t1 = tm.ev[tm.used + 1];
         tm.used += 2;
     }
-    if (!h_opts) h_opts = lp.opts.data();
-    if (!h_prefix) h_prefix = lp.unit_prefix.data();
     const WsLayout w = ws_layout(lp);
     if (ws_bytes < w.total) return fail(QCPW_ENOMEM, "workspace too small");
     char *base = (char *)ws;
@@ -1038,10 +1047,14 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
     double *d_per_shift = dev_out_per_shift ? dev_out_per_shift : (double *)(base + w.per_shift);
     unsigned long long *d_counter = (unsigned long long *)(base + w.counter);
     const size_t n = lp.opts.size();
-    QCPW_HIP(hipMemcpyAsync(d_opts, h_opts, n * sizeof(OptDev), hipMemcpyHostToDevice, stream));
-    QCPW_HIP(hipMemcpyAsync(d_prefix, h_prefix, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-    reset_counter_kernel<<<1, 64, 0, stream>>>(d_counter);
-    QCPW_HIP(hipGetLastError());
+    // options, unit prefix and zeroed queue heads in one copy
+    std::vector<unsigned char> staged;
+    if (!h_upload) {
+        staged.resize(w.upload);
+        fill_launch_upload(lp, staged.data());
+        h_upload = staged.data();
+    }
+    QCPW_HIP(hipMemcpyAsync(base, h_upload, w.upload, hipMemcpyHostToDevice, stream));
 
     LaunchDesc ld;
     ld.opts = d_opts;

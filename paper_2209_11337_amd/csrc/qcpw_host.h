@@ -119,17 +119,21 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
 
 // Device bytes one launch needs in the workspace.
 size_t launch_workspace_bytes(const LaunchPlan &lp);
+// Host bytes a launch uploads to the start of its workspace (option table,
+// unit prefix, zeroed work-queue heads), and the routine that writes them.
+size_t launch_upload_bytes(const LaunchPlan &lp);
+void fill_launch_upload(const LaunchPlan &lp, void *dst);
 
 // Enqueues the whole hot path on `stream`: uploads, the per-path kernel, the
 // finalize kernel; results go to dev_out_greeks / dev_out_stderr ([n][4],
 // caller order) and optionally dev_out_per_shift ([n][L][4]).
-// h_opts / h_prefix: host copies to upload from (default: lp's own vectors;
-// graph capture passes pinned copies that outlive the call).
+// h_upload: the launch_upload_bytes(lp) bytes to upload (default: written
+// from lp into a host buffer here; graph capture passes a pinned copy that
+// outlives the call).
 qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream,
                            double *dev_out_greeks, double *dev_out_stderr,
                            double *dev_out_per_shift, void *ws, size_t ws_bytes,
-                           const OptDev *h_opts = nullptr, const int64_t *h_prefix = nullptr,
-                           bool timed = false);
+                           const void *h_upload = nullptr, bool timed = false);
 
 qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index, int32_t n_dims,
                                 int64_t k0, int64_t count, uint32_t *dev_out, hipStream_t stream,
