@@ -158,6 +158,18 @@ def test_fp32_mixed_within_bound(path):
         assert err[..., k].max() <= FP32_TOL[k], (k, err[..., k].max())
 
 
+@pytest.mark.parametrize("d", [16, 32, 128, 256])
+def test_fp32_bridge_across_d(d):
+    # compile-time bridges (n = 15, 31, 127) and the plan walker (n = 255)
+    opts = workloads.three_products_grid(d=d, n_points=4096 + 77)[::4]
+    say("fp32 bridge", d)
+    g, e, ps = q.greeks(opts, 2, q.PATH_BB, q.FP32_MIXED, per_shift=True)
+    m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_BB)
+    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    for k in range(4):
+        assert err[..., k].max() <= FP32_TOL[k], (d, k, err[..., k].max())
+
+
 def test_fp32_mixed_portfolio_within_bound():
     opts = workloads.portfolio(24, seed=99, log2_points=(10, 12))
     say("fp32 portfolio")
