@@ -311,22 +311,25 @@ def more_products_leg(q, workloads, torch, prec, L=32, steps=2):
 
 def small_call_leg(q, workloads, torch, calls=200):
     """Latency-bound call: one arithmetic Asian, d = 16, 2^12 points x 16
-    shifts, FP64 bridge, device outputs; per-call time eager vs replayed
-    from a captured HIP graph."""
+    shifts, bridge, device outputs; per-call time eager vs replayed from a
+    captured HIP graph, in FP64 (eager_us, graph_us) and FP32-mixed
+    (fp32_eager_us, fp32_graph_us)."""
     opts = workloads.single_asian()
     s = torch.cuda.Stream()
     out = (torch.empty((1, 4), dtype=torch.float64, device="cuda"),
            torch.empty((1, 4), dtype=torch.float64, device="cuda"))
-    res = {"workload": "1 arithmetic Asian, d=16, 2^12 points x 16 shifts, FP64, bridge"}
-    for name, graph in (("eager_us", False), ("graph_us", True)):
-        for _ in range(3):
-            q.greeks(opts, 16, q.PATH_BB, q.FP64, device_outputs=True, out=out, stream=s, graph=graph)
-        s.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(calls):
-            q.greeks(opts, 16, q.PATH_BB, q.FP64, device_outputs=True, out=out, stream=s, graph=graph)
-        s.synchronize()
-        res[name] = (time.perf_counter() - t0) / calls * 1e6
+    res = {"workload": "1 arithmetic Asian, d=16, 2^12 points x 16 shifts, bridge; FP64 (eager_us, graph_us) "
+                       "and FP32-mixed (fp32_eager_us, fp32_graph_us)"}
+    for prefix, prec in (("", q.FP64), ("fp32_", q.FP32_MIXED)):
+        for name, graph in (("eager_us", False), ("graph_us", True)):
+            for _ in range(3):
+                q.greeks(opts, 16, q.PATH_BB, prec, device_outputs=True, out=out, stream=s, graph=graph)
+            s.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                q.greeks(opts, 16, q.PATH_BB, prec, device_outputs=True, out=out, stream=s, graph=graph)
+            s.synchronize()
+            res[prefix + name] = (time.perf_counter() - t0) / calls * 1e6
     return res
 
 
