@@ -96,7 +96,7 @@ enum { QCPW_FP64 = 0, QCPW_FP32_MIXED = 1 };
  * products hi*hi + hi*lo + lo*hi accumulated in FP32.  Ignored otherwise. */
 enum { QCPW_GEMM_FP32 = 0, QCPW_GEMM_BF16X3 = 1 };
 
-/* One option.  Field order and sizes are part of the ABI (64 bytes). */
+/* One option.  Field order and sizes are part of the ABI (80 bytes). */
 typedef struct {
     int32_t type;      /* QCPW_*_CALL, QCPW_*_PUT                              */
     int32_t d;         /* monitoring dates; used when the call's d == 0        */
@@ -167,6 +167,10 @@ typedef struct {
                                    (workgroup size of the per-path kernel; the PCA
                                    kernel always uses 256)                          */
     int32_t flags;              /* QCPW_FLAG_* bits                                  */
+    double *out_paper_sigma;    /* optional [n_opts][4]: the spread of the single
+                                   replications sqrt((1/L) sum_l (C - C_l)^2), the
+                                   sigma Sec. 5 reports (= out_stderr sqrt(L - 1));
+                                   host or device as out_greeks; NaN when L == 1  */
 } qcpw_run_config;
 
 /* Capture the device work of a call into a HIP graph the first time a given
@@ -205,8 +209,10 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
  * qcpw_sobol_points -- the shifted Sobol integers the kernels consume, for
  * checking them bit for bit: out[k][j] = (G_j gray(k0 + k)) XOR s_{l,j},
  * k = 0..count-1, j = 0..n_dims-1 (dimension 0 unshifted), computed on the
- * device by the same code path as the per-path kernel.  out is a host array
- * [count][n_dims] (uint32).  n_dims <= 1024, count <= 2^24.
+ * device by a kernel of its own through the same lane-table / wave-uniform
+ * split as the per-path kernel (qcpw_path_coordinates records what the
+ * per-path kernel itself consumes).  out is a host array [count][n_dims]
+ * (uint32).  n_dims <= 1024, count <= 2^24.
  */
 qcpw_status qcpw_sobol_points(uint64_t seed, int32_t shift_index, int32_t n_dims,
                               int64_t k0, int64_t count, uint32_t *out);
@@ -218,6 +224,23 @@ qcpw_status qcpw_sobol_points(uint64_t seed, int32_t shift_index, int32_t n_dims
  */
 qcpw_status qcpw_scrambled_points(uint64_t seed, int32_t shift_index, int32_t n_dims,
                                   int64_t k0, int64_t count, uint32_t *out);
+
+/*
+ * qcpw_path_coordinates -- the randomised Sobol integers (Sec. 2.2.2 XOR form
+ * in Gray-code order, then the digital shift or, with QCPW_FLAG_OWEN in
+ * flags, nested scrambling, Sec. 2.2.3) exactly as the fused per-path kernel
+ * consumes them while it walks one option, recorded by an instance of that
+ * kernel that also stores every coordinate it reads: out[l][k][j] for
+ * replication l < n_shifts, point k < spec->n_points and dimension j + 1,
+ * j < spec->d - 1 (plus n_assets * d for baskets).  spec: one option (its
+ * d and n_points fields are used); path_construction QCPW_PATH_BB or
+ * QCPW_PATH_STANDARD; precision as for _ex (the FP32 kernel walks
+ * d = 16, 32, 64, 128 with its compile-time bridges).  out: host array,
+ * caller-owned.  Errors: QCPW_EINVAL (as qmc_cpw_greeks, other
+ * constructions or flags, d = 1, more than 2^28 bytes of output).
+ */
+qcpw_status qcpw_path_coordinates(const qcpw_option_spec *spec, int32_t n_shifts, int32_t path_construction,
+                                  int32_t precision, int32_t flags, uint32_t *out);
 
 /*
  * qcpw_path_factor -- the factor A (row-major (d-1) x (d-1), FP64) that the

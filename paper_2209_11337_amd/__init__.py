@@ -35,7 +35,8 @@ STATUS = {0: "QCPW_OK", -1: "QCPW_EINVAL", -2: "QCPW_ENOMEM", -3: "QCPW_EDEVICE"
           -5: "QCPW_EBUSY", -6: "QCPW_ECANCELLED", -7: "QCPW_ENOTFOUND"}
 
 # names of every entry point declared in include/qmc_cpw.h
-EXPORTS = ("qmc_cpw_greeks", "qmc_cpw_greeks_ex", "qcpw_sobol_points", "qcpw_scrambled_points", "qcpw_path_factor",
+EXPORTS = ("qmc_cpw_greeks", "qmc_cpw_greeks_ex", "qcpw_sobol_points", "qcpw_scrambled_points",
+           "qcpw_path_coordinates", "qcpw_path_factor",
            "qcpw_kernel_timer", "qcpw_last_error", "qcpw_version", "qcpw_server_create", "qcpw_submit", "qcpw_poll",
            "qcpw_wait", "qcpw_cancel", "qcpw_server_stats", "qcpw_server_destroy")
 
@@ -55,7 +56,8 @@ class OptionSpec(C.Structure):
 class RunConfig(C.Structure):
     _fields_ = [("precision", C.c_int32), ("pca_gemm", C.c_int32), ("device", C.c_int32),
                 ("outputs_on_device", C.c_int32), ("stream", C.c_void_p),
-                ("out_per_shift", C.c_void_p), ("block_threads", C.c_int32), ("flags", C.c_int32)]
+                ("out_per_shift", C.c_void_p), ("block_threads", C.c_int32), ("flags", C.c_int32),
+                ("out_paper_sigma", C.c_void_p)]
 
 
 _lib = None
@@ -83,6 +85,7 @@ def lib() -> C.CDLL:
             L.qmc_cpw_greeks_ex.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p, vp]
             L.qcpw_sobol_points.argtypes = [u64, i32, i32, i64, i64, vp]
             L.qcpw_scrambled_points.argtypes = [u64, i32, i32, i64, i64, vp]
+            L.qcpw_path_coordinates.argtypes = [vp, i32, i32, i32, i32, vp]
             L.qcpw_path_factor.argtypes = [i32, i32, C.c_double, vp]
             L.qcpw_kernel_timer.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(i64)]
             L.qcpw_last_error.restype = C.c_char_p
@@ -129,13 +132,15 @@ def make_specs(options: Sequence[dict]) -> C.Array:
 def greeks(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precision: int = FP64,
            d: int = 0, n_points: int = 0, pca_gemm: int = GEMM_FP32, per_shift: bool = False,
            block_threads: int = 0, stream=None, device_outputs: bool = False, device: int = -1,
-           out=None, graph: bool = False, owen: bool = False):
+           out=None, graph: bool = False, owen: bool = False, paper_sigma: bool = False):
     """Greeks of many options in one launch.
 
-    Host mode (default): returns (greeks[n][4], stderr[n][4]) numpy arrays
-    (and per_shift[n][L][4] if asked).  Device mode: ``out`` is a tuple of
-    torch CUDA tensors (greeks, stderr[, per_shift]) the results are written
-    to on ``stream`` (default: torch's current stream); returns ``out``.
+    Host mode (default): returns (greeks[n][4], stderr[n][4]) numpy arrays,
+    followed by per_shift[n][L][4] and paper_sigma[n][4] (the spread of the
+    single replications) when asked for.  Device mode: ``out`` is a tuple of
+    torch CUDA tensors (greeks, stderr[, per_shift][, paper_sigma]) the
+    results are written to on ``stream`` (default: torch's current stream);
+    returns ``out``.
     """
     specs = make_specs(options)
     n = len(options)
@@ -149,23 +154,30 @@ def greeks(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precisio
                    torch.empty((n, 4), dtype=torch.float64, device=dev))
             if per_shift:
                 out = out + (torch.empty((n, n_shifts, 4), dtype=torch.float64, device=dev),)
+            if paper_sigma:
+                out = out + (torch.empty((n, 4), dtype=torch.float64, device=dev),)
         s = stream if stream is not None else torch.cuda.current_stream()
         cfg.stream = C.c_void_p(s.cuda_stream)
         if per_shift:
             cfg.out_per_shift = C.c_void_p(out[2].data_ptr())
+        if paper_sigma:
+            cfg.out_paper_sigma = C.c_void_p(out[3 if per_shift else 2].data_ptr())
         _check(lib().qmc_cpw_greeks_ex(specs, n, d, n_points, n_shifts, path, out[0].data_ptr(),
                                        out[1].data_ptr(), C.byref(cfg)))
         return out
     g = np.zeros((n, 4))
     e = np.zeros((n, 4))
     ps = np.zeros((n, n_shifts, 4)) if per_shift else None
+    sg = np.zeros((n, 4)) if paper_sigma else None
     if per_shift:
         cfg.out_per_shift = C.c_void_p(ps.ctypes.data)
+    if paper_sigma:
+        cfg.out_paper_sigma = C.c_void_p(sg.ctypes.data)
     if stream is not None:
         cfg.stream = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
     _check(lib().qmc_cpw_greeks_ex(specs, n, d, n_points, n_shifts, path, g.ctypes.data, e.ctypes.data,
                                    C.byref(cfg)))
-    return (g, e, ps) if per_shift else (g, e)
+    return (g, e) + ((ps,) if per_shift else ()) + ((sg,) if paper_sigma else ())
 
 
 def greeks_plain(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, d: int = 0,
@@ -186,6 +198,19 @@ def sobol_points(seed: int, shift_index: int, n_dims: int, k0: int, count: int,
     out = np.zeros((count, n_dims), dtype=np.uint32)
     f = lib().qcpw_scrambled_points if owen else lib().qcpw_sobol_points
     _check(f(seed & (2**64 - 1), shift_index, n_dims, k0, count, out.ctypes.data))
+    return out
+
+
+def path_coordinates(option: dict, n_shifts: int, path: int = PATH_BB, precision: int = FP32_MIXED,
+                     owen: bool = False) -> np.ndarray:
+    """The randomised Sobol integers the per-path kernel consumes for one
+    option: [n_shifts][n_points][dimensions 1..], recorded by the kernel."""
+    spec = make_specs([option])
+    d = int(option["d"])
+    nd = d - 1 + (int(option.get("n_assets", 0)) * d if option["type"] in (BASKET_ASIAN, BASKET_ASIAN_PUT) else 0)
+    out = np.zeros((n_shifts, int(option["n_points"]), nd), dtype=np.uint32)
+    _check(lib().qcpw_path_coordinates(spec, n_shifts, path, precision, FLAG_OWEN if owen else 0,
+                                       out.ctypes.data))
     return out
 
 

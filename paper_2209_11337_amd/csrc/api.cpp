@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -15,6 +16,14 @@
 namespace qcpw {
 
 #include "ninv_table.inc"
+
+// the option record's size and field offsets are ABI
+static_assert(sizeof(qcpw_option_spec) == 80, "qcpw_option_spec is 80 bytes");
+static_assert(sizeof(qcpw_run_config) == 48 && offsetof(qcpw_run_config, out_paper_sigma) == 40,
+              "qcpw_run_config layout");
+static_assert(offsetof(qcpw_option_spec, seed) == 48 && offsetof(qcpw_option_spec, n_points) == 56 &&
+                  offsetof(qcpw_option_spec, rho) == 72,
+              "qcpw_option_spec field offsets");
 
 static thread_local std::string g_last_error;
 
@@ -230,7 +239,7 @@ static qcpw_status run_graph(Context *ctx, const qcpw_option_spec *specs, int32_
     append(key, specs, sizeof(qcpw_option_spec) * (size_t)n_opts);
     const int64_t scal[] = {n_opts, d, n_points, n_shifts, path, c.precision, c.pca_gemm, c.block_threads, c.flags};
     append(key, scal, sizeof scal);
-    const void *ptrs[] = {c.stream, g_out, e_out, c.out_per_shift};
+    const void *ptrs[] = {c.stream, g_out, e_out, c.out_per_shift, c.out_paper_sigma};
     append(key, ptrs, sizeof ptrs);
     hipStream_t stream = (hipStream_t)c.stream;
     for (auto &g : ctx->graphs)
@@ -265,7 +274,8 @@ static qcpw_status run_graph(Context *ctx, const qcpw_option_spec *specs, int32_
         free_graph(g);
         return fail(QCPW_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
-    st = enqueue_launch(ctx, lp, stream, g_out, e_out, c.out_per_shift, g.ws, need, g.host);
+    st = enqueue_launch(ctx, lp, stream, g_out, e_out, c.out_per_shift, g.ws, need, g.host, false,
+                        c.out_paper_sigma);
     e = hipStreamEndCapture(stream, &g.graph);
     if (st != QCPW_OK || e != hipSuccess) {
         free_graph(g);
@@ -322,7 +332,8 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
     const size_t ps_bytes = n * (size_t)n_shifts * 4 * sizeof(double);
     const size_t need = launch_workspace_bytes(lp);
     const bool dev_out = c.outputs_on_device != 0;
-    const size_t extra = dev_out ? 0 : 2 * out_bytes + (c.out_per_shift ? ps_bytes : 0) + 768;
+    const size_t out_al = (out_bytes + 255) / 256 * 256;
+    const size_t extra = dev_out ? 0 : 3 * out_al + (c.out_per_shift ? ps_bytes : 0) + 256;
     hipStream_t stream = (hipStream_t)c.stream;   // NULL is the default stream
     if (ctx->ws_pending) {
         // the workspace may still be in use by a launch on another stream
@@ -332,14 +343,15 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
     st = ctx->ws.ensure(need + extra);
     if (st != QCPW_OK) return st;
     char *ws = (char *)ctx->ws.ptr;
-    double *g = out_greeks, *e = out_stderr, *ps = c.out_per_shift;
+    double *g = out_greeks, *e = out_stderr, *ps = c.out_per_shift, *sg = c.out_paper_sigma;
     if (!dev_out) {
         char *p = ws + need;
         g = (double *)p;
-        e = (double *)(p + ((out_bytes + 255) / 256) * 256);
-        ps = c.out_per_shift ? (double *)(p + 2 * ((out_bytes + 255) / 256) * 256) : nullptr;
+        e = (double *)(p + out_al);
+        sg = c.out_paper_sigma ? (double *)(p + 2 * out_al) : nullptr;
+        ps = c.out_per_shift ? (double *)(p + 3 * out_al) : nullptr;
     }
-    st = enqueue_launch(ctx, lp, stream, g, e, ps, ws, need, nullptr, true);
+    st = enqueue_launch(ctx, lp, stream, g, e, ps, ws, need, nullptr, true, sg);
     if (st != QCPW_OK) return st;
     QCPW_HIP(hipEventRecord(ctx->ws_done, stream));
     ctx->ws_pending = true;
@@ -348,6 +360,8 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
         QCPW_HIP(hipMemcpyAsync(out_stderr, e, out_bytes, hipMemcpyDeviceToHost, stream));
         if (c.out_per_shift)
             QCPW_HIP(hipMemcpyAsync(c.out_per_shift, ps, ps_bytes, hipMemcpyDeviceToHost, stream));
+        if (c.out_paper_sigma)
+            QCPW_HIP(hipMemcpyAsync(c.out_paper_sigma, sg, out_bytes, hipMemcpyDeviceToHost, stream));
         QCPW_HIP(hipStreamSynchronize(stream));
     }
     return QCPW_OK;
@@ -425,6 +439,57 @@ static qcpw_status points(uint64_t seed, int32_t shift_index, int32_t n_dims, in
     if (st != QCPW_OK) return st;
     QCPW_HIP(hipMemcpyAsync(out, ctx->ws.ptr, bytes, hipMemcpyDeviceToHost, ctx->own_stream));
     QCPW_HIP(hipStreamSynchronize(ctx->own_stream));
+    return QCPW_OK;
+}
+
+qcpw_status qcpw_path_coordinates(const qcpw_option_spec *spec, int32_t n_shifts, int32_t path_construction,
+                                  int32_t precision, int32_t flags, uint32_t *out)
+{
+    g_last_error.clear();
+    if (!out) return fail(QCPW_EINVAL, "out is NULL");
+    qcpw_status st = validate_call(spec, 1, 0, 0, n_shifts, path_construction, precision, QCPW_GEMM_FP32, 0);
+    if (st != QCPW_OK) return st;
+    if (path_construction != QCPW_PATH_BB && path_construction != QCPW_PATH_STANDARD)
+        return fail(QCPW_EINVAL, "coordinates are recorded by the per-path kernel (BB and STANDARD)");
+    if (flags & ~QCPW_FLAG_OWEN) return fail(QCPW_EINVAL, "only QCPW_FLAG_OWEN is accepted");
+    const bool owen = (flags & QCPW_FLAG_OWEN) != 0;
+    const bool basket = spec->type == QCPW_BASKET_ASIAN_CALL || spec->type == QCPW_BASKET_ASIAN_PUT;
+    const int64_t ndims = (int64_t)(spec->d - 1) + (basket ? (int64_t)spec->n_assets * spec->d : 0);
+    if (ndims < 1) return fail(QCPW_EINVAL, "the option has no sampled coordinate (d = 1)");
+    const int64_t N = spec->n_points;
+    if ((int64_t)n_shifts * N * ndims * 4 > (int64_t(1) << 28))
+        return fail(QCPW_EINVAL, "n_shifts * n_points * dimensions * 4 exceeds 2^28 bytes");
+    Context *ctx = nullptr;
+    st = get_context(-1, &ctx);
+    if (st != QCPW_OK) return st;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    LaunchPlan lp;
+    st = plan_launch(ctx, spec, 1, 0, 0, n_shifts, path_construction, precision, QCPW_GEMM_FP32, 256, lp, nullptr,
+                     owen);
+    if (st != QCPW_OK) return st;
+    const OptDev &op = lp.opts[0];
+    const size_t need = (launch_workspace_bytes(lp) + 255) / 256 * 256;
+    const size_t pbytes = (size_t)lp.total_units * op.unit_pts * ndims * 4;
+    if (ctx->ws_pending) QCPW_HIP(hipEventSynchronize(ctx->ws_done));
+    st = ctx->ws.ensure(need + 1024 + pbytes);
+    if (st != QCPW_OK) return st;
+    char *ws = (char *)ctx->ws.ptr;
+    double *g = (double *)(ws + need);
+    lp.probe = (uint32_t *)(ws + need + 1024);
+    st = enqueue_launch(ctx, lp, ctx->own_stream, g, g + 4, g + 8, ws, need);
+    if (st != QCPW_OK) return st;
+    std::vector<uint32_t> rec(pbytes / 4);
+    QCPW_HIP(hipMemcpyAsync(rec.data(), lp.probe, pbytes, hipMemcpyDeviceToHost, ctx->own_stream));
+    QCPW_HIP(hipStreamSynchronize(ctx->own_stream));
+    // recorded as [unit][batch][dim][lane], unit = l * chunks + chunk, point
+    // k = chunk * unit_pts + batch * 64 + lane
+    for (int64_t l = 0; l < n_shifts; ++l)
+        for (int64_t k = 0; k < N; ++k) {
+            const int64_t pb = l * (int64_t)op.chunks * (op.unit_pts / 64) + k / 64;
+            const uint32_t *src = rec.data() + (size_t)pb * ndims * 64 + (k & 63);
+            uint32_t *dst = out + ((size_t)l * N + k) * ndims;
+            for (int64_t j = 0; j < ndims; ++j) dst[j] = src[j * 64];
+        }
     return QCPW_OK;
 }
 

@@ -57,15 +57,25 @@ struct UnitCtx {
 // s = lane + 64 q, U[q] = G_dim gray(base), folded with the digital shift
 // (the lane table is folded too), or -- with nested scrambling -- raw, with
 // the dimension's scrambling seed in Sd[q] (the lane table then raw too).
-template <bool OWEN>
+// PROBE instances also record every coordinate the walk consumes, at
+// pr[(dim - 1) * 64 + lane] of the current 64-point batch, so that the
+// integers of the per-path kernel itself can be checked bit for bit.
+template <bool OWEN_, bool PROBE = false>
 struct UParts {
+    static constexpr bool OWEN = OWEN_;
     uint32_t U[QCPW_UQ];
     uint32_t Sd[OWEN ? QCPW_UQ : 1];
+    uint32_t *pr;
     // randomised coordinate of step 64 q + k from the lane's table word
     __device__ __forceinline__ uint32_t bits(uint32_t lane_word, int q, int k) const
     {
         if constexpr (OWEN) return owen_scramble(lane_word ^ rdlane(U[q], k), rdlane(Sd[q], k));
         else return lane_word ^ rdlane(U[q], k);
+    }
+    __device__ __forceinline__ uint32_t rec(uint32_t y, int dim, int lane) const
+    {
+        if constexpr (PROBE) pr[(dim - 1) * 64 + lane] = y;
+        return y;
     }
 };
 
@@ -77,10 +87,10 @@ __device__ __forceinline__ int lane_row(int r)
     return F32 ? qcpw_row_word(r) : 64 * r;
 }
 
-template <bool F32, int MODE, bool OWEN>
+template <bool F32, int MODE, class UP>
 __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
                                        typename Real<F32>::T *stk, int lane,
-                                       const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps)
+                                       const UP &U, PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
     const int n = op.n;
@@ -89,7 +99,7 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
     R L = R(0), Rr;
     {   // terminal point
         const PlanStep st = plan[0];
-        const uint32_t x = U.bits(lds_lane[(F32 ? st.lds_off : (st.dim - 1) * 64) + lane], 0, 0);
+        const uint32_t x = U.rec(U.bits(lds_lane[(F32 ? st.lds_off : (st.dim - 1) * 64) + lane], 0, 0), st.dim, lane);
         const R z = coord_tab<F32>(x, op);
         const R sd = F32 ? (R)st.sd * op.zs_t : (R)plan64[0].sd;
         const R drift = F32 ? (R)op.ydrift_n_f : (R)op.ydrift_n;
@@ -112,7 +122,8 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
                 L = st.pops == 1 ? Rr : slot[64];
                 Rr = r;
             }
-            const uint32_t x = U.bits(lds_lane[(F32 ? st.lds_off : (st.dim - 1) * 64) + lane], q, s - 64 * q);
+            const uint32_t x =
+                U.rec(U.bits(lds_lane[(F32 ? st.lds_off : (st.dim - 1) * 64) + lane], q, s - 64 * q), st.dim, lane);
             const R z = coord_tab<F32>(x, op);
             R Ym;
             R mf;
@@ -147,14 +158,15 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
 // (row_newbcast) hands step S's value to all lanes inside the very XOR that
 // combines it with the lane word: no v_readlane per date.  With nested
 // scrambling the distributed parts are read as in the plan walker.
-template <bool OWEN, int NSTEP>
+template <class UP, int NSTEP, bool OWEN = UP::OWEN>
 struct FixedU;
 
-template <int NSTEP>
-struct FixedU<false, NSTEP> {
+template <class UP, int NSTEP>
+struct FixedU<UP, NSTEP, false> {
     static constexpr int NR = (NSTEP + 15) / 16;
     uint32_t R[NR];
-    __device__ __forceinline__ FixedU(const UParts<false> &U, int lane)
+    const UP &Up;
+    __device__ __forceinline__ FixedU(const UP &U, int lane) : Up(U)
     {
 #pragma unroll
         for (int i = 0; i < NR; ++i) R[i] = (uint32_t)__shfl((int)U.U[i / 4], 16 * (i % 4) + (lane & 15), 64);
@@ -164,22 +176,24 @@ struct FixedU<false, NSTEP> {
     {
         return lane_word ^ (uint32_t)__builtin_amdgcn_update_dpp(0, (int)R[S / 16], 0x150 + S % 16, 0xF, 0xF, false);
     }
+    __device__ __forceinline__ uint32_t rec(uint32_t y, int dim, int lane) const { return Up.rec(y, dim, lane); }
 };
 
-template <int NSTEP>
-struct FixedU<true, NSTEP> {
-    const UParts<true> &U;
-    __device__ __forceinline__ FixedU(const UParts<true> &u, int) : U(u) {}
+template <class UP, int NSTEP>
+struct FixedU<UP, NSTEP, true> {
+    const UP &U;
+    __device__ __forceinline__ FixedU(const UP &u, int) : U(u) {}
     template <int S>
     __device__ __forceinline__ uint32_t bits(uint32_t lane_word) const
     {
         return U.bits(lane_word, S / 64, S % 64);
     }
+    __device__ __forceinline__ uint32_t rec(uint32_t y, int dim, int lane) const { return U.rec(y, dim, lane); }
 };
 
-template <int MODE, bool OWEN, int N, int LO, int HI>
-__device__ __forceinline__ void fixed_interval(const uint32_t *row0, float zs,
-                                               const FixedU<OWEN, N> &U, float WL, float WR,
+template <int MODE, class UP, int N, int LO, int HI>
+__device__ __forceinline__ void fixed_interval(const uint32_t *row0, int lane, float zs,
+                                               const FixedU<UP, N> &U, float WL, float WR,
                                                PathSums<float> &ps)
 {
     if constexpr (HI - LO >= 2) {
@@ -190,47 +204,47 @@ __device__ __forceinline__ void fixed_interval(const uint32_t *row0, float zs,
         constexpr float wl = (float)((double)(HI - M) / (double)(HI - LO));
         constexpr float wr = (float)((double)(M - LO) / (double)(HI - LO));
         constexpr float sd = (float)qcpw_csqrt((double)(M - LO) * (double)(HI - M) / (double)(HI - LO));
-        const uint32_t x = U.template bits<S>(row0[qcpw_row_word(DIM - 1)]);
+        const uint32_t x = U.rec(U.template bits<S>(row0[qcpw_row_word(DIM - 1)]), DIM, lane);
         const float z = ninv_table_f32(x);
         const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
         consume<float, MODE>(ps, Ym, (float)M);
-        fixed_interval<MODE, OWEN, N, LO, M>(row0, zs, U, WL, Ym, ps);
-        fixed_interval<MODE, OWEN, N, M, HI>(row0, zs, U, Ym, WR, ps);
+        fixed_interval<MODE, UP, N, LO, M>(row0, lane, zs, U, WL, Ym, ps);
+        fixed_interval<MODE, UP, N, M, HI>(row0, lane, zs, U, Ym, WR, ps);
     }
 }
 
-template <int MODE, bool OWEN, int N>
+template <int MODE, class UP, int N>
 __device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_t *lds_lane,
-                                                 int lane, const UParts<OWEN> &Ud, PathSums<float> &ps)
+                                                 int lane, const UP &Ud, PathSums<float> &ps)
 {
     const uint32_t *row0 = lds_lane + lane;
     const float zs = op.zs_t;
     constexpr float sd0 = (float)qcpw_csqrt((double)N);
-    const FixedU<OWEN, N> U(Ud, lane);
-    const float z = ninv_table_f32(U.template bits<0>(row0[qcpw_row_word(0)]));   // terminal point, dimension 1
+    const FixedU<UP, N> U(Ud, lane);
+    const float z = ninv_table_f32(U.rec(U.template bits<0>(row0[qcpw_row_word(0)]), 1, lane));   // terminal, dimension 1
     const float WR = fmaf(sd0 * zs, z, op.ydrift_n_f);
     consume<float, MODE>(ps, WR, (float)N);
-    fixed_interval<MODE, OWEN, N, 0, N>(row0, zs, U, 0.0f, WR, ps);
+    fixed_interval<MODE, UP, N, 0, N>(row0, lane, zs, U, 0.0f, WR, ps);
 }
 
 // true if op.n has a compile-time bridge (then the path is done)
-template <int MODE, bool OWEN>
+template <int MODE, class UP>
 __device__ inline bool bridge_fixed_any(const OptDev &op, const uint32_t *lds_lane, int lane,
-                                        const UParts<OWEN> &U, PathSums<float> &ps)
+                                        const UP &U, PathSums<float> &ps)
 {
     if (!qcpw_has_fixed_bridge(op.n)) return false;
     switch (op.n) {
-    case 15: run_bridge_fixed<MODE, OWEN, 15>(op, lds_lane, lane, U, ps); return true;
-    case 31: run_bridge_fixed<MODE, OWEN, 31>(op, lds_lane, lane, U, ps); return true;
-    case 63: run_bridge_fixed<MODE, OWEN, 63>(op, lds_lane, lane, U, ps); return true;
-    case 127: run_bridge_fixed<MODE, OWEN, 127>(op, lds_lane, lane, U, ps); return true;
+    case 15: run_bridge_fixed<MODE, UP, 15>(op, lds_lane, lane, U, ps); return true;
+    case 31: run_bridge_fixed<MODE, UP, 31>(op, lds_lane, lane, U, ps); return true;
+    case 63: run_bridge_fixed<MODE, UP, 63>(op, lds_lane, lane, U, ps); return true;
+    case 127: run_bridge_fixed<MODE, UP, 127>(op, lds_lane, lane, U, ps); return true;
     default: return false;
     }
 }
 
-template <bool F32, int MODE, bool OWEN>
+template <bool F32, int MODE, class UP>
 __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, int lane,
-                                         const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps)
+                                         const UP &U, PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
     const int n = op.n;
@@ -241,7 +255,7 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
     for (int q = 0; q < QCPW_UQ; ++q) {
         const int s_hi = min(64 * (q + 1), n);
         for (int s = 64 * q; s < s_hi; ++s) {
-            const uint32_t y = U.bits(lds_lane[lane_row<F32>(s) + lane], q, s - 64 * q);
+            const uint32_t y = U.rec(U.bits(lds_lane[lane_row<F32>(s) + lane], q, s - 64 * q), s + 1, lane);
             const R z = coord_tab<F32>(y, op);
             Y = Y + fma(zs, z, drift);
             consume<R, MODE>(ps, Y, (R)(s + 1));
@@ -253,8 +267,8 @@ __device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_l
 // The uniform part of Sobol step s (dimension s + 1) for a step index known
 // only at run time (wave-uniform): the register holding it is picked by a
 // uniform branch.
-template <bool OWEN>
-__device__ __forceinline__ uint32_t ubits_at(const UParts<OWEN> &U, uint32_t lane_word, int s)
+template <class UP>
+__device__ __forceinline__ uint32_t ubits_at(const UP &U, uint32_t lane_word, int s)
 {
     const int k = s & 63;
     switch (s >> 6) {
@@ -273,8 +287,8 @@ __device__ __forceinline__ uint32_t ubits_at(const UParts<OWEN> &U, uint32_t lan
 // I_i = log2(e) sigma sqrt(1 - rho) B_i(t_{m+1}) (dimensions n + 1 + i d + m)
 // add to Y_{i,m} = C_m + I_i, and every (asset, date) pair feeds the
 // average's sums, date 1 included (its idiosyncratic part is random).
-template <bool F32, bool OWEN>
-__device__ inline void run_basket_wave(const OptDev &op, const uint32_t *lds_lane, int lane, const UParts<OWEN> &U,
+template <bool F32, class UP>
+__device__ inline void run_basket_wave(const OptDev &op, const uint32_t *lds_lane, int lane, const UP &U,
                                        PathSums<typename Real<F32>::T> &ps)
 {
     using R = typename Real<F32>::T;
@@ -283,7 +297,7 @@ __device__ inline void run_basket_wave(const OptDev &op, const uint32_t *lds_lan
     const R bc = F32 ? (R)op.b_common_f : (R)op.b_common;
     const R bi = F32 ? (R)op.b_idio_f : (R)op.b_idio;
     auto normal = [&](int s) -> R {
-        const uint32_t y = ubits_at(U, lds_lane[lane_row<F32>(s) + lane], s);
+        const uint32_t y = U.rec(ubits_at(U, lds_lane[lane_row<F32>(s) + lane], s), s + 1, lane);
         if constexpr (F32) return ninv_table_f32(y);
         else return (R)ninv_f64(y);
     };
@@ -306,24 +320,24 @@ __device__ inline void run_basket_wave(const OptDev &op, const uint32_t *lds_lan
 
 // One wave's 64 paths from the terminal point (bridge) or the first step
 // (standard) to the last date, accumulated into ps.
-template <bool F32, int PATHK, bool OWEN, int MODE>
+template <bool F32, int PATHK, int MODE, class UP>
 __device__ inline void walk_path(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
                                  typename Real<F32>::T *stk, int lane,
-                                 const UParts<OWEN> &U, PathSums<typename Real<F32>::T> &ps, int fixed_bridges)
+                                 const UP &U, PathSums<typename Real<F32>::T> &ps, int fixed_bridges)
 {
     if constexpr (PATHK == QCPW_PATH_BB) {
         if constexpr (F32) {
-            if (fixed_bridges && bridge_fixed_any<MODE, OWEN>(op, lds_lane, lane, U, ps)) return;
+            if (fixed_bridges && bridge_fixed_any<MODE>(op, lds_lane, lane, U, ps)) return;
         }
-        run_bridge_wave<F32, MODE, OWEN>(ld, op, lds_lane, stk, lane, U, ps);
+        run_bridge_wave<F32, MODE>(ld, op, lds_lane, stk, lane, U, ps);
     } else {
         if constexpr (MODE == QCPW_STAT_AVG) {
             if (op.n_assets > 0) {
-                run_basket_wave<F32, OWEN>(op, lds_lane, lane, U, ps);
+                run_basket_wave<F32>(op, lds_lane, lane, U, ps);
                 return;
             }
         }
-        run_standard_wave<F32, MODE, OWEN>(op, lds_lane, lane, U, ps);
+        run_standard_wave<F32, MODE>(op, lds_lane, lane, U, ps);
     }
 }
 
@@ -334,9 +348,9 @@ __device__ inline int step_dim(const LaunchDesc &ld, const OptDev &op, int s)
     return (PATHK == QCPW_PATH_BB) ? ld.plan[op.plan_off + s].dim : s + 1;
 }
 
-template <int PATHK, bool OWEN>
+template <int PATHK, class UP>
 __device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op, int shift, int lane,
-                                         uint64_t base, UParts<OWEN> &U)
+                                         uint64_t base, UP &U)
 {
     const uint64_t g = (base ^ (base >> 1)) >> 5;   // gray(base) has no bits below 5
 #pragma unroll
@@ -352,7 +366,7 @@ __device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op,
             for (int b = 5; gg != 0; ++b, gg >>= 1)
                 if (gg & 1) u ^= v[b];
         }
-        if constexpr (OWEN) {
+        if constexpr (UP::OWEN) {
             U.U[q] = u;
             U.Sd[q] = key;
         } else {
@@ -362,9 +376,9 @@ __device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op,
 }
 
 // base -> base + 64: gray changes in bits 5 and 6 + ctz(base/64 + 1).
-template <int PATHK, bool OWEN>
+template <int PATHK, class UP>
 __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op, int lane, uint64_t base,
-                                         UParts<OWEN> &U)
+                                         UP &U)
 {
     const int c = __builtin_ctzll((base >> 6) + 1);
 #pragma unroll
@@ -386,7 +400,10 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
 // on scalar plan loads and two dependent LDS reads), so it is held to 80
 // VGPRs: six waves per SIMD instead of four (measured 1.3x faster); with
 // 512-thread workgroups the LDS of three workgroups fits a CU at d = 64.
-template <bool F32, int PATHK, bool OWEN>
+// PROBE instances (coordinate checks only) walk every option as an average
+// and also store the coordinates each 64-point batch consumes at
+// probe[((unit * unit_pts / 64 + batch) * ndims + dim - 1) * 64 + lane].
+template <bool F32, int PATHK, bool OWEN, bool PROBE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 1))) void paths_kernel(const OptDev *__restrict__ opts,
                                                      const int64_t *__restrict__ unit_prefix,
                                                      const PlanStep *__restrict__ plan_all,
@@ -397,7 +414,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
                                                      double *__restrict__ partials,
                                                      unsigned long long *__restrict__ counter,
                                                      int n_opts, int max_n, int stack_depth, int stk_off,
-                                                     long long total_units, int fixed_bridges)
+                                                     long long total_units, int fixed_bridges,
+                                                     uint32_t *__restrict__ probe)
 {
     LaunchDesc ld;
     ld.opts = opts;
@@ -473,26 +491,28 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
         const int64_t start = op.k_begin + chunk * op.unit_pts;
         const int64_t end = min(start + (int64_t)op.unit_pts, k_end);
         const int mode = qcpw_stat_of(op.type);
-        UParts<OWEN> U;
-        init_uniform_part<PATHK, OWEN>(ld, op, shift, lane, (uint64_t)start, U);
+        UParts<OWEN, PROBE> U;
+        init_uniform_part<PATHK>(ld, op, shift, lane, (uint64_t)start, U);
         for (int64_t base = start; base < end; base += 64) {
             const bool valid = base + lane < k_end;
             double F[4] = {0.0, 0.0, 0.0, 0.0};
             PathSums<R> ps;
             init_sums(ps);
+            if constexpr (PROBE)
+                U.pr = probe + ((unit * (op.unit_pts / 64) + (base - start) / 64) * op.ndims) * 64;
             if (op.ndims > 0) {
-                switch (mode) {
+                switch (PROBE ? QCPW_STAT_AVG : mode) {
                 case QCPW_STAT_MAX:
-                    walk_path<F32, PATHK, OWEN, QCPW_STAT_MAX>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, QCPW_STAT_MAX>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
                 case QCPW_STAT_GEO:
-                    walk_path<F32, PATHK, OWEN, QCPW_STAT_GEO>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, QCPW_STAT_GEO>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
                 case QCPW_STAT_MIN:
-                    walk_path<F32, PATHK, OWEN, QCPW_STAT_MIN>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, QCPW_STAT_MIN>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
                 default:
-                    walk_path<F32, PATHK, OWEN, QCPW_STAT_AVG>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, QCPW_STAT_AVG>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                 }
             }
             if (valid) {
@@ -500,7 +520,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc_add(s[i], c[i], F[i]);
             }
-            if (base + 64 < end) step_uniform_part<PATHK, OWEN>(ld, op, lane, (uint64_t)base, U);
+            if (base + 64 < end) step_uniform_part<PATHK>(ld, op, lane, (uint64_t)base, U);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -517,9 +537,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 
 // One block per option: replication estimates C_l (chunk partials added in
 // chunk order), then the mean over replications and its standard error.
 // per_shift: [n_opts(caller order)][L][4].
+// out_sigma (optional): the spread of the single replications about the mean.
 __global__ __launch_bounds__(256) void finalize_kernel(const OptDev *opts, const double *partials,
                                                        double *per_shift, double *out_mean,
-                                                       double *out_stderr)
+                                                       double *out_stderr, double *out_sigma)
 {
     __shared__ double red_s[256], red_c[256];
     const OptDev &op = opts[blockIdx.x];
@@ -574,6 +595,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const OptDev *opts, const
             out_mean[op.out_index * 4 + i] = mean;
             out_stderr[op.out_index * 4 + i] =
                 L >= 2 ? sqrt(red_s[0] / ((double)L * (double)(L - 1))) : NAN;
+            if (out_sigma) out_sigma[op.out_index * 4 + i] = L >= 2 ? sqrt(red_s[0] / (double)L) : NAN;
         }
         __syncthreads();
     }
@@ -898,24 +920,26 @@ qcpw_status check_lds_at_zero(const void *fn)
     return QCPW_OK;
 }
 
-template <bool F32, int PATHK, bool OWEN>
+template <bool F32, int PATHK, bool OWEN, bool PROBE>
 static const void *paths_fn()
 {
-    return reinterpret_cast<const void *>(&paths_kernel<F32, PATHK, OWEN>);
+    return reinterpret_cast<const void *>(&paths_kernel<F32, PATHK, OWEN, PROBE>);
 }
 
-template <bool OWEN>
+template <bool OWEN, bool PROBE>
 static const void *select_paths_kernel_r(const LaunchPlan &lp)
 {
     const bool f32 = lp.precision == QCPW_FP32_MIXED;
     if (lp.path == QCPW_PATH_STANDARD)
-        return f32 ? paths_fn<true, QCPW_PATH_STANDARD, OWEN>() : paths_fn<false, QCPW_PATH_STANDARD, OWEN>();
-    return f32 ? paths_fn<true, QCPW_PATH_BB, OWEN>() : paths_fn<false, QCPW_PATH_BB, OWEN>();
+        return f32 ? paths_fn<true, QCPW_PATH_STANDARD, OWEN, PROBE>()
+                   : paths_fn<false, QCPW_PATH_STANDARD, OWEN, PROBE>();
+    return f32 ? paths_fn<true, QCPW_PATH_BB, OWEN, PROBE>() : paths_fn<false, QCPW_PATH_BB, OWEN, PROBE>();
 }
 
 static const void *select_paths_kernel(const LaunchPlan &lp)
 {
-    return lp.owen ? select_paths_kernel_r<true>(lp) : select_paths_kernel_r<false>(lp);
+    if (lp.probe) return lp.owen ? select_paths_kernel_r<true, true>(lp) : select_paths_kernel_r<false, true>(lp);
+    return lp.owen ? select_paths_kernel_r<true, false>(lp) : select_paths_kernel_r<false, false>(lp);
 }
 
 // Resident waves per CU of the fused kernel at workgroup size bd (0 if it
@@ -1023,7 +1047,7 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
 
 qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream, double *dev_out_greeks,
                            double *dev_out_stderr, double *dev_out_per_shift, void *ws, size_t ws_bytes,
-                           const void *h_upload, bool timed)
+                           const void *h_upload, bool timed, double *dev_out_sigma)
 {
     // qcpw_kernel_timer: a pair of events around the main kernel
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -1102,13 +1126,15 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         int a_nopts = ld.n_opts, a_maxn = ld.max_n, a_depth = lp.stack_depth;
         long long a_total = ld.total_units;
         int a_fixed_arg = fixed_bridges_on() ? 1 : 0;
+        uint32_t *a_probe = lp.probe;
         void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_dir, &a_lane, &a_tab, &a_part, &a_ctr,
-                        &a_nopts, &a_maxn, &a_depth, &a_stk_off, &a_total, &a_fixed_arg};
+                        &a_nopts, &a_maxn, &a_depth, &a_stk_off, &a_total, &a_fixed_arg, &a_probe};
         if (t0) QCPW_HIP(hipEventRecord(t0, stream));
         QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
         if (t1) QCPW_HIP(hipEventRecord(t1, stream));
     }
-    finalize_kernel<<<(unsigned)n, 256, 0, stream>>>(d_opts, d_partials, d_per_shift, dev_out_greeks, dev_out_stderr);
+    finalize_kernel<<<(unsigned)n, 256, 0, stream>>>(d_opts, d_partials, d_per_shift, dev_out_greeks, dev_out_stderr,
+                                                     dev_out_sigma);
     QCPW_HIP(hipGetLastError());
     return QCPW_OK;
 }

@@ -101,6 +101,7 @@ struct LaunchPlan {
     int64_t total_units = 0;
     int64_t full_blocks = 0;           // PCA_FULL in FP64: workgroups with a global scratch tile
     bool owen = false;                 // nested scrambling instead of the digital shift
+    uint32_t *probe = nullptr;         // device buffer: run the coordinate-recording kernel instance
     std::vector<const Context::Pca *> pca;   // per sorted option (PCA and PCA_FULL)
 };
 
@@ -126,14 +127,16 @@ void fill_launch_upload(const LaunchPlan &lp, void *dst);
 
 // Enqueues the whole hot path on `stream`: uploads, the per-path kernel, the
 // finalize kernel; results go to dev_out_greeks / dev_out_stderr ([n][4],
-// caller order) and optionally dev_out_per_shift ([n][L][4]).
+// caller order) and optionally dev_out_per_shift ([n][L][4]) and
+// dev_out_sigma ([n][4], the spread of the replications).
 // h_upload: the launch_upload_bytes(lp) bytes to upload (default: written
 // from lp into a host buffer here; graph capture passes a pinned copy that
 // outlives the call).
 qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t stream,
                            double *dev_out_greeks, double *dev_out_stderr,
                            double *dev_out_per_shift, void *ws, size_t ws_bytes,
-                           const void *h_upload = nullptr, bool timed = false);
+                           const void *h_upload = nullptr, bool timed = false,
+                           double *dev_out_sigma = nullptr);
 
 qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index, int32_t n_dims,
                                 int64_t k0, int64_t count, uint32_t *dev_out, hipStream_t stream,

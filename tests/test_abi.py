@@ -33,7 +33,8 @@ def test_struct_layout():
     assert C.sizeof(q.OptionSpec) == 80
     assert q.OptionSpec.seed.offset == 48 and q.OptionSpec.n_points.offset == 56
     assert q.OptionSpec.n_assets.offset == 64 and q.OptionSpec.rho.offset == 72
-    assert C.sizeof(q.RunConfig) == 40
+    assert C.sizeof(q.RunConfig) == 48
+    assert q.RunConfig.out_paper_sigma.offset == 40
 
 
 def test_version_string():

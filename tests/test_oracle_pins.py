@@ -266,6 +266,32 @@ def test_bridge_terminal_and_first_midpoint():
     assert W[31] == pytest.approx(math.sqrt(dt * 31 * 32 / 63), rel=1e-14)
 
 
+@pytest.mark.parametrize("n", [7, 10])
+def test_bridge_dimension_to_date_order(n, golden_dir):
+    """Which normal drives which point (hand-derived table): the path of the
+    unit vector e_j must be the hat function on (l, r) peaking at m with the
+    conditional standard deviation sqrt(dt (m - l)(r - m)/(r - l)) -- or, for
+    the terminal, the straight line to sqrt(n dt).  A swapped push order, a
+    ceiling midpoint or a depth-first numbering all fail it."""
+    dt = 0.1
+    rows = [tuple(int(v) for v in r) for r in _read_rows(os.path.join(golden_dir, "bridge_order_n7_n10.txt"))]
+    rows = [r for r in rows if r[0] == n]
+    assert sorted(r[1] for r in rows) == list(range(1, n + 1))
+    k = np.arange(n + 1, dtype=np.float64)
+    for _, j, l, m, r in rows:
+        z = np.zeros(n)
+        z[j - 1] = 1.0
+        W = oracle.build_path(oracle.PATH_BB, n, dt, z)
+        if j == 1:
+            want = k / n * math.sqrt(n * dt)
+        else:
+            peak = math.sqrt(dt * (m - l) * (r - m) / (r - l))
+            want = np.where((k >= l) & (k <= m), (k - l) / (m - l), 0.0) + \
+                np.where((k > m) & (k <= r), (r - k) / (r - m), 0.0)
+            want = want * peak
+        assert np.allclose(W, want, rtol=0, atol=1e-15), (n, j)
+
+
 @pytest.mark.parametrize("n", [5, 63, 255, 364])
 def test_pca_factor_matches_library_eigensolver(n):
     """The oracle's closed-form principal components must be the eigenpairs a
