@@ -24,6 +24,17 @@ def say(*a):
     sys.stdout.flush()
 
 
+def scaled_err(got, ref, scale):
+    """|got - ref| / max(|ref|, scale), the summand-scale reading of "1e-10
+    relative".  A zero scale means every summand was zero (a Gaussian density
+    that underflows far from the money): then the two must be equal, so 0/0
+    counts as 0 and any difference as infinite."""
+    diff = np.abs(got - ref)
+    den = np.maximum(np.abs(ref), scale)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(diff == 0, 0.0, diff / den)
+
+
 def oracle_range(o, l, path, N, parts=16):
     """Replication l of option o over points 0..N-1, from `parts` equal point
     ranges run side by side on the host cores (each a plain oracle call)."""
@@ -44,6 +55,21 @@ def scale_of(o, path, N=512):
 # relative rounding of the path statistic by 1/s1 ~ 380.
 # ------------------------------------------------------------------------
 CORNER = dict(S0=100.0, r=0.05, sigma=0.1, T=0.25, d=365)
+# Relative FP32 rounding of the path statistic X (a few ulps of the sum of d
+# exponentials), which the breakpoint turns into delta psi = EPS_PATH / s1.
+EPS_PATH = 2e-7
+
+
+def fp32_bound(o, k):
+    """FP32-mixed bound for Greek k of call o, relative to the summand scale.
+    A summand moves by |d ln F / d psi| delta psi ~ |psi| EPS_PATH / s1 when
+    the FP32 path shifts the breakpoint: at the money that stays inside
+    FP32_TOL, far out of the money (psi >> 1 at the forward, prices below
+    1e-60 here) the relative error grows with psi while the absolute error
+    is negligible."""
+    s1 = o["sigma"] * np.sqrt(o["T"] / o["d"])
+    psi_f = max(0.0, (np.log(o["K"] / o["S0"]) - o["r"] * o["T"]) / s1)
+    return FP32_TOL[k] + EPS_PATH * psi_f / s1
 
 
 @pytest.mark.parametrize("K", [70.0, 80.0, 97.0, 100.0, 103.0, 120.0, 130.0])
@@ -56,10 +82,11 @@ def test_fp32_corner_short_low_vol_many_dates(K):
                          o["n_points"], 2, oracle.PATH_BB) for o in opts]
     Cl = np.array([r["C_l"] for r in ref])
     am = np.array([r["abs_mean"] for r in ref])
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("corner K=%g scaled error per type:" % K, err.max(axis=1))
-    for k in range(4):
-        assert err[..., k].max() <= FP32_TOL[k], (K, k, err[..., k].max())
+    for i, o in enumerate(opts):
+        for k in range(4):
+            assert err[i, :, k].max() <= fp32_bound(o, k), (K, i, k, err[i, :, k].max(), fp32_bound(o, k))
 
 
 def test_fp32_lookback_near_ties():
@@ -75,10 +102,11 @@ def test_fp32_lookback_near_ties():
                          o["n_points"], 2, oracle.PATH_BB) for o in opts]
     Cl = np.array([r["C_l"] for r in ref])
     am = np.array([r["abs_mean"] for r in ref])
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("near-tie scaled error:", err.max(axis=(0, 1)))
-    for k in range(4):
-        assert err[..., k].max() <= FP32_TOL[k], (k, err[..., k].max())
+    for i, o in enumerate(opts):
+        for k in range(4):
+            assert err[i, :, k].max() <= fp32_bound(o, k), (i, k, err[i, :, k].max(), fp32_bound(o, k))
 
 
 # ------------------------------------------------------------------------
@@ -96,7 +124,7 @@ def test_pca_d256_replication_against_oracle(gemm, tol):
     for i, o in enumerate(opts):
         ref = oracle_range(o, l, oracle.PATH_PCA, N)
         sc = scale_of(o, oracle.PATH_PCA)
-        err = np.abs(ps[i, l] - ref) / np.maximum(np.abs(ref), sc)
+        err = scaled_err(ps[i, l], ref, sc)
         say("pca d256 option %d scaled error" % i, err)
         assert (err <= tol).all(), err
     se = ps.std(axis=1, ddof=1) / np.sqrt(L)
@@ -118,8 +146,7 @@ def test_served_request_matches_oracle(prec, tol):
     for i, o in enumerate(opts):
         ref = oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["seed"], pts, L,
                             oracle.PATH_BB)
-        sc = np.maximum(np.abs(ref["mean"]), ref["abs_mean"])
-        err = np.abs(g[i] - ref["mean"]) / sc
+        err = scaled_err(g[i], ref["mean"], ref["abs_mean"])
         say("served option %d scaled error" % i, err)
         assert (err <= (TOL64 if tol is None else tol)).all(), err
         if prec == q.FP64:
