@@ -3,15 +3,20 @@
 One step = one call of the whole hot path (Sobol points + shifts, inverse
 normal, Brownian-bridge path, exponentials and sums, breakpoint, Phi tails,
 price/delta/vega/gamma, reduction over points and replications) over the
-workload "three products at d = 64": arithmetic Asian, binary Asian and
-lookback calls x K {90, 100, 110} x sigma {0.1, 0.3}, S0 = 100, r = 0.05,
-T = 1, 2^20 Sobol points x 32 random shifts each (18 options, 6.04e8
-Greek-paths, 3.8e10 path-dates), FP32-mixed arithmetic.  Inputs are
-synthetic option parameters (no dataset) and stay on the device.
+uneven portfolio: 4096 options in one persistent launch, type uniform over
+{arithmetic Asian, binary Asian, lookback} calls, d uniform in [4, 365],
+K ~ U[80,120], sigma ~ U[0.1,0.5], T ~ U[0.25,2], r ~ U[0,0.08], S0 = 100,
+2^k Sobol points with k uniform in [14, 20], 16 random shifts, Brownian
+bridge, FP32 path arithmetic with FP64 breakpoint, tails and sums (1.95e10
+Greek-paths, 3.6e12 path-dates).  Inputs are synthetic option parameters
+(no dataset) and stay on the device; outputs are written on the device.
 
 Prints one JSON line.  Extra legs (each its own timed loop, outside the
-headline value): the same workload in plain FP64, and the oracle on the
-host cores (cpu_baseline, a bounded sample).
+headline value): the three-product grid at d = 64 (FP32-mixed and plain
+FP64), the principal-component pair at d = 256 on the matrix cores, nested
+scrambling, more products, the latency-bound single call, the serving
+stream, and the oracle on the host cores (cpu_baseline, a bounded sample of
+the headline workload).
 """
 from __future__ import annotations
 
@@ -32,19 +37,24 @@ sys.path.insert(0, ROOT)
 # exponential (1) and the running sums (5) make about 35 FP32 flops (36 with
 # the uint->float conversion); per path the breakpoint (log), two Phi tails,
 # the density, the four Greeks and the compensated sums make about 200 FP64
-# flops.
+# flops.  Plain FP64 mode: about 75 FP64 flops per path-date (software exp
+# and log in place of the FP32 table lookups).
 F32_PER_PATH_DATE = 36.0
+F64_PER_PATH_DATE_PLAIN = 75.0
 F64_PER_PATH = 200.0
 PEAK_F32 = 157.3e12       # MI355X vector FP32 (packed), 256 CU x 2.4 GHz x 256 flop/clk
 PEAK_F64 = 78.6e12        # MI355X vector FP64
+PEAK_MFMA_F32 = 157.3e12  # MI355X dense FP32 matrix
+PEAK_MFMA_BF16 = 2.5e15   # MI355X dense BF16 matrix
 
-# HBM bytes per launch of the fused kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (profiles/
-# paths_kernel_fp32_bridge_three_products_d64.md), valid only for the kernel
-# sources they were taken on (sha256 prefix of their concatenation).
+# HBM bytes per launch of the fused kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by a plain 1 GiB copy (profiles/), valid only for the
+# kernel sources they were taken on (sha256 prefix of their concatenation).
 TRAFFIC_SOURCES = ("kernels.hip", "device_math.h", "qcpw_internal.h", "ninv_table.inc")
-TRAFFIC_SHA = "058e69e34590da59"
-TRAFFIC_BYTES = {"fetch": 0.925e6, "write": 15.729e6}
+TRAFFIC = {
+    "portfolio": {"sha": None, "fetch": None, "write": None},
+    "three_products": {"sha": "058e69e34590da59", "fetch": 0.925e6, "write": 15.729e6},
+}
 
 
 def kernel_sources_sha() -> str:
@@ -54,6 +64,35 @@ def kernel_sources_sha() -> str:
         with open(os.path.join(ROOT, "paper_2209_11337_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def traffic_of(workload: str):
+    t = TRAFFIC[workload]
+    if t["sha"] is None or t["sha"] != kernel_sources_sha():
+        return None
+    return t["fetch"] + t["write"]
+
+
+def roofline(paths, path_dates, kernel_ms, fp32=True, mfma_flops=0.0, mfma_peak=PEAK_MFMA_F32,
+             kernel="qcpw::paths_kernel", traffic=None, call_ms=None):
+    """Whole-kernel roofline of the op-count model: t_ideal = F32 / 157.3e12 +
+    F64 / 78.6e12 (+ matrix flops / their peak); frac = t_ideal / t_kernel;
+    achieved in FP32-equivalent TFLOP/s (each term weighted by 157.3e12 over
+    its own peak)."""
+    f32 = F32_PER_PATH_DATE * path_dates if fp32 else 0.0
+    f64 = F64_PER_PATH * paths + (0.0 if fp32 else F64_PER_PATH_DATE_PLAIN * path_dates)
+    t_ideal = f32 / PEAK_F32 + f64 / PEAK_F64 + mfma_flops / mfma_peak
+    t_kernel = kernel_ms * 1e-3
+    out = {"bound": "alu", "achieved": t_ideal * PEAK_F32 / t_kernel / 1e12, "peak": PEAK_F32 / 1e12,
+           "unit": "TFLOP/s", "frac": t_ideal / t_kernel, "traffic": traffic,
+           "model": "FP32-equivalent flops: %s + %.0f FP64/path%s" % (
+               "%.0f FP32/path-date" % F32_PER_PATH_DATE if fp32 else
+               "%.0f FP64/path-date" % F64_PER_PATH_DATE_PLAIN, F64_PER_PATH,
+               " + %.3g matrix flops at %.4g TFLOP/s" % (mfma_flops, mfma_peak / 1e12) if mfma_flops else ""),
+           "ideal_ms": t_ideal * 1e3, "kernel": kernel, "kernel_ms": kernel_ms}
+    if call_ms is not None:
+        out["call_ms"] = call_ms
+    return out
 
 
 # The paper's own timings (Sec. 6.1; Tesla T4, CUDA 11.2, FP32 path arithmetic, CPU model not
@@ -79,22 +118,77 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def host_threads() -> int:
+    """Threads for the oracle: the host share given to this process
+    (OMP_NUM_THREADS when set), at most 16."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    if n <= 0:
+        n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(n, 16))
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", choices=["portfolio", "three_products"], default="portfolio",
+                   help="headline workload: the 4096-option uneven portfolio (default) or the "
+                        "18-option three-product grid at d = 64")
     p.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    p.add_argument("--no-extras", action="store_true", help="skip the FP64 and CPU legs")
-    p.add_argument("--cpu-points", type=int, default=1 << 19)
-    p.add_argument("--no-portfolio", action="store_true", help="skip the uneven-portfolio leg")
-    p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    p.add_argument("--no-extras", action="store_true", help="headline only: no extra legs, no CPU baseline")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving legs")
     p.add_argument("--pca-only", action="store_true",
                    help="run only the principal-component leg (one timed call per GEMM) and print it")
+    p.add_argument("--serve-sweep", action="store_true",
+                   help="run only the serving sweep (saturation rate, then arrival rates 0.25, 0.5, 0.8 "
+                        "times it, FP32-mixed and plain FP64 servers) and print it")
+    p.add_argument("--serve-requests", type=int, default=300, help="requests per arrival rate in --serve-sweep")
+    p.add_argument("--serve-rates", type=str, default="0.25,0.5,0.8",
+                   help="arrival rates of --serve-sweep as fractions of the saturation rate")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed loop, run one plain device copy of this many MiB "
                         "(reference kernel for HBM byte counters)")
     return p.parse_args()
+
+
+def headline_workload(workloads, name):
+    if name == "portfolio":
+        opts = workloads.portfolio(4096)
+        return opts, 16, ("uneven portfolio: 4096 options in one persistent launch, type uniform over "
+                          "{arith Asian, binary Asian, lookback} calls, d ~ U{4..365}, K ~ U[80,120], "
+                          "sigma ~ U[0.1,0.5], T ~ U[0.25,2], r ~ U[0,0.08], 2^k points k ~ U{14..20}, "
+                          "16 shifts, Brownian bridge")
+    opts = workloads.three_products_grid(d=64, n_points=1 << 20)
+    return opts, 32, ("three products (arith Asian, binary Asian, lookback) x K{90,100,110} x "
+                      "sigma{0.1,0.3}, d=64, Brownian bridge, 2^20 Sobol points x 32 shifts")
+
+
+def timed_calls(q, torch, opts, L, path, prec, steps, warmup, out, stream, **kw):
+    """W untimed calls, then K calls bracketed by synchronisation on both
+    sides: (wall seconds of the K calls, mean per-call ms from torch events
+    on the launch stream, mean fused-kernel ms from the library's HIP events
+    on the same stream)."""
+    for _ in range(warmup):
+        q.greeks(opts, L, path, prec, device_outputs=True, out=out, stream=stream, **kw)
+    torch.cuda.synchronize()
+    stream.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    q.kernel_timer(q.TIMER_START)
+    t0 = time.perf_counter()
+    for s, e in evs:
+        s.record(stream)
+        q.greeks(opts, L, path, prec, device_outputs=True, out=out, stream=stream, **kw)
+        e.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
+    ev_ms = float(np.mean([s.elapsed_time(e) for s, e in evs]))
+    return wall, ev_ms, k_ms / max(k_n, 1)
 
 
 def main():
@@ -114,41 +208,20 @@ def main():
     if a.pca_only:
         print(json.dumps({"pca": pca_leg(q, workloads, torch, steps=1)}), flush=True)
         return
-    L = 32
-    opts = workloads.three_products_grid(d=64, n_points=1 << 20)
+    if a.serve_sweep:
+        print(json.dumps({"serving_sweep": serve_sweep(q, workloads, a.serve_requests,
+                                                       [float(x) for x in a.serve_rates.split(",")])}),
+              flush=True)
+        return
+    opts, L, desc = headline_workload(workloads, a.workload)
     n_paths = workloads.total_paths(opts, L)
     n_pd = workloads.total_path_dates(opts, L)
     prec = q.FP32_MIXED if a.precision == "fp32" else q.FP64
     out = (torch.empty((len(opts), 4), dtype=torch.float64, device=dev),
            torch.empty((len(opts), 4), dtype=torch.float64, device=dev))
     stream = torch.cuda.Stream()
-
-    def step(p):
-        q.greeks(opts, L, q.PATH_BB, p, device_outputs=True, out=out, stream=stream)
-
-    def timed(p, steps, warmup):
-        for _ in range(warmup):
-            step(p)
-        torch.cuda.synchronize()
-        stream.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        q.kernel_timer(q.TIMER_START)
-        t0 = time.perf_counter()
-        for s, e in evs:
-            s.record(stream)
-            step(p)
-            e.record(stream)
-        stream.synchronize()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
-        ev_ms = float(np.mean([s.elapsed_time(e) for s, e in evs]))
-        return wall, ev_ms, k_ms / max(k_n, 1)
-
-    # HIP events recorded by the library on the launch stream around the
-    # fused per-path kernel alone (kernel_ms), and torch events around each
-    # whole call on the same stream (call_ms)
-    wall, ev_ms, kern_ms = timed(prec, a.steps, a.warmup)
+    print("headline: %s, %d steps after %d warmup" % (a.workload, a.steps, a.warmup), file=sys.stderr, flush=True)
+    wall, ev_ms, kern_ms = timed_calls(q, torch, opts, L, q.PATH_BB, prec, a.steps, a.warmup, out, stream)
     if a.copy_mib > 0:
         src = torch.ones(a.copy_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -158,88 +231,39 @@ def main():
     print("timed %d steps: %.3f s wall, %.3f ms/call, %.3f ms/kernel (events)" % (a.steps, wall, ev_ms, kern_ms),
           file=sys.stderr, flush=True)
     value = n_paths * a.steps / wall
-    g = out[0].cpu().numpy()
-    e = out[1].cpu().numpy()
-
-    f32 = F32_PER_PATH_DATE * n_pd if prec == q.FP32_MIXED else 0.0
-    f64 = F64_PER_PATH * n_paths + (0.0 if prec == q.FP32_MIXED else F32_PER_PATH_DATE * n_pd)
-    t_ideal = f32 / PEAK_F32 + f64 / PEAK_F64
-    t_kernel = kern_ms * 1e-3
-    achieved = (f32 + f64 * PEAK_F32 / PEAK_F64) / t_kernel
-    same_kernel = prec == q.FP32_MIXED and kernel_sources_sha() == TRAFFIC_SHA
-    traffic = TRAFFIC_BYTES["fetch"] + TRAFFIC_BYTES["write"] if same_kernel else None
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_F32 / 1e12, "unit": "TFLOP/s",
-                "frac": t_ideal / t_kernel, "traffic": traffic,
-                "model": "FP32-equivalent flops: %.0f FP32/path-date + %.0f FP64/path (FP64 weighted x2)"
-                         % (F32_PER_PATH_DATE, F64_PER_PATH),
-                "kernel": "qcpw::paths_kernel", "kernel_ms": kern_ms, "call_ms": ev_ms}
+    fp32 = prec == q.FP32_MIXED
+    rl = roofline(n_paths, n_pd, kern_ms, fp32=fp32, traffic=traffic_of(a.workload) if fp32 else None,
+                  call_ms=ev_ms)
 
     res = {"metric": "Greek-paths/sec (delta+vega+gamma) at fixed RMSE vs FP64; p99 request latency",
            "value": value, "unit": "Greek-paths/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "ms_per_step": wall / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32+f64" if prec == q.FP32_MIXED else "f64",
+           "vs_baseline": None, "dtype": "f32+f64" if fp32 else "f64",
            "data": "synthetic (Black-Scholes option parameters, seeded)",
-           "config": {"workload": "three products (arith Asian, binary Asian, lookback) x K{90,100,110} x "
-                                  "sigma{0.1,0.3}, d=64, Brownian bridge, 2^20 Sobol points x 32 shifts",
-                      "options": len(opts), "greek_paths_per_step": n_paths, "path_dates_per_step": n_pd,
-                      "precision": a.precision},
-           "roofline": roofline}
-
-    if not a.no_extras:
-        # plain FP64 on the same workload, same launch path
-        w64, ev64, _ = timed(q.FP64, 2, 1)
-        g64 = out[0].cpu().numpy()
-        res["fp64"] = {"value": n_paths * 2 / w64, "ms_per_step": w64 / 2 * 1e3, "kernel_ms": ev64}
-        if prec == q.FP32_MIXED:
-            rel = np.abs(g - g64) / np.maximum(np.abs(g64), 1e-300)
-            res["fp32_vs_fp64_max_rel_diff"] = {k: float(rel[:, i].max()) for i, k in enumerate(q.OUTPUTS)}
-            res["stderr_max_rel"] = {k: float((e[:, i] / np.maximum(np.abs(g64[:, i]), 1e-300)).max())
-                                     for i, k in enumerate(q.OUTPUTS)}
-        # the oracle on the host cores, a bounded sample of the same workload
-        import oracle
-        n_cpu = a.cpu_points
-        Ls = 8
-        sample = workloads.three_products_grid(d=64, n_points=n_cpu)
-        threads = os.cpu_count() or 1
-        t0 = time.perf_counter()
-        _, _, _, used = oracle.options(sample, Ls, oracle.PATH_BB, n_threads=threads)
-        tc = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": workloads.total_paths(sample, Ls) / tc, "unit": "Greek-paths/s",
-                               "cores": used, "kind": "oracle",
-                               "sample": "the 18 options at d=64, 2^%d points x %d shifts (%.1f s)"
-                                         % (int(np.log2(n_cpu)), Ls, tc),
-                               "cpu_model": cpu_model()}
-        # one host thread, a smaller sample of the same workload
-        sample1 = workloads.three_products_grid(d=64, n_points=1 << 14)
-        t0 = time.perf_counter()
-        oracle.options(sample1, 2, oracle.PATH_BB, n_threads=1)
-        t1c = time.perf_counter() - t0
-        res["cpu_baseline"]["single_thread"] = {"value": workloads.total_paths(sample1, 2) / t1c,
-                                                "sample": "the 18 options at d=64, 2^14 points x 2 shifts (%.1f s)"
-                                                          % t1c}
-        res["paper_context"] = PAPER_CONTEXT
-    if not a.no_extras:
-        # the same workload randomised by nested scrambling instead of the shift
-        q.greeks(opts, L, q.PATH_BB, prec, device_outputs=True, out=out, stream=stream, owen=True)
-        stream.synchronize()
-        q.kernel_timer(q.TIMER_START)
-        t0 = time.perf_counter()
-        for _ in range(3):
-            q.greeks(opts, L, q.PATH_BB, prec, device_outputs=True, out=out, stream=stream, owen=True)
-        stream.synchronize()
-        w_owen = (time.perf_counter() - t0) / 3
-        k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
-        e_owen = out[1].cpu().numpy()
-        res["owen"] = {"value": n_paths / w_owen, "unit": "Greek-paths/s", "kernel_ms": k_ms / max(k_n, 1),
-                       "stderr_ratio_owen_over_shift": {k: float(np.median(e_owen[:, i] / e[:, i]))
-                                                        for i, k in enumerate(q.OUTPUTS)}}
-        res["geometric"] = geometric_leg(q, workloads, torch, prec)
-        res["more_products"] = more_products_leg(q, workloads, torch, prec)
-        res["small_call"] = small_call_leg(q, workloads, torch)
-        res["pca"] = pca_leg(q, workloads, torch)
-    if not a.no_extras and not a.no_portfolio:
-        res["portfolio"] = portfolio_leg(q, workloads, torch)
-    if not a.no_extras and not a.no_serve:
+           "config": {"workload": desc, "options": len(opts), "shifts": L, "greek_paths_per_step": n_paths,
+                      "path_dates_per_step": n_pd, "precision": a.precision},
+           "roofline": rl}
+    if a.no_extras:
+        print(json.dumps(res), flush=True)
+        return
+    # the oracle on the host cores: a bounded sample of the headline workload
+    res["cpu_baseline"] = cpu_baseline(workloads, opts, L, a.workload, n_pd)
+    res["paper_context"] = PAPER_CONTEXT
+    if a.workload == "portfolio":
+        # plain FP64 on the same portfolio (one persistent launch)
+        w64, ev64, k64 = timed_calls(q, torch, opts, L, q.PATH_BB, q.FP64, 1, 1, out, stream)
+        res["fp64"] = {"value": n_paths / w64, "ms_per_step": w64 * 1e3, "kernel_ms": k64,
+                       "roofline": roofline(n_paths, n_pd, k64, fp32=False)}
+        res["three_products"] = three_products_leg(q, workloads, torch)
+    else:
+        res["three_products"] = None
+    res["owen"] = owen_leg(q, workloads, torch)
+    res["geometric"] = geometric_leg(q, workloads, torch, q.FP32_MIXED)
+    res["more_products"] = more_products_leg(q, workloads, torch, q.FP32_MIXED)
+    res["small_call"] = small_call_leg(q, workloads, torch)
+    res["pca"] = pca_leg(q, workloads, torch)
+    res["portfolio_fp64_one_option_per_launch"] = per_option_fp64_leg(q, workloads, opts, L)
+    if not a.no_serve:
         # the configured stream (1..512 options, d in [4, 365], targets 1e-4 / 1e-6, which the
         # point cap of 2^22 per option decides): a short stream at a rate the GPU sustains
         res["serving"] = serving_leg(q, workloads, n_requests=12, rate=0.3, max_opts=512, d_range=(4, 365),
@@ -247,6 +271,101 @@ def main():
         # a dense stream of small requests (1..32 options, d in [4, 64], targets 1e-3 / 1e-4)
         res["serving_small_requests"] = serving_leg(q, workloads)
     print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(workloads, opts, L, workload, n_pd_full):
+    """The oracle (plain FP64 C, OpenMP over option x shift) on the host
+    cores, on a bounded sample of the headline workload: every 64th option
+    of the portfolio at its first 2^14 points and all shifts (or, for the
+    three-product grid, all 18 options at 2^19 points x 8 shifts), plus one
+    host thread on a smaller sample.  A reported baseline, not a target."""
+    import oracle
+    threads = host_threads()
+    if workload == "portfolio":
+        sample = [dict(o, n_points=min(o["n_points"], 1 << 14)) for o in opts[::64]]
+        Ls, what = L, "every 64th option of the portfolio (%d), first 2^14 points, %d shifts" % (len(opts[::64]), L)
+        sample1 = [dict(o, n_points=1 << 12) for o in opts[::256]]
+        L1, what1 = 2, "every 256th option (%d), first 2^12 points, 2 shifts" % len(opts[::256])
+    else:
+        sample = [dict(o, n_points=1 << 19) for o in opts]
+        Ls, what = 8, "the 18 options at d=64, 2^19 points x 8 shifts"
+        sample1 = [dict(o, n_points=1 << 14) for o in opts]
+        L1, what1 = 2, "the 18 options at d=64, 2^14 points x 2 shifts"
+    t0 = time.perf_counter()
+    _, _, _, used = oracle.options(sample, Ls, oracle.PATH_BB, n_threads=threads)
+    tc = time.perf_counter() - t0
+    pd_s = workloads.total_path_dates(sample, Ls)
+    res = {"value": workloads.total_paths(sample, Ls) / tc, "unit": "Greek-paths/s", "cores": used,
+           "kind": "oracle", "sample": "%s (%.1f s)" % (what, tc), "cpu_model": cpu_model(),
+           "path_dates_per_s": pd_s / tc,
+           "extrapolated_full_workload_s": tc * n_pd_full / pd_s}
+    t0 = time.perf_counter()
+    oracle.options(sample1, L1, oracle.PATH_BB, n_threads=1)
+    t1c = time.perf_counter() - t0
+    res["single_thread"] = {"value": workloads.total_paths(sample1, L1) / t1c,
+                            "path_dates_per_s": workloads.total_path_dates(sample1, L1) / t1c,
+                            "sample": "%s (%.1f s)" % (what1, t1c)}
+    return res
+
+
+def three_products_leg(q, workloads, torch, steps=5, warmup=1):
+    """The 18-option three-product grid at d = 64 (2^20 points x 32 shifts,
+    bridge): FP32-mixed with its roofline, plain FP64, their differences."""
+    dev = torch.device("cuda", 0)
+    opts = workloads.three_products_grid(d=64, n_points=1 << 20)
+    L = 32
+    paths = workloads.total_paths(opts, L)
+    pd = workloads.total_path_dates(opts, L)
+    out = (torch.empty((len(opts), 4), dtype=torch.float64, device=dev),
+           torch.empty((len(opts), 4), dtype=torch.float64, device=dev))
+    stream = torch.cuda.Stream()
+    wall, ev_ms, k_ms = timed_calls(q, torch, opts, L, q.PATH_BB, q.FP32_MIXED, steps, warmup, out, stream)
+    g = out[0].cpu().numpy()
+    e = out[1].cpu().numpy()
+    res = {"value": paths * steps / wall, "unit": "Greek-paths/s", "ms_per_step": wall / steps * 1e3,
+           "greek_paths": paths, "path_dates": pd,
+           "roofline": roofline(paths, pd, k_ms, traffic=traffic_of("three_products"), call_ms=ev_ms)}
+    w64, ev64, k64 = timed_calls(q, torch, opts, L, q.PATH_BB, q.FP64, 2, 1, out, stream)
+    g64 = out[0].cpu().numpy()
+    res["fp64"] = {"value": paths * 2 / w64, "ms_per_step": w64 / 2 * 1e3, "kernel_ms": k64}
+    rel = np.abs(g - g64) / np.maximum(np.abs(g64), 1e-300)
+    res["fp32_vs_fp64_max_rel_diff"] = {k: float(rel[:, i].max()) for i, k in enumerate(q.OUTPUTS)}
+    res["stderr_max_rel"] = {k: float((e[:, i] / np.maximum(np.abs(g64[:, i]), 1e-300)).max())
+                             for i, k in enumerate(q.OUTPUTS)}
+    res["stderr_min_rel"] = {k: float((e[:, i] / np.maximum(np.abs(g64[:, i]), 1e-300)).min())
+                             for i, k in enumerate(q.OUTPUTS)}
+    return res
+
+
+def owen_leg(q, workloads, torch, steps=3):
+    """The three-product grid randomised by nested scrambling instead of the
+    digital shift: rate, kernel time, standard errors against the shift."""
+    dev = torch.device("cuda", 0)
+    opts = workloads.three_products_grid(d=64, n_points=1 << 20)
+    L = 32
+    out = (torch.empty((len(opts), 4), dtype=torch.float64, device=dev),
+           torch.empty((len(opts), 4), dtype=torch.float64, device=dev))
+    stream = torch.cuda.Stream()
+    timed_calls(q, torch, opts, L, q.PATH_BB, q.FP32_MIXED, 1, 0, out, stream)
+    e = out[1].cpu().numpy()
+    wall, ev_ms, k_ms = timed_calls(q, torch, opts, L, q.PATH_BB, q.FP32_MIXED, steps, 1, out, stream, owen=True)
+    e_owen = out[1].cpu().numpy()
+    return {"value": workloads.total_paths(opts, L) * steps / wall, "unit": "Greek-paths/s", "kernel_ms": k_ms,
+            "stderr_ratio_owen_over_shift": {k: float(np.median(e_owen[:, i] / e[:, i]))
+                                             for i, k in enumerate(q.OUTPUTS)}}
+
+
+def per_option_fp64_leg(q, workloads, opts, L):
+    """The plain path beside the persistent launch: FP64, one option per
+    launch, on every 128th option of the portfolio."""
+    sample = opts[::128]
+    t1 = time.perf_counter()
+    for o in sample:
+        q.greeks([o], L, q.PATH_BB, q.FP64)
+    t64 = time.perf_counter() - t1
+    p64 = workloads.total_paths(sample, L)
+    return {"value": p64 / t64, "unit": "Greek-paths/s", "sample": "every 128th option (%d)" % len(sample),
+            "seconds": t64}
 
 
 def geometric_leg(q, workloads, torch, prec, L=32, steps=3):
@@ -338,79 +457,158 @@ def pca_leg(q, workloads, torch, steps=3):
     a dense (256 x 256) x (256 x 64-point) product per tile on the matrix
     cores): arithmetic and binary Asian, 2^22 points x 16 shifts, FP32-mixed,
     GEMM in FP32 MFMA and in split BF16x3; kernel time from the library's
-    HIP events.  gemm_frac is the product's algorithmic flops 2 n^2 per path
-    over the time of the whole fused kernel, against the FP32 MFMA peak
-    (157.3 TFLOP/s) or, for BF16x3 (three BF16 products per FP32 product),
-    a third of the BF16 peak (2.5 PFLOP/s / 3)."""
+    HIP events.  The roofline is the whole kernel's: the product's 2 n^2
+    flops per path at the FP32 matrix peak (BF16x3: three BF16 products at
+    the BF16 matrix peak), plus the VALU model (36 FP32 flops per path-date,
+    200 FP64 flops per path) at the vector peaks."""
     opts = workloads.pca_pair(d=256, n_points=1 << 22)
     L = 16
     n = 255
     paths = workloads.total_paths(opts, L)
+    pd = workloads.total_path_dates(opts, L)
     s = torch.cuda.Stream()
     out = (torch.empty((2, 4), dtype=torch.float64, device="cuda"),
            torch.empty((2, 4), dtype=torch.float64, device="cuda"))
     res = {"workload": "arith + binary Asian, d=256, PCA, 2^22 points x 16 shifts, FP32-mixed",
            "greek_paths": paths}
-    for name, gemm, peak in (("fp32_mfma", q.GEMM_FP32, 157.3e12), ("bf16x3_mfma", q.GEMM_BF16X3, 2.5e15 / 3)):
-        q.greeks(opts, L, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, device_outputs=True, out=out, stream=s)
-        s.synchronize()
-        q.kernel_timer(q.TIMER_START)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            q.greeks(opts, L, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, device_outputs=True, out=out, stream=s)
-        s.synchronize()
-        wall = (time.perf_counter() - t0) / steps
-        k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
-        k_ms /= max(k_n, 1)
-        gflop = 2.0 * n * n * paths
-        res[name] = {"value": paths / wall, "unit": "Greek-paths/s", "kernel_ms": k_ms,
-                     "gemm_tflops": gflop / (k_ms * 1e-3) / 1e12,
-                     "gemm_frac": gflop / (k_ms * 1e-3) / peak}
+    gflop = 2.0 * n * n * paths
+    for name, gemm, mf, peak in (("fp32_mfma", q.GEMM_FP32, gflop, PEAK_MFMA_F32),
+                                 ("bf16x3_mfma", q.GEMM_BF16X3, 3 * gflop, PEAK_MFMA_BF16)):
+        wall, ev_ms, k_ms = timed_calls(q, torch, opts, L, q.PATH_PCA, q.FP32_MIXED, steps, 1, out, s,
+                                        pca_gemm=gemm)
+        res[name] = {"value": paths * steps / wall, "unit": "Greek-paths/s", "kernel_ms": k_ms,
+                     "roofline": roofline(paths, pd, k_ms, mfma_flops=mf, mfma_peak=peak,
+                                          kernel="qcpw::pca_f32_kernel"),
+                     "gemm_only_frac": mf / peak / (k_ms * 1e-3)}
         if gemm == q.GEMM_FP32:
             se_x1 = out[1].cpu().numpy().copy()
     # the same points conditioned on the first principal component of all d
     # dates (FP64 Newton root-find per path): time, and the variance ratio of
     # each Greek against conditioning on the first date's normal
-    q.greeks(opts, L, q.PATH_PCA_FULL, q.FP32_MIXED, device_outputs=True, out=out, stream=s)
-    s.synchronize()
-    q.kernel_timer(q.TIMER_START)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        q.greeks(opts, L, q.PATH_PCA_FULL, q.FP32_MIXED, device_outputs=True, out=out, stream=s)
-    s.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    k_ms, k_n = q.kernel_timer(q.TIMER_STOP)
+    wall, ev_ms, k_ms = timed_calls(q, torch, opts, L, q.PATH_PCA_FULL, q.FP32_MIXED, steps, 1, out, s)
     se_full = out[1].cpu().numpy()
     res["pca_full_fp32_mfma"] = {
-        "value": paths / wall, "unit": "Greek-paths/s", "kernel_ms": k_ms / max(k_n, 1),
+        "value": paths * steps / wall, "unit": "Greek-paths/s", "kernel_ms": k_ms,
         "variance_ratio_vs_first_date": {k: [float((se_x1[i, j] / se_full[i, j]) ** 2) for i in range(2)]
                                          for j, k in enumerate(q.OUTPUTS)}}
     return res
 
 
-def portfolio_leg(q, workloads, torch):
-    """4096 options of uneven type, d, K, sigma, T, r and 2^14..2^20 points,
-    16 shifts, FP32-mixed, in one persistent launch; beside it the plain
-    path (FP64, one option per launch) on a fixed sample of the options."""
-    opts = workloads.portfolio(4096)
-    L = 16
-    q.greeks(opts[:64], L, q.PATH_BB, q.FP32_MIXED)   # warm the tables / workspace
-    torch.cuda.synchronize()
+def run_stream(q, srv, stream, L=16):
+    """Submit a request stream at its arrival times into server srv, poll for
+    results from a second thread; returns (latency seconds per request,
+    points reached per request, wall seconds)."""
+    import threading
+    done = {}
+    pending = []
+    lock = threading.Lock()
+    finished = threading.Event()
+
+    def poller():
+        # completion times are taken as soon as a result is ready
+        while True:
+            with lock:
+                todo = list(pending)
+            for item in todo:
+                rid, ts, r = item
+                out = srv.poll(rid, len(r["options"]))
+                if out is not None:
+                    done[rid] = (time.perf_counter() - ts, out[2])
+                    with lock:
+                        pending.remove(item)
+            if finished.is_set() and not todo:
+                return
+            time.sleep(0.0002)
+
+    th = threading.Thread(target=poller)
+    th.start()
     t0 = time.perf_counter()
-    g, e = q.greeks(opts, L, q.PATH_BB, q.FP32_MIXED)
-    t = time.perf_counter() - t0
-    paths = workloads.total_paths(opts, L)
-    sample = opts[::128]
-    t1 = time.perf_counter()
-    for o in sample:
-        q.greeks([o], L, q.PATH_BB, q.FP64)
-    t64 = time.perf_counter() - t1
-    p64 = workloads.total_paths(sample, L)
-    return {"options": len(opts), "shifts": L, "greek_paths": paths,
-            "path_dates": workloads.total_path_dates(opts, L), "seconds": t, "value": paths / t,
-            "unit": "Greek-paths/s", "precision": "fp32-mixed, one persistent launch",
-            "fp64_one_option_per_launch": {"value": p64 / t64, "sample": "every 128th option (%d)" % len(sample),
-                                           "seconds": t64}}
+    ids = []
+    for r in stream:
+        now = time.perf_counter() - t0
+        if r["t_arrival"] > now:
+            time.sleep(r["t_arrival"] - now)
+        item = (srv.submit(r["options"], L, r["target_stderr"]), t0 + r["t_arrival"], r)
+        ids.append(item)
+        with lock:
+            pending.append(item)
+    finished.set()
+    th.join()
+    wall = time.perf_counter() - t0
+    lat = np.array([done[rid][0] for rid, _, _ in ids])
+    pts = [done[rid][1] for rid, _, _ in ids]
+    return lat, pts, wall
+
+
+def plain_fp64_stream(q, stream, pts, L=16, cap_s=120.0):
+    """The plain method under the same arrivals: one worker takes requests in
+    arrival order and prices each option alone (FP64, one option per launch)
+    at the points the mixed-precision server reached for that request (so
+    both sides have the same RMSE).  Stops taking requests cap_s seconds
+    after the first arrival; a request not finished by then counts with its
+    waiting time so far (a lower bound on its latency)."""
+    lat, finished, paths = [], 0, 0
+    t0 = time.perf_counter()
+    for r, p in zip(stream, pts):
+        now = time.perf_counter() - t0
+        if now > cap_s:
+            break
+        if r["t_arrival"] > now:
+            time.sleep(r["t_arrival"] - now)
+        for o in r["options"]:
+            q.greeks([dict(o, n_points=p)], L, q.PATH_BB, q.FP64)
+        lat.append(time.perf_counter() - t0 - r["t_arrival"])
+        finished += 1
+        paths += len(r["options"]) * p * L
+    busy = time.perf_counter() - t0
+    t_end = time.perf_counter() - t0
+    censored = [t_end - r["t_arrival"] for r in stream[finished:] if r["t_arrival"] < t_end]
+    all_lat = np.array(lat + censored) * 1e3
+    return {"requests_finished": finished, "requests_arrived_unfinished": len(censored),
+            "value": paths / busy if busy > 0 else 0.0, "unit": "Greek-paths/s",
+            "p50_ms": float(np.percentile(all_lat, 50)) if len(all_lat) else None,
+            "p99_ms": float(np.percentile(all_lat, 99)) if len(all_lat) else None,
+            "latency_is_lower_bound": bool(censored), "cap_s": cap_s}
+
+
+def serve_sweep(q, workloads, n_requests, fracs, max_opts=512, d_range=(4, 365), targets=(1e-4, 1e-6),
+                n_burst=24, L=16, fp64_cap_s=120.0):
+    """The configured serving stream (Poisson arrivals of 1..max_opts-option
+    portfolios drawn as the uneven portfolio, target standard error 1e-4 or
+    1e-6 relative): the saturation rate of the mixed-precision server (a
+    burst of n_burst requests submitted at once, over the time to finish
+    them), then n_requests requests at each rate frac x saturation with
+    p50/p99 latency and throughput; beside each, the plain FP64
+    one-option-per-launch method under the same arrivals."""
+    burst = workloads.request_stream(n_burst, 1e9, seed=5150, max_opts=max_opts, d_range=d_range,
+                                     targets=targets)
+    for r in burst:
+        r["t_arrival"] = 0.0
+    with q.Server(hbm_budget_bytes=8 << 30, precision=q.FP32_MIXED) as srv:
+        lat, pts, wall = run_stream(q, srv, burst, L)
+    sat = n_burst / float(lat.max())
+    print("serve sweep: saturation %.3f requests/s" % sat, file=sys.stderr, flush=True)
+    res = {"stream": {"options_per_request": [1, max_opts], "d_range": list(d_range),
+                      "target_stderr": list(targets), "shifts": L},
+           "saturation_requests_per_s": sat, "rates": []}
+    for frac in fracs:
+        rate = frac * sat
+        stream = workloads.request_stream(n_requests, rate, seed=22091 + int(frac * 1000), max_opts=max_opts,
+                                          d_range=d_range, targets=targets)
+        with q.Server(hbm_budget_bytes=8 << 30, precision=q.FP32_MIXED) as srv:
+            lat, pts, wall = run_stream(q, srv, stream, L)
+            stats = srv.stats()
+        paths = sum(len(r["options"]) * p * L for r, p in zip(stream, pts))
+        lat_ms = lat * 1e3
+        entry = {"fraction_of_saturation": frac, "rate_per_s": rate, "requests": n_requests,
+                 "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+                 "max_ms": float(lat_ms.max()), "value": paths / wall, "unit": "Greek-paths/s",
+                 "launches": stats["launches"], "mean_points": float(np.mean(pts))}
+        print("serve sweep: %.2f x saturation: p50 %.1f ms, p99 %.1f ms" % (frac, entry["p50_ms"], entry["p99_ms"]),
+              file=sys.stderr, flush=True)
+        entry["fp64_one_option_per_launch"] = plain_fp64_stream(q, stream, pts, L, cap_s=fp64_cap_s)
+        res["rates"].append(entry)
+    return res
 
 
 def serving_leg(q, workloads, n_requests=300, rate=100.0, max_opts=32, d_range=(4, 64), targets=(1e-3, 1e-4),

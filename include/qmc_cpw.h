@@ -81,8 +81,10 @@ enum { QCPW_ARITH_ASIAN_CALL = 0, QCPW_BINARY_ASIAN_CALL = 1, QCPW_LOOKBACK_FIXE
  *                     eigenvalue) is the conditioned variable instead of x_1
  *                     -- the principal-component conditioning Sec. 7 names
  *                     for larger variance reduction.  Its breakpoint needs a
- *                     root-find (Newton, FP64).  Arithmetic and binary Asian
- *                     calls only; d <= QCPW_MAX_D_PCA_FULL.                */
+ *                     root-find (Newton, FP64; for the lookback the upper
+ *                     envelope of the dates' log-price lines).  Arithmetic
+ *                     and binary Asian and lookback calls; d <=
+ *                     QCPW_MAX_D_PCA_FULL.                                  */
 enum { QCPW_PATH_BB = 0, QCPW_PATH_PCA = 1, QCPW_PATH_STANDARD = 2, QCPW_PATH_PCA_FULL = 3 };
 
 /* Arithmetic of the per-path work.  QCPW_FP64: everything in FP64.
@@ -291,14 +293,19 @@ const char *qcpw_version(void);
 typedef struct qcpw_server qcpw_server;
 
 /* cfg: precision / device / block_threads as for _ex (stream and output
- * fields ignored).  hbm_budget_bytes > 0 bounds the device memory held for
- * admitted requests.  *out receives the server. */
+ * fields ignored).  hbm_budget_bytes > 0 bounds the device memory of the
+ * server's launch workspaces together (two launch slots, each at most half
+ * of it; the resident tables are not counted).  With block_threads == 0 the
+ * workgroup-size autotuner runs for every lane-table bucket here, so that no
+ * request pays for its probe launches.  *out receives the server. */
 qcpw_status qcpw_server_create(const qcpw_run_config *cfg, int64_t hbm_budget_bytes,
                                qcpw_server **out);
 
-/* Copies the specs; 1 <= n_opts <= 4096; every spec's d and n_points fields
- * are used (n_points is ignored: the target sets the count).  QCPW_ENOMEM if
- * the request alone exceeds the budget.  *request_id receives the id. */
+/* Copies the specs; 1 <= n_opts <= 4096; every spec's d field is used
+ * (n_points is ignored: the target sets the count).  A request is admitted
+ * into a launch when its smallest slice (8192 points of every option) fits
+ * the memory left in that launch's slot; QCPW_ENOMEM if it cannot fit even
+ * an empty slot.  *request_id receives the id. */
 qcpw_status qcpw_submit(qcpw_server *srv, const qcpw_option_spec *specs, int32_t n_opts,
                         int32_t n_shifts, int32_t path_construction,
                         double target_stderr, uint64_t *request_id);
@@ -318,10 +325,12 @@ qcpw_status qcpw_wait(qcpw_server *srv, uint64_t request_id, double *out_greeks,
 qcpw_status qcpw_cancel(qcpw_server *srv, uint64_t request_id);
 
 /* Counters since creation: [0] admitted, [1] completed, [2] cancelled,
- * [3] launches, [4] bytes in use, [5] peak bytes in use, [6] queued now. */
-qcpw_status qcpw_server_stats(qcpw_server *srv, int64_t out[7]);
+ * [3] launches, [4] device bytes of the launches in flight, [5] their peak,
+ * [6] queued now, [7] device bytes the launch workspaces hold now. */
+qcpw_status qcpw_server_stats(qcpw_server *srv, int64_t out[8]);
 
-/* Stops the worker after the running launch; pending requests are cancelled. */
+/* Stops taking work at once, waits for the launches in flight (at most two,
+ * each bounded in size), then cancels every queued or running request. */
 qcpw_status qcpw_server_destroy(qcpw_server *srv);
 
 #ifdef __cplusplus

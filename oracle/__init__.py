@@ -230,7 +230,7 @@ def path_greeks_full(type_: int, d: int, S0, K, r, sigma, T, a, c) -> np.ndarray
     c = np.ascontiguousarray(c, dtype=np.float64)
     out = np.zeros(4)
     if _load().oracle_path_greeks_full(type_, d, S0, K, r, sigma, T, a, c, out) != 0:
-        raise ValueError("full-PCA conditioning covers arithmetic and binary Asian options only")
+        raise ValueError("full-PCA conditioning covers the arithmetic and binary Asian and the lookback calls")
     return out
 
 

@@ -45,7 +45,8 @@
  *     dt min(j, k); the first component z_1 (largest eigenvalue) is the
  *     conditioned variable, integrated out in closed form; z_2..z_d come from
  *     Sobol dimensions 1..d-1 (dimension 0 stays reserved).  Arithmetic and
- *     binary Asian only.
+ *     binary Asian calls, and the fixed-strike lookback call through the
+ *     upper envelope of the log-prices' lines in the conditioned variable.
  */
 #include <math.h>
 #include <stdint.h>
@@ -466,11 +467,90 @@ double oracle_full_root(int d, const double *al, const double *be, double K)
     return x;
 }
 
+/* ------------------------------------------------------------------------
+ * Lookback (fixed-strike call on the discrete maximum) under the same
+ * conditioning.  Every beta_j > 0, so M(x) = max_j (alpha_j + beta_j x), the
+ * upper envelope of d increasing lines, is increasing, convex and piecewise
+ * linear, and the payoff (e^{M(x)} - K)^+ is positive exactly for x > psi:
+ *   psi = min_j (ln K - alpha_j) / beta_j
+ * (M(x) <= ln K iff every line is, iff x <= each line's own crossing).
+ * On [psi, inf) the envelope is a chain of segments [x_s, x_{s+1}) with one
+ * line j_s on top; starting from the line that meets ln K at psi (the
+ * steeper one on a tie), the next line is the steeper one that overtakes
+ * the current line first.  Over a segment [a, b) of line j, with
+ * E_j = exp(alpha_j + beta_j^2 / 2) and e^{alpha + beta x} phi(x) =
+ * E phi(x - beta):
+ *   int (e^{alpha_j + beta_j x} - K) phi = E_j dP_j - K (Phi(b) - Phi(a)),
+ *        dP_j = Phi(b - beta_j) - Phi(a - beta_j)
+ * (each difference of Phi taken as the probability of the interval, from
+ * the upper tail right of 0);
+ *   int e^{alpha_j + beta_j x} (alpha_j' + beta_j' x) phi
+ *        = E_j [alpha_j' dP_j + beta_j' (beta_j dP_j + phi(a - beta_j) - phi(b - beta_j))].
+ * The integrand is continuous across breakpoints and zero at psi, so the
+ * derivatives of the price are the integrals of the payoff's derivatives:
+ *   G     = D sum_s [E_j dP_j - K (Phi(b) - Phi(a))],
+ *   delta = D sum_s E_j dP_j / S0                (d alpha_j / d S0 = 1/S0),
+ *   vega  = D sum_s E_j [alpha_j' dP_j + a_j (beta_j dP_j + phi(a - beta_j) - phi(b - beta_j))],
+ *           alpha_j' = c_j - sigma t_j, beta_j' = a_j,
+ *   gamma = D K phi(psi) / (S0^2 beta*),  beta* the slope on top at psi
+ *           (the only S0-dependence left in delta is the lower end psi,
+ *           d psi / d S0 = -1 / (S0 beta*), and E* phi(psi - beta*) = K phi(psi)).
+ * ---------------------------------------------------------------------- */
+/* P(lo < X < hi) for X ~ N(0, 1), lo <= hi (hi may be +inf), from the
+ * upper tail when the interval lies right of 0 so that it keeps its
+ * relative accuracy far out. */
+static double norm_interval(double lo, double hi)
+{
+    if (lo >= 0.0) return 0.5 * erfc(lo / sqrt(2.0)) - (isinf(hi) ? 0.0 : 0.5 * erfc(hi / sqrt(2.0)));
+    return (isinf(hi) ? 1.0 : oracle_norm_cdf(hi)) - oracle_norm_cdf(lo);
+}
+
+static void full_lookback(int d, const double *al, const double *be, const double *a, const double *c,
+                          double S0, double K, double sigma, double dt, double D, double *out)
+{
+    const double lnK = log(K);
+    int j = 0;
+    double psi = (lnK - al[0]) / be[0];
+    for (int i = 1; i < d; ++i) {
+        const double xi = (lnK - al[i]) / be[i];
+        if (xi < psi || (xi == psi && be[i] > be[j])) { psi = xi; j = i; }
+    }
+    const double bstar = be[j];
+    double G = 0.0, dl = 0.0, vg = 0.0;
+    double x0 = psi;
+    for (;;) {
+        /* the steeper line that overtakes line j first, if any */
+        int nx = -1;
+        double x1 = INFINITY;
+        for (int i = 0; i < d; ++i) {
+            if (!(be[i] > be[j])) continue;
+            const double xi = (al[j] - al[i]) / (be[i] - be[j]);
+            if (xi < x1 || (xi == x1 && nx >= 0 && be[i] > be[nx])) { x1 = xi; nx = i; }
+        }
+        if (x1 < x0) x1 = x0;   /* rounding: a line crossing at x0 itself */
+        const double E = exp(al[j] + 0.5 * be[j] * be[j]);
+        const double fb = isinf(x1) ? 0.0 : oracle_norm_pdf(x1 - be[j]);
+        const double fa = oracle_norm_pdf(x0 - be[j]);
+        const double dP = norm_interval(x0 - be[j], x1 - be[j]);
+        const double t = (j + 1) * dt;
+        G += E * dP - K * norm_interval(x0, x1);
+        dl += E * dP;
+        vg += E * ((c[j] - sigma * t) * dP + a[j] * (be[j] * dP + fa - fb));
+        if (nx < 0) break;
+        j = nx;
+        x0 = x1;
+    }
+    out[0] = D * G;
+    out[1] = D * dl / S0;
+    out[2] = D * vg;
+    out[3] = D * K * oracle_norm_pdf(psi) / (S0 * S0 * bstar);
+}
+
 int oracle_path_greeks_full(int type, int d, double S0, double K, double r,
                             double sigma, double T, const double *a, const double *c,
                             double *out)
 {
-    if (type != ORC_ARITH && type != ORC_BINARY) return -1;
+    if (type != ORC_ARITH && type != ORC_BINARY && type != ORC_LOOKBACK) return -1;
     double dt = T / d;
     double omega = r - 0.5 * sigma * sigma;
     double D = exp(-r * T);
@@ -480,6 +560,11 @@ int oracle_path_greeks_full(int type, int d, double S0, double K, double r,
         double t = (j + 1) * dt;
         al[j] = log(S0) + omega * t + sigma * c[j];
         be[j] = sigma * a[j];
+    }
+    if (type == ORC_LOOKBACK) {
+        full_lookback(d, al, be, a, c, S0, K, sigma, dt, D, out);
+        free(al); free(be);
+        return 0;
     }
     double psi = oracle_full_root(d, al, be, K);
     double phi0 = oracle_norm_pdf(psi);
@@ -607,7 +692,7 @@ int oracle_replication(int type, int d, double S0, double K, double r, double si
                        int rand, const uint32_t *V, const double *A, double *C_l, double *abs_sum)
 {
     if (d < 1 || N < 1 || k0 < 0) return -1;
-    if (path == ORC_PCA_FULL && (!A || (type != ORC_ARITH && type != ORC_BINARY))) return -1;
+    if (path == ORC_PCA_FULL && (!A || (type != ORC_ARITH && type != ORC_BINARY && type != ORC_LOOKBACK))) return -1;
     int n = d - 1;
     double dt = T / d;
     double *z = (double *)malloc(sizeof(double) * (size_t)(n + 1));

@@ -275,9 +275,10 @@ class Server:
         _check(lib().qcpw_cancel(self._h, rid))
 
     def stats(self) -> dict:
-        out = (C.c_int64 * 7)()
+        out = (C.c_int64 * 8)()
         _check(lib().qcpw_server_stats(self._h, out))
-        keys = ("admitted", "completed", "cancelled", "launches", "bytes_in_use", "peak_bytes", "queued")
+        keys = ("admitted", "completed", "cancelled", "launches", "bytes_in_use", "peak_bytes", "queued",
+                "workspace_bytes")
         return dict(zip(keys, list(out)))
 
     def close(self):

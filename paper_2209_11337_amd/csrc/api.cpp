@@ -2,6 +2,7 @@
 // resident tables, workspace management and the synchronous entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -35,7 +36,7 @@ qcpw_status fail(qcpw_status code, const std::string &msg)
     return code;
 }
 
-qcpw_status Workspace::ensure(size_t need)
+qcpw_status Workspace::ensure(size_t need, size_t cap)
 {
     if (need <= bytes) return QCPW_OK;
     if (ptr) {
@@ -43,7 +44,7 @@ qcpw_status Workspace::ensure(size_t need)
         ptr = nullptr;
         bytes = 0;
     }
-    size_t want = need + need / 4;
+    size_t want = std::max(need, std::min(need + need / 4, cap));
     hipError_t e = hipMalloc(&ptr, want);
     if (e != hipSuccess) {
         ptr = nullptr;
@@ -83,6 +84,29 @@ static qcpw_status init_tables(Context *ctx, int device)
         all.insert(all.end(), s.begin(), s.end());
         all64.insert(all64.end(), s64.begin(), s64.end());
     }
+    // split-bridge plans, each checked against the plan walker's: the FP64
+    // factor its walk applies must equal the plan's bit for bit, or n keeps
+    // the plan walker
+    std::vector<uint32_t> sev((size_t)(QCPW_MAX_N + 1) * QCPW_SPLIT_EVENTS * QCPW_EV_WORDS, 0u);
+    std::vector<uint16_t> sdim((size_t)(QCPW_MAX_N + 1) * QCPW_SPLIT_SLOTS, 0);
+    t.split_slots.assign(QCPW_MAX_N + 1, 0);
+    for (int n = QCPW_SUB_MIN_LEN; n <= QCPW_MAX_N; ++n) {
+        std::vector<uint32_t> ev;
+        std::vector<uint16_t> sd;
+        const int slots = build_split_plan(n, ev, sd);
+        if (slots <= 0 || slots > (n > QCPW_WIDE_MIN_N ? 8 : QCPW_UQ) * 64) continue;
+        std::vector<double> A_split, A_plan;
+        split_plan_factor(n, 1.0, ev, A_split);
+        build_factor(QCPW_PATH_BB, n, 1.0, A_plan);
+        if (memcmp(A_split.data(), A_plan.data(), A_plan.size() * sizeof(double)) != 0) continue;
+        t.split_slots[n] = slots;
+        std::copy(ev.begin(), ev.end(), sev.begin() + (size_t)n * QCPW_SPLIT_EVENTS * QCPW_EV_WORDS);
+        std::copy(sd.begin(), sd.end(), sdim.begin() + (size_t)n * QCPW_SPLIT_SLOTS);
+    }
+    QCPW_HIP(hipMalloc(&t.split_ev, sev.size() * 4));
+    QCPW_HIP(hipMalloc(&t.split_dim, sdim.size() * 2));
+    QCPW_HIP(hipMemcpy(t.split_ev, sev.data(), sev.size() * 4, hipMemcpyHostToDevice));
+    QCPW_HIP(hipMemcpy(t.split_dim, sdim.data(), sdim.size() * 2, hipMemcpyHostToDevice));
     QCPW_HIP(hipMalloc(&t.dir, dir.size() * 4));
     QCPW_HIP(hipMalloc(&t.lane, lane.size() * 4));
     QCPW_HIP(hipMalloc(&t.plan, all.size() * sizeof(PlanStep)));
@@ -508,6 +532,18 @@ qcpw_status qcpw_path_factor(int32_t path_construction, int32_t d, double T, dou
     std::vector<double> A;
     if (path_construction == QCPW_PATH_PCA_FULL) build_pca_factor(d, T / d, A);
     else build_factor(path_construction, d - 1, T / d, A);
+    if (path_construction == QCPW_PATH_BB) {
+        // the split bridge's walk (FP32 kernel) must apply the same factor
+        // as the plan walker's, bit for bit; NaNs report a mismatch
+        std::vector<uint32_t> ev;
+        std::vector<uint16_t> sd;
+        if (build_split_plan(d - 1, ev, sd) > 0) {
+            std::vector<double> As;
+            split_plan_factor(d - 1, T / d, ev, As);
+            if (memcmp(As.data(), A.data(), A.size() * sizeof(double)) != 0)
+                std::fill(A.begin(), A.end(), std::nan(""));
+        }
+    }
     if (!A.empty()) memcpy(out, A.data(), A.size() * sizeof(double));
     return QCPW_OK;
 }

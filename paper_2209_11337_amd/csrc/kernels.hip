@@ -1,33 +1,6 @@
-// kernels.hip -- the fused per-path QMC-CPW kernel for gfx950 (MI355X), the
-// per-replication finalize kernel, and their launch planning.
-//
-// One persistent launch covers every option of a call.  Work units are
-// (option, replication l, range of unit_pts consecutive Sobol points, a
-// function of the option's point count alone); each wave pulls units from
-// device counters and gives each lane one point per iteration, so for point
-// k = base + lane (base a multiple of 64):
-//
-//   Sobol integer of dimension j (Sec. 2.2.2, XOR form of
-//   eqn:GeneratorMatrixExpression, Gray-code order):
-//       y_j = lane_table[j][lane]  XOR  U_j(base),
-//   where U_j(base) = dir_j . gray(base) XOR s_{l,j} is the same for the
-//   whole wave (the digital shift of Sec. 2.2.3 is folded in).  Stepping to
-//   the next base changes U_j by two direction numbers only.  U is held in
-//   registers, distributed over the lanes in the order the path consumes the
-//   dimensions, and broadcast with v_readlane.
-//
-//   Inverse normal, path construction (Sec. 3.4.1 W~ = A z, Sec. 4.4 bridge
-//   or Alg. 3 increments), exponentials and running sums (Sec. 4.1: nothing
-//   about the path is stored) all stay in registers / LDS.  The path is
-//   built directly in log2 space, Y_m = log2(S~(t_{m+1}) / S0), so each date
-//   costs one exp2.
-//
-//   Per path, in FP64: breakpoint psi of the conditioned normal x_1
-//   (Sec. 3.4.2), Phi tails, and price/delta/vega/gamma (Sec. 4.5), added
-//   into compensated per-lane sums; a fixed wave butterfly reduces them to
-//   one partial per unit.  The finalize kernel adds a replication's partials
-//   in chunk order and forms mean and standard error over replications
-//   (Sec. 5).
+// kernels.hip -- launch planning for the fused per-path QMC-CPW kernel
+// (paths_kernel.h), the per-replication finalize kernel, the Sobol probe
+// kernel, the workgroup-size autotuner and the launch sequence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,497 +15,6 @@
 #include "device_math.h"
 
 namespace qcpw {
-
-// ------------------------------------------------------------------------
-// the fused per-path kernel
-// ------------------------------------------------------------------------
-struct UnitCtx {
-    int64_t unit;
-    int o;
-    int shift;
-    int64_t chunk;
-};
-
-// The wave-uniform part of the Sobol coordinates the lanes consume: for step
-// s = lane + 64 q, U[q] = G_dim gray(base), folded with the digital shift
-// (the lane table is folded too), or -- with nested scrambling -- raw, with
-// the dimension's scrambling seed in Sd[q] (the lane table then raw too).
-// PROBE instances also record every coordinate the walk consumes, at
-// pr[(dim - 1) * 64 + lane] of the current 64-point batch, so that the
-// integers of the per-path kernel itself can be checked bit for bit.
-template <bool OWEN_, bool PROBE = false>
-struct UParts {
-    static constexpr bool OWEN = OWEN_;
-    uint32_t U[QCPW_UQ];
-    uint32_t Sd[OWEN ? QCPW_UQ : 1];
-    uint32_t *pr;
-    // randomised coordinate of step 64 q + k from the lane's table word
-    __device__ __forceinline__ uint32_t bits(uint32_t lane_word, int q, int k) const
-    {
-        if constexpr (OWEN) return owen_scramble(lane_word ^ rdlane(U[q], k), rdlane(Sd[q], k));
-        else return lane_word ^ rdlane(U[q], k);
-    }
-    __device__ __forceinline__ uint32_t rec(uint32_t y, int dim, int lane) const
-    {
-        if constexpr (PROBE) pr[(dim - 1) * 64 + lane] = y;
-        return y;
-    }
-};
-
-// LDS word of lane-table row r: around the inverse-normal cells in the FP32
-// kernels (qcpw_row_word), contiguous from 0 in the FP64 kernels.
-template <bool F32>
-__device__ __forceinline__ int lane_row(int r)
-{
-    return F32 ? qcpw_row_word(r) : 64 * r;
-}
-
-template <bool F32, int MODE, class UP>
-__device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
-                                       typename Real<F32>::T *stk, int lane,
-                                       const UP &U, PathSums<typename Real<F32>::T> &ps)
-{
-    using R = typename Real<F32>::T;
-    const int n = op.n;
-    const PlanStep *plan = ld.plan + op.plan_off;
-    const PlanStep64 *plan64 = ld.plan64 + op.plan_off;
-    R L = R(0), Rr;
-    {   // terminal point
-        const PlanStep st = plan[0];
-        const uint32_t x = U.rec(U.bits(lds_lane[(F32 ? st.lds_off : (st.dim - 1) * 64) + lane], 0, 0), st.dim, lane);
-        const R z = coord_tab<F32>(x, op);
-        const R sd = F32 ? (R)st.sd * op.zs_t : (R)plan64[0].sd;
-        const R drift = F32 ? (R)op.ydrift_n_f : (R)op.ydrift_n;
-        Rr = fma(sd, z, drift);
-        consume<R, MODE>(ps, Rr, F32 ? (R)st.mf : (R)plan64[0].mf);
-    }
-#pragma unroll
-    for (int q = 0; q < QCPW_UQ; ++q) {
-        const int s_lo = q == 0 ? 1 : 64 * q;
-        const int s_hi = min(64 * (q + 1), n);
-#pragma unroll 2
-        for (int s = s_lo; s < s_hi; ++s) {
-            const PlanStep st = plan[s];
-            // stack: this lane's column, slot k at stk[64 k]
-            R *slot = stk + st.slot * 64;
-            if (st.pops == 0) {
-                *slot = Rr;
-            } else {
-                const R r = slot[0];
-                L = st.pops == 1 ? Rr : slot[64];
-                Rr = r;
-            }
-            const uint32_t x =
-                U.rec(U.bits(lds_lane[(F32 ? st.lds_off : (st.dim - 1) * 64) + lane], q, s - 64 * q), st.dim, lane);
-            const R z = coord_tab<F32>(x, op);
-            R Ym;
-            R mf;
-            if constexpr (F32) {
-                Ym = fmaf(st.sd, __fmul_rn(z, op.zs_t), fmaf(st.wr, Rr, st.wl * L));
-                mf = st.mf;
-            } else {
-                const PlanStep64 s64 = plan64[s];
-                Ym = fma(s64.sd, z, fma(s64.wr, Rr, s64.wl * L));
-                mf = s64.mf;
-            }
-            Rr = Ym;
-            consume<R, MODE>(ps, Ym, mf);
-        }
-        if (s_hi >= n) break;
-    }
-}
-
-// ---- compile-time bridges ------------------------------------------------
-// For n = 15, 31, 63, 127 (d = 16, 32, 64, 128) the bridge is unrolled at
-// compile time: the depth-first walk becomes template recursion over the
-// intervals, the pending right end points live in registers (no LDS stack,
-// no register shuffles), lane-table rows and U lanes are immediates, and the
-// weights are literals.  The intervals, dimensions, step order, weights and
-// formulas are those of the run-time plan (the host checks the plan against
-// the same constexpr functions); price, delta and gamma come out bit-identical
-// to the plan walker's, vega (from the FP32 sums of E Y and E m) within FP32
-// rounding.  Removes about a quarter of the VALU work per date.
-// The wave-uniform parts as the compile-time bridges read them.  Without
-// scrambling they are copied once per 64 points into every row of 16 lanes
-// (lane l of R[i] holds step 16 i + l mod 16), so that a DPP row broadcast
-// (row_newbcast) hands step S's value to all lanes inside the very XOR that
-// combines it with the lane word: no v_readlane per date.  With nested
-// scrambling the distributed parts are read as in the plan walker.
-template <class UP, int NSTEP, bool OWEN = UP::OWEN>
-struct FixedU;
-
-template <class UP, int NSTEP>
-struct FixedU<UP, NSTEP, false> {
-    static constexpr int NR = (NSTEP + 15) / 16;
-    uint32_t R[NR];
-    const UP &Up;
-    __device__ __forceinline__ FixedU(const UP &U, int lane) : Up(U)
-    {
-#pragma unroll
-        for (int i = 0; i < NR; ++i) R[i] = (uint32_t)__shfl((int)U.U[i / 4], 16 * (i % 4) + (lane & 15), 64);
-    }
-    template <int S>
-    __device__ __forceinline__ uint32_t bits(uint32_t lane_word) const
-    {
-        return lane_word ^ (uint32_t)__builtin_amdgcn_update_dpp(0, (int)R[S / 16], 0x150 + S % 16, 0xF, 0xF, false);
-    }
-    __device__ __forceinline__ uint32_t rec(uint32_t y, int dim, int lane) const { return Up.rec(y, dim, lane); }
-};
-
-template <class UP, int NSTEP>
-struct FixedU<UP, NSTEP, true> {
-    const UP &U;
-    __device__ __forceinline__ FixedU(const UP &u, int) : U(u) {}
-    template <int S>
-    __device__ __forceinline__ uint32_t bits(uint32_t lane_word) const
-    {
-        return U.bits(lane_word, S / 64, S % 64);
-    }
-    __device__ __forceinline__ uint32_t rec(uint32_t y, int dim, int lane) const { return U.rec(y, dim, lane); }
-};
-
-template <int MODE, class UP, int N, int LO, int HI>
-__device__ __forceinline__ void fixed_interval(const uint32_t *row0, int lane, float zs,
-                                               const FixedU<UP, N> &U, float WL, float WR,
-                                               PathSums<float> &ps)
-{
-    if constexpr (HI - LO >= 2) {
-        constexpr int M = (LO + HI) / 2;
-        constexpr int DIM = qcpw_bridge_dim(N, LO, HI);
-        constexpr int S = qcpw_bridge_step(N, LO, HI);
-        static_assert(DIM >= 2 && S >= 1, "interval outside the bridge");
-        constexpr float wl = (float)((double)(HI - M) / (double)(HI - LO));
-        constexpr float wr = (float)((double)(M - LO) / (double)(HI - LO));
-        constexpr float sd = (float)qcpw_csqrt((double)(M - LO) * (double)(HI - M) / (double)(HI - LO));
-        const uint32_t x = U.rec(U.template bits<S>(row0[qcpw_row_word(DIM - 1)]), DIM, lane);
-        const float z = ninv_table_f32(x);
-        const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
-        consume<float, MODE>(ps, Ym, (float)M);
-        fixed_interval<MODE, UP, N, LO, M>(row0, lane, zs, U, WL, Ym, ps);
-        fixed_interval<MODE, UP, N, M, HI>(row0, lane, zs, U, Ym, WR, ps);
-    }
-}
-
-template <int MODE, class UP, int N>
-__device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_t *lds_lane,
-                                                 int lane, const UP &Ud, PathSums<float> &ps)
-{
-    const uint32_t *row0 = lds_lane + lane;
-    const float zs = op.zs_t;
-    constexpr float sd0 = (float)qcpw_csqrt((double)N);
-    const FixedU<UP, N> U(Ud, lane);
-    const float z = ninv_table_f32(U.rec(U.template bits<0>(row0[qcpw_row_word(0)]), 1, lane));   // terminal, dimension 1
-    const float WR = fmaf(sd0 * zs, z, op.ydrift_n_f);
-    consume<float, MODE>(ps, WR, (float)N);
-    fixed_interval<MODE, UP, N, 0, N>(row0, lane, zs, U, 0.0f, WR, ps);
-}
-
-// true if op.n has a compile-time bridge (then the path is done)
-template <int MODE, class UP>
-__device__ inline bool bridge_fixed_any(const OptDev &op, const uint32_t *lds_lane, int lane,
-                                        const UP &U, PathSums<float> &ps)
-{
-    if (!qcpw_has_fixed_bridge(op.n)) return false;
-    switch (op.n) {
-    case 15: run_bridge_fixed<MODE, UP, 15>(op, lds_lane, lane, U, ps); return true;
-    case 31: run_bridge_fixed<MODE, UP, 31>(op, lds_lane, lane, U, ps); return true;
-    case 63: run_bridge_fixed<MODE, UP, 63>(op, lds_lane, lane, U, ps); return true;
-    case 127: run_bridge_fixed<MODE, UP, 127>(op, lds_lane, lane, U, ps); return true;
-    default: return false;
-    }
-}
-
-template <bool F32, int MODE, class UP>
-__device__ inline void run_standard_wave(const OptDev &op, const uint32_t *lds_lane, int lane,
-                                         const UP &U, PathSums<typename Real<F32>::T> &ps)
-{
-    using R = typename Real<F32>::T;
-    const int n = op.n;
-    const R drift = F32 ? (R)op.ydrift_1_f : (R)op.ydrift_1;
-    const R zs = F32 ? (R)op.zs_t : R(1);   // the FP32 table gives a standard normal
-    R Y = R(0);
-#pragma unroll
-    for (int q = 0; q < QCPW_UQ; ++q) {
-        const int s_hi = min(64 * (q + 1), n);
-        for (int s = 64 * q; s < s_hi; ++s) {
-            const uint32_t y = U.rec(U.bits(lds_lane[lane_row<F32>(s) + lane], q, s - 64 * q), s + 1, lane);
-            const R z = coord_tab<F32>(y, op);
-            Y = Y + fma(zs, z, drift);
-            consume<R, MODE>(ps, Y, (R)(s + 1));
-        }
-        if (s_hi >= n) break;
-    }
-}
-
-// The uniform part of Sobol step s (dimension s + 1) for a step index known
-// only at run time (wave-uniform): the register holding it is picked by a
-// uniform branch.
-template <class UP>
-__device__ __forceinline__ uint32_t ubits_at(const UP &U, uint32_t lane_word, int s)
-{
-    const int k = s & 63;
-    switch (s >> 6) {
-    case 0: return U.bits(lane_word, 0, k);
-    case 1: return U.bits(lane_word, 1, k);
-    case 2: return U.bits(lane_word, 2, k);
-    case 3: return U.bits(lane_word, 3, k);
-    case 4: return U.bits(lane_word, 4, k);
-    default: return U.bits(lane_word, QCPW_UQ - 1, k);
-    }
-}
-
-// Basket of M assets (one-factor model), standard construction, in date
-// order: the common part C_m = log2(e) (omega tau_m + sigma sqrt(rho) B~_0)
-// (steps from dimensions 1..n) and asset i's idiosyncratic part
-// I_i = log2(e) sigma sqrt(1 - rho) B_i(t_{m+1}) (dimensions n + 1 + i d + m)
-// add to Y_{i,m} = C_m + I_i, and every (asset, date) pair feeds the
-// average's sums, date 1 included (its idiosyncratic part is random).
-template <bool F32, class UP>
-__device__ inline void run_basket_wave(const OptDev &op, const uint32_t *lds_lane, int lane, const UP &U,
-                                       PathSums<typename Real<F32>::T> &ps)
-{
-    using R = typename Real<F32>::T;
-    const int n = op.n, d = op.d, M = op.n_assets;
-    const R drift = F32 ? (R)op.ydrift_1_f : (R)op.ydrift_1;
-    const R bc = F32 ? (R)op.b_common_f : (R)op.b_common;
-    const R bi = F32 ? (R)op.b_idio_f : (R)op.b_idio;
-    auto normal = [&](int s) -> R {
-        const uint32_t y = U.rec(ubits_at(U, lds_lane[lane_row<F32>(s) + lane], s), s + 1, lane);
-        if constexpr (F32) return ninv_table_f32(y);
-        else return (R)ninv_f64(y);
-    };
-    R I[QCPW_MAX_ASSETS];
-#pragma unroll
-    for (int i = 0; i < QCPW_MAX_ASSETS; ++i) I[i] = R(0);
-    ps.A1 = R(0);   // no date with a known value: every (asset, date) pair is summed below
-    R Cm = R(0);
-    for (int m = 0; m < d; ++m) {
-        if (m >= 1) Cm = Cm + fma(bc, normal(m - 1), drift);
-#pragma unroll
-        for (int i = 0; i < QCPW_MAX_ASSETS; ++i) {
-            if (i < M) {
-                I[i] = fma(bi, normal(n + i * d + m), I[i]);
-                consume<R, QCPW_STAT_AVG>(ps, Cm + I[i], (R)m);
-            }
-        }
-    }
-}
-
-// One wave's 64 paths from the terminal point (bridge) or the first step
-// (standard) to the last date, accumulated into ps.
-template <bool F32, int PATHK, int MODE, class UP>
-__device__ inline void walk_path(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
-                                 typename Real<F32>::T *stk, int lane,
-                                 const UP &U, PathSums<typename Real<F32>::T> &ps, int fixed_bridges)
-{
-    if constexpr (PATHK == QCPW_PATH_BB) {
-        if constexpr (F32) {
-            if (fixed_bridges && bridge_fixed_any<MODE>(op, lds_lane, lane, U, ps)) return;
-        }
-        run_bridge_wave<F32, MODE>(ld, op, lds_lane, stk, lane, U, ps);
-    } else {
-        if constexpr (MODE == QCPW_STAT_AVG) {
-            if (op.n_assets > 0) {
-                run_basket_wave<F32>(op, lds_lane, lane, U, ps);
-                return;
-            }
-        }
-        run_standard_wave<F32, MODE>(op, lds_lane, lane, U, ps);
-    }
-}
-
-// U_j(base) (and its seed) for the dimensions this lane holds: steps s = lane + 64 q.
-template <int PATHK>
-__device__ inline int step_dim(const LaunchDesc &ld, const OptDev &op, int s)
-{
-    return (PATHK == QCPW_PATH_BB) ? ld.plan[op.plan_off + s].dim : s + 1;
-}
-
-template <int PATHK, class UP>
-__device__ inline void init_uniform_part(const LaunchDesc &ld, const OptDev &op, int shift, int lane,
-                                         uint64_t base, UP &U)
-{
-    const uint64_t g = (base ^ (base >> 1)) >> 5;   // gray(base) has no bits below 5
-#pragma unroll
-    for (int q = 0; q < QCPW_UQ; ++q) {
-        const int s = lane + 64 * q;
-        int dim;
-        uint32_t u = 0, key = 0;
-        if (s < op.ndims) {
-            dim = step_dim<PATHK>(ld, op, s);
-            key = digital_shift(op.seed, shift, dim);
-            const uint32_t *v = ld.dir + (size_t)dim * 32;
-            uint64_t gg = g;
-            for (int b = 5; gg != 0; ++b, gg >>= 1)
-                if (gg & 1) u ^= v[b];
-        }
-        if constexpr (UP::OWEN) {
-            U.U[q] = u;
-            U.Sd[q] = key;
-        } else {
-            U.U[q] = u ^ key;
-        }
-    }
-}
-
-// base -> base + 64: gray changes in bits 5 and 6 + ctz(base/64 + 1).
-template <int PATHK, class UP>
-__device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op, int lane, uint64_t base,
-                                         UP &U)
-{
-    const int c = __builtin_ctzll((base >> 6) + 1);
-#pragma unroll
-    for (int q = 0; q < QCPW_UQ; ++q) {
-        const int s = lane + 64 * q;
-        if (s < op.ndims) {
-            const uint32_t *v = ld.dir + (size_t)step_dim<PATHK>(ld, op, s) * 32;
-            U.U[q] ^= v[5] ^ v[6 + c];
-        }
-    }
-}
-
-// Every wave pulls its own work units (option, replication, range of
-// unit_pts consecutive points): no workgroup barrier after start-up, and the
-// order of every sum depends on the unit alone.  The workgroup only shares
-// the LDS tables (inverse-normal cells, lane rows of all dimensions the
-// launch needs), loaded once.
-// The FP32 kernel is bound by latency as much as by issue (every step waits
-// on scalar plan loads and two dependent LDS reads), so it is held to 80
-// VGPRs: six waves per SIMD instead of four (measured 1.3x faster); with
-// 512-thread workgroups the LDS of three workgroups fits a CU at d = 64.
-// PROBE instances (coordinate checks only) walk every option as an average
-// and also store the coordinates each 64-point batch consumes at
-// probe[((unit * unit_pts / 64 + batch) * ndims + dim - 1) * 64 + lane].
-template <bool F32, int PATHK, bool OWEN, bool PROBE>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 1))) void paths_kernel(const OptDev *__restrict__ opts,
-                                                     const int64_t *__restrict__ unit_prefix,
-                                                     const PlanStep *__restrict__ plan_all,
-                                                     const PlanStep64 *__restrict__ plan64_all,
-                                                     const uint32_t *__restrict__ dir,
-                                                     const uint32_t *__restrict__ lane_tab,
-                                                     const float4 *__restrict__ ninv_tab,   // [2][256] cells
-                                                     double *__restrict__ partials,
-                                                     unsigned long long *__restrict__ counter,
-                                                     int n_opts, int max_n, int stack_depth, int stk_off,
-                                                     long long total_units, int fixed_bridges,
-                                                     uint32_t *__restrict__ probe)
-{
-    LaunchDesc ld;
-    ld.opts = opts;
-    ld.unit_prefix = unit_prefix;
-    ld.n_opts = n_opts;
-    ld.max_n = max_n;
-    ld.total_units = total_units;
-    ld.plan = plan_all;
-    ld.plan64 = plan64_all;
-    ld.dir = dir;
-    ld.lane = lane_tab;
-    ld.partials = partials;
-    ld.counter = counter;
-    using R = typename Real<F32>::T;
-    // all LDS is dynamic and starts at address 0, so a cell's address is its
-    // byte offset: FP32 keeps the cells of both halves, lane rows
-    // (qcpw_row_word) and stacks; FP64 the rows from 0 and the stacks
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int bd = blockDim.x;
-    uint32_t *lds_lane = (uint32_t *)smem;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    // bridge stack: [wave][stack_depth][64]; this lane's column
-    R *stk = (R *)(smem + stk_off) + (size_t)(tid >> 6) * stack_depth * 64 + lane;
-    if (F32) {
-        float4 *cells = (float4 *)smem;
-        for (int i = tid; i < 2 * QCPW_NINV_TAB_CELLS; i += bd)
-            cells[(i < QCPW_NINV_TAB_CELLS ? 0 : QCPW_LDS_TAB_HI / 16 - QCPW_NINV_TAB_CELLS) + i] = ninv_tab[i];
-    }
-    for (int i = tid; i < max_n * 64; i += bd) lds_lane[lane_row<F32>(i >> 6) + (i & 63)] = lane_tab[64 + i];
-    __syncthreads();
-
-    // Units are dealt out by QCPW_QUEUES counters, queue q holding units
-    // q, q + QCPW_QUEUES, ...  All waves of the chip would otherwise take
-    // turns on one atomic (served one after another in memory, of the order
-    // of 10 ns each), which bounds launches of many cheap units.  Workgroups
-    // go to the XCDs in turn, so a wave starts on the queue of its
-    // workgroup's XCD and, once that queue is empty, helps the others in
-    // order; it leaves after finding all of them empty.
-    int o = 0;
-    int q = blockIdx.x & (QCPW_QUEUES - 1);
-    int empty = 0;
-    for (;;) {
-        unsigned long long u = 0;
-        if (lane == 0) u = atomicAdd(counter + q * QCPW_QUEUE_STRIDE, 1ull);
-        const long long j = ((long long)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
-                            (unsigned)__builtin_amdgcn_readfirstlane((int)u);
-        const long long unit = j * QCPW_QUEUES + q;
-        if (unit >= total_units) {
-            if (++empty == QCPW_QUEUES) break;
-            q = (q + 1) & (QCPW_QUEUES - 1);
-            continue;
-        }
-
-        // option of this unit (units are consumed in increasing order, so the
-        // previous option is the usual answer)
-        if (!(unit_prefix[o] <= unit && unit < unit_prefix[o + 1])) {
-            int lo = 0, hi = n_opts - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (unit_prefix[mid] <= unit) lo = mid; else hi = mid - 1;
-            }
-            o = lo;
-        }
-        const OptDev &op = opts[o];
-        const int64_t rem = unit - op.unit0;
-        const int shift = (int)(rem / op.chunks);
-        const int64_t chunk = rem - (int64_t)shift * op.chunks;
-
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
-        double c[4] = {0.0, 0.0, 0.0, 0.0};
-        const int64_t k_end = op.k_begin + op.n_points;
-        const int64_t start = op.k_begin + chunk * op.unit_pts;
-        const int64_t end = min(start + (int64_t)op.unit_pts, k_end);
-        const int mode = qcpw_stat_of(op.type);
-        UParts<OWEN, PROBE> U;
-        init_uniform_part<PATHK>(ld, op, shift, lane, (uint64_t)start, U);
-        for (int64_t base = start; base < end; base += 64) {
-            const bool valid = base + lane < k_end;
-            double F[4] = {0.0, 0.0, 0.0, 0.0};
-            PathSums<R> ps;
-            init_sums(ps);
-            if constexpr (PROBE)
-                U.pr = probe + ((unit * (op.unit_pts / 64) + (base - start) / 64) * op.ndims) * 64;
-            if (op.ndims > 0) {
-                switch (PROBE ? QCPW_STAT_AVG : mode) {
-                case QCPW_STAT_MAX:
-                    walk_path<F32, PATHK, QCPW_STAT_MAX>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
-                    break;
-                case QCPW_STAT_GEO:
-                    walk_path<F32, PATHK, QCPW_STAT_GEO>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
-                    break;
-                case QCPW_STAT_MIN:
-                    walk_path<F32, PATHK, QCPW_STAT_MIN>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
-                    break;
-                default:
-                    walk_path<F32, PATHK, QCPW_STAT_AVG>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
-                }
-            }
-            if (valid) {
-                path_tail<R>(op, ps, mode, F);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc_add(s[i], c[i], F[i]);
-            }
-            if (base + 64 < end) step_uniform_part<PATHK>(ld, op, lane, (uint64_t)base, U);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            wave_reduce(s[i], c[i]);
-            if (lane == 0) {
-                partials[unit * 8 + i] = s[i];
-                partials[unit * 8 + 4 + i] = c[i];
-            }
-        }
-    }
-}
-
 
 // One block per option: replication estimates C_l (chunk partials added in
 // chunk order), then the mean over replications and its standard error.
@@ -680,10 +162,11 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
                 return fail(QCPW_EDIMS, "option " + std::to_string(i) + ": (d - 1) + n_assets d exceeds " +
                                             std::to_string(QCPW_MAX_BASKET_DIMS));
         }
-        if (path == QCPW_PATH_PCA_FULL && sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL)
+        if (path == QCPW_PATH_PCA_FULL && sp.type != QCPW_ARITH_ASIAN_CALL && sp.type != QCPW_BINARY_ASIAN_CALL &&
+            sp.type != QCPW_LOOKBACK_FIXED_CALL)
             return fail(QCPW_EINVAL, "option " + std::to_string(i) +
-                                         ": conditioning on the first principal component covers "
-                                         "arithmetic and binary Asian calls only");
+                                         ": conditioning on the first principal component covers the "
+                                         "arithmetic and binary Asian and the lookback calls");
         if (di < 1) return fail(QCPW_EINVAL, "option " + std::to_string(i) + ": d must be >= 1");
         if (di > dmax)
             return fail(QCPW_EDIMS, "option " + std::to_string(i) + ": d = " + std::to_string(di) +
@@ -708,6 +191,17 @@ static bool fixed_bridges_on()
     return on;
 }
 
+// Split bridge (FP32 kernel, n >= QCPW_SUB_MIN_LEN): on unless
+// QCPW_SPLIT_BRIDGE=0 (then the plan walker takes those options).
+static bool split_bridge_on()
+{
+    static const bool on = [] {
+        const char *e = getenv("QCPW_SPLIT_BRIDGE");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
                         int64_t n_points, int32_t n_shifts, int32_t path, int32_t precision,
                         int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp, const int64_t *k_begin,
@@ -715,7 +209,7 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
 {
     {
         qcpw_status st = validate_call(specs, n_opts, d, n_points, n_shifts, path, precision, pca_gemm,
-                                       block_threads);
+                                       block_threads < 0 ? 0 : block_threads);
         if (st != QCPW_OK) return st;
     }
     if (owen && path != QCPW_PATH_BB && path != QCPW_PATH_STANDARD)
@@ -798,25 +292,70 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         }
         cost[i] = (double)std::max(op.ndims, 1) * (double)op.chunks;
         lp.max_n = std::max(lp.max_n, op.ndims);
-        // options walked by a compile-time bridge need no LDS stack
-        const bool fixed = precision == QCPW_FP32_MIXED && fixed_bridges_on() && qcpw_has_fixed_bridge(op.n);
-        if (path == QCPW_PATH_BB && op.n >= 1 && !fixed)
+        // options walked by a compile-time bridge or the split bridge need no LDS stack
+        const bool f32 = precision == QCPW_FP32_MIXED;
+        const bool fixed = f32 && fixed_bridges_on() && qcpw_has_fixed_bridge(op.n);
+        op.split = (path == QCPW_PATH_BB && f32 && !fixed && split_bridge_on() && ctx->tab.split_slots[op.n] > 0) ? 1 : 0;
+        op.n_slots = op.split ? ctx->tab.split_slots[op.n] : op.ndims;
+        if (path == QCPW_PATH_BB && op.n >= 1 && !fixed && !op.split)
             lp.stack_depth = std::max(lp.stack_depth, ctx->tab.depth[op.n]);
     }
+    // the lane rows of more than QCPW_WIDE_MIN_N dimensions leave room for one
+    // 1024-thread workgroup per CU: 4 waves per SIMD, so 128 VGPRs cost nothing
+    lp.wide = precision == QCPW_FP32_MIXED && lp.max_n > QCPW_WIDE_MIN_N;
+    // Matrix-core PCA: options whose paths are identical -- same n, seed and
+    // point range, same z scale and drift, same path statistic (they differ
+    // in strike or payoff) -- share one product and one epilogue per tile;
+    // only the FP64 tail runs per option.  They are sorted next to each other
+    // and the first (leader) carries the group.
+    const bool grouping = path == QCPW_PATH_PCA && precision == QCPW_FP32_MIXED;
+    auto same_paths = [&](const OptDev &a, const OptDev &b) {
+        return a.n == b.n && a.seed == b.seed && a.n_points == b.n_points && a.k_begin == b.k_begin &&
+               a.zs_t == b.zs_t && a.ydrift_1_f == b.ydrift_1_f && qcpw_stat_of(a.type) == qcpw_stat_of(b.type);
+    };
     // most expensive units first (longest-processing-time order)
     std::vector<int32_t> order(n_opts);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return opts[a].ndims > opts[b].ndims; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const OptDev &x = opts[a], &y = opts[b];
+        if (x.ndims != y.ndims || !grouping) return x.ndims > y.ndims;
+        if (x.seed != y.seed) return x.seed < y.seed;
+        if (x.n_points != y.n_points) return x.n_points < y.n_points;
+        if (x.k_begin != y.k_begin) return x.k_begin < y.k_begin;
+        if (x.zs_t != y.zs_t) return x.zs_t < y.zs_t;
+        if (x.ydrift_1_f != y.ydrift_1_f) return x.ydrift_1_f < y.ydrift_1_f;
+        return qcpw_stat_of(x.type) < qcpw_stat_of(y.type);
+    });
     lp.opts.resize(n_opts);
     lp.unit_prefix.assign(n_opts + 1, 0);
+    std::vector<int> members;
+    int leader = -1;
     for (int i = 0; i < n_opts; ++i) {
         lp.opts[i] = opts[order[i]];
-        lp.opts[i].unit0 = lp.unit_prefix[i];
-        lp.unit_prefix[i + 1] = lp.unit_prefix[i] + (int64_t)lp.opts[i].chunks * n_shifts;
+        OptDev &op = lp.opts[i];
+        const int64_t units = (int64_t)op.chunks * n_shifts;
+        if (grouping && leader >= 0 && lp.opts[leader].grp < QCPW_PCA_MAX_GROUP && same_paths(lp.opts[leader], op)) {
+            op.grp = 0;   // a member: no units of its own to deal
+            ++lp.opts[leader].grp;
+            lp.unit_prefix[i + 1] = lp.unit_prefix[i];
+            members.push_back(i);
+            continue;
+        }
+        leader = i;
+        op.grp = 1;
+        op.unit0 = lp.unit_prefix[i];
+        lp.unit_prefix[i + 1] = lp.unit_prefix[i] + units;
     }
     lp.order = order;
     lp.total_units = lp.unit_prefix[n_opts];
-    lp.block_threads = block_threads ? block_threads : autotune_block_threads(ctx, lp);
+    // members' partials follow the dealt units
+    for (int i : members) {
+        lp.opts[i].unit0 = lp.total_units + lp.member_units;
+        lp.member_units += (int64_t)lp.opts[i].chunks * n_shifts;
+    }
+    lp.block_threads = block_threads > 0 ? block_threads
+                       : block_threads < 0 ? known_block_threads(ctx, lp)
+                                           : autotune_block_threads(ctx, lp);
     if (path == QCPW_PATH_PCA || path == QCPW_PATH_PCA_FULL) {
         const bool full = path == QCPW_PATH_PCA_FULL;
         lp.pca.resize(n_opts, nullptr);
@@ -859,7 +398,7 @@ static WsLayout ws_layout(const LaunchPlan &lp)
     w.counter = align_up(w.prefix + (n + 1) * sizeof(int64_t), 256);
     w.upload = w.counter + QCPW_QUEUES * QCPW_QUEUE_STRIDE * sizeof(unsigned long long);
     w.partials = align_up(w.upload, 256);
-    w.per_shift = align_up(w.partials + (size_t)lp.total_units * 8 * sizeof(double), 256);
+    w.per_shift = align_up(w.partials + (size_t)(lp.total_units + lp.member_units) * 8 * sizeof(double), 256);
     w.scratch = align_up(w.per_shift + n * (size_t)lp.n_shifts * 4 * sizeof(double), 256);
     w.total = align_up(w.scratch + (size_t)lp.full_blocks * 64 * QCPW_MAX_D_PCA_FULL * sizeof(double), 256);
     return w;
@@ -920,26 +459,16 @@ qcpw_status check_lds_at_zero(const void *fn)
     return QCPW_OK;
 }
 
-template <bool F32, int PATHK, bool OWEN, bool PROBE>
-static const void *paths_fn()
-{
-    return reinterpret_cast<const void *>(&paths_kernel<F32, PATHK, OWEN, PROBE>);
-}
-
-template <bool OWEN, bool PROBE>
-static const void *select_paths_kernel_r(const LaunchPlan &lp)
-{
-    const bool f32 = lp.precision == QCPW_FP32_MIXED;
-    if (lp.path == QCPW_PATH_STANDARD)
-        return f32 ? paths_fn<true, QCPW_PATH_STANDARD, OWEN, PROBE>()
-                   : paths_fn<false, QCPW_PATH_STANDARD, OWEN, PROBE>();
-    return f32 ? paths_fn<true, QCPW_PATH_BB, OWEN, PROBE>() : paths_fn<false, QCPW_PATH_BB, OWEN, PROBE>();
-}
-
+// The kernel instance of a launch: precision, construction, randomisation,
+// coordinate recording (probe instances are always wide) and register
+// budget.
 static const void *select_paths_kernel(const LaunchPlan &lp)
 {
-    if (lp.probe) return lp.owen ? select_paths_kernel_r<true, true>(lp) : select_paths_kernel_r<false, true>(lp);
-    return lp.owen ? select_paths_kernel_r<true, false>(lp) : select_paths_kernel_r<false, false>(lp);
+    const bool f32 = lp.precision == QCPW_FP32_MIXED;
+    if (!f32) return paths_fn_f64(lp.path, lp.owen, lp.probe != nullptr);
+    if (lp.probe) return paths_fn_f32_probe(lp.path, lp.owen);
+    if (lp.path == QCPW_PATH_STANDARD) return paths_fn_f32_std(lp.owen, lp.wide);
+    return lp.owen ? paths_fn_f32_bb_owen(lp.wide) : paths_fn_f32_bb(lp.wide);
 }
 
 // Resident waves per CU of the fused kernel at workgroup size bd (0 if it
@@ -1042,6 +571,30 @@ int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
     return best;
 }
 
+// The workgroup size the autotuner has chosen for this launch's key, or --
+// without running its probes, which allocate -- 512 threads (256 when 512
+// do not fit the LDS).
+int known_block_threads(Context *ctx, const LaunchPlan &lp)
+{
+    if (lp.path == QCPW_PATH_PCA || lp.path == QCPW_PATH_PCA_FULL) return 256;
+    const int key = ((lp.path * 2 + lp.precision) * 2 + (lp.owen ? 1 : 0)) * 64 + (lp.max_n + 31) / 32;
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second;
+    return paths_lds_fits(lp, 512) ? 512 : 256;
+}
+
+void pretune_block_threads(Context *ctx, int path, int precision, bool owen)
+{
+    for (int b = 0; 32 * b <= QCPW_MAX_N; ++b) {
+        LaunchPlan lp;
+        lp.path = path;
+        lp.precision = precision;
+        lp.owen = owen;
+        lp.max_n = 32 * b;
+        (void)autotune_block_threads(ctx, lp);
+    }
+}
+
 qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, const LaunchDesc &ld,
                         const OptDev *d_opts);
 
@@ -1119,6 +672,8 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         const int64_t *a_prefix = ld.unit_prefix;
         const PlanStep *a_plan = ld.plan;
         const PlanStep64 *a_plan64 = ld.plan64;
+        const uint32_t *a_sev = ctx->tab.split_ev;
+        const uint16_t *a_sdim = ctx->tab.split_dim;
         const uint32_t *a_dir = ld.dir, *a_lane = ld.lane;
         const float4 *a_tab = ctx->tab.ninv_tab;
         double *a_part = ld.partials;
@@ -1127,8 +682,8 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         long long a_total = ld.total_units;
         int a_fixed_arg = fixed_bridges_on() ? 1 : 0;
         uint32_t *a_probe = lp.probe;
-        void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_dir, &a_lane, &a_tab, &a_part, &a_ctr,
-                        &a_nopts, &a_maxn, &a_depth, &a_stk_off, &a_total, &a_fixed_arg, &a_probe};
+        void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_sev, &a_sdim, &a_dir, &a_lane, &a_tab, &a_part,
+                        &a_ctr, &a_nopts, &a_maxn, &a_depth, &a_stk_off, &a_total, &a_fixed_arg, &a_probe};
         if (t0) QCPW_HIP(hipEventRecord(t0, stream));
         QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
         if (t1) QCPW_HIP(hipEventRecord(t1, stream));

@@ -190,9 +190,112 @@ __device__ inline void tile_tail(const OptDev &op, const PcaSums<R> *red, int la
 // (to the right of the root), so the iterates decrease to the root.  Price,
 // delta, vega and gamma then follow in closed form (arithmetic: the terms in
 // d psi cancel at the root; binary: through d psi = -dF / F').
+// P(lo < X < hi), X ~ N(0, 1), lo <= hi (hi may be +inf): from the upper
+// tail when the interval lies right of 0, so far-out intervals keep their
+// relative accuracy.
+__device__ inline double norm_interval(double lo, double hi)
+{
+    if (lo >= 0.0) return 0.5 * erfc(lo * M_SQRT1_2) - (isinf(hi) ? 0.0 : 0.5 * erfc(hi * M_SQRT1_2));
+    return (isinf(hi) ? 1.0 : 0.5 * erfc(-hi * M_SQRT1_2)) - 0.5 * erfc(-lo * M_SQRT1_2);
+}
+
+// Lookback (call on the discrete maximum) conditioned on the first principal
+// component: ln S(t_j) = alpha_j + beta_j x are d increasing lines, their
+// upper envelope M(x) is increasing, convex and piecewise linear, and the
+// payoff is positive for x > psi = min_j (ln K - alpha_j) / beta_j.  The
+// envelope is walked from psi (the line crossing ln K there, the steeper one
+// on a tie) to +inf, each next line being the steeper one that overtakes the
+// current one first; over a segment [a, b) of line j, with
+// E_j = exp(alpha_j + beta_j^2 / 2) and dP = P(a - beta_j < X < b - beta_j),
+//   G     += D [E_j dP - K P(a < X < b)],   delta += D E_j dP / S0,
+//   vega  += D E_j [(c_j - sigma t_j) dP + a_j (beta_j dP + phi(a - beta_j) - phi(b - beta_j))],
+// and gamma = D K phi(psi) / (S0^2 beta*) with beta* the slope on top at psi.
+// The PARTS threads of a point scan their dates j = part (mod PARTS) and
+// agree on each candidate through the same fixed butterfly.
+template <int PARTS, typename YF>
+__device__ inline void full_lookback_tail(const OptDev &op, YF y, int part, double F[4])
+{
+    constexpr double LN2 = 0.69314718055994530942;
+    const int d = op.n + 1;
+    const double sig = 1.0 / op.inv_sigma;
+    const double sdt = op.zscale * LN2;     // sigma sqrt(dt)
+    const double wdt = op.ydrift_1 * LN2;   // omega dt
+    const double dt = op.sqrt_t1 * op.sqrt_t1;
+    const double lnS0 = log(op.S0), K = op.K, lnK = log(op.K);
+    const double *a1 = op.pca_a1;
+    auto alpha = [&](int j) { return lnS0 + wdt * (j + 1) + LN2 * y(j); };
+    auto beta = [&](int j) { return sdt * a1[j]; };
+    // smallest x; equal x: steeper line; the same bits in all PARTS threads
+    auto pick = [](double &x, int &j, double &b) {
+#pragma unroll
+        for (int m = 1; m < PARTS; m <<= 1) {
+            const double xo = __shfl_xor(x, m, 64), bo = __shfl_xor(b, m, 64);
+            const int jo = __shfl_xor(j, m, 64);
+            if (xo < x || (xo == x && bo > b) || (xo == x && bo == b && jo < j)) {
+                x = xo;
+                b = bo;
+                j = jo;
+            }
+        }
+    };
+    double psi = INFINITY, bs = 0.0;
+    int js = d;
+    for (int j = part; j < d; j += PARTS) {
+        const double b = beta(j), xj = (lnK - alpha(j)) / b;
+        if (xj < psi || (xj == psi && b > bs)) {
+            psi = xj;
+            bs = b;
+            js = j;
+        }
+    }
+    pick(psi, js, bs);
+    const double bstar = bs;
+    double G = 0.0, dl = 0.0, vg = 0.0;
+    double x0 = psi;
+    int j = js;
+    for (int seg = 0; seg < d; ++seg) {
+        const double aj = alpha(j), bj = bs;
+        double x1 = INFINITY, bn = 0.0;
+        int jn = d;
+        for (int i = part; i < d; i += PARTS) {
+            const double bi = beta(i);
+            if (!(bi > bj)) continue;
+            const double xi = (aj - alpha(i)) / (bi - bj);
+            if (xi < x1 || (xi == x1 && bi > bn)) {
+                x1 = xi;
+                bn = bi;
+                jn = i;
+            }
+        }
+        pick(x1, jn, bn);
+        if (x1 < x0) x1 = x0;   // a line crossing at x0 itself (rounding)
+        const double E = exp(aj + 0.5 * bj * bj);
+        const double dP = norm_interval(x0 - bj, x1 - bj);
+        const double fa = 0.39894228040143267794 * exp(-0.5 * (x0 - bj) * (x0 - bj));
+        const double fb = isinf(x1) ? 0.0 : 0.39894228040143267794 * exp(-0.5 * (x1 - bj) * (x1 - bj));
+        const double das = LN2 * y(j) / sig - sig * dt * (j + 1);   // c_j - sigma t_j
+        G += E * dP - K * norm_interval(x0, x1);
+        dl += E * dP;
+        vg += E * (das * dP + (bj / sig) * (bj * dP + fa - fb));
+        if (jn >= d) break;
+        j = jn;
+        bs = bn;
+        x0 = x1;
+    }
+    const double D = op.D, S0 = op.S0;
+    F[0] = D * G;
+    F[1] = D * dl / S0;
+    F[2] = D * vg;
+    F[3] = D * K * 0.39894228040143267794 * exp(-0.5 * psi * psi) / (S0 * S0 * bstar);
+}
+
 template <int PARTS, typename YF>
 __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double F[4])
 {
+    if (op.type == QCPW_LOOKBACK_FIXED_CALL) {
+        full_lookback_tail<PARTS>(op, y, part, F);
+        return;
+    }
     constexpr double LN2 = 0.69314718055994530942;
     const int d = op.n + 1;
     const double sig = 1.0 / op.inv_sigma;
@@ -364,7 +467,10 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
     unsigned short *Zl = Zh + (size_t)TP * zstride;
     PcaSums<float> *red = (PcaSums<float> *)(smem + QCPW_LDS_GAP_BEGIN);   // [PCA_AS_WAVES][TP]
     long long *s_unit = (long long *)(smem + QCPW_LDS_GAP_BEGIN + PCA_AS_WAVES * TP * sizeof(PcaSums<float>));
-    static_assert(QCPW_LDS_GAP_BEGIN + PCA_AS_WAVES * TP * sizeof(PcaSums<float>) + 8 <= QCPW_LDS_TAB_HI, "gap");
+    // compensated sums of the other members of a group (wave 0): [member - 1][8][TP]
+    constexpr size_t MACC_OFF = QCPW_LDS_GAP_BEGIN + PCA_AS_WAVES * TP * sizeof(PcaSums<float>) + 64;
+    double *macc = (double *)(smem + MACC_OFF);
+    static_assert(MACC_OFF + (QCPW_PCA_MAX_GROUP - 1) * 8 * TP * sizeof(double) <= QCPW_LDS_TAB_HI, "gap");
     {
         float4 *cells = (float4 *)smem;
         for (int i = tid; i < 2 * QCPW_NINV_TAB_CELLS; i += blockDim.x)
@@ -432,6 +538,10 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
         if (wave > 0 && lane < PD && myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
         const int jcount = wave > 0 ? max(0, min(PD, n - PD * pw)) : 0;
         double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
+        // options sharing these paths (same product and epilogue, FP64 tail each)
+        const int grp = FULL ? 1 : op.grp;
+        if (wave == 0)
+            for (int i = 0; i < (grp - 1) * 8; ++i) macc[i * TP + lane] = 0.0;
         // ---- prologue: z' = Phi^{-1}(u) * sigma sqrt(dt) log2(e) for the 64 points of the
         // tile at `base` x this wave's dimensions, then the Gray-code step to the next tile
         const int jc = __builtin_amdgcn_readfirstlane(jcount);
@@ -591,9 +701,24 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
             if (khalf) red[wave * TP + lane] = ps1;
             else red[wave * TP + lane] = ps0;
             __syncthreads();
-            if (wave == 0) {   // this tile's tail, while the other waves fill Z with the next tile
+            if (wave == 0) {   // this tile's tails, while the other waves fill Z with the next tile
                 const int waves_pt[PCA_AS_WAVES] = {0, 1, 2, 3, 4, 5, 6, 7};
                 tile_tail<float>(op, red, lane, base + lane < t1, PCA_AS_WAVES, waves_pt, s, c);
+                for (int mi = 1; mi < grp; ++mi) {
+                    double sm[4], cm[4];
+                    double *acc = macc + (size_t)(mi - 1) * 8 * TP + lane;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        sm[i] = acc[i * TP];
+                        cm[i] = acc[(4 + i) * TP];
+                    }
+                    tile_tail<float>(opts[o + mi], red, lane, base + lane < t1, PCA_AS_WAVES, waves_pt, sm, cm);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        acc[i * TP] = sm[i];
+                        acc[(4 + i) * TP] = cm[i];
+                    }
+                }
             } else if (base + TP < t1) {
                 prologue(base + TP);
             }
@@ -606,6 +731,20 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
                 if (lane == 0) {
                     partials[unit * 8 + i] = s[i];
                     partials[unit * 8 + 4 + i] = c[i];
+                }
+            }
+            // the members' partials at the same offset in their own units
+            for (int mi = 1; mi < grp; ++mi) {
+                const double *acc = macc + (size_t)(mi - 1) * 8 * TP + lane;
+                const int64_t mu = opts[o + mi].unit0 + rem;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    double sm = acc[i * TP], cm = acc[(4 + i) * TP];
+                    wave_reduce(sm, cm);
+                    if (lane == 0) {
+                        partials[mu * 8 + i] = sm;
+                        partials[mu * 8 + 4 + i] = cm;
+                    }
                 }
             }
         }

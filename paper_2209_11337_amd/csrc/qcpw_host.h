@@ -18,6 +18,8 @@ namespace qcpw {
 void build_direction_numbers(std::vector<uint32_t> &dir);
 void build_lane_table(const std::vector<uint32_t> &dir, std::vector<uint32_t> &lane);
 int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep64> &steps64);
+int build_split_plan(int n, std::vector<uint32_t> &events, std::vector<uint16_t> &slot_dim);
+void split_plan_factor(int n, double dt, const std::vector<uint32_t> &events, std::vector<double> &A);
 void build_pca_factor(int n, double dt, std::vector<double> &A);
 void build_factor(int path, int n, double dt, std::vector<double> &A);
 
@@ -43,13 +45,18 @@ struct DeviceTables {
     std::vector<int32_t> plan_off;   // [QCPW_MAX_N + 1]
     std::vector<int32_t> depth;      // [QCPW_MAX_N + 1] bridge stack depth per n
     int max_stack = 0;
+    uint32_t *split_ev = nullptr;    // split-bridge events [QCPW_MAX_N + 1][QCPW_SPLIT_EVENTS][QCPW_EV_WORDS]
+    uint16_t *split_dim = nullptr;   // slot dimensions [QCPW_MAX_N + 1][QCPW_SPLIT_SLOTS]
+    std::vector<int32_t> split_slots;   // [QCPW_MAX_N + 1] slots used, 0: no split bridge for n
 };
 
 // Grow-only device workspace.
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
-    qcpw_status ensure(size_t need);
+    // grow to at least need bytes (25 % spare, never beyond cap); keeps the
+    // buffer when it is large enough
+    qcpw_status ensure(size_t need, size_t cap = SIZE_MAX);
 };
 
 struct Context {
@@ -98,9 +105,11 @@ struct LaunchPlan {
     int pca_gemm = 0;
     int n_shifts = 0;
     int block_threads = 0;
-    int64_t total_units = 0;
+    int64_t total_units = 0;           // work units dealt by the queues
+    int64_t member_units = 0;          // further units whose partials a group leader's units write
     int64_t full_blocks = 0;           // PCA_FULL in FP64: workgroups with a global scratch tile
     bool owen = false;                 // nested scrambling instead of the digital shift
+    bool wide = false;                 // FP32 kernel instance with 128 VGPRs and 8 slot registers
     uint32_t *probe = nullptr;         // device buffer: run the coordinate-recording kernel instance
     std::vector<const Context::Pca *> pca;   // per sorted option (PCA and PCA_FULL)
 };
@@ -143,6 +152,18 @@ qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index
                                 bool owen = false);
 
 int autotune_block_threads(Context *ctx, const LaunchPlan &lp);
+// The autotuner's choice if it has one for lp's key, else a default; never
+// launches or allocates.  plan_launch takes block_threads < 0 as this.
+int known_block_threads(Context *ctx, const LaunchPlan &lp);
+// Instances of the fused per-path kernel (paths_*.hip), as kernel pointers.
+const void *paths_fn_f32_bb(bool wide);
+const void *paths_fn_f32_bb_owen(bool wide);
+const void *paths_fn_f32_std(bool owen, bool wide);
+const void *paths_fn_f32_probe(int path, bool owen);
+const void *paths_fn_f64(int path, bool owen, bool probe);
+// Runs the autotuner for every lane-table bucket of (path, precision,
+// scrambling) ahead of use; caller holds ctx->mu.
+void pretune_block_threads(Context *ctx, int path, int precision, bool owen);
 
 // Fails unless kernel `fn` has no static LDS (its dynamic LDS starts at 0).
 qcpw_status check_lds_at_zero(const void *fn);

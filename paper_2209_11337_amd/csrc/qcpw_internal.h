@@ -61,6 +61,7 @@ static inline int64_t qcpw_unit_points(int64_t n_points)
 static inline bool qcpw_block_threads_ok(int v) { return v == 0 || (v >= 64 && v <= 1024 && v % 64 == 0); }
 #define QCPW_STACK_MAX 12        // bridge stack depth bound (ceil log2 QCPW_MAX_N + 2)
 #define QCPW_PCA_NPAD 256        // padded factor size of the matrix-core PCA kernel
+#define QCPW_PCA_MAX_GROUP 4     // options sharing one product and epilogue in the matrix-core PCA kernel
 #define QCPW_FIXED_MAX_N 127     // largest n with a compile-time bridge
 
 // n (= d - 1) that the FP32 kernel walks with a compile-time bridge; the
@@ -158,6 +159,56 @@ struct PlanStep64 {
     double wl, wr, sd, mf;
 };
 
+// ---- split bridge (FP32 kernel, any n >= QCPW_SUB_MIN_LEN) ---------------
+// At level k of the bridge (k = 0 for the interval (0, n) itself) every
+// interval has length floor(n / 2^k) or ceil(n / 2^k).  With k the smallest
+// level whose lengths are at most QCPW_SUB_MAX_LEN, they lie in
+// [QCPW_SUB_MIN_LEN, QCPW_SUB_MAX_LEN] (n >= QCPW_SUB_MIN_LEN), and each such
+// interval is walked by a compile-time subtree of its length: its midpoints
+// depth first with literal weights and pending right end points in
+// registers.  Only the 2^k - 1 midpoints above level k ("top nodes") and
+// every node's Sobol dimension come from the plan, as a list of events in
+// depth-first order: the terminal point, then top midpoints and subtrees.
+// The wave-uniform parts are laid out in "slots" (slot s in register s / 64,
+// lane s % 64): the terminal and the top nodes first, then each subtree's
+// nodes contiguous and inside one register, so that one row broadcast per
+// node serves them.
+#define QCPW_SUB_MIN_LEN 12
+#define QCPW_SUB_MAX_LEN 24
+#define QCPW_SPLIT_EVENTS 32     // 1 + (2^k - 1) + 2^k, k <= 4
+#define QCPW_SPLIT_SLOTS 512     // 8 registers of 64 lanes
+#define QCPW_EV_WORDS 16         // one 64-byte event, one scalar load
+#define QCPW_WIDE_MIN_N 288      // FP32 launches with more lane rows use the 128-VGPR kernel instances
+
+// Event header (word 0): kind, subtree length, slot register and lane.
+enum { QCPW_EV_TERMINAL = 0, QCPW_EV_TOP = 1, QCPW_EV_SUB = 2 };
+__host__ __device__ constexpr uint32_t qcpw_ev_header(int kind, int len, int reg, int lane)
+{
+    return (uint32_t)kind | ((uint32_t)len << 8) | ((uint32_t)reg << 16) | ((uint32_t)lane << 24);
+}
+// Event words: [0] header; [1] grid index m (terminal n, top midpoint m,
+// subtree left end l); [2] float(m) bits; [3] float(2^23 + m) bits (an
+// index carried in a float whose bits grow with it by one per step);
+// terminal / top: [4] lane-table word of the node's dimension, [5] wl,
+// [6] wr, [7] sd (units of sqrt(dt)); terminal: [8] the number of events;
+// top: [8] l, [9] r (its interval); subtree: [4..15] the lane-table words of
+// its nodes in depth-first order, two 16-bit values per word.
+
+// Depth-first position of the midpoint of (lo, hi) inside a subtree over
+// (0, len) (root 0, left subtree before right subtree): the midpoint of an
+// interval of length L is followed by the L - 2 midpoints below it.
+__host__ __device__ constexpr int qcpw_sub_step(int len, int lo, int hi)
+{
+    int l = 0, r = len, step = 0;
+    while (r - l >= 2) {
+        const int m = (l + r) / 2;
+        if (l == lo && r == hi) return step;
+        if (hi <= m) { ++step; r = m; }
+        else { step += m - l; l = m; }   // skip the midpoint and its left subtree's m - l - 1 nodes
+    }
+    return -1;
+}
+
 // Per-option constants (host-computed in FP64).
 struct OptDev {
     int32_t type, d, n, path;     // n = d - 1
@@ -191,7 +242,10 @@ struct OptDev {
     int32_t pca_np;               // rows / columns padded to a multiple of 32 (<= QCPW_PCA_NPAD)
     int32_t n_assets;             // basket: assets M (0 for the single-asset products)
     int32_t ndims;                // Sobol dimensions a path reads after x_1: n, or n + M d (basket)
-    int32_t pad_;
+    int32_t split;                // split bridge (FP32): 1 = walk the events of n, 0 = the plan
+    int32_t n_slots;              // wave-uniform slots (split bridge) or ndims
+    int32_t grp;                  // matrix-core PCA: options sharing this one's paths (leader), 0 (member)
+    int32_t pad2_;
     // basket: scales of the common and idiosyncratic normals in Y units
     // (sqrt(rho), sqrt(1 - rho) times sigma sqrt(dt) log2 e), and the sigma
     // derivative of the drift factor exp(omega t1 + s1^2/2) per unit X
@@ -211,6 +265,8 @@ struct LaunchDesc {
     const uint32_t *dir;          // [QCPW_TAB_DIMS][32]
     const uint32_t *lane;         // [QCPW_TAB_DIMS][64]
     double *partials;             // [total_units][8]
+    const uint32_t *split_ev;     // [QCPW_MAX_N + 1][QCPW_SPLIT_EVENTS][QCPW_EV_WORDS]
+    const uint16_t *split_dim;    // [QCPW_MAX_N + 1][QCPW_SPLIT_SLOTS] Sobol dimension of each slot (0: none)
     double *scratch;              // FP64 PCA_FULL: [workgroup][date][64] products
     unsigned long long *counter;  // work-queue heads, QCPW_QUEUES of them, QCPW_QUEUE_STRIDE apart
 };

@@ -13,9 +13,18 @@
 // all earlier sums are kept), at least doubling, up to 2^22.
 //
 // Launch size: a launch carries at most ~kLaunchPathDates path-dates.  A
-// large round is cut into point ranges (slices) that ride in successive
-// launches, so a request that arrives behind it waits for one bounded launch
-// rather than for the whole round.
+// large round is cut into point ranges (slices, at most kMaxSlicePoints
+// points) that ride in successive launches, so a request that arrives behind
+// it waits for one bounded launch rather than for the whole round.
+//
+// Device memory: the launches' workspaces are the server's only device
+// buffers beyond the resident tables.  Each of the two slots may hold at
+// most half the HBM budget; a launch is packed only with slices whose bytes
+// (as the launch workspace lays them out) fit what is left of its slot, so
+// the workspaces together never exceed the budget.  A queued request is
+// admitted when its smallest slice (one QCPW_CHUNK of points) fits the
+// launch being packed; one that cannot fit an empty slot is refused at
+// submission.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +45,7 @@ namespace qcpw {
 
 static constexpr int64_t kFirstPoints = int64_t(1) << 14;
 static constexpr int64_t kMaxPoints = int64_t(1) << 22;
+static constexpr int64_t kMaxSlicePoints = kMaxPoints / 2;
 static constexpr int kMaxBatchOptions = 8192;
 static constexpr int kSlots = 2;
 static constexpr double kLaunchPathDates = 2.0e10;   // ~25 ms of FP32-mixed work
@@ -56,24 +66,40 @@ struct Request {
     double cost_per_point = 0.0;   // path-dates per point (all options, all replications)
     std::vector<double> S, Cc;     // [n_opts][L][4] compensated sums of F over points
     std::vector<double> greeks, stderr_;
-    int64_t footprint = 0;
-    bool charged = false;
     bool collected = false;        // cancelled and reported while a launch still held it
 };
 
-// Device bytes one option occupies in a launch at most (the largest round
-// covers 2^21 new points).
-static int64_t option_footprint(int n_shifts)
+// Device bytes a slice of len points of request r adds to a launch: per
+// option its constants, unit-prefix entry and per-replication means in the
+// workspace, its outputs (greeks, standard errors, per-replication means),
+// and 8 doubles per work unit (ws_layout and qcpw_unit_points give the
+// units).
+static int64_t slice_bytes(const Request *r, int64_t len)
 {
-    const int64_t chunks = (kMaxPoints / 2) / qcpw_unit_points(kMaxPoints / 2);
-    return chunks * n_shifts * 8 * (int64_t)sizeof(double) + (int64_t)n_shifts * 4 * sizeof(double) +
-           (int64_t)sizeof(OptDev) + 16 * (int64_t)sizeof(double) + 64;
+    const bool pca_like = r->path == QCPW_PATH_PCA || r->path == QCPW_PATH_PCA_FULL;
+    const int64_t up = pca_like ? QCPW_CHUNK : qcpw_unit_points(len);
+    const int64_t n = (int64_t)r->specs.size(), L = r->n_shifts;
+    const int64_t units = (len + up - 1) / up * L;
+    return n * ((int64_t)sizeof(OptDev) + (int64_t)sizeof(int64_t) + 2 * L * 4 * (int64_t)sizeof(double) +
+                2 * 4 * (int64_t)sizeof(double) + units * 8 * (int64_t)sizeof(double));
+}
+
+// Bytes of a launch that do not scale with its options: region alignment,
+// the work-queue heads, the prefix's last entry, output alignment, and the
+// FP64 full-covariance scratch tiles.
+static int64_t launch_fixed_bytes(int path, int precision, int n_cu)
+{
+    int64_t b = 16 * 256 + QCPW_QUEUES * QCPW_QUEUE_STRIDE * 8 + 8;
+    if (path == QCPW_PATH_PCA_FULL && precision == QCPW_FP64)
+        b += (int64_t)2 * std::max(n_cu, 1) * 64 * QCPW_MAX_D_PCA_FULL * (int64_t)sizeof(double);
+    return b;
 }
 
 struct Slot {
     hipStream_t stream = nullptr;
     Workspace ws;
     bool busy = false;
+    int64_t bytes = 0;                 // accounted device bytes of the launch it holds
     std::vector<Request *> reqs;
     std::vector<int64_t> k0, len;      // point slice of each request in the launch
     std::vector<int> first_opt;        // first option of each request in the launch
@@ -89,8 +115,8 @@ struct Slot {
 struct qcpw_server {
     qcpw::Context *ctx = nullptr;
     qcpw_run_config cfg;
-    int64_t budget = 0;
-    int64_t in_use = 0, peak = 0;
+    int64_t budget = 0;                // device bytes of both slots' workspaces together
+    int64_t in_use = 0, peak = 0;      // accounted bytes of the launches in flight
     int64_t n_admitted = 0, n_completed = 0, n_cancelled = 0, n_launches = 0;
     uint64_t next_id = 1;
     std::mutex mu;
@@ -106,23 +132,26 @@ namespace qcpw {
 
 static void finish_locked(qcpw_server *s, Request *r, ReqState st)
 {
-    r->state = st;   // slices still in launches keep r->in_flight until absorbed
-    if (r->charged) {
-        s->in_use -= r->footprint;
-        r->charged = false;
-    }
+    // slices still in launches keep r->in_flight, and their bytes stay
+    // accounted to the slot, until the launch is retired
+    r->state = st;
     if (st == RQ_DONE) ++s->n_completed;
     if (st == RQ_CANCELLED) ++s->n_cancelled;
     s->cv_done.notify_all();
 }
 
+static int64_t slot_cap(const qcpw_server *s) { return s->budget / kSlots; }
+
 // Pick the work of one launch (caller holds the lock): running requests
 // with points left in their round, then newly admitted ones, each with one
-// slice, until the launch's path-date budget is used.  All requests of a
-// launch share path construction and replication count; the oldest runnable
-// request decides which.
+// slice, until the launch's path-date budget or its slot's memory is used.
+// A slice is as long as the round's remaining points, the path-date budget,
+// kMaxSlicePoints and the slot's memory allow, a multiple of QCPW_CHUNK.
+// All requests of a launch share path construction and replication count;
+// the oldest runnable request decides which.  *bytes receives the launch's
+// accounted device bytes.
 static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out, std::vector<int64_t> &k0,
-                              std::vector<int64_t> &len)
+                              std::vector<int64_t> &len, int64_t *bytes)
 {
     out.clear();
     k0.clear();
@@ -130,18 +159,25 @@ static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out, std::
     int group_path = -1, group_L = -1;
     int n_opts = 0;
     double budget = kLaunchPathDates;
+    int64_t mem = 0;
     auto fits_group = [&](Request *r) {
         if (group_path < 0) {
             group_path = r->path;
             group_L = r->n_shifts;
+            mem = slot_cap(s) - launch_fixed_bytes(r->path, s->cfg.precision, s->ctx->tab.n_cu);
         }
         return r->path == group_path && r->n_shifts == group_L;
     };
-    auto take = [&](Request *r) {
-        const int64_t remaining = r->n_target - r->n_issued;
+    // the longest slice of r that fits the path-date budget and the memory
+    // left, 0 if not even one chunk fits the memory
+    auto slice_len = [&](Request *r) -> int64_t {
+        int64_t l = std::min(r->n_target - r->n_issued, kMaxSlicePoints);
         int64_t cap = (int64_t)(budget / r->cost_per_point) / QCPW_CHUNK * QCPW_CHUNK;
-        if (cap < QCPW_CHUNK) cap = QCPW_CHUNK;
-        const int64_t l = std::min(remaining, cap);
+        l = std::min(l, std::max(cap, (int64_t)QCPW_CHUNK));
+        while (l > QCPW_CHUNK && slice_bytes(r, l) > mem) l = std::max<int64_t>(QCPW_CHUNK, l / 2 / QCPW_CHUNK * QCPW_CHUNK);
+        return slice_bytes(r, l) <= mem ? l : 0;
+    };
+    auto take = [&](Request *r, int64_t l) {
         out.push_back(r);
         k0.push_back(r->n_issued);
         len.push_back(l);
@@ -149,6 +185,7 @@ static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out, std::
         r->slices_in_flight += 1;
         r->in_flight = true;
         budget -= (double)l * r->cost_per_point;
+        mem -= slice_bytes(r, l);
         n_opts += (int)r->specs.size();
     };
     for (auto &kv : s->reqs) {   // ids increase with arrival: FIFO
@@ -157,7 +194,8 @@ static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out, std::
         if (r->state != RQ_RUNNING || r->n_issued >= r->n_target) continue;
         if (!fits_group(r)) continue;
         if (n_opts + (int)r->specs.size() > kMaxBatchOptions && !out.empty()) break;
-        take(r);
+        const int64_t l = slice_len(r);
+        if (l > 0) take(r, l);
     }
     while (!s->queue.empty() && budget > 0.0) {
         auto it = s->reqs.find(s->queue.front());
@@ -166,22 +204,21 @@ static void pick_batch_locked(qcpw_server *s, std::vector<Request *> &out, std::
             continue;
         }
         Request *r = it->second.get();
-        if (s->in_use + r->footprint > s->budget) break;             // wait for memory
         if (n_opts + (int)r->specs.size() > kMaxBatchOptions && !out.empty()) break;
         if (!fits_group(r)) break;
+        r->n_target = kFirstPoints;
+        const int64_t l = slice_len(r);
+        if (l == 0) break;                                           // wait for memory
         s->queue.pop_front();
         r->state = RQ_RUNNING;
-        r->charged = true;
-        s->in_use += r->footprint;
-        s->peak = std::max(s->peak, s->in_use);
         ++s->n_admitted;
-        r->n_target = kFirstPoints;
-        take(r);
+        take(r, l);
     }
+    *bytes = out.empty() ? 0 : slot_cap(s) - mem;
 }
 
 static qcpw_status enqueue_slot(qcpw_server *s, Slot &sl, std::vector<Request *> &batch,
-                                const std::vector<int64_t> &k0, const std::vector<int64_t> &len)
+                                const std::vector<int64_t> &k0, const std::vector<int64_t> &len, int64_t bytes)
 {
     std::vector<qcpw_option_spec> specs;
     std::vector<int64_t> kb;
@@ -212,7 +249,11 @@ static qcpw_status enqueue_slot(qcpw_server *s, Slot &sl, std::vector<Request *>
     const size_t need = launch_workspace_bytes(lp);
     const size_t out_bytes = ((size_t)n * 4 * sizeof(double) + 255) / 256 * 256;
     const size_t ps_bytes = ((size_t)n * L * 4 * sizeof(double) + 255) / 256 * 256;
-    st = sl.ws.ensure(need + 2 * out_bytes + ps_bytes);
+    const size_t total = need + 2 * out_bytes + ps_bytes;
+    if ((int64_t)total > bytes)
+        return fail(QCPW_ENOMEM, "launch needs " + std::to_string(total) + " bytes, " + std::to_string(bytes) +
+                                     " were accounted");
+    st = sl.ws.ensure(total, (size_t)slot_cap(s));   // never more than the slot's share of the budget
     if (st != QCPW_OK) return st;
     char *base = (char *)sl.ws.ptr;
     sl.d_g = (double *)(base + need);
@@ -299,6 +340,8 @@ static void absorb_slot_locked(qcpw_server *s, Slot &sl)
     }
     sl.reqs.clear();
     sl.busy = false;
+    s->in_use -= sl.bytes;
+    sl.bytes = 0;
     ++s->n_launches;
 }
 
@@ -312,6 +355,8 @@ static void fail_slot_locked(qcpw_server *s, Slot &sl)
     }
     sl.reqs.clear();
     sl.busy = false;
+    s->in_use -= sl.bytes;
+    sl.bytes = 0;
 }
 
 static bool work_available_locked(qcpw_server *s)
@@ -338,6 +383,7 @@ static void worker_main(qcpw_server *s)
     for (;;) {
         std::vector<Request *> batch;
         std::vector<int64_t> bk0, blen;
+        int64_t bytes = 0;
         int free_slot = -1, busy = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
@@ -346,16 +392,24 @@ static void worker_main(qcpw_server *s)
                 s->cv_work.wait(lk, [&] { return s->stop || work_available_locked(s); });
                 if (s->stop) break;
             }
+            if (s->stop) break;   // launches in flight are retired below
             for (int i = 0; i < kSlots; ++i)
                 if (!s->slots[i].busy) {
                     free_slot = i;
                     break;
                 }
-            if (free_slot >= 0) pick_batch_locked(s, batch, bk0, blen);
+            if (free_slot >= 0) {
+                pick_batch_locked(s, batch, bk0, blen, &bytes);
+                if (!batch.empty()) {
+                    s->slots[free_slot].bytes = bytes;
+                    s->in_use += bytes;
+                    s->peak = std::max(s->peak, s->in_use);
+                }
+            }
         }
         if (!batch.empty()) {
             Slot &sl = s->slots[free_slot];
-            if (dev_ok && enqueue_slot(s, sl, batch, bk0, blen) == QCPW_OK) {
+            if (dev_ok && enqueue_slot(s, sl, batch, bk0, blen, bytes) == QCPW_OK) {
                 slot_seq[free_slot] = ++seq;
                 ++busy;
             } else {
@@ -399,6 +453,13 @@ qcpw_status qcpw_server_create(const qcpw_run_config *cfg, int64_t hbm_budget_by
     Context *ctx = nullptr;
     qcpw_status st = get_context(c.device, &ctx);
     if (st != QCPW_OK) return st;
+    if (c.block_threads == 0) {
+        // tune the workgroup size of every lane-table bucket now, so that no
+        // request pays for the autotuner's probe launches in its latency
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (int path : {QCPW_PATH_BB, QCPW_PATH_STANDARD})
+            pretune_block_threads(ctx, path, c.precision, (c.flags & QCPW_FLAG_OWEN) != 0);
+    }
     std::unique_ptr<qcpw_server> s(new qcpw_server());
     s->ctx = ctx;
     s->cfg = c;
@@ -428,9 +489,14 @@ qcpw_status qcpw_submit(qcpw_server *srv, const qcpw_option_spec *specs, int32_t
     r->n_shifts = n_shifts;
     r->path = path_construction;
     r->target = target_stderr;
-    r->footprint = option_footprint(n_shifts) * n_opts;
-    for (int i = 0; i < n_opts; ++i) r->cost_per_point += (double)std::max(specs[i].d - 1, 1) * n_shifts;
-    if (r->footprint > srv->budget) return fail(QCPW_ENOMEM, "request footprint exceeds the HBM budget");
+    for (int i = 0; i < n_opts; ++i) {
+        const bool basket = specs[i].type == QCPW_BASKET_ASIAN_CALL || specs[i].type == QCPW_BASKET_ASIAN_PUT;
+        const int64_t ndims = (int64_t)(specs[i].d - 1) + (basket ? (int64_t)specs[i].n_assets * specs[i].d : 0);
+        r->cost_per_point += (double)std::max<int64_t>(ndims, 1) * n_shifts;
+    }
+    if (slice_bytes(r.get(), QCPW_CHUNK) + launch_fixed_bytes(path_construction, srv->cfg.precision,
+                                                              srv->ctx->tab.n_cu) > slot_cap(srv))
+        return fail(QCPW_ENOMEM, "even the request's smallest slice exceeds half the HBM budget");
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return fail(QCPW_EINVAL, "server is shutting down");
     r->id = srv->next_id++;
@@ -499,7 +565,7 @@ qcpw_status qcpw_cancel(qcpw_server *srv, uint64_t request_id)
     return QCPW_OK;
 }
 
-qcpw_status qcpw_server_stats(qcpw_server *srv, int64_t out[7])
+qcpw_status qcpw_server_stats(qcpw_server *srv, int64_t out[8])
 {
     if (!srv || !out) return fail(QCPW_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -512,6 +578,8 @@ qcpw_status qcpw_server_stats(qcpw_server *srv, int64_t out[7])
     out[4] = srv->in_use;
     out[5] = srv->peak;
     out[6] = queued;
+    out[7] = 0;
+    for (auto &sl : srv->slots) out[7] += (int64_t)sl.ws.bytes;
     return QCPW_OK;
 }
 

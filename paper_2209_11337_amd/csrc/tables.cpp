@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <utility>
 #include <vector>
@@ -146,6 +147,174 @@ int build_bridge_plan(int n, std::vector<PlanStep> &steps, std::vector<PlanStep6
     }
     if (!consistent) return -1;
     return std::max(max_depth, max_sp);
+}
+
+// Breadth-first dimensions of the bridge's intervals (as build_bridge_plan).
+static std::map<std::pair<int, int>, int> bridge_dims(int n)
+{
+    std::map<std::pair<int, int>, int> dim_of;
+    std::deque<std::pair<int, int>> fifo;
+    fifo.emplace_back(0, n);
+    int next_dim = 2;
+    while (!fifo.empty()) {
+        auto iv = fifo.front();
+        fifo.pop_front();
+        if (iv.second - iv.first < 2) continue;
+        const int m = (iv.first + iv.second) / 2;
+        dim_of[iv] = next_dim++;
+        fifo.emplace_back(iv.first, m);
+        fifo.emplace_back(m, iv.second);
+    }
+    return dim_of;
+}
+
+static uint32_t fbits(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+// Split-bridge plan for n (see qcpw_internal.h): events in depth-first
+// order -- the terminal point, then top midpoints and subtrees -- and the
+// Sobol dimension of every wave-uniform slot.  Slots: the terminal point and
+// the top nodes take 0 .. 2^k - 1 in event order; each subtree then takes
+// the next len - 1 slots, moved to the start of the next register when they
+// would straddle one.  The terminal event's word 8 holds the event count.
+// Returns the slots used, or 0 when n has no split plan.
+int build_split_plan(int n, std::vector<uint32_t> &ev, std::vector<uint16_t> &slot_dim)
+{
+    ev.assign((size_t)QCPW_SPLIT_EVENTS * QCPW_EV_WORDS, 0u);
+    slot_dim.assign(QCPW_SPLIT_SLOTS, 0);
+    if (n < QCPW_SUB_MIN_LEN || n > QCPW_MAX_N) return 0;
+    int k = 0;
+    while (((n + (1 << k) - 1) >> k) > QCPW_SUB_MAX_LEN) ++k;
+    const auto dim_of = bridge_dims(n);
+    int e = 0, top_slot = 0, sub_slot = 1 << k;
+    bool ok = true;
+    auto head = [&](int kind, int len, int slot, int m) -> uint32_t * {
+        uint32_t *w = &ev[(size_t)e * QCPW_EV_WORDS];
+        w[0] = qcpw_ev_header(kind, len, slot / 64, slot % 64);
+        w[1] = (uint32_t)m;
+        w[2] = fbits((float)m);
+        w[3] = fbits(8388608.0f + (float)m);
+        ++e;
+        return w;
+    };
+    {   // terminal point, dimension 1
+        const int slot = top_slot++;
+        uint32_t *w = head(QCPW_EV_TERMINAL, 0, slot, n);
+        w[4] = (uint32_t)qcpw_row_word(0);
+        w[7] = fbits((float)qcpw_csqrt((double)n));
+        slot_dim[slot] = 1;
+    }
+    std::function<void(int, int, int)> visit = [&](int l, int r, int level) {
+        if (!ok) return;
+        const int len = r - l;
+        if (level == k) {
+            if (len < QCPW_SUB_MIN_LEN || len > QCPW_SUB_MAX_LEN) { ok = false; return; }
+            const int nodes = len - 1;
+            if (sub_slot / 64 != (sub_slot + nodes - 1) / 64) sub_slot = (sub_slot / 64 + 1) * 64;
+            if (sub_slot + nodes > QCPW_SPLIT_SLOTS) { ok = false; return; }
+            uint32_t *w = head(QCPW_EV_SUB, len, sub_slot, l);
+            // the subtree's midpoints in depth-first order
+            int t = 0;
+            std::function<void(int, int)> walk = [&](int lo, int hi) {
+                if (hi - lo < 2) return;
+                const int m = (lo + hi) / 2;
+                auto it = dim_of.find({l + lo, l + hi});
+                if (it == dim_of.end() || qcpw_sub_step(len, lo, hi) != t) { ok = false; return; }
+                const int off = qcpw_row_word(it->second - 1);
+                if (off > 0xFFFF) { ok = false; return; }
+                w[4 + t / 2] |= (uint32_t)off << (16 * (t & 1));
+                slot_dim[sub_slot + t] = (uint16_t)it->second;
+                ++t;
+                walk(lo, m);
+                walk(m, hi);
+            };
+            walk(0, len);
+            if (t != nodes) ok = false;
+            sub_slot += nodes;
+            return;
+        }
+        const int m = (l + r) / 2;
+        auto it = dim_of.find({l, r});
+        if (it == dim_of.end()) { ok = false; return; }
+        const int slot = top_slot++;
+        uint32_t *w = head(QCPW_EV_TOP, 0, slot, m);
+        w[4] = (uint32_t)qcpw_row_word(it->second - 1);
+        w[5] = fbits((float)((double)(r - m) / len));
+        w[6] = fbits((float)((double)(m - l) / len));
+        w[7] = fbits((float)qcpw_csqrt((double)(m - l) * (double)(r - m) / len));
+        w[8] = (uint32_t)l;
+        w[9] = (uint32_t)r;
+        slot_dim[slot] = (uint16_t)it->second;
+        visit(l, m, level + 1);
+        visit(m, r, level + 1);
+    };
+    visit(0, n, 0);
+    if (!ok || e != (2 << k) || e > QCPW_SPLIT_EVENTS) return 0;
+    ev[8] = (uint32_t)e;
+    return sub_slot;
+}
+
+// The factor A (n x n, row-major) that the split plan's walk applies, in
+// FP64 (the kernel's steps with FP64 weights): for every unit vector z the
+// events and subtrees are walked exactly as the FP32 kernel walks them.
+void split_plan_factor(int n, double dt, const std::vector<uint32_t> &ev, std::vector<double> &A)
+{
+    A.assign((size_t)n * n, std::nan(""));
+    const int n_ev = (int)ev[8];
+    auto word_dim = [](uint32_t w) {
+        const int r = w < QCPW_LDS_TAB_HI / 4 ? (int)(w - QCPW_LDS_GAP_BEGIN / 4) / 64
+                                              : QCPW_LDS_GAP_ROWS + (int)(w - QCPW_LDS_FIXED / 4) / 64;
+        return r + 1;
+    };
+    const double sdt = std::sqrt(dt);
+    for (int col = 0; col < n; ++col) {
+        std::vector<double> W(n + 1, std::nan(""));
+        W[0] = 0.0;
+        auto zof = [&](int dim) { return dim - 1 == col ? sdt : 0.0; };
+        const uint32_t *t = ev.data();
+        double R = (double)qcpw_csqrt((double)n) * zof(word_dim(t[4])), L = 0.0;
+        W[n] = R;
+        std::vector<double> stack;
+        for (int e = 1; e < n_ev; ++e) {
+            const uint32_t *w = ev.data() + (size_t)e * QCPW_EV_WORDS;
+            const int kind = w[0] & 255, len = (w[0] >> 8) & 255, m = (int)w[1];
+            if (kind == QCPW_EV_TOP) {
+                // FP64 weights of the interval (l, r) the event names
+                const int l = (int)w[8], r = (int)w[9];
+                const double len_d = r - l;
+                const double M = (r - m) / len_d * L + (m - l) / len_d * R +
+                                 qcpw_csqrt((double)(m - l) * (double)(r - m) / len_d) * zof(word_dim(w[4]));
+                W[m] = M;
+                stack.push_back(R);
+                R = M;
+            } else {
+                int t_node = 0;
+                std::function<void(int, int, double, double)> walk = [&](int lo, int hi, double WL, double WR) {
+                    if (hi - lo < 2) return;
+                    const int mm = (lo + hi) / 2;
+                    const double wl = (double)(hi - mm) / (double)(hi - lo), wr = (double)(mm - lo) / (double)(hi - lo);
+                    const double sd = qcpw_csqrt((double)(mm - lo) * (double)(hi - mm) / (double)(hi - lo));
+                    const uint32_t off = (w[4 + t_node / 2] >> (16 * (t_node & 1))) & 0xFFFFu;
+                    ++t_node;
+                    const double Y = wl * WL + wr * WR + sd * zof(word_dim(off));
+                    W[m + mm] = Y;
+                    walk(lo, mm, WL, Y);
+                    walk(mm, hi, Y, WR);
+                };
+                walk(0, len, L, R);
+                L = R;
+                if (!stack.empty()) {
+                    R = stack.back();
+                    stack.pop_back();
+                }
+            }
+        }
+        for (int kk = 0; kk < n; ++kk) A[(size_t)kk * n + col] = W[kk + 1];
+    }
 }
 
 // Principal components of Sigma_{kl} = dt min(k, l), k, l = 1..n, in closed

@@ -123,10 +123,10 @@ def test_library_full_pca_factor_matches_oracle(d):
 
 def test_full_pca_argument_checks():
     o = dict(type=0, d=16, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, seed=1, n_points=64)
-    for t in (2, 3, 4, 5, 6, 7):   # lookback, geometric, puts
+    for t in (3, 4, 5, 6, 7):   # geometric, puts
         with pytest.raises(q.QcpwError) as ei:
             q.greeks([dict(o, type=t)], 4, q.PATH_PCA_FULL)
-        assert ei.value.status == -1 and "Asian" in str(ei.value)
+        assert ei.value.status == -1 and "lookback calls" in str(ei.value)
     with pytest.raises(q.QcpwError) as ei:
         q.greeks([dict(o, d=257)], 4, q.PATH_PCA_FULL)
     assert ei.value.status == -4

@@ -44,6 +44,16 @@ def oracle_many(opts, L, path):
             np.array([r["abs_mean"] for r in out]), np.array([r["C_l"] for r in out]))
 
 
+def scaled_err(got, ref, scale):
+    """|got - ref| / max(|ref|, scale); a zero scale means every summand was
+    zero (a density that underflows far from the money), so the two must be
+    equal: 0/0 counts as 0, any difference as infinite."""
+    diff = np.abs(np.asarray(got) - np.asarray(ref))
+    den = np.maximum(np.abs(ref), scale)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(diff == 0, 0.0, diff / den)
+
+
 def assert_scaled(g, o, scale, tol, what=""):
     g, o, scale = np.asarray(g), np.asarray(o), np.asarray(scale)
     bound = tol * np.maximum(np.abs(o), scale)
@@ -152,7 +162,7 @@ def test_fp32_mixed_within_bound(path):
     say("fp32 bound", path)
     g, e, ps = q.greeks(opts, 2, path, q.FP32_MIXED, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, path)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("fp32 scaled error per output (max over options, shifts):", err.max(axis=(0, 1)))
     for k in range(4):
         assert err[..., k].max() <= FP32_TOL[k], (k, err[..., k].max())
@@ -165,7 +175,7 @@ def test_fp32_bridge_across_d(d):
     say("fp32 bridge", d)
     g, e, ps = q.greeks(opts, 2, q.PATH_BB, q.FP32_MIXED, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_BB)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     for k in range(4):
         assert err[..., k].max() <= FP32_TOL[k], (d, k, err[..., k].max())
 
@@ -175,7 +185,7 @@ def test_fp32_mixed_portfolio_within_bound():
     say("fp32 portfolio")
     g, e, ps = q.greeks(opts, 2, q.PATH_BB, q.FP32_MIXED, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_BB)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("portfolio fp32 scaled error:", err.max(axis=(0, 1)))
     for k in range(4):
         assert err[..., k].max() <= FP32_TOL[k], (k, err[..., k].max())
@@ -280,8 +290,33 @@ def test_pca_matrix_cores_within_bound(gemm, tol, d):
     say("pca mfma", gemm, d)
     g, e, ps = q.greeks(opts, 2, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_PCA)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("pca scaled error", gemm, d, err.max(axis=(0, 1)))
+    for k in range(4):
+        assert err[..., k].max() <= tol[k], (k, err[..., k].max())
+
+
+@pytest.mark.parametrize("gemm,tol", [(q.GEMM_FP32, FP32_TOL), (q.GEMM_BF16X3, BF16X3_TOL)])
+def test_pca_shared_paths_one_product(gemm, tol):
+    """Options with the same paths (seed, d, sigma, r, T) but other strikes
+    and payoffs share one product and epilogue per tile in the matrix-core
+    kernel: each result equals the option's result alone, bit for bit, and
+    the oracle's within the bound; a lookback and an option of another seed
+    in the same launch keep their own paths."""
+    base = dict(d=65, S0=100.0, r=0.05, sigma=0.25, T=1.0, seed=0x5eed, n_points=8192 + 300)
+    grp = [dict(base, type=t, K=K) for t, K in ((q.ARITH_ASIAN, 95.0), (q.BINARY_ASIAN, 95.0),
+                                                 (q.ARITH_ASIAN, 108.0), (q.BINARY_ASIAN, 101.0),
+                                                 (q.ARITH_ASIAN, 100.0))]   # five: a group of 4 and one more
+    others = [dict(base, type=q.LOOKBACK, K=100.0), dict(base, type=q.ARITH_ASIAN, K=100.0, seed=0x5eee)]
+    opts = grp + others
+    say("pca shared paths", gemm)
+    g, e, ps = q.greeks(opts, 4, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+    for i, o in enumerate(opts):
+        g1, e1, ps1 = q.greeks([o], 4, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+        assert np.array_equal(ps[i], ps1[0]), i
+    m, se, am, Cl = oracle_many(opts, 4, oracle.PATH_PCA)
+    err = scaled_err(ps, Cl, am[:, None, :])
+    say("pca shared scaled error", gemm, err.max(axis=(0, 1)))
     for k in range(4):
         assert err[..., k].max() <= tol[k], (k, err[..., k].max())
 
@@ -300,7 +335,7 @@ def test_pca_full_size_properties():
         o1 = [oracle.option(o["type"], o["d"], o["S0"], o["K"], o["r"], o["sigma"], o["T"], o["seed"], 512, 1,
                             oracle.PATH_PCA)["abs_mean"] for o in opts]
         scale = np.array(o1)[:, None, :]
-        err = np.abs(ps - p64) / np.maximum(np.abs(p64), scale)
+        err = scaled_err(ps, p64, scale)
         say("full pca scaled diff", gemm, err.max(axis=(0, 1)))
         for k in range(4):
             assert err[..., k].max() <= tol[k]
@@ -311,14 +346,10 @@ def test_pca_full_size_properties():
 # ------------------------------------------------------------------------
 # conditioning on the first principal component of all d dates
 # ------------------------------------------------------------------------
-def _asians(opts):
-    return [o for o in opts if o["type"] != workloads.LOOKBACK]
-
-
 @pytest.mark.parametrize("d,pts,step", [(1, 8192 + 150, 3), (2, 8192 + 150, 3), (16, 8192 + 150, 3),
                                         (63, 8192 + 150, 3), (256, 4096 + 100, 6)])
 def test_fp64_pca_full_parity(d, pts, step):
-    opts = _asians(workloads.three_products_grid(d=d, n_points=pts))[::step]
+    opts = workloads.three_products_grid(d=d, n_points=pts)[::step]   # arithmetic, binary, lookback
     say("pca_full fp64", d, len(opts))
     g, e, ps = q.greeks(opts, 2, q.PATH_PCA_FULL, q.FP64, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_PCA_FULL)
@@ -329,11 +360,11 @@ def test_fp64_pca_full_parity(d, pts, step):
 @pytest.mark.parametrize("gemm,tol", [(q.GEMM_FP32, FP32_TOL), (q.GEMM_BF16X3, BF16X3_TOL)])
 @pytest.mark.parametrize("d", [17, 64, 256])
 def test_pca_full_matrix_cores_within_bound(gemm, tol, d):
-    opts = _asians(workloads.three_products_grid(d=d, n_points=4096 + 100))[::3 if d < 256 else 6]
+    opts = workloads.three_products_grid(d=d, n_points=4096 + 100)[::3 if d < 256 else 6]
     say("pca_full mfma", gemm, d)
     g, e, ps = q.greeks(opts, 2, q.PATH_PCA_FULL, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, oracle.PATH_PCA_FULL)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("pca_full scaled error", gemm, d, err.max(axis=(0, 1)))
     for k in range(4):
         assert err[..., k].max() <= tol[k], (k, err[..., k].max())
@@ -357,7 +388,7 @@ def test_pca_full_large_properties():
     for gemm, tol in [(q.GEMM_FP32, FP32_TOL), (q.GEMM_BF16X3, BF16X3_TOL)]:
         say("pca_full large", gemm)
         g, e, ps = q.greeks(opts, 8, q.PATH_PCA_FULL, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
-        err = np.abs(ps - p64) / np.maximum(np.abs(p64), scale[:, None, :])
+        err = scaled_err(ps, p64, scale[:, None, :])
         say("pca_full large scaled diff", gemm, err.max(axis=(0, 1)))
         for k in range(4):
             assert err[..., k].max() <= tol[k]
@@ -397,7 +428,7 @@ def test_fp32_owen_within_bound(path, d):
     say("owen fp32", path, d)
     g, e, ps = q.greeks(opts, 3, path, q.FP32_MIXED, per_shift=True, owen=True)
     m, se, am, Cl = oracle_many_rand(opts, 3, path, oracle.RAND_OWEN)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     for k in range(4):
         assert err[..., k].max() <= FP32_TOL[k], (k, err[..., k].max())
 
@@ -429,7 +460,7 @@ def test_fp32_geometric_within_bound(path, d, gemm):
     say("geometric fp32", path, d, gemm)
     g, e, ps = q.greeks(opts, 2, path, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, path)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("geometric fp32 scaled error", err.max(axis=(0, 1)))
     tol = BF16X3_TOL if (path == q.PATH_PCA and gemm == q.GEMM_BF16X3) else FP32_TOL
     for k in range(4):
@@ -478,7 +509,7 @@ def test_fp32_puts_within_bound(path, d, gemm):
     say("puts fp32", path, d, gemm)
     g, e, ps = q.greeks(opts, 2, path, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, path)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("puts fp32 scaled error", err.max(axis=(0, 1)))
     tol = BF16X3_TOL if (path == q.PATH_PCA and gemm == q.GEMM_BF16X3) else FP32_TOL
     for k in range(4):
@@ -527,7 +558,7 @@ def test_fp32_basket_within_bound(d, M):
     say("basket fp32", d, M)
     g, e, ps = q.greeks(opts, 2, q.PATH_STANDARD, q.FP32_MIXED, per_shift=True)
     m, se, am, Cl = oracle_many(opts, 2, q.PATH_STANDARD)
-    err = np.abs(ps - Cl) / np.maximum(np.abs(Cl), am[:, None, :])
+    err = scaled_err(ps, Cl, am[:, None, :])
     say("basket fp32 scaled error", err.max(axis=(0, 1)))
     for k in range(4):
         assert err[..., k].max() <= FP32_TOL[k], (k, err[..., k].max())
@@ -569,12 +600,14 @@ def test_server_results_match_direct_calls_and_overlap():
 
 
 def test_server_admission_budget_and_cancel():
-    # each request holds 20 options x 16 shifts (~5.3 MB at its largest
-    # round), so at most two of them fit the 12 MB budget at a time
+    # each request holds 20 options x 16 shifts: a slice of 2^21 points would
+    # take 10.5 MB, so under a 12 MB budget (6 MB per launch slot) the rounds
+    # ride in slices of 2^20 points, one request per launch
     small = workloads.portfolio(20, seed=1, d_range=(8, 32))
-    with q.Server(hbm_budget_bytes=12 << 20, precision=q.FP32_MIXED) as srv:
+    budget = 12 << 20
+    with q.Server(hbm_budget_bytes=budget, precision=q.FP32_MIXED) as srv:
         with pytest.raises(q.QcpwError):
-            srv.submit(workloads.portfolio(200, seed=2), 16, 1e-6)      # alone exceeds the budget
+            srv.submit(workloads.portfolio(200, seed=2), 16, 1e-6)      # smallest slice exceeds a slot
         ids = [srv.submit(small, 16, 1e-9) for _ in range(6)]           # unmet target: run to the cap
         srv.cancel(ids[-1])
         out = [srv.wait(i, len(small)) if i != ids[-1] else None for i in ids]
@@ -582,9 +615,27 @@ def test_server_admission_budget_and_cancel():
             srv.wait(ids[-1], len(small))
         st = srv.stats()
     say("admission stats", st)
-    assert st["peak_bytes"] <= 12 << 20
+    assert st["peak_bytes"] <= budget
+    assert st["workspace_bytes"] <= budget          # what the slots actually hold on the device
+    assert st["bytes_in_use"] == 0
     assert st["cancelled"] >= 1
     assert all(o[2] == 1 << 22 for o in out if o is not None)
+
+
+def test_server_destroy_returns_promptly():
+    """Destroying a server with long requests queued and running stops taking
+    work at once: it waits only for the (bounded) launches in flight."""
+    import time
+    heavy = workloads.portfolio(64, seed=9, d_range=(300, 365))
+    srv = q.Server(hbm_budget_bytes=8 << 30, precision=q.FP32_MIXED)
+    for _ in range(8):
+        srv.submit(heavy, 16, 1e-12)        # each would run to 2^22 points: seconds of work
+    time.sleep(0.2)
+    t0 = time.perf_counter()
+    srv.close()
+    dt = time.perf_counter() - t0
+    say("destroy took %.3f s" % dt)
+    assert dt < 1.0
 
 
 # ------------------------------------------------------------------------

@@ -607,7 +607,8 @@ def _full_path(d, T, rng):
                                           (100, 120, 0.02, 0.4, 0.5)])
 def test_full_pca_one_date_is_black_scholes(S0, K, r, sig, T):
     """d = 1 leaves only the conditioned component: the estimate is the
-    Black-Scholes call / cash-or-nothing digital and their Greeks."""
+    Black-Scholes call (arithmetic average or maximum of one date) /
+    cash-or-nothing digital and their Greeks."""
     d1 = (math.log(S0 / K) + (r + sig**2 / 2) * T) / (sig * math.sqrt(T))
     d2 = d1 - sig * math.sqrt(T)
     D = math.exp(-r * T)
@@ -615,7 +616,7 @@ def test_full_pca_one_date_is_black_scholes(S0, K, r, sig, T):
     call = [S0 * N(d1) - K * D * N(d2), N(d1), S0 * math.sqrt(T) * n(d1), n(d1) / (S0 * sig * math.sqrt(T))]
     dig = [D * N(d2), D * n(d2) / (S0 * sig * math.sqrt(T)), -D * n(d2) * d1 / sig,
            -D * n(d2) * d1 / (S0 * S0 * sig * sig * T)]
-    for typ, ref in ((oracle.ARITH_ASIAN, call), (oracle.BINARY_ASIAN, dig)):
+    for typ, ref in ((oracle.ARITH_ASIAN, call), (oracle.BINARY_ASIAN, dig), (oracle.LOOKBACK, call)):
         res = oracle.option(typ, 1, S0, K, r, sig, T, 99, 64, 2, oracle.PATH_PCA_FULL)
         np.testing.assert_allclose(res["mean"], ref, rtol=1e-12, atol=1e-15)
 
@@ -634,7 +635,7 @@ def test_full_pca_root_matches_bracketing_solver(d):
         assert abs(oracle.full_root(al, be, K) - ref) <= 1e-12 * max(1.0, abs(ref))
 
 
-@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN])
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK])
 @pytest.mark.parametrize("d", [2, 7, 32])
 def test_full_pca_greeks_equal_finite_differences(typ, d):
     """Per path, the pathwise delta, vega and gamma equal Richardson finite
@@ -662,16 +663,18 @@ def test_full_pca_greeks_equal_finite_differences(typ, d):
             assert abs(got - fd) <= 1e-6 * abs(fd) + 50 * eps * scale / h, (typ, d, got, fd)
 
 
-@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN])
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK])
 def test_full_pca_conditional_price_is_quadrature_of_payoff(typ):
     """G = E[discounted payoff | other components]: integrate the original
-    payoff over the first component numerically and compare."""
+    payoff (average, or maximum over the dates) over the first component
+    numerically and compare."""
     S0, r, sig, T, d = 100.0, 0.05, 0.3, 1.0, 12
     rng = np.random.default_rng(12 + typ)
     t = T / d * np.arange(1, d + 1)
+    stat = np.max if typ == oracle.LOOKBACK else np.mean
     for K in (85.0, 100.0, 120.0):
         a, c = _full_path(d, T, rng)
-        avg = lambda x: np.mean(S0 * np.exp((r - sig**2 / 2) * t + sig * (a * x + c)))
+        avg = lambda x: stat(S0 * np.exp((r - sig**2 / 2) * t + sig * (a * x + c)))
         root = scipy.optimize.brentq(lambda x: avg(x) - K, -60, 60, xtol=1e-15, rtol=1e-15)
         if typ == oracle.BINARY_ASIAN:
             f = lambda x: math.exp(-r * T) * scipy.stats.norm.pdf(x)
@@ -682,7 +685,7 @@ def test_full_pca_conditional_price_is_quadrature_of_payoff(typ):
         assert abs(g[0] - val) <= 1e-10 * max(abs(val), 1e-12), (g[0], val)
 
 
-@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN])
+@pytest.mark.parametrize("typ", [oracle.ARITH_ASIAN, oracle.BINARY_ASIAN, oracle.LOOKBACK])
 def test_full_pca_estimate_agrees_with_first_date_conditioning(typ):
     """Two different conditional estimators of the same Greeks -- the first
     principal component integrated out, or the first date's normal with a
@@ -712,9 +715,33 @@ def test_full_pca_estimate_agrees_with_quadrature_at_two_dates():
         assert abs(res["mean"][i] - ref[i]) <= 4 * res["stderr"][i] + 1e-13 * abs(ref[i]), i
 
 
-def test_full_pca_rejects_lookback():
-    with pytest.raises(ValueError):
-        oracle.option(oracle.LOOKBACK, 8, 100.0, 100.0, 0.05, 0.2, 1.0, 1, 64, 2, oracle.PATH_PCA_FULL)
+def test_full_pca_lookback_envelope_against_brute_force():
+    """The lookback's conditional price on one path, by its envelope walk,
+    against the same integral done line by line on a fine grid of x: at every
+    x the payoff is (max over dates - K)^+, integrated by a composite rule
+    over [psi, 12] with the breakpoints of the envelope found by brute force
+    (where the argmax over the dates changes), so a wrong segment or line
+    shows.  Also: psi is the smallest of the lines' own crossings of ln K."""
+    S0, r, sig, T, d = 100.0, 0.03, 0.35, 1.5, 40
+    rng = np.random.default_rng(4040)
+    t = T / d * np.arange(1, d + 1)
+    for K in (95.0, 110.0, 140.0):
+        a, c = _full_path(d, T, rng)
+        al = math.log(S0) + (r - sig**2 / 2) * t + sig * c
+        be = sig * a
+        psi = np.min((math.log(K) - al) / be)
+        assert abs(np.max(al + be * psi) - math.log(K)) <= 1e-12
+        xs = np.linspace(psi, 12.0, 400001)
+        top = np.argmax(al[None, :] + be[None, :] * xs[:, None], axis=1)
+        cuts = [psi] + [0.5 * (xs[i] + xs[i + 1]) for i in np.nonzero(np.diff(top))[0]] + [12.0]
+        val = 0.0
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            j = top[np.searchsorted(xs, 0.5 * (lo + hi))]
+            f = lambda x: (math.exp(al[j] + be[j] * x) - K) * scipy.stats.norm.pdf(x)
+            val += scipy.integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-12, limit=200)[0]
+        g = oracle.path_greeks_full(oracle.LOOKBACK, d, S0, K, r, sig, T, a, c)
+        # the grid locates breakpoints to 1e-4 in x; the payoff is continuous there
+        assert abs(g[0] / math.exp(-r * T) - val) <= 1e-6 * max(abs(val), 1e-3), (K, g[0], val)
 
 
 # --------------------------------------------------------------------------

@@ -107,12 +107,15 @@ def basket_grid(d: int = 16, n_assets: int = 4, n_points: int = 1 << 20) -> list
     return out
 
 
-def pca_pair(d: int = 256, n_points: int = 1 << 22) -> list[dict]:
+def pca_pair(d: int = 256, n_points: int = 1 << 22, shared: bool = True) -> list[dict]:
     """Arithmetic and binary Asian, S0 = K = 100, r = 0.05, sigma = 0.2, T = 1,
-    d = 256 (255 conditioned coordinates, padded to a 256 x 256 factor)."""
+    d = 256 (255 conditioned coordinates, padded to a 256 x 256 factor).
+    shared: one seed for both, so that they price the same paths (one
+    product per shift, both payoffs in its epilogue); else a seed each."""
     out = [dict(type=t, d=d, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, n_points=n_points)
            for t in (ARITH_ASIAN, BINARY_ASIAN)]
-    for o, s in zip(out, _seeds(2, BASE_SEED + 2)):
+    seeds = _seeds(2, BASE_SEED + 2)
+    for o, s in zip(out, seeds[:1] * 2 if shared else seeds):
         o["seed"] = s
     return out
 
