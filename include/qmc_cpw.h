@@ -208,6 +208,35 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
                               const qcpw_run_config *cfg);
 
 /*
+ * qmc_cpw_greeks_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): qmc_cpw_greeks_ex with the launch workspace in a fixed device
+ * array of QCPW_NOALLOC_BYTES per device, held from the library's load
+ * until the process ends, instead of library-allocated buffers.  Same
+ * arguments, results and errors as qmc_cpw_greeks_ex, except:
+ *   - path_construction QCPW_PATH_BB or QCPW_PATH_STANDARD, flags 0 or
+ *     QCPW_FLAG_OWEN (QCPW_EINVAL otherwise);
+ *   - block_threads 0 takes the autotuner's earlier choice for the launch's
+ *     shape if there is one, else 512 threads -- its probe launches are
+ *     never run here;
+ *   - QCPW_ENOMEM, before any device work, when the launch needs more than
+ *     QCPW_NOALLOC_BYTES: 64 bytes per work unit (units = sum over options
+ *     of n_shifts * ceil(n_points / unit points), 256..4096 points per unit)
+ *     plus about 400 bytes per option, and with host outputs their staging.
+ * Nothing is allocated and nothing freed by the call; the first call of the
+ * library on a device (any entry point) builds the device tables, so a
+ * caller that must not allocate at all makes one call first.  Every call on
+ * a device shares its array, which keeps the last call's contents: calls
+ * that overlap on one device (different streams or threads) race on it.
+ */
+#define QCPW_NOALLOC_BYTES (64 << 20)
+qcpw_status qmc_cpw_greeks_noalloc(const qcpw_option_spec *option_specs, int32_t n_opts,
+                                   int32_t d, int64_t n_points, int32_t n_shifts,
+                                   int32_t path_construction,
+                                   double *out_greeks, double *out_stderr,
+                                   const qcpw_run_config *cfg);
+
+/*
  * qcpw_sobol_points -- the shifted Sobol integers the kernels consume, for
  * checking them bit for bit: out[k][j] = (G_j gray(k0 + k)) XOR s_{l,j},
  * k = 0..count-1, j = 0..n_dims-1 (dimension 0 unshifted), computed on the

@@ -35,7 +35,7 @@ STATUS = {0: "QCPW_OK", -1: "QCPW_EINVAL", -2: "QCPW_ENOMEM", -3: "QCPW_EDEVICE"
           -5: "QCPW_EBUSY", -6: "QCPW_ECANCELLED", -7: "QCPW_ENOTFOUND"}
 
 # names of every entry point declared in include/qmc_cpw.h
-EXPORTS = ("qmc_cpw_greeks", "qmc_cpw_greeks_ex", "qcpw_sobol_points", "qcpw_scrambled_points",
+EXPORTS = ("qmc_cpw_greeks", "qmc_cpw_greeks_ex", "qmc_cpw_greeks_noalloc", "qcpw_sobol_points", "qcpw_scrambled_points",
            "qcpw_path_coordinates", "qcpw_path_factor",
            "qcpw_kernel_timer", "qcpw_last_error", "qcpw_version", "qcpw_server_create", "qcpw_submit", "qcpw_poll",
            "qcpw_wait", "qcpw_cancel", "qcpw_server_stats", "qcpw_server_destroy")
@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
             vp, i32, i64, u64, f64p = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
             L.qmc_cpw_greeks.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p]
             L.qmc_cpw_greeks_ex.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p, vp]
+            L.qmc_cpw_greeks_noalloc.argtypes = [vp, i32, i32, i64, i32, i32, f64p, f64p, vp]
             L.qcpw_sobol_points.argtypes = [u64, i32, i32, i64, i64, vp]
             L.qcpw_scrambled_points.argtypes = [u64, i32, i32, i64, i64, vp]
             L.qcpw_path_coordinates.argtypes = [vp, i32, i32, i32, i32, vp]
@@ -178,6 +179,34 @@ def greeks(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precisio
     _check(lib().qmc_cpw_greeks_ex(specs, n, d, n_points, n_shifts, path, g.ctypes.data, e.ctypes.data,
                                    C.byref(cfg)))
     return (g, e) + ((ps,) if per_shift else ()) + ((sg,) if paper_sigma else ())
+
+
+NOALLOC_BYTES = 64 << 20
+
+
+def greeks_noalloc(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, precision: int = FP64,
+                   d: int = 0, n_points: int = 0, block_threads: int = 0, owen: bool = False, out=None,
+                   stream=None):
+    """qmc_cpw_greeks_noalloc: the launch workspace in the library's fixed
+    device array (no device allocation).  out=None: host outputs, returns
+    (greeks[n][4], stderr[n][4]); out = (greeks, stderr) torch CUDA tensors:
+    written on `stream` (default: torch's current stream), returns out."""
+    specs = make_specs(options)
+    n = len(options)
+    cfg = RunConfig(precision, GEMM_FP32, -1, 1 if out is not None else 0, None, None, block_threads,
+                    FLAG_OWEN if owen else 0)
+    if out is not None:
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        cfg.stream = C.c_void_p(s.cuda_stream)
+        _check(lib().qmc_cpw_greeks_noalloc(specs, n, d, n_points, n_shifts, path, out[0].data_ptr(),
+                                            out[1].data_ptr(), C.byref(cfg)))
+        return out
+    g = np.zeros((n, 4))
+    e = np.zeros((n, 4))
+    _check(lib().qmc_cpw_greeks_noalloc(specs, n, d, n_points, n_shifts, path, g.ctypes.data, e.ctypes.data,
+                                        C.byref(cfg)))
+    return g, e
 
 
 def greeks_plain(options: Sequence[dict], n_shifts: int, path: int = PATH_BB, d: int = 0,
