@@ -169,8 +169,9 @@ template <typename R, int MODE>
 __device__ inline void consume(PathSums<R> &ps, R Y, R mf)
 {
     if (MODE == QCPW_STAT_MAX || MODE == QCPW_STAT_MIN) {
+        // bitwise, not short-circuit: two compares and selects, no branch
         const bool better = MODE == QCPW_STAT_MAX ? Y > ps.bY : Y < ps.bY;
-        const bool take = better || (Y == ps.bY && mf < ps.bm);   // lowest index wins ties
+        const bool take = better | ((Y == ps.bY) & (mf < ps.bm));   // lowest index wins ties
         ps.bY = take ? Y : ps.bY;
         ps.bm = take ? mf : ps.bm;
     } else if (MODE == QCPW_STAT_GEO) {

@@ -34,6 +34,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "qcpw_host.h"
 #include "device_math.h"
 
@@ -189,25 +191,44 @@ struct FixedU<UP, NSTEP, true> {
     __device__ __forceinline__ uint32_t rec(uint32_t y, int dim, int lane) const { return U.rec(y, dim, lane); }
 };
 
+// The normals are formed QCPW_ZB steps at a time, ahead of the bridge
+// arithmetic that consumes them (they do not depend on the path): the lane
+// words and inverse-normal cells of a batch are all read before the first is
+// used, so their LDS latencies overlap inside the wave.
+#define QCPW_ZB 4
+
+template <class UP, int N, int S0, int... I>
+__device__ __forceinline__ void fixed_zbatch(const uint32_t *row0, int lane, const FixedU<UP, N> &U, float (&zb)[QCPW_ZB],
+                                             std::integer_sequence<int, I...>)
+{
+    constexpr int dims[] = {qcpw_bridge_dim_at_step(N, S0 + I)...};
+    uint32_t w[] = {(S0 + I < N ? row0[qcpw_row_word((dims[I] > 0 ? dims[I] : 1) - 1)] : 0u)...};
+    uint32_t x[] = {U.template bits<S0 + I>(w[I])...};
+    ((S0 + I < N ? (void)U.rec(x[I], dims[I], lane) : (void)0), ...);
+    ((zb[I] = ninv_table_f32(x[I])), ...);
+}
+
 template <int MODE, class UP, int N, int LO, int HI>
 __device__ __forceinline__ void fixed_interval(const uint32_t *row0, int lane, float zs,
                                                const FixedU<UP, N> &U, float WL, float WR,
-                                               PathSums<float> &ps)
+                                               PathSums<float> &ps, float (&zb)[QCPW_ZB])
 {
     if constexpr (HI - LO >= 2) {
         constexpr int M = (LO + HI) / 2;
         constexpr int DIM = qcpw_bridge_dim(N, LO, HI);
         constexpr int S = qcpw_bridge_step(N, LO, HI);
         static_assert(DIM >= 2 && S >= 1, "interval outside the bridge");
+        static_assert(qcpw_bridge_dim_at_step(N, S) == DIM, "step order");
         constexpr float wl = (float)((double)(HI - M) / (double)(HI - LO));
         constexpr float wr = (float)((double)(M - LO) / (double)(HI - LO));
         constexpr float sd = (float)qcpw_csqrt((double)(M - LO) * (double)(HI - M) / (double)(HI - LO));
-        const uint32_t x = U.rec(U.template bits<S>(row0[qcpw_row_word(DIM - 1)]), DIM, lane);
-        const float z = ninv_table_f32(x);
+        if constexpr ((S - 1) % QCPW_ZB == 0)
+            fixed_zbatch<UP, N, S>(row0, lane, U, zb, std::make_integer_sequence<int, QCPW_ZB>());
+        const float z = zb[(S - 1) % QCPW_ZB];
         const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
         consume<float, MODE>(ps, Ym, (float)M);
-        fixed_interval<MODE, UP, N, LO, M>(row0, lane, zs, U, WL, Ym, ps);
-        fixed_interval<MODE, UP, N, M, HI>(row0, lane, zs, U, Ym, WR, ps);
+        fixed_interval<MODE, UP, N, LO, M>(row0, lane, zs, U, WL, Ym, ps, zb);
+        fixed_interval<MODE, UP, N, M, HI>(row0, lane, zs, U, Ym, WR, ps, zb);
     }
 }
 
@@ -222,7 +243,8 @@ __device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_
     const float z = ninv_table_f32(U.rec(U.template bits<0>(row0[qcpw_row_word(0)]), 1, lane));   // terminal, dimension 1
     const float WR = fmaf(sd0 * zs, z, op.ydrift_n_f);
     consume<float, MODE>(ps, WR, (float)N);
-    fixed_interval<MODE, UP, N, 0, N>(row0, lane, zs, U, 0.0f, WR, ps);
+    float zb[QCPW_ZB];
+    fixed_interval<MODE, UP, N, 0, N>(row0, lane, zs, U, 0.0f, WR, ps, zb);
 }
 
 // true if op.n has a compile-time bridge (then the path is done)
@@ -247,15 +269,19 @@ __device__ inline bool bridge_fixed_any(const OptDev &op, const uint32_t *lds_la
 // the work is that of the compile-time bridges plus one address add for its
 // lane-table row.
 
-// Register `reg` (wave-uniform) of a slot array.
+// Register `reg` (wave-uniform) of a slot array, by a tree of selects on the
+// bits of reg: an indexed read of the array would make the compiler keep it
+// in scratch memory.
 template <int NQ>
 __device__ __forceinline__ uint32_t pick_reg(const uint32_t (&V)[NQ], int reg)
 {
-    uint32_t r = V[0];
-#pragma unroll
-    for (int q = 1; q < NQ; ++q)
-        if (reg == q) r = V[q];
-    return r;
+    static_assert(NQ <= 8, "three select levels");
+    auto at = [&](int q) { return q < NQ ? V[q] : V[0]; };
+    const bool b0 = reg & 1, b1 = reg & 2, b2 = reg & 4;
+    const uint32_t a0 = b0 ? at(1) : at(0), a1 = b0 ? at(3) : at(2);
+    const uint32_t a2 = b0 ? at(5) : at(4), a3 = b0 ? at(7) : at(6);
+    const uint32_t c0 = b1 ? a1 : a0, c1 = b1 ? a3 : a2;
+    return b2 ? c1 : c0;
 }
 
 // Dimension of a lane-table word offset (probe instances only).
@@ -345,10 +371,22 @@ __device__ __forceinline__ void consume_sub(PathSums<float> &ps, SubSums &ss, fl
     }
 }
 
+// Normals of subtree nodes S0 .. S0 + QCPW_ZB - 1 (those below LEN - 1).
+template <class UP, int LEN, int S0, int... I>
+__device__ __forceinline__ void sub_zbatch(const uint32_t *E, const uint32_t *row0, int lane, const UP &U,
+                                           const SubU<UP> &su, float (&zb)[QCPW_ZB], std::integer_sequence<int, I...>)
+{
+    const uint32_t off[] = {(S0 + I < LEN - 1 ? (E[4 + (S0 + I) / 2] >> (16 * ((S0 + I) & 1))) & 0xFFFFu
+                                              : (uint32_t)QCPW_LDS_GAP_BEGIN / 4)...};
+    uint32_t x[] = {su.template bits<S0 + I>(row0[off[I]])...};
+    if constexpr (UP::PROBE) ((S0 + I < LEN - 1 ? (void)U.rec(x[I], dim_of_row_word(off[I]), lane) : (void)0), ...);
+    ((zb[I] = ninv_table_f32(x[I])), ...);
+}
+
 template <int MODE, class UP, int LEN, int LO, int HI>
 __device__ __forceinline__ void sub_interval(const uint32_t *E, const uint32_t *row0, int lane, float zs,
                                              const UP &U, const SubU<UP> &su, float WL, float WR, SubSums &ss,
-                                             PathSums<float> &ps)
+                                             PathSums<float> &ps, float (&zb)[QCPW_ZB])
 {
     if constexpr (HI - LO >= 2) {
         constexpr int M = (LO + HI) / 2;
@@ -357,14 +395,13 @@ __device__ __forceinline__ void sub_interval(const uint32_t *E, const uint32_t *
         constexpr float wl = (float)((double)(HI - M) / (double)(HI - LO));
         constexpr float wr = (float)((double)(M - LO) / (double)(HI - LO));
         constexpr float sd = (float)qcpw_csqrt((double)(M - LO) * (double)(HI - M) / (double)(HI - LO));
-        const uint32_t off = (E[4 + S / 2] >> (16 * (S & 1))) & 0xFFFFu;
-        uint32_t x = su.template bits<S>(row0[off]);
-        if constexpr (UP::PROBE) x = U.rec(x, dim_of_row_word(off), lane);
-        const float z = ninv_table_f32(x);
+        if constexpr (S % QCPW_ZB == 0)
+            sub_zbatch<UP, LEN, S>(E, row0, lane, U, su, zb, std::make_integer_sequence<int, QCPW_ZB>());
+        const float z = zb[S % QCPW_ZB];
         const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
         consume_sub<MODE, M>(ps, ss, Ym, E[3]);
-        sub_interval<MODE, UP, LEN, LO, M>(E, row0, lane, zs, U, su, WL, Ym, ss, ps);
-        sub_interval<MODE, UP, LEN, M, HI>(E, row0, lane, zs, U, su, Ym, WR, ss, ps);
+        sub_interval<MODE, UP, LEN, LO, M>(E, row0, lane, zs, U, su, WL, Ym, ss, ps, zb);
+        sub_interval<MODE, UP, LEN, M, HI>(E, row0, lane, zs, U, su, Ym, WR, ss, ps, zb);
     }
 }
 
@@ -375,7 +412,8 @@ __device__ __forceinline__ void run_subtree(const uint32_t *E, const uint32_t *r
     const uint32_t h = E[0];
     const SubU<UP> su(U, (h >> 16) & 255, h >> 24, lane);
     SubSums ss = {0.0f, 0.0f};
-    sub_interval<MODE, UP, LEN, 0, LEN>(E, row0, lane, zs, U, su, L, R, ss, ps);
+    float zb[QCPW_ZB];
+    sub_interval<MODE, UP, LEN, 0, LEN>(E, row0, lane, zs, U, su, L, R, ss, ps, zb);
     if constexpr (MODE == QCPW_STAT_AVG) {
         ps.A1 += ss.A1;
         ps.A2m += fmaf(__uint_as_float(E[2]), ss.A1, ss.A2m);
@@ -747,14 +785,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? (WID
             }
             if (base + 64 < end) step_uniform_part<PATHK>(ld, op, lane, (uint64_t)base, U);
         }
+        // the butterfly leaves the totals in every lane: lanes 0..7 store the
+        // unit's 64-byte record with one coalesced store
+        double rec = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             wave_reduce(s[i], c[i]);
-            if (lane == 0) {
-                partials[unit * 8 + i] = s[i];
-                partials[unit * 8 + 4 + i] = c[i];
-            }
+            rec = lane == i ? s[i] : lane == 4 + i ? c[i] : rec;
         }
+        if (lane < 8) partials[unit * 8 + lane] = rec;
     }
 }
 

@@ -136,6 +136,29 @@ constexpr int qcpw_bridge_step(int n, int lo, int hi)
     return -1;
 }
 
+// Sobol dimension of the midpoint the kernels visit at step S (1 <= S < n)
+// of the depth-first walk; -1 past the end.
+constexpr int qcpw_bridge_dim_at_step(int n, int S)
+{
+    int sl[64] = {}, sh[64] = {};
+    if (n > QCPW_FIXED_MAX_N) return -1;
+    int top = 0, step = 1;
+    sl[top] = 0;
+    sh[top] = n;
+    ++top;
+    while (top > 0) {
+        --top;
+        const int l = sl[top], r = sh[top];
+        if (r - l < 2) continue;
+        if (step == S) return qcpw_bridge_dim(n, l, r);
+        ++step;
+        const int m = (l + r) / 2;
+        sl[top] = m; sh[top] = r; ++top;
+        sl[top] = l; sh[top] = m; ++top;
+    }
+    return -1;
+}
+
 // One step of a bridge plan, in the order the kernel walks the bridge: the
 // intervals of the breadth-first bridge are visited depth first, so that only
 // a short stack of right end points is live at any time.  Step 0 is the
