@@ -50,10 +50,10 @@ PEAK_MFMA_BF16 = 2.5e15   # MI355X dense BF16 matrix
 # HBM bytes per launch of the fused kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a plain 1 GiB copy (profiles/), valid only for the
 # kernel sources they were taken on (sha256 prefix of their concatenation).
-TRAFFIC_SOURCES = ("kernels.hip", "device_math.h", "qcpw_internal.h", "ninv_table.inc")
+TRAFFIC_SOURCES = ("paths_kernel.h", "device_math.h", "qcpw_internal.h", "ninv_table.inc")
 TRAFFIC = {
     "portfolio": {"sha": None, "fetch": None, "write": None},
-    "three_products": {"sha": "058e69e34590da59", "fetch": 0.925e6, "write": 15.729e6},
+    "three_products": {"sha": None, "fetch": None, "write": None},
 }
 
 
@@ -455,23 +455,26 @@ def small_call_leg(q, workloads, torch, calls=200):
 def pca_leg(q, workloads, torch, steps=3):
     """Principal-component paths at d = 256 (255 x 255 factor padded to 256,
     a dense (256 x 256) x (256 x 64-point) product per tile on the matrix
-    cores): arithmetic and binary Asian, 2^22 points x 16 shifts, FP32-mixed,
-    GEMM in FP32 MFMA and in split BF16x3; kernel time from the library's
-    HIP events.  The roofline is the whole kernel's: the product's 2 n^2
-    flops per path at the FP32 matrix peak (BF16x3: three BF16 products at
-    the BF16 matrix peak), plus the VALU model (36 FP32 flops per path-date,
-    200 FP64 flops per path) at the vector peaks."""
+    cores): arithmetic and binary Asian on the same paths (one seed), 2^22
+    points x 16 shifts, FP32-mixed, GEMM in FP32 MFMA and in split BF16x3;
+    kernel time from the library's HIP events.  The two options share one
+    product and one epilogue per tile, as the configuration states (one
+    256 x 256 by 256 x 2^22 GEMM per shift, both payoffs' Greeks in its
+    epilogue), so the whole-kernel roofline counts: the product's 2 n^2
+    flops per point and shift once, at the FP32 matrix peak (BF16x3: three
+    BF16 products at the BF16 matrix peak), 36 FP32 flops per path-date of
+    the one path set, and 200 FP64 flops per path of each option."""
     opts = workloads.pca_pair(d=256, n_points=1 << 22)
     L = 16
     n = 255
-    paths = workloads.total_paths(opts, L)
-    pd = workloads.total_path_dates(opts, L)
+    paths = workloads.total_paths(opts, L)          # Greek-paths: both options
+    pd = workloads.total_path_dates(opts[:1], L)    # one shared path set
     s = torch.cuda.Stream()
     out = (torch.empty((2, 4), dtype=torch.float64, device="cuda"),
            torch.empty((2, 4), dtype=torch.float64, device="cuda"))
     res = {"workload": "arith + binary Asian, d=256, PCA, 2^22 points x 16 shifts, FP32-mixed",
            "greek_paths": paths}
-    gflop = 2.0 * n * n * paths
+    gflop = 2.0 * n * n * workloads.total_paths(opts[:1], L)   # one product per point and shift
     for name, gemm, mf, peak in (("fp32_mfma", q.GEMM_FP32, gflop, PEAK_MFMA_F32),
                                  ("bf16x3_mfma", q.GEMM_BF16X3, 3 * gflop, PEAK_MFMA_BF16)):
         wall, ev_ms, k_ms = timed_calls(q, torch, opts, L, q.PATH_PCA, q.FP32_MIXED, steps, 1, out, s,

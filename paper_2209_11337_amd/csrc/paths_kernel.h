@@ -329,14 +329,14 @@ struct SubU<UP, true> {
     }
 };
 
-// Coordinate of a top node or the terminal point (slot register and lane in
-// the event header).
+// Coordinate of a top node or the terminal point: their slots are the first
+// 2^k <= 16, all in register 0, at the lane in the event header.
 template <class UP>
 __device__ __forceinline__ uint32_t top_bits(const UP &U, uint32_t h, uint32_t lane_word)
 {
-    const int reg = (h >> 16) & 255, k = h >> 24;
-    if constexpr (UP::OWEN) return owen_scramble(lane_word ^ rdlane(pick_reg(U.U, reg), k), rdlane(pick_reg(U.Sd, reg), k));
-    else return lane_word ^ rdlane(pick_reg(U.U, reg), k);
+    const int k = h >> 24;
+    if constexpr (UP::OWEN) return owen_scramble(lane_word ^ rdlane(U.U[0], k), rdlane(U.Sd[0], k));
+    else return lane_word ^ rdlane(U.U[0], k);
 }
 
 // What a date adds to the path statistic, with its grid index given as

@@ -253,7 +253,8 @@ int build_split_plan(int n, std::vector<uint32_t> &ev, std::vector<uint16_t> &sl
         visit(m, r, level + 1);
     };
     visit(0, n, 0);
-    if (!ok || e != (2 << k) || e > QCPW_SPLIT_EVENTS) return 0;
+    // the kernel reads the terminal point's and the top nodes' parts from register 0
+    if (!ok || e != (2 << k) || e > QCPW_SPLIT_EVENTS || top_slot > 64) return 0;
     ev[8] = (uint32_t)e;
     return sub_slot;
 }
