@@ -105,6 +105,37 @@ __device__ inline float ninv_table_f32(uint32_t y)
     return fmaf(fmaf(fmaf(c.x, a, c.y), a, c.z), a, c.w);
 }
 
+// Four of them with their cell reads in flight together: the compiler, short
+// of registers, would otherwise reuse one register quadruple and wait for
+// each read before issuing the next.  The four reads and their wait are one
+// asm block (no output can be reused before its load has landed; the
+// outputs are early-clobber, so no address is overwritten by a load).
+__device__ inline void ninv_table_f32_x4(const uint32_t (&y)[4], float (&z)[4])
+{
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    float q[4];
+    uint32_t addr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        q[i] = (float)(int32_t)y[i];
+        addr[i] = (__float_as_uint(q[i]) >> 16) & 0x8FF0u;
+    }
+    f32x4 c0, c1, c2, c3;
+    asm volatile("ds_read_b128 %0, %4\n\t"
+                 "ds_read_b128 %1, %5\n\t"
+                 "ds_read_b128 %2, %6\n\t"
+                 "ds_read_b128 %3, %7\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(c0), "=&v"(c1), "=&v"(c2), "=&v"(c3)
+                 : "v"(addr[0]), "v"(addr[1]), "v"(addr[2]), "v"(addr[3]));
+    const f32x4 c[4] = {c0, c1, c2, c3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float a = fabsf(q[i]);
+        z[i] = fmaf(fmaf(fmaf(c[i].x, a, c[i].y), a, c[i].z), a, c[i].w);
+    }
+}
+
 __device__ inline float exp2_r(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline double exp2_r(double x) { return exp2(x); }
 

@@ -292,17 +292,21 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         }
         cost[i] = (double)std::max(op.ndims, 1) * (double)op.chunks;
         lp.max_n = std::max(lp.max_n, op.ndims);
-        // options walked by a compile-time bridge or the split bridge need no LDS stack
-        const bool f32 = precision == QCPW_FP32_MIXED;
-        const bool fixed = f32 && fixed_bridges_on() && qcpw_has_fixed_bridge(op.n);
+    }
+    // the lane rows of more than QCPW_WIDE_MIN_N dimensions leave room for one
+    // 1024-thread workgroup per CU: 4 waves per SIMD, so 128 VGPRs cost nothing
+    const bool f32 = precision == QCPW_FP32_MIXED;
+    lp.wide = f32 && lp.max_n > QCPW_WIDE_MIN_N;
+    for (int i = 0; i < n_opts; ++i) {
+        OptDev &op = opts[i];
+        // options walked by a compile-time bridge (not in wide instances) or the
+        // split bridge need no LDS stack
+        const bool fixed = f32 && !lp.wide && fixed_bridges_on() && qcpw_has_fixed_bridge(op.n);
         op.split = (path == QCPW_PATH_BB && f32 && !fixed && split_bridge_on() && ctx->tab.split_slots[op.n] > 0) ? 1 : 0;
         op.n_slots = op.split ? ctx->tab.split_slots[op.n] : op.ndims;
         if (path == QCPW_PATH_BB && op.n >= 1 && !fixed && !op.split)
             lp.stack_depth = std::max(lp.stack_depth, ctx->tab.depth[op.n]);
     }
-    // the lane rows of more than QCPW_WIDE_MIN_N dimensions leave room for one
-    // 1024-thread workgroup per CU: 4 waves per SIMD, so 128 VGPRs cost nothing
-    lp.wide = precision == QCPW_FP32_MIXED && lp.max_n > QCPW_WIDE_MIN_N;
     // Matrix-core PCA: options whose paths are identical -- same n, seed and
     // point range, same z scale and drift, same path statistic (they differ
     // in strike or payoff) -- share one product and one epilogue per tile;

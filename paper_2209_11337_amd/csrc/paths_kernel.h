@@ -142,6 +142,28 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
     }
 }
 
+// Sums of one subtree kept apart: sum E and sum E (m - l) with m - l a
+// literal; folded into the path's sums (sum E m = l sum E + sum E (m - l))
+// when the subtree ends.
+struct SubSums {
+    float A1, A2m;
+};
+
+template <int MODE, int M>
+__device__ __forceinline__ void consume_sub(PathSums<float> &ps, SubSums &ss, float Y, uint32_t mb_bits_l)
+{
+    if constexpr (MODE == QCPW_STAT_AVG) {
+        const float E = exp2_r(Y);
+        ss.A1 += E;
+        ps.A2y = fmaf(E, Y, ps.A2y);
+        ss.A2m = fmaf(E, (float)M, ss.A2m);
+    } else if constexpr (MODE == QCPW_STAT_GEO) {
+        ps.A2y += Y;
+    } else {
+        consume<float, MODE>(ps, Y, __uint_as_float(mb_bits_l + (uint32_t)M));
+    }
+}
+
 // ---- compile-time bridges ------------------------------------------------
 // For n = 15, 31, 63, 127 (d = 16, 32, 64, 128) the bridge is unrolled at
 // compile time: the depth-first walk becomes template recursion over the
@@ -149,9 +171,11 @@ __device__ inline void run_bridge_wave(const LaunchDesc &ld, const OptDev &op, c
 // no register shuffles), lane-table rows and U lanes are immediates, and the
 // weights are literals.  The intervals, dimensions, step order, weights and
 // formulas are those of the run-time plan (the host checks the plan against
-// the same constexpr functions); price, delta and gamma come out bit-identical
-// to the plan walker's, vega (from the FP32 sums of E Y and E m) within FP32
-// rounding.  Removes about a quarter of the VALU work per date.
+// the same constexpr functions), and the arithmetic average's sums are folded
+// per subtree as in the split bridge: the results are bit-identical to the
+// split bridge's for the same n, which the 128-VGPR instances use for these
+// n instead (so an option gives the same bits whatever launch it is in).
+// Removes about a quarter of the VALU work per date.
 // The wave-uniform parts as the compile-time bridges read them.  Without
 // scrambling they are copied once per 64 points into every row of 16 lanes
 // (lane l of R[i] holds step 16 i + l mod 16), so that a DPP row broadcast
@@ -197,6 +221,20 @@ struct FixedU<UP, NSTEP, true> {
 // used, so their LDS latencies overlap inside the wave.
 #define QCPW_ZB 4
 
+// Four normals of a batch.  Wide instances (128 VGPRs) keep the four cell
+// reads in flight together; in the others the extra registers would push
+// the wave-uniform state into scratch, so each read is waited for alone.
+template <class UP>
+__device__ __forceinline__ void ninv_batch(const uint32_t (&x)[4], float (&zb)[4])
+{
+    if constexpr (UP::NQ > QCPW_UQ) {
+        ninv_table_f32_x4(x, zb);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) zb[i] = ninv_table_f32(x[i]);
+    }
+}
+
 template <class UP, int N, int S0, int... I>
 __device__ __forceinline__ void fixed_zbatch(const uint32_t *row0, int lane, const FixedU<UP, N> &U, float (&zb)[QCPW_ZB],
                                              std::integer_sequence<int, I...>)
@@ -205,15 +243,24 @@ __device__ __forceinline__ void fixed_zbatch(const uint32_t *row0, int lane, con
     uint32_t w[] = {(S0 + I < N ? row0[qcpw_row_word((dims[I] > 0 ? dims[I] : 1) - 1)] : 0u)...};
     uint32_t x[] = {U.template bits<S0 + I>(w[I])...};
     ((S0 + I < N ? (void)U.rec(x[I], dims[I], lane) : (void)0), ...);
-    ((zb[I] = ninv_table_f32(x[I])), ...);
+    ninv_batch<UP>(x, zb);
 }
 
-template <int MODE, class UP, int N, int LO, int HI>
+// LEVEL: depth of the interval (LO, HI); L0: left end of the subtree it
+// lies in (-1 above the split bridge's subtree level).  The arithmetic
+// average's sums of a subtree are kept apart and folded in when it ends, as
+// the split bridge does, so that both walks of n give the same bits.
+template <int MODE, class UP, int N, int LO, int HI, int LEVEL, int L0>
 __device__ __forceinline__ void fixed_interval(const uint32_t *row0, int lane, float zs,
                                                const FixedU<UP, N> &U, float WL, float WR,
-                                               PathSums<float> &ps, float (&zb)[QCPW_ZB])
+                                               PathSums<float> &ps, SubSums &ss, float (&zb)[QCPW_ZB])
 {
-    if constexpr (HI - LO >= 2) {
+    if constexpr (MODE == QCPW_STAT_AVG && L0 < 0 && LEVEL == qcpw_split_level(N)) {
+        SubSums sub = {0.0f, 0.0f};
+        fixed_interval<MODE, UP, N, LO, HI, LEVEL, LO>(row0, lane, zs, U, WL, WR, ps, sub, zb);
+        ps.A1 += sub.A1;
+        ps.A2m += fmaf((float)LO, sub.A1, sub.A2m);
+    } else if constexpr (HI - LO >= 2) {
         constexpr int M = (LO + HI) / 2;
         constexpr int DIM = qcpw_bridge_dim(N, LO, HI);
         constexpr int S = qcpw_bridge_step(N, LO, HI);
@@ -226,9 +273,10 @@ __device__ __forceinline__ void fixed_interval(const uint32_t *row0, int lane, f
             fixed_zbatch<UP, N, S>(row0, lane, U, zb, std::make_integer_sequence<int, QCPW_ZB>());
         const float z = zb[(S - 1) % QCPW_ZB];
         const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
-        consume<float, MODE>(ps, Ym, (float)M);
-        fixed_interval<MODE, UP, N, LO, M>(row0, lane, zs, U, WL, Ym, ps, zb);
-        fixed_interval<MODE, UP, N, M, HI>(row0, lane, zs, U, Ym, WR, ps, zb);
+        if constexpr (L0 >= 0) consume_sub<MODE, M - L0>(ps, ss, Ym, 0u);
+        else consume<float, MODE>(ps, Ym, (float)M);
+        fixed_interval<MODE, UP, N, LO, M, LEVEL + 1, L0>(row0, lane, zs, U, WL, Ym, ps, ss, zb);
+        fixed_interval<MODE, UP, N, M, HI, LEVEL + 1, L0>(row0, lane, zs, U, Ym, WR, ps, ss, zb);
     }
 }
 
@@ -244,7 +292,8 @@ __device__ __forceinline__ void run_bridge_fixed(const OptDev &op, const uint32_
     const float WR = fmaf(sd0 * zs, z, op.ydrift_n_f);
     consume<float, MODE>(ps, WR, (float)N);
     float zb[QCPW_ZB];
-    fixed_interval<MODE, UP, N, 0, N>(row0, lane, zs, U, 0.0f, WR, ps, zb);
+    SubSums ss = {0.0f, 0.0f};
+    fixed_interval<MODE, UP, N, 0, N, 0, -1>(row0, lane, zs, U, 0.0f, WR, ps, ss, zb);
 }
 
 // true if op.n has a compile-time bridge (then the path is done)
@@ -349,28 +398,6 @@ __device__ __forceinline__ void consume_ev(PathSums<float> &ps, float Y, uint32_
     else consume<float, MODE>(ps, Y, __uint_as_float(mf_bits));
 }
 
-// Sums of one subtree kept apart: sum E and sum E (m - l) with m - l a
-// literal; folded into the path's sums (sum E m = l sum E + sum E (m - l))
-// when the subtree ends.
-struct SubSums {
-    float A1, A2m;
-};
-
-template <int MODE, int M>
-__device__ __forceinline__ void consume_sub(PathSums<float> &ps, SubSums &ss, float Y, uint32_t mb_bits_l)
-{
-    if constexpr (MODE == QCPW_STAT_AVG) {
-        const float E = exp2_r(Y);
-        ss.A1 += E;
-        ps.A2y = fmaf(E, Y, ps.A2y);
-        ss.A2m = fmaf(E, (float)M, ss.A2m);
-    } else if constexpr (MODE == QCPW_STAT_GEO) {
-        ps.A2y += Y;
-    } else {
-        consume<float, MODE>(ps, Y, __uint_as_float(mb_bits_l + (uint32_t)M));
-    }
-}
-
 // Normals of subtree nodes S0 .. S0 + QCPW_ZB - 1 (those below LEN - 1).
 template <class UP, int LEN, int S0, int... I>
 __device__ __forceinline__ void sub_zbatch(const uint32_t *E, const uint32_t *row0, int lane, const UP &U,
@@ -380,7 +407,7 @@ __device__ __forceinline__ void sub_zbatch(const uint32_t *E, const uint32_t *ro
                                               : (uint32_t)QCPW_LDS_GAP_BEGIN / 4)...};
     uint32_t x[] = {su.template bits<S0 + I>(row0[off[I]])...};
     if constexpr (UP::PROBE) ((S0 + I < LEN - 1 ? (void)U.rec(x[I], dim_of_row_word(off[I]), lane) : (void)0), ...);
-    ((zb[I] = ninv_table_f32(x[I])), ...);
+    ninv_batch<UP>(x, zb);
 }
 
 template <int MODE, class UP, int LEN, int LO, int HI>
@@ -568,14 +595,15 @@ __device__ inline void run_basket_wave(const OptDev &op, const uint32_t *lds_lan
 
 // One wave's 64 paths from the terminal point (bridge) or the first step
 // (standard) to the last date, accumulated into ps.
-template <bool F32, int PATHK, int MODE, class UP>
+template <bool F32, int PATHK, int MODE, bool FIXED, class UP>
 __device__ inline void walk_path(const LaunchDesc &ld, const OptDev &op, const uint32_t *lds_lane,
                                  typename Real<F32>::T *stk, int lane,
                                  const UP &U, PathSums<typename Real<F32>::T> &ps, int fixed_bridges)
 {
     if constexpr (PATHK == QCPW_PATH_BB) {
         if constexpr (F32) {
-            if (fixed_bridges && bridge_fixed_any<MODE>(op, lds_lane, lane, U, ps)) return;
+            if constexpr (FIXED)
+                if (fixed_bridges && bridge_fixed_any<MODE>(op, lds_lane, lane, U, ps)) return;
             if (op.split) {
                 run_bridge_split<MODE>(ld, op, lds_lane, lane, U, ps);
                 return;
@@ -660,7 +688,9 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
 // WIDE instances (FP32, launches whose lane rows leave room for at most one
 // 1024-thread workgroup per CU, i.e. 4 waves per SIMD anyway) may use 128
 // VGPRs and hold 8 registers of wave-uniform slots, which the split bridge
-// needs beyond n = 356.
+// needs beyond n = 356; they walk n = 15, 31, 63, 127 with the split bridge
+// too (the compile-time bridges would raise the register need of the whole
+// kernel).
 template <bool F32, int PATHK, bool OWEN, bool PROBE, bool WIDE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? (WIDE ? 4 : 6) : 1))) void paths_kernel(
     const OptDev *__restrict__ opts, const int64_t *__restrict__ unit_prefix, const PlanStep *__restrict__ plan_all,
@@ -766,16 +796,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? (WID
             if (op.ndims > 0) {
                 switch (PROBE ? QCPW_STAT_AVG : mode) {
                 case QCPW_STAT_MAX:
-                    walk_path<F32, PATHK, QCPW_STAT_MAX>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, QCPW_STAT_MAX, !WIDE>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
                 case QCPW_STAT_GEO:
-                    walk_path<F32, PATHK, QCPW_STAT_GEO>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, QCPW_STAT_GEO, !WIDE>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
                 case QCPW_STAT_MIN:
-                    walk_path<F32, PATHK, QCPW_STAT_MIN>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, QCPW_STAT_MIN, !WIDE>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                     break;
                 default:
-                    walk_path<F32, PATHK, QCPW_STAT_AVG>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
+                    walk_path<F32, PATHK, QCPW_STAT_AVG, !WIDE>(ld, op, lds_lane, stk, lane, U, ps, fixed_bridges);
                 }
             }
             if (valid) {

@@ -203,6 +203,14 @@ struct PlanStep64 {
 #define QCPW_EV_WORDS 16         // one 64-byte event, one scalar load
 #define QCPW_WIDE_MIN_N 288      // FP32 launches with more lane rows use the 128-VGPR kernel instances
 
+// The level k at which the split bridge of n starts its subtrees.
+__host__ __device__ constexpr int qcpw_split_level(int n)
+{
+    int k = 0;
+    while (((n + (1 << k) - 1) >> k) > QCPW_SUB_MAX_LEN) ++k;
+    return k;
+}
+
 // Event header (word 0): kind, subtree length, slot register and lane.
 enum { QCPW_EV_TERMINAL = 0, QCPW_EV_TOP = 1, QCPW_EV_SUB = 2 };
 __host__ __device__ constexpr uint32_t qcpw_ev_header(int kind, int len, int reg, int lane)

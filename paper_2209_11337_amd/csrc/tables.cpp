@@ -187,8 +187,7 @@ int build_split_plan(int n, std::vector<uint32_t> &ev, std::vector<uint16_t> &sl
     ev.assign((size_t)QCPW_SPLIT_EVENTS * QCPW_EV_WORDS, 0u);
     slot_dim.assign(QCPW_SPLIT_SLOTS, 0);
     if (n < QCPW_SUB_MIN_LEN || n > QCPW_MAX_N) return 0;
-    int k = 0;
-    while (((n + (1 << k) - 1) >> k) > QCPW_SUB_MAX_LEN) ++k;
+    const int k = qcpw_split_level(n);
     const auto dim_of = bridge_dims(n);
     int e = 0, top_slot = 0, sub_slot = 1 << k;
     bool ok = true;

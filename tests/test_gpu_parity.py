@@ -194,6 +194,25 @@ def test_fp32_mixed_portfolio_within_bound():
 # ------------------------------------------------------------------------
 # batching
 # ------------------------------------------------------------------------
+@pytest.mark.parametrize("typ", [q.ARITH_ASIAN, q.BINARY_ASIAN, q.LOOKBACK])
+def test_same_bits_in_narrow_and_wide_launches(typ):
+    """An option gives the same bits alone (a launch whose lane rows fit
+    several workgroups per CU) and beside a d = 365 option (the 128-VGPR
+    kernel instances): d = 16, 32, 64, 128 are walked by the compile-time
+    bridges in one and by the split bridge in the other, d = 8 by the plan
+    walker, d = 40 and 200 by the split bridge in both."""
+    ds = (8, 16, 32, 40, 64, 128, 200)
+    opts = [dict(type=typ, d=d, S0=100.0, K=95.0 + 2 * i, r=0.05, sigma=0.25, T=1.0,
+                 seed=1000 + d, n_points=1 << 12) for i, d in enumerate(ds)]
+    big = dict(type=q.ARITH_ASIAN, d=365, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0,
+               seed=5, n_points=1 << 10)
+    say("narrow/wide invariance", typ)
+    g_mix, e_mix = q.greeks(opts + [big], 4, q.PATH_BB, q.FP32_MIXED)
+    for i, o in enumerate(opts):
+        g1, e1 = q.greeks([o], 4, q.PATH_BB, q.FP32_MIXED)
+        assert np.array_equal(g1[0], g_mix[i]) and np.array_equal(e1[0], e_mix[i]), (o["d"], g1[0], g_mix[i])
+
+
 @pytest.mark.parametrize("prec", [q.FP64, q.FP32_MIXED])
 def test_each_option_same_alone_and_in_a_mix(prec):
     mix = workloads.portfolio(40, seed=7, log2_points=(10, 14))
