@@ -272,7 +272,7 @@ __device__ __forceinline__ void fixed_interval(const uint32_t *row0, int lane, f
         if constexpr ((S - 1) % QCPW_ZB == 0)
             fixed_zbatch<UP, N, S>(row0, lane, U, zb, std::make_integer_sequence<int, QCPW_ZB>());
         const float z = zb[(S - 1) % QCPW_ZB];
-        const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
+        const float Ym = fmaf(__fmul_rn(sd, zs), z, fmaf(wr, WR, wl * WL));   // as the split bridge
         if constexpr (L0 >= 0) consume_sub<MODE, M - L0>(ps, ss, Ym, 0u);
         else consume<float, MODE>(ps, Ym, (float)M);
         fixed_interval<MODE, UP, N, LO, M, LEVEL + 1, L0>(row0, lane, zs, U, WL, Ym, ps, ss, zb);
@@ -425,7 +425,9 @@ __device__ __forceinline__ void sub_interval(const uint32_t *E, const uint32_t *
         if constexpr (S % QCPW_ZB == 0)
             sub_zbatch<UP, LEN, S>(E, row0, lane, U, su, zb, std::make_integer_sequence<int, QCPW_ZB>());
         const float z = zb[S % QCPW_ZB];
-        const float Ym = fmaf(sd, __fmul_rn(z, zs), fmaf(wr, WR, wl * WL));   // no contraction: as the plan walker
+        // sd zs rounded first: the product depends on the interval length
+        // alone, so the few distinct lengths of a subtree share it
+        const float Ym = fmaf(__fmul_rn(sd, zs), z, fmaf(wr, WR, wl * WL));
         consume_sub<MODE, M>(ps, ss, Ym, E[3]);
         sub_interval<MODE, UP, LEN, LO, M>(E, row0, lane, zs, U, su, WL, Ym, ss, ps, zb);
         sub_interval<MODE, UP, LEN, M, HI>(E, row0, lane, zs, U, su, Ym, WR, ss, ps, zb);
@@ -474,7 +476,7 @@ __device__ inline void run_bridge_split(const LaunchDesc &ld, const OptDev &op, 
             uint32_t x = top_bits(U, h, row0[E[4]]);
             if constexpr (UP::PROBE) x = U.rec(x, dim_of_row_word(E[4]), lane);
             const float z = ninv_table_f32(x);
-            const float M = fmaf(__uint_as_float(E[7]), __fmul_rn(z, zs),
+            const float M = fmaf(__fmul_rn(__uint_as_float(E[7]), zs), z,
                                  fmaf(__uint_as_float(E[6]), R, __uint_as_float(E[5]) * L));
             consume_ev<MODE>(ps, M, E[2], E[3]);
             switch (sp) {
