@@ -52,8 +52,8 @@ PEAK_MFMA_BF16 = 2.5e15   # MI355X dense BF16 matrix
 # kernel sources they were taken on (sha256 prefix of their concatenation).
 TRAFFIC_SOURCES = ("paths_kernel.h", "device_math.h", "qcpw_internal.h", "ninv_table.inc")
 TRAFFIC = {
-    "portfolio": {"sha": None, "fetch": None, "write": None},
-    "three_products": {"sha": None, "fetch": None, "write": None},
+    "portfolio": {"sha": "c2a38747a8ada59a", "fetch": 1145841105, "write": 1329002528},
+    "three_products": {"sha": "c2a38747a8ada59a", "fetch": 18244292, "write": 20448288},
 }
 
 
