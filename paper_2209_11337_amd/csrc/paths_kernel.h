@@ -224,14 +224,16 @@ struct FixedU<UP, NSTEP, true> {
 // Four normals of a batch.  Wide instances (128 VGPRs) keep the four cell
 // reads in flight together; in the others the extra registers would push
 // the wave-uniform state into scratch, so each read is waited for alone.
-template <class UP>
+// CNT: the batch's normals that are used (the last batch of a walk may be
+// partial; the others are neither read nor formed).
+template <class UP, int CNT = 4>
 __device__ __forceinline__ void ninv_batch(const uint32_t (&x)[4], float (&zb)[4])
 {
-    if constexpr (UP::NQ > QCPW_UQ) {
+    if constexpr (UP::NQ > QCPW_UQ && CNT == 4) {
         ninv_table_f32_x4(x, zb);
     } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) zb[i] = ninv_table_f32(x[i]);
+        for (int i = 0; i < CNT; ++i) zb[i] = ninv_table_f32(x[i]);
     }
 }
 
@@ -243,7 +245,7 @@ __device__ __forceinline__ void fixed_zbatch(const uint32_t *row0, int lane, con
     uint32_t w[] = {(S0 + I < N ? row0[qcpw_row_word((dims[I] > 0 ? dims[I] : 1) - 1)] : 0u)...};
     uint32_t x[] = {U.template bits<S0 + I>(w[I])...};
     ((S0 + I < N ? (void)U.rec(x[I], dims[I], lane) : (void)0), ...);
-    ninv_batch<UP>(x, zb);
+    ninv_batch<UP, (N - S0 < QCPW_ZB ? N - S0 : QCPW_ZB)>(x, zb);
 }
 
 // LEVEL: depth of the interval (LO, HI); L0: left end of the subtree it
@@ -354,9 +356,12 @@ struct SubU<UP, false> {
     uint32_t R0, R1;
     __device__ __forceinline__ SubU(const UP &U, int reg, int base, int lane)
     {
+        // lane l reads lane base + 16 i + l % 16 (ds_bpermute takes the lane
+        // from address bits 2..7: no wrap-around arithmetic needed)
         const int u = (int)pick_reg(U.U, reg);
-        R0 = (uint32_t)__shfl(u, base + (lane & 15), 64);
-        R1 = (uint32_t)__shfl(u, base + 16 + (lane & 15), 64);
+        const int a = (lane & 15) * 4;
+        R0 = (uint32_t)__builtin_amdgcn_ds_bpermute(a + base * 4, u);
+        R1 = (uint32_t)__builtin_amdgcn_ds_bpermute(a + base * 4 + 64, u);
     }
     template <int S>
     __device__ __forceinline__ uint32_t bits(uint32_t lane_word) const
@@ -407,7 +412,7 @@ __device__ __forceinline__ void sub_zbatch(const uint32_t *E, const uint32_t *ro
                                               : (uint32_t)QCPW_LDS_GAP_BEGIN / 4)...};
     uint32_t x[] = {su.template bits<S0 + I>(row0[off[I]])...};
     if constexpr (UP::PROBE) ((S0 + I < LEN - 1 ? (void)U.rec(x[I], dim_of_row_word(off[I]), lane) : (void)0), ...);
-    ninv_batch<UP>(x, zb);
+    ninv_batch<UP, (LEN - 1 - S0 < QCPW_ZB ? LEN - 1 - S0 : QCPW_ZB)>(x, zb);
 }
 
 template <int MODE, class UP, int LEN, int LO, int HI>
