@@ -269,9 +269,10 @@ __device__ inline double ln_f64(double x)
     return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * p));
 }
 
-// exp x for x <= 0 (underflows to 0 below about -745): x = k ln 2 + r,
-// |r| <= ln2/2, e^r by its Taylor series to r^13, scaled by 2^k.
-__device__ inline double exp_neg_f64(double x)   // any |x| < 700 (named for its use on -psi^2/2)
+// exp x for |x| < 700 (beyond, below about -745 it underflows to 0):
+// x = k ln 2 + r, |r| <= ln2/2, e^r by its Taylor series to r^13, scaled by
+// 2^k.
+__device__ inline double exp_f64(double x)
 {
     const double k = rint(x * 1.44269504088896340736);
     double r = fma(-k, 6.93147180369123816490e-01, x);
@@ -298,6 +299,19 @@ __device__ inline double erfcx_f64(double x)
     return t * p;
 }
 
+// erfc x for finite or infinite x: erfcx(|x|) e^{-x^2} with x^2 split into
+// its rounded value and the rounding error (e^{-x^2} keeps its relative
+// accuracy for large |x|), and 2 - that for x < 0.
+__device__ inline double erfc_f64(double x)
+{
+    const double a = fabs(x);
+    const double a2 = a * a;
+    if (!(a2 < 745.0)) return a2 == a2 ? (x < 0.0 ? 2.0 : 0.0) : x;   // underflow; NaN stays NaN
+    const double e = exp_f64(-a2) * (1.0 - fma(a, a, -a2));
+    const double r = erfcx_f64(a) * e;
+    return x < 0.0 ? 2.0 - r : r;
+}
+
 // Phi^{-1}((y + 1/2) 2^-32) in FP64 for the raw 32-bit Sobol coordinate y.
 // On the lower half (m = min(y, ~y), u = (m + 1/2) 2^-32 <= 1/2, z <= 0,
 // so 1 - u is never formed) the FP32 estimate z0 (about 1e-6 relative) is
@@ -312,7 +326,7 @@ __device__ inline double ninv_f64(uint32_t y)
     const uint32_t m = (y >> 31) ? ~y : y;
     const double u = ((double)m + 0.5) * 0x1p-32;
     const double z0 = (double)ninv_scaled_f32(m, (float)(M_SQRT2 * 0x1p-31));   // <= 0
-    const double ez = exp_neg_f64(0.5 * z0 * z0);                                 // e^{+z0^2/2}
+    const double ez = exp_f64(0.5 * z0 * z0);                                 // e^{+z0^2/2}
     const double ex = erfcx_f64(-z0 * M_SQRT1_2);
     const double rho = 2.50662827463100050242 * fma(0.5, ex, -u * ez);
     const double z = z0 - rho + 0.5 * z0 * rho * rho;
@@ -337,7 +351,7 @@ __device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, dou
     const OptDev &op = *reread(&op_in);
     const double psi = (op.c0 - ln_f64(A)) * op.inv_s1;
     const double psi1 = psi - op.s1;
-    const double g0 = exp_neg_f64(-0.5 * psi * psi);
+    const double g0 = exp_f64(-0.5 * psi * psi);
     const double invA = recip_f64(A);
     const double e0 = 0.5 * g0 * erfcx_f64(fabs(psi) * M_SQRT1_2);
     const double e1 = 0.5 * (g0 * op.h * invA) * erfcx_f64(fabs(psi1) * M_SQRT1_2);
@@ -375,7 +389,7 @@ __device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, int
     } else if (mode == QCPW_STAT_GEO) {
         // X/S0 = 2^{mean Y}; sum over dates of (W~ - sigma tau) = (sum Y - kappa sum m)/(sigma log2 e)
         const double sy = (double)ps.A2y;
-        A = exp_neg_f64(sy * op.invd * 0.69314718055994530942);
+        A = exp_f64(sy * op.invd * 0.69314718055994530942);
         Xs = A;
         VXs = A * (sy - op.kappa * 0.5 * (double)op.n * (double)(op.n + 1)) * op.invd * op.inv_sig_log2e;
     } else {
