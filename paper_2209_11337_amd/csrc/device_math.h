@@ -222,11 +222,15 @@ __device__ inline void consume(PathSums<R> &ps, R Y, R mf)
 // each coefficient to the previous Horner value, so the compiler materialises
 // it (two scalar moves) just before its use instead of hoisting all of them
 // into ~80 registers held across the point loop, which would halve the
-// kernel's occupancy.
+// kernel's occupancy.  ORDERED = false drops the asm's volatile: the tie
+// stays, but two independent evaluations may then interleave (with volatile
+// their empty asms keep program order, which serialises the chains).
+template <bool ORDERED = true>
 __device__ inline double coef_after(double c, double dep)
 {
     uint64_t b = __builtin_bit_cast(uint64_t, c);
-    asm volatile("" : "+s"(b) : "v"(dep));
+    if constexpr (ORDERED) asm volatile("" : "+s"(b) : "v"(dep));
+    else asm("" : "+s"(b) : "v"(dep));
     return __builtin_bit_cast(double, b);
 }
 
@@ -252,6 +256,7 @@ __device__ inline double recip_f64(double d)
 // ln x for finite x > 0: x = 2^e m, m in [sqrt(1/2), sqrt(2)),
 // ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^23/23), s = (m - 1)/(m + 1),
 // |s| <= 0.1716; ln 2 split so that e ln2_hi is exact.
+template <bool ORDERED = true>
 __device__ inline double ln_f64(double x)
 {
     int e;
@@ -264,7 +269,7 @@ __device__ inline double ln_f64(double x)
     const double z = s * s;
     double p = 1.0 / 23.0;
 #pragma unroll
-    for (int k = 21; k >= 1; k -= 2) p = fma(p, z, coef_after(1.0 / k, p));
+    for (int k = 21; k >= 1; k -= 2) p = fma(p, z, coef_after<ORDERED>(1.0 / k, p));
     const double de = (double)e;
     return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * p));
 }
@@ -272,6 +277,7 @@ __device__ inline double ln_f64(double x)
 // exp x for |x| < 700 (beyond, below about -745 it underflows to 0):
 // x = k ln 2 + r, |r| <= ln2/2, e^r by its Taylor series to r^13, scaled by
 // 2^k.
+template <bool ORDERED = true>
 __device__ inline double exp_f64(double x)
 {
     const double k = rint(x * 1.44269504088896340736);
@@ -282,33 +288,35 @@ __device__ inline double exp_f64(double x)
 #pragma unroll
     for (int j = 12; j >= 0; --j) {
         f /= (j + 1);                 // j! (compile-time constant after unrolling)
-        p = fma(p, r, coef_after(1.0 / f, p));
+        p = fma(p, r, coef_after<ORDERED>(1.0 / f, p));
     }
     return ldexp(p, (int)k);
 }
 
 // erfcx(x) = exp(x^2) erfc(x) for x >= 0: t P(t), t = 3/(3 + x)
 // (phi_f64_coeffs.inc).
+template <bool ORDERED = true>
 __device__ inline double erfcx_f64(double x)
 {
     const double t = QCPW_ERFCX_C * recip_f64(QCPW_ERFCX_C + x);
-    double p = coef_after(QCPW_ERFCX_P[0], t);
+    double p = coef_after<ORDERED>(QCPW_ERFCX_P[0], t);
 #pragma unroll
     for (int i = 1; i < (int)(sizeof(QCPW_ERFCX_P) / sizeof(double)); ++i)
-        p = fma(p, t, coef_after(QCPW_ERFCX_P[i], p));
+        p = fma(p, t, coef_after<ORDERED>(QCPW_ERFCX_P[i], p));
     return t * p;
 }
 
 // erfc x for finite or infinite x: erfcx(|x|) e^{-x^2} with x^2 split into
 // its rounded value and the rounding error (e^{-x^2} keeps its relative
 // accuracy for large |x|), and 2 - that for x < 0.
+template <bool ORDERED = true>
 __device__ inline double erfc_f64(double x)
 {
     const double a = fabs(x);
     const double a2 = a * a;
     if (!(a2 < 745.0)) return a2 == a2 ? (x < 0.0 ? 2.0 : 0.0) : x;   // underflow; NaN stays NaN
-    const double e = exp_f64(-a2) * (1.0 - fma(a, a, -a2));
-    const double r = erfcx_f64(a) * e;
+    const double e = exp_f64<ORDERED>(-a2) * (1.0 - fma(a, a, -a2));
+    const double r = erfcx_f64<ORDERED>(a) * e;
     return x < 0.0 ? 2.0 - r : r;
 }
 

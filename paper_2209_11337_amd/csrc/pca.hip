@@ -195,8 +195,8 @@ __device__ inline void tile_tail(const OptDev &op, const PcaSums<R> *red, int la
 // relative accuracy.
 __device__ inline double norm_interval(double lo, double hi)
 {
-    if (lo >= 0.0) return 0.5 * erfc_f64(lo * M_SQRT1_2) - (isinf(hi) ? 0.0 : 0.5 * erfc_f64(hi * M_SQRT1_2));
-    return (isinf(hi) ? 1.0 : 0.5 * erfc_f64(-hi * M_SQRT1_2)) - 0.5 * erfc_f64(-lo * M_SQRT1_2);
+    if (lo >= 0.0) return 0.5 * erfc_f64<false>(lo * M_SQRT1_2) - (isinf(hi) ? 0.0 : 0.5 * erfc_f64<false>(hi * M_SQRT1_2));
+    return (isinf(hi) ? 1.0 : 0.5 * erfc_f64<false>(-hi * M_SQRT1_2)) - 0.5 * erfc_f64<false>(-lo * M_SQRT1_2);
 }
 
 // Lookback (call on the discrete maximum) conditioned on the first principal
@@ -221,7 +221,7 @@ __device__ inline void full_lookback_tail(const OptDev &op, YF y, int part, doub
     const double sdt = op.zscale * LN2;     // sigma sqrt(dt)
     const double wdt = op.ydrift_1 * LN2;   // omega dt
     const double dt = op.sqrt_t1 * op.sqrt_t1;
-    const double lnS0 = ln_f64(op.S0), K = op.K, lnK = ln_f64(op.K);
+    const double lnS0 = ln_f64<false>(op.S0), K = op.K, lnK = ln_f64<false>(op.K);
     const double *a1 = op.pca_a1;
     auto alpha = [&](int j) { return lnS0 + wdt * (j + 1) + LN2 * y(j); };
     auto beta = [&](int j) { return sdt * a1[j]; };
@@ -269,10 +269,10 @@ __device__ inline void full_lookback_tail(const OptDev &op, YF y, int part, doub
         }
         pick(x1, jn, bn);
         if (x1 < x0) x1 = x0;   // a line crossing at x0 itself (rounding)
-        const double E = exp_f64(aj + 0.5 * bj * bj);
+        const double E = exp_f64<false>(aj + 0.5 * bj * bj);
         const double dP = norm_interval(x0 - bj, x1 - bj);
-        const double fa = 0.39894228040143267794 * exp_f64(-0.5 * (x0 - bj) * (x0 - bj));
-        const double fb = isinf(x1) ? 0.0 : 0.39894228040143267794 * exp_f64(-0.5 * (x1 - bj) * (x1 - bj));
+        const double fa = 0.39894228040143267794 * exp_f64<false>(-0.5 * (x0 - bj) * (x0 - bj));
+        const double fb = isinf(x1) ? 0.0 : 0.39894228040143267794 * exp_f64<false>(-0.5 * (x1 - bj) * (x1 - bj));
         const double das = LN2 * y(j) / sig - sig * dt * (j + 1);   // c_j - sigma t_j
         G += E * dP - K * norm_interval(x0, x1);
         dl += E * dP;
@@ -286,7 +286,7 @@ __device__ inline void full_lookback_tail(const OptDev &op, YF y, int part, doub
     F[0] = D * G;
     F[1] = D * dl / S0;
     F[2] = D * vg;
-    F[3] = D * K * 0.39894228040143267794 * exp_f64(-0.5 * psi * psi) / (S0 * S0 * bstar);
+    F[3] = D * K * 0.39894228040143267794 * exp_f64<false>(-0.5 * psi * psi) / (S0 * S0 * bstar);
 }
 
 template <int PARTS, typename YF>
@@ -302,7 +302,7 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
     const double sdt = op.zscale * LN2;     // sigma sqrt(dt)
     const double wdt = op.ydrift_1 * LN2;   // omega dt
     const double dt = op.sqrt_t1 * op.sqrt_t1;
-    const double lnS0 = ln_f64(op.S0), K = op.K;
+    const double lnS0 = ln_f64<false>(op.S0), K = op.K;
     const double *a1 = op.pca_a1;
     auto quad_sum = [](double v) {          // the same bits in all PARTS threads of the point
 #pragma unroll
@@ -316,8 +316,8 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
     }
     sa = quad_sum(sa);
     sb = quad_sum(sb);
-    const double x0 = (ln_f64(K) - sa / d) / (sb / d);   // Jensen bound, right of the root
-    const double lndk = ln_f64(K * d);
+    const double x0 = (ln_f64<false>(K) - sa / d) / (sb / d);   // Jensen bound, right of the root
+    const double lndk = ln_f64<false>(K * d);
     // Moments M_k = sum_j g_j beta_j^k of g_j = exp(alpha_j + beta_j x0), k = 0..KM:
     // S(x0 + delta) = sum_k M_k delta^k / k! is the Taylor series of the sum,
     // so Newton's method runs on it without further exponentials.
@@ -326,15 +326,22 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
 #pragma unroll
     for (int k = 0; k <= KM; ++k) Mk[k] = 0.0;
     double bmax = 0.0;
-    for (int j = part; j < d; j += PARTS) {
-        const double be = sdt * a1[j];
-        double p = exp_f64(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x0);
+    // Two dates per step (the second weighted 0 past the last date): their
+    // exponentials are independent dependency chains, which the two waves
+    // per SIMD could not overlap otherwise.
+    for (int j = part; j < d; j += 2 * PARTS) {
+        const int jb = j + PARTS < d ? j + PARTS : j;
+        const double wb = j + PARTS < d ? 1.0 : 0.0;
+        const double be = sdt * a1[j], beb = sdt * a1[jb];
+        double p = exp_f64<false>(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x0);
+        double pb = wb * exp_f64<false>(lnS0 + wdt * (jb + 1) + LN2 * y(jb) + beb * x0);
 #pragma unroll
         for (int k = 0; k <= KM; ++k) {
-            Mk[k] += p;
+            Mk[k] += p + pb;
             p *= be;
+            pb *= beb;
         }
-        bmax = fmax(bmax, fabs(be));
+        bmax = fmax(bmax, fmax(fabs(be), fabs(beb)));
     }
 #pragma unroll
     for (int k = 0; k <= KM; ++k) Mk[k] = quad_sum(Mk[k]);
@@ -350,7 +357,7 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
             S1 = fma(S1, delta, Mk[k + 1] / fk);
             S = fma(S, delta, Mk[k] / fk);
         }
-        const double dd = (ln_f64(S) - lndk) * S / S1;
+        const double dd = (ln_f64<false>(S) - lndk) * S / S1;
         delta -= dd;
         if (!(fabs(dd) > 1e-13 * (1.0 + fabs(x0 + delta)))) break;   // also ends on NaN
     }
@@ -362,34 +369,35 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
             double S = 0.0, S1 = 0.0;
             for (int j = part; j < d; j += PARTS) {
                 const double be = sdt * a1[j];
-                const double g = exp_f64(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x);
+                const double g = exp_f64<false>(lnS0 + wdt * (j + 1) + LN2 * y(j) + be * x);
                 S += g;
                 S1 += be * g;
             }
             S = quad_sum(S);
             S1 = quad_sum(S1);
-            const double dx = (ln_f64(S) - lndk) * S / S1;
+            const double dx = (ln_f64<false>(S) - lndk) * S / S1;
             x -= dx;
             if (!(fabs(dx) > 1e-12 * (1.0 + fabs(x)))) break;   // also ends on NaN
         }
     }
     const double psi = x;
-    const double epsi = exp_f64(-0.5 * psi * psi);
+    const double epsi = exp_f64<false>(-0.5 * psi * psi);
     const bool arith = op.type == QCPW_ARITH_ASIAN_CALL;
     double F1 = 0.0, F2 = 0.0, Fs = 0.0, sEP = 0.0, sV = 0.0, sAg = 0.0;
-    for (int j = part; j < d; j += PARTS) {
+    // date j's terms (weight w: 1, or 0 for the padding date of the last step)
+    auto terms = [&](int j, double w) {
         const double yj = y(j);
         const double al = lnS0 + wdt * (j + 1) + LN2 * yj, be = sdt * a1[j];
         const double a = be / sig;                                // first-column entry, W units
         const double das = LN2 * yj / sig - sig * dt * (j + 1);   // c_j - sigma t_j
-        const double g = exp_f64(al + be * psi);
+        const double g = w * exp_f64<false>(al + be * psi);
         F1 += be * g;
         if (arith) {
             // EP = e^{alpha + beta^2/2} erfc(u)/2, u = (psi - beta)/sqrt 2; e^{alpha + beta^2/2 - u^2}
             // = g e^{-psi^2/2}, so EP = erfcx(u) g e^{-psi^2/2} / 2 for u >= 0 (no exponential)
             const double u = (psi - be) * M_SQRT1_2;
-            const double t = 0.5 * erfcx_f64(fabs(u)) * g * epsi;
-            const double EP = u >= 0.0 ? t : exp_f64(al + 0.5 * be * be) - t;
+            const double t = 0.5 * erfcx_f64<false>(fabs(u)) * g * epsi;
+            const double EP = u >= 0.0 ? t : w * exp_f64<false>(al + 0.5 * be * be) - t;
             sEP += EP;
             sV += EP * (das + be * a);
             sAg += a * g;
@@ -397,6 +405,12 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
             F2 += be * be * g;
             Fs += g * (das + psi * a);
         }
+    };
+    // two dates per step, as above
+    for (int j = part; j < d; j += 2 * PARTS) {
+        const bool two = j + PARTS < d;
+        terms(j, 1.0);
+        terms(two ? j + PARTS : j, two ? 1.0 : 0.0);
     }
     F1 = quad_sum(F1) / d;
     const double D = op.D, S0 = op.S0;
@@ -405,7 +419,7 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
         sEP = quad_sum(sEP) / d;
         sV = quad_sum(sV) / d;
         sAg = quad_sum(sAg) / d;
-        F[0] = D * (sEP - K * 0.5 * erfc_f64(psi * M_SQRT1_2));
+        F[0] = D * (sEP - K * 0.5 * erfc_f64<false>(psi * M_SQRT1_2));
         F[1] = D * sEP / S0;
         F[2] = D * (sV + phi0 * sAg);
         F[3] = D * phi0 * K * K / (S0 * S0 * F1);
@@ -413,7 +427,7 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
         F2 = quad_sum(F2) / d;
         Fs = quad_sum(Fs) / d;
         const double psiS = -(K / S0) / F1;   // d psi / d S0
-        F[0] = D * 0.5 * erfc_f64(psi * M_SQRT1_2);
+        F[0] = D * 0.5 * erfc_f64<false>(psi * M_SQRT1_2);
         F[1] = -D * phi0 * psiS;
         F[2] = D * phi0 * Fs / F1;
         F[3] = D * K * phi0 / (S0 * F1) * (-psi * psiS - 2.0 / S0 - F2 * psiS / F1);
