@@ -307,12 +307,13 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         if (path == QCPW_PATH_BB && op.n >= 1 && !fixed && !op.split)
             lp.stack_depth = std::max(lp.stack_depth, ctx->tab.depth[op.n]);
     }
-    // Matrix-core PCA: options whose paths are identical -- same n, seed and
-    // point range, same z scale and drift, same path statistic (they differ
-    // in strike or payoff) -- share one product and one epilogue per tile;
-    // only the FP64 tail runs per option.  They are sorted next to each other
-    // and the first (leader) carries the group.
-    const bool grouping = path == QCPW_PATH_PCA && precision == QCPW_FP32_MIXED;
+    // Matrix-core PCA (either conditioning): options whose paths are
+    // identical -- same n, seed and point range, same z scale and drift,
+    // same path statistic (they differ in strike or payoff) -- share one
+    // product and one epilogue per tile; only the FP64 tail runs per option.
+    // They are sorted next to each other and the first (leader) carries the
+    // group.
+    const bool grouping = (path == QCPW_PATH_PCA || path == QCPW_PATH_PCA_FULL) && precision == QCPW_FP32_MIXED;
     auto same_paths = [&](const OptDev &a, const OptDev &b) {
         return a.n == b.n && a.seed == b.seed && a.n_points == b.n_points && a.k_begin == b.k_begin &&
                a.zs_t == b.zs_t && a.ydrift_1_f == b.ydrift_1_f && qcpw_stat_of(a.type) == qcpw_stat_of(b.type);

@@ -435,10 +435,12 @@ __device__ inline void full_point_tail(const OptDev &op, YF y, int part, double 
 }
 
 // The PARTS threads of point p = tid / PARTS run full_point_tail; the first
-// writes F to Fb[p][4]; wave 0, lane p, adds valid points into its sums.
-template <int PARTS, typename YF>
+// writes F to Fb[p][4]; wave 0, lane p, hands each valid point's F[k] to
+// acc(k, F[k]) (compensated sums in registers, or in LDS for the other
+// options of a group).
+template <int PARTS, typename YF, typename ACC>
 __device__ inline void full_tile_tail(const OptDev &op, YF y_of, double *Fb, int tid, int lane, int wave,
-                                      bool lane_valid_for_wave0, double (&s)[4], double (&c)[4])
+                                      bool lane_valid_for_wave0, ACC acc)
 {
     static_assert(PARTS == 4 || PARTS == 8, "threads per point");
     const int p = tid / PARTS, part = tid % PARTS;
@@ -451,7 +453,7 @@ __device__ inline void full_tile_tail(const OptDev &op, YF y_of, double *Fb, int
     __syncthreads();
     if (wave == 0 && lane_valid_for_wave0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc_add(s[k], c[k], Fb[lane * 4 + k]);
+        for (int k = 0; k < 4; ++k) acc(k, Fb[lane * 4 + k]);
     }
 }
 
@@ -553,7 +555,7 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
         const int jcount = wave > 0 ? max(0, min(PD, n - PD * pw)) : 0;
         double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
         // options sharing these paths (same product and epilogue, FP64 tail each)
-        const int grp = FULL ? 1 : op.grp;
+        const int grp = op.grp;
         if (wave == 0)
             for (int i = 0; i < (grp - 1) * 8; ++i) macc[i * TP + lane] = 0.0;
         // ---- prologue: z' = Phi^{-1}(u) * sigma sqrt(dt) log2(e) for the 64 points of the
@@ -667,8 +669,21 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
                     }
                 }
                 __syncthreads();
-                full_tile_tail<PCA_AS_WAVES>(op, [&](int p, int j) { return (double)Cb[p * cstride + j]; }, (double *)red, tid,
-                               lane, wave, base + lane < t1, s, c);
+                auto y_of = [&](int p, int j) { return (double)Cb[p * cstride + j]; };
+                full_tile_tail<PCA_AS_WAVES>(op, y_of, (double *)red, tid, lane, wave, base + lane < t1,
+                                             [&](int k, double v) { acc_add(s[k], c[k], v); });
+                // the group's other options: their own tails on the same products
+                for (int mi = 1; mi < grp; ++mi) {
+                    __syncthreads();   // wave 0 is done reading the previous tails' F
+                    double *a = macc + (size_t)(mi - 1) * 8 * TP + lane;
+                    full_tile_tail<PCA_AS_WAVES>(opts[o + mi], y_of, (double *)red, tid, lane, wave, base + lane < t1,
+                                                 [&](int k, double v) {
+                                                     double sk = a[k * TP], ck = a[(4 + k) * TP];
+                                                     acc_add(sk, ck, v);
+                                                     a[k * TP] = sk;
+                                                     a[(4 + k) * TP] = ck;
+                                                 });
+                }
                 __syncthreads();
                 zero_padding();   // the prologue writes columns 0..n-1 only
                 if (base + TP < t1) prologue(base + TP);
@@ -848,7 +863,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             if constexpr (FULL) {
                 __syncthreads();
                 full_tile_tail<PCA_WAVES>(op, [&](int p, int j) { return Cg[(size_t)j * TP + p]; }, (double *)red, tid, lane,
-                               wave, base + lane < t1, s, c);
+                                          wave, base + lane < t1, [&](int k, double v) { acc_add(s[k], c[k], v); });
                 __syncthreads();
                 continue;
             }

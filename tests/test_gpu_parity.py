@@ -315,25 +315,28 @@ def test_pca_matrix_cores_within_bound(gemm, tol, d):
         assert err[..., k].max() <= tol[k], (k, err[..., k].max())
 
 
+@pytest.mark.parametrize("path", [q.PATH_PCA, q.PATH_PCA_FULL])
 @pytest.mark.parametrize("gemm,tol", [(q.GEMM_FP32, FP32_TOL), (q.GEMM_BF16X3, BF16X3_TOL)])
-def test_pca_shared_paths_one_product(gemm, tol):
+def test_pca_shared_paths_one_product(gemm, tol, path):
     """Options with the same paths (seed, d, sigma, r, T) but other strikes
     and payoffs share one product and epilogue per tile in the matrix-core
-    kernel: each result equals the option's result alone, bit for bit, and
-    the oracle's within the bound; a lookback and an option of another seed
-    in the same launch keep their own paths."""
+    kernel (under either conditioning; with the first principal component
+    each option still runs its own FP64 root-find): each result equals the
+    option's result alone, bit for bit, and the oracle's within the bound; a
+    lookback and an option of another seed in the same launch keep their own
+    paths."""
     base = dict(d=65, S0=100.0, r=0.05, sigma=0.25, T=1.0, seed=0x5eed, n_points=8192 + 300)
     grp = [dict(base, type=t, K=K) for t, K in ((q.ARITH_ASIAN, 95.0), (q.BINARY_ASIAN, 95.0),
                                                  (q.ARITH_ASIAN, 108.0), (q.BINARY_ASIAN, 101.0),
                                                  (q.ARITH_ASIAN, 100.0))]   # five: a group of 4 and one more
     others = [dict(base, type=q.LOOKBACK, K=100.0), dict(base, type=q.ARITH_ASIAN, K=100.0, seed=0x5eee)]
     opts = grp + others
-    say("pca shared paths", gemm)
-    g, e, ps = q.greeks(opts, 4, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+    say("pca shared paths", gemm, path)
+    g, e, ps = q.greeks(opts, 4, path, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
     for i, o in enumerate(opts):
-        g1, e1, ps1 = q.greeks([o], 4, q.PATH_PCA, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
+        g1, e1, ps1 = q.greeks([o], 4, path, q.FP32_MIXED, pca_gemm=gemm, per_shift=True)
         assert np.array_equal(ps[i], ps1[0]), i
-    m, se, am, Cl = oracle_many(opts, 4, oracle.PATH_PCA)
+    m, se, am, Cl = oracle_many(opts, 4, oracle.PATH_PCA if path == q.PATH_PCA else oracle.PATH_PCA_FULL)
     err = scaled_err(ps, Cl, am[:, None, :])
     say("pca shared scaled error", gemm, err.max(axis=(0, 1)))
     for k in range(4):
