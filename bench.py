@@ -149,6 +149,10 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=300, help="requests per arrival rate in --serve-sweep")
     p.add_argument("--serve-rates", type=str, default="0.25,0.5,0.8",
                    help="arrival rates of --serve-sweep as fractions of the saturation rate")
+    p.add_argument("--serve-sat", type=float, default=0.0,
+                   help="saturation rate (requests/s) measured before: --serve-sweep skips its burst")
+    p.add_argument("--serve-fp64-cap", type=float, default=120.0,
+                   help="seconds after the first arrival at which the plain FP64 server stops taking requests")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed loop, run one plain device copy of this many MiB "
                         "(reference kernel for HBM byte counters)")
@@ -210,7 +214,8 @@ def main():
         return
     if a.serve_sweep:
         print(json.dumps({"serving_sweep": serve_sweep(q, workloads, a.serve_requests,
-                                                       [float(x) for x in a.serve_rates.split(",")])}),
+                                                       [float(x) for x in a.serve_rates.split(",")],
+                                                       fp64_cap_s=a.serve_fp64_cap, sat=a.serve_sat)}),
               flush=True)
         return
     opts, L, desc = headline_workload(workloads, a.workload)
@@ -497,7 +502,21 @@ def pca_leg(q, workloads, torch, steps=3):
     return res
 
 
-def run_stream(q, srv, stream, L=16):
+class Progress:
+    """A line on stderr at most every `every` seconds while work completes."""
+
+    def __init__(self, what, total, every=20.0):
+        self.what, self.total, self.every = what, total, every
+        self.t_last = time.perf_counter()
+
+    def step(self, k):
+        now = time.perf_counter()
+        if now - self.t_last >= self.every or k == self.total:
+            self.t_last = now
+            print("%s: %d / %d" % (self.what, k, self.total), file=sys.stderr, flush=True)
+
+
+def run_stream(q, srv, stream, L=16, what="served"):
     """Submit a request stream at its arrival times into server srv, poll for
     results from a second thread; returns (latency seconds per request,
     points reached per request, wall seconds)."""
@@ -506,6 +525,7 @@ def run_stream(q, srv, stream, L=16):
     pending = []
     lock = threading.Lock()
     finished = threading.Event()
+    prog = Progress(what, len(stream))
 
     def poller():
         # completion times are taken as soon as a result is ready
@@ -519,6 +539,7 @@ def run_stream(q, srv, stream, L=16):
                     done[rid] = (time.perf_counter() - ts, out[2])
                     with lock:
                         pending.remove(item)
+                    prog.step(len(done))
             if finished.is_set() and not todo:
                 return
             time.sleep(0.0002)
@@ -551,6 +572,7 @@ def plain_fp64_stream(q, stream, pts, L=16, cap_s=120.0):
     after the first arrival; a request not finished by then counts with its
     waiting time so far (a lower bound on its latency)."""
     lat, finished, paths = [], 0, 0
+    prog = Progress("fp64 one option per launch", len(stream))
     t0 = time.perf_counter()
     for r, p in zip(stream, pts):
         now = time.perf_counter() - t0
@@ -560,6 +582,7 @@ def plain_fp64_stream(q, stream, pts, L=16, cap_s=120.0):
             time.sleep(r["t_arrival"] - now)
         for o in r["options"]:
             q.greeks([dict(o, n_points=p)], L, q.PATH_BB, q.FP64)
+            prog.step(finished)
         lat.append(time.perf_counter() - t0 - r["t_arrival"])
         finished += 1
         paths += len(r["options"]) * p * L
@@ -575,22 +598,24 @@ def plain_fp64_stream(q, stream, pts, L=16, cap_s=120.0):
 
 
 def serve_sweep(q, workloads, n_requests, fracs, max_opts=512, d_range=(4, 365), targets=(1e-4, 1e-6),
-                n_burst=24, L=16, fp64_cap_s=120.0):
+                n_burst=24, L=16, fp64_cap_s=120.0, sat=0.0):
     """The configured serving stream (Poisson arrivals of 1..max_opts-option
     portfolios drawn as the uneven portfolio, target standard error 1e-4 or
     1e-6 relative): the saturation rate of the mixed-precision server (a
     burst of n_burst requests submitted at once, over the time to finish
     them), then n_requests requests at each rate frac x saturation with
     p50/p99 latency and throughput; beside each, the plain FP64
-    one-option-per-launch method under the same arrivals."""
-    burst = workloads.request_stream(n_burst, 1e9, seed=5150, max_opts=max_opts, d_range=d_range,
-                                     targets=targets)
-    for r in burst:
-        r["t_arrival"] = 0.0
-    with q.Server(hbm_budget_bytes=8 << 30, precision=q.FP32_MIXED) as srv:
-        lat, pts, wall = run_stream(q, srv, burst, L)
-    sat = n_burst / float(lat.max())
-    print("serve sweep: saturation %.3f requests/s" % sat, file=sys.stderr, flush=True)
+    one-option-per-launch method under the same arrivals.  sat > 0: the
+    saturation rate measured before (the burst is skipped)."""
+    if sat <= 0.0:
+        burst = workloads.request_stream(n_burst, 1e9, seed=5150, max_opts=max_opts, d_range=d_range,
+                                         targets=targets)
+        for r in burst:
+            r["t_arrival"] = 0.0
+        with q.Server(hbm_budget_bytes=8 << 30, precision=q.FP32_MIXED) as srv:
+            lat, pts, wall = run_stream(q, srv, burst, L, what="burst")
+        sat = n_burst / float(lat.max())
+        print("serve sweep: saturation %.3f requests/s" % sat, file=sys.stderr, flush=True)
     res = {"stream": {"options_per_request": [1, max_opts], "d_range": list(d_range),
                       "target_stderr": list(targets), "shifts": L},
            "saturation_requests_per_s": sat, "rates": []}
@@ -611,6 +636,7 @@ def serve_sweep(q, workloads, n_requests, fracs, max_opts=512, d_range=(4, 365),
               file=sys.stderr, flush=True)
         entry["fp64_one_option_per_launch"] = plain_fp64_stream(q, stream, pts, L, cap_s=fp64_cap_s)
         res["rates"].append(entry)
+        print(json.dumps({"serving_rate": entry}), flush=True)
     return res
 
 
