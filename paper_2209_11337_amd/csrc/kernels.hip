@@ -293,8 +293,8 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         cost[i] = (double)std::max(op.ndims, 1) * (double)op.chunks;
         lp.max_n = std::max(lp.max_n, op.ndims);
     }
-    // the lane rows of more than QCPW_WIDE_MIN_N dimensions leave room for one
-    // 1024-thread workgroup per CU: 4 waves per SIMD, so 128 VGPRs cost nothing
+    // the lane rows of more than QCPW_WIDE_MIN_N dimensions leave room for at
+    // most two workgroups per CU, so the 80-VGPR instances gain no occupancy
     const bool f32 = precision == QCPW_FP32_MIXED;
     lp.wide = f32 && lp.max_n > QCPW_WIDE_MIN_N;
     for (int i = 0; i < n_opts; ++i) {

@@ -201,7 +201,10 @@ struct PlanStep64 {
 #define QCPW_SPLIT_EVENTS 32     // 1 + (2^k - 1) + 2^k, k <= 4
 #define QCPW_SPLIT_SLOTS 512     // 8 registers of 64 lanes
 #define QCPW_EV_WORDS 16         // one 64-byte event, one scalar load
-#define QCPW_WIDE_MIN_N 288      // FP32 launches with more lane rows use the 128-VGPR kernel instances
+// FP32 launches with more lane rows use the 128-VGPR kernel instances:
+// beyond 181 rows at most two workgroups fit the LDS of a CU, and the
+// 80-VGPR instances' extra occupancy is gone.
+#define QCPW_WIDE_MIN_N 181
 
 // The level k at which the split bridge of n starts its subtrees.
 __host__ __device__ constexpr int qcpw_split_level(int n)
