@@ -354,18 +354,16 @@ __device__ inline double ninv_f64(uint32_t y)
 // with the X terms negated (binary: all negated).  For a basket (one-factor
 // model) D1 = e^{-rT} e^{omega t1 + s1^2/2}, s1 = sigma sqrt(rho t1), and
 // the vega gains vx_shift X from the sigma dependence of that factor.
-__device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, double VXs, double F[4])
+// lnA = ln A (the path statistics that come as a power of two pass it in
+// exactly; the others compute it).
+__device__ inline void path_greeks(const OptDev &op_in, double A, double lnA, double Xs, double VXs, double F[4])
 {
     const OptDev &op = *reread(&op_in);
-    const double psi = (op.c0 - ln_f64(A)) * op.inv_s1;
-    const double psi1 = psi - op.s1;
+    const double psi = (op.c0 - lnA) * op.inv_s1;
     const double g0 = exp_f64(-0.5 * psi * psi);
-    const double invA = recip_f64(A);
     const double e0 = 0.5 * g0 * erfcx_f64(fabs(psi) * M_SQRT1_2);
-    const double e1 = 0.5 * (g0 * op.h * invA) * erfcx_f64(fabs(psi1) * M_SQRT1_2);
     const bool put = qcpw_is_put(op.type);
     const double T0 = ((psi >= 0.0) != put) ? e0 : 1.0 - e0;    // call: 1 - Phi(psi); put: Phi(psi)
-    const double T1 = ((psi1 >= 0.0) != put) ? e1 : 1.0 - e1;   // the same at psi - s1
     const double sgn = put ? -1.0 : 1.0;
     const double phi0 = g0 * 0.398942280401432677939946;
     if (op.type == QCPW_BINARY_ASIAN_CALL || op.type == QCPW_BINARY_ASIAN_PUT) {
@@ -375,6 +373,10 @@ __device__ inline void path_greeks(const OptDev &op_in, double A, double Xs, dou
         F[2] = Dphi * (VXs * recip_f64(Xs) * op.inv_s1 + psi * op.inv_sigma - op.sqrt_t1);
         F[3] = Dphi * op.inv_s1 * op.inv_S0sq * (psi * op.inv_s1 - 1.0);
     } else {
+        // the Gaussian factor at psi - s1 only where the payoff needs it
+        const double psi1 = psi - op.s1;
+        const double e1 = 0.5 * (g0 * op.h * recip_f64(A)) * erfcx_f64(fabs(psi1) * M_SQRT1_2);
+        const double T1 = ((psi1 >= 0.0) != put) ? e1 : 1.0 - e1;   // the same at psi - s1
         const double X = op.S0 * Xs;
         const double DKphi = op.D * op.K * phi0;
         const double D1T1 = sgn * op.D1 * T1;
@@ -389,23 +391,28 @@ template <typename R>
 __device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, int mode, double F[4])
 {
     const OptDev &op = *reread(&op_in);
-    double A, Xs, VXs;
+    double A, lnA, Xs, VXs;
     if (mode == QCPW_STAT_MAX || mode == QCPW_STAT_MIN) {
-        A = (double)exp2_r(ps.bY);
+        // A = 2^bY: ln A = bY ln 2 exactly (no logarithm of the rounded power)
+        const double by = (double)ps.bY;
+        A = exp_f64(by * 0.69314718055994530942);
+        lnA = by * 0.69314718055994530942;
         Xs = A;
-        VXs = A * ((double)ps.bY - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
+        VXs = A * (by - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
     } else if (mode == QCPW_STAT_GEO) {
         // X/S0 = 2^{mean Y}; sum over dates of (W~ - sigma tau) = (sum Y - kappa sum m)/(sigma log2 e)
         const double sy = (double)ps.A2y;
-        A = exp_f64(sy * op.invd * 0.69314718055994530942);
+        lnA = sy * op.invd * 0.69314718055994530942;
+        A = exp_f64(lnA);
         Xs = A;
         VXs = A * (sy - op.kappa * 0.5 * (double)op.n * (double)(op.n + 1)) * op.invd * op.inv_sig_log2e;
     } else {
         A = (double)ps.A1;                      // ln d is folded into c0
+        lnA = ln_f64(A);
         Xs = A * op.invd;
         VXs = ((double)ps.A2y - op.kappa * (double)ps.A2m) * op.invd * op.inv_sig_log2e;
     }
-    path_greeks(op, A, Xs, VXs, F);
+    path_greeks(op, A, lnA, Xs, VXs, F);
 }
 
 template <typename R>
