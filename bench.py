@@ -339,6 +339,16 @@ def three_products_leg(q, workloads, torch, steps=5, warmup=1):
                              for i, k in enumerate(q.OUTPUTS)}
     res["stderr_min_rel"] = {k: float((e[:, i] / np.maximum(np.abs(g64[:, i]), 1e-300)).min())
                              for i, k in enumerate(q.OUTPUTS)}
+    # the same grid with principal-component paths (matrix cores, FP32 MFMA):
+    # rate, and each Greek's variance against the bridge at the same points
+    wp, evp, kp = timed_calls(q, torch, opts, L, q.PATH_PCA, q.FP32_MIXED, steps, warmup, out, stream)
+    ep = out[1].cpu().numpy()
+    vr = (e / np.maximum(ep, 1e-300)) ** 2
+    res["pca_fp32_mfma"] = {"value": paths * steps / wp, "unit": "Greek-paths/s", "ms_per_step": wp / steps * 1e3,
+                            "kernel_ms": kp,
+                            "variance_ratio_bridge_over_pca": {k: [float(np.min(vr[:, i])), float(np.median(vr[:, i])),
+                                                                   float(np.max(vr[:, i]))]
+                                                               for i, k in enumerate(q.OUTPUTS)}}
     return res
 
 

@@ -3,17 +3,20 @@
 // square roots of their eigenvalues, largest first).
 //
 // For a tile of 64 consecutive Sobol points the product W~ = A Z is a dense
-// (n x n) by (n x 64) contraction, so it runs on the matrix cores:
+// (n x n) by (n x 64) contraction, so it runs on the matrix cores.  A
+// workgroup has one wave per 32 rows of the padded factor (at least two;
+// eight for the full conditioning):
 //
-//   prologue   each of the 4 waves generates 64 dimensions of the tile
+//   prologue   waves 1.. generate the tile's dimensions, an equal share each
 //              (lane = point; Sobol via the lane table and a wave-uniform
 //              part, digital shift, FP32 inverse normal, scaled to log2
-//              units) and stores Z^T in LDS, as FP32 or split into BF16
-//              hi + lo;
-//   GEMM       wave w owns the 32 x 32 output blocks t = w, w+4, ... (row
-//              block t/2, point block t%2): FP32 v_mfma_f32_32x32x2f32, or
-//              three v_mfma_f32_32x32x16_bf16 per 16-wide k slab
-//              (hi*hi + hi*lo + lo*hi), accumulating in FP32;
+//              units) and store Z^T in LDS, as FP32 or split into BF16
+//              hi + lo, while wave 0 runs the previous tile's FP64 tails;
+//   GEMM       wave w keeps rows 32 w .. 32 w + 31 of A in registers for the
+//              whole work unit and multiplies them by both 32-point blocks:
+//              FP32 v_mfma_f32_32x32x2f32, or three v_mfma_f32_32x32x16_bf16
+//              per 16-wide k slab (hi*hi + hi*lo + lo*hi), accumulating in
+//              FP32;
 //   epilogue   Y_m = W'_m + drift m; E = exp2(Y) and the path sums (or the
 //              running maximum) over the lane's rows; the two lane halves
 //              and the waves of a point block are combined through LDS; the
@@ -476,6 +479,11 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
     // after: FP32 [TP][np+1], or BF16 hi and lo [TP][np+8] each
     extern __shared__ __align__(16) unsigned char smem[];   // no static LDS: smem is address 0
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // waves in the workgroup: 8 (PCA_FULL, and n > 224), else max(2, NP / 32) for
+    // the launch's largest padded n: every wave then owns a row block of A
+    // (the first also runs the tails), so a small n keeps as many waves per
+    // CU on the matrix cores as a large one
+    const int W = (int)(blockDim.x >> 6);
     const int lr = lane & 31, khalf = lane >> 5;
     const int zstride = BF16X3 ? np_max + 8 : np_max + 1;
     float *Zf = (float *)(smem + QCPW_LDS_FIXED);
@@ -541,13 +549,13 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
             }
         };
         zero_padding();
-        // Waves 1..7 generate the normals (wave 0 meanwhile runs the previous
+        // Waves 1..W-1 generate the normals (wave 0 meanwhile runs the previous
         // tile's FP64 tail): prologue wave pw = wave - 1 takes dimensions
         // 1 + PD pw .. PD (pw + 1), and its lane l holds the uniform part of 1 + PD pw + l.
-        // (even with BF16 Z, so that pairs of columns share one 32-bit store)
-        constexpr int PD0 = (QCPW_PCA_NPAD + PCA_AS_WAVES - 2) / (PCA_AS_WAVES - 1);
-        constexpr int PD = BF16X3 ? (PD0 + 1) & ~1 : PD0;
-        static_assert(PD <= 64, "one uniform part per lane");
+        // (even with BF16 Z, so that pairs of columns share one 32-bit store);
+        // PD <= 64 since W >= NP / 32 (checked at launch)
+        const int PD0 = (n + W - 2) / (W - 1);
+        const int PD = BF16X3 ? (PD0 + 1) & ~1 : PD0;
         const int pw = wave - 1;
         const int myj = 1 + PD * pw + lane;
         uint32_t U = 0;
@@ -732,7 +740,7 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
             __syncthreads();
             if (wave == 0) {   // this tile's tails, while the other waves fill Z with the next tile
                 const int waves_pt[PCA_AS_WAVES] = {0, 1, 2, 3, 4, 5, 6, 7};
-                tile_tail<float>(op, red, lane, base + lane < t1, PCA_AS_WAVES, waves_pt, s, c);
+                tile_tail<float>(op, red, lane, base + lane < t1, W, waves_pt, s, c);
                 for (int mi = 1; mi < grp; ++mi) {
                     double sm[4], cm[4];
                     double *acc = macc + (size_t)(mi - 1) * 8 * TP + lane;
@@ -741,7 +749,7 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
                         sm[i] = acc[i * TP];
                         cm[i] = acc[(4 + i) * TP];
                     }
-                    tile_tail<float>(opts[o + mi], red, lane, base + lane < t1, PCA_AS_WAVES, waves_pt, sm, cm);
+                    tile_tail<float>(opts[o + mi], red, lane, base + lane < t1, W, waves_pt, sm, cm);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         acc[i * TP] = sm[i];
@@ -926,7 +934,17 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
     }
     QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    const int bd = 64 * (lp.precision == QCPW_FP64 ? PCA_WAVES : PCA_AS_WAVES);
+    // matrix cores, first-date conditioning: one wave per 32 rows of the
+    // launch's largest padded factor, at least two (the tails and a prologue
+    // wave); PCA_FULL runs eight threads per point in its tail
+    int waves = PCA_AS_WAVES;
+    if (lp.precision == QCPW_FP32_MIXED && !full) {
+        waves = std::min(PCA_AS_WAVES, std::max(2, np_max / 32));
+        int n_top = 1;
+        for (const auto &op : lp.opts) n_top = std::max(n_top, op.n);
+        if ((n_top + waves - 2) / (waves - 1) > 64) return fail(QCPW_EDEVICE, "PCA prologue exceeds one wave per 64 dimensions");
+    }
+    const int bd = 64 * (lp.precision == QCPW_FP64 ? PCA_WAVES : waves);
     QCPW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds));
     if (per_cu < 1) return fail(QCPW_EDEVICE, "PCA kernel cannot be resident");
     int64_t grid = std::min<int64_t>((int64_t)per_cu * ctx->tab.n_cu, lp.total_units);
