@@ -57,6 +57,26 @@ TRAFFIC = {
 }
 
 
+# Per-unit work the fused kernel itself executes, from the rocprofv3 counters
+# of the same kernel sources (profiles/): SQ_INSTS_VALU, SQ_INSTS_VALU_FLOPS_FP32
+# and _FP64 (per wave, x64 lanes) over the launch's path-dates and paths.
+COUNTERS = {
+    "portfolio": {"sha": None, "valu_per_path_date": None, "fp32_flops_per_path_date": None,
+                  "fp64_flops_per_path": None},
+    "three_products": {"sha": None, "valu_per_path_date": None, "fp32_flops_per_path_date": None,
+                       "fp64_flops_per_path": None},
+}
+CLOCK_HZ = 2.4e9
+SIMDS = 1024
+
+
+def counters_of(workload: str):
+    c = COUNTERS[workload]
+    if c["sha"] is None or c["sha"] != kernel_sources_sha():
+        return None
+    return c
+
+
 def kernel_sources_sha() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -74,7 +94,7 @@ def traffic_of(workload: str):
 
 
 def roofline(paths, path_dates, kernel_ms, fp32=True, mfma_flops=0.0, mfma_peak=PEAK_MFMA_F32,
-             kernel="qcpw::paths_kernel", traffic=None, call_ms=None):
+             kernel="qcpw::paths_kernel", traffic=None, call_ms=None, counters=None):
     """Whole-kernel roofline of the op-count model: t_ideal = F32 / 157.3e12 +
     F64 / 78.6e12 (+ matrix flops / their peak); frac = t_ideal / t_kernel;
     achieved in FP32-equivalent TFLOP/s (each term weighted by 157.3e12 over
@@ -92,6 +112,17 @@ def roofline(paths, path_dates, kernel_ms, fp32=True, mfma_flops=0.0, mfma_peak=
            "ideal_ms": t_ideal * 1e3, "kernel": kernel, "kernel_ms": kernel_ms}
     if call_ms is not None:
         out["call_ms"] = call_ms
+    if counters is not None:
+        # what the kernel executes (counters), beside the algorithmic model
+        # above: FLOP/s it issues and the share of the SIMDs' VALU issue
+        # slots (a wave64 VALU instruction holds a SIMD for 4 cycles) it fills
+        f32c = counters["fp32_flops_per_path_date"] * path_dates
+        f64c = counters["fp64_flops_per_path"] * paths
+        waves = counters["valu_per_path_date"] * path_dates / 64.0
+        out["measured"] = {"source": "rocprofv3 counters of these kernel sources (profiles/)",
+                           "fp32_tflops": f32c / t_kernel / 1e12, "fp64_tflops": f64c / t_kernel / 1e12,
+                           "valu_lane_instructions_per_path_date": counters["valu_per_path_date"],
+                           "valu_issue_frac": waves * 4.0 / (t_kernel * CLOCK_HZ * SIMDS)}
     return out
 
 
@@ -238,6 +269,7 @@ def main():
     value = n_paths * a.steps / wall
     fp32 = prec == q.FP32_MIXED
     rl = roofline(n_paths, n_pd, kern_ms, fp32=fp32, traffic=traffic_of(a.workload) if fp32 else None,
+                  counters=counters_of(a.workload) if fp32 else None,
                   call_ms=ev_ms)
 
     res = {"metric": "Greek-paths/sec (delta+vega+gamma) at fixed RMSE vs FP64; p99 request latency",
@@ -329,7 +361,8 @@ def three_products_leg(q, workloads, torch, steps=5, warmup=1):
     e = out[1].cpu().numpy()
     res = {"value": paths * steps / wall, "unit": "Greek-paths/s", "ms_per_step": wall / steps * 1e3,
            "greek_paths": paths, "path_dates": pd,
-           "roofline": roofline(paths, pd, k_ms, traffic=traffic_of("three_products"), call_ms=ev_ms)}
+           "roofline": roofline(paths, pd, k_ms, traffic=traffic_of("three_products"), call_ms=ev_ms,
+                                counters=counters_of("three_products"))}
     w64, ev64, k64 = timed_calls(q, torch, opts, L, q.PATH_BB, q.FP64, 2, 1, out, stream)
     g64 = out[0].cpu().numpy()
     res["fp64"] = {"value": paths * 2 / w64, "ms_per_step": w64 / 2 * 1e3, "kernel_ms": k64}
