@@ -192,7 +192,10 @@ static bool fixed_bridges_on()
 }
 
 // Split bridge (FP32 kernel, n >= QCPW_SUB_MIN_LEN): on unless
-// QCPW_SPLIT_BRIDGE=0 (then the plan walker takes those options).
+// QCPW_SPLIT_BRIDGE=0 (then the plan walker takes those options).  Both
+// switches are diagnostics: with either one off, an option's bits may
+// depend on which kernel instance its launch runs (the compile-time and
+// split walks give the same bits, the plan walker does not).
 static bool split_bridge_on()
 {
     static const bool on = [] {
