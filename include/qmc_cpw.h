@@ -188,8 +188,8 @@ typedef struct {
  * (replication l, dimension j) by the same 32-bit value s_{l,j} that is the
  * digital shift otherwise (hash-based nested scrambling: a seeded addition
  * and four rounds v ^= (v mod 2^24) * C, C even, on the bit-reversed
- * value).  QCPW_PATH_BB and QCPW_PATH_STANDARD only (QCPW_EINVAL
- * otherwise); also accepted by qcpw_server_create. */
+ * value).  Every path construction; also accepted by
+ * qcpw_server_create. */
 #define QCPW_FLAG_OWEN 2
 
 /*

@@ -340,8 +340,6 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
     if (st != QCPW_OK) return st;
     if (c.flags & ~(QCPW_FLAG_GRAPH | QCPW_FLAG_OWEN)) return fail(QCPW_EINVAL, "unknown flags");
     const bool owen = (c.flags & QCPW_FLAG_OWEN) != 0;
-    if (owen && path_construction != QCPW_PATH_BB && path_construction != QCPW_PATH_STANDARD)
-        return fail(QCPW_EINVAL, "nested scrambling is available with the BB and STANDARD constructions");
     if ((c.flags & QCPW_FLAG_GRAPH) && !c.outputs_on_device)
         return fail(QCPW_EINVAL, "QCPW_FLAG_GRAPH needs outputs_on_device");
     Context *ctx = nullptr;

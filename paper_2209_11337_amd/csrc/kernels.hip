@@ -215,9 +215,6 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
                                        block_threads < 0 ? 0 : block_threads);
         if (st != QCPW_OK) return st;
     }
-    if (owen && path != QCPW_PATH_BB && path != QCPW_PATH_STANDARD)
-        return fail(QCPW_EINVAL, "nested scrambling is available with the BB and STANDARD constructions");
-
     lp = LaunchPlan();
     lp.owen = owen;
     lp.path = path;

@@ -78,9 +78,11 @@ __device__ inline long long next_unit(unsigned long long *counter, long long *s_
 
 // U_j(base) for dimension j (held by one lane), shift folded in.
 __device__ inline uint32_t uniform_part(const uint32_t *__restrict__ dir, uint64_t seed, int shift, int j,
-                                        uint64_t base)
+                                        uint64_t base, bool owen)
 {
-    uint32_t u = digital_shift(seed, shift, j);
+    // with nested scrambling the seed is applied after the XOR with the
+    // lane word (owen_scramble), so the part stays raw
+    uint32_t u = owen ? 0u : digital_shift(seed, shift, j);
     uint64_t g = (base ^ (base >> 1)) >> 5;
     const uint32_t *v = dir + (size_t)j * 32;
     for (int b = 5; g != 0; ++b, g >>= 1)
@@ -472,7 +474,7 @@ template <bool BF16X3, bool FULL>
 __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_eu(2, 2))) void pca_f32_kernel(
     const OptDev *__restrict__ opts, const int64_t *__restrict__ unit_prefix, const uint32_t *__restrict__ dir,
     const uint32_t *__restrict__ lane_tab, const float4 *__restrict__ ninv_tab, double *__restrict__ partials,
-    unsigned long long *__restrict__ counter, int n_opts, int np_max, long long total_units)
+    unsigned long long *__restrict__ counter, int n_opts, int np_max, long long total_units, int owen)
 {
     // LDS (all dynamic, from address 0): the inverse-normal cells of both halves
     // at 0 and QCPW_LDS_TAB_HI, the wave partials between them, the Z^T tile
@@ -559,7 +561,11 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
         const int pw = wave - 1;
         const int myj = 1 + PD * pw + lane;
         uint32_t U = 0;
-        if (wave > 0 && lane < PD && myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
+        uint32_t Key = 0;   // nested scrambling: the dimension's seed
+        if (wave > 0 && lane < PD && myj <= n) {
+            U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0, owen != 0);
+            if (owen) Key = digital_shift(op.seed, shift, myj);
+        }
         const int jcount = wave > 0 ? max(0, min(PD, n - PD * pw)) : 0;
         double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
         // options sharing these paths (same product and epilogue, FP64 tail each)
@@ -601,8 +607,14 @@ __global__ __launch_bounds__(64 * PCA_AS_WAVES) __attribute__((amdgpu_waves_per_
                 // no branch between them, so their latencies overlap (past jc the
                 // value is computed from a zero word and never stored)
                 float z[8];
+                if (owen) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) z[i] = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
+                    for (int i = 0; i < 8; ++i)
+                        z[i] = ninv_table_f32(owen_scramble(w[i] ^ rdlane(U, j0 + i), rdlane(Key, j0 + i))) * op.zs_t;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) z[i] = ninv_table_f32(w[i] ^ rdlane(U, j0 + i)) * op.zs_t;
+                }
                 if (j0 + 8 <= jc) {
 #pragma unroll
                     for (int i = 0; i < 8; i += BF16X3 ? 2 : 1) {
@@ -799,7 +811,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                                                       double *__restrict__ partials,
                                                       unsigned long long *__restrict__ counter, int n_opts,
                                                       int n_max, long long total_units,
-                                                      double *__restrict__ scratch)
+                                                      double *__restrict__ scratch, int owen)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_unit;
@@ -824,15 +836,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const int64_t t0 = op.k_begin + chunk * op.unit_pts;
         const int64_t t1 = min(t0 + (int64_t)op.unit_pts, k_end);
         const int myj = 1 + 64 * wave + lane;
-        uint32_t U = 0;
-        if (myj <= n) U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0);
+        uint32_t U = 0, Key = 0;
+        if (myj <= n) {
+            U = uniform_part(dir, op.seed, shift, myj, (uint64_t)t0, owen != 0);
+            if (owen) Key = digital_shift(op.seed, shift, myj);
+        }
         const int jcount = max(0, min(64, n - 64 * wave));
         double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
 
         for (int64_t base = t0; base < t1; base += TP) {
             for (int jj = 0; jj < jcount; ++jj) {
                 const int j = 1 + 64 * wave + jj;
-                const uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
+                uint32_t y = lane_tab[(size_t)j * 64 + lane] ^ rdlane(U, jj);
+                if (owen) y = owen_scramble(y, rdlane(Key, jj));
                 Z[lane * zstride + (j - 1)] = ninv_f64(y) * op.zscale;
             }
             if (base + TP < t1 && myj <= n) {
@@ -961,8 +977,10 @@ qcpw_status enqueue_pca(Context *ctx, const LaunchPlan &lp, hipStream_t stream, 
     long long a_total = ld.total_units;
     double *a_scratch = ld.scratch;
     const float4 *a_tab = ctx->tab.ninv_tab;
-    void *args32[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_tab, &a_part, &a_ctr, &a_nopts, &extra, &a_total};
-    void *args64[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_part, &a_ctr, &a_nopts, &extra, &a_total, &a_scratch};
+    int a_owen = lp.owen ? 1 : 0;
+    void *args32[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_tab, &a_part, &a_ctr, &a_nopts, &extra, &a_total, &a_owen};
+    void *args64[] = {&a_opts, &a_prefix, &a_dir, &a_lane, &a_part, &a_ctr, &a_nopts, &extra, &a_total, &a_scratch,
+                      &a_owen};
     QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), lp.precision == QCPW_FP64 ? args64 : args32, lds,
                              stream));
     return QCPW_OK;

@@ -149,12 +149,15 @@ def test_basket_argument_checks():
         assert msg in str(ei.value), (patch, str(ei.value))
 
 
-def test_owen_flag_checks():
+def test_noalloc_flag_and_construction_checks():
+    """The call that allocates nothing takes the bridge and standard
+    constructions and no flag but QCPW_FLAG_OWEN; both are refused before
+    any device work."""
     o = dict(type=0, d=16, S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, seed=1, n_points=64)
     for path in (q.PATH_PCA, q.PATH_PCA_FULL):
         with pytest.raises(q.QcpwError) as ei:
-            q.greeks([o], 4, path, owen=True)
-        assert ei.value.status == -1 and "scrambling" in str(ei.value)
+            q.greeks_noalloc([o], 4, path, owen=True)
+        assert ei.value.status == -1 and "no-allocation" in str(ei.value)
 
 
 def test_kernel_timer_argument_checks():

@@ -435,7 +435,8 @@ def test_scrambled_points_bit_exact(n_dims, k0, count, shift):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("path,d", [(q.PATH_BB, 16), (q.PATH_BB, 65), (q.PATH_STANDARD, 33)])
+@pytest.mark.parametrize("path,d", [(q.PATH_BB, 16), (q.PATH_BB, 65), (q.PATH_STANDARD, 33), (q.PATH_PCA, 17),
+                                    (q.PATH_PCA, 64), (q.PATH_PCA_FULL, 16), (q.PATH_PCA_FULL, 63)])
 def test_fp64_owen_parity(path, d):
     opts = workloads.three_products_grid(d=d, n_points=4096 + 77)[::4]
     say("owen fp64", path, d)
@@ -444,7 +445,8 @@ def test_fp64_owen_parity(path, d):
     assert_scaled(ps, Cl, am[:, None, :], TOL64, "per shift")
 
 
-@pytest.mark.parametrize("path,d", [(q.PATH_BB, 64), (q.PATH_BB, 65), (q.PATH_STANDARD, 17)])
+@pytest.mark.parametrize("path,d", [(q.PATH_BB, 64), (q.PATH_BB, 65), (q.PATH_STANDARD, 17), (q.PATH_PCA, 64),
+                                    (q.PATH_PCA, 257), (q.PATH_PCA_FULL, 17)])
 def test_fp32_owen_within_bound(path, d):
     opts = workloads.three_products_grid(d=d, n_points=4096 + 77)[::3]
     say("owen fp32", path, d)
