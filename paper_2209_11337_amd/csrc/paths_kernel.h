@@ -785,6 +785,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? (WID
         const int shift = (int)(rem / op.chunks);
         const int64_t chunk = rem - (int64_t)shift * op.chunks;
 
+        // Per-lane FP64 sums of the unit's points (at most 64 per lane): plain
+        // in the FP32-mixed kernels (their rounding stays below 64 ulps of
+        // the summands' scale, far below the path's FP32 rounding),
+        // compensated in the FP64 kernel; every sum across lanes, units and
+        // replications is compensated in both.
         double s[4] = {0.0, 0.0, 0.0, 0.0};
         double c[4] = {0.0, 0.0, 0.0, 0.0};
         const int64_t k_end = op.k_begin + op.n_points;
@@ -818,7 +823,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? (WID
             if (valid) {
                 path_tail<R>(op, ps, mode, F);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc_add(s[i], c[i], F[i]);
+                for (int i = 0; i < 4; ++i) {
+                    if constexpr (F32) s[i] += F[i];
+                    else acc_add(s[i], c[i], F[i]);
+                }
             }
             if (base + 64 < end) step_uniform_part<PATHK>(ld, op, lane, (uint64_t)base, U);
         }
