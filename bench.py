@@ -52,8 +52,8 @@ PEAK_MFMA_BF16 = 2.5e15   # MI355X dense BF16 matrix
 # kernel sources they were taken on (sha256 prefix of their concatenation).
 TRAFFIC_SOURCES = ("paths_kernel.h", "device_math.h", "qcpw_internal.h", "ninv_table.inc")
 TRAFFIC = {
-    "portfolio": {"sha": "c2bcd3b6537a9e2d", "fetch": 1148062108, "write": 1329608192},
-    "three_products": {"sha": "c2bcd3b6537a9e2d", "fetch": 23252990, "write": 23593312},
+    "portfolio": {"sha": "cb8f8e9da2bb447d", "fetch": 1157290443, "write": 1329729088},
+    "three_products": {"sha": "cb8f8e9da2bb447d", "fetch": 14734926, "write": 17302144},
 }
 
 
@@ -61,10 +61,10 @@ TRAFFIC = {
 # of the same kernel sources (profiles/): SQ_INSTS_VALU, SQ_INSTS_VALU_FLOPS_FP32
 # and _FP64 (per wave, x64 lanes) over the launch's path-dates and paths.
 COUNTERS = {
-    "portfolio": {"sha": "c2bcd3b6537a9e2d", "valu_per_path_date": 17.94, "fp32_flops_per_path_date": 15.36,
-                  "fp64_flops_per_path": 244.2},
-    "three_products": {"sha": "c2bcd3b6537a9e2d", "valu_per_path_date": 17.32, "fp32_flops_per_path_date": 14.75,
-                       "fp64_flops_per_path": 237.3},
+    "portfolio": {"sha": "cb8f8e9da2bb447d", "valu_per_path_date": 17.78, "fp32_flops_per_path_date": 15.36,
+                  "fp64_flops_per_path": 220.0},
+    "three_products": {"sha": "cb8f8e9da2bb447d", "valu_per_path_date": 16.87, "fp32_flops_per_path_date": 14.75,
+                       "fp64_flops_per_path": 213.3},
 }
 CLOCK_HZ = 2.4e9
 SIMDS = 1024
