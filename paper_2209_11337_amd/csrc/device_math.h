@@ -256,7 +256,12 @@ __device__ inline double recip_f64(double d)
 // ln x for finite x > 0: x = 2^e m, m in [sqrt(1/2), sqrt(2)),
 // ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^23/23), s = (m - 1)/(m + 1),
 // |s| <= 0.1716; ln 2 split so that e ln2_hi is exact.
-template <bool ORDERED = true>
+//
+// SHORT = true (the kernels whose path statistic is an FP32 sum, itself
+// rounded near 1e-7 relative): shorter expansions held to about 1e-12
+// relative, here the series to s^13 (the first term left out, s^15/15, is
+// at most 1.3e-12 of s).
+template <bool ORDERED = true, bool SHORT = false>
 __device__ inline double ln_f64(double x)
 {
     int e;
@@ -267,26 +272,30 @@ __device__ inline double ln_f64(double x)
     }
     const double s = (m - 1.0) * recip_f64(m + 1.0);
     const double z = s * s;
-    double p = 1.0 / 23.0;
+    constexpr int KTOP = SHORT ? 13 : 23;
+    double p = 1.0 / KTOP;
 #pragma unroll
-    for (int k = 21; k >= 1; k -= 2) p = fma(p, z, coef_after<ORDERED>(1.0 / k, p));
+    for (int k = KTOP - 2; k >= 1; k -= 2) p = fma(p, z, coef_after<ORDERED>(1.0 / k, p));
     const double de = (double)e;
     return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * p));
 }
 
 // exp x for |x| < 700 (beyond, below about -745 it underflows to 0):
 // x = k ln 2 + r, |r| <= ln2/2, e^r by its Taylor series to r^13, scaled by
-// 2^k.
-template <bool ORDERED = true>
+// 2^k; SHORT: to r^10 (the remainder r^11/11! e^r <= 3.2e-13 relative).
+template <bool ORDERED = true, bool SHORT = false>
 __device__ inline double exp_f64(double x)
 {
     const double k = rint(x * 1.44269504088896340736);
     double r = fma(-k, 6.93147180369123816490e-01, x);
     r = fma(-k, 1.90821492927058770002e-10, r);
-    double p = 1.0 / 6227020800.0;   // 1/13!
-    double f = 6227020800.0;
+    constexpr int JTOP = SHORT ? 10 : 13;
+    double f = 1.0;
 #pragma unroll
-    for (int j = 12; j >= 0; --j) {
+    for (int j = 2; j <= JTOP; ++j) f *= j;   // JTOP! (compile-time constant)
+    double p = 1.0 / f;
+#pragma unroll
+    for (int j = JTOP - 1; j >= 0; --j) {
         f /= (j + 1);                 // j! (compile-time constant after unrolling)
         p = fma(p, r, coef_after<ORDERED>(1.0 / f, p));
     }
@@ -294,15 +303,19 @@ __device__ inline double exp_f64(double x)
 }
 
 // erfcx(x) = exp(x^2) erfc(x) for x >= 0: t P(t), t = 3/(3 + x)
-// (phi_f64_coeffs.inc).
-template <bool ORDERED = true>
+// (phi_f64_coeffs.inc: degree 21, 8.6e-16 relative; SHORT: degree 15,
+// 1.5e-11 relative).
+template <bool ORDERED = true, bool SHORT = false>
 __device__ inline double erfcx_f64(double x)
 {
+    constexpr const double *P = SHORT ? QCPW_ERFCX_S : QCPW_ERFCX_P;
+    constexpr int NP = SHORT ? (int)(sizeof(QCPW_ERFCX_S) / sizeof(double))
+                             : (int)(sizeof(QCPW_ERFCX_P) / sizeof(double));
     const double t = QCPW_ERFCX_C * recip_f64(QCPW_ERFCX_C + x);
-    double p = coef_after<ORDERED>(QCPW_ERFCX_P[0], t);
+    double p = coef_after<ORDERED>(P[0], t);
 #pragma unroll
-    for (int i = 1; i < (int)(sizeof(QCPW_ERFCX_P) / sizeof(double)); ++i)
-        p = fma(p, t, coef_after<ORDERED>(QCPW_ERFCX_P[i], p));
+    for (int i = 1; i < NP; ++i)
+        p = fma(p, t, coef_after<ORDERED>(P[i], p));
     return t * p;
 }
 
@@ -355,47 +368,48 @@ __device__ inline double ninv_f64(uint32_t y)
 // model) D1 = e^{-rT} e^{omega t1 + s1^2/2}, s1 = sigma sqrt(rho t1), and
 // the vega gains vx_shift X from the sigma dependence of that factor.
 // lnA = ln A (the path statistics that come as a power of two pass it in
-// exactly; the others compute it).
+// exactly; the others compute it).  SHORT: the shorter expansions of ln, exp
+// and erfcx, for path statistics summed in FP32.
+template <bool SHORT = false>
 __device__ inline void path_greeks(const OptDev &op_in, double A, double lnA, double Xs, double VXs, double F[4])
 {
     const OptDev &op = *reread(&op_in);
     const double psi = (op.c0 - lnA) * op.inv_s1;
-    const double g0 = exp_f64(-0.5 * psi * psi);
-    const double e0 = 0.5 * g0 * erfcx_f64(fabs(psi) * M_SQRT1_2);
+    const double g0 = exp_f64<true, SHORT>(-0.5 * psi * psi);
+    const double e0 = 0.5 * g0 * erfcx_f64<true, SHORT>(fabs(psi) * M_SQRT1_2);
     const bool put = qcpw_is_put(op.type);
     const double T0 = ((psi >= 0.0) != put) ? e0 : 1.0 - e0;    // call: 1 - Phi(psi); put: Phi(psi)
-    const double sgn = put ? -1.0 : 1.0;
-    const double phi0 = g0 * 0.398942280401432677939946;
+    // the per-option factors sDK, sD1, h2, gv, gg, gb, gd fold the products of
+    // D, K, D1, h, S0, s1, sqrt(t1) and 1/sqrt(2 pi) (qcpw_internal.h)
     if (op.type == QCPW_BINARY_ASIAN_CALL || op.type == QCPW_BINARY_ASIAN_PUT) {
-        const double Dphi = sgn * op.D * phi0;
+        const double Dphi = g0 * op.gb;                          // sgn D phi(psi)
         F[0] = op.D * T0;
-        F[1] = Dphi * op.inv_s1 * op.inv_S0;
+        F[1] = g0 * op.gd;
         F[2] = Dphi * (VXs * recip_f64(Xs) * op.inv_s1 + psi * op.inv_sigma - op.sqrt_t1);
-        F[3] = Dphi * op.inv_s1 * op.inv_S0sq * (psi * op.inv_s1 - 1.0);
+        F[3] = g0 * op.gg * (psi * op.inv_s1 - 1.0);
     } else {
         // the Gaussian factor at psi - s1 only where the payoff needs it
         const double psi1 = psi - op.s1;
-        const double e1 = 0.5 * (g0 * op.h * recip_f64(A)) * erfcx_f64(fabs(psi1) * M_SQRT1_2);
+        const double e1 = (g0 * op.h2) * recip_f64(A) * erfcx_f64<true, SHORT>(fabs(psi1) * M_SQRT1_2);
         const double T1 = ((psi1 >= 0.0) != put) ? e1 : 1.0 - e1;   // the same at psi - s1
-        const double X = op.S0 * Xs;
-        const double DKphi = op.D * op.K * phi0;
-        const double D1T1 = sgn * op.D1 * T1;
-        F[0] = D1T1 * X - sgn * op.D * op.K * T0;
+        const double D1T1 = op.sD1 * T1;
+        F[0] = fma(D1T1, op.S0 * Xs, -op.sDK * T0);
         F[1] = D1T1 * Xs;
-        F[2] = D1T1 * (op.S0 * fma(op.vx_shift, Xs, VXs)) + DKphi * op.sqrt_t1;
-        F[3] = DKphi * op.inv_s1 * op.inv_S0sq;
+        F[2] = fma(D1T1, op.S0 * fma(op.vx_shift, Xs, VXs), g0 * op.gv);
+        F[3] = g0 * op.gg;
     }
 }
 
 template <typename R>
 __device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, int mode, double F[4])
 {
+    constexpr bool SHORT = sizeof(R) == sizeof(float);   // the statistic is an FP32 sum
     const OptDev &op = *reread(&op_in);
     double A, lnA, Xs, VXs;
     if (mode == QCPW_STAT_MAX || mode == QCPW_STAT_MIN) {
         // A = 2^bY: ln A = bY ln 2 exactly (no logarithm of the rounded power)
         const double by = (double)ps.bY;
-        A = exp_f64(by * 0.69314718055994530942);
+        A = exp_f64<true, SHORT>(by * 0.69314718055994530942);
         lnA = by * 0.69314718055994530942;
         Xs = A;
         VXs = A * (by - op.kappa * (double)ps.bm) * op.inv_sig_log2e;
@@ -403,16 +417,16 @@ __device__ inline void path_tail(const OptDev &op_in, const PathSums<R> &ps, int
         // X/S0 = 2^{mean Y}; sum over dates of (W~ - sigma tau) = (sum Y - kappa sum m)/(sigma log2 e)
         const double sy = (double)ps.A2y;
         lnA = sy * op.invd * 0.69314718055994530942;
-        A = exp_f64(lnA);
+        A = exp_f64<true, SHORT>(lnA);
         Xs = A;
         VXs = A * (sy - op.kappa * 0.5 * (double)op.n * (double)(op.n + 1)) * op.invd * op.inv_sig_log2e;
     } else {
         A = (double)ps.A1;                      // ln d is folded into c0
-        lnA = ln_f64(A);
+        lnA = ln_f64<true, SHORT>(A);
         Xs = A * op.invd;
         VXs = ((double)ps.A2y - op.kappa * (double)ps.A2m) * op.invd * op.inv_sig_log2e;
     }
-    path_greeks(op, A, lnA, Xs, VXs, F);
+    path_greeks<SHORT>(op, A, lnA, Xs, VXs, F);
 }
 
 template <typename R>

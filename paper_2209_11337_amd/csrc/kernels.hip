@@ -290,6 +290,20 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
             op.b_common_f = (float)op.b_common;
             op.b_idio_f = (float)op.b_idio;
         }
+        {
+            const double sgn = qcpw_is_put(sp.type) ? -1.0 : 1.0;
+            const double PHI_C = 0.398942280401432677939946;   // 1/sqrt(2 pi)
+            op.sDK = sgn * op.D * op.K;
+            op.sD1 = sgn * op.D1;
+            op.h2 = 0.5 * op.h;
+            op.gv = op.D * op.K * PHI_C * op.sqrt_t1;
+            op.gg = op.D * op.K * PHI_C * op.inv_s1 * op.inv_S0sq;
+            if (sp.type == QCPW_BINARY_ASIAN_CALL || sp.type == QCPW_BINARY_ASIAN_PUT) {
+                op.gb = sgn * op.D * PHI_C;
+                op.gd = op.gb * op.inv_s1 * op.inv_S0;
+                op.gg = op.gb * op.inv_s1 * op.inv_S0sq;
+            }
+        }
         cost[i] = (double)std::max(op.ndims, 1) * (double)op.chunks;
         lp.max_n = std::max(lp.max_n, op.ndims);
     }

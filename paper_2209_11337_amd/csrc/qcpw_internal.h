@@ -285,6 +285,11 @@ struct OptDev {
     // derivative of the drift factor exp(omega t1 + s1^2/2) per unit X
     double b_common, b_idio, vx_shift;
     float b_common_f, b_idio_f;
+    // per-option factors of the FP64 tail (sgn = -1 for puts, phi_c =
+    // 1/sqrt(2 pi)); averages, extremes: sDK = sgn D K, sD1 = sgn D1, h2 = h/2,
+    // gv = D K phi_c sqrt_t1, gg = D K phi_c inv_s1 inv_S0sq; binary:
+    // gb = sgn D phi_c, gd = gb inv_s1 inv_S0, gg = gb inv_s1 inv_S0sq
+    double sDK, sD1, h2, gv, gg, gb, gd;
 };
 
 // Packed work description for one launch.
