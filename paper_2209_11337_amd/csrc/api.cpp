@@ -103,10 +103,11 @@ static qcpw_status init_tables(Context *ctx, int device)
         std::copy(ev.begin(), ev.end(), sev.begin() + (size_t)n * QCPW_SPLIT_EVENTS * QCPW_EV_WORDS);
         std::copy(sd.begin(), sd.end(), sdim.begin() + (size_t)n * QCPW_SPLIT_SLOTS);
     }
-    // the compile-time bridges give the split bridge's bits, and the
-    // 128-VGPR kernel instances walk their n with the split bridge
-    for (int n = 1; n <= QCPW_MAX_N; ++n)
-        if (qcpw_has_fixed_bridge(n) && t.split_slots[n] == 0)
+    // every n from QCPW_SUB_MIN_LEN on has a split plan (the compile-time
+    // bridges give its bits, and the 128-VGPR kernel instances walk their n
+    // with it): a missing one is a defect of the plan builder
+    for (int n = QCPW_SUB_MIN_LEN; n <= QCPW_MAX_N; ++n)
+        if (t.split_slots[n] == 0)
             return fail(QCPW_EDEVICE, "no split-bridge plan for n = " + std::to_string(n));
     QCPW_HIP(hipMalloc(&t.split_ev, sev.size() * 4));
     QCPW_HIP(hipMalloc(&t.split_dim, sdim.size() * 2));

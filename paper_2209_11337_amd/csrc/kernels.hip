@@ -437,7 +437,8 @@ void fill_launch_upload(const LaunchPlan &lp, void *dst)
 size_t launch_workspace_bytes(const LaunchPlan &lp) { return ws_layout(lp).total; }
 
 // LDS of the fused kernel at workgroup size bd.  FP32: the inverse-normal
-// cells and the lane rows at fixed places (qcpw_row_word), the bridge stacks
+// cells and the lane rows at fixed places (qcpw_row_word, with the copies of
+// the gap's last rows when rows go beyond it), the bridge stacks
 // after the last row, or in the gap below the upper cells when they fit
 // there.  FP64: the rows from 0, then the stacks.  *stk_off (optional)
 // receives the stacks' byte offset.
@@ -451,7 +452,7 @@ static size_t paths_lds_bytes(const LaunchPlan &lp, int bd, int *stk_off)
     }
     const bool in_gap = lp.max_n <= QCPW_LDS_GAP_ROWS;
     const size_t rows_end = in_gap ? QCPW_LDS_GAP_BEGIN + (size_t)lp.max_n * 256
-                                   : QCPW_LDS_FIXED + (size_t)(lp.max_n - QCPW_LDS_GAP_ROWS) * 256;
+                                   : (size_t)qcpw_row_word_hi(lp.max_n) * 4;
     const size_t s = (in_gap && rows_end + stack > QCPW_LDS_TAB_HI) ? QCPW_LDS_FIXED : rows_end;
     if (stk_off) *stk_off = (int)s;
     return std::max<size_t>(s + stack, QCPW_LDS_FIXED);

@@ -336,12 +336,7 @@ __device__ __forceinline__ uint32_t pick_reg(const uint32_t (&V)[NQ], int reg)
 }
 
 // Dimension of a lane-table word offset (probe instances only).
-__device__ __forceinline__ int dim_of_row_word(uint32_t w)
-{
-    const int r = w < QCPW_LDS_TAB_HI / 4 ? (int)(w - QCPW_LDS_GAP_BEGIN / 4) / 64
-                                          : QCPW_LDS_GAP_ROWS + (int)(w - QCPW_LDS_FIXED / 4) / 64;
-    return r + 1;
-}
+__device__ __forceinline__ int dim_of_row_word(uint32_t w) { return qcpw_word_row(w) + 1; }
 
 // The wave-uniform parts of one subtree's nodes: slots base .. base + len - 2
 // of register reg.  Without scrambling they are copied into every row of 16
@@ -403,15 +398,38 @@ __device__ __forceinline__ void consume_ev(PathSums<float> &ps, float Y, uint32_
     else consume<float, MODE>(ps, Y, __uint_as_float(mf_bits));
 }
 
+// Lane-table word of depth-first subtree step S: the first node of its
+// level (event word 4 + level) plus 64 per node to its left on that level
+// (a compile-time offset, so the read takes it as an immediate).
+template <int LEN, int S>
+__device__ __forceinline__ uint32_t sub_word(const uint32_t *E)
+{
+    if constexpr (S < LEN - 1) {
+        constexpr QcpwSubPos p = qcpw_sub_pos(LEN, S);
+        return E[4 + p.level] + 64u * p.index;
+    } else {
+        return (uint32_t)QCPW_LDS_GAP_BEGIN / 4;   // past the subtree: a row that exists
+    }
+}
+template <int LEN, int S>
+__device__ __forceinline__ const uint32_t *sub_row(const uint32_t *E, const uint32_t *row0)
+{
+    if constexpr (S < LEN - 1) {
+        constexpr QcpwSubPos p = qcpw_sub_pos(LEN, S);
+        return row0 + E[4 + p.level] + 64 * p.index;
+    } else {
+        return row0 + QCPW_LDS_GAP_BEGIN / 4;
+    }
+}
+
 // Normals of subtree nodes S0 .. S0 + QCPW_ZB - 1 (those below LEN - 1).
 template <class UP, int LEN, int S0, int... I>
 __device__ __forceinline__ void sub_zbatch(const uint32_t *E, const uint32_t *row0, int lane, const UP &U,
                                            const SubU<UP> &su, float (&zb)[QCPW_ZB], std::integer_sequence<int, I...>)
 {
-    const uint32_t off[] = {(S0 + I < LEN - 1 ? (E[4 + (S0 + I) / 2] >> (16 * ((S0 + I) & 1))) & 0xFFFFu
-                                              : (uint32_t)QCPW_LDS_GAP_BEGIN / 4)...};
-    uint32_t x[] = {su.template bits<S0 + I>(row0[off[I]])...};
-    if constexpr (UP::PROBE) ((S0 + I < LEN - 1 ? (void)U.rec(x[I], dim_of_row_word(off[I]), lane) : (void)0), ...);
+    uint32_t x[] = {su.template bits<S0 + I>(*sub_row<LEN, S0 + I>(E, row0))...};
+    if constexpr (UP::PROBE)
+        ((S0 + I < LEN - 1 ? (void)U.rec(x[I], dim_of_row_word(sub_word<LEN, S0 + I>(E)), lane) : (void)0), ...);
     ninv_batch<UP, (LEN - 1 - S0 < QCPW_ZB ? LEN - 1 - S0 : QCPW_ZB)>(x, zb);
 }
 
@@ -738,6 +756,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? (WID
             cells[(i < QCPW_NINV_TAB_CELLS ? 0 : QCPW_LDS_TAB_HI / 16 - QCPW_NINV_TAB_CELLS) + i] = ninv_tab[i];
     }
     for (int i = tid; i < max_n * 64; i += bd) lds_lane[lane_row<F32>(i >> 6) + (i & 63)] = lane_tab[64 + i];
+    if (F32 && max_n > QCPW_LDS_GAP_ROWS) {
+        // the upper region's copies of the gap's last rows
+        constexpr int r0 = QCPW_LDS_GAP_ROWS - QCPW_LDS_DUP_ROWS;
+        for (int i = tid; i < QCPW_LDS_DUP_ROWS * 64; i += bd)
+            lds_lane[qcpw_row_word_hi(r0 + (i >> 6)) + (i & 63)] = lane_tab[64 + r0 * 64 + i];
+    }
     __syncthreads();
 
     // Units are dealt out by QCPW_QUEUES counters, queue q holding units

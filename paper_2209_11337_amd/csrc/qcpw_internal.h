@@ -27,17 +27,33 @@
 // the lower-half inverse-normal cells at 0, the upper-half cells at
 // QCPW_LDS_TAB_HI (the sign bit of the cell offset), the lane-table rows of
 // dimensions 1..QCPW_LDS_GAP_ROWS between them and the rest after the upper
-// cells; the bridge stacks follow the rows.
+// cells; the bridge stacks follow the rows.  When rows go beyond the gap,
+// the upper region starts with a second copy of the last QCPW_LDS_DUP_ROWS
+// rows of the gap, so that a run of consecutive rows that crosses the gap
+// (the split bridge reads a subtree's nodes of one level as such a run) can
+// be read at one base and a fixed stride from the upper region.
 #define QCPW_LDS_TAB_HI 0x8000
 #define QCPW_LDS_GAP_BEGIN 0x1000
 #define QCPW_LDS_FIXED (QCPW_LDS_TAB_HI + 0x1000)
 #define QCPW_LDS_GAP_ROWS ((QCPW_LDS_TAB_HI - QCPW_LDS_GAP_BEGIN) / 256)
+#define QCPW_LDS_DUP_ROWS 8
 
+// 32-bit word offset of lane-table row r (dimension r + 1) in the upper
+// region, r >= QCPW_LDS_GAP_ROWS - QCPW_LDS_DUP_ROWS
+__host__ __device__ constexpr int qcpw_row_word_hi(int r)
+{
+    return QCPW_LDS_FIXED / 4 + 64 * (r - (QCPW_LDS_GAP_ROWS - QCPW_LDS_DUP_ROWS));
+}
 // 32-bit word offset in that LDS of lane-table row r (dimension r + 1)
 __host__ __device__ constexpr int qcpw_row_word(int r)
 {
-    return r < QCPW_LDS_GAP_ROWS ? QCPW_LDS_GAP_BEGIN / 4 + 64 * r
-                                 : QCPW_LDS_FIXED / 4 + 64 * (r - QCPW_LDS_GAP_ROWS);
+    return r < QCPW_LDS_GAP_ROWS ? QCPW_LDS_GAP_BEGIN / 4 + 64 * r : qcpw_row_word_hi(r);
+}
+// ... and back: the row at a word offset of either region
+__host__ __device__ constexpr int qcpw_word_row(uint32_t w)
+{
+    return w < QCPW_LDS_TAB_HI / 4 ? (int)(w - QCPW_LDS_GAP_BEGIN / 4) / 64
+                                   : QCPW_LDS_GAP_ROWS - QCPW_LDS_DUP_ROWS + (int)(w - QCPW_LDS_FIXED / 4) / 64;
 }
 
 // Work queues of the fused kernel: one head per XCD, each on its own
@@ -225,8 +241,37 @@ __host__ __device__ constexpr uint32_t qcpw_ev_header(int kind, int len, int reg
 // index carried in a float whose bits grow with it by one per step);
 // terminal / top: [4] lane-table word of the node's dimension, [5] wl,
 // [6] wr, [7] sd (units of sqrt(dt)); terminal: [8] the number of events;
-// top: [8] l, [9] r (its interval); subtree: [4..15] the lane-table words of
-// its nodes in depth-first order, two 16-bit values per word.
+// top: [8] l, [9] r (its interval); subtree: [4 + j], j = 0..4, the
+// lane-table word of the first node of the subtree's level j.  The
+// breadth-first numbering gives the nodes of one level of a subtree
+// consecutive dimensions, left to right, so node i of level j reads the
+// word [4 + j] + 64 i (qcpw_sub_pos gives (j, i) of a depth-first step).
+
+// Level and left-to-right index, among the nodes of that level, of the
+// depth-first step s of a subtree over (0, len).
+struct QcpwSubPos {
+    int level, index;
+};
+__host__ __device__ constexpr int qcpw_sub_left(int l, int r, int depth, int level, int lo)
+{
+    // nodes of the given level below (l, r) whose interval starts left of lo
+    if (r - l < 2) return 0;
+    if (depth == level) return l < lo ? 1 : 0;
+    const int m = (l + r) / 2;
+    return qcpw_sub_left(l, m, depth + 1, level, lo) + qcpw_sub_left(m, r, depth + 1, level, lo);
+}
+__host__ __device__ constexpr QcpwSubPos qcpw_sub_pos(int len, int s)
+{
+    int l = 0, r = len, step = 0, depth = 0;
+    while (step != s) {
+        const int m = (l + r) / 2;
+        if (s <= step + (m - l - 1)) { step += 1; r = m; }   // in the left subtree (m - l - 1 nodes)
+        else { step += m - l; l = m; }                      // skip the midpoint and its left subtree
+        ++depth;
+    }
+    return QcpwSubPos{depth, qcpw_sub_left(0, len, 0, depth, l)};
+}
+#define QCPW_SUB_LEVELS 5        // levels of a subtree of length <= QCPW_SUB_MAX_LEN
 
 // Depth-first position of the midpoint of (lo, hi) inside a subtree over
 // (0, len) (root 0, left subtree before right subtree): the midpoint of an

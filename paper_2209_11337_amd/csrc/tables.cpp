@@ -216,16 +216,23 @@ int build_split_plan(int n, std::vector<uint32_t> &ev, std::vector<uint16_t> &sl
             if (sub_slot / 64 != (sub_slot + nodes - 1) / 64) sub_slot = (sub_slot / 64 + 1) * 64;
             if (sub_slot + nodes > QCPW_SPLIT_SLOTS) { ok = false; return; }
             uint32_t *w = head(QCPW_EV_SUB, len, sub_slot, l);
-            // the subtree's midpoints in depth-first order
+            // the subtree's midpoints in depth-first order; per level the
+            // first node's row, the others following it one row apart (in
+            // the upper region when the level's rows cross the gap)
             int t = 0;
+            int first[QCPW_SUB_LEVELS], last[QCPW_SUB_LEVELS];
+            for (int j = 0; j < QCPW_SUB_LEVELS; ++j) first[j] = last[j] = -1;
             std::function<void(int, int)> walk = [&](int lo, int hi) {
                 if (hi - lo < 2) return;
                 const int m = (lo + hi) / 2;
                 auto it = dim_of.find({l + lo, l + hi});
                 if (it == dim_of.end() || qcpw_sub_step(len, lo, hi) != t) { ok = false; return; }
-                const int off = qcpw_row_word(it->second - 1);
-                if (off > 0xFFFF) { ok = false; return; }
-                w[4 + t / 2] |= (uint32_t)off << (16 * (t & 1));
+                const QcpwSubPos p = qcpw_sub_pos(len, t);
+                const int row = it->second - 1;
+                if (p.level >= QCPW_SUB_LEVELS || (p.index == 0) != (first[p.level] < 0) ||
+                    (p.index > 0 && row != first[p.level] + p.index)) { ok = false; return; }
+                if (p.index == 0) first[p.level] = row;
+                last[p.level] = row;
                 slot_dim[sub_slot + t] = (uint16_t)it->second;
                 ++t;
                 walk(lo, m);
@@ -233,6 +240,11 @@ int build_split_plan(int n, std::vector<uint32_t> &ev, std::vector<uint16_t> &sl
             };
             walk(0, len);
             if (t != nodes) ok = false;
+            for (int j = 0; ok && j < QCPW_SUB_LEVELS && first[j] >= 0; ++j) {
+                if (last[j] < QCPW_LDS_GAP_ROWS) w[4 + j] = (uint32_t)qcpw_row_word(first[j]);
+                else if (first[j] >= QCPW_LDS_GAP_ROWS - QCPW_LDS_DUP_ROWS) w[4 + j] = (uint32_t)qcpw_row_word_hi(first[j]);
+                else ok = false;
+            }
             sub_slot += nodes;
             return;
         }
@@ -265,11 +277,7 @@ void split_plan_factor(int n, double dt, const std::vector<uint32_t> &ev, std::v
 {
     A.assign((size_t)n * n, std::nan(""));
     const int n_ev = (int)ev[8];
-    auto word_dim = [](uint32_t w) {
-        const int r = w < QCPW_LDS_TAB_HI / 4 ? (int)(w - QCPW_LDS_GAP_BEGIN / 4) / 64
-                                              : QCPW_LDS_GAP_ROWS + (int)(w - QCPW_LDS_FIXED / 4) / 64;
-        return r + 1;
-    };
+    auto word_dim = [](uint32_t w) { return qcpw_word_row(w) + 1; };
     const double sdt = std::sqrt(dt);
     for (int col = 0; col < n; ++col) {
         std::vector<double> W(n + 1, std::nan(""));
@@ -298,7 +306,8 @@ void split_plan_factor(int n, double dt, const std::vector<uint32_t> &ev, std::v
                     const int mm = (lo + hi) / 2;
                     const double wl = (double)(hi - mm) / (double)(hi - lo), wr = (double)(mm - lo) / (double)(hi - lo);
                     const double sd = qcpw_csqrt((double)(mm - lo) * (double)(hi - mm) / (double)(hi - lo));
-                    const uint32_t off = (w[4 + t_node / 2] >> (16 * (t_node & 1))) & 0xFFFFu;
+                    const QcpwSubPos p = qcpw_sub_pos(len, t_node);
+                    const uint32_t off = w[4 + p.level] + 64u * (uint32_t)p.index;
                     ++t_node;
                     const double Y = wl * WL + wr * WR + sd * zof(word_dim(off));
                     W[m + mm] = Y;
