@@ -398,43 +398,65 @@ __device__ __forceinline__ void consume_ev(PathSums<float> &ps, float Y, uint32_
     else consume<float, MODE>(ps, Y, __uint_as_float(mf_bits));
 }
 
-// Lane-table word of depth-first subtree step S: the first node of its
-// level (event word 4 + level) plus 64 per node to its left on that level
-// (a compile-time offset, so the read takes it as an immediate).
-template <int LEN, int S>
-__device__ __forceinline__ uint32_t sub_word(const uint32_t *E)
+// Number of levels of a subtree over (0, len).
+__host__ __device__ constexpr int qcpw_sub_levels(int len)
 {
-    if constexpr (S < LEN - 1) {
-        constexpr QcpwSubPos p = qcpw_sub_pos(LEN, S);
-        return E[4 + p.level] + 64u * p.index;
-    } else {
-        return (uint32_t)QCPW_LDS_GAP_BEGIN / 4;   // past the subtree: a row that exists
-    }
+    int lv = 0;
+    for (int s = 0; s < len - 1; ++s)
+        if (qcpw_sub_pos(len, s).level + 1 > lv) lv = qcpw_sub_pos(len, s).level + 1;
+    return lv;
 }
-template <int LEN, int S>
-__device__ __forceinline__ const uint32_t *sub_row(const uint32_t *E, const uint32_t *row0)
-{
-    if constexpr (S < LEN - 1) {
-        constexpr QcpwSubPos p = qcpw_sub_pos(LEN, S);
-        return row0 + E[4 + p.level] + 64 * p.index;
-    } else {
-        return row0 + QCPW_LDS_GAP_BEGIN / 4;
+
+// This lane's LDS byte address in the first row of each level of a subtree
+// (the event's word 4 + level): node i of a level reads 256 i bytes further,
+// a compile-time offset.  In the 128-VGPR instances an empty asm keeps each
+// base in a register for the whole subtree (the compiler would otherwise
+// form it again per batch of nodes); the 80-VGPR instances leave that choice
+// to the compiler (measured: pinned there, they were 1-2 % slower).
+template <class UP, int LEN>
+struct SubRows {
+    static constexpr int LEVELS = qcpw_sub_levels(LEN);
+    static constexpr bool PIN = UP::NQ > QCPW_UQ;
+    const uint32_t *E, *row0;
+    uint32_t b[PIN ? LEVELS : 1];
+    __device__ __forceinline__ SubRows(const uint32_t *E_, const uint32_t *row0_, int lane) : E(E_), row0(row0_)
+    {
+        if constexpr (PIN) {
+#pragma unroll
+            for (int j = 0; j < LEVELS; ++j) {
+                b[j] = (E[4 + j] + (uint32_t)lane) * 4u;
+                asm("" : "+v"(b[j]));
+            }
+        }
     }
-}
+    template <int S>
+    __device__ __forceinline__ uint32_t word() const
+    {
+        constexpr QcpwSubPos p = qcpw_sub_pos(LEN, S < LEN - 1 ? S : 0);   // past the subtree: a row that exists
+        if constexpr (PIN) return *(const __attribute__((address_space(3))) uint32_t *)(b[p.level] + 256u * p.index);
+        else return row0[E[4 + p.level] + 64 * p.index];
+    }
+    template <int S>
+    __device__ __forceinline__ int dim() const   // probe instances only
+    {
+        constexpr QcpwSubPos p = qcpw_sub_pos(LEN, S < LEN - 1 ? S : 0);
+        return qcpw_word_row(E[4 + p.level] + 64u * p.index) + 1;
+    }
+};
 
 // Normals of subtree nodes S0 .. S0 + QCPW_ZB - 1 (those below LEN - 1).
 template <class UP, int LEN, int S0, int... I>
-__device__ __forceinline__ void sub_zbatch(const uint32_t *E, const uint32_t *row0, int lane, const UP &U,
+__device__ __forceinline__ void sub_zbatch(const uint32_t *E, const SubRows<UP, LEN> &rows, int lane, const UP &U,
                                            const SubU<UP> &su, float (&zb)[QCPW_ZB], std::integer_sequence<int, I...>)
 {
-    uint32_t x[] = {su.template bits<S0 + I>(*sub_row<LEN, S0 + I>(E, row0))...};
+    uint32_t x[] = {su.template bits<S0 + I>(rows.template word<S0 + I>())...};
     if constexpr (UP::PROBE)
-        ((S0 + I < LEN - 1 ? (void)U.rec(x[I], dim_of_row_word(sub_word<LEN, S0 + I>(E)), lane) : (void)0), ...);
+        ((S0 + I < LEN - 1 ? (void)U.rec(x[I], rows.template dim<S0 + I>(), lane) : (void)0), ...);
     ninv_batch<UP, (LEN - 1 - S0 < QCPW_ZB ? LEN - 1 - S0 : QCPW_ZB)>(x, zb);
 }
 
 template <int MODE, class UP, int LEN, int LO, int HI>
-__device__ __forceinline__ void sub_interval(const uint32_t *E, const uint32_t *row0, int lane, float zs,
+__device__ __forceinline__ void sub_interval(const uint32_t *E, const SubRows<UP, LEN> &rows, int lane, float zs,
                                              const UP &U, const SubU<UP> &su, float WL, float WR, SubSums &ss,
                                              PathSums<float> &ps, float (&zb)[QCPW_ZB])
 {
@@ -446,14 +468,14 @@ __device__ __forceinline__ void sub_interval(const uint32_t *E, const uint32_t *
         constexpr float wr = (float)((double)(M - LO) / (double)(HI - LO));
         constexpr float sd = (float)qcpw_csqrt((double)(M - LO) * (double)(HI - M) / (double)(HI - LO));
         if constexpr (S % QCPW_ZB == 0)
-            sub_zbatch<UP, LEN, S>(E, row0, lane, U, su, zb, std::make_integer_sequence<int, QCPW_ZB>());
+            sub_zbatch<UP, LEN, S>(E, rows, lane, U, su, zb, std::make_integer_sequence<int, QCPW_ZB>());
         const float z = zb[S % QCPW_ZB];
         // sd zs rounded first: the product depends on the interval length
         // alone, so the few distinct lengths of a subtree share it
         const float Ym = fmaf(__fmul_rn(sd, zs), z, fmaf(wr, WR, wl * WL));
         consume_sub<MODE, M>(ps, ss, Ym, E[3]);
-        sub_interval<MODE, UP, LEN, LO, M>(E, row0, lane, zs, U, su, WL, Ym, ss, ps, zb);
-        sub_interval<MODE, UP, LEN, M, HI>(E, row0, lane, zs, U, su, Ym, WR, ss, ps, zb);
+        sub_interval<MODE, UP, LEN, LO, M>(E, rows, lane, zs, U, su, WL, Ym, ss, ps, zb);
+        sub_interval<MODE, UP, LEN, M, HI>(E, rows, lane, zs, U, su, Ym, WR, ss, ps, zb);
     }
 }
 
@@ -465,7 +487,8 @@ __device__ __forceinline__ void run_subtree(const uint32_t *E, const uint32_t *r
     const SubU<UP> su(U, (h >> 16) & 255, h >> 24, lane);
     SubSums ss = {0.0f, 0.0f};
     float zb[QCPW_ZB];
-    sub_interval<MODE, UP, LEN, 0, LEN>(E, row0, lane, zs, U, su, L, R, ss, ps, zb);
+    const SubRows<UP, LEN> rows(E, row0, lane);
+    sub_interval<MODE, UP, LEN, 0, LEN>(E, rows, lane, zs, U, su, L, R, ss, ps, zb);
     if constexpr (MODE == QCPW_STAT_AVG) {
         ps.A1 += ss.A1;
         ps.A2m += fmaf(__uint_as_float(E[2]), ss.A1, ss.A2m);
