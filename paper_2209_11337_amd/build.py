@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqmccpw.so")
-SOURCES = ["paths_f32_bb.hip", "paths_f32_bb_owen.hip", "paths_f32_std.hip", "paths_f32_probe.hip", "paths_f64.hip",
+SOURCES = ["paths_f32_bb.hip", "paths_f32_bb_owen.hip", "paths_f32_std.hip", "paths_f32_probe.hip", "paths_f32_probe_narrow.hip", "paths_f64.hip",
            "kernels.hip", "pca.hip", "noalloc.hip", "api.cpp", "tables.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

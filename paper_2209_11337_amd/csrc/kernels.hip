@@ -480,13 +480,13 @@ qcpw_status check_lds_at_zero(const void *fn)
 }
 
 // The kernel instance of a launch: precision, construction, randomisation,
-// coordinate recording (probe instances are always wide) and register
-// budget.
+// coordinate recording and register budget (the one the plan was made for:
+// compile-time bridges run only in the 80-VGPR instances).
 static const void *select_paths_kernel(const LaunchPlan &lp)
 {
     const bool f32 = lp.precision == QCPW_FP32_MIXED;
     if (!f32) return paths_fn_f64(lp.path, lp.owen, lp.probe != nullptr);
-    if (lp.probe) return paths_fn_f32_probe(lp.path, lp.owen);
+    if (lp.probe) return paths_fn_f32_probe(lp.path, lp.owen, lp.wide);
     if (lp.path == QCPW_PATH_STANDARD) return paths_fn_f32_std(lp.owen, lp.wide);
     return lp.owen ? paths_fn_f32_bb_owen(lp.wide) : paths_fn_f32_bb(lp.wide);
 }

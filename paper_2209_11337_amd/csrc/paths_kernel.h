@@ -738,9 +738,11 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
 // VGPRs and hold 8 registers of wave-uniform slots, which the split bridge
 // needs beyond n = 356; they walk n = 15, 31, 63, 127 with the split bridge
 // too (the compile-time bridges would raise the register need of the whole
-// kernel).
+// kernel).  Coordinate-recording instances take the 128-VGPR budget either
+// way (their code paths are those of the instance they record for; only the
+// register allocation differs).
 template <bool F32, int PATHK, bool OWEN, bool PROBE, bool WIDE>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? (WIDE ? 4 : 6) : 1))) void paths_kernel(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? ((WIDE || PROBE) ? 4 : 6) : 1))) void paths_kernel(
     const OptDev *__restrict__ opts, const int64_t *__restrict__ unit_prefix, const PlanStep *__restrict__ plan_all,
     const PlanStep64 *__restrict__ plan64_all, const uint32_t *__restrict__ split_ev,
     const uint16_t *__restrict__ split_dim, const uint32_t *__restrict__ dir, const uint32_t *__restrict__ lane_tab,

@@ -159,7 +159,8 @@ int known_block_threads(Context *ctx, const LaunchPlan &lp);
 const void *paths_fn_f32_bb(bool wide);
 const void *paths_fn_f32_bb_owen(bool wide);
 const void *paths_fn_f32_std(bool owen, bool wide);
-const void *paths_fn_f32_probe(int path, bool owen);
+const void *paths_fn_f32_probe(int path, bool owen, bool wide);
+const void *paths_fn_f32_probe_narrow(bool owen);
 const void *paths_fn_f64(int path, bool owen, bool probe);
 // Runs the autotuner for every lane-table bucket of (path, precision,
 // scrambling) ahead of use; caller holds ctx->mu.
