@@ -122,7 +122,6 @@ __global__ __launch_bounds__(64) void sobol_points_kernel(const uint32_t *dir, c
 // launch planning (host)
 // ------------------------------------------------------------------------
 static inline bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
-static size_t paths_lds_bytes(const LaunchPlan &lp, int bd, int *stk_off = nullptr);
 
 qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t d, int64_t n_points,
                           int32_t n_shifts, int32_t path, int32_t precision, int32_t pca_gemm,
@@ -205,10 +204,123 @@ static bool split_bridge_on()
     return on;
 }
 
+static size_t paths_lds_bytes(const LaunchPlan &lp, const LaunchSeg &sg, int bd, int *stk_off = nullptr);
+
+// How an option is walked by a launch of the given register budget
+// (compile-time bridge in the 80-VGPR instances, split bridge, or the plan
+// walker with its LDS stack), with the uniform slots it needs.
+struct Walk {
+    bool split;
+    int slots, depth;
+};
+static Walk walk_of(Context *ctx, const LaunchPlan &lp, const OptDev &op, bool wide)
+{
+    const bool f32 = lp.precision == QCPW_FP32_MIXED;
+    const bool fixed = f32 && !wide && fixed_bridges_on() && qcpw_has_fixed_bridge(op.n);
+    Walk w;
+    w.split = lp.path == QCPW_PATH_BB && f32 && !fixed && split_bridge_on() && ctx->tab.split_slots[op.n] > 0;
+    w.slots = w.split ? ctx->tab.split_slots[op.n] : op.ndims;
+    w.depth = (lp.path == QCPW_PATH_BB && op.n >= 1 && !fixed && !w.split) ? ctx->tab.depth[op.n] : 0;
+    return w;
+}
+
+// The walks of a launch's options, and its lane rows, stack depth and units.
+static void assign_walks(Context *ctx, LaunchPlan &lp, LaunchSeg &sg)
+{
+    sg.max_n = 0;
+    sg.stack_depth = 0;
+    for (int i = sg.opt0; i < sg.opt0 + sg.n_opts; ++i) {
+        OptDev &op = lp.opts[i];
+        const Walk w = walk_of(ctx, lp, op, sg.wide);
+        op.split = w.split ? 1 : 0;
+        op.n_slots = w.slots;
+        sg.stack_depth = std::max(sg.stack_depth, w.depth);
+        sg.max_n = std::max(sg.max_n, op.ndims);
+    }
+    sg.unit0 = lp.unit_prefix[sg.opt0];
+    sg.units = lp.unit_prefix[sg.opt0 + sg.n_opts] - sg.unit0;
+}
+
+// Uniform-slot registers of the instances: the 80-VGPR ones hold QCPW_UQ.
+static bool slots_fit_narrow(const LaunchPlan &lp, const LaunchSeg &sg)
+{
+    for (int i = sg.opt0; i < sg.opt0 + sg.n_opts; ++i)
+        if (lp.opts[i].n_slots > QCPW_UQ * 64) return false;
+    return true;
+}
+
+// The fused kernel's launches.  FP64: one.  FP32: the 80-VGPR instances
+// (six waves per SIMD) as long as the lane rows fit the LDS of enough
+// workgroups to use them; up to QCPW_WIDE_MIN_N rows that holds at 512
+// threads, beyond it at 768 threads (two workgroups, 24 waves per CU) while
+// two such workgroups fit.  Longer rows leave room for one workgroup, where
+// the 128-VGPR instances (16 waves per CU, eight slot registers) are
+// faster.  A launch that mixes both kinds of options is split in two, the
+// longest options (which lead the sorted order) in a launch of the 128-VGPR
+// instances, the others in a launch of the 80-VGPR ones -- when the latter
+// hold at least a quarter of the work and the call is large enough that the
+// first launch's last units cost little.  Each option's work units, hence
+// its bits, do not depend on the launch that runs them.
+static void plan_segments(Context *ctx, LaunchPlan &lp, int force_wide)
+{
+    const bool f32 = lp.precision == QCPW_FP32_MIXED;
+    const int n = (int)lp.opts.size();
+    LaunchSeg all;
+    all.opt0 = 0;
+    all.n_opts = n;
+    all.wide = f32 && (force_wide >= 0 ? force_wide != 0 : lp.max_n > QCPW_WIDE_MIN_N);
+    int split_at = n;   // first option of an 80-VGPR launch after the 128-VGPR one (n: none)
+    if (f32 && force_wide < 0 && all.wide) {
+        // longest suffix of the sorted options (descending Sobol dimensions,
+        // so option s has the suffix's longest rows) that two 768-thread
+        // workgroups run from the LDS
+        LaunchSeg t;
+        t.wide = false;
+        for (int s = n - 1; s >= 0; --s) {
+            const Walk w = walk_of(ctx, lp, lp.opts[s], false);
+            t.max_n = lp.opts[s].ndims;
+            t.stack_depth = std::max(t.stack_depth, w.depth);
+            if (w.slots > QCPW_UQ * 64 || 2 * ((paths_lds_bytes(lp, t, 768) + 2047) / 2048 * 2048) > 160 * 1024)
+                break;
+            split_at = s;
+        }
+        if (split_at == 0) {
+            all.wide = false;
+            split_at = n;
+        } else if (split_at < n) {
+            double work = 0.0, tail = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double w = (double)(lp.unit_prefix[i + 1] - lp.unit_prefix[i]) * std::max(lp.opts[i].ndims, 1);
+                work += w;
+                if (i >= split_at) tail += w;
+            }
+            if (!(tail >= 0.25 * work && lp.total_units >= 8192)) split_at = n;
+        }
+    }
+    lp.segs.clear();
+    all.n_opts = split_at;
+    lp.segs.push_back(all);
+    if (split_at < n) {
+        LaunchSeg nar;
+        nar.opt0 = split_at;
+        nar.n_opts = n - split_at;
+        nar.wide = false;
+        lp.segs.push_back(nar);
+    }
+    for (LaunchSeg &sg : lp.segs) {
+        assign_walks(ctx, lp, sg);
+        // a forced 80-VGPR launch whose slots do not fit takes the 128-VGPR instances
+        if (f32 && !sg.wide && !slots_fit_narrow(lp, sg)) {
+            sg.wide = true;
+            assign_walks(ctx, lp, sg);
+        }
+    }
+}
+
 qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
                         int64_t n_points, int32_t n_shifts, int32_t path, int32_t precision,
                         int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp, const int64_t *k_begin,
-                        bool owen)
+                        bool owen, int force_wide)
 {
     {
         qcpw_status st = validate_call(specs, n_opts, d, n_points, n_shifts, path, precision, pca_gemm,
@@ -307,20 +419,6 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         cost[i] = (double)std::max(op.ndims, 1) * (double)op.chunks;
         lp.max_n = std::max(lp.max_n, op.ndims);
     }
-    // the lane rows of more than QCPW_WIDE_MIN_N dimensions leave room for at
-    // most two workgroups per CU, so the 80-VGPR instances gain no occupancy
-    const bool f32 = precision == QCPW_FP32_MIXED;
-    lp.wide = f32 && lp.max_n > QCPW_WIDE_MIN_N;
-    for (int i = 0; i < n_opts; ++i) {
-        OptDev &op = opts[i];
-        // options walked by a compile-time bridge (not in wide instances) or the
-        // split bridge need no LDS stack
-        const bool fixed = f32 && !lp.wide && fixed_bridges_on() && qcpw_has_fixed_bridge(op.n);
-        op.split = (path == QCPW_PATH_BB && f32 && !fixed && split_bridge_on() && ctx->tab.split_slots[op.n] > 0) ? 1 : 0;
-        op.n_slots = op.split ? ctx->tab.split_slots[op.n] : op.ndims;
-        if (path == QCPW_PATH_BB && op.n >= 1 && !fixed && !op.split)
-            lp.stack_depth = std::max(lp.stack_depth, ctx->tab.depth[op.n]);
-    }
     // Matrix-core PCA (either conditioning): options whose paths are
     // identical -- same n, seed and point range, same z scale and drift,
     // same path statistic (they differ in strike or payoff) -- share one
@@ -372,9 +470,16 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         lp.opts[i].unit0 = lp.total_units + lp.member_units;
         lp.member_units += (int64_t)lp.opts[i].chunks * n_shifts;
     }
-    lp.block_threads = block_threads > 0 ? block_threads
-                       : block_threads < 0 ? known_block_threads(ctx, lp)
-                                           : autotune_block_threads(ctx, lp);
+    if (path == QCPW_PATH_BB || path == QCPW_PATH_STANDARD) {
+        plan_segments(ctx, lp, force_wide);
+        for (LaunchSeg &sg : lp.segs)
+            sg.block_threads = block_threads > 0 ? block_threads
+                               : block_threads < 0 ? known_block_threads(ctx, lp, sg)
+                                                   : autotune_block_threads(ctx, lp, sg);
+        lp.block_threads = lp.segs[0].block_threads;
+    } else {
+        lp.block_threads = block_threads > 0 ? block_threads : 256;
+    }
     if (path == QCPW_PATH_PCA || path == QCPW_PATH_PCA_FULL) {
         const bool full = path == QCPW_PATH_PCA_FULL;
         lp.pca.resize(n_opts, nullptr);
@@ -415,7 +520,7 @@ static WsLayout ws_layout(const LaunchPlan &lp)
     w.opts = 0;
     w.prefix = align_up(w.opts + n * sizeof(OptDev), 256);
     w.counter = align_up(w.prefix + (n + 1) * sizeof(int64_t), 256);
-    w.upload = w.counter + QCPW_QUEUES * QCPW_QUEUE_STRIDE * sizeof(unsigned long long);
+    w.upload = w.counter + QCPW_MAX_SEGS * QCPW_QUEUES * QCPW_QUEUE_STRIDE * sizeof(unsigned long long);
     w.partials = align_up(w.upload, 256);
     w.per_shift = align_up(w.partials + (size_t)(lp.total_units + lp.member_units) * 8 * sizeof(double), 256);
     w.scratch = align_up(w.per_shift + n * (size_t)lp.n_shifts * 4 * sizeof(double), 256);
@@ -442,24 +547,27 @@ size_t launch_workspace_bytes(const LaunchPlan &lp) { return ws_layout(lp).total
 // after the last row, or in the gap below the upper cells when they fit
 // there.  FP64: the rows from 0, then the stacks.  *stk_off (optional)
 // receives the stacks' byte offset.
-static size_t paths_lds_bytes(const LaunchPlan &lp, int bd, int *stk_off)
+static size_t paths_lds_bytes(const LaunchPlan &lp, const LaunchSeg &sg, int bd, int *stk_off)
 {
     const bool f32 = lp.precision == QCPW_FP32_MIXED;
-    const size_t stack = lp.path == QCPW_PATH_BB ? (size_t)lp.stack_depth * bd * (f32 ? 4 : 8) : 0;
+    const size_t stack = lp.path == QCPW_PATH_BB ? (size_t)sg.stack_depth * bd * (f32 ? 4 : 8) : 0;
     if (!f32) {
-        if (stk_off) *stk_off = lp.max_n * 256;
-        return (size_t)lp.max_n * 256 + stack;
+        if (stk_off) *stk_off = sg.max_n * 256;
+        return (size_t)sg.max_n * 256 + stack;
     }
-    const bool in_gap = lp.max_n <= QCPW_LDS_GAP_ROWS;
-    const size_t rows_end = in_gap ? QCPW_LDS_GAP_BEGIN + (size_t)lp.max_n * 256
-                                   : (size_t)qcpw_row_word_hi(lp.max_n) * 4;
+    const bool in_gap = sg.max_n <= QCPW_LDS_GAP_ROWS;
+    const size_t rows_end = in_gap ? QCPW_LDS_GAP_BEGIN + (size_t)sg.max_n * 256
+                                   : (size_t)qcpw_row_word_hi(sg.max_n) * 4;
     const size_t s = (in_gap && rows_end + stack > QCPW_LDS_TAB_HI) ? QCPW_LDS_FIXED : rows_end;
     if (stk_off) *stk_off = (int)s;
     return std::max<size_t>(s + stack, QCPW_LDS_FIXED);
 }
 
 // ... against the CU's 160 KiB.
-static bool paths_lds_fits(const LaunchPlan &lp, int bd) { return paths_lds_bytes(lp, bd) <= 160 * 1024; }
+static bool paths_lds_fits(const LaunchPlan &lp, const LaunchSeg &sg, int bd)
+{
+    return paths_lds_bytes(lp, sg, bd) <= 160 * 1024;
+}
 
 // The FP32 kernels read the inverse-normal cells at absolute LDS addresses
 // (cell address = bits of q), which holds only while the kernel has no
@@ -482,67 +590,77 @@ qcpw_status check_lds_at_zero(const void *fn)
 // The kernel instance of a launch: precision, construction, randomisation,
 // coordinate recording and register budget (the one the plan was made for:
 // compile-time bridges run only in the 80-VGPR instances).
-static const void *select_paths_kernel(const LaunchPlan &lp)
+static const void *select_paths_kernel(const LaunchPlan &lp, const LaunchSeg &sg)
 {
     const bool f32 = lp.precision == QCPW_FP32_MIXED;
     if (!f32) return paths_fn_f64(lp.path, lp.owen, lp.probe != nullptr);
-    if (lp.probe) return paths_fn_f32_probe(lp.path, lp.owen, lp.wide);
-    if (lp.path == QCPW_PATH_STANDARD) return paths_fn_f32_std(lp.owen, lp.wide);
-    return lp.owen ? paths_fn_f32_bb_owen(lp.wide) : paths_fn_f32_bb(lp.wide);
+    if (lp.probe) return paths_fn_f32_probe(lp.path, lp.owen, sg.wide);
+    if (lp.path == QCPW_PATH_STANDARD) return paths_fn_f32_std(lp.owen, sg.wide);
+    return lp.owen ? paths_fn_f32_bb_owen(sg.wide) : paths_fn_f32_bb(sg.wide);
 }
 
 // Resident waves per CU of the fused kernel at workgroup size bd (0 if it
 // cannot be resident): registers, LDS and the workgroup granularity decide.
-static int resident_waves(const LaunchPlan &lp, int bd)
+static int resident_waves(const LaunchPlan &lp, const LaunchSeg &sg, int bd)
 {
-    if (!paths_lds_fits(lp, bd)) return 0;
-    const size_t lds = paths_lds_bytes(lp, bd);
-    const void *fn = select_paths_kernel(lp);
+    if (!paths_lds_fits(lp, sg, bd)) return 0;
+    const size_t lds = paths_lds_bytes(lp, sg, bd);
+    const void *fn = select_paths_kernel(lp, sg);
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds) != hipSuccess) return 0;
     return per_cu * bd / 64;
 }
 
-// Workgroup size of the fused kernel, chosen by measurement among 256, 512
-// and 1024 threads (whole multiples of the CU's four SIMDs, so that every
-// SIMD holds the same number of waves; sizes in between measured slower).
-// The lane rows and inverse-normal cells are shared per workgroup and the
-// bridge stack is per thread, so the best size depends on d.  Each size that
-// can be resident is timed on a probe -- one arithmetic Asian option with the
-// launch's largest d, 2^18 points x 64 replications (16384 work units, a few
-// per resident wave) -- and the fastest is kept per (construction,
-// precision, lane-table size bucket).  QCPW_BLOCK_THREADS in the environment
-// overrides the choice.  Only the order of floating-point sums depends on it.
-int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
+// Workgroup size of a fused-kernel launch, chosen by measurement among 256,
+// 512, 768 and 1024 threads (whole multiples of the CU's four SIMDs, so that
+// every SIMD holds the same number of waves).  The lane rows and
+// inverse-normal cells are shared per workgroup and the bridge stack is per
+// thread, so the best size depends on d and on the register budget.  Each
+// size that can be resident is timed on a probe -- one arithmetic Asian
+// option with the launch's largest d, 2^18 points x 64 replications (16384
+// work units, a few per resident wave), on the launch's kernel instance --
+// and the fastest is kept per (construction, precision, randomisation,
+// register budget, lane-table size bucket).  QCPW_BLOCK_THREADS in the
+// environment overrides the choice.  Results do not depend on it.
+static int tune_key(const LaunchPlan &lp, const LaunchSeg &sg)
+{
+    return (((lp.path * 2 + lp.precision) * 2 + (lp.owen ? 1 : 0)) * 2 + (sg.wide ? 1 : 0)) * 64 + (sg.max_n + 31) / 32;
+}
+
+int autotune_block_threads(Context *ctx, const LaunchPlan &lp, const LaunchSeg &sg)
 {
     if (lp.path == QCPW_PATH_PCA || lp.path == QCPW_PATH_PCA_FULL) return 256;
     if (const char *env = getenv("QCPW_BLOCK_THREADS")) {
         const int v = atoi(env);
-        if (v != 0 && qcpw_block_threads_ok(v) && resident_waves(lp, v) > 0) return v;
+        if (v != 0 && qcpw_block_threads_ok(v) && resident_waves(lp, sg, v) > 0) return v;
     }
-    const int key = ((lp.path * 2 + lp.precision) * 2 + (lp.owen ? 1 : 0)) * 64 + (lp.max_n + 31) / 32;
+    const int key = tune_key(lp, sg);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return it->second;
     qcpw_option_spec probe;
     memset(&probe, 0, sizeof probe);
     probe.type = QCPW_ARITH_ASIAN_CALL;
-    probe.d = std::max(lp.max_n, 1) + 1;
+    probe.d = std::max(sg.max_n, 1) + 1;
     probe.S0 = 100.0; probe.K = 100.0; probe.r = 0.05; probe.sigma = 0.2; probe.T = 1.0;
     probe.seed = 0x51ab;
     probe.n_points = int64_t(1) << 18;
     const int n_probe_shifts = 64;
+    const bool f32 = lp.precision == QCPW_FP32_MIXED;
 
     std::vector<LaunchPlan> plans;
     std::vector<int> cands;
-    for (int bd : {256, 512, 1024}) {
+    for (int bd : {256, 512, 768, 1024}) {
         LaunchPlan p;
         if (plan_launch(ctx, &probe, 1, 0, 0, n_probe_shifts, lp.path, lp.precision, lp.pca_gemm, bd, p, nullptr,
-                        lp.owen) != QCPW_OK)
+                        lp.owen, f32 ? (sg.wide ? 1 : 0) : -1) != QCPW_OK)
             continue;
-        p.max_n = std::max(p.max_n, lp.max_n);
-        p.stack_depth = std::max(p.stack_depth, lp.stack_depth);
-        if (resident_waves(p, bd) == 0) continue;
+        LaunchSeg &ps = p.segs[0];
+        if (ps.wide != sg.wide) continue;
+        ps.max_n = std::max(ps.max_n, sg.max_n);
+        ps.stack_depth = std::max(ps.stack_depth, sg.stack_depth);
+        p.max_n = ps.max_n;
+        if (resident_waves(p, ps, bd) == 0) continue;
         cands.push_back(bd);
         plans.push_back(std::move(p));
     }
@@ -592,26 +710,38 @@ int autotune_block_threads(Context *ctx, const LaunchPlan &lp)
 }
 
 // The workgroup size the autotuner has chosen for this launch's key, or --
-// without running its probes, which allocate -- 512 threads (256 when 512
-// do not fit the LDS).
-int known_block_threads(Context *ctx, const LaunchPlan &lp)
+// without running its probes, which allocate -- 768 threads for the 80-VGPR
+// instances beyond QCPW_WIDE_MIN_N lane rows, else 512 (256 when those do
+// not fit the LDS).
+int known_block_threads(Context *ctx, const LaunchPlan &lp, const LaunchSeg &sg)
 {
     if (lp.path == QCPW_PATH_PCA || lp.path == QCPW_PATH_PCA_FULL) return 256;
-    const int key = ((lp.path * 2 + lp.precision) * 2 + (lp.owen ? 1 : 0)) * 64 + (lp.max_n + 31) / 32;
-    auto it = ctx->tuned.find(key);
+    auto it = ctx->tuned.find(tune_key(lp, sg));
     if (it != ctx->tuned.end()) return it->second;
-    return paths_lds_fits(lp, 512) ? 512 : 256;
+    if (lp.precision == QCPW_FP32_MIXED && !sg.wide && sg.max_n > QCPW_WIDE_MIN_N && paths_lds_fits(lp, sg, 768))
+        return 768;
+    return paths_lds_fits(lp, sg, 512) ? 512 : 256;
 }
 
+// Tunes every lane-table size bucket of one (construction, precision,
+// randomisation) ahead of use, for each register budget a launch of that
+// size can take.
 void pretune_block_threads(Context *ctx, int path, int precision, bool owen)
 {
+    const bool f32 = precision == QCPW_FP32_MIXED;
     for (int b = 0; 32 * b <= QCPW_MAX_N; ++b) {
         LaunchPlan lp;
         lp.path = path;
         lp.precision = precision;
         lp.owen = owen;
-        lp.max_n = 32 * b;
-        (void)autotune_block_threads(ctx, lp);
+        LaunchSeg sg;
+        sg.max_n = 32 * b;
+        for (int wide = 0; wide < (f32 ? 2 : 1); ++wide) {
+            sg.wide = wide != 0;
+            if (f32 && sg.wide && sg.max_n <= QCPW_WIDE_MIN_N) continue;
+            if (f32 && !sg.wide && sg.max_n > QCPW_WIDE_MIN_N && !paths_lds_fits(lp, sg, 768)) continue;
+            (void)autotune_block_threads(ctx, lp, sg);
+        }
     }
 }
 
@@ -673,39 +803,49 @@ qcpw_status enqueue_launch(Context *ctx, const LaunchPlan &lp, hipStream_t strea
         if (st != QCPW_OK) return st;
         if (t1) QCPW_HIP(hipEventRecord(t1, stream));
     } else {
-        const int bd = lp.block_threads;
-        if (!paths_lds_fits(lp, bd)) return fail(QCPW_EDIMS, "LDS footprint exceeds 160 KiB");
-        int a_stk_off = 0;
-        const size_t lds = paths_lds_bytes(lp, bd, &a_stk_off);
-        const void *fn = select_paths_kernel(lp);
-        if (lp.precision == QCPW_FP32_MIXED) {
-            qcpw_status st = check_lds_at_zero(fn);
-            if (st != QCPW_OK) return st;
+        // the launches (one, or the 128-VGPR one and then the 80-VGPR one):
+        // each takes its options and units, with queue heads of its own
+        if (lp.segs.empty() || lp.segs.size() > QCPW_MAX_SEGS) return fail(QCPW_EDEVICE, "launch without segments");
+        for (size_t si = 0; si < lp.segs.size(); ++si) {
+            const LaunchSeg &sg = lp.segs[si];
+            if (sg.opt0 < 0 || sg.n_opts < 1 || (size_t)sg.opt0 + sg.n_opts > n || sg.units < 1 ||
+                sg.unit0 != lp.unit_prefix[sg.opt0] || sg.unit0 + sg.units != lp.unit_prefix[sg.opt0 + sg.n_opts])
+                return fail(QCPW_EDEVICE, "inconsistent launch segment");
+            const int bd = sg.block_threads;
+            if (!paths_lds_fits(lp, sg, bd)) return fail(QCPW_EDIMS, "LDS footprint exceeds 160 KiB");
+            int a_stk_off = 0;
+            const size_t lds = paths_lds_bytes(lp, sg, bd, &a_stk_off);
+            const void *fn = select_paths_kernel(lp, sg);
+            if (lp.precision == QCPW_FP32_MIXED) {
+                qcpw_status st = check_lds_at_zero(fn);
+                if (st != QCPW_OK) return st;
+            }
+            QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            int per_cu = 0;
+            QCPW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds));
+            if (per_cu < 1) return fail(QCPW_EDEVICE, "per-path kernel cannot be resident with this block size");
+            int64_t grid = (int64_t)per_cu * ctx->tab.n_cu;
+            grid = std::min<int64_t>(grid, sg.units);
+            const OptDev *a_opts = ld.opts + sg.opt0;
+            const int64_t *a_prefix = ld.unit_prefix + sg.opt0;
+            const PlanStep *a_plan = ld.plan;
+            const PlanStep64 *a_plan64 = ld.plan64;
+            const uint32_t *a_sev = ctx->tab.split_ev;
+            const uint16_t *a_sdim = ctx->tab.split_dim;
+            const uint32_t *a_dir = ld.dir, *a_lane = ld.lane;
+            const float4 *a_tab = ctx->tab.ninv_tab;
+            double *a_part = ld.partials;
+            unsigned long long *a_ctr = ld.counter + si * QCPW_QUEUES * QCPW_QUEUE_STRIDE;
+            int a_nopts = sg.n_opts, a_maxn = sg.max_n, a_depth = sg.stack_depth;
+            long long a_total = sg.units, a_base = sg.unit0;
+            int a_fixed_arg = fixed_bridges_on() ? 1 : 0;
+            uint32_t *a_probe = lp.probe;
+            void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_sev,  &a_sdim,      &a_dir,
+                            &a_lane, &a_tab,    &a_part, &a_ctr,    &a_nopts, &a_maxn,     &a_depth,
+                            &a_stk_off, &a_total, &a_base, &a_fixed_arg, &a_probe};
+            if (t0 && si == 0) QCPW_HIP(hipEventRecord(t0, stream));
+            QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
         }
-        QCPW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        int per_cu = 0;
-        QCPW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, bd, lds));
-        if (per_cu < 1) return fail(QCPW_EDEVICE, "per-path kernel cannot be resident with this block size");
-        int64_t grid = (int64_t)per_cu * ctx->tab.n_cu;
-        grid = std::min<int64_t>(grid, lp.total_units);
-        const OptDev *a_opts = ld.opts;
-        const int64_t *a_prefix = ld.unit_prefix;
-        const PlanStep *a_plan = ld.plan;
-        const PlanStep64 *a_plan64 = ld.plan64;
-        const uint32_t *a_sev = ctx->tab.split_ev;
-        const uint16_t *a_sdim = ctx->tab.split_dim;
-        const uint32_t *a_dir = ld.dir, *a_lane = ld.lane;
-        const float4 *a_tab = ctx->tab.ninv_tab;
-        double *a_part = ld.partials;
-        unsigned long long *a_ctr = ld.counter;
-        int a_nopts = ld.n_opts, a_maxn = ld.max_n, a_depth = lp.stack_depth;
-        long long a_total = ld.total_units;
-        int a_fixed_arg = fixed_bridges_on() ? 1 : 0;
-        uint32_t *a_probe = lp.probe;
-        void *args[] = {&a_opts, &a_prefix, &a_plan, &a_plan64, &a_sev, &a_sdim, &a_dir, &a_lane, &a_tab, &a_part,
-                        &a_ctr, &a_nopts, &a_maxn, &a_depth, &a_stk_off, &a_total, &a_fixed_arg, &a_probe};
-        if (t0) QCPW_HIP(hipEventRecord(t0, stream));
-        QCPW_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(bd), args, lds, stream));
         if (t1) QCPW_HIP(hipEventRecord(t1, stream));
     }
     finalize_kernel<<<(unsigned)n, 256, 0, stream>>>(d_opts, d_partials, d_per_shift, dev_out_greeks, dev_out_stderr,

@@ -748,7 +748,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? ((WI
     const uint16_t *__restrict__ split_dim, const uint32_t *__restrict__ dir, const uint32_t *__restrict__ lane_tab,
     const float4 *__restrict__ ninv_tab,   // [2][256] cells
     double *__restrict__ partials, unsigned long long *__restrict__ counter, int n_opts, int max_n, int stack_depth,
-    int stk_off, long long total_units, int fixed_bridges, uint32_t *__restrict__ probe)
+    int stk_off, long long total_units, long long unit_base, int fixed_bridges, uint32_t *__restrict__ probe)
 {
     LaunchDesc ld;
     ld.split_ev = split_ev;
@@ -812,12 +812,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? ((WI
             j = ((long long)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
                 (unsigned)__builtin_amdgcn_readfirstlane((int)u);
         }
-        const long long unit = j * QCPW_QUEUES + q;
-        if (unit >= total_units) {
+        if (j * QCPW_QUEUES + q >= total_units) {
             if (++empty == QCPW_QUEUES) break;
             q = (q + 1) & (QCPW_QUEUES - 1);
             continue;
         }
+        // this launch's units follow unit_base in the option table's numbering
+        const long long unit = unit_base + j * QCPW_QUEUES + q;
 
         // option of this unit (units are consumed in increasing order, so the
         // previous option is the usual answer)

@@ -93,24 +93,36 @@ qcpw_status get_context(int device, Context **out);
 qcpw_status get_pca(Context *ctx, int n, double dt, const Context::Pca **out, bool full = false);
 
 // ---- launches (kernels.hip) -------------------------------------------------
+// One launch of the fused per-path kernel: the sorted options
+// [opt0, opt0 + n_opts) and their work units [unit0, unit0 + units), with
+// the kernel instance (register budget) and workgroup size chosen for them.
+struct LaunchSeg {
+    int32_t opt0 = 0, n_opts = 0;
+    int64_t unit0 = 0, units = 0;
+    int max_n = 0;                     // lane rows: the largest Sobol dimension count of a path
+    int stack_depth = 0;               // deepest bridge stack among the options
+    int block_threads = 0;
+    bool wide = false;                 // FP32 kernel instance with 128 VGPRs and 8 slot registers
+};
+#define QCPW_MAX_SEGS 2
+
 struct LaunchPlan {
     // host copies of what the kernels read
     std::vector<OptDev> opts;          // sorted by cost (descending)
     std::vector<int64_t> unit_prefix;  // [n_opts + 1]
     std::vector<int32_t> order;        // opts[i] is caller's option order[i]
     int max_n = 0;
-    int stack_depth = 0;               // deepest bridge stack among the options
     int path = 0;
     int precision = 0;
     int pca_gemm = 0;
     int n_shifts = 0;
-    int block_threads = 0;
+    int block_threads = 0;             // the first launch's (256 for the matrix-core PCA kernels)
     int64_t total_units = 0;           // work units dealt by the queues
     int64_t member_units = 0;          // further units whose partials a group leader's units write
     int64_t full_blocks = 0;           // PCA_FULL in FP64: workgroups with a global scratch tile
     bool owen = false;                 // nested scrambling instead of the digital shift
-    bool wide = false;                 // FP32 kernel instance with 128 VGPRs and 8 slot registers
     uint32_t *probe = nullptr;         // device buffer: run the coordinate-recording kernel instance
+    std::vector<LaunchSeg> segs;       // fused per-path kernel launches, in order (bridge, standard)
     std::vector<const Context::Pca *> pca;   // per sorted option (PCA and PCA_FULL)
 };
 
@@ -122,10 +134,12 @@ qcpw_status validate_call(const qcpw_option_spec *specs, int32_t n_opts, int32_t
 // Builds the per-option constants and work units.  k_begin (optional, per
 // caller option) starts an option's points at a multiple of QCPW_CHUNK
 // instead of 0; n_points then counts the points from there.
+// force_wide (fused kernel, FP32): -1 chooses the launches and their
+// register budgets, 0 / 1 makes one launch of the 80- / 128-VGPR instances.
 qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_opts, int32_t d,
                         int64_t n_points, int32_t n_shifts, int32_t path, int32_t precision,
                         int32_t pca_gemm, int32_t block_threads, LaunchPlan &lp,
-                        const int64_t *k_begin = nullptr, bool owen = false);
+                        const int64_t *k_begin = nullptr, bool owen = false, int force_wide = -1);
 
 // Device bytes one launch needs in the workspace.
 size_t launch_workspace_bytes(const LaunchPlan &lp);
@@ -151,10 +165,10 @@ qcpw_status launch_sobol_points(Context *ctx, uint64_t seed, int32_t shift_index
                                 int64_t k0, int64_t count, uint32_t *dev_out, hipStream_t stream,
                                 bool owen = false);
 
-int autotune_block_threads(Context *ctx, const LaunchPlan &lp);
-// The autotuner's choice if it has one for lp's key, else a default; never
-// launches or allocates.  plan_launch takes block_threads < 0 as this.
-int known_block_threads(Context *ctx, const LaunchPlan &lp);
+int autotune_block_threads(Context *ctx, const LaunchPlan &lp, const LaunchSeg &sg);
+// The autotuner's choice if it has one for the launch's key, else a default;
+// never launches or allocates.  plan_launch takes block_threads < 0 as this.
+int known_block_threads(Context *ctx, const LaunchPlan &lp, const LaunchSeg &sg);
 // Instances of the fused per-path kernel (paths_*.hip), as kernel pointers.
 const void *paths_fn_f32_bb(bool wide);
 const void *paths_fn_f32_bb_owen(bool wide);
