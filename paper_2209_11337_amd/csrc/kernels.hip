@@ -255,8 +255,9 @@ static bool slots_fit_narrow(const LaunchPlan &lp, const LaunchSeg &sg)
 // threads, beyond it at 768 threads (two workgroups, 24 waves per CU) while
 // two such workgroups fit.  Longer rows leave room for one workgroup, where
 // the 128-VGPR instances (16 waves per CU, eight slot registers) are
-// faster.  A launch that mixes both kinds of options is split in two, the
-// longest options (which lead the sorted order) in a launch of the 128-VGPR
+// faster.  A launch that mixes both kinds of options is split in two: the
+// options that lead the sorted order (those the 80-VGPR instances would walk
+// with an LDS stack, then the longest) in a launch of the 128-VGPR
 // instances, the others in a launch of the 80-VGPR ones -- when the latter
 // hold at least a quarter of the work and the call is large enough that the
 // first launch's last units cost little.  Each option's work units, hence
@@ -271,14 +272,13 @@ static void plan_segments(Context *ctx, LaunchPlan &lp, int force_wide)
     all.wide = f32 && (force_wide >= 0 ? force_wide != 0 : lp.max_n > QCPW_WIDE_MIN_N);
     int split_at = n;   // first option of an 80-VGPR launch after the 128-VGPR one (n: none)
     if (f32 && force_wide < 0 && all.wide) {
-        // longest suffix of the sorted options (descending Sobol dimensions,
-        // so option s has the suffix's longest rows) that two 768-thread
-        // workgroups run from the LDS
+        // longest suffix of the sorted options that two 768-thread workgroups
+        // run from the LDS
         LaunchSeg t;
         t.wide = false;
         for (int s = n - 1; s >= 0; --s) {
             const Walk w = walk_of(ctx, lp, lp.opts[s], false);
-            t.max_n = lp.opts[s].ndims;
+            t.max_n = std::max(t.max_n, lp.opts[s].ndims);
             t.stack_depth = std::max(t.stack_depth, w.depth);
             if (w.slots > QCPW_UQ * 64 || 2 * ((paths_lds_bytes(lp, t, 768) + 2047) / 2048 * 2048) > 160 * 1024)
                 break;
@@ -430,11 +430,19 @@ qcpw_status plan_launch(Context *ctx, const qcpw_option_spec *specs, int32_t n_o
         return a.n == b.n && a.seed == b.seed && a.n_points == b.n_points && a.k_begin == b.k_begin &&
                a.zs_t == b.zs_t && a.ydrift_1_f == b.ydrift_1_f && qcpw_stat_of(a.type) == qcpw_stat_of(b.type);
     };
-    // most expensive units first (longest-processing-time order)
+    // most expensive units first (longest-processing-time order); in FP32
+    // bridge launches the options that the 80-VGPR instances would walk with
+    // the plan walker (its LDS stack, 12 KiB per 768-thread workgroup at
+    // n < 12) lead, so that a split call leaves them to the 128-VGPR launch
+    // and its 80-VGPR launch needs no stack
+    std::vector<char> stacked(n_opts, 0);
+    if (path == QCPW_PATH_BB && precision == QCPW_FP32_MIXED)
+        for (int i = 0; i < n_opts; ++i) stacked[i] = walk_of(ctx, lp, opts[i], false).depth > 0;
     std::vector<int32_t> order(n_opts);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const OptDev &x = opts[a], &y = opts[b];
+        if (stacked[a] != stacked[b]) return stacked[a] > stacked[b];
         if (x.ndims != y.ndims || !grouping) return x.ndims > y.ndims;
         if (x.seed != y.seed) return x.seed < y.seed;
         if (x.n_points != y.n_points) return x.n_points < y.n_points;

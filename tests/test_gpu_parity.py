@@ -215,12 +215,13 @@ def test_same_bits_in_narrow_and_wide_launches(typ):
 
 def test_same_bits_in_a_split_launch():
     """A call whose longest options need the 128-VGPR instances and whose
-    others hold most of the work runs as two launches (d = 365 in one; d =
-    16, 64, 200, 250 in the 80-VGPR one at 768 threads): 5 options x 256
-    units x 16 replications, 20480 units, 59 % of the path-dates in the second
-    launch.  Every option gives the bits it gives alone (where d = 200 and 250
-    run the 80-VGPR instances, d = 365 the 128-VGPR ones)."""
-    ds = (365, 16, 64, 200, 250)
+    others hold most of the work runs as two launches (d = 8, walked by the
+    plan walker with its stack, and d = 365 in one; d = 16, 64, 200, 250 in
+    the 80-VGPR one at 768 threads): 6 options x 256 units x 16 replications,
+    24576 units, 59 % of the path-dates in the second launch.  Every option
+    gives the bits it gives alone (where d = 8, 200 and 250 run the 80-VGPR
+    instances, d = 365 the 128-VGPR ones)."""
+    ds = (365, 16, 64, 8, 200, 250)
     opts = [dict(type=(q.ARITH_ASIAN, q.BINARY_ASIAN, q.LOOKBACK)[i % 3], d=d, S0=100.0, K=97.0 + 2 * i, r=0.04,
                  sigma=0.3, T=1.2, seed=7000 + d, n_points=1 << 16) for i, d in enumerate(ds)]
     say("split launch invariance")
