@@ -47,10 +47,12 @@ PEAK_F64 = 78.6e12        # MI355X vector FP64
 PEAK_MFMA_F32 = 157.3e12  # MI355X dense FP32 matrix
 PEAK_MFMA_BF16 = 2.5e15   # MI355X dense BF16 matrix
 
-# HBM bytes per launch of the fused kernel, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by a plain 1 GiB copy (profiles/), valid only for the
-# kernel sources they were taken on (sha256 prefix of their concatenation).
-TRAFFIC_SOURCES = ("paths_kernel.h", "device_math.h", "qcpw_internal.h", "ninv_table.inc")
+# HBM bytes per call of the fused kernel (its launches summed), from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain 1 GiB copy
+# (profiles/), valid only for the kernel and launch-planning sources they
+# were taken on (sha256 prefix of their concatenation).
+TRAFFIC_SOURCES = ("paths_kernel.h", "device_math.h", "qcpw_internal.h", "ninv_table.inc", "phi_f64_coeffs.inc",
+                   "kernels.hip")
 TRAFFIC = {
     "portfolio": {"sha": "cb8f8e9da2bb447d", "fetch": 1157290443, "write": 1329729088},
     "three_products": {"sha": "cb8f8e9da2bb447d", "fetch": 14734926, "write": 17302144},
@@ -94,7 +96,7 @@ def traffic_of(workload: str):
 
 
 def roofline(paths, path_dates, kernel_ms, fp32=True, mfma_flops=0.0, mfma_peak=PEAK_MFMA_F32,
-             kernel="qcpw::paths_kernel", traffic=None, call_ms=None, counters=None):
+             kernel="qcpw::paths_kernel (every launch of the call)", traffic=None, call_ms=None, counters=None):
     """Whole-kernel roofline of the op-count model: t_ideal = F32 / 157.3e12 +
     F64 / 78.6e12 (+ matrix flops / their peak); frac = t_ideal / t_kernel;
     achieved in FP32-equivalent TFLOP/s (each term weighted by 157.3e12 over
