@@ -54,19 +54,20 @@ PEAK_MFMA_BF16 = 2.5e15   # MI355X dense BF16 matrix
 TRAFFIC_SOURCES = ("paths_kernel.h", "device_math.h", "qcpw_internal.h", "ninv_table.inc", "phi_f64_coeffs.inc",
                    "kernels.hip")
 TRAFFIC = {
-    "portfolio": {"sha": "cb8f8e9da2bb447d", "fetch": 1157290443, "write": 1329729088},
-    "three_products": {"sha": "cb8f8e9da2bb447d", "fetch": 14734926, "write": 17302144},
+    "portfolio": {"sha": "33f0b1a17e91fc71", "fetch": 1180912546, "write": 1335600832},
+    "three_products": {"sha": "33f0b1a17e91fc71", "fetch": 15639492, "write": 20447840},
 }
 
 
 # Per-unit work the fused kernel itself executes, from the rocprofv3 counters
 # of the same kernel sources (profiles/): SQ_INSTS_VALU, SQ_INSTS_VALU_FLOPS_FP32
-# and _FP64 (per wave, x64 lanes) over the launch's path-dates and paths.
+# and _FP64 (per wave, x64 lanes, the call's launches summed) over its
+# path-dates and paths.
 COUNTERS = {
-    "portfolio": {"sha": "cb8f8e9da2bb447d", "valu_per_path_date": 17.78, "fp32_flops_per_path_date": 15.36,
-                  "fp64_flops_per_path": 220.0},
-    "three_products": {"sha": "cb8f8e9da2bb447d", "valu_per_path_date": 16.87, "fp32_flops_per_path_date": 14.75,
-                       "fp64_flops_per_path": 213.3},
+    "portfolio": {"sha": "33f0b1a17e91fc71", "valu_per_path_date": 16.83, "fp32_flops_per_path_date": 15.28,
+                  "fp64_flops_per_path": 178.7},
+    "three_products": {"sha": "33f0b1a17e91fc71", "valu_per_path_date": 16.43, "fp32_flops_per_path_date": 14.75,
+                       "fp64_flops_per_path": 172.3},
 }
 CLOCK_HZ = 2.4e9
 SIMDS = 1024
@@ -121,6 +122,8 @@ def roofline(paths, path_dates, kernel_ms, fp32=True, mfma_flops=0.0, mfma_peak=
         f32c = counters["fp32_flops_per_path_date"] * path_dates
         f64c = counters["fp64_flops_per_path"] * paths
         waves = counters["valu_per_path_date"] * path_dates / 64.0
+        # (valu_issue_frac counts 4 cycles per wave64 instruction; it exceeds 1
+        # where transcendental and other instructions overlap in the SIMD)
         out["measured"] = {"source": "rocprofv3 counters of these kernel sources (profiles/)",
                            "fp32_tflops": f32c / t_kernel / 1e12, "fp64_tflops": f64c / t_kernel / 1e12,
                            "valu_lane_instructions_per_path_date": counters["valu_per_path_date"],
