@@ -166,8 +166,8 @@ typedef struct {
     void *stream;               /* hipStream_t to run on (NULL = the default stream) */
     double *out_per_shift;      /* optional [n_opts][L][4] per-replication C_l       */
     int32_t block_threads;      /* 0 = autotuned; else a multiple of 64 in [64, 1024]
-                                   (workgroup size of the per-path kernel; the PCA
-                                   kernel always uses 256)                          */
+                                   (workgroup size of the per-path kernel's launches;
+                                   the PCA kernel always uses 256)                  */
     int32_t flags;              /* QCPW_FLAG_* bits                                  */
     double *out_paper_sigma;    /* optional [n_opts][4]: the spread of the single
                                    replications sqrt((1/L) sum_l (C - C_l)^2), the
@@ -196,10 +196,13 @@ typedef struct {
  * qmc_cpw_greeks_ex -- as qmc_cpw_greeks with explicit precision, device,
  * stream and output placement.  cfg may be NULL (defaults of
  * qmc_cpw_greeks).  Options of different d, n_points and type share one
- * persistent launch.  With outputs_on_device the caller keeps the output
- * buffers alive until the stream reaches them; the library's temporary
- * device buffers stay owned by the library and are reused by later calls on
- * the same device (calls on one device are serialised internally).
+ * persistent launch -- or two, when the call mixes options whose Sobol
+ * dimensions fill the LDS with others that run faster apart (an option's
+ * results do not depend on which).  With outputs_on_device the caller keeps
+ * the output buffers alive until the stream reaches them; the library's
+ * temporary device buffers stay owned by the library and are reused by
+ * later calls on the same device (calls on one device are serialised
+ * internally).
  */
 qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_opts,
                               int32_t d, int64_t n_points, int32_t n_shifts,
@@ -216,8 +219,9 @@ qcpw_status qmc_cpw_greeks_ex(const qcpw_option_spec *option_specs, int32_t n_op
  * arguments, results and errors as qmc_cpw_greeks_ex, except:
  *   - path_construction QCPW_PATH_BB or QCPW_PATH_STANDARD, flags 0 or
  *     QCPW_FLAG_OWEN (QCPW_EINVAL otherwise);
- *   - block_threads 0 takes the autotuner's earlier choice for the launch's
- *     shape if there is one, else 512 threads -- its probe launches are
+ *   - block_threads 0 takes the autotuner's earlier choice for each
+ *     launch's shape if there is one, else 512 threads (768 for the
+ *     launches that need them to fill a CU) -- its probe launches are
  *     never run here;
  *   - QCPW_ENOMEM, before any device work, when the launch needs more than
  *     QCPW_NOALLOC_BYTES: 64 bytes per work unit (units = sum over options
@@ -287,7 +291,8 @@ qcpw_status qcpw_path_factor(int32_t path_construction, int32_t d, double T, dou
  * kernel, or the PCA kernel) of each qmc_cpw_greeks / qmc_cpw_greeks_ex call
  * on `device` (-1 = current) that runs eagerly (not from a captured graph,
  * not from a server).  The library records a pair of HIP events on the
- * call's stream around that kernel alone.
+ * call's stream around that kernel alone (before its first and after its
+ * last launch when the call takes two).
  *   op = QCPW_TIMER_START: forget earlier pairs and start recording;
  *   op = QCPW_TIMER_READ:  wait for the recorded events, write the summed
  *        kernel time in milliseconds to *total_ms and the number of timed
