@@ -273,7 +273,7 @@ __device__ inline double ln_f64(double x)
     const double s = (m - 1.0) * recip_f64(m + 1.0);
     const double z = s * s;
     constexpr int KTOP = SHORT ? 13 : 23;
-    double p = 1.0 / KTOP;
+    double p = coef_after<ORDERED>(1.0 / KTOP, z);
 #pragma unroll
     for (int k = KTOP - 2; k >= 1; k -= 2) p = fma(p, z, coef_after<ORDERED>(1.0 / k, p));
     const double de = (double)e;
@@ -293,7 +293,7 @@ __device__ inline double exp_f64(double x)
     double f = 1.0;
 #pragma unroll
     for (int j = 2; j <= JTOP; ++j) f *= j;   // JTOP! (compile-time constant)
-    double p = 1.0 / f;
+    double p = coef_after<ORDERED>(1.0 / f, r);
 #pragma unroll
     for (int j = JTOP - 1; j >= 0; --j) {
         f /= (j + 1);                 // j! (compile-time constant after unrolling)

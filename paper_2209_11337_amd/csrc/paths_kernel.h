@@ -888,7 +888,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(F32 ? ((WI
             wave_reduce(s[i], c[i]);
             rec = lane == i ? s[i] : lane == 4 + i ? c[i] : rec;
         }
-        if (lane < 8) partials[unit * 8 + lane] = rec;
+        // the partials' base passes through an empty asm so that its per-lane
+        // address is formed here, not held (and spilled) across the unit loop
+        double *pp = partials;
+        asm volatile("" : "+s"(pp));
+        if (lane < 8) pp[unit * 8 + lane] = rec;
     }
 }
 
