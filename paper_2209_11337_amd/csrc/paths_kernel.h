@@ -727,14 +727,14 @@ __device__ inline void step_uniform_part(const LaunchDesc &ld, const OptDev &op,
 // the LDS tables (inverse-normal cells, lane rows of all dimensions the
 // launch needs), loaded once.
 // The FP32 kernel is bound by latency as much as by issue (every step waits
-// on scalar plan loads and two dependent LDS reads), so it is held to 80
-// VGPRs: six waves per SIMD instead of four (measured 1.3x faster); with
-// 512-thread workgroups the LDS of three workgroups fits a CU at d = 64.
+// on two dependent LDS reads), so it is held to 80 VGPRs: six waves per
+// SIMD instead of four (measured 1.3x faster); the LDS of three 512-thread
+// workgroups fits a CU up to 181 lane rows, of two 768-thread ones up to 280.
 // PROBE instances (coordinate checks only) walk every option as an average
 // and also store the coordinates each 64-point batch consumes at
 // probe[((unit * unit_pts / 64 + batch) * ndims + dim - 1) * 64 + lane].
-// WIDE instances (FP32, launches whose lane rows leave room for at most one
-// 1024-thread workgroup per CU, i.e. 4 waves per SIMD anyway) may use 128
+// WIDE instances (FP32, launches whose lane rows leave room for one
+// workgroup per CU, 4 waves per SIMD at 1024 threads anyway) may use 128
 // VGPRs and hold 8 registers of wave-uniform slots, which the split bridge
 // needs beyond n = 356; they walk n = 15, 31, 63, 127 with the split bridge
 // too (the compile-time bridges would raise the register need of the whole

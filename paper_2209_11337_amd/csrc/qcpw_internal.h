@@ -217,9 +217,10 @@ struct PlanStep64 {
 #define QCPW_SPLIT_EVENTS 32     // 1 + (2^k - 1) + 2^k, k <= 4
 #define QCPW_SPLIT_SLOTS 512     // 8 registers of 64 lanes
 #define QCPW_EV_WORDS 16         // one 64-byte event, one scalar load
-// FP32 launches with more lane rows use the 128-VGPR kernel instances:
-// beyond 181 rows at most two workgroups fit the LDS of a CU, and the
-// 80-VGPR instances' extra occupancy is gone.
+// Beyond 181 lane rows three 512-thread workgroups of the 80-VGPR kernel
+// instances no longer fit the LDS of a CU: FP32 launches of more rows take
+// those instances only at 768 threads while two such workgroups fit, and
+// the 128-VGPR instances otherwise (the launch planner decides).
 #define QCPW_WIDE_MIN_N 181
 
 // The level k at which the split bridge of n starts its subtrees.
