@@ -54,8 +54,8 @@ PEAK_MFMA_BF16 = 2.5e15   # MI355X dense BF16 matrix
 TRAFFIC_SOURCES = ("paths_kernel.h", "device_math.h", "qcpw_internal.h", "ninv_table.inc", "phi_f64_coeffs.inc",
                    "kernels.hip")
 TRAFFIC = {
-    "portfolio": {"sha": "4bb5f87d13c27964", "fetch": 1169814661, "write": 1329740320},
-    "three_products": {"sha": "4bb5f87d13c27964", "fetch": 12799891, "write": 14156832},
+    "portfolio": {"sha": "5c97a5a5ac6d6577", "fetch": 1169816677, "write": 1329362464},
+    "three_products": {"sha": "5c97a5a5ac6d6577", "fetch": 12950537, "write": 14156128},
 }
 
 
@@ -64,9 +64,9 @@ TRAFFIC = {
 # and _FP64 (per wave, x64 lanes, the call's launches summed) over its
 # path-dates and paths.
 COUNTERS = {
-    "portfolio": {"sha": "4bb5f87d13c27964", "valu_per_path_date": 16.84, "fp32_flops_per_path_date": 15.28,
+    "portfolio": {"sha": "5c97a5a5ac6d6577", "valu_per_path_date": 16.84, "fp32_flops_per_path_date": 15.28,
                   "fp64_flops_per_path": 178.7},
-    "three_products": {"sha": "4bb5f87d13c27964", "valu_per_path_date": 16.46, "fp32_flops_per_path_date": 14.75,
+    "three_products": {"sha": "5c97a5a5ac6d6577", "valu_per_path_date": 16.46, "fp32_flops_per_path_date": 14.75,
                        "fp64_flops_per_path": 172.3},
 }
 CLOCK_HZ = 2.4e9
