@@ -217,20 +217,22 @@ def test_same_bits_in_a_split_launch():
     """A call whose longest options need the 128-VGPR instances and whose
     others hold most of the work runs as two launches (d = 8, walked by the
     plan walker with its stack, and d = 365 in one; d = 16, 64, 200, 250 in
-    the 80-VGPR one at 768 threads): 6 options x 256 units x 16 replications,
-    24576 units, 59 % of the path-dates in the second launch.  Every option
-    gives the bits it gives alone (where d = 8, 200 and 250 run the 80-VGPR
+    the 80-VGPR one at 768 threads): 6 options x 1024 units x 64
+    replications, 262144 units and 59 % of the path-dates in the second
+    launch.  Every option gives
+    the bits it gives alone (where d = 8, 200 and 250 run the 80-VGPR
     instances, d = 365 the 128-VGPR ones)."""
     ds = (365, 16, 64, 8, 200, 250)
+    L = 64
     opts = [dict(type=(q.ARITH_ASIAN, q.BINARY_ASIAN, q.LOOKBACK)[i % 3], d=d, S0=100.0, K=97.0 + 2 * i, r=0.04,
-                 sigma=0.3, T=1.2, seed=7000 + d, n_points=1 << 16) for i, d in enumerate(ds)]
+                 sigma=0.3, T=1.2, seed=7000 + d, n_points=1 << 22) for i, d in enumerate(ds)]
     say("split launch invariance")
-    g_mix, e_mix = q.greeks(opts, 16, q.PATH_BB, q.FP32_MIXED)
+    g_mix, e_mix = q.greeks(opts, L, q.PATH_BB, q.FP32_MIXED)
     for i, o in enumerate(opts):
-        g1, e1 = q.greeks([o], 16, q.PATH_BB, q.FP32_MIXED)
+        g1, e1 = q.greeks([o], L, q.PATH_BB, q.FP32_MIXED)
         assert np.array_equal(g1[0], g_mix[i]) and np.array_equal(e1[0], e_mix[i]), (o["d"], g1[0], g_mix[i])
     # and the FP32-mixed results stay those of the FP64 kernel within the FP32 bound
-    g64, _ = q.greeks(opts, 16, q.PATH_BB, q.FP64)
+    g64, _ = q.greeks(opts, L, q.PATH_BB, q.FP64)
     scale = np.maximum(np.abs(g64), 1e-3 * np.abs(g64).max(axis=0))
     assert (np.abs(g_mix - g64) / scale).max() <= 1e-3
 
