@@ -182,6 +182,9 @@ def parse():
     p.add_argument("--serve-sweep", action="store_true",
                    help="run only the serving sweep (saturation rate, then arrival rates 0.25, 0.5, 0.8 "
                         "times it, FP32-mixed and plain FP64 servers) and print it")
+    p.add_argument("--serve-burst", action="store_true",
+                   help="run only the serving sweep's saturation burst (24 requests at once) and print its time "
+                        "and the server's counts")
     p.add_argument("--serve-requests", type=int, default=300, help="requests per arrival rate in --serve-sweep")
     p.add_argument("--serve-rates", type=str, default="0.25,0.5,0.8",
                    help="arrival rates of --serve-sweep as fractions of the saturation rate")
@@ -247,6 +250,11 @@ def main():
     torch.cuda.set_device(dev)
     if a.pca_only:
         print(json.dumps({"pca": pca_leg(q, workloads, torch, steps=1)}), flush=True)
+        return
+    if a.serve_burst:
+        sec, stats = serve_burst(q, workloads)
+        print(json.dumps({"serving_burst": {"requests": 24, "seconds": sec,
+                                            "saturation_requests_per_s": 24 / sec, "server": stats}}), flush=True)
         return
     if a.serve_sweep:
         print(json.dumps({"serving_sweep": serve_sweep(q, workloads, a.serve_requests,
@@ -645,6 +653,20 @@ def plain_fp64_stream(q, stream, pts, L=16, cap_s=120.0):
             "latency_is_lower_bound": bool(censored), "cap_s": cap_s}
 
 
+def serve_burst(q, workloads, n_burst=24, max_opts=512, d_range=(4, 365), targets=(1e-4, 1e-6), L=16):
+    """n_burst requests of the serving stream submitted at once to a
+    FP32-mixed server: seconds until the last result, and the server's
+    counts."""
+    burst = workloads.request_stream(n_burst, 1e9, seed=5150, max_opts=max_opts, d_range=d_range,
+                                     targets=targets)
+    for r in burst:
+        r["t_arrival"] = 0.0
+    with q.Server(hbm_budget_bytes=8 << 30, precision=q.FP32_MIXED) as srv:
+        lat, pts, wall = run_stream(q, srv, burst, L, what="burst")
+        stats = srv.stats()
+    return float(lat.max()), stats
+
+
 def serve_sweep(q, workloads, n_requests, fracs, max_opts=512, d_range=(4, 365), targets=(1e-4, 1e-6),
                 n_burst=24, L=16, fp64_cap_s=120.0, sat=0.0):
     """The configured serving stream (Poisson arrivals of 1..max_opts-option
@@ -656,13 +678,8 @@ def serve_sweep(q, workloads, n_requests, fracs, max_opts=512, d_range=(4, 365),
     one-option-per-launch method under the same arrivals.  sat > 0: the
     saturation rate measured before (the burst is skipped)."""
     if sat <= 0.0:
-        burst = workloads.request_stream(n_burst, 1e9, seed=5150, max_opts=max_opts, d_range=d_range,
-                                         targets=targets)
-        for r in burst:
-            r["t_arrival"] = 0.0
-        with q.Server(hbm_budget_bytes=8 << 30, precision=q.FP32_MIXED) as srv:
-            lat, pts, wall = run_stream(q, srv, burst, L, what="burst")
-        sat = n_burst / float(lat.max())
+        sec, _ = serve_burst(q, workloads, n_burst, max_opts, d_range, targets, L)
+        sat = n_burst / sec
         print("serve sweep: saturation %.3f requests/s" % sat, file=sys.stderr, flush=True)
     res = {"stream": {"options_per_request": [1, max_opts], "d_range": list(d_range),
                       "target_stderr": list(targets), "shifts": L},
